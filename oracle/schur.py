@@ -1,0 +1,198 @@
+"""Schur complement, block-Jacobi blocks, deflation and null vectors (oracle).
+
+Test infrastructure: see the package docstring.
+
+Sec. 2.3, Eq. (operator_decomp): S = I + B A^-1 E over the inter-strip flux
+unknowns x_S = B u, b_S = B A^-1 f, u = A^-1 (f - E x_S).
+Sec. 3.1: S is assembled from per-strip blocks and applied as a sum of
+block products.  Strip j feeds the rows Gamma_{j-1}^L and Gamma_j^R from its
+own edge values Gamma_{j-1}^R, Gamma_j^L, so S = I + sum_j (rows_j) W_j
+(cols_j) with W_j = B[rows_j, strip j] A_j^-1 E[strip j, cols_j].  The oracle
+computes every W_j with a sparse LU of that strip's block of A.
+Sec. 3.2: block-Jacobi blocks are the principal submatrices of S on two
+consecutive interfaces (Gamma_{2b}, Gamma_{2b+1}); the last block holds a
+single interface when the interface count is odd.
+Sec. 3.3, Eqs. (projection1), (projection2): Z holds one indicator column
+per interface, C = Z^T S Z, P = I - S Z C^-1 Z^T, Q = I - Z C^-1 Z^T S; for
+the singular Poisson case the coarse division is C \\ (I - u_C u_C^T) with u_C
+the unit left null vector of C.
+Sec. 2.4, Claim 1: u_S = E^T u_L and u_L = A^-T B^T u_S (up to scale).
+"""
+from dataclasses import dataclass, field
+
+import numpy as np
+import scipy.linalg as sla
+import scipy.sparse as sp
+import scipy.sparse.linalg as spla
+
+from . import smpm
+
+
+def strip_range(grid, j):
+    m = grid.n * grid.n * grid.mz
+    return np.arange(j * m, (j + 1) * m)
+
+
+def half_range(grid, h):
+    N = grid.nhalf
+    return np.arange(h * N, (h + 1) * N)
+
+
+def strip_rows_cols(grid, j):
+    """Half-interfaces written (rows) and read (cols) by strip j."""
+    nh = 2 * (grid.mx - 1)
+    rows = [h for h in (2 * j - 2, 2 * j + 1) if 0 <= h < nh]
+    cols = [h for h in (2 * j - 1, 2 * j) if 0 <= h < nh]
+    return rows, cols
+
+
+@dataclass
+class SchurSystem:
+    grid: smpm.Grid
+    tau: float
+    kwave: float
+    A: sp.csr_matrix
+    B: sp.csr_matrix
+    E: sp.csr_matrix
+    lus: list                 # per-strip sparse LU of A_j(k)
+    W: list                   # per-strip dense W_j
+    S: sp.csr_matrix          # assembled Schur matrix
+    bj_index: list            # per block, Gamma indices
+    bj_inv: list              # per block, dense M_b^-1
+    labels: np.ndarray        # Z label map: Gamma index -> interface
+    C: np.ndarray             # Z^T S Z
+    SZ: np.ndarray            # S Z (k x d)
+    uS: np.ndarray = None     # left null vectors (k = 0 only)
+    uL: np.ndarray = None
+    uC: np.ndarray = None
+    extra: dict = field(default_factory=dict)
+
+    @property
+    def singular(self):
+        return self.kwave == 0.0
+
+    # ---- operators -------------------------------------------------------
+    def A_solve(self, v, trans=False):
+        """A(k)^-1 v (or A(k)^-T v), strip by strip."""
+        out = np.empty_like(v)
+        for j, lu in enumerate(self.lus):
+            idx = strip_range(self.grid, j)
+            out[idx] = lu.solve(v[idx], trans="T" if trans else "N")
+        return out
+
+    def S_apply(self, x):
+        return self.S @ x
+
+    def Minv_apply(self, x):
+        y = np.empty_like(x)
+        for idx, Mi in zip(self.bj_index, self.bj_inv):
+            y[idx] = Mi @ x[idx]
+        return y
+
+    def Zt(self, x):
+        return np.bincount(self.labels, weights=x, minlength=self.grid.mx - 1)
+
+    def Z(self, c):
+        return c[self.labels]
+
+    def coarse(self, t):
+        """C^dagger (I - u_C u_C^T) t: the regularized coarse division of
+        Sec. 3.3 (plain C^-1 t when C is nonsingular).  C has rank d - 1 for
+        k = 0; C^dagger is the Moore-Penrose inverse of that rank-(d-1)
+        matrix, V_{d-1} Sigma_{d-1}^-1 U_{d-1}^T from the SVD of C, whose
+        range is orthogonal to 1_d.  P does not depend on which solution is
+        taken (a shift along 1_d is annihilated by S Z)."""
+        if self.singular:
+            U, s, Vt = self.extra["C_svd"]
+            return Vt[:-1].T @ ((U[:, :-1].T @ (t - self.uC * (self.uC @ t))) / s[:-1])
+        return np.linalg.solve(self.C, t)
+
+    def P_apply(self, y):
+        return y - self.SZ @ self.coarse(self.Zt(y))
+
+    def Q_apply(self, x):
+        return x - self.Z(self.coarse(self.Zt(self.S_apply(x))))
+
+
+def _strip(grid, A, B, E, j):
+    """Sparse LU of A_j(k) (kept for A^-1 v) and the strip block
+    W_j = B[rows_j] A_j^-1 E[cols_j], computed with a dense LU of A_j(k)."""
+    sidx = strip_range(grid, j)
+    Aj = A[sidx][:, sidx]
+    lu = spla.splu(Aj.tocsc())
+    rows, cols = strip_rows_cols(grid, j)
+    ridx = np.concatenate([half_range(grid, h) for h in rows])
+    cidx = np.concatenate([half_range(grid, h) for h in cols])
+    X = sla.lu_solve(sla.lu_factor(Aj.toarray()), E[sidx][:, cidx].toarray())
+    return lu, B[ridx][:, sidx] @ X, ridx, cidx
+
+
+def build(grid, tau=None, kwave=0.0):
+    """Assemble every operator of the Schur method for one 2-D problem."""
+    if tau is None:
+        tau = smpm.default_tau(grid)
+    A = smpm.assemble_A(grid, tau, kwave)
+    B = smpm.assemble_B(grid, tau)
+    E = smpm.assemble_E(grid)
+    k = grid.k
+    parts = [_strip(grid, A, B, E, j) for j in range(grid.mx)]
+    lus = [p[0] for p in parts]
+    W = [p[1] for p in parts]
+    Srows, Scols, Svals = [np.arange(k)], [np.arange(k)], [np.ones(k)]
+    for (_, Wj, ridx, cidx) in parts:
+        rr, cc = np.meshgrid(ridx, cidx, indexing="ij")
+        Srows.append(rr.ravel()); Scols.append(cc.ravel()); Svals.append(Wj.ravel())
+    S = sp.coo_matrix((np.concatenate(Svals), (np.concatenate(Srows), np.concatenate(Scols))),
+                      shape=(k, k)).tocsr()
+    # Block-Jacobi: pairs of interfaces (Sec. 3.2).
+    nif = grid.mx - 1
+    bj_index = []
+    for b0 in range(0, nif, 2):
+        ifs = [i for i in (b0, b0 + 1) if i < nif]
+        bj_index.append(np.concatenate([np.concatenate([half_range(grid, 2 * i),
+                                                        half_range(grid, 2 * i + 1)]) for i in ifs]))
+    bj_inv = [np.linalg.inv(S[idx][:, idx].toarray()) for idx in bj_index]
+    labels = np.repeat(np.arange(nif), 2 * grid.nhalf)
+    Zs = sp.coo_matrix((np.ones(k), (np.arange(k), labels)), shape=(k, nif)).tocsr()
+    SZ = (S @ Zs).toarray()
+    C = (Zs.T @ SZ)
+    sysm = SchurSystem(grid, tau, float(kwave), A, B, E, lus, W, S, bj_index, bj_inv,
+                       labels, np.asarray(C), SZ)
+    if kwave == 0.0:
+        null_vectors(sysm)
+    return sysm
+
+
+def null_vectors(sysm):
+    """Left null vectors for the Poisson (k = 0) case.
+
+    u_S: S^T u = 0 with the last component pinned to 1 and the last equation
+    dropped; the remaining (k-1) x (k-1) system is the transpose of a proper
+    principal submatrix of S, invertible (Sec. 3.1), and the dropped equation
+    is the negative sum of the others because S 1 = 0.
+    u_L = A^-T B^T u_S (Claim 1, part 2), normalized.
+    u_C: the unit left singular vector of the smallest singular value of C.
+    Signs: each vector is scaled to have a positive sum.
+    """
+    S = sysm.S
+    k = S.shape[0]
+    lu = spla.splu(S[:-1, :-1].T.tocsc())
+    u = np.append(lu.solve(-np.asarray(S[k - 1, :-1].todense()).ravel()), 1.0)
+    uS = u / np.linalg.norm(u)
+    uS *= np.sign(uS.sum())
+    uL = sysm.A_solve(sysm.B.T @ uS, trans=True)
+    uL /= np.linalg.norm(uL)
+    uL *= np.sign(uL.sum())
+    U, s, Vt = np.linalg.svd(sysm.C)
+    sysm.extra["C_svd"] = (U, s, Vt)
+    uC = U[:, -1] * np.sign(U[:, -1].sum())
+    sysm.uS, sysm.uL, sysm.uC = uS, uL, uC
+    return uS, uL, uC
+
+
+def dense_schur(grid, tau, kwave=0.0):
+    """S = I + B A^-1 E formed with a dense inverse of A (tiny grids only)."""
+    A = smpm.assemble_A(grid, tau, kwave).toarray()
+    B = smpm.assemble_B(grid, tau).toarray()
+    E = smpm.assemble_E(grid).toarray()
+    return np.eye(grid.k) + B @ np.linalg.inv(A) @ E

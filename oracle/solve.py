@@ -1,0 +1,194 @@
+"""Schur-method solves (oracle).
+
+Test infrastructure: see the package docstring.
+
+dbj_solve follows Algorithm 2 (Sec. 3.3, "Block-Jacobi Preconditioned and
+Deflated Schur Method") in the paper's order:
+  1. b <- b - u_L u_L^T b                       (Sec. 2.4, Eq. regularize_poisson)
+  2. b_S = B A^-1 b
+  3. b_S <- b_S - u_S (u_S^T b_S)               (Eq. regularize_schur)
+  4. x_1 = GMRES(P S M^-1, P b_S)               (Eq. deflated_schur)
+  5. x_1 <- Q M^-1 x_1
+  6. x_2 = Z^T b_S - u_C u_C^T Z^T b_S
+  7. x_2 <- Z C\\x_2
+  8. x = x_1 + x_2
+  9. u = A^-1 (b - E x)
+The Poisson (k = 0) solution is defined up to a constant (Sec. 2.4); it is
+returned with zero nodal mean.  For a Helmholtz mode k > 0 (Sec. 5) the
+projections of steps 1, 3 and 6 are skipped: L - k^2 I and C(k) are
+nonsingular.
+
+The comparison methods of Table 1 (Sec. 4) are selectable with `method`:
+'schur' GMRES(S, b_S); 'bj' GMRES(S M^-1, b_S) then M^-1; 'dbj' (above);
+'2las' GMRES(S (M^-1 + Z C\\(I - u_C u_C^T) Z^T), b_S).
+
+direct_solve is the plain definition the method must reproduce: the
+projected system L(k) u = f - u_L u_L^T f solved by least squares on a dense
+L, gauge-fixed.  Tiny grids only.
+"""
+from dataclasses import dataclass
+
+import numpy as np
+
+from . import gmres as _gmres
+from . import schur as _schur
+from . import smpm
+
+
+@dataclass
+class Result:
+    u: np.ndarray
+    xS: np.ndarray
+    bS: np.ndarray
+    iters: int
+    converged: bool
+    schur_relres: float
+    history: list
+    compat_defect: float
+
+
+def schur_rhs(sysm, F):
+    """Steps 1-3: the projected right-hand side and the Schur right-hand side."""
+    Ft = F.copy()
+    compat = 0.0
+    if sysm.singular:
+        compat = abs(sysm.uL @ F) / max(np.linalg.norm(F), 1e-300)
+        Ft = F - sysm.uL * (sysm.uL @ F)
+    bS = sysm.B @ sysm.A_solve(Ft)
+    if sysm.singular:
+        bS = bS - sysm.uS * (sysm.uS @ bS)
+    return Ft, bS, compat
+
+
+def schur_solve(sysm, bS, method="dbj", tol=1e-10, maxit=300):
+    """Solve S x = b_S with one of the Table 1 methods; returns
+    (x_S, iterations, converged, history)."""
+    if method == "schur":
+        x, it, ok, hist = _gmres.gmres(sysm.S_apply, bS, tol, maxit)
+        return x, it, ok, hist
+    if method == "bj":
+        op = lambda v: sysm.S_apply(sysm.Minv_apply(v))
+        xp, it, ok, hist = _gmres.gmres(op, bS, tol, maxit)
+        return sysm.Minv_apply(xp), it, ok, hist
+    if method == "dbj":
+        op = lambda v: sysm.P_apply(sysm.S_apply(sysm.Minv_apply(v)))
+        xp, it, ok, hist = _gmres.gmres(op, sysm.P_apply(bS), tol, maxit)
+        x1 = sysm.Q_apply(sysm.Minv_apply(xp))
+        x2 = sysm.Z(sysm.coarse(sysm.Zt(bS)))
+        return x1 + x2, it, ok, hist
+    if method == "2las":
+        def prec(v):
+            return sysm.Minv_apply(v) + sysm.Z(sysm.coarse(sysm.Zt(v)))
+        xp, it, ok, hist = _gmres.gmres(lambda v: sysm.S_apply(prec(v)), bS, tol, maxit)
+        return prec(xp), it, ok, hist
+    raise ValueError(method)
+
+
+def recover(sysm, Ft, xS):
+    """Step 9: u = A^-1 (b - E x_S), gauge-fixed to zero mean for k = 0."""
+    u = sysm.A_solve(Ft - sysm.E @ xS)
+    if sysm.singular:
+        u = u - u.mean()
+    return u
+
+
+def dbj_solve(sysm, F, method="dbj", tol=1e-10, maxit=300):
+    """Algorithm 2 for one right-hand side F = f + tau g (node layout)."""
+    Ft, bS, compat = schur_rhs(sysm, F)
+    xS, it, ok, hist = schur_solve(sysm, bS, method, tol, maxit)
+    res = np.linalg.norm(sysm.S_apply(xS) - bS) / max(np.linalg.norm(bS), 1e-300)
+    u = recover(sysm, Ft, xS)
+    return Result(u, xS, bS, it, ok, res, hist, compat)
+
+
+def direct_solve(grid, tau, F, kwave=0.0):
+    """Dense least-squares solve of L(k) u = F - u_L u_L^T F (tiny grids)."""
+    L = smpm.assemble_L(grid, tau, kwave).toarray()
+    if kwave == 0.0:
+        U, s, Vt = np.linalg.svd(L)
+        uL = U[:, -1]
+        F = F - uL * (uL @ F)
+        u = np.linalg.lstsq(L, F, rcond=None)[0]
+        return u - u.mean()
+    return np.linalg.solve(L, F)
+
+
+def dense_schur_solve(grid, tau, F, kwave=0.0):
+    """The explicitly assembled dense Schur matrix solved directly (with the
+    null-space projections of Sec. 2.4), then recovery.  Tiny grids only."""
+    A = smpm.assemble_A(grid, tau, kwave).toarray()
+    B = smpm.assemble_B(grid, tau).toarray()
+    E = smpm.assemble_E(grid).toarray()
+    Ainv = np.linalg.inv(A)
+    S = np.eye(grid.k) + B @ Ainv @ E
+    Ft = F.copy()
+    if kwave == 0.0:
+        L = A + E @ B
+        U, s, Vt = np.linalg.svd(L)
+        uL = U[:, -1]
+        Ft = F - uL * (uL @ F)
+    bS = B @ Ainv @ Ft
+    if kwave == 0.0:
+        Us, ss, Vts = np.linalg.svd(S)
+        uS = Us[:, -1]
+        bS = bS - uS * (uS @ bS)
+        xS = np.linalg.lstsq(S, bS, rcond=None)[0]
+    else:
+        xS = np.linalg.solve(S, bS)
+    u = Ainv @ (Ft - E @ xS)
+    if kwave == 0.0:
+        u = u - u.mean()
+    return u, xS
+
+
+def refine_solve(sysm, F, inner_tol=1e-6, tol=1e-10, maxit=300, max_sweeps=20,
+                 dtype=np.float32):
+    """FP64 iterative refinement around a reduced-precision DBJ inner solve
+    (the mixed-precision form; not in the paper).  The inner solve rounds the
+    Schur blocks, the block-Jacobi inverses and every inner vector to `dtype`;
+    the outer residual b_S - S x, the projections and the coarse solve stay
+    FP64.  Returns (Result, sweeps, total inner iterations)."""
+    Ft, bS, compat = schur_rhs(sysm, F)
+    S_lo = sysm.S.astype(dtype)
+    Mi_lo = [m.astype(dtype) for m in sysm.bj_inv]
+    SZ = sysm.SZ
+
+    def rnd(v):
+        return v.astype(dtype).astype(np.float64)
+
+    def Minv_lo(v):
+        y = np.empty_like(v)
+        vl = v.astype(dtype)
+        for idx, Mi in zip(sysm.bj_index, Mi_lo):
+            y[idx] = (Mi @ vl[idx]).astype(np.float64)
+        return y
+
+    def S_lo_apply(v):
+        return (S_lo @ v.astype(dtype)).astype(np.float64)
+
+    def P_lo(y):
+        return rnd(y - SZ @ sysm.coarse(sysm.Zt(y)))
+
+    x = np.zeros_like(bS)
+    nb = np.linalg.norm(bS)
+    total = 0
+    sweeps = 0
+    hist = []
+    for sweeps in range(1, max_sweeps + 1):
+        r = bS - sysm.S_apply(x)
+        if sysm.singular:
+            r = r - sysm.uS * (sysm.uS @ r)
+        rel = np.linalg.norm(r) / nb
+        hist.append(rel)
+        if rel <= tol:
+            sweeps -= 1
+            break
+        op = lambda v: P_lo(S_lo_apply(Minv_lo(v)))
+        xp, it, ok, _ = _gmres.gmres(op, P_lo(r), inner_tol, maxit)
+        total += it
+        d1 = sysm.Q_apply(Minv_lo(xp))
+        d2 = sysm.Z(sysm.coarse(sysm.Zt(r)))
+        x = x + d1 + d2
+    res = np.linalg.norm(sysm.S_apply(x) - bS) / nb
+    u = recover(sysm, Ft, x)
+    return Result(u, x, bS, total, res <= tol, res, hist, compat), sweeps, total
