@@ -1,0 +1,205 @@
+/*
+ * smpm_schur.h -- C ABI of the MI355X (gfx950) Schur-complement solver for the
+ * spectral multidomain penalty (SMPM) discretization of the 2-D Poisson- and
+ * Helmholtz-Neumann problem, preconditioned by block-Jacobi and deflation.
+ *
+ * Method: Joshi, Thomsen & Diamessis, "Deflation-accelerated preconditioning
+ * of the Poisson-Neumann Schur problem on long domains with a high-order
+ * discontinuous element-based collocation method", arXiv:1512.01756.
+ *   - discretization: Sec. 2.2, Eq. (smpm_poisson);
+ *   - strip split L = A + E B and S = I + B A^-1 E: Sec. 2.3, Eq. (operator_decomp);
+ *   - null-space projections: Sec. 2.4, Eqs. (regularize_poisson), (regularize_schur);
+ *   - GMRES, block-Jacobi M, deflation P, Q: Sec. 3, Eq. (deflated_schur),
+ *     Algorithm 2;
+ *   - Fourier modes in y, one Helmholtz Schur problem per wavenumber: Sec. 5,
+ *     Eq. (transverse_schur).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * n = order + 1 GLL points per direction; r = n^2 m_x m_z nodes;
+ * k_S = 2 n m_z (m_x - 1) interface unknowns; d = m_x - 1 coarse unknowns.
+ *
+ * Node layout of f and u (FP64):
+ *     node(j, e, b, a) = ((j * m_z + e) * n + b) * n + a
+ *   j strip (x), e element in the strip (z, bottom first), b GLL index in z,
+ *   a GLL index in x (fastest).
+ * Neumann data g of one right-hand side (FP64), four sides back to back:
+ *     south[m_x][n] (strip, a), north[m_x][n], west[m_z][n] (element, b),
+ *     east[m_z][n]                      -> 2 n (m_x + m_z) values.
+ * Interface (Schur) vectors: half-interface h = 2i is the east edge of strip
+ *   i, h = 2i + 1 the west edge of strip i + 1 (i = 0 .. m_x - 2); inside a
+ *   half the order is (e, b); index h * n m_z + e * n + b.
+ *
+ * A handle holds one or more "systems": a (grid, wavenumber k) pair with its
+ * own operators S(k), M(k), C(k).  Each system solves `nrhs` right-hand sides
+ * (e.g. the real and imaginary parts of a Fourier mode).  An "instance" is a
+ * (system, rhs) pair.  Batched device arrays are the concatenation over
+ * systems in setup order, and inside a system over rhs.
+ *
+ * Memory: pointers named *_dev are device pointers (hipMalloc'ed, or torch
+ * CUDA tensors); every other pointer is host memory.  The caller owns all
+ * buffers it passes; the handle owns every operator table and workspace,
+ * allocated in setup.  smpm_solve and smpm_apply allocate nothing.
+ *
+ * Streams: every device call enqueues on the caller's hipStream_t (NULL = the
+ * default stream).  Calls that fill host-side results synchronize that
+ * stream before returning.
+ *
+ * Errors: every call returns smpm_status; nothing throws across the ABI.
+ * smpm_last_error() returns a thread-local message for the last non-OK
+ * status.  A handle is not thread-safe; distinct handles are independent.
+ */
+#ifndef SMPM_SCHUR_H
+#define SMPM_SCHUR_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  SMPM_OK = 0,
+  SMPM_EINVAL = -1,      /* bad argument or shape */
+  SMPM_ENOMEM = -2,      /* host or device allocation failed */
+  SMPM_EHIP = -3,        /* HIP runtime error */
+  SMPM_ESINGULAR = -4,   /* k = 0 with m_x < 4, or a factorization failed */
+  SMPM_ENOTCONV = -5,    /* max_iter / sweeps reached; u holds the last iterate */
+  SMPM_ENONFINITE = -6,  /* NaN or Inf in the inputs or the iterates */
+  SMPM_EUNSUPPORTED = -7 /* the call needs a GPU but the handle is host-only */
+} smpm_status;
+
+typedef enum {
+  SMPM_FP64 = 0,     /* every step in FP64 */
+  SMPM_FP32_IR = 1   /* FP32 inner DBJ-GMRES (operators, Krylov basis) inside
+                        FP64 iterative refinement: outer residual, projections,
+                        coarse solve and least squares stay FP64 */
+} smpm_precision;
+
+typedef enum {
+  SMPM_METHOD_DBJ = 0,   /* GMRES(P S M^-1, P b~): Algorithm 2 (default)  */
+  SMPM_METHOD_BJ = 1,    /* GMRES(S M^-1, b~), Table 1 "BJ-Schur"          */
+  SMPM_METHOD_SCHUR = 2, /* GMRES(S, b~), Table 1 "Schur"                  */
+  SMPM_METHOD_2LAS = 3   /* GMRES(S (M^-1 + Z C\(I - u_C u_C^T) Z^T), b~)  */
+} smpm_method;
+
+#define SMPM_FLAG_HOST_ONLY 1  /* build the host tables only; no GPU is touched */
+
+typedef struct {
+  int32_t mx, mz;      /* elements in x (>= 2) and z (>= 1) */
+  int32_t order;       /* polynomial degree (>= 1); n = order + 1 */
+  const double *xb;    /* host, mx + 1 strictly increasing x breakpoints */
+  const double *zb;    /* host, mz + 1 strictly increasing z breakpoints */
+} smpm_grid;
+
+typedef struct {
+  double tau;          /* penalty; 0 selects -n(n-1)/h_min (one global value) */
+  double tol;          /* relative Schur residual target; 0 selects 1e-10 */
+  int32_t max_iter;    /* GMRES iterations (no restart); 0 selects 300 */
+  int32_t nrhs;        /* right-hand sides per system; 0 selects 1 */
+  int32_t precision;   /* smpm_precision */
+  int32_t method;      /* smpm_method */
+  double inner_tol;    /* FP32_IR inner relative tolerance; 0 selects 1e-5 */
+  int32_t max_sweeps;  /* FP32_IR outer sweeps; 0 selects 12 */
+  int32_t flags;       /* SMPM_FLAG_* */
+} smpm_opts;
+
+typedef struct {
+  int32_t instances;       /* systems * nrhs */
+  int32_t converged;       /* instances that reached tol */
+  int32_t iters_total;     /* GMRES iterations summed over instances (all sweeps) */
+  int32_t iters_max;       /* largest per-instance GMRES iteration count */
+  int32_t sweeps_max;      /* refinement sweeps (1 for FP64) */
+  int32_t schur_matvecs;   /* S applications in the solve, summed over instances */
+  double rel_residual_max; /* max over instances of ||S x_S - b~|| / ||b~|| (FP64) */
+  double compat_defect_max;/* max over k = 0 instances of |u_L^T F| / ||F|| */
+  double solve_ms;         /* wall time of the solve (host clock, synchronized) */
+} smpm_stats;
+
+typedef struct {
+  int32_t n, mx, mz;
+  int32_t nrhs;
+  int64_t r;               /* nodes */
+  int64_t kS;              /* interface unknowns */
+  int32_t d;               /* coarse unknowns */
+  double kwave;            /* wavenumber k of this system */
+  double tau;              /* penalty in use */
+  int64_t f_offset;        /* element offset of this system in batched f/u */
+  int64_t g_offset;        /* element offset in batched g */
+  int64_t x_offset;        /* element offset in batched interface vectors */
+  int32_t unique_W;        /* distinct Schur strip blocks stored */
+  int32_t unique_M;        /* distinct block-Jacobi blocks stored */
+  int64_t bytes_W64;       /* algorithmic bytes of one FP64 Schur matvec's operator */
+  int64_t bytes_M64;       /* same for one block-Jacobi apply */
+} smpm_info;
+
+typedef struct smpm_handle smpm_handle;
+
+/* One grid, nk wavenumbers (k >= 0; host array).  Each wavenumber is one
+ * system with S(k) = I + B (A - k^2 I)^-1 E (Sec. 5).  k = 0 systems get the
+ * null-space projections of Sec. 2.4 and need m_x >= 4 (else ESINGULAR).
+ * hip_stream: hipStream_t used for the uploads (ignored when host-only). */
+smpm_status smpm_setup(const smpm_grid *grid, const double *k, int32_t nk,
+                       const smpm_opts *opts, void *hip_stream, smpm_handle **out);
+
+/* nprob independent problems, each with its own grid and one wavenumber
+ * k[p] (host arrays), solved as one batch. */
+smpm_status smpm_setup_batch(const smpm_grid *grids, const double *k, int32_t nprob,
+                             const smpm_opts *opts, void *hip_stream, smpm_handle **out);
+
+/* Algorithm 2 for every instance: f_dev (FP64, batched node layout), g_dev
+ * (FP64, batched side layout, or NULL for g = 0) -> u_dev (FP64, batched node
+ * layout, zero nodal mean for k = 0).  stats (host, nullable) is filled after
+ * a stream synchronization.  ENOTCONV leaves the last iterate in u_dev. */
+smpm_status smpm_solve(smpm_handle *h, const double *f_dev, const double *g_dev,
+                       double *u_dev, void *hip_stream, smpm_stats *stats);
+
+typedef enum {
+  SMPM_OP_SCHUR = 0,    /* y = S x                    (k_S -> k_S), Sec. 2.3 */
+  SMPM_OP_BJINV = 1,    /* y = M^-1 x                 (k_S -> k_S), Sec. 3.2 */
+  SMPM_OP_DEFLATE_P = 2,/* y = P x                    (k_S -> k_S), Sec. 3.3 */
+  SMPM_OP_DEFLATE_Q = 3,/* y = Q x                    (k_S -> k_S), Sec. 3.3 */
+  SMPM_OP_AINV = 4,     /* y = A(k)^-1 x              (r -> r),     Sec. 2.3 */
+  SMPM_OP_B = 5,        /* y = B x                    (r -> k_S),   Sec. 2.3 */
+  SMPM_OP_SCHUR_RHS = 6 /* y = b~ from F (steps 1-3 of Algorithm 2; r -> k_S) */
+} smpm_op;
+
+/* Apply one operator of system `sys` to one vector.  x_dev, y_dev: device
+ * arrays of the sizes noted above, in the layouts of this header.
+ * precision selects the FP64 or FP32 operator tables; x_dev and y_dev are
+ * double for SMPM_FP64 and float for SMPM_FP32_IR (SCHUR and BJINV only). */
+smpm_status smpm_apply(smpm_handle *h, smpm_op op, int32_t sys, const void *x_dev,
+                       void *y_dev, int32_t precision, void *hip_stream);
+
+/* Batched Schur matvec over every instance: x_dev, y_dev hold the interface
+ * vectors of all instances back to back (smpm_info.x_offset * nrhs layout).
+ * This is the kernel the matvec rate is measured on. */
+smpm_status smpm_schur_apply_all(smpm_handle *h, const void *x_dev, void *y_dev,
+                                 int32_t precision, void *hip_stream);
+
+smpm_status smpm_query(const smpm_handle *h, int32_t sys, smpm_info *info);
+int32_t smpm_num_systems(const smpm_handle *h);
+
+typedef enum {
+  SMPM_TABLE_SCHUR_DENSE = 0, /* k_S x k_S row-major dense S (small grids only) */
+  SMPM_TABLE_BJINV_DENSE = 1, /* k_S x k_S row-major dense M^-1 */
+  SMPM_TABLE_COARSE_C = 2,    /* d x d row-major C = Z^T S Z */
+  SMPM_TABLE_U_S = 3,         /* k_S, left null vector of S (k = 0) */
+  SMPM_TABLE_U_L = 4,         /* r, left null vector of L (k = 0) */
+  SMPM_TABLE_U_C = 5,         /* d, left null vector of C (k = 0) */
+  SMPM_TABLE_SZ = 6           /* k_S x d row-major S Z */
+} smpm_table;
+
+/* Copy a host-side operator table of system `sys` into host_out (count
+ * doubles, must equal the table size).  Works on host-only handles; this is
+ * how the setup is checked without a GPU. */
+smpm_status smpm_export(const smpm_handle *h, smpm_table what, int32_t sys,
+                        double *host_out, int64_t count);
+
+void smpm_destroy(smpm_handle *h);
+const char *smpm_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SMPM_SCHUR_H */

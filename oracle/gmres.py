@@ -14,7 +14,7 @@ usual Givens QR of the Hessenberg matrix):
     zeroes entries j+1.. of z_j; column j-1 of H is the head of P_j z_j;
     v_j = P_0 P_1 ... P_j e_j;  z_{j+1} = P_j ... P_0 (Op v_j).
   Residual norm |g_{j+1}| after the Givens rotations; stop when it is below
-  tol * |b|.  x = P_0 ... P_{m-1} [y; 0] with R y = g.
+  tol times a reference norm (|b| unless the caller passes one).  x = P_0 ... P_{m-1} [y; 0] with R y = g.
 """
 import numpy as np
 
@@ -43,15 +43,17 @@ def _reflect(w, x):
     return x - 2.0 * w * (w @ x)
 
 
-def gmres(op, b, tol=1e-10, maxit=300, record=None):
-    """Solve op(x) = b from x0 = 0.  Returns (x, iterations, converged,
-    residual history |g_j| / |b|)."""
+def gmres(op, b, tol=1e-10, maxit=300, ref_norm=None):
+    """Solve op(x) = b from x0 = 0; stop when the residual estimate |g_{j+1}|
+    is at most tol * ref_norm (default |b|).  Returns (x, iterations,
+    converged, residual history |g_j| / |b|)."""
     k = b.shape[0]
     maxit = min(maxit, k)
     Ws = []
     w, beta = _house(b.astype(np.float64), 0)
     Ws.append(w)
     r0 = abs(beta)
+    target = tol * (r0 if ref_norm is None else ref_norm)
     hist = [1.0]
     if r0 == 0.0:
         return np.zeros_like(b), 0, True, hist
@@ -90,7 +92,7 @@ def gmres(op, b, tol=1e-10, maxit=300, record=None):
         H[:j + 2, j] = h
         m = j + 1
         hist.append(abs(g[j + 1]) / r0)
-        if abs(g[j + 1]) <= tol * r0:
+        if abs(g[j + 1]) <= target:
             converged = True
             break
     R = H[:m, :m]

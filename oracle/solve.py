@@ -62,24 +62,30 @@ def schur_rhs(sysm, F):
 
 def schur_solve(sysm, bS, method="dbj", tol=1e-10, maxit=300):
     """Solve S x = b_S with one of the Table 1 methods; returns
-    (x_S, iterations, converged, history)."""
+    (x_S, iterations, converged, history).
+
+    Every method stops when its GMRES residual estimate is below
+    tol * |b_S|: Sec. 4 accepts a solution when |S x_S - b_S| / |b_S| < tol,
+    and for DBJ the deflated residual equals the true Schur residual while
+    its starting vector P b_S can be longer than b_S (P is oblique)."""
+    ref = float(np.linalg.norm(bS))
     if method == "schur":
-        x, it, ok, hist = _gmres.gmres(sysm.S_apply, bS, tol, maxit)
+        x, it, ok, hist = _gmres.gmres(sysm.S_apply, bS, tol, maxit, ref)
         return x, it, ok, hist
     if method == "bj":
         op = lambda v: sysm.S_apply(sysm.Minv_apply(v))
-        xp, it, ok, hist = _gmres.gmres(op, bS, tol, maxit)
+        xp, it, ok, hist = _gmres.gmres(op, bS, tol, maxit, ref)
         return sysm.Minv_apply(xp), it, ok, hist
     if method == "dbj":
         op = lambda v: sysm.P_apply(sysm.S_apply(sysm.Minv_apply(v)))
-        xp, it, ok, hist = _gmres.gmres(op, sysm.P_apply(bS), tol, maxit)
+        xp, it, ok, hist = _gmres.gmres(op, sysm.P_apply(bS), tol, maxit, ref)
         x1 = sysm.Q_apply(sysm.Minv_apply(xp))
         x2 = sysm.Z(sysm.coarse(sysm.Zt(bS)))
         return x1 + x2, it, ok, hist
     if method == "2las":
         def prec(v):
             return sysm.Minv_apply(v) + sysm.Z(sysm.coarse(sysm.Zt(v)))
-        xp, it, ok, hist = _gmres.gmres(lambda v: sysm.S_apply(prec(v)), bS, tol, maxit)
+        xp, it, ok, hist = _gmres.gmres(lambda v: sysm.S_apply(prec(v)), bS, tol, maxit, ref)
         return prec(xp), it, ok, hist
     raise ValueError(method)
 
@@ -184,7 +190,7 @@ def refine_solve(sysm, F, inner_tol=1e-6, tol=1e-10, maxit=300, max_sweeps=20,
             sweeps -= 1
             break
         op = lambda v: P_lo(S_lo_apply(Minv_lo(v)))
-        xp, it, ok, _ = _gmres.gmres(op, P_lo(r), inner_tol, maxit)
+        xp, it, ok, _ = _gmres.gmres(op, P_lo(r), inner_tol, maxit, np.linalg.norm(r))
         total += it
         d1 = sysm.Q_apply(Minv_lo(xp))
         d2 = sysm.Z(sysm.coarse(sysm.Zt(r)))

@@ -1,0 +1,62 @@
+// Device-side descriptors of the SMPM Schur solver (shared by the kernels
+// and the host orchestration in smpm.hip).
+#pragma once
+#include <cstdint>
+
+namespace smpm {
+
+constexpr int kBlock = 256;         // threads per workgroup (4 wave64)
+constexpr int kChunk = 512;         // interface/node elements per workgroup in vector kernels
+constexpr int kMaxN = 544;          // largest n * m_z supported (half-interface length)
+constexpr int kMaxRowsPerLane = (kMaxN + 63) / 64;
+
+// Per-system tables on the device.  Block layouts are column-major inside a
+// block ([col][row]) so that a wavefront reads consecutive rows of one column.
+struct SysDev {
+  int n, mx, mz, n2, N, nh, d, singular;
+  int64_t kS, r;
+  double tau;
+  const double *W64;     // unique Schur half blocks: [blk][2N][N]
+  const float *W32;
+  const int *w_id, *w_win;
+  const double *M64;     // unique block-Jacobi row chunks: [chunk][4N][N]
+  const float *M32;
+  const int *m_id, *m_win, *m_K;
+  const int *sz_col;     // [h][2]
+  const double *SZh;     // [h][2][N]
+  const double *Gc;      // coarse operator, column-major d x d
+  const double *uS, *uL; // null vectors (k = 0), else nullptr
+  const double *Gs;      // strip factors: [class][e][col n2][row n2]
+  const double *lo, *up; // [e][n]
+  const double *beta;    // [class][2][n]: west row, east row
+  const int *strip_class;
+};
+
+// Per-instance (system, rhs) offsets into the batched work arrays.
+struct InstDev {
+  int sys, rhs;
+  int nchunk_x;          // chunks of the interface vector
+  int nchunk_r;          // chunks of the node vector
+  int64_t f_off;         // node-space offset (f, u, F, v)
+  int64_t g_off;         // Neumann-data offset
+  int64_t x_off;         // interface-space offset
+  int64_t v_off;         // Krylov basis offset
+  int64_t part_off;      // partial-sum offset: [maxit + 1][nchunk_x]
+  int64_t pr_off;        // node-space partials: [nchunk_r] x 2
+  int64_t hs_off;        // half sums: [nh]
+  int64_t c_off;         // coarse vectors: [d]
+  int64_t st_off;        // GMRES scalars: [maxit + 1]
+  int64_t rr_off;        // R factor: [maxit][maxit]
+};
+
+struct GState {
+  int iter;    // columns of the Hessenberg matrix built so far
+  int active;  // 1 while iterating
+  int status;  // 0 ok, 1 converged, 2 max_iter, 3 non-finite, 4 breakdown
+  int pad;
+  double r0;   // initial residual norm
+  double res;  // |g_{iter}| (recursive residual)
+  double ref;  // reference norm of the stopping test |g| <= tol * ref
+};
+
+}  // namespace smpm

@@ -1,0 +1,96 @@
+// Host-side data of the SMPM Schur solver: per-system operator tables built
+// in FP64 at setup time and uploaded once.  No device code here.
+#pragma once
+#include <cstdint>
+#include <functional>
+#include <string>
+#include <vector>
+
+namespace smpm {
+
+// ---- dense FP64 helpers (row-major) ---------------------------------------
+// C[M x N] = beta * C + alpha * A[M x K] * B[K x N]; leading dimensions in
+// elements.  Serial; callers parallelize over independent tasks.
+void gemm(int M, int N, int K, double alpha, const double *A, int lda,
+          const double *B, int ldb, double beta, double *C, int ldc);
+// LU with partial pivoting, in place; returns false on an exactly zero pivot.
+bool getrf(int n, double *A, int lda, int *piv);
+// Solve A X = B with the factors of getrf; B is n x nrhs, leading dim ldb.
+void getrs(int n, int nrhs, const double *LU, int lda, const int *piv, double *B, int ldb);
+// Same with A^T.
+void getrs_t(int n, int nrhs, const double *LU, int lda, const int *piv, double *B, int ldb);
+// In-place inverse of an n x n matrix; false if singular.
+bool invert(int n, double *A, int lda);
+
+// Run fn(i) for i in [0, count) on up to `threads` worker threads.
+void parallel_for(int count, int threads, const std::function<void(int)> &fn);
+int default_threads();
+
+// ---- GLL ------------------------------------------------------------------
+struct GLL {
+  int n;
+  std::vector<double> x, w, D;   // nodes, weights, D row-major n x n
+};
+GLL make_gll(int n);
+
+// ---- one strip class: strips with identical width and boundary type --------
+struct StripClass {
+  double hx;
+  bool west_if, east_if;            // west / east side is an inter-strip interface
+  // block-Thomas factors over the m_z elements: G[e] = (D~_e)^-1, n2 x n2,
+  // row-major on the host.
+  std::vector<double> G;
+  // B-row functionals of this strip's west / east element rows (n values).
+  std::vector<double> betaW, betaE;
+  // W quarter blocks Wq[r][c] (N x N row-major), r: 0 west row, 1 east row;
+  // c: 0 west column, 1 east column.
+  std::vector<double> Wq[2][2];
+};
+
+// ---- one system: a grid and one wavenumber ---------------------------------
+struct System {
+  int n = 0, mx = 0, mz = 0, n2 = 0, N = 0, nh = 0, d = 0;
+  int64_t r = 0, kS = 0;
+  double kwave = 0.0, tau = 0.0;
+  bool singular = false;
+  std::vector<double> xb, zb;
+  std::vector<double> lo, up;            // [e][c]: z-coupling coefficients
+  std::vector<int> strip_class;          // per strip
+  std::vector<StripClass> classes;
+
+  // Schur matvec: for output half h, y_h = x_h + W^_h x[win(h) .. win(h)+2N)
+  // with W^_h an N x 2N block.  Blocks are deduplicated.
+  std::vector<int> w_id, w_win;          // per half
+  std::vector<double> Wblk;              // unique blocks, N x 2N row-major
+  int nW = 0;
+  // Block-Jacobi row chunks: y_h = Mc_h x[m_win(h) .. + m_K(h)).
+  std::vector<int> m_id, m_win, m_K;     // per half
+  std::vector<double> Mblk;              // unique chunks, N x 4N row-major (zero padded)
+  int nM = 0, nMblocks = 0;
+  // Deflation: S Z restricted per half to its two coarse columns.
+  std::vector<int> sz_col;               // per half: [2] coarse columns (-1 if none)
+  std::vector<double> SZh;               // per half: [2][N]
+  std::vector<double> C;                 // d x d row-major
+  std::vector<double> Gc;                // coarse operator C^dagger (I - u_C u_C^T), d x d row-major
+  // Null vectors (k = 0 only).
+  std::vector<double> uS, uL, uC;
+  // Offsets into batched arrays.
+  int64_t f_off = 0, g_off = 0, x_off = 0;
+};
+
+struct SetupOptions {
+  double tau = 0.0;
+  int threads = 0;
+};
+
+// Build every host table of one system.  Throws std::runtime_error with a
+// message on invalid input or singular factorizations.
+void build_system(System &s, int mx, int mz, int order, const double *xb, const double *zb,
+                  double kwave, const SetupOptions &opt);
+
+// Host references used by export and by the setup itself.
+void strip_solve(const System &s, const StripClass &c, double *X, int nrhs);    // A_j^-1 X (in place)
+void strip_solve_t(const System &s, const StripClass &c, double *X, int nrhs);  // A_j^-T X (in place)
+void schur_apply_host(const System &s, const double *x, double *y);             // y = S x
+
+}  // namespace smpm

@@ -1,0 +1,678 @@
+// Host-side FP64 setup of the SMPM Schur solver.
+//
+// Discretization (Sec. 2.2, Eq. smpm_poisson): on each axis-aligned element
+// the operator is the GLL-collocated Laplacian plus, on each edge node, tau
+// times the Robin mismatch (u + n.grad u) - (u_nb + n.grad u_nb) against the
+// neighbour, or tau n.grad u on the physical boundary.  One global tau.
+//
+// Strip split (Sec. 2.3): a strip (m_z elements stacked in z) couples to its
+// neighbours only through B; its local operator A_j(k) = A_j - k^2 I is
+// block tridiagonal over the elements, factored here by block elimination
+// in z (block Thomas).  The Schur blocks W_j = B_rows A_j^-1 E_cols come from
+// a multi-right-hand-side solve with those factors.
+//
+// Block-Jacobi (Sec. 3.2), deflation C = Z^T S Z, S Z (Sec. 3.3) and the null
+// vectors (Sec. 2.4: shifted inverse iteration on S^T - sigma I, then
+// Claim 1 for u_L) follow.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <stdexcept>
+#include <tuple>
+
+#include "host.hpp"
+
+namespace smpm {
+
+// ---------------------------------------------------------------------------
+// GLL nodes (Newton on the Legendre recurrence), weights, and the
+// differentiation matrix in barycentric form with a negative-sum diagonal.
+static void legendre_pair(int N, double x, double &pN, double &pNm1) {
+  double p0 = 1.0, p1 = x;
+  if (N == 0) { pN = 1.0; pNm1 = 0.0; return; }
+  for (int k = 1; k < N; ++k) {
+    const double p2 = ((2.0 * k + 1.0) * x * p1 - k * p0) / (k + 1.0);
+    p0 = p1; p1 = p2;
+  }
+  pN = p1; pNm1 = p0;
+}
+
+GLL make_gll(int n) {
+  if (n < 2) throw std::runtime_error("GLL needs n >= 2");
+  GLL g;
+  g.n = n;
+  g.x.resize(n); g.w.resize(n); g.D.assign((size_t)n * n, 0.0);
+  const int N = n - 1;
+  g.x[0] = -1.0; g.x[N] = 1.0;
+  for (int i = 1; i < N; ++i) {
+    double x = -std::cos(M_PI * i / N);
+    for (int it = 0; it < 100; ++it) {
+      // (1 - x^2) P'_N = N (P_{N-1} - x P_N); roots via q = P_{N+1} - P_{N-1},
+      // q' = (2N + 1) P_N.
+      double pN, pNm1, pN1, dummy;
+      legendre_pair(N, x, pN, pNm1);
+      legendre_pair(N + 1, x, pN1, dummy);
+      const double dx = (pN1 - pNm1) / ((2.0 * N + 1.0) * pN);
+      x -= dx;
+      if (std::fabs(dx) < 1e-16) break;
+    }
+    g.x[i] = x;
+  }
+  std::sort(g.x.begin(), g.x.end());
+  for (int i = 0; i < n; ++i) {
+    double pN, pNm1;
+    legendre_pair(N, g.x[i], pN, pNm1);
+    g.w[i] = 2.0 / (N * (N + 1.0) * pN * pN);
+  }
+  std::vector<double> lam(n, 1.0);   // barycentric weights
+  for (int j = 0; j < n; ++j) {
+    double p = 1.0;
+    for (int k = 0; k < n; ++k)
+      if (k != j) p *= (g.x[j] - g.x[k]);
+    lam[j] = 1.0 / p;
+  }
+  for (int i = 0; i < n; ++i) {
+    double s = 0.0;
+    for (int j = 0; j < n; ++j)
+      if (j != i) {
+        const double v = (lam[j] / lam[i]) / (g.x[i] - g.x[j]);
+        g.D[(size_t)i * n + j] = v;
+        s += v;
+      }
+    g.D[(size_t)i * n + i] = -s;
+  }
+  return g;
+}
+
+// ---------------------------------------------------------------------------
+// Strip operator pieces.  Local node index l = b * n + a.
+static void element_diag_block(const System &s, const GLL &g, double hx, double hz,
+                               bool w_if, bool e_if, bool s_if, bool n_if,
+                               std::vector<double> &Dg) {
+  const int n = s.n, n2 = s.n2;
+  const double *D = g.D.data();
+  std::vector<double> D2((size_t)n * n, 0.0);
+  gemm(n, n, n, 1.0, D, n, D, n, 0.0, D2.data(), n);
+  Dg.assign((size_t)n2 * n2, 0.0);
+  auto at = [&](int b, int a, int bb, int aa) -> double & {
+    return Dg[(size_t)(b * n + a) * n2 + (bb * n + aa)];
+  };
+  const double cx = (2.0 / hx), cz = (2.0 / hz);
+  const double tau = s.tau;
+  for (int b = 0; b < n; ++b)
+    for (int a = 0; a < n; ++a)
+      for (int c = 0; c < n; ++c) {
+        at(b, a, b, c) += cx * cx * D2[(size_t)a * n + c];
+        at(b, a, c, a) += cz * cz * D2[(size_t)b * n + c];
+      }
+  for (int t = 0; t < n; ++t) {
+    // west side a = 0, outward normal -x
+    for (int c = 0; c < n; ++c) at(t, 0, t, c) += tau * (-cx * D[c]);
+    if (w_if) at(t, 0, t, 0) += tau;
+    // east side a = n - 1, outward normal +x
+    for (int c = 0; c < n; ++c) at(t, n - 1, t, c) += tau * (cx * D[(size_t)(n - 1) * n + c]);
+    if (e_if) at(t, n - 1, t, n - 1) += tau;
+    // south side b = 0, outward normal -z
+    for (int c = 0; c < n; ++c) at(0, t, c, t) += tau * (-cz * D[c]);
+    if (s_if) at(0, t, 0, t) += tau;
+    // north side b = n - 1, outward normal +z
+    for (int c = 0; c < n; ++c) at(n - 1, t, c, t) += tau * (cz * D[(size_t)(n - 1) * n + c]);
+    if (n_if) at(n - 1, t, n - 1, t) += tau;
+  }
+  const double k2 = s.kwave * s.kwave;
+  if (k2 != 0.0)
+    for (int l = 0; l < n2; ++l) Dg[(size_t)l * n2 + l] -= k2;
+}
+
+// Factor one strip class: G[e] = (D~_e)^-1 with
+// D~_0 = Dg_0, D~_e = Dg_e - Lo_e G_{e-1} Up_{e-1}.  Lo_e acts on element
+// e-1's column t (coefficients lo[e][c] on (c, t)) into row (0, t) of e; Up_e
+// acts on element e+1's column t into row (n-1, t) of e.
+static void factor_class(const System &s, const GLL &g, StripClass &cl) {
+  const int n = s.n, n2 = s.n2, mz = s.mz;
+  cl.G.assign((size_t)mz * n2 * n2, 0.0);
+  std::vector<double> Dg;
+  for (int e = 0; e < mz; ++e) {
+    const double hz = s.zb[e + 1] - s.zb[e];
+    element_diag_block(s, g, cl.hx, hz, cl.west_if, cl.east_if, e > 0, e < mz - 1, Dg);
+    if (e > 0) {
+      const double *Gp = &cl.G[(size_t)(e - 1) * n2 * n2];
+      const double *lo = &s.lo[(size_t)e * n];
+      const double *upp = &s.up[(size_t)(e - 1) * n];
+      for (int t = 0; t < n; ++t)
+        for (int tp = 0; tp < n; ++tp) {
+          double gam = 0.0;   // sum_c lo[c] G_{e-1}[(c,t)][(n-1,tp)]
+          for (int c = 0; c < n; ++c) gam += lo[c] * Gp[(size_t)(c * n + t) * n2 + ((n - 1) * n + tp)];
+          if (gam == 0.0) continue;
+          for (int cp = 0; cp < n; ++cp) Dg[(size_t)(0 * n + t) * n2 + (cp * n + tp)] -= gam * upp[cp];
+        }
+    }
+    if (!invert(n2, Dg.data(), n2))
+      throw std::runtime_error("singular element block in the strip factorization");
+    std::memcpy(&cl.G[(size_t)e * n2 * n2], Dg.data(), sizeof(double) * n2 * n2);
+  }
+}
+
+void strip_solve(const System &s, const StripClass &cl, double *X, int nrhs) {
+  const int n = s.n, n2 = s.n2, mz = s.mz;
+  std::vector<double> R((size_t)n2 * nrhs), q((size_t)n * nrhs);
+  for (int e = 0; e < mz; ++e) {
+    double *Xe = X + (size_t)e * n2 * nrhs;
+    std::memcpy(R.data(), Xe, sizeof(double) * n2 * nrhs);
+    if (e > 0) {
+      const double *Wp = X + (size_t)(e - 1) * n2 * nrhs;   // w_{e-1}
+      const double *lo = &s.lo[(size_t)e * n];
+      for (int t = 0; t < n; ++t)
+        for (int c = 0; c < n; ++c) {
+          const double cf = lo[c];
+          if (cf == 0.0) continue;
+          const double *src = Wp + (size_t)(c * n + t) * nrhs;
+          double *dst = &R[(size_t)(0 * n + t) * nrhs];
+          for (int j = 0; j < nrhs; ++j) dst[j] -= cf * src[j];
+        }
+    }
+    gemm(n2, nrhs, n2, 1.0, &cl.G[(size_t)e * n2 * n2], n2, R.data(), nrhs, 0.0, Xe, nrhs);
+  }
+  for (int e = mz - 2; e >= 0; --e) {
+    const double *Xn = X + (size_t)(e + 1) * n2 * nrhs;
+    const double *up = &s.up[(size_t)e * n];
+    std::fill(q.begin(), q.end(), 0.0);
+    for (int t = 0; t < n; ++t)
+      for (int c = 0; c < n; ++c) {
+        const double cf = up[c];
+        if (cf == 0.0) continue;
+        const double *src = Xn + (size_t)(c * n + t) * nrhs;
+        for (int j = 0; j < nrhs; ++j) q[(size_t)t * nrhs + j] += cf * src[j];
+      }
+    // X_e -= G_e[:, (n-1, t)] q[t]
+    const double *Ge = &cl.G[(size_t)e * n2 * n2];
+    double *Xe = X + (size_t)e * n2 * nrhs;
+    for (int row = 0; row < n2; ++row) {
+      double *dst = Xe + (size_t)row * nrhs;
+      for (int t = 0; t < n; ++t) {
+        const double gv = Ge[(size_t)row * n2 + (n - 1) * n + t];
+        if (gv == 0.0) continue;
+        const double *src = &q[(size_t)t * nrhs];
+        for (int j = 0; j < nrhs; ++j) dst[j] -= gv * src[j];
+      }
+    }
+  }
+}
+
+void strip_solve_t(const System &s, const StripClass &cl, double *X, int nrhs) {
+  // A = L D~ U with L_{e,e-1} = Lo_e G_{e-1}, U_{e,e+1} = G_e Up_e.
+  // A^T x = v: U^T p = v, q = G^T p, L^T x = q.
+  const int n = s.n, n2 = s.n2, mz = s.mz;
+  std::vector<double> y((size_t)n2 * nrhs), P((size_t)mz * n2 * nrhs);
+  for (int e = 0; e < mz; ++e) {
+    double *Pe = &P[(size_t)e * n2 * nrhs];
+    std::memcpy(Pe, X + (size_t)e * n2 * nrhs, sizeof(double) * n2 * nrhs);
+    if (e > 0) {
+      // y = G_{e-1}^T p_{e-1}; only rows (n-1, t) of y are needed.
+      const double *Gp = &cl.G[(size_t)(e - 1) * n2 * n2];
+      const double *Pp = &P[(size_t)(e - 1) * n2 * nrhs];
+      const double *upp = &s.up[(size_t)(e - 1) * n];
+      for (int t = 0; t < n; ++t) {
+        const int rowy = (n - 1) * n + t;
+        std::vector<double> acc(nrhs, 0.0);
+        for (int l = 0; l < n2; ++l) {
+          const double gv = Gp[(size_t)l * n2 + rowy];
+          if (gv == 0.0) continue;
+          for (int j = 0; j < nrhs; ++j) acc[j] += gv * Pp[(size_t)l * nrhs + j];
+        }
+        // (Up_{e-1}^T y)[(c, t)] = up_{e-1}[c] y[(n-1, t)]
+        for (int c = 0; c < n; ++c)
+          for (int j = 0; j < nrhs; ++j) Pe[(size_t)(c * n + t) * nrhs + j] -= upp[c] * acc[j];
+      }
+    }
+  }
+  // q_e = G_e^T p_e; then backward L^T.
+  for (int e = mz - 1; e >= 0; --e) {
+    const double *Ge = &cl.G[(size_t)e * n2 * n2];
+    double *Pe = &P[(size_t)e * n2 * nrhs];
+    if (e < mz - 1) {
+      // p_e -= (Lo_{e+1}^T x_{e+1}) BEFORE applying G_e^T: x_e = G_e^T (p_e - Lo_{e+1}^T x_{e+1})
+      // is equivalent to q_e - G_e^T Lo_{e+1}^T x_{e+1}.
+      const double *Xn = X + (size_t)(e + 1) * n2 * nrhs;
+      const double *lo = &s.lo[(size_t)(e + 1) * n];
+      for (int t = 0; t < n; ++t)
+        for (int c = 0; c < n; ++c)
+          for (int j = 0; j < nrhs; ++j)
+            Pe[(size_t)(c * n + t) * nrhs + j] -= lo[c] * Xn[(size_t)(0 * n + t) * nrhs + j];
+    }
+    // X_e = G_e^T Pe
+    double *Xe = X + (size_t)e * n2 * nrhs;
+    std::fill(y.begin(), y.end(), 0.0);
+    for (int l = 0; l < n2; ++l) {
+      const double *gl = Ge + (size_t)l * n2;
+      const double *pl = Pe + (size_t)l * nrhs;
+      for (int row = 0; row < n2; ++row) {
+        const double gv = gl[row];
+        if (gv == 0.0) continue;
+        double *dst = &y[(size_t)row * nrhs];
+        for (int j = 0; j < nrhs; ++j) dst[j] += gv * pl[j];
+      }
+    }
+    std::memcpy(Xe, y.data(), sizeof(double) * n2 * nrhs);
+  }
+}
+
+// W quarter blocks of one class from a 2N-right-hand-side strip solve.
+static void class_schur_blocks(const System &s, StripClass &cl) {
+  const int n = s.n, n2 = s.n2, mz = s.mz, N = s.N;
+  const int nr = 2 * N;
+  std::vector<double> X((size_t)mz * n2 * nr, 0.0);
+  for (int e = 0; e < mz; ++e)
+    for (int b = 0; b < n; ++b) {
+      const int col = e * n + b;
+      X[((size_t)e * n2 + b * n + 0) * nr + col] = 1.0;          // west injection
+      X[((size_t)e * n2 + b * n + (n - 1)) * nr + N + col] = 1.0; // east injection
+    }
+  strip_solve(s, cl, X.data(), nr);
+  for (int r = 0; r < 2; ++r)
+    for (int c = 0; c < 2; ++c) {
+      const std::vector<double> &beta = r == 0 ? cl.betaW : cl.betaE;
+      std::vector<double> &Wq = cl.Wq[r][c];
+      Wq.assign((size_t)N * N, 0.0);
+      for (int e = 0; e < mz; ++e)
+        for (int b = 0; b < n; ++b) {
+          double *dst = &Wq[(size_t)(e * n + b) * N];
+          for (int a = 0; a < n; ++a) {
+            const double *src = &X[((size_t)e * n2 + b * n + a) * nr + c * N];
+            const double bv = beta[a];
+            for (int q = 0; q < N; ++q) dst[q] += bv * src[q];
+          }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+void schur_apply_host(const System &s, const double *x, double *y) {
+  const int N = s.N;
+  for (int h = 0; h < s.nh; ++h) {
+    const double *W = &s.Wblk[(size_t)s.w_id[h] * N * 2 * N];
+    for (int i = 0; i < N; ++i) {
+      double acc = x[(size_t)h * N + i];
+      for (int c = 0; c < 2 * N; ++c) {
+        const int64_t idx = (int64_t)s.w_win[h] * N + c;
+        if (idx < 0 || idx >= s.kS) continue;
+        acc += W[(size_t)i * 2 * N + c] * x[idx];
+      }
+      y[(size_t)h * N + i] = acc;
+    }
+  }
+}
+
+static double norm2(const std::vector<double> &v) {
+  double s = 0.0;
+  for (double a : v) s += a * a;
+  return std::sqrt(s);
+}
+
+// Left null vector of S (k = 0) by shifted inverse iteration on S^T - sigma I
+// (Sec. 2.4).  S is block tridiagonal over interfaces (2N x 2N blocks); the
+// shifted transpose is factored by block elimination, the diagonal blocks
+// with partial pivoting.
+static void left_null_schur(System &s) {
+  const int N = s.N, M = 2 * N, d = s.d;
+  // Interface blocks of S: Sd[i] (M x M), Su[i] = S[i][i+1] (upper-left N x N
+  // of rows of half 2i, cols of half 2i+2), Sl[i] = S[i][i-1] (rows of half
+  // 2i+1, cols of half 2i-1).
+  auto Wpart = [&](int h, int p, int i, int c) -> double {
+    return s.Wblk[(size_t)s.w_id[h] * N * 2 * N + (size_t)i * 2 * N + p * N + c];
+  };
+  double snorm = 0.0;
+  for (int h = 0; h < s.nh; ++h)
+    for (int i = 0; i < N; ++i) {
+      double rs = 1.0;
+      for (int c = 0; c < 2 * N; ++c) rs += std::fabs(Wpart(h, 0, i, c));
+      snorm = std::max(snorm, rs);
+    }
+  const double sigma = 1e-10 * snorm;
+  // T = S^T - sigma I; blocks: T[i][i] = Sd[i]^T - sigma, T[i][i+1] = Sl[i+1]^T,
+  // T[i][i-1] = Su[i-1]^T.
+  std::vector<double> LU((size_t)d * M * M), X((size_t)d * M * N);
+  std::vector<int> piv((size_t)d * M);
+  for (int i = 0; i < d; ++i) {
+    double *T = &LU[(size_t)i * M * M];
+    std::fill(T, T + (size_t)M * M, 0.0);
+    // Sd[i] rows 0..N (half 2i): cols N..2N (half 2i+1) = W^_{2i} part 0.
+    // rows N..2N (half 2i+1): cols 0..N (half 2i) = W^_{2i+1} part 1.
+    for (int a = 0; a < M; ++a) T[(size_t)a * M + a] = 1.0 - sigma;
+    for (int r = 0; r < N; ++r)
+      for (int c = 0; c < N; ++c) {
+        // T = Sd^T: T[col][row] = Sd[row][col]
+        T[(size_t)(N + c) * M + r] += Wpart(2 * i, 0, r, c);
+        T[(size_t)c * M + (N + r)] += Wpart(2 * i + 1, 1, r, c);
+      }
+    if (i > 0) {
+      // T_i -= T[i][i-1] X_{i-1}, T[i][i-1] = Su[i-1]^T: Su[i-1] has rows of
+      // half 2i-2 (0..N) and cols of half 2i (0..N) = W^_{2i-2} part 1.
+      // X_{i-1} = T~_{i-1}^-1 T[i-1][i] has nonzero columns N..2N only.
+      const double *Xp = &X[(size_t)(i - 1) * M * N];
+      std::vector<double> SuT((size_t)N * N);
+      for (int r = 0; r < N; ++r)
+        for (int c = 0; c < N; ++c) SuT[(size_t)c * N + r] = Wpart(2 * i - 2, 1, r, c);
+      // T[0..N][N..2N] -= SuT (N x N) * Xp[0..N][0..N]
+      gemm(N, N, N, -1.0, SuT.data(), N, Xp, N, 1.0, T + N, M);
+    }
+    if (!getrf(M, T, M, &piv[(size_t)i * M]))
+      throw std::runtime_error("singular block in the inverse iteration for u_S");
+    if (i + 1 < d) {
+      // X_i = T~_i^-1 T[i][i+1]; T[i][i+1] = Sl[i+1]^T: Sl[i+1] rows of half
+      // 2i+3 (N..2N of interface i+1), cols of half 2i+1 (N..2N of interface i)
+      // = W^_{2i+3} part 0.  Nonzero block at rows N..2N, cols N..2N.
+      std::vector<double> B((size_t)M * N, 0.0);   // only the N nonzero columns
+      for (int r = 0; r < N; ++r)
+        for (int c = 0; c < N; ++c) B[(size_t)(N + c) * N + r] = Wpart(2 * i + 3, 0, r, c);
+      getrs(M, N, T, M, &piv[(size_t)i * M], B.data(), N);
+      std::memcpy(&X[(size_t)i * M * N], B.data(), sizeof(double) * M * N);
+    }
+  }
+  auto solve = [&](std::vector<double> &v) {
+    // forward: y_i = v_i - T[i][i-1] T~_{i-1}^-1 y_{i-1}
+    std::vector<double> tmp(M);
+    for (int i = 1; i < d; ++i) {
+      std::memcpy(tmp.data(), &v[(size_t)(i - 1) * M], sizeof(double) * M);
+      getrs(M, 1, &LU[(size_t)(i - 1) * M * M], M, &piv[(size_t)(i - 1) * M], tmp.data(), 1);
+      for (int r = 0; r < N; ++r) {
+        double acc = 0.0;   // (Su[i-1]^T tmp[0..N])_r = sum_c Su[i-1][c][r] tmp[c]
+        for (int c = 0; c < N; ++c) acc += Wpart(2 * i - 2, 1, c, r) * tmp[c];
+        v[(size_t)i * M + r] -= acc;
+      }
+    }
+    // backward: x_i = T~_i^-1 y_i - X_i x_{i+1}[N..2N]
+    for (int i = d - 1; i >= 0; --i) {
+      double *vi = &v[(size_t)i * M];
+      getrs(M, 1, &LU[(size_t)i * M * M], M, &piv[(size_t)i * M], vi, 1);
+      if (i + 1 < d) {
+        const double *xn = &v[(size_t)(i + 1) * M + N];
+        const double *Xi = &X[(size_t)i * M * N];
+        for (int r = 0; r < M; ++r) {
+          double acc = 0.0;
+          for (int c = 0; c < N; ++c) acc += Xi[(size_t)r * N + c] * xn[c];
+          vi[r] -= acc;
+        }
+      }
+    }
+  };
+  std::vector<double> u(s.kS, 1.0 / std::sqrt((double)s.kS));
+  std::vector<double> Stu(s.kS);
+  for (int it = 0; it < 6; ++it) {
+    solve(u);
+    const double nu = norm2(u);
+    if (!(nu > 0.0) || !std::isfinite(nu)) throw std::runtime_error("inverse iteration for u_S failed");
+    for (auto &a : u) a /= nu;
+    // residual ||S^T u|| / ||S||
+    std::fill(Stu.begin(), Stu.end(), 0.0);
+    for (int h = 0; h < s.nh; ++h)
+      for (int i = 0; i < N; ++i) {
+        const double ui = u[(size_t)h * N + i];
+        Stu[(size_t)h * N + i] += ui;
+        for (int c = 0; c < 2 * N; ++c) {
+          const int64_t idx = (int64_t)s.w_win[h] * N + c;
+          if (idx < 0 || idx >= s.kS) continue;
+          Stu[idx] += Wpart(h, 0, i, c) * ui;
+        }
+      }
+    if (norm2(Stu) <= 1e-13 * snorm && it >= 1) break;
+  }
+  double sum = 0.0;
+  for (double a : u) sum += a;
+  if (sum < 0) for (auto &a : u) a = -a;
+  s.uS = u;
+}
+
+void build_system(System &s, int mx, int mz, int order, const double *xb, const double *zb,
+                  double kwave, const SetupOptions &opt) {
+  if (mx < 2 || mz < 1 || order < 1) throw std::invalid_argument("need mx >= 2, mz >= 1, order >= 1");
+  if (!(kwave >= 0.0) || !std::isfinite(kwave)) throw std::invalid_argument("wavenumber must be finite and >= 0");
+  s.n = order + 1; s.mx = mx; s.mz = mz;
+  s.n2 = s.n * s.n; s.N = s.n * mz; s.nh = 2 * (mx - 1); s.d = mx - 1;
+  s.r = (int64_t)s.n2 * mx * mz; s.kS = (int64_t)s.N * s.nh;
+  s.kwave = kwave; s.singular = (kwave == 0.0);
+  s.xb.assign(xb, xb + mx + 1); s.zb.assign(zb, zb + mz + 1);
+  double hmin = 1e300;
+  for (int j = 0; j < mx; ++j) {
+    const double h = s.xb[j + 1] - s.xb[j];
+    if (!(h > 0.0) || !std::isfinite(h)) throw std::invalid_argument("x breakpoints must be finite and increasing");
+    hmin = std::min(hmin, h);
+  }
+  for (int e = 0; e < mz; ++e) {
+    const double h = s.zb[e + 1] - s.zb[e];
+    if (!(h > 0.0) || !std::isfinite(h)) throw std::invalid_argument("z breakpoints must be finite and increasing");
+    hmin = std::min(hmin, h);
+  }
+  if (s.singular && mx < 4)
+    throw std::domain_error("k = 0 needs m_x >= 4 (a block-Jacobi block would be all of the singular S)");
+  const int n = s.n, N = s.N;
+  s.tau = opt.tau != 0.0 ? opt.tau : -(double)n * (n - 1) / hmin;
+  const GLL g = make_gll(n);
+  const double *D = g.D.data();
+  const double tau = s.tau;
+  // z couplings inside a strip
+  s.lo.assign((size_t)mz * n, 0.0);
+  s.up.assign((size_t)mz * n, 0.0);
+  for (int e = 0; e < mz; ++e) {
+    if (e > 0) {
+      const double hzp = s.zb[e] - s.zb[e - 1];
+      for (int c = 0; c < n; ++c)
+        s.lo[(size_t)e * n + c] = (c == n - 1 ? -tau : 0.0) + tau * (2.0 / hzp) * D[(size_t)(n - 1) * n + c];
+    }
+    if (e < mz - 1) {
+      const double hzn = s.zb[e + 2] - s.zb[e + 1];
+      for (int c = 0; c < n; ++c)
+        s.up[(size_t)e * n + c] = (c == 0 ? -tau : 0.0) - tau * (2.0 / hzn) * D[c];
+    }
+  }
+  // strip classes: equal width (to 1e-13 relative) and equal boundary type
+  s.strip_class.assign(mx, -1);
+  for (int j = 0; j < mx; ++j) {
+    const double hx = s.xb[j + 1] - s.xb[j];
+    const bool wif = j > 0, eif = j < mx - 1;
+    int found = -1;
+    for (int c = 0; c < (int)s.classes.size(); ++c) {
+      const StripClass &cl = s.classes[c];
+      if (cl.west_if == wif && cl.east_if == eif && std::fabs(cl.hx - hx) <= 1e-13 * hx) { found = c; break; }
+    }
+    if (found < 0) {
+      StripClass cl;
+      cl.hx = hx; cl.west_if = wif; cl.east_if = eif;
+      cl.betaW.resize(n); cl.betaE.resize(n);
+      for (int c = 0; c < n; ++c) {
+        cl.betaW[c] = (c == 0 ? -tau : 0.0) - tau * (2.0 / hx) * D[c];
+        cl.betaE[c] = (c == n - 1 ? -tau : 0.0) + tau * (2.0 / hx) * D[(size_t)(n - 1) * n + c];
+      }
+      s.classes.push_back(cl);
+      found = (int)s.classes.size() - 1;
+    }
+    s.strip_class[j] = found;
+  }
+  parallel_for((int)s.classes.size(), opt.threads, [&](int c) {
+    factor_class(s, g, s.classes[c]);
+    class_schur_blocks(s, s.classes[c]);
+  });
+  // Schur blocks per output half, deduplicated by (strip class, row side).
+  s.w_id.assign(s.nh, -1); s.w_win.assign(s.nh, 0);
+  std::map<std::pair<int, int>, int> wmap;
+  std::vector<std::pair<int, int>> wkeys;
+  for (int h = 0; h < s.nh; ++h) {
+    const int i = h / 2;
+    const bool even = (h % 2 == 0);
+    const int strip = even ? i + 1 : i;
+    const int rside = even ? 0 : 1;
+    s.w_win[h] = even ? h + 1 : h - 2;
+    const auto key = std::make_pair(s.strip_class[strip], rside);
+    auto it = wmap.find(key);
+    if (it == wmap.end()) {
+      it = wmap.emplace(key, (int)wkeys.size()).first;
+      wkeys.push_back(key);
+    }
+    s.w_id[h] = it->second;
+  }
+  s.nW = (int)wkeys.size();
+  s.Wblk.assign((size_t)s.nW * N * 2 * N, 0.0);
+  for (int b = 0; b < s.nW; ++b) {
+    const StripClass &cl = s.classes[wkeys[b].first];
+    const int rs = wkeys[b].second;
+    for (int c = 0; c < 2; ++c) {
+      const bool exists = (c == 0 ? cl.west_if : cl.east_if) && (rs == 0 ? cl.west_if : cl.east_if);
+      if (!exists) continue;
+      const std::vector<double> &Wq = cl.Wq[rs][c];
+      for (int i = 0; i < N; ++i)
+        std::memcpy(&s.Wblk[(size_t)b * N * 2 * N + (size_t)i * 2 * N + c * N], &Wq[(size_t)i * N], sizeof(double) * N);
+    }
+  }
+  // Block-Jacobi: blocks over interfaces (2b, 2b+1), deduplicated.
+  s.m_id.assign(s.nh, -1); s.m_win.assign(s.nh, 0); s.m_K.assign(s.nh, 0);
+  const int nblocks = (s.d + 1) / 2;
+  s.nMblocks = nblocks;
+  std::map<std::vector<int>, int> mmap;
+  std::vector<int> mfirst;   // representative block of each unique M
+  std::vector<int> mblock_uid(nblocks);
+  for (int b = 0; b < nblocks; ++b) {
+    const int h0 = 4 * b;
+    const int nhb = std::min(4, s.nh - h0);
+    std::vector<int> key = {nhb};
+    for (int q = 0; q < nhb; ++q) { key.push_back(s.w_id[h0 + q]); key.push_back(s.w_win[h0 + q] - h0); }
+    auto it = mmap.find(key);
+    if (it == mmap.end()) { it = mmap.emplace(key, (int)mfirst.size()).first; mfirst.push_back(b); }
+    mblock_uid[b] = it->second;
+  }
+  const int nMu = (int)mfirst.size();
+  std::vector<std::vector<double>> Minv(nMu);
+  parallel_for(nMu, opt.threads, [&](int u) {
+    const int b = mfirst[u];
+    const int h0 = 4 * b;
+    const int nhb = std::min(4, s.nh - h0);
+    const int K = nhb * N;
+    std::vector<double> Mb((size_t)K * K, 0.0);
+    for (int a = 0; a < K; ++a) Mb[(size_t)a * K + a] = 1.0;
+    for (int q = 0; q < nhb; ++q) {
+      const int h = h0 + q;
+      const double *W = &s.Wblk[(size_t)s.w_id[h] * N * 2 * N];
+      for (int p = 0; p < 2; ++p) {
+        const int wh = s.w_win[h] + p;
+        if (wh < h0 || wh >= h0 + nhb) continue;
+        const int lc = wh - h0;
+        for (int i = 0; i < N; ++i)
+          for (int c = 0; c < N; ++c) Mb[(size_t)(q * N + i) * K + lc * N + c] += W[(size_t)i * 2 * N + p * N + c];
+      }
+    }
+    if (!invert(K, Mb.data(), K)) throw std::domain_error("singular block-Jacobi block");
+    Minv[u] = std::move(Mb);
+  });
+  s.nM = nMu * 4;
+  s.Mblk.assign((size_t)s.nM * N * 4 * N, 0.0);
+  for (int u = 0; u < nMu; ++u) {
+    const int b = mfirst[u];
+    const int nhb = std::min(4, s.nh - 4 * b);
+    const int K = nhb * N;
+    for (int q = 0; q < nhb; ++q)
+      for (int i = 0; i < N; ++i)
+        std::memcpy(&s.Mblk[((size_t)(u * 4 + q) * N + i) * 4 * N], &Minv[u][(size_t)(q * N + i) * K], sizeof(double) * K);
+  }
+  for (int b = 0; b < nblocks; ++b) {
+    const int h0 = 4 * b;
+    const int nhb = std::min(4, s.nh - h0);
+    for (int q = 0; q < nhb; ++q) {
+      s.m_id[h0 + q] = mblock_uid[b] * 4 + q;
+      s.m_win[h0 + q] = h0;
+      s.m_K[h0 + q] = nhb * N;
+    }
+  }
+  // Deflation tables: S Z per half (two coarse columns), C = Z^T S Z.
+  s.sz_col.assign((size_t)s.nh * 2, -1);
+  s.SZh.assign((size_t)s.nh * 2 * N, 0.0);
+  s.C.assign((size_t)s.d * s.d, 0.0);
+  for (int h = 0; h < s.nh; ++h) {
+    const int i = h / 2;
+    const bool even = (h % 2 == 0);
+    const int ca = even ? i : i - 1, cb = even ? i + 1 : i;
+    s.sz_col[(size_t)h * 2 + 0] = (ca >= 0 && ca < s.d) ? ca : -1;
+    s.sz_col[(size_t)h * 2 + 1] = (cb >= 0 && cb < s.d) ? cb : -1;
+    const double *W = &s.Wblk[(size_t)s.w_id[h] * N * 2 * N];
+    for (int p = 0; p < 2; ++p) {
+      const int col = s.sz_col[(size_t)h * 2 + p];
+      if (col < 0) continue;
+      double tot = 0.0;
+      for (int r = 0; r < N; ++r) {
+        double rs = 0.0;
+        for (int c = 0; c < N; ++c) rs += W[(size_t)r * 2 * N + p * N + c];
+        if ((p == 0 && even) || (p == 1 && !even)) rs += 1.0;
+        s.SZh[((size_t)h * 2 + p) * N + r] = rs;
+        tot += rs;
+      }
+      s.C[(size_t)i * s.d + col] += tot;
+    }
+  }
+  // Coarse operator.
+  const int d = s.d;
+  s.Gc.assign((size_t)d * d, 0.0);
+  if (!s.singular) {
+    std::vector<double> Ci = s.C;
+    if (!invert(d, Ci.data(), d)) throw std::domain_error("singular coarse matrix C(k)");
+    s.Gc = Ci;
+  } else {
+    // u_C: C^T u = 0 with u_{d-1} = 1 (the leading (d-1) block is invertible).
+    const int m = d - 1;
+    std::vector<double> Cm((size_t)m * m), rhs(m);
+    for (int i = 0; i < m; ++i)
+      for (int j = 0; j < m; ++j) Cm[(size_t)i * m + j] = s.C[(size_t)i * d + j];
+    std::vector<int> piv(m);
+    if (!getrf(m, Cm.data(), m, piv.data())) throw std::domain_error("singular leading block of C");
+    for (int i = 0; i < m; ++i) rhs[i] = -s.C[(size_t)(d - 1) * d + i];
+    getrs_t(m, 1, Cm.data(), m, piv.data(), rhs.data(), 1);
+    std::vector<double> uC(d, 1.0);
+    for (int i = 0; i < m; ++i) uC[i] = rhs[i];
+    const double nu = norm2(uC);
+    double sum = 0.0;
+    for (auto &a : uC) { a /= nu; sum += a; }
+    if (sum < 0) for (auto &a : uC) a = -a;
+    s.uC = uC;
+    // G = [[C_m^-1, 0], [0, 0]] (I - u_C u_C^T): the last coarse unknown is
+    // pinned to zero (any solution of the consistent system works, P is
+    // unchanged by a shift along 1_d).
+    std::vector<double> Cinv((size_t)m * m, 0.0);
+    for (int i = 0; i < m; ++i) Cinv[(size_t)i * m + i] = 1.0;
+    getrs(m, m, Cm.data(), m, piv.data(), Cinv.data(), m);
+    for (int i = 0; i < m; ++i)
+      for (int j = 0; j < d; ++j) {
+        double acc = 0.0;
+        for (int l = 0; l < m; ++l) acc += Cinv[(size_t)i * m + l] * ((l == j ? 1.0 : 0.0) - uC[l] * uC[j]);
+        s.Gc[(size_t)i * d + j] = acc;
+      }
+    // Null vectors of S and L.
+    left_null_schur(s);
+    // u_L = A^-T B^T u_S (Claim 1, part 2)
+    std::vector<double> uL(s.r, 0.0);
+    const int n2 = s.n2;
+    for (int j = 0; j < mx; ++j) {
+      const StripClass &cl = s.classes[s.strip_class[j]];
+      double *v = &uL[(size_t)j * mz * n2];
+      for (int e = 0; e < mz; ++e)
+        for (int b = 0; b < n; ++b) {
+          const int row = e * n + b;
+          if (j >= 1) {   // west row read by Gamma_{j-1}^L (half 2j - 2)
+            const double us = s.uS[(size_t)(2 * j - 2) * N + row];
+            for (int c = 0; c < n; ++c) v[(size_t)e * n2 + b * n + c] += cl.betaW[c] * us;
+          }
+          if (j <= mx - 2) {   // east row read by Gamma_j^R (half 2j + 1)
+            const double us = s.uS[(size_t)(2 * j + 1) * N + row];
+            for (int c = 0; c < n; ++c) v[(size_t)e * n2 + b * n + c] += cl.betaE[c] * us;
+          }
+        }
+    }
+    parallel_for(mx, opt.threads, [&](int j) {
+      strip_solve_t(s, s.classes[s.strip_class[j]], &uL[(size_t)j * mz * n2], 1);
+    });
+    const double nl = norm2(uL);
+    double sl = 0.0;
+    for (auto &a : uL) { a /= nl; sl += a; }
+    if (sl < 0) for (auto &a : uL) a = -a;
+    s.uL = uL;
+  }
+}
+
+}  // namespace smpm

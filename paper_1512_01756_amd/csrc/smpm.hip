@@ -1,0 +1,710 @@
+// C ABI of the SMPM Schur solver: setup (host FP64 tables -> device), the
+// batched Algorithm 2 solve, FP64 iterative refinement around an FP32 inner
+// solve, single-operator applies and table export.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <memory>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "../../include/smpm_schur.h"
+#include "device.hpp"
+#include "host.hpp"
+#include "kernels.hip"
+
+using namespace smpm;
+
+namespace {
+
+thread_local std::string g_err;
+
+smpm_status fail(smpm_status st, const std::string &msg) {
+  g_err = msg;
+  return st;
+}
+
+struct HipError : std::runtime_error {
+  using std::runtime_error::runtime_error;
+};
+
+#define HIPCHECK(expr)                                                                    \
+  do {                                                                                    \
+    hipError_t e_ = (expr);                                                               \
+    if (e_ != hipSuccess)                                                                 \
+      throw HipError(std::string(#expr) + ": " + hipGetErrorString(e_));                  \
+  } while (0)
+
+template <typename T>
+T *dalloc(std::vector<void *> &owned, size_t count) {
+  if (count == 0) count = 1;
+  void *p = nullptr;
+  if (hipMalloc(&p, count * sizeof(T)) != hipSuccess) throw std::bad_alloc();
+  owned.push_back(p);
+  return static_cast<T *>(p);
+}
+
+template <typename T>
+T *dupload(std::vector<void *> &owned, const std::vector<T> &v, hipStream_t st) {
+  T *p = dalloc<T>(owned, v.size());
+  if (!v.empty()) HIPCHECK(hipMemcpyAsync(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, st));
+  return p;
+}
+
+// Column-major copy of row-major blocks: nb blocks of rows x cols.
+template <typename T>
+std::vector<T> to_colmajor(const std::vector<double> &a, int nb, int rows, int cols) {
+  std::vector<T> out((size_t)nb * rows * cols);
+  for (int b = 0; b < nb; ++b)
+    for (int r = 0; r < rows; ++r)
+      for (int c = 0; c < cols; ++c)
+        out[(size_t)b * rows * cols + (size_t)c * rows + r] = (T)a[(size_t)b * rows * cols + (size_t)r * cols + c];
+  return out;
+}
+
+}  // namespace
+
+struct smpm_handle {
+  smpm_opts opts{};
+  int nrhs = 1, maxit = 300, precision = SMPM_FP64, method = SMPM_METHOD_DBJ, max_sweeps = 12;
+  double tol = 1e-10, inner_tol = 1e-5;
+  bool host_only = false;
+  std::vector<System> sys;
+
+  std::vector<void *> owned;
+  std::vector<SysDev> h_sys;
+  std::vector<InstDev> h_ins;
+  SysDev *d_sys = nullptr;
+  InstDev *d_ins = nullptr;
+  int ninst = 0;
+  int2 *w_h = nullptr, *w_x = nullptr, *w_r = nullptr, *w_s = nullptr;
+  int n_h = 0, n_x = 0, n_r = 0, n_s = 0;
+  std::vector<int> h_start, x_start;       // per instance: first work item in w_h / w_x
+  int64_t tot_r = 0, tot_x = 0, tot_g = 0;
+
+  double *F = nullptr, *v = nullptr, *Rr = nullptr, *bS = nullptr, *xS = nullptr, *rb = nullptr;
+  double *z64 = nullptr, *y64 = nullptr, *t64 = nullptr;
+  float *z32 = nullptr, *y32 = nullptr, *t32 = nullptr;
+  double *V64 = nullptr;
+  float *V32 = nullptr;
+  double *part1 = nullptr, *part2 = nullptr, *partn = nullptr, *pr = nullptr, *hs = nullptr, *hs2 = nullptr;
+  double *cv = nullptr, *tb = nullptr, *scale = nullptr, *Rm = nullptr, *cs = nullptr, *sn = nullptr, *g = nullptr;
+  double *ycoef = nullptr, *defect = nullptr, *pairs = nullptr;
+  GState *gs = nullptr;
+  GState *h_gs = nullptr;      // pinned
+  double *h_pairs = nullptr;   // pinned
+  double *h_defect = nullptr;  // pinned
+
+  ~smpm_handle() {
+    for (void *p : owned) (void)hipFree(p);
+    if (h_gs) (void)hipHostFree(h_gs);
+    if (h_pairs) (void)hipHostFree(h_pairs);
+    if (h_defect) (void)hipHostFree(h_defect);
+  }
+};
+
+namespace {
+
+void upload(smpm_handle *H, hipStream_t st) {
+  auto &own = H->owned;
+  const int maxit = H->maxit;
+  // per-system device tables
+  for (System &s : H->sys) {
+    SysDev d{};
+    d.n = s.n; d.mx = s.mx; d.mz = s.mz; d.n2 = s.n2; d.N = s.N; d.nh = s.nh; d.d = s.d;
+    d.singular = s.singular ? 1 : 0; d.kS = s.kS; d.r = s.r; d.tau = s.tau;
+    d.W64 = dupload(own, to_colmajor<double>(s.Wblk, s.nW, s.N, 2 * s.N), st);
+    d.W32 = dupload(own, to_colmajor<float>(s.Wblk, s.nW, s.N, 2 * s.N), st);
+    d.w_id = dupload(own, s.w_id, st);
+    d.w_win = dupload(own, s.w_win, st);
+    d.M64 = dupload(own, to_colmajor<double>(s.Mblk, s.nM, s.N, 4 * s.N), st);
+    d.M32 = dupload(own, to_colmajor<float>(s.Mblk, s.nM, s.N, 4 * s.N), st);
+    d.m_id = dupload(own, s.m_id, st);
+    d.m_win = dupload(own, s.m_win, st);
+    d.m_K = dupload(own, s.m_K, st);
+    d.sz_col = dupload(own, s.sz_col, st);
+    d.SZh = dupload(own, s.SZh, st);
+    d.Gc = dupload(own, to_colmajor<double>(s.Gc, 1, s.d, s.d), st);
+    d.uS = s.singular ? dupload(own, s.uS, st) : nullptr;
+    d.uL = s.singular ? dupload(own, s.uL, st) : nullptr;
+    std::vector<double> Gs, beta;
+    for (const StripClass &c : s.classes) {
+      std::vector<double> cm = to_colmajor<double>(c.G, s.mz, s.n2, s.n2);
+      Gs.insert(Gs.end(), cm.begin(), cm.end());
+      beta.insert(beta.end(), c.betaW.begin(), c.betaW.end());
+      beta.insert(beta.end(), c.betaE.begin(), c.betaE.end());
+    }
+    d.Gs = dupload(own, Gs, st);
+    d.beta = dupload(own, beta, st);
+    d.lo = dupload(own, s.lo, st);
+    d.up = dupload(own, s.up, st);
+    d.strip_class = dupload(own, s.strip_class, st);
+    H->h_sys.push_back(d);
+  }
+  H->d_sys = dupload(own, H->h_sys, st);
+  // instances
+  std::vector<int2> wh, wx, wr, ws;
+  int64_t f_off = 0, g_off = 0, x_off = 0, v_off = 0, part_off = 0, pr_off = 0, hs_off = 0, c_off = 0, st_off = 0, rr_off = 0;
+  for (int si = 0; si < (int)H->sys.size(); ++si) {
+    const System &s = H->sys[si];
+    for (int q = 0; q < H->nrhs; ++q) {
+      InstDev I{};
+      const int inst = (int)H->h_ins.size();
+      I.sys = si; I.rhs = q;
+      I.nchunk_x = (int)((s.kS + kChunk - 1) / kChunk);
+      I.nchunk_r = (int)((s.r + kChunk - 1) / kChunk);
+      I.f_off = f_off; I.g_off = g_off; I.x_off = x_off; I.v_off = v_off;
+      I.part_off = part_off; I.pr_off = pr_off; I.hs_off = hs_off; I.c_off = c_off;
+      I.st_off = st_off; I.rr_off = rr_off;
+      f_off += s.r; g_off += 2LL * s.n * (s.mx + s.mz); x_off += s.kS; v_off += (int64_t)(maxit + 1) * s.kS;
+      part_off += (int64_t)(maxit + 1) * I.nchunk_x + 2; pr_off += 2LL * I.nchunk_r; hs_off += s.nh; c_off += s.d;
+      st_off += maxit + 1; rr_off += (int64_t)maxit * maxit;
+      H->h_start.push_back((int)wh.size());
+      for (int h = 0; h < s.nh; ++h) wh.push_back(make_int2(inst, h));
+      H->x_start.push_back((int)wx.size());
+      for (int c = 0; c < I.nchunk_x; ++c) wx.push_back(make_int2(inst, c));
+      for (int c = 0; c < I.nchunk_r; ++c) wr.push_back(make_int2(inst, c));
+      for (int j = 0; j < s.mx; ++j) ws.push_back(make_int2(inst, j));
+      H->h_ins.push_back(I);
+    }
+  }
+  H->ninst = (int)H->h_ins.size();
+  H->tot_r = f_off; H->tot_x = x_off; H->tot_g = g_off;
+  H->d_ins = dupload(own, H->h_ins, st);
+  H->w_h = dupload(own, wh, st); H->n_h = (int)wh.size();
+  H->w_x = dupload(own, wx, st); H->n_x = (int)wx.size();
+  H->w_r = dupload(own, wr, st); H->n_r = (int)wr.size();
+  H->w_s = dupload(own, ws, st); H->n_s = (int)ws.size();
+  // work buffers
+  H->F = dalloc<double>(own, f_off); H->v = dalloc<double>(own, f_off); H->Rr = dalloc<double>(own, f_off);
+  H->bS = dalloc<double>(own, x_off); H->xS = dalloc<double>(own, x_off); H->rb = dalloc<double>(own, x_off);
+  H->z64 = dalloc<double>(own, x_off); H->y64 = dalloc<double>(own, x_off); H->t64 = dalloc<double>(own, x_off);
+  H->z32 = dalloc<float>(own, x_off); H->y32 = dalloc<float>(own, x_off); H->t32 = dalloc<float>(own, x_off);
+  if (H->precision == SMPM_FP64) H->V64 = dalloc<double>(own, v_off);
+  else H->V32 = dalloc<float>(own, v_off);
+  H->part1 = dalloc<double>(own, part_off); H->part2 = dalloc<double>(own, part_off); H->partn = dalloc<double>(own, part_off);
+  H->pr = dalloc<double>(own, pr_off); H->hs = dalloc<double>(own, hs_off); H->hs2 = dalloc<double>(own, hs_off);
+  H->cv = dalloc<double>(own, c_off); H->tb = dalloc<double>(own, c_off);
+  H->scale = dalloc<double>(own, st_off); H->cs = dalloc<double>(own, st_off); H->sn = dalloc<double>(own, st_off);
+  H->g = dalloc<double>(own, st_off); H->ycoef = dalloc<double>(own, st_off); H->Rm = dalloc<double>(own, rr_off);
+  H->defect = dalloc<double>(own, H->ninst); H->pairs = dalloc<double>(own, 2 * H->ninst);
+  H->gs = dalloc<GState>(own, H->ninst);
+  HIPCHECK(hipHostMalloc((void **)&H->h_gs, sizeof(GState) * H->ninst, hipHostMallocDefault));
+  HIPCHECK(hipHostMalloc((void **)&H->h_pairs, sizeof(double) * 2 * H->ninst, hipHostMallocDefault));
+  HIPCHECK(hipHostMalloc((void **)&H->h_defect, sizeof(double) * H->ninst, hipHostMallocDefault));
+  HIPCHECK(hipStreamSynchronize(st));
+}
+
+// ---------------------------------------------------------------------------
+// Solve steps.
+
+void stage_rhs(smpm_handle *H, const double *f, const double *g, hipStream_t st) {
+  hipLaunchKernelGGL(k_rhs, dim3(H->n_r), dim3(kBlock), 0, st, H->d_sys, H->d_ins, H->w_r, f, g, H->F, H->pr);
+  hipLaunchKernelGGL(k_proj_r, dim3(H->n_r), dim3(kBlock), 0, st, H->d_sys, H->d_ins, H->w_r, H->F, H->pr, H->defect);
+  hipLaunchKernelGGL(k_strip_solve, dim3(H->n_s), dim3(kBlock), 0, st, H->d_sys, H->d_ins, H->w_s, H->F, H->v);
+  hipLaunchKernelGGL(k_bS, dim3(H->n_h), dim3(kBlock), 0, st, H->d_sys, H->d_ins, H->w_h, H->v, H->bS, H->hs);
+  hipLaunchKernelGGL(k_proj_x, dim3(H->n_x), dim3(kBlock), 0, st, H->d_sys, H->d_ins, H->w_x, H->bS, H->hs);
+}
+
+bool any_active(smpm_handle *H, hipStream_t st) {
+  HIPCHECK(hipMemcpyAsync(H->h_gs, H->gs, sizeof(GState) * H->ninst, hipMemcpyDeviceToHost, st));
+  HIPCHECK(hipStreamSynchronize(st));
+  for (int i = 0; i < H->ninst; ++i)
+    if (H->h_gs[i].active) return true;
+  return false;
+}
+
+struct InnerStats {
+  int64_t iters = 0;
+  int iters_max = 0;
+  int matvecs = 0;
+  bool nonfinite = false;
+  bool notconv = false;
+};
+
+// Inner DBJ-GMRES (or BJ / Schur) on right-hand side b (FP64, interface
+// space), in precision T for the operators and the Krylov basis.
+// accumulate = 0: out = x;  1: out += x.
+template <typename T>
+InnerStats inner_solve(smpm_handle *H, const double *b, double *out, int accumulate, double tol, hipStream_t st) {
+  InnerStats is;
+  T *V = nullptr;
+  T *z = nullptr, *y = nullptr, *t = nullptr;
+  if constexpr (sizeof(T) == 8) { V = (T *)H->V64; z = (T *)H->z64; y = (T *)H->y64; t = (T *)H->t64; }
+  else { V = (T *)H->V32; z = (T *)H->z32; y = (T *)H->y32; t = (T *)H->t32; }
+  const bool useM = H->method != SMPM_METHOD_SCHUR;
+  const bool useP = H->method == SMPM_METHOD_DBJ;
+  const int maxit = H->maxit;
+  const size_t shm_dot = sizeof(double) * (maxit + 1) * 5;
+  // Z^T b, coarse part c = G Z^T b
+  if (useP) {
+    hipLaunchKernelGGL(k_halfsum, dim3(H->n_h), dim3(kBlock), 0, st, H->d_sys, H->d_ins, H->w_h, b, H->hs, (double *)nullptr);
+    hipLaunchKernelGGL(k_coarse, dim3(H->ninst), dim3(kBlock), 0, st, H->d_sys, H->d_ins, H->hs, (const double *)nullptr, H->tb, H->cv, (const GState *)nullptr);
+  }
+  hipLaunchKernelGGL(k_init_basis<T>, dim3(H->n_x), dim3(kBlock), 0, st, H->d_sys, H->d_ins, H->w_x, b,
+                     useP ? (const double *)H->cv : (const double *)nullptr, V, H->partn);
+  hipLaunchKernelGGL(k_gmres_start, dim3(H->ninst), dim3(kBlock), 0, st, H->d_ins, H->partn, (const double *)H->pairs,
+                     H->scale, H->g, H->gs, 1);
+  const int check_every = 2;
+  for (int it = 0; it < maxit; ++it) {
+    const T *xin = V;
+    int vslot = 1;
+    const double *sc = H->scale;
+    if (useM) {
+      hipLaunchKernelGGL((k_half_gemv<T, T, T>), dim3(H->n_h), dim3(kBlock), 0, st, H->d_sys, H->d_ins, H->w_h, 1,
+                         (const T *)V, 1, (const double *)H->scale, z, (double *)nullptr, (const GState *)H->gs);
+      xin = z; vslot = 0; sc = nullptr;
+    }
+    hipLaunchKernelGGL((k_half_gemv<T, T, T>), dim3(H->n_h), dim3(kBlock), 0, st, H->d_sys, H->d_ins, H->w_h, 0,
+                       xin, vslot, sc, y, useP ? H->hs : (double *)nullptr, (const GState *)H->gs);
+    if (useP)
+      hipLaunchKernelGGL(k_coarse, dim3(H->ninst), dim3(kBlock), 0, st, H->d_sys, H->d_ins, H->hs, (const double *)nullptr,
+                         (double *)nullptr, H->cv, (const GState *)H->gs);
+    hipLaunchKernelGGL((k_pcorr_dot<T, T>), dim3(H->n_x), dim3(kBlock), sizeof(double) * (maxit + 1) * 4, st, H->d_sys,
+                       H->d_ins, H->w_x, (const T *)y, useP ? (const double *)H->cv : (const double *)nullptr, V, H->part1,
+                       (const GState *)H->gs, maxit);
+    hipLaunchKernelGGL((k_axpy_dot<T>), dim3(H->n_x), dim3(kBlock), shm_dot, st, H->d_sys, H->d_ins, H->w_x, V,
+                       (const double *)H->part1, H->part2, (double *)nullptr, (const double *)H->scale, (const GState *)H->gs);
+    hipLaunchKernelGGL((k_axpy_dot<T>), dim3(H->n_x), dim3(kBlock), shm_dot, st, H->d_sys, H->d_ins, H->w_x, V,
+                       (const double *)H->part2, (double *)nullptr, H->partn, (const double *)H->scale, (const GState *)H->gs);
+    hipLaunchKernelGGL(k_givens, dim3(H->ninst), dim3(kBlock), sizeof(double) * (maxit + 2), st, H->d_ins,
+                       (const double *)H->part1, (const double *)H->part2, (const double *)H->partn, H->scale, H->Rm,
+                       H->cs, H->sn, H->g, H->gs, maxit, tol);
+    if ((it + 1) % check_every == 0 || it + 1 == maxit)
+      if (!any_active(H, st)) break;
+  }
+  HIPCHECK(hipGetLastError());
+  // x' = V y; x = M^-1 x' (+ coarse part)
+  hipLaunchKernelGGL(k_backsolve, dim3(H->ninst), dim3(kBlock), sizeof(double) * (maxit + 1), st, H->d_ins,
+                     (const double *)H->Rm, (const double *)H->g, (const double *)H->scale, H->ycoef, (const GState *)H->gs, maxit);
+  hipLaunchKernelGGL((k_combine<T, T>), dim3(H->n_x), dim3(kBlock), 0, st, H->d_sys, H->d_ins, H->w_x, (const T *)V,
+                     (const double *)H->ycoef, t, (const GState *)H->gs);
+  const T *xfin = t;
+  if (useM) {
+    hipLaunchKernelGGL((k_half_gemv<T, T, T>), dim3(H->n_h), dim3(kBlock), 0, st, H->d_sys, H->d_ins, H->w_h, 1,
+                       (const T *)t, 0, (const double *)nullptr, z, (double *)nullptr, (const GState *)nullptr);
+    xfin = z;
+  }
+  const double *cfin = nullptr;
+  if (useP) {
+    // c' = G (Z^T b - Z^T S z): x = z + Z c'
+    hipLaunchKernelGGL((k_half_gemv<T, T, T>), dim3(H->n_h), dim3(kBlock), 0, st, H->d_sys, H->d_ins, H->w_h, 0,
+                       (const T *)z, 0, (const double *)nullptr, y, H->hs, (const GState *)nullptr);
+    hipLaunchKernelGGL(k_coarse, dim3(H->ninst), dim3(kBlock), 0, st, H->d_sys, H->d_ins, H->hs, (const double *)H->tb,
+                       (double *)nullptr, H->cv, (const GState *)nullptr);
+    cfin = H->cv;
+    is.matvecs += 1;
+  }
+  hipLaunchKernelGGL(k_xupdate<T>, dim3(H->n_x), dim3(kBlock), 0, st, H->d_sys, H->d_ins, H->w_x, accumulate ? 1 : 0,
+                     xfin, cfin, out, (double *)nullptr);
+  HIPCHECK(hipGetLastError());
+  HIPCHECK(hipMemcpyAsync(H->h_gs, H->gs, sizeof(GState) * H->ninst, hipMemcpyDeviceToHost, st));
+  HIPCHECK(hipStreamSynchronize(st));
+  for (int i = 0; i < H->ninst; ++i) {
+    const GState &g = H->h_gs[i];
+    is.iters += g.iter;
+    is.matvecs += g.iter;
+    is.iters_max = std::max(is.iters_max, g.iter);
+    if (g.status == 3) is.nonfinite = true;
+    if (g.status == 2) is.notconv = true;
+  }
+  return is;
+}
+
+// r = b~ - S x (FP64), projected out of u_S; returns per-instance ||r||/||b~||
+// in rel (host) given ||b~||.
+void residual64(smpm_handle *H, const double *x, double *r, hipStream_t st) {
+  hipLaunchKernelGGL((k_half_gemv<double, double, double>), dim3(H->n_h), dim3(kBlock), 0, st, H->d_sys, H->d_ins, H->w_h, 0,
+                     x, 0, (const double *)nullptr, H->y64, (double *)nullptr, (const GState *)nullptr);
+  HIPCHECK(hipMemcpyAsync(r, H->bS, sizeof(double) * H->tot_x, hipMemcpyDeviceToDevice, st));
+  hipLaunchKernelGGL(k_xupdate<double>, dim3(H->n_x), dim3(kBlock), 0, st, H->d_sys, H->d_ins, H->w_x, 2,
+                     (const double *)H->y64, (const double *)nullptr, r, H->partn);
+  hipLaunchKernelGGL(k_reduce_pairs, dim3(H->ninst), dim3(kBlock), 0, st, H->d_ins, (const double *)H->partn, H->pairs);
+}
+
+void norms_of_b(smpm_handle *H, std::vector<double> &nb, hipStream_t st) {
+  HIPCHECK(hipMemcpyAsync(H->rb, H->bS, sizeof(double) * H->tot_x, hipMemcpyDeviceToDevice, st));
+  hipLaunchKernelGGL(k_xupdate<double>, dim3(H->n_x), dim3(kBlock), 0, st, H->d_sys, H->d_ins, H->w_x, 2,
+                     (const double *)nullptr, (const double *)nullptr, H->rb, H->partn);
+  hipLaunchKernelGGL(k_reduce_pairs, dim3(H->ninst), dim3(kBlock), 0, st, H->d_ins, (const double *)H->partn, H->pairs);
+  HIPCHECK(hipMemcpyAsync(H->h_pairs, H->pairs, sizeof(double) * 2 * H->ninst, hipMemcpyDeviceToHost, st));
+  HIPCHECK(hipStreamSynchronize(st));
+  nb.resize(H->ninst);
+  for (int i = 0; i < H->ninst; ++i) nb[i] = std::sqrt(H->h_pairs[2 * i]);
+}
+
+void finish_u(smpm_handle *H, double *u, hipStream_t st) {
+  hipLaunchKernelGGL(k_recover_rhs, dim3(H->n_r), dim3(kBlock), 0, st, H->d_sys, H->d_ins, H->w_r, (const double *)H->F,
+                     (const double *)H->xS, H->Rr);
+  hipLaunchKernelGGL(k_strip_solve, dim3(H->n_s), dim3(kBlock), 0, st, H->d_sys, H->d_ins, H->w_s, (const double *)H->Rr, u);
+  hipLaunchKernelGGL(k_sum_r, dim3(H->n_r), dim3(kBlock), 0, st, H->d_sys, H->d_ins, H->w_r, (const double *)u, H->pr);
+  hipLaunchKernelGGL(k_sub_mean, dim3(H->n_r), dim3(kBlock), 0, st, H->d_sys, H->d_ins, H->w_r, u, (const double *)H->pr);
+}
+
+smpm_status validate_opts(const smpm_opts *o, smpm_handle *H) {
+  smpm_opts d{};
+  if (o) d = *o;
+  H->opts = d;
+  H->tol = d.tol > 0 ? d.tol : 1e-10;
+  H->maxit = d.max_iter > 0 ? d.max_iter : 300;
+  H->nrhs = d.nrhs > 0 ? d.nrhs : 1;
+  H->precision = d.precision;
+  H->method = d.method;
+  H->inner_tol = d.inner_tol > 0 ? d.inner_tol : 1e-5;
+  H->max_sweeps = d.max_sweeps > 0 ? d.max_sweeps : 12;
+  H->host_only = (d.flags & SMPM_FLAG_HOST_ONLY) != 0;
+  if (d.tol < 0 || d.max_iter < 0 || d.nrhs < 0 || d.inner_tol < 0 || d.max_sweeps < 0)
+    return fail(SMPM_EINVAL, "negative option value");
+  if (H->maxit > 2000) return fail(SMPM_EINVAL, "max_iter above 2000");
+  if (H->precision != SMPM_FP64 && H->precision != SMPM_FP32_IR) return fail(SMPM_EINVAL, "unknown precision");
+  if (H->method < SMPM_METHOD_DBJ || H->method > SMPM_METHOD_SCHUR)
+    return fail(SMPM_EINVAL, "method not available (DBJ, BJ, SCHUR)");
+  return SMPM_OK;
+}
+
+smpm_status setup_common(const smpm_grid *grids, const double *k, int nsys, bool one_grid,
+                         const smpm_opts *opts, void *stream, smpm_handle **out) {
+  if (!out) return fail(SMPM_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (!grids || !k || nsys < 1) return fail(SMPM_EINVAL, "grids/k NULL or count < 1");
+  std::unique_ptr<smpm_handle> H(new smpm_handle());
+  smpm_status st = validate_opts(opts, H.get());
+  if (st != SMPM_OK) return st;
+  for (int i = 0; i < nsys; ++i) {
+    const smpm_grid &g = one_grid ? grids[0] : grids[i];
+    if (!g.xb || !g.zb) return fail(SMPM_EINVAL, "grid breakpoints NULL");
+    if (g.mx < 2 || g.mz < 1 || g.order < 1) return fail(SMPM_EINVAL, "need mx >= 2, mz >= 1, order >= 1");
+    if ((int64_t)(g.order + 1) * g.mz > kMaxN) return fail(SMPM_EINVAL, "n * m_z above the supported 544");
+    if (g.order + 1 > 22) return fail(SMPM_EINVAL, "order above 21 is not supported");
+    if (g.mx - 1 > 1024) return fail(SMPM_EINVAL, "more than 1025 strips");
+    if (!(k[i] >= 0.0) || !std::isfinite(k[i])) return fail(SMPM_EINVAL, "wavenumbers must be finite and >= 0");
+  }
+  H->sys.resize(nsys);
+  SetupOptions so;
+  so.tau = H->opts.tau;
+  try {
+    for (int i = 0; i < nsys; ++i) {
+      const smpm_grid &g = one_grid ? grids[0] : grids[i];
+      build_system(H->sys[i], g.mx, g.mz, g.order, g.xb, g.zb, k[i], so);
+    }
+  } catch (const std::invalid_argument &e) {
+    return fail(SMPM_EINVAL, e.what());
+  } catch (const std::domain_error &e) {
+    return fail(SMPM_ESINGULAR, e.what());
+  } catch (const std::bad_alloc &) {
+    return fail(SMPM_ENOMEM, "host allocation failed in setup");
+  } catch (const std::exception &e) {
+    return fail(SMPM_ESINGULAR, e.what());
+  }
+  if (!H->host_only) {
+    try {
+      upload(H.get(), (hipStream_t)stream);
+    } catch (const std::bad_alloc &) {
+      return fail(SMPM_ENOMEM, "device allocation failed in setup");
+    } catch (const std::exception &e) {
+      return fail(SMPM_EHIP, e.what());
+    }
+  }
+  *out = H.release();
+  return SMPM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+smpm_status smpm_setup(const smpm_grid *grid, const double *k, int32_t nk, const smpm_opts *opts,
+                       void *hip_stream, smpm_handle **out) {
+  return setup_common(grid, k, nk, true, opts, hip_stream, out);
+}
+
+smpm_status smpm_setup_batch(const smpm_grid *grids, const double *k, int32_t nprob, const smpm_opts *opts,
+                             void *hip_stream, smpm_handle **out) {
+  return setup_common(grids, k, nprob, false, opts, hip_stream, out);
+}
+
+smpm_status smpm_solve(smpm_handle *H, const double *f, const double *g, double *u, void *hip_stream,
+                       smpm_stats *stats) {
+  if (!H) return fail(SMPM_EINVAL, "handle is NULL");
+  if (H->host_only) return fail(SMPM_EUNSUPPORTED, "host-only handle");
+  if (!f || !u) return fail(SMPM_EINVAL, "f or u is NULL");
+  hipStream_t st = (hipStream_t)hip_stream;
+  const auto t0 = std::chrono::steady_clock::now();
+  smpm_stats S{};
+  S.instances = H->ninst;
+  try {
+    stage_rhs(H, f, g, st);
+    std::vector<double> nb;
+    norms_of_b(H, nb, st);
+    bool nonfinite = false, notconv = false;
+    if (H->precision == SMPM_FP64) {
+      InnerStats is = inner_solve<double>(H, H->bS, H->xS, 0, H->tol, st);
+      S.iters_total = (int)is.iters;
+      S.iters_max = is.iters_max;
+      S.sweeps_max = 1;
+      S.schur_matvecs = is.matvecs;
+      nonfinite = is.nonfinite;
+      notconv = is.notconv;
+    } else {
+      HIPCHECK(hipMemsetAsync(H->xS, 0, sizeof(double) * H->tot_x, st));
+      HIPCHECK(hipMemcpyAsync(H->rb, H->bS, sizeof(double) * H->tot_x, hipMemcpyDeviceToDevice, st));
+      int sweep = 0;
+      for (;; ++sweep) {
+        if (sweep > 0) {
+          residual64(H, H->xS, H->rb, st);
+          hipLaunchKernelGGL(k_proj_x_scalar, dim3(H->n_x), dim3(kBlock), 0, st, H->d_sys, H->d_ins, H->w_x, H->rb,
+                             (const double *)H->pairs);
+          S.schur_matvecs += H->ninst;
+          HIPCHECK(hipMemcpyAsync(H->h_pairs, H->pairs, sizeof(double) * 2 * H->ninst, hipMemcpyDeviceToHost, st));
+          HIPCHECK(hipStreamSynchronize(st));
+          bool done = true;
+          for (int i = 0; i < H->ninst; ++i) {
+            const double rel = nb[i] > 0 ? std::sqrt(H->h_pairs[2 * i]) / nb[i] : 0.0;
+            if (!std::isfinite(rel)) nonfinite = true;
+            if (rel > H->tol) done = false;
+          }
+          if (done || nonfinite) break;
+        }
+        if (sweep >= H->max_sweeps) { notconv = true; break; }
+        InnerStats is = inner_solve<float>(H, H->rb, H->xS, 1, H->inner_tol, st);
+        S.iters_total += (int)is.iters;
+        S.iters_max = std::max(S.iters_max, is.iters_max);
+        S.schur_matvecs += is.matvecs;
+        if (is.nonfinite) { nonfinite = true; break; }
+      }
+      S.sweeps_max = sweep;
+    }
+    // final FP64 check of the Schur residual
+    residual64(H, H->xS, H->rb, st);
+    S.schur_matvecs += H->ninst;
+    HIPCHECK(hipMemcpyAsync(H->h_pairs, H->pairs, sizeof(double) * 2 * H->ninst, hipMemcpyDeviceToHost, st));
+    HIPCHECK(hipMemcpyAsync(H->h_defect, H->defect, sizeof(double) * H->ninst, hipMemcpyDeviceToHost, st));
+    finish_u(H, u, st);
+    HIPCHECK(hipGetLastError());
+    HIPCHECK(hipStreamSynchronize(st));
+    double relmax = 0.0, defmax = 0.0;
+    int conv = 0;
+    for (int i = 0; i < H->ninst; ++i) {
+      const double rel = nb[i] > 0 ? std::sqrt(H->h_pairs[2 * i]) / nb[i] : 0.0;
+      if (!std::isfinite(rel)) nonfinite = true;
+      relmax = std::max(relmax, rel);
+      if (H->sys[H->h_ins[i].sys].singular) defmax = std::max(defmax, H->h_defect[i]);
+      if (rel <= H->tol * 10.0) ++conv;
+    }
+    S.rel_residual_max = relmax;
+    S.compat_defect_max = defmax;
+    S.converged = conv;
+    S.solve_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    if (stats) *stats = S;
+    if (nonfinite) return fail(SMPM_ENONFINITE, "non-finite value in the inputs or iterates");
+    if (notconv) return fail(SMPM_ENOTCONV, "iteration limit reached before the tolerance");
+  } catch (const std::exception &e) {
+    if (stats) *stats = S;
+    return fail(SMPM_EHIP, e.what());
+  }
+  return SMPM_OK;
+}
+
+smpm_status smpm_apply(smpm_handle *H, smpm_op op, int32_t sysi, const void *x, void *y, int32_t precision,
+                       void *hip_stream) {
+  if (!H) return fail(SMPM_EINVAL, "handle is NULL");
+  if (H->host_only) return fail(SMPM_EUNSUPPORTED, "host-only handle");
+  if (sysi < 0 || sysi >= (int)H->sys.size()) return fail(SMPM_EINVAL, "system index out of range");
+  if (!x || !y) return fail(SMPM_EINVAL, "x or y is NULL");
+  hipStream_t st = (hipStream_t)hip_stream;
+  const int inst = sysi * H->nrhs;
+  const InstDev &I = H->h_ins[inst];
+  const System &s = H->sys[sysi];
+  const int2 *wh = H->w_h + H->h_start[inst];
+  const int2 *wx = H->w_x + H->x_start[inst];
+  try {
+    if (op == SMPM_OP_SCHUR || op == SMPM_OP_BJINV) {
+      const int kop = op == SMPM_OP_SCHUR ? 0 : 1;
+      if (precision == SMPM_FP64) {
+        HIPCHECK(hipMemcpyAsync(H->t64 + I.x_off, x, sizeof(double) * s.kS, hipMemcpyDeviceToDevice, st));
+        hipLaunchKernelGGL((k_half_gemv<double, double, double>), dim3(s.nh), dim3(kBlock), 0, st, H->d_sys, H->d_ins, wh,
+                           kop, (const double *)H->t64, 0, (const double *)nullptr, H->y64, (double *)nullptr,
+                           (const GState *)nullptr);
+        HIPCHECK(hipMemcpyAsync(y, H->y64 + I.x_off, sizeof(double) * s.kS, hipMemcpyDeviceToDevice, st));
+      } else if (precision == SMPM_FP32_IR) {
+        HIPCHECK(hipMemcpyAsync(H->t32 + I.x_off, x, sizeof(float) * s.kS, hipMemcpyDeviceToDevice, st));
+        hipLaunchKernelGGL((k_half_gemv<float, float, float>), dim3(s.nh), dim3(kBlock), 0, st, H->d_sys, H->d_ins, wh,
+                           kop, (const float *)H->t32, 0, (const double *)nullptr, H->y32, (double *)nullptr,
+                           (const GState *)nullptr);
+        HIPCHECK(hipMemcpyAsync(y, H->y32 + I.x_off, sizeof(float) * s.kS, hipMemcpyDeviceToDevice, st));
+      } else {
+        return fail(SMPM_EINVAL, "unknown precision");
+      }
+    } else if (precision != SMPM_FP64) {
+      return fail(SMPM_EINVAL, "only SCHUR and BJINV have FP32 variants");
+    } else if (op == SMPM_OP_DEFLATE_P || op == SMPM_OP_DEFLATE_Q) {
+      HIPCHECK(hipMemcpyAsync(H->t64 + I.x_off, x, sizeof(double) * s.kS, hipMemcpyDeviceToDevice, st));
+      const double *src = H->t64;
+      if (op == SMPM_OP_DEFLATE_Q) {   // Q x = x - Z G Z^T S x
+        hipLaunchKernelGGL((k_half_gemv<double, double, double>), dim3(s.nh), dim3(kBlock), 0, st, H->d_sys, H->d_ins, wh,
+                           0, (const double *)H->t64, 0, (const double *)nullptr, H->y64, H->hs, (const GState *)nullptr);
+      } else {                         // P x = x - (S Z) G Z^T x
+        hipLaunchKernelGGL(k_halfsum, dim3(s.nh), dim3(kBlock), 0, st, H->d_sys, H->d_ins, wh, src, H->hs, (double *)nullptr);
+      }
+      hipLaunchKernelGGL(k_coarse, dim3(1), dim3(kBlock), 0, st, H->d_sys, H->d_ins + inst, H->hs, (const double *)nullptr,
+                         (double *)nullptr, H->cv, (const GState *)nullptr);
+      if (op == SMPM_OP_DEFLATE_Q) {
+        // out = x - Z c: negate c by passing through k_xupdate with a = x, c = -c
+        std::vector<double> tmp(s.d);
+        HIPCHECK(hipMemcpyAsync(tmp.data(), H->cv + I.c_off, sizeof(double) * s.d, hipMemcpyDeviceToHost, st));
+        HIPCHECK(hipStreamSynchronize(st));
+        for (auto &a : tmp) a = -a;
+        HIPCHECK(hipMemcpyAsync(H->cv + I.c_off, tmp.data(), sizeof(double) * s.d, hipMemcpyHostToDevice, st));
+        hipLaunchKernelGGL(k_xupdate<double>, dim3(I.nchunk_x), dim3(kBlock), 0, st, H->d_sys, H->d_ins, wx, 0,
+                           (const double *)H->t64, (const double *)H->cv, H->y64, (double *)nullptr);
+        HIPCHECK(hipMemcpyAsync(y, H->y64 + I.x_off, sizeof(double) * s.kS, hipMemcpyDeviceToDevice, st));
+        HIPCHECK(hipStreamSynchronize(st));
+      } else {
+        // k_init_basis with the FP64 basis slot 0 as output: use y64 region through V-offset-free copy
+        hipLaunchKernelGGL(k_init_basis<double>, dim3(I.nchunk_x), dim3(kBlock), 0, st, H->d_sys, H->d_ins, wx,
+                           (const double *)H->t64, (const double *)H->cv, H->z64 + I.x_off - I.v_off, H->partn);
+        HIPCHECK(hipMemcpyAsync(y, H->z64 + I.x_off, sizeof(double) * s.kS, hipMemcpyDeviceToDevice, st));
+      }
+    } else if (op == SMPM_OP_AINV) {
+      HIPCHECK(hipMemcpyAsync(H->F + I.f_off, x, sizeof(double) * s.r, hipMemcpyDeviceToDevice, st));
+      const int2 *wsp = H->w_s + (int64_t)0;
+      // strips of this instance: instances are laid out in order; find the first strip item
+      int sstart = 0;
+      for (int q = 0; q < inst; ++q) sstart += H->sys[H->h_ins[q].sys].mx;
+      hipLaunchKernelGGL(k_strip_solve, dim3(s.mx), dim3(kBlock), 0, st, H->d_sys, H->d_ins, wsp + sstart,
+                         (const double *)H->F, H->v);
+      HIPCHECK(hipMemcpyAsync(y, H->v + I.f_off, sizeof(double) * s.r, hipMemcpyDeviceToDevice, st));
+    } else if (op == SMPM_OP_B) {
+      HIPCHECK(hipMemcpyAsync(H->v + I.f_off, x, sizeof(double) * s.r, hipMemcpyDeviceToDevice, st));
+      hipLaunchKernelGGL(k_bS, dim3(s.nh), dim3(kBlock), 0, st, H->d_sys, H->d_ins, wh, (const double *)H->v, H->y64, H->hs);
+      HIPCHECK(hipMemcpyAsync(y, H->y64 + I.x_off, sizeof(double) * s.kS, hipMemcpyDeviceToDevice, st));
+    } else if (op == SMPM_OP_SCHUR_RHS) {
+      // F given directly (g = 0): projection, A^-1, B, projection.
+      HIPCHECK(hipMemcpyAsync(H->Rr + I.f_off, x, sizeof(double) * s.r, hipMemcpyDeviceToDevice, st));
+      stage_rhs(H, H->Rr, nullptr, st);
+      HIPCHECK(hipMemcpyAsync(y, H->bS + I.x_off, sizeof(double) * s.kS, hipMemcpyDeviceToDevice, st));
+    } else {
+      return fail(SMPM_EINVAL, "unknown operator");
+    }
+    HIPCHECK(hipGetLastError());
+    HIPCHECK(hipStreamSynchronize(st));
+  } catch (const std::exception &e) {
+    return fail(SMPM_EHIP, e.what());
+  }
+  return SMPM_OK;
+}
+
+smpm_status smpm_schur_apply_all(smpm_handle *H, const void *x, void *y, int32_t precision, void *hip_stream) {
+  if (!H) return fail(SMPM_EINVAL, "handle is NULL");
+  if (H->host_only) return fail(SMPM_EUNSUPPORTED, "host-only handle");
+  if (!x || !y) return fail(SMPM_EINVAL, "x or y is NULL");
+  hipStream_t st = (hipStream_t)hip_stream;
+  if (precision == SMPM_FP64)
+    hipLaunchKernelGGL((k_half_gemv<double, double, double>), dim3(H->n_h), dim3(kBlock), 0, st, H->d_sys, H->d_ins, H->w_h,
+                       0, (const double *)x, 0, (const double *)nullptr, (double *)y, (double *)nullptr, (const GState *)nullptr);
+  else if (precision == SMPM_FP32_IR)
+    hipLaunchKernelGGL((k_half_gemv<float, float, float>), dim3(H->n_h), dim3(kBlock), 0, st, H->d_sys, H->d_ins, H->w_h,
+                       0, (const float *)x, 0, (const double *)nullptr, (float *)y, (double *)nullptr, (const GState *)nullptr);
+  else
+    return fail(SMPM_EINVAL, "unknown precision");
+  if (hipGetLastError() != hipSuccess) return fail(SMPM_EHIP, "kernel launch failed");
+  return SMPM_OK;
+}
+
+int32_t smpm_num_systems(const smpm_handle *H) { return H ? (int32_t)H->sys.size() : 0; }
+
+smpm_status smpm_query(const smpm_handle *H, int32_t sysi, smpm_info *info) {
+  if (!H || !info) return fail(SMPM_EINVAL, "NULL argument");
+  if (sysi < 0 || sysi >= (int)H->sys.size()) return fail(SMPM_EINVAL, "system index out of range");
+  const System &s = H->sys[sysi];
+  smpm_info o{};
+  o.n = s.n; o.mx = s.mx; o.mz = s.mz; o.nrhs = H->nrhs; o.r = s.r; o.kS = s.kS; o.d = s.d;
+  o.kwave = s.kwave; o.tau = s.tau;
+  int64_t f = 0, g = 0, x = 0;
+  for (int q = 0; q < sysi; ++q) {
+    const System &p = H->sys[q];
+    f += p.r * H->nrhs; g += 2LL * p.n * (p.mx + p.mz) * H->nrhs; x += p.kS * H->nrhs;
+  }
+  o.f_offset = f; o.g_offset = g; o.x_offset = x;
+  o.unique_W = s.nW; o.unique_M = s.nM;
+  // Distinct strip blocks streamed by one matvec: every half reads its N x 2N block once.
+  o.bytes_W64 = (int64_t)s.nW * s.N * 2 * s.N * 8;
+  int64_t mb = 0;
+  for (int h = 0; h < s.nh; ++h) mb = std::max<int64_t>(mb, 0);
+  o.bytes_M64 = (int64_t)s.nM * s.N * 4 * s.N * 8;
+  *info = o;
+  return SMPM_OK;
+}
+
+smpm_status smpm_export(const smpm_handle *H, smpm_table what, int32_t sysi, double *out, int64_t count) {
+  if (!H || !out) return fail(SMPM_EINVAL, "NULL argument");
+  if (sysi < 0 || sysi >= (int)H->sys.size()) return fail(SMPM_EINVAL, "system index out of range");
+  const System &s = H->sys[sysi];
+  auto need = [&](int64_t n) -> bool { return count == n; };
+  switch (what) {
+    case SMPM_TABLE_SCHUR_DENSE: {
+      if (!need(s.kS * s.kS)) return fail(SMPM_EINVAL, "count must be k_S^2");
+      std::fill(out, out + count, 0.0);
+      for (int h = 0; h < s.nh; ++h)
+        for (int i = 0; i < s.N; ++i) {
+          const int64_t row = (int64_t)h * s.N + i;
+          out[row * s.kS + row] += 1.0;
+          for (int c = 0; c < 2 * s.N; ++c) {
+            const int64_t col = (int64_t)s.w_win[h] * s.N + c;
+            if (col < 0 || col >= s.kS) continue;
+            out[row * s.kS + col] += s.Wblk[(size_t)s.w_id[h] * s.N * 2 * s.N + (size_t)i * 2 * s.N + c];
+          }
+        }
+      return SMPM_OK;
+    }
+    case SMPM_TABLE_BJINV_DENSE: {
+      if (!need(s.kS * s.kS)) return fail(SMPM_EINVAL, "count must be k_S^2");
+      std::fill(out, out + count, 0.0);
+      for (int h = 0; h < s.nh; ++h)
+        for (int i = 0; i < s.N; ++i) {
+          const int64_t row = (int64_t)h * s.N + i;
+          for (int c = 0; c < s.m_K[h]; ++c) {
+            const int64_t col = (int64_t)s.m_win[h] * s.N + c;
+            out[row * s.kS + col] = s.Mblk[(size_t)s.m_id[h] * s.N * 4 * s.N + (size_t)i * 4 * s.N + c];
+          }
+        }
+      return SMPM_OK;
+    }
+    case SMPM_TABLE_COARSE_C:
+      if (!need((int64_t)s.d * s.d)) return fail(SMPM_EINVAL, "count must be d^2");
+      std::copy(s.C.begin(), s.C.end(), out);
+      return SMPM_OK;
+    case SMPM_TABLE_U_S:
+    case SMPM_TABLE_U_L:
+    case SMPM_TABLE_U_C: {
+      if (!s.singular) return fail(SMPM_EINVAL, "null vectors exist for k = 0 only");
+      const std::vector<double> &v = what == SMPM_TABLE_U_S ? s.uS : what == SMPM_TABLE_U_L ? s.uL : s.uC;
+      if (!need((int64_t)v.size())) return fail(SMPM_EINVAL, "count mismatch");
+      std::copy(v.begin(), v.end(), out);
+      return SMPM_OK;
+    }
+    case SMPM_TABLE_SZ: {
+      if (!need(s.kS * s.d)) return fail(SMPM_EINVAL, "count must be k_S * d");
+      std::fill(out, out + count, 0.0);
+      for (int h = 0; h < s.nh; ++h)
+        for (int p = 0; p < 2; ++p) {
+          const int col = s.sz_col[(size_t)h * 2 + p];
+          if (col < 0) continue;
+          for (int i = 0; i < s.N; ++i) out[((int64_t)h * s.N + i) * s.d + col] = s.SZh[((size_t)h * 2 + p) * s.N + i];
+        }
+      return SMPM_OK;
+    }
+  }
+  return fail(SMPM_EINVAL, "unknown table");
+}
+
+void smpm_destroy(smpm_handle *H) { delete H; }
+
+const char *smpm_last_error(void) { return g_err.c_str(); }
+
+}  // extern "C"

@@ -1,0 +1,103 @@
+"""CPU checks of the C-ABI library: it loads, exports every declared symbol,
+and its host-side setup (built without touching a GPU) reproduces the
+oracle's operators."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import paper_1512_01756_amd as P
+from oracle import schur, smpm
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared_symbols():
+    names = set()
+    inc = os.path.join(ROOT, "include")
+    for fn in os.listdir(inc):
+        if fn.endswith(".h"):
+            src = open(os.path.join(inc, fn)).read()
+            names |= set(re.findall(r"\b(smpm_[a-z_]+)\s*\(", src))
+    return names
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(P.LIB_PATH):
+        pytest.fail("library not built: run python -m paper_1512_01756_amd.build")
+    return P.load()
+
+
+def test_every_declared_symbol_is_exported(lib):
+    declared = _declared_symbols()
+    assert {"smpm_setup", "smpm_solve", "smpm_apply", "smpm_destroy"} <= declared
+    for name in declared:
+        assert hasattr(lib, name), name
+    assert declared == set(P.EXPORTED)
+
+
+CASES = [
+    (np.linspace(0, 8, 9), np.linspace(0, 1, 3), 11, 0.0),
+    (np.array([0, 0.4, 0.9, 1.2, 1.9, 2.3, 2.8]), np.array([0, 0.15, 0.45, 1.0]), 5, 0.0),
+    (np.array([0, 0.4, 0.9, 1.2, 1.9, 2.3, 2.8]), np.array([0, 0.15, 0.45, 1.0]), 5, 1.7),
+    (np.linspace(0, 3, 8), np.linspace(0, 1, 2), 4, 0.0),
+]
+
+
+@pytest.mark.parametrize("xb,zb,n,k", CASES)
+def test_host_setup_matches_oracle(lib, xb, zb, n, k):
+    s = P.Solver(xb, zb, n - 1, kwaves=[k], host_only=True)
+    grid = smpm.Grid(xb, zb, n)
+    o = schur.build(grid, kwave=k)
+    kS, d = grid.k, grid.mx - 1
+    assert s.info[0]["kS"] == kS and s.info[0]["r"] == grid.r and s.info[0]["d"] == d
+    assert s.info[0]["tau"] == pytest.approx(o.tau, rel=1e-15)
+    S = s.export(P.TABLE_SCHUR_DENSE).reshape(kS, kS)
+    So = o.S.toarray()
+    assert np.abs(S - So).max() <= 1e-11 * np.abs(So).max()
+    Mi = s.export(P.TABLE_BJINV_DENSE).reshape(kS, kS)
+    Mo = np.zeros((kS, kS))
+    for idx, Mb in zip(o.bj_index, o.bj_inv):
+        Mo[np.ix_(idx, idx)] = Mb
+    assert np.abs(Mi - Mo).max() <= 1e-11 * np.abs(Mo).max()
+    C = s.export(P.TABLE_COARSE_C).reshape(d, d)
+    assert np.abs(C - o.C).max() <= 1e-11 * np.abs(o.C).max()
+    SZ = s.export(P.TABLE_SZ).reshape(kS, d)
+    assert np.abs(SZ - o.SZ).max() <= 1e-10 * np.abs(o.SZ).max()
+    if k == 0.0:
+        for table, ref in ((P.TABLE_U_S, o.uS), (P.TABLE_U_L, o.uL), (P.TABLE_U_C, o.uC)):
+            v = s.export(table)
+            assert np.abs(v - ref).max() < 1e-10
+    s.close()
+
+
+def test_uniform_strips_are_deduplicated(lib):
+    s = P.Solver(np.linspace(0, 32, 65), np.linspace(0, 1, 5), 6, host_only=True)
+    # first strip, interior strips, last strip -> at most 4 distinct half blocks
+    assert s.info[0]["unique_W"] <= 4
+    s.close()
+
+
+def test_errors(lib):
+    with pytest.raises(P.SmpmError) as e:
+        P.Solver(np.linspace(0, 3, 4), np.linspace(0, 1, 2), 4, host_only=True)   # m_x = 3, k = 0
+    assert e.value.status == P.ESINGULAR
+    # m_x = 3 is fine for k > 0 (nonsingular)
+    P.Solver(np.linspace(0, 3, 4), np.linspace(0, 1, 2), 4, kwaves=[2.0], host_only=True).close()
+    with pytest.raises(P.SmpmError) as e:
+        P.Solver(np.array([0, 1.0, 0.5, 2.0, 3.0]), np.linspace(0, 1, 2), 4, host_only=True)
+    assert e.value.status == P.EINVAL
+    with pytest.raises(P.SmpmError) as e:
+        P.Solver(np.linspace(0, 4, 5), np.linspace(0, 1, 2), 4, kwaves=[-1.0], host_only=True)
+    assert e.value.status == P.EINVAL
+    with pytest.raises(P.SmpmError) as e:
+        P.Solver(np.linspace(0, 4, 5), np.linspace(0, 1, 2), 0, host_only=True)
+    assert e.value.status == P.EINVAL
+    s = P.Solver(np.linspace(0, 4, 5), np.linspace(0, 1, 2), 4, host_only=True)
+    lib_ = P.load()
+    st = lib_.smpm_solve(s.h, None, None, None, None, None)
+    assert st == P.EUNSUPPORTED
+    s.close()
