@@ -26,7 +26,9 @@ struct SysDev {
   const double *SZh;     // [h][2][N]
   const double *Gc;      // coarse operator, column-major d x d
   const double *uS, *uL; // null vectors (k = 0), else nullptr
-  const double *Gs;      // strip factors: [class][e][col n2][row n2]
+  const double *Dinv;    // element inverses: [class][e][col n2][row n2]
+  const double *Kinv;    // z-interface capacitance inverses: [class][nq][nq] row-major
+  int nq;                // 2 n (m_z - 1)
   const double *lo, *up; // [e][n]
   const double *beta;    // [class][2][n]: west row, east row
   const int *strip_class;
@@ -47,6 +49,15 @@ struct InstDev {
   int64_t c_off;         // coarse vectors: [d]
   int64_t st_off;        // GMRES scalars: [maxit + 1]
   int64_t rr_off;        // R factor: [maxit][maxit]
+  int64_t lam_off;       // z-interface functionals: [m_x][nq]
+};
+
+// Work item of the half-interface GEMV: up to kGroup halves of one instance
+// that share the same operator block.
+constexpr int kGroup = 4;
+struct HWork {
+  int inst, cnt;
+  int h[kGroup];
 };
 
 struct GState {

@@ -40,6 +40,12 @@ struct StripClass {
   // block-Thomas factors over the m_z elements: G[e] = (D~_e)^-1, n2 x n2,
   // row-major on the host.
   std::vector<double> G;
+  // Element-parallel form for the device (Woodbury in z): A_j = D + P Lambda
+  // with D = blockdiag(Dg_e) and P Lambda the z-interface coupling.
+  // Dinv[e] = Dg_e^-1 (n2 x n2 row-major); Kinv = (I + Lambda D^-1 P)^-1,
+  // nq = 2 n (m_z - 1) square, row-major.  q ordering: interface i (between
+  // elements i and i+1): [lo: rows (0, t) of i+1 | up: rows (n-1, t) of i].
+  std::vector<double> Dinv, Kinv;
   // B-row functionals of this strip's west / east element rows (n values).
   std::vector<double> betaW, betaE;
   // W quarter blocks Wq[r][c] (N x N row-major), r: 0 west row, 1 east row;
@@ -90,6 +96,7 @@ void build_system(System &s, int mx, int mz, int order, const double *xb, const 
 
 // Host references used by export and by the setup itself.
 void strip_solve(const System &s, const StripClass &c, double *X, int nrhs);    // A_j^-1 X (in place)
+void strip_solve_woodbury(const System &s, const StripClass &c, double *x);     // A_j^-1 x (one rhs)
 void strip_solve_t(const System &s, const StripClass &c, double *X, int nrhs);  // A_j^-T X (in place)
 void schur_apply_host(const System &s, const double *x, double *y);             // y = S x
 

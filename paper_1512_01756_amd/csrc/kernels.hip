@@ -39,82 +39,112 @@ __device__ inline double block_sum(double v, double *lds4) {
 }
 
 // ---------------------------------------------------------------------------
+// Column-split GEMV core: lane `lane` owns row `row` (< R) of a column-major
+// R x K block and accumulates columns [c0, c1) for G right-hand sides held in
+// LDS (xw[g * xs + c]).  Loads are issued UNROLL columns at a time.
+template <typename TO, int G, int UNROLL>
+__device__ inline void colsplit(const TO *__restrict__ blk, int R, int row, int c0, int c1,
+                                const double *xw, int xs, TO (&acc)[G]) {
+  const bool live = row < R;
+  const TO *col = blk + row;
+  int c = c0;
+  for (; c + UNROLL <= c1; c += UNROLL) {
+    TO v[UNROLL];
+#pragma unroll
+    for (int u = 0; u < UNROLL; ++u) v[u] = live ? col[(size_t)(c + u) * R] : (TO)0;
+#pragma unroll
+    for (int u = 0; u < UNROLL; ++u)
+#pragma unroll
+      for (int g = 0; g < G; ++g) acc[g] += v[u] * (TO)xw[g * xs + c + u];
+  }
+  for (; c < c1; ++c) {
+    const TO v = live ? col[(size_t)c * R] : (TO)0;
+#pragma unroll
+    for (int g = 0; g < G; ++g) acc[g] += v * (TO)xw[g * xs + c];
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Half-interface block GEMV (Sec. 3.1 Schur matvec, Sec. 3.2 block-Jacobi):
 //   op 0:  y_h = x_h + W^_h x[w_win(h) N .. + 2N)      (S = I + sum_j W_j)
 //   op 1:  y_h = Mc_h x[m_win(h) N .. + m_K(h))         (M^-1 row chunk)
-// One workgroup per (instance, half).  The window is staged in LDS; each
-// wave takes a quarter of the columns and each lane rows lane + 64 q, so a
-// column of the column-major block is one coalesced read.
-// x_vslot: read x from Krylov slot `iter` of the instance, scaled by
-// scale[iter].  hsum: write the sum of y_h (for Z^T y).
-template <typename TO, typename TX, typename TY>
-__global__ __launch_bounds__(kBlock) void k_half_gemv(
-    const SysDev *__restrict__ sys, const InstDev *__restrict__ ins, const int2 *__restrict__ work,
+// A workgroup takes a 64-row tile of a group of up to G halves of one
+// instance that share the same column-major block, so one block load feeds
+// G windows.  The windows sit in LDS; the 4 waves split the columns and a
+// lane owns one row; wave partials are summed in LDS.
+// Grid: (group, row tile).  x_vslot: read x from Krylov slot `iter` of the
+// instance, scaled by scale[iter].  hsum: per-tile partial sums of y_h,
+// hsum[hs_off + h * tiles + tile] (for Z^T y).
+template <typename TO, typename TX, typename TY, int G, int NW>
+__global__ __launch_bounds__(64 * NW) void k_half_gemv(
+    const SysDev *__restrict__ sys, const InstDev *__restrict__ ins, const HWork *__restrict__ work,
     int op, const TX *__restrict__ xbase, int x_vslot, const double *__restrict__ scale,
     TY *__restrict__ ybase, double *__restrict__ hsum, const GState *__restrict__ gs) {
-  __shared__ double xw[4 * kMaxN];
-  __shared__ double red[4 * kMaxN];
+  extern __shared__ double sm[];
   __shared__ double lds4[4];
-  const int2 wk = work[blockIdx.x];
-  const int i = wk.x, h = wk.y;
+  __shared__ int hh[kGroup];
+  const int i = work[blockIdx.x].inst, cnt = work[blockIdx.x].cnt;
   if (gs && !gs[i].active) return;
+  if (threadIdx.x < kGroup) hh[threadIdx.x] = work[blockIdx.x].h[threadIdx.x];
   const InstDev I = ins[i];
   const SysDev &S = sys[I.sys];
   const int N = S.N;
+  const int tiles = (N + 63) >> 6;
+  const int tile = blockIdx.y;
+  if (tile >= tiles) return;
+  __syncthreads();
   const int64_t kS = S.kS;
+  const int h0 = hh[0];
   int K;
-  int64_t win;
   const TO *blk;
   if (op == 0) {
     K = 2 * N;
-    win = (int64_t)S.w_win[h] * N;
-    blk = Tab<TO>::W(S) + (size_t)S.w_id[h] * 2 * N * N;
+    blk = Tab<TO>::W(S) + (size_t)S.w_id[h0] * 2 * N * N;
   } else {
-    K = S.m_K[h];
-    win = (int64_t)S.m_win[h] * N;
-    blk = Tab<TO>::M(S) + (size_t)S.m_id[h] * 4 * N * N;
+    K = S.m_K[h0];
+    blk = Tab<TO>::M(S) + (size_t)S.m_id[h0] * 4 * N * N;
   }
   const int it = gs ? gs[i].iter : 0;
   const TX *x = xbase + (x_vslot ? I.v_off + (int64_t)it * kS : I.x_off);
   const double xs = scale ? scale[I.st_off + it] : 1.0;
-  for (int c = threadIdx.x; c < K; c += kBlock) {
-    const int64_t idx = win + c;
-    xw[c] = (idx >= 0 && idx < kS) ? (double)x[idx] * xs : 0.0;
+  double *xw = sm;                 // [G][K]
+  double *red = sm + G * K;        // [NW][G][64]
+  for (int g = 0; g < G; ++g) {
+    const int h = g < cnt ? hh[g] : h0;
+    const int64_t win = (int64_t)(op == 0 ? S.w_win[h] : S.m_win[h]) * N;
+    for (int c = threadIdx.x; c < K; c += 64 * NW) {
+      const int64_t idx = win + c;
+      xw[g * K + c] = (g < cnt && idx >= 0 && idx < kS) ? (double)x[idx] * xs : 0.0;
+    }
   }
   __syncthreads();
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int c0 = (K * wave) >> 2, c1 = (K * (wave + 1)) >> 2;
-  TO acc[kMaxRowsPerLane];
+  const int row = tile * 64 + lane;
+  const int c0 = (K * wave) / NW, c1 = (K * (wave + 1)) / NW;
+  TO acc[G];
 #pragma unroll
-  for (int q = 0; q < kMaxRowsPerLane; ++q) acc[q] = (TO)0;
-  for (int c = c0; c < c1; ++c) {
-    const TO xv = (TO)xw[c];
-    const TO *col = blk + (size_t)c * N;
+  for (int g = 0; g < G; ++g) acc[g] = (TO)0;
+  colsplit<TO, G, 8>(blk, N, row, c0, c1, xw, K, acc);
 #pragma unroll
-    for (int q = 0; q < kMaxRowsPerLane; ++q) {
-      const int row = lane + 64 * q;
-      if (row < N) acc[q] += col[row] * xv;
-    }
-  }
-#pragma unroll
-  for (int q = 0; q < kMaxRowsPerLane; ++q) {
-    const int row = lane + 64 * q;
-    if (row < N) red[wave * N + row] = (double)acc[q];
-  }
+  for (int g = 0; g < G; ++g) red[(wave * G + g) * 64 + lane] = (double)acc[g];
   __syncthreads();
-  TY *y = ybase + I.x_off + (int64_t)h * N;
-  double lsum = 0.0;
-  for (int row = threadIdx.x; row < N; row += kBlock) {
-    TO v = ((TO)red[row] + (TO)red[N + row]) + ((TO)red[2 * N + row] + (TO)red[3 * N + row]);
-    double vd = (double)v;
-    if (op == 0) vd += (double)x[(int64_t)h * N + row] * xs;
-    const TY out = (TY)vd;
-    y[row] = out;
-    lsum += (double)out;
-  }
-  if (hsum) {
-    const double s = block_sum(lsum, lds4);
-    if (threadIdx.x == 0) hsum[I.hs_off + h] = s;
+  for (int g = 0; g < cnt; ++g) {
+    const int h = hh[g];
+    double out_d = 0.0;
+    if (threadIdx.x < 64 && row < N) {
+      TO v = (TO)0;
+#pragma unroll
+      for (int w = 0; w < NW; ++w) v += (TO)red[(w * G + g) * 64 + lane];
+      double vd = (double)v;
+      if (op == 0) vd += (double)x[(int64_t)h * N + row] * xs;
+      const TY out = (TY)vd;
+      ybase[I.x_off + (int64_t)h * N + row] = out;
+      out_d = (double)out;
+    }
+    if (hsum) {   // only the first wave holds outputs
+      const double sgrp = wave_sum(out_d);
+      if (threadIdx.x == 0) hsum[I.hs_off + (int64_t)h * tiles + tile] = sgrp;
+    }
   }
 }
 
@@ -135,28 +165,42 @@ __global__ __launch_bounds__(kBlock) void k_coarse(const SysDev *__restrict__ sy
   const InstDev I = ins[i];
   const SysDev &S = sys[I.sys];
   const int d = S.d;
+  const int tiles = (S.N + 63) >> 6;
   for (int c = threadIdx.x; c < d; c += kBlock) {
-    double v = hsum[I.hs_off + 2 * c] + hsum[I.hs_off + 2 * c + 1];
+    double v = 0.0;
+    for (int q = 0; q < 2 * tiles; ++q) v += hsum[I.hs_off + (int64_t)2 * c * tiles + q];
     if (tsub) v = tsub[I.c_off + c] - v;
     t[c] = v;
     if (tout) tout[I.c_off + c] = v;
   }
   __syncthreads();
-  for (int r = threadIdx.x; r < d; r += kBlock) {
-    double acc = 0.0;
-    for (int l = 0; l < d; ++l) acc += S.Gc[(size_t)l * d + r] * t[l];
-    cout[I.c_off + r] = acc;
+  // c = G t: column-split over the 4 waves, lanes over rows.
+  __shared__ double red[4 * 64];
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  for (int r0 = 0; r0 < d; r0 += 64) {
+    double acc[1] = {0.0};
+    colsplit<double, 1, 8>(S.Gc + r0, d, r0 + lane < d ? lane : d, (d * wave) >> 2, (d * (wave + 1)) >> 2, t, 0, acc);
+    red[wave * 64 + lane] = acc[0];
+    __syncthreads();
+    if (threadIdx.x < 64 && r0 + lane < d)
+      cout[I.c_off + r0 + lane] = (red[lane] + red[64 + lane]) + (red[128 + lane] + red[192 + lane]);
+    __syncthreads();
   }
 }
 
-// Arnoldi step, part 1: w = y - (S Z) c (the deflation P, Sec. 3.3; c = null
-// skips it), stored in Krylov slot iter + 1; partial dots V_t . w, t <= iter.
+// Arnoldi step, part 1: w = y - (S Z) c with c = G Z^T y (the deflation P,
+// Sec. 3.3; useP = 0 skips it), stored in Krylov slot iter + 1; partial dots
+// V_t . w for t <= iter.  The coarse solve is fused: every workgroup forms
+// t = Z^T y from the per-tile half sums and computes only the coarse values
+// its chunk needs.
 template <typename TV, typename TY>
 __global__ __launch_bounds__(kBlock) void k_pcorr_dot(
     const SysDev *__restrict__ sys, const InstDev *__restrict__ ins, const int2 *__restrict__ work,
-    const TY *__restrict__ ybase, const double *__restrict__ cvec, TV *__restrict__ V,
+    const TY *__restrict__ ybase, const double *__restrict__ hsum, int useP, TV *__restrict__ V,
     double *__restrict__ part, const GState *__restrict__ gs, int maxit) {
   extern __shared__ double red[];   // (maxit + 1) * 4
+  __shared__ double t_s[1024];
+  __shared__ double c_s[kChunk / 2 + 8];
   const int2 wk = work[blockIdx.x];
   const int i = wk.x, ch = wk.y;
   if (!gs[i].active) return;
@@ -166,6 +210,29 @@ __global__ __launch_bounds__(kBlock) void k_pcorr_dot(
   const int64_t kS = S.kS;
   const int j = gs[i].iter;
   const int64_t e0 = (int64_t)ch * kChunk;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  int ilo = 0;
+  if (useP) {
+    const int d = S.d;
+    const int tiles = (N + 63) >> 6;
+    for (int c = threadIdx.x; c < d; c += kBlock) {
+      double v = 0.0;
+      for (int q = 0; q < 2 * tiles; ++q) v += hsum[I.hs_off + (int64_t)2 * c * tiles + q];
+      t_s[c] = v;
+    }
+    const int64_t elast = (e0 + kChunk < kS ? e0 + kChunk : kS) - 1;
+    const int hlo = (int)(e0 / N), hhi = (int)(elast / N);
+    ilo = hlo / 2 - 1 < 0 ? 0 : hlo / 2 - 1;
+    const int ihi = hhi / 2 + 1 > d - 1 ? d - 1 : hhi / 2 + 1;
+    __syncthreads();
+    for (int r = wave; r <= ihi - ilo; r += 4) {
+      double a = 0.0;
+      for (int l = lane; l < d; l += 64) a += S.Gc[(size_t)l * d + ilo + r] * t_s[l];
+      a = wave_sum(a);
+      if (lane == 0) c_s[r] = a;
+    }
+    __syncthreads();
+  }
   double wv[kChunk / kBlock];
 #pragma unroll
   for (int q = 0; q < kChunk / kBlock; ++q) {
@@ -173,11 +240,11 @@ __global__ __launch_bounds__(kBlock) void k_pcorr_dot(
     double w = 0.0;
     if (e < kS) {
       w = (double)ybase[I.x_off + e];
-      if (cvec) {
+      if (useP) {
         const int h = (int)(e / N), row = (int)(e - (int64_t)h * N);
         const int ca = S.sz_col[2 * h], cb = S.sz_col[2 * h + 1];
-        if (ca >= 0) w -= S.SZh[((size_t)2 * h) * N + row] * cvec[I.c_off + ca];
-        if (cb >= 0) w -= S.SZh[((size_t)2 * h + 1) * N + row] * cvec[I.c_off + cb];
+        if (ca >= 0) w -= S.SZh[((size_t)2 * h) * N + row] * c_s[ca - ilo];
+        if (cb >= 0) w -= S.SZh[((size_t)2 * h + 1) * N + row] * c_s[cb - ilo];
       }
       const TV wt = (TV)w;
       V[I.v_off + (int64_t)(j + 1) * kS + e] = wt;
@@ -185,7 +252,6 @@ __global__ __launch_bounds__(kBlock) void k_pcorr_dot(
     }
     wv[q] = w;
   }
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   for (int t = 0; t <= j; ++t) {
     const TV *Vt = V + I.v_off + (int64_t)t * kS;
     double a = 0.0;
@@ -394,60 +460,159 @@ __global__ __launch_bounds__(kBlock) void k_combine(const SysDev *__restrict__ s
 }
 
 // ---------------------------------------------------------------------------
-// Element-interior elimination (Sec. 2.3): A(k)^-1 per strip by block
-// elimination over the m_z elements with the precomputed inverse Schur
-// blocks G_e.  One workgroup per (instance, strip).
-__global__ __launch_bounds__(kBlock) void k_strip_solve(const SysDev *__restrict__ sys,
-                                                        const InstDev *__restrict__ ins,
-                                                        const int2 *__restrict__ work,
-                                                        const double *__restrict__ src,
-                                                        double *__restrict__ dst) {
-  __shared__ double rl[512];
-  __shared__ double qv[32];
+// Element-interior elimination (Sec. 2.3): A(k)^-1 per strip.  The strip
+// operator is A_j = D + P Lambda, D = blockdiag of the element operators
+// (with their own Robin terms), P Lambda the coupling across the z-interfaces
+// inside the strip.  By the capacitance (Woodbury) identity
+//   A_j^-1 v = w - D^-1 P q,  w = D^-1 v,  q = K^-1 Lambda w,  K = I + Lambda D^-1 P,
+// every element is solved independently (one dense GEMV with the element
+// inverse) and only the small z-interface system K couples them.
+//
+// k_elem_solve: w = D^-1 v.  Grid (element item, 64-row tile); an item is
+// (inst, first strip, strip count, element e) with strips of one class, so
+// one load of the element inverse feeds up to SG strips.
+template <int SG, int NW>
+__global__ __launch_bounds__(64 * NW) void k_elem_solve(const SysDev *__restrict__ sys,
+                                                       const InstDev *__restrict__ ins,
+                                                       const int4 *__restrict__ work,
+                                                       const double *__restrict__ src,
+                                                       double *__restrict__ dst) {
+  extern __shared__ double sm[];
+  const int4 wk = work[blockIdx.x];
+  const int i = wk.x, j0 = wk.y, ng = wk.z, e = wk.w;
+  const InstDev I = ins[i];
+  const SysDev &S = sys[I.sys];
+  const int n2 = S.n2, mz = S.mz;
+  const int tile = blockIdx.y;
+  if (tile * 64 >= n2) return;
+  const double *Di = S.Dinv + ((size_t)S.strip_class[j0] * mz + e) * n2 * n2;
+  double *vl = sm;              // [SG][n2]
+  double *red = sm + SG * n2;   // [NW][SG][64]
+  for (int idx = threadIdx.x; idx < SG * n2; idx += 64 * NW) {
+    const int sI = idx / n2, l = idx - sI * n2;
+    vl[idx] = sI < ng ? src[I.f_off + ((int64_t)(j0 + sI) * mz + e) * n2 + l] : 0.0;
+  }
+  __syncthreads();
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int row = tile * 64 + lane;
+  double acc[SG];
+#pragma unroll
+  for (int q = 0; q < SG; ++q) acc[q] = 0.0;
+  colsplit<double, SG, 8>(Di, n2, row, (n2 * wave) / NW, (n2 * (wave + 1)) / NW, vl, n2, acc);
+#pragma unroll
+  for (int q = 0; q < SG; ++q) red[(wave * SG + q) * 64 + lane] = acc[q];
+  __syncthreads();
+  if (threadIdx.x < 64 && row < n2)
+    for (int q = 0; q < ng; ++q) {
+      double a = 0.0;
+#pragma unroll
+      for (int w = 0; w < NW; ++w) a += red[(w * SG + q) * 64 + lane];
+      dst[I.f_off + ((int64_t)(j0 + q) * mz + e) * n2 + row] = a;
+    }
+}
+
+// k_strip_q: lambda = Lambda w for one strip (the lo functional of interface
+// i reads element i, the up functional reads element i+1), then one 64-row
+// tile of q = K^-1 lambda.  Grid (inst * strip, q tile).
+template <int NW>
+__global__ __launch_bounds__(64 * NW) void k_strip_q(const SysDev *__restrict__ sys,
+                                                    const InstDev *__restrict__ ins,
+                                                    const int2 *__restrict__ work,
+                                                    const double *__restrict__ w,
+                                                    double *__restrict__ qout) {
+  extern __shared__ double sm[];
   const int2 wk = work[blockIdx.x];
   const int i = wk.x, j = wk.y;
   const InstDev I = ins[i];
   const SysDev &S = sys[I.sys];
-  const int n = S.n, n2 = S.n2, mz = S.mz;
-  const double *Gcl = S.Gs + (size_t)S.strip_class[j] * mz * n2 * n2;
-  const double *in = src + I.f_off + (int64_t)j * mz * n2;
-  double *out = dst + I.f_off + (int64_t)j * mz * n2;
-  for (int e = 0; e < mz; ++e) {
-    for (int l = threadIdx.x; l < n2; l += kBlock) rl[l] = in[(int64_t)e * n2 + l];
-    __syncthreads();
-    if (e > 0 && threadIdx.x < n) {
-      const int t = threadIdx.x;
-      const double *prev = out + (int64_t)(e - 1) * n2;
-      double a = 0.0;
-      for (int c = 0; c < n; ++c) a += S.lo[e * n + c] * prev[c * n + t];
-      rl[t] -= a;   // row (0, t)
+  const int n = S.n, n2 = S.n2, mz = S.mz, nq = S.nq;
+  const int tile = blockIdx.y;
+  if (tile * 64 >= nq) return;
+  double *lamv = sm;            // [nq]
+  double *red = sm + nq;        // [NW][64]
+  const double *ws = w + I.f_off + (int64_t)j * mz * n2;
+  for (int idx = threadIdx.x; idx < nq; idx += 64 * NW) {
+    const int iface = idx / (2 * n), r = idx - iface * 2 * n;
+    const int part = r / n, t = r - part * n;
+    double a = 0.0;
+    if (part == 0) {
+      const double *we = ws + (int64_t)iface * n2;
+      for (int c = 0; c < n; ++c) a += S.lo[(iface + 1) * n + c] * we[c * n + t];
+    } else {
+      const double *we = ws + (int64_t)(iface + 1) * n2;
+      for (int c = 0; c < n; ++c) a += S.up[iface * n + c] * we[c * n + t];
     }
-    __syncthreads();
-    const double *Ge = Gcl + (size_t)e * n2 * n2;
-    for (int row = threadIdx.x; row < n2; row += kBlock) {
-      double a = 0.0;
-      for (int l = 0; l < n2; ++l) a += Ge[(size_t)l * n2 + row] * rl[l];
-      out[(int64_t)e * n2 + row] = a;
-    }
-    __syncthreads();
+    lamv[idx] = a;
   }
-  for (int e = mz - 2; e >= 0; --e) {
-    if (threadIdx.x < n) {
-      const int t = threadIdx.x;
-      const double *nx = out + (int64_t)(e + 1) * n2;
-      double a = 0.0;
-      for (int c = 0; c < n; ++c) a += S.up[e * n + c] * nx[c * n + t];
-      qv[t] = a;
-    }
-    __syncthreads();
-    const double *Ge = Gcl + (size_t)e * n2 * n2;
-    for (int row = threadIdx.x; row < n2; row += kBlock) {
-      double a = out[(int64_t)e * n2 + row];
-      for (int t = 0; t < n; ++t) a -= Ge[(size_t)((n - 1) * n + t) * n2 + row] * qv[t];
-      out[(int64_t)e * n2 + row] = a;
-    }
-    __syncthreads();
+  __syncthreads();
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int row = tile * 64 + lane;
+  const double *Ki = S.Kinv + (size_t)S.strip_class[j] * nq * nq;   // column-major
+  double acc[1] = {0.0};
+  colsplit<double, 1, 8>(Ki, nq, row, (nq * wave) / NW, (nq * (wave + 1)) / NW, lamv, 0, acc);
+  red[wave * 64 + lane] = acc[0];
+  __syncthreads();
+  if (threadIdx.x < 64 && row < nq) {
+    double a = 0.0;
+#pragma unroll
+    for (int w2 = 0; w2 < NW; ++w2) a += red[w2 * 64 + lane];
+    qout[I.lam_off + (int64_t)j * nq + row] = a;
   }
+}
+
+// k_elem_correct: u_e = w_e - Dg_e^-1[:, rows (0,t)] q_lo - Dg_e^-1[:, rows
+// (n-1,t)] q_up (in place).  Grid (element item, 64-row tile).
+template <int SG>
+__global__ __launch_bounds__(kBlock) void k_elem_correct(const SysDev *__restrict__ sys,
+                                                         const InstDev *__restrict__ ins,
+                                                         const int4 *__restrict__ work,
+                                                         double *__restrict__ dst,
+                                                         const double *__restrict__ qv) {
+  __shared__ double qs[SG * 64];     // [SG][2n], n <= 32
+  __shared__ double red[4 * SG * 64];
+  const int4 wk = work[blockIdx.x];
+  const int i = wk.x, j0 = wk.y, ng = wk.z, e = wk.w;
+  const InstDev I = ins[i];
+  const SysDev &S = sys[I.sys];
+  const int n = S.n, n2 = S.n2, mz = S.mz, nq = S.nq;
+  if (nq == 0) return;
+  const int tile = blockIdx.y;
+  if (tile * 64 >= n2) return;
+  const double *Di = S.Dinv + ((size_t)S.strip_class[j0] * mz + e) * n2 * n2;
+  for (int idx = threadIdx.x; idx < SG * 2 * n; idx += kBlock) {
+    const int sI = idx / (2 * n), r = idx - sI * 2 * n;
+    const int part = r / n, t = r - part * n;
+    double a = 0.0;
+    if (sI < ng) {
+      if (part == 0 && e >= 1) a = qv[I.lam_off + (int64_t)(j0 + sI) * nq + (2 * (e - 1)) * n + t];
+      if (part == 1 && e + 1 < mz) a = qv[I.lam_off + (int64_t)(j0 + sI) * nq + (2 * e + 1) * n + t];
+    }
+    qs[idx] = a;
+  }
+  __syncthreads();
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int row = tile * 64 + lane;
+  const bool live = row < n2;
+  double acc[SG];
+#pragma unroll
+  for (int q = 0; q < SG; ++q) acc[q] = 0.0;
+  // 2n columns: t < n -> Di column t (row (0,t)); t >= n -> column (n-1)n + t - n
+  const int nc = 2 * n;
+  const int c0 = (nc * wave) >> 2, c1 = (nc * (wave + 1)) >> 2;
+  for (int c = c0; c < c1; ++c) {
+    const int colidx = c < n ? c : (n - 1) * n + (c - n);
+    const double v = live ? Di[(size_t)colidx * n2 + row] : 0.0;
+#pragma unroll
+    for (int q = 0; q < SG; ++q) acc[q] += v * qs[q * 2 * n + c];
+  }
+#pragma unroll
+  for (int q = 0; q < SG; ++q) red[(wave * SG + q) * 64 + lane] = acc[q];
+  __syncthreads();
+  if (threadIdx.x < 64 && live)
+    for (int q = 0; q < ng; ++q)
+      dst[I.f_off + ((int64_t)(j0 + q) * mz + e) * n2 + row] -=
+          (red[(0 * SG + q) * 64 + lane] + red[(1 * SG + q) * 64 + lane]) +
+          (red[(2 * SG + q) * 64 + lane] + red[(3 * SG + q) * 64 + lane]);
 }
 
 // RHS of Eq. (smpm_poisson): F = f + tau g on the physical edges (corners get
@@ -608,10 +773,12 @@ __global__ __launch_bounds__(kBlock) void k_halfsum(const SysDev *__restrict__ s
   a = block_sum(a, lds4);
   __syncthreads();
   if (hdot) b = block_sum(b, lds4);
+  const int tiles = (N + 63) >> 6;
   if (threadIdx.x == 0) {
-    hs[I.hs_off + h] = a;
+    hs[I.hs_off + (int64_t)h * tiles] = a;
     if (hdot) hdot[I.hs_off + h] = b;
   }
+  for (int q = 1 + (int)threadIdx.x; q < tiles; q += kBlock) hs[I.hs_off + (int64_t)h * tiles + q] = 0.0;
 }
 
 // r0 = P b~ = b~ - (S Z) c into Krylov slot 0 (or b~ itself without
@@ -683,7 +850,9 @@ __global__ __launch_bounds__(kBlock) void k_gmres_start(const InstDev *__restric
 // Elementwise interface-space helpers.
 // mode 0: out = a + Z c          (x_S = z + Z c')
 // mode 1: out = out + a + Z c    (refinement update)
-// mode 2: out = a - out          (residual r = b - S x), partials ||r||^2 and u_S . r
+// mode 2: out = out - a          (residual r = b - S x with out holding b), partials ||r||^2 and u_S . r
+// mode 3: out = a - (S Z) c      (deflation P)
+// mode 4: out = a - Z c          (deflation Q after c = G Z^T S a)
 template <typename TA>
 __global__ __launch_bounds__(kBlock) void k_xupdate(const SysDev *__restrict__ sys,
                                                     const InstDev *__restrict__ ins,
@@ -702,17 +871,27 @@ __global__ __launch_bounds__(kBlock) void k_xupdate(const SysDev *__restrict__ s
   for (int q = 0; q < kChunk / kBlock; ++q) {
     const int64_t e = (int64_t)ch * kChunk + threadIdx.x + q * kBlock;
     if (e >= S.kS) continue;
-    const int iface = (int)(e / N) >> 1;
+    const int h = (int)(e / N);
+    const int iface = h >> 1;
     double v = a ? (double)a[I.x_off + e] : 0.0;
     if (mode == 2) {
-      v = out[I.x_off + e] - v;   // out holds b
+      v = out[I.x_off + e] - v;
       out[I.x_off + e] = v;
       nn += v * v;
       if (S.singular) ud += S.uS[e] * v;
       continue;
     }
-    if (cvec) v += cvec[I.c_off + iface];
-    if (mode == 1) v += out[I.x_off + e];
+    if (mode == 3) {
+      const int row = (int)(e - (int64_t)h * N);
+      const int ca = S.sz_col[2 * h], cb = S.sz_col[2 * h + 1];
+      if (ca >= 0) v -= S.SZh[((size_t)2 * h) * N + row] * cvec[I.c_off + ca];
+      if (cb >= 0) v -= S.SZh[((size_t)2 * h + 1) * N + row] * cvec[I.c_off + cb];
+    } else if (mode == 4) {
+      v -= cvec[I.c_off + iface];
+    } else {
+      if (cvec) v += cvec[I.c_off + iface];
+      if (mode == 1) v += out[I.x_off + e];
+    }
     out[I.x_off + e] = v;
   }
   if (mode == 2) {

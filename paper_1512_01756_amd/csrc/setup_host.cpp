@@ -154,6 +154,96 @@ static void factor_class(const System &s, const GLL &g, StripClass &cl) {
   }
 }
 
+// Element inverses and the z-interface capacitance matrix of one class:
+// A_j^-1 = D^-1 - D^-1 P K^-1 Lambda D^-1, K = I + Lambda D^-1 P.
+static void element_woodbury(const System &s, const GLL &g, StripClass &cl) {
+  const int n = s.n, n2 = s.n2, mz = s.mz;
+  const int nq = 2 * n * (mz - 1);
+  cl.Dinv.assign((size_t)mz * n2 * n2, 0.0);
+  std::vector<double> Dg;
+  for (int e = 0; e < mz; ++e) {
+    const double hz = s.zb[e + 1] - s.zb[e];
+    element_diag_block(s, g, cl.hx, hz, cl.west_if, cl.east_if, e > 0, e < mz - 1, Dg);
+    if (!invert(n2, Dg.data(), n2)) throw std::runtime_error("singular element operator");
+    std::memcpy(&cl.Dinv[(size_t)e * n2 * n2], Dg.data(), sizeof(double) * n2 * n2);
+  }
+  cl.Kinv.assign((size_t)nq * nq, 0.0);
+  if (nq == 0) return;
+  std::vector<double> K((size_t)nq * nq, 0.0);
+  for (int a = 0; a < nq; ++a) K[(size_t)a * nq + a] = 1.0;
+  // column (interface i, part p, t): P puts a unit at element e_c, local l_c
+  for (int i = 0; i + 1 < mz; ++i)
+    for (int p = 0; p < 2; ++p)
+      for (int t = 0; t < n; ++t) {
+        const int col = (2 * i + p) * n + t;
+        const int ec = p == 0 ? i + 1 : i;
+        const int lc = p == 0 ? t : (n - 1) * n + t;
+        const double *Di = &cl.Dinv[(size_t)ec * n2 * n2];
+        // rows reading element ec: lo of interface ec (reads element ec, i.e.
+        // lo_{ec+1}) and up of interface ec-1 (reads element ec, up_{ec-1}).
+        if (ec + 1 < mz) {
+          const double *lo = &s.lo[(size_t)(ec + 1) * n];
+          for (int tr = 0; tr < n; ++tr) {
+            double a = 0.0;
+            for (int c = 0; c < n; ++c) a += lo[c] * Di[(size_t)(c * n + tr) * n2 + lc];
+            K[(size_t)((2 * ec + 0) * n + tr) * nq + col] += a;
+          }
+        }
+        if (ec >= 1) {
+          const double *up = &s.up[(size_t)(ec - 1) * n];
+          for (int tr = 0; tr < n; ++tr) {
+            double a = 0.0;
+            for (int c = 0; c < n; ++c) a += up[c] * Di[(size_t)(c * n + tr) * n2 + lc];
+            K[(size_t)((2 * (ec - 1) + 1) * n + tr) * nq + col] += a;
+          }
+        }
+      }
+  if (!invert(nq, K.data(), nq)) throw std::runtime_error("singular z-interface capacitance matrix");
+  cl.Kinv = std::move(K);
+}
+
+void strip_solve_woodbury(const System &s, const StripClass &cl, double *x) {
+  const int n = s.n, n2 = s.n2, mz = s.mz;
+  const int nq = 2 * n * (mz - 1);
+  std::vector<double> w((size_t)mz * n2, 0.0), lam(nq, 0.0), q(nq, 0.0);
+  for (int e = 0; e < mz; ++e) {
+    const double *Di = &cl.Dinv[(size_t)e * n2 * n2];
+    for (int r = 0; r < n2; ++r) {
+      double a = 0.0;
+      for (int l = 0; l < n2; ++l) a += Di[(size_t)r * n2 + l] * x[(size_t)e * n2 + l];
+      w[(size_t)e * n2 + r] = a;
+    }
+    for (int t = 0; t < n; ++t) {
+      if (e + 1 < mz) {
+        double a = 0.0;
+        for (int c = 0; c < n; ++c) a += s.lo[(size_t)(e + 1) * n + c] * w[(size_t)e * n2 + c * n + t];
+        lam[(size_t)(2 * e) * n + t] = a;
+      }
+      if (e >= 1) {
+        double a = 0.0;
+        for (int c = 0; c < n; ++c) a += s.up[(size_t)(e - 1) * n + c] * w[(size_t)e * n2 + c * n + t];
+        lam[(size_t)(2 * (e - 1) + 1) * n + t] = a;
+      }
+    }
+  }
+  for (int a = 0; a < nq; ++a) {
+    double acc = 0.0;
+    for (int b = 0; b < nq; ++b) acc += cl.Kinv[(size_t)a * nq + b] * lam[b];
+    q[a] = acc;
+  }
+  for (int e = 0; e < mz; ++e) {
+    const double *Di = &cl.Dinv[(size_t)e * n2 * n2];
+    for (int r = 0; r < n2; ++r) {
+      double a = w[(size_t)e * n2 + r];
+      for (int t = 0; t < n; ++t) {
+        if (e >= 1) a -= Di[(size_t)r * n2 + t] * q[(size_t)(2 * (e - 1)) * n + t];
+        if (e + 1 < mz) a -= Di[(size_t)r * n2 + (n - 1) * n + t] * q[(size_t)(2 * e + 1) * n + t];
+      }
+      x[(size_t)e * n2 + r] = a;
+    }
+  }
+}
+
 void strip_solve(const System &s, const StripClass &cl, double *X, int nrhs) {
   const int n = s.n, n2 = s.n2, mz = s.mz;
   std::vector<double> R((size_t)n2 * nrhs), q((size_t)n * nrhs);
@@ -492,6 +582,7 @@ void build_system(System &s, int mx, int mz, int order, const double *xb, const 
   parallel_for((int)s.classes.size(), opt.threads, [&](int c) {
     factor_class(s, g, s.classes[c]);
     class_schur_blocks(s, s.classes[c]);
+    element_woodbury(s, g, s.classes[c]);
   });
   // Schur blocks per output half, deduplicated by (strip class, row side).
   s.w_id.assign(s.nh, -1); s.w_win.assign(s.nh, 0);

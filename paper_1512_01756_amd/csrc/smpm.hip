@@ -8,6 +8,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <map>
 #include <memory>
 #include <stdexcept>
 #include <string>
@@ -67,6 +68,10 @@ std::vector<T> to_colmajor(const std::vector<double> &a, int nb, int rows, int c
   return out;
 }
 
+constexpr int kStripsPerGroup = 4;
+constexpr int kIterChunk = 4;
+constexpr int kWaves = 16;   // waves per workgroup of the GEMV-shaped kernels
+
 }  // namespace
 
 struct smpm_handle {
@@ -81,10 +86,14 @@ struct smpm_handle {
   std::vector<InstDev> h_ins;
   SysDev *d_sys = nullptr;
   InstDev *d_ins = nullptr;
-  int ninst = 0;
+  int ninst = 0, Nmax = 0, group = 1, nq_max = 0, n2_max = 0;
+  // Work lists: grouped halves for S and M^-1, plain halves, element items,
+  // interface and node vector chunks.  Per instance [start, start + count).
+  HWork *w_S = nullptr, *w_M = nullptr;
   int2 *w_h = nullptr, *w_x = nullptr, *w_r = nullptr, *w_s = nullptr;
-  int n_h = 0, n_x = 0, n_r = 0, n_s = 0;
-  std::vector<int> h_start, x_start;       // per instance: first work item in w_h / w_x
+  int4 *w_E = nullptr;
+  int n_S = 0, n_M = 0, n_h = 0, n_E = 0, n_x = 0, n_r = 0, n_s = 0;
+  std::vector<int> S_start, S_cnt, M_start, M_cnt, h_start, E_start, E_cnt, x_start, r_start, s_start;
   int64_t tot_r = 0, tot_x = 0, tot_g = 0;
 
   double *F = nullptr, *v = nullptr, *Rr = nullptr, *bS = nullptr, *xS = nullptr, *rb = nullptr;
@@ -92,15 +101,26 @@ struct smpm_handle {
   float *z32 = nullptr, *y32 = nullptr, *t32 = nullptr;
   double *V64 = nullptr;
   float *V32 = nullptr;
-  double *part1 = nullptr, *part2 = nullptr, *partn = nullptr, *pr = nullptr, *hs = nullptr, *hs2 = nullptr;
+  double *part1 = nullptr, *part2 = nullptr, *partn = nullptr, *pr = nullptr, *hs = nullptr;
   double *cv = nullptr, *tb = nullptr, *scale = nullptr, *Rm = nullptr, *cs = nullptr, *sn = nullptr, *g = nullptr;
-  double *ycoef = nullptr, *defect = nullptr, *pairs = nullptr;
+  double *ycoef = nullptr, *defect = nullptr, *pairs = nullptr, *lam = nullptr;
   GState *gs = nullptr;
   GState *h_gs = nullptr;      // pinned
   double *h_pairs = nullptr;   // pinned
   double *h_defect = nullptr;  // pinned
+  // The solve runs on an internal stream (default priority) ordered against
+  // the caller's stream with events; the GMRES iteration is replayed from a
+  // captured graph of kIterChunk iterations per precision.
+  hipStream_t ws = nullptr;
+  hipEvent_t ev_in = nullptr, ev_out = nullptr;
+  hipGraphExec_t loop64 = nullptr, loop32 = nullptr;
 
   ~smpm_handle() {
+    if (loop64) (void)hipGraphExecDestroy(loop64);
+    if (loop32) (void)hipGraphExecDestroy(loop32);
+    if (ev_in) (void)hipEventDestroy(ev_in);
+    if (ev_out) (void)hipEventDestroy(ev_out);
+    if (ws) (void)hipStreamDestroy(ws);
     for (void *p : owned) (void)hipFree(p);
     if (h_gs) (void)hipHostFree(h_gs);
     if (h_pairs) (void)hipHostFree(h_pairs);
@@ -110,14 +130,37 @@ struct smpm_handle {
 
 namespace {
 
+// Group the halves of one instance that share a block id (up to `group`).
+void group_halves(int inst, const std::vector<int> &ids, int group, std::vector<HWork> &out) {
+  std::map<int, std::vector<int>> by;
+  for (int h = 0; h < (int)ids.size(); ++h) by[ids[h]].push_back(h);
+  for (auto &kv : by) {
+    const std::vector<int> &hs = kv.second;
+    for (size_t a = 0; a < hs.size(); a += group) {
+      HWork w{};
+      w.inst = inst;
+      w.cnt = (int)std::min<size_t>(group, hs.size() - a);
+      for (int q = 0; q < kGroup; ++q) w.h[q] = q < w.cnt ? hs[a + q] : hs[a];
+      out.push_back(w);
+    }
+  }
+}
+
 void upload(smpm_handle *H, hipStream_t st) {
   auto &own = H->owned;
   const int maxit = H->maxit;
-  // per-system device tables
+  for (System &s : H->sys) {
+    H->Nmax = std::max(H->Nmax, s.N);
+    H->nq_max = std::max(H->nq_max, 2 * s.n * (s.mz - 1));
+    H->n2_max = std::max(H->n2_max, s.n2);
+  }
+  // Group size bounded by the GEMV's LDS budget (windows + wave partials).
+  H->group = ((size_t)kGroup * (4 * H->Nmax + kWaves * 64) * sizeof(double) <= 64 * 1024) ? kGroup : 1;
   for (System &s : H->sys) {
     SysDev d{};
     d.n = s.n; d.mx = s.mx; d.mz = s.mz; d.n2 = s.n2; d.N = s.N; d.nh = s.nh; d.d = s.d;
     d.singular = s.singular ? 1 : 0; d.kS = s.kS; d.r = s.r; d.tau = s.tau;
+    d.nq = 2 * s.n * (s.mz - 1);
     d.W64 = dupload(own, to_colmajor<double>(s.Wblk, s.nW, s.N, 2 * s.N), st);
     d.W32 = dupload(own, to_colmajor<float>(s.Wblk, s.nW, s.N, 2 * s.N), st);
     d.w_id = dupload(own, s.w_id, st);
@@ -132,14 +175,18 @@ void upload(smpm_handle *H, hipStream_t st) {
     d.Gc = dupload(own, to_colmajor<double>(s.Gc, 1, s.d, s.d), st);
     d.uS = s.singular ? dupload(own, s.uS, st) : nullptr;
     d.uL = s.singular ? dupload(own, s.uL, st) : nullptr;
-    std::vector<double> Gs, beta;
+    std::vector<double> Dinv, Kinv, beta;
     for (const StripClass &c : s.classes) {
-      std::vector<double> cm = to_colmajor<double>(c.G, s.mz, s.n2, s.n2);
-      Gs.insert(Gs.end(), cm.begin(), cm.end());
+      std::vector<double> cm = to_colmajor<double>(c.Dinv, s.mz, s.n2, s.n2);
+      Dinv.insert(Dinv.end(), cm.begin(), cm.end());
+      const int nq = 2 * s.n * (s.mz - 1);
+      std::vector<double> kc = to_colmajor<double>(c.Kinv, 1, nq, nq);
+      Kinv.insert(Kinv.end(), kc.begin(), kc.end());
       beta.insert(beta.end(), c.betaW.begin(), c.betaW.end());
       beta.insert(beta.end(), c.betaE.begin(), c.betaE.end());
     }
-    d.Gs = dupload(own, Gs, st);
+    d.Dinv = dupload(own, Dinv, st);
+    d.Kinv = dupload(own, Kinv, st);
     d.beta = dupload(own, beta, st);
     d.lo = dupload(own, s.lo, st);
     d.up = dupload(own, s.up, st);
@@ -147,11 +194,14 @@ void upload(smpm_handle *H, hipStream_t st) {
     H->h_sys.push_back(d);
   }
   H->d_sys = dupload(own, H->h_sys, st);
-  // instances
+  std::vector<HWork> wS, wM;
+  std::vector<int4> wE;
   std::vector<int2> wh, wx, wr, ws;
-  int64_t f_off = 0, g_off = 0, x_off = 0, v_off = 0, part_off = 0, pr_off = 0, hs_off = 0, c_off = 0, st_off = 0, rr_off = 0;
+  int64_t f_off = 0, g_off = 0, x_off = 0, v_off = 0, part_off = 0, pr_off = 0, hs_off = 0, c_off = 0,
+          st_off = 0, rr_off = 0, lam_off = 0;
   for (int si = 0; si < (int)H->sys.size(); ++si) {
     const System &s = H->sys[si];
+    const int nq = 2 * s.n * (s.mz - 1);
     for (int q = 0; q < H->nrhs; ++q) {
       InstDev I{};
       const int inst = (int)H->h_ins.size();
@@ -160,27 +210,46 @@ void upload(smpm_handle *H, hipStream_t st) {
       I.nchunk_r = (int)((s.r + kChunk - 1) / kChunk);
       I.f_off = f_off; I.g_off = g_off; I.x_off = x_off; I.v_off = v_off;
       I.part_off = part_off; I.pr_off = pr_off; I.hs_off = hs_off; I.c_off = c_off;
-      I.st_off = st_off; I.rr_off = rr_off;
+      I.st_off = st_off; I.rr_off = rr_off; I.lam_off = lam_off;
       f_off += s.r; g_off += 2LL * s.n * (s.mx + s.mz); x_off += s.kS; v_off += (int64_t)(maxit + 1) * s.kS;
-      part_off += (int64_t)(maxit + 1) * I.nchunk_x + 2; pr_off += 2LL * I.nchunk_r; hs_off += s.nh; c_off += s.d;
-      st_off += maxit + 1; rr_off += (int64_t)maxit * maxit;
+      part_off += (int64_t)(maxit + 1) * I.nchunk_x + 2; pr_off += 2LL * I.nchunk_r;
+      hs_off += (int64_t)s.nh * ((s.N + 63) / 64); c_off += s.d;
+      st_off += maxit + 1; rr_off += (int64_t)maxit * maxit; lam_off += (int64_t)s.mx * nq;
+      H->S_start.push_back((int)wS.size());
+      group_halves(inst, s.w_id, H->group, wS);
+      H->S_cnt.push_back((int)wS.size() - H->S_start.back());
+      H->M_start.push_back((int)wM.size());
+      group_halves(inst, s.m_id, H->group, wM);
+      H->M_cnt.push_back((int)wM.size() - H->M_start.back());
       H->h_start.push_back((int)wh.size());
       for (int h = 0; h < s.nh; ++h) wh.push_back(make_int2(inst, h));
+      H->E_start.push_back((int)wE.size());
+      for (int j = 0; j < s.mx;) {
+        int ng = 1;
+        while (ng < kStripsPerGroup && j + ng < s.mx && s.strip_class[j + ng] == s.strip_class[j]) ++ng;
+        for (int e = 0; e < s.mz; ++e) wE.push_back(make_int4(inst, j, ng, e));
+        j += ng;
+      }
+      H->E_cnt.push_back((int)wE.size() - H->E_start.back());
+      H->s_start.push_back((int)ws.size());
+      for (int j = 0; j < s.mx; ++j) ws.push_back(make_int2(inst, j));
       H->x_start.push_back((int)wx.size());
       for (int c = 0; c < I.nchunk_x; ++c) wx.push_back(make_int2(inst, c));
+      H->r_start.push_back((int)wr.size());
       for (int c = 0; c < I.nchunk_r; ++c) wr.push_back(make_int2(inst, c));
-      for (int j = 0; j < s.mx; ++j) ws.push_back(make_int2(inst, j));
       H->h_ins.push_back(I);
     }
   }
   H->ninst = (int)H->h_ins.size();
   H->tot_r = f_off; H->tot_x = x_off; H->tot_g = g_off;
   H->d_ins = dupload(own, H->h_ins, st);
+  H->w_S = dupload(own, wS, st); H->n_S = (int)wS.size();
+  H->w_M = dupload(own, wM, st); H->n_M = (int)wM.size();
   H->w_h = dupload(own, wh, st); H->n_h = (int)wh.size();
+  H->w_E = dupload(own, wE, st); H->n_E = (int)wE.size();
   H->w_x = dupload(own, wx, st); H->n_x = (int)wx.size();
   H->w_r = dupload(own, wr, st); H->n_r = (int)wr.size();
   H->w_s = dupload(own, ws, st); H->n_s = (int)ws.size();
-  // work buffers
   H->F = dalloc<double>(own, f_off); H->v = dalloc<double>(own, f_off); H->Rr = dalloc<double>(own, f_off);
   H->bS = dalloc<double>(own, x_off); H->xS = dalloc<double>(own, x_off); H->rb = dalloc<double>(own, x_off);
   H->z64 = dalloc<double>(own, x_off); H->y64 = dalloc<double>(own, x_off); H->t64 = dalloc<double>(own, x_off);
@@ -188,27 +257,92 @@ void upload(smpm_handle *H, hipStream_t st) {
   if (H->precision == SMPM_FP64) H->V64 = dalloc<double>(own, v_off);
   else H->V32 = dalloc<float>(own, v_off);
   H->part1 = dalloc<double>(own, part_off); H->part2 = dalloc<double>(own, part_off); H->partn = dalloc<double>(own, part_off);
-  H->pr = dalloc<double>(own, pr_off); H->hs = dalloc<double>(own, hs_off); H->hs2 = dalloc<double>(own, hs_off);
+  H->pr = dalloc<double>(own, pr_off); H->hs = dalloc<double>(own, hs_off);
   H->cv = dalloc<double>(own, c_off); H->tb = dalloc<double>(own, c_off);
   H->scale = dalloc<double>(own, st_off); H->cs = dalloc<double>(own, st_off); H->sn = dalloc<double>(own, st_off);
   H->g = dalloc<double>(own, st_off); H->ycoef = dalloc<double>(own, st_off); H->Rm = dalloc<double>(own, rr_off);
+  H->lam = dalloc<double>(own, lam_off);
   H->defect = dalloc<double>(own, H->ninst); H->pairs = dalloc<double>(own, 2 * H->ninst);
   H->gs = dalloc<GState>(own, H->ninst);
   HIPCHECK(hipHostMalloc((void **)&H->h_gs, sizeof(GState) * H->ninst, hipHostMallocDefault));
   HIPCHECK(hipHostMalloc((void **)&H->h_pairs, sizeof(double) * 2 * H->ninst, hipHostMallocDefault));
   HIPCHECK(hipHostMalloc((void **)&H->h_defect, sizeof(double) * H->ninst, hipHostMallocDefault));
+  HIPCHECK(hipStreamCreateWithFlags(&H->ws, hipStreamNonBlocking));
+  HIPCHECK(hipEventCreateWithFlags(&H->ev_in, hipEventDisableTiming));
+  HIPCHECK(hipEventCreateWithFlags(&H->ev_out, hipEventDisableTiming));
   HIPCHECK(hipStreamSynchronize(st));
+}
+
+// ---------------------------------------------------------------------------
+// Launch helpers.  `inst` >= 0 restricts a launch to one instance's items.
+
+template <typename TO, typename TX, typename TY>
+void gemv(smpm_handle *H, int op, const TX *x, int vslot, const double *scale, TY *y, double *hsum,
+          const GState *gs, hipStream_t st, int inst = -1) {
+  const HWork *w = op == 0 ? H->w_S : H->w_M;
+  int count = op == 0 ? H->n_S : H->n_M;
+  if (inst >= 0) {
+    w += op == 0 ? H->S_start[inst] : H->M_start[inst];
+    count = op == 0 ? H->S_cnt[inst] : H->M_cnt[inst];
+  }
+  if (count == 0) return;
+  const int Kmax = (op == 0 ? 2 : 4) * H->Nmax;
+  const int tiles = (H->Nmax + 63) / 64;
+  if (H->group == kGroup) {
+    const size_t shm = sizeof(double) * kGroup * (Kmax + kWaves * 64);
+    hipLaunchKernelGGL((k_half_gemv<TO, TX, TY, kGroup, kWaves>), dim3(count, tiles), dim3(64 * kWaves), shm, st, H->d_sys,
+                       H->d_ins, w, op, x, vslot, scale, y, hsum, gs);
+  } else {
+    const size_t shm = sizeof(double) * (Kmax + kWaves * 64);
+    hipLaunchKernelGGL((k_half_gemv<TO, TX, TY, 1, kWaves>), dim3(count, tiles), dim3(64 * kWaves), shm, st, H->d_sys,
+                       H->d_ins, w, op, x, vslot, scale, y, hsum, gs);
+  }
+}
+
+// dst = A(k)^-1 src (node space; src may alias dst): element solves, the
+// per-strip z-interface capacitance solve, element corrections.
+void ainv(smpm_handle *H, const double *src, double *dst, hipStream_t st, int inst = -1) {
+  const int4 *w = H->w_E + (inst >= 0 ? H->E_start[inst] : 0);
+  const int count = inst >= 0 ? H->E_cnt[inst] : H->n_E;
+  if (count == 0) return;
+  const int rtiles = (H->n2_max + 63) / 64;
+  const size_t shm1 = sizeof(double) * kStripsPerGroup * (H->n2_max + kWaves * 64);
+  hipLaunchKernelGGL((k_elem_solve<kStripsPerGroup, kWaves>), dim3(count, rtiles), dim3(64 * kWaves), shm1, st, H->d_sys,
+                     H->d_ins, w, src, dst);
+  if (H->nq_max > 0) {
+    const int2 *ws = H->w_s + (inst >= 0 ? H->s_start[inst] : 0);
+    const int scount = inst >= 0 ? H->sys[H->h_ins[inst].sys].mx : H->n_s;
+    const size_t shm2 = sizeof(double) * (H->nq_max + kWaves * 64);
+    hipLaunchKernelGGL((k_strip_q<kWaves>), dim3(scount, (H->nq_max + 63) / 64), dim3(64 * kWaves), shm2, st, H->d_sys,
+                       H->d_ins, ws, (const double *)dst, H->lam);
+    hipLaunchKernelGGL(k_elem_correct<kStripsPerGroup>, dim3(count, rtiles), dim3(kBlock), 0, st, H->d_sys, H->d_ins, w,
+                       dst, (const double *)H->lam);
+  }
+}
+
+const int2 *xwork(smpm_handle *H, int inst, int &count) {
+  if (inst < 0) { count = H->n_x; return H->w_x; }
+  count = H->h_ins[inst].nchunk_x;
+  return H->w_x + H->x_start[inst];
+}
+
+const int2 *hwork(smpm_handle *H, int inst, int &count) {
+  if (inst < 0) { count = H->n_h; return H->w_h; }
+  count = H->sys[H->h_ins[inst].sys].nh;
+  return H->w_h + H->h_start[inst];
 }
 
 // ---------------------------------------------------------------------------
 // Solve steps.
 
+// Steps 1-3 of Algorithm 2: F = f + tau g, F~ = F - u_L u_L^T F, v = A^-1 F~,
+// b~ = B v - u_S u_S^T B v.
 void stage_rhs(smpm_handle *H, const double *f, const double *g, hipStream_t st) {
   hipLaunchKernelGGL(k_rhs, dim3(H->n_r), dim3(kBlock), 0, st, H->d_sys, H->d_ins, H->w_r, f, g, H->F, H->pr);
   hipLaunchKernelGGL(k_proj_r, dim3(H->n_r), dim3(kBlock), 0, st, H->d_sys, H->d_ins, H->w_r, H->F, H->pr, H->defect);
-  hipLaunchKernelGGL(k_strip_solve, dim3(H->n_s), dim3(kBlock), 0, st, H->d_sys, H->d_ins, H->w_s, H->F, H->v);
-  hipLaunchKernelGGL(k_bS, dim3(H->n_h), dim3(kBlock), 0, st, H->d_sys, H->d_ins, H->w_h, H->v, H->bS, H->hs);
-  hipLaunchKernelGGL(k_proj_x, dim3(H->n_x), dim3(kBlock), 0, st, H->d_sys, H->d_ins, H->w_x, H->bS, H->hs);
+  ainv(H, H->F, H->v, st);
+  hipLaunchKernelGGL(k_bS, dim3(H->n_h), dim3(kBlock), 0, st, H->d_sys, H->d_ins, H->w_h, (const double *)H->v, H->bS, H->hs);
+  hipLaunchKernelGGL(k_proj_x, dim3(H->n_x), dim3(kBlock), 0, st, H->d_sys, H->d_ins, H->w_x, H->bS, (const double *)H->hs);
 }
 
 bool any_active(smpm_handle *H, hipStream_t st) {
@@ -228,45 +362,37 @@ struct InnerStats {
 };
 
 // Inner DBJ-GMRES (or BJ / Schur) on right-hand side b (FP64, interface
-// space), in precision T for the operators and the Krylov basis.
+// space), operators and Krylov basis in precision T.  The stopping test is
+// |g| <= tol * sqrt(pairs[2 i]) (the caller leaves ||b||^2 there).
 // accumulate = 0: out = x;  1: out += x.
 template <typename T>
 InnerStats inner_solve(smpm_handle *H, const double *b, double *out, int accumulate, double tol, hipStream_t st) {
   InnerStats is;
-  T *V = nullptr;
-  T *z = nullptr, *y = nullptr, *t = nullptr;
+  T *V = nullptr, *z = nullptr, *y = nullptr, *t = nullptr;
   if constexpr (sizeof(T) == 8) { V = (T *)H->V64; z = (T *)H->z64; y = (T *)H->y64; t = (T *)H->t64; }
   else { V = (T *)H->V32; z = (T *)H->z32; y = (T *)H->y32; t = (T *)H->t32; }
   const bool useM = H->method != SMPM_METHOD_SCHUR;
   const bool useP = H->method == SMPM_METHOD_DBJ;
   const int maxit = H->maxit;
   const size_t shm_dot = sizeof(double) * (maxit + 1) * 5;
-  // Z^T b, coarse part c = G Z^T b
-  if (useP) {
+  if (useP) {   // coarse part: c = G Z^T b (kept as t_b = Z^T b for the final assembly)
     hipLaunchKernelGGL(k_halfsum, dim3(H->n_h), dim3(kBlock), 0, st, H->d_sys, H->d_ins, H->w_h, b, H->hs, (double *)nullptr);
-    hipLaunchKernelGGL(k_coarse, dim3(H->ninst), dim3(kBlock), 0, st, H->d_sys, H->d_ins, H->hs, (const double *)nullptr, H->tb, H->cv, (const GState *)nullptr);
+    hipLaunchKernelGGL(k_coarse, dim3(H->ninst), dim3(kBlock), 0, st, H->d_sys, H->d_ins, (const double *)H->hs,
+                       (const double *)nullptr, H->tb, H->cv, (const GState *)nullptr);
   }
   hipLaunchKernelGGL(k_init_basis<T>, dim3(H->n_x), dim3(kBlock), 0, st, H->d_sys, H->d_ins, H->w_x, b,
                      useP ? (const double *)H->cv : (const double *)nullptr, V, H->partn);
-  hipLaunchKernelGGL(k_gmres_start, dim3(H->ninst), dim3(kBlock), 0, st, H->d_ins, H->partn, (const double *)H->pairs,
-                     H->scale, H->g, H->gs, 1);
-  const int check_every = 2;
-  for (int it = 0; it < maxit; ++it) {
-    const T *xin = V;
-    int vslot = 1;
-    const double *sc = H->scale;
+  hipLaunchKernelGGL(k_gmres_start, dim3(H->ninst), dim3(kBlock), 0, st, H->d_ins, (const double *)H->partn,
+                     (const double *)H->pairs, H->scale, H->g, H->gs, 1);
+  auto one_iteration = [&]() {
     if (useM) {
-      hipLaunchKernelGGL((k_half_gemv<T, T, T>), dim3(H->n_h), dim3(kBlock), 0, st, H->d_sys, H->d_ins, H->w_h, 1,
-                         (const T *)V, 1, (const double *)H->scale, z, (double *)nullptr, (const GState *)H->gs);
-      xin = z; vslot = 0; sc = nullptr;
+      gemv<T, T, T>(H, 1, (const T *)V, 1, H->scale, z, nullptr, H->gs, st);
+      gemv<T, T, T>(H, 0, (const T *)z, 0, nullptr, y, useP ? H->hs : nullptr, H->gs, st);
+    } else {
+      gemv<T, T, T>(H, 0, (const T *)V, 1, H->scale, y, useP ? H->hs : nullptr, H->gs, st);
     }
-    hipLaunchKernelGGL((k_half_gemv<T, T, T>), dim3(H->n_h), dim3(kBlock), 0, st, H->d_sys, H->d_ins, H->w_h, 0,
-                       xin, vslot, sc, y, useP ? H->hs : (double *)nullptr, (const GState *)H->gs);
-    if (useP)
-      hipLaunchKernelGGL(k_coarse, dim3(H->ninst), dim3(kBlock), 0, st, H->d_sys, H->d_ins, H->hs, (const double *)nullptr,
-                         (double *)nullptr, H->cv, (const GState *)H->gs);
     hipLaunchKernelGGL((k_pcorr_dot<T, T>), dim3(H->n_x), dim3(kBlock), sizeof(double) * (maxit + 1) * 4, st, H->d_sys,
-                       H->d_ins, H->w_x, (const T *)y, useP ? (const double *)H->cv : (const double *)nullptr, V, H->part1,
+                       H->d_ins, H->w_x, (const T *)y, (const double *)H->hs, useP ? 1 : 0, V, H->part1,
                        (const GState *)H->gs, maxit);
     hipLaunchKernelGGL((k_axpy_dot<T>), dim3(H->n_x), dim3(kBlock), shm_dot, st, H->d_sys, H->d_ins, H->w_x, V,
                        (const double *)H->part1, H->part2, (double *)nullptr, (const double *)H->scale, (const GState *)H->gs);
@@ -275,30 +401,38 @@ InnerStats inner_solve(smpm_handle *H, const double *b, double *out, int accumul
     hipLaunchKernelGGL(k_givens, dim3(H->ninst), dim3(kBlock), sizeof(double) * (maxit + 2), st, H->d_ins,
                        (const double *)H->part1, (const double *)H->part2, (const double *)H->partn, H->scale, H->Rm,
                        H->cs, H->sn, H->g, H->gs, maxit, tol);
-    if ((it + 1) % check_every == 0 || it + 1 == maxit)
-      if (!any_active(H, st)) break;
+  };
+  hipGraphExec_t &exec = sizeof(T) == 8 ? H->loop64 : H->loop32;
+  if (!exec) {
+    hipGraph_t graph = nullptr;
+    HIPCHECK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+    for (int c = 0; c < kIterChunk; ++c) one_iteration();
+    HIPCHECK(hipStreamEndCapture(st, &graph));
+    HIPCHECK(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
+    HIPCHECK(hipGraphDestroy(graph));
+  }
+  for (int it = 0; it < maxit; it += kIterChunk) {
+    HIPCHECK(hipGraphLaunch(exec, st));
+    if (!any_active(H, st)) break;
   }
   HIPCHECK(hipGetLastError());
-  // x' = V y; x = M^-1 x' (+ coarse part)
+  // x' = V y; x = M^-1 x' + coarse part
   hipLaunchKernelGGL(k_backsolve, dim3(H->ninst), dim3(kBlock), sizeof(double) * (maxit + 1), st, H->d_ins,
                      (const double *)H->Rm, (const double *)H->g, (const double *)H->scale, H->ycoef, (const GState *)H->gs, maxit);
   hipLaunchKernelGGL((k_combine<T, T>), dim3(H->n_x), dim3(kBlock), 0, st, H->d_sys, H->d_ins, H->w_x, (const T *)V,
                      (const double *)H->ycoef, t, (const GState *)H->gs);
   const T *xfin = t;
   if (useM) {
-    hipLaunchKernelGGL((k_half_gemv<T, T, T>), dim3(H->n_h), dim3(kBlock), 0, st, H->d_sys, H->d_ins, H->w_h, 1,
-                       (const T *)t, 0, (const double *)nullptr, z, (double *)nullptr, (const GState *)nullptr);
+    gemv<T, T, T>(H, 1, (const T *)t, 0, nullptr, z, nullptr, nullptr, st);
     xfin = z;
   }
   const double *cfin = nullptr;
-  if (useP) {
-    // c' = G (Z^T b - Z^T S z): x = z + Z c'
-    hipLaunchKernelGGL((k_half_gemv<T, T, T>), dim3(H->n_h), dim3(kBlock), 0, st, H->d_sys, H->d_ins, H->w_h, 0,
-                       (const T *)z, 0, (const double *)nullptr, y, H->hs, (const GState *)nullptr);
-    hipLaunchKernelGGL(k_coarse, dim3(H->ninst), dim3(kBlock), 0, st, H->d_sys, H->d_ins, H->hs, (const double *)H->tb,
-                       (double *)nullptr, H->cv, (const GState *)nullptr);
+  if (useP) {   // c' = G (Z^T b - Z^T S z): x = z + Z c'
+    gemv<T, T, T>(H, 0, (const T *)z, 0, nullptr, y, H->hs, nullptr, st);
+    hipLaunchKernelGGL(k_coarse, dim3(H->ninst), dim3(kBlock), 0, st, H->d_sys, H->d_ins, (const double *)H->hs,
+                       (const double *)H->tb, (double *)nullptr, H->cv, (const GState *)nullptr);
     cfin = H->cv;
-    is.matvecs += 1;
+    is.matvecs += H->ninst;
   }
   hipLaunchKernelGGL(k_xupdate<T>, dim3(H->n_x), dim3(kBlock), 0, st, H->d_sys, H->d_ins, H->w_x, accumulate ? 1 : 0,
                      xfin, cfin, out, (double *)nullptr);
@@ -316,17 +450,16 @@ InnerStats inner_solve(smpm_handle *H, const double *b, double *out, int accumul
   return is;
 }
 
-// r = b~ - S x (FP64), projected out of u_S; returns per-instance ||r||/||b~||
-// in rel (host) given ||b~||.
+// r = b~ - S x (FP64); pairs[2 i] = ||r||^2, pairs[2 i + 1] = u_S . r.
 void residual64(smpm_handle *H, const double *x, double *r, hipStream_t st) {
-  hipLaunchKernelGGL((k_half_gemv<double, double, double>), dim3(H->n_h), dim3(kBlock), 0, st, H->d_sys, H->d_ins, H->w_h, 0,
-                     x, 0, (const double *)nullptr, H->y64, (double *)nullptr, (const GState *)nullptr);
+  gemv<double, double, double>(H, 0, x, 0, nullptr, H->y64, nullptr, nullptr, st);
   HIPCHECK(hipMemcpyAsync(r, H->bS, sizeof(double) * H->tot_x, hipMemcpyDeviceToDevice, st));
   hipLaunchKernelGGL(k_xupdate<double>, dim3(H->n_x), dim3(kBlock), 0, st, H->d_sys, H->d_ins, H->w_x, 2,
                      (const double *)H->y64, (const double *)nullptr, r, H->partn);
   hipLaunchKernelGGL(k_reduce_pairs, dim3(H->ninst), dim3(kBlock), 0, st, H->d_ins, (const double *)H->partn, H->pairs);
 }
 
+// ||b~|| per instance (host), and pairs[2 i] = ||b~||^2 on the device.
 void norms_of_b(smpm_handle *H, std::vector<double> &nb, hipStream_t st) {
   HIPCHECK(hipMemcpyAsync(H->rb, H->bS, sizeof(double) * H->tot_x, hipMemcpyDeviceToDevice, st));
   hipLaunchKernelGGL(k_xupdate<double>, dim3(H->n_x), dim3(kBlock), 0, st, H->d_sys, H->d_ins, H->w_x, 2,
@@ -338,10 +471,11 @@ void norms_of_b(smpm_handle *H, std::vector<double> &nb, hipStream_t st) {
   for (int i = 0; i < H->ninst; ++i) nb[i] = std::sqrt(H->h_pairs[2 * i]);
 }
 
+// Step 9 of Algorithm 2 and the gauge: u = A^-1 (F~ - E x_S), minus its mean for k = 0.
 void finish_u(smpm_handle *H, double *u, hipStream_t st) {
   hipLaunchKernelGGL(k_recover_rhs, dim3(H->n_r), dim3(kBlock), 0, st, H->d_sys, H->d_ins, H->w_r, (const double *)H->F,
                      (const double *)H->xS, H->Rr);
-  hipLaunchKernelGGL(k_strip_solve, dim3(H->n_s), dim3(kBlock), 0, st, H->d_sys, H->d_ins, H->w_s, (const double *)H->Rr, u);
+  ainv(H, H->Rr, u, st);
   hipLaunchKernelGGL(k_sum_r, dim3(H->n_r), dim3(kBlock), 0, st, H->d_sys, H->d_ins, H->w_r, (const double *)u, H->pr);
   hipLaunchKernelGGL(k_sub_mean, dim3(H->n_r), dim3(kBlock), 0, st, H->d_sys, H->d_ins, H->w_r, u, (const double *)H->pr);
 }
@@ -385,22 +519,27 @@ smpm_status setup_common(const smpm_grid *grids, const double *k, int nsys, bool
     if (!(k[i] >= 0.0) || !std::isfinite(k[i])) return fail(SMPM_EINVAL, "wavenumbers must be finite and >= 0");
   }
   H->sys.resize(nsys);
+  std::vector<std::string> errs(nsys);
+  std::vector<int> codes(nsys, SMPM_OK);
   SetupOptions so;
   so.tau = H->opts.tau;
-  try {
-    for (int i = 0; i < nsys; ++i) {
-      const smpm_grid &g = one_grid ? grids[0] : grids[i];
+  so.threads = nsys > 1 ? 1 : 0;   // parallel over systems, or over strip classes of one system
+  parallel_for(nsys, nsys > 1 ? 0 : 1, [&](int i) {
+    const smpm_grid &g = one_grid ? grids[0] : grids[i];
+    try {
       build_system(H->sys[i], g.mx, g.mz, g.order, g.xb, g.zb, k[i], so);
+    } catch (const std::invalid_argument &e) {
+      codes[i] = SMPM_EINVAL; errs[i] = e.what();
+    } catch (const std::domain_error &e) {
+      codes[i] = SMPM_ESINGULAR; errs[i] = e.what();
+    } catch (const std::bad_alloc &) {
+      codes[i] = SMPM_ENOMEM; errs[i] = "host allocation failed in setup";
+    } catch (const std::exception &e) {
+      codes[i] = SMPM_ESINGULAR; errs[i] = e.what();
     }
-  } catch (const std::invalid_argument &e) {
-    return fail(SMPM_EINVAL, e.what());
-  } catch (const std::domain_error &e) {
-    return fail(SMPM_ESINGULAR, e.what());
-  } catch (const std::bad_alloc &) {
-    return fail(SMPM_ENOMEM, "host allocation failed in setup");
-  } catch (const std::exception &e) {
-    return fail(SMPM_ESINGULAR, e.what());
-  }
+  });
+  for (int i = 0; i < nsys; ++i)
+    if (codes[i] != SMPM_OK) return fail((smpm_status)codes[i], "system " + std::to_string(i) + ": " + errs[i]);
   if (!H->host_only) {
     try {
       upload(H.get(), (hipStream_t)stream);
@@ -433,11 +572,14 @@ smpm_status smpm_solve(smpm_handle *H, const double *f, const double *g, double 
   if (!H) return fail(SMPM_EINVAL, "handle is NULL");
   if (H->host_only) return fail(SMPM_EUNSUPPORTED, "host-only handle");
   if (!f || !u) return fail(SMPM_EINVAL, "f or u is NULL");
-  hipStream_t st = (hipStream_t)hip_stream;
+  hipStream_t caller = (hipStream_t)hip_stream;
+  hipStream_t st = H->ws;
   const auto t0 = std::chrono::steady_clock::now();
   smpm_stats S{};
   S.instances = H->ninst;
   try {
+    HIPCHECK(hipEventRecord(H->ev_in, caller));
+    HIPCHECK(hipStreamWaitEvent(st, H->ev_in, 0));
     stage_rhs(H, f, g, st);
     std::vector<double> nb;
     norms_of_b(H, nb, st);
@@ -486,6 +628,8 @@ smpm_status smpm_solve(smpm_handle *H, const double *f, const double *g, double 
     HIPCHECK(hipMemcpyAsync(H->h_defect, H->defect, sizeof(double) * H->ninst, hipMemcpyDeviceToHost, st));
     finish_u(H, u, st);
     HIPCHECK(hipGetLastError());
+    HIPCHECK(hipEventRecord(H->ev_out, st));
+    HIPCHECK(hipStreamWaitEvent(caller, H->ev_out, 0));
     HIPCHECK(hipStreamSynchronize(st));
     double relmax = 0.0, defmax = 0.0;
     int conv = 0;
@@ -494,7 +638,7 @@ smpm_status smpm_solve(smpm_handle *H, const double *f, const double *g, double 
       if (!std::isfinite(rel)) nonfinite = true;
       relmax = std::max(relmax, rel);
       if (H->sys[H->h_ins[i].sys].singular) defmax = std::max(defmax, H->h_defect[i]);
-      if (rel <= H->tol * 10.0) ++conv;
+      if (rel <= H->tol * 1.001) ++conv;
     }
     S.rel_residual_max = relmax;
     S.compat_defect_max = defmax;
@@ -516,80 +660,67 @@ smpm_status smpm_apply(smpm_handle *H, smpm_op op, int32_t sysi, const void *x, 
   if (H->host_only) return fail(SMPM_EUNSUPPORTED, "host-only handle");
   if (sysi < 0 || sysi >= (int)H->sys.size()) return fail(SMPM_EINVAL, "system index out of range");
   if (!x || !y) return fail(SMPM_EINVAL, "x or y is NULL");
+  if (precision != SMPM_FP64 && !(precision == SMPM_FP32_IR && (op == SMPM_OP_SCHUR || op == SMPM_OP_BJINV)))
+    return fail(SMPM_EINVAL, "only SCHUR and BJINV have FP32 variants");
   hipStream_t st = (hipStream_t)hip_stream;
   const int inst = sysi * H->nrhs;
   const InstDev &I = H->h_ins[inst];
   const System &s = H->sys[sysi];
-  const int2 *wh = H->w_h + H->h_start[inst];
-  const int2 *wx = H->w_x + H->x_start[inst];
+  int nxc = 0, nhc = 0;
+  const int2 *wx = xwork(H, inst, nxc);
+  const int2 *wh = hwork(H, inst, nhc);
+  const size_t bx = sizeof(double) * s.kS, br = sizeof(double) * s.r;
   try {
-    if (op == SMPM_OP_SCHUR || op == SMPM_OP_BJINV) {
-      const int kop = op == SMPM_OP_SCHUR ? 0 : 1;
-      if (precision == SMPM_FP64) {
-        HIPCHECK(hipMemcpyAsync(H->t64 + I.x_off, x, sizeof(double) * s.kS, hipMemcpyDeviceToDevice, st));
-        hipLaunchKernelGGL((k_half_gemv<double, double, double>), dim3(s.nh), dim3(kBlock), 0, st, H->d_sys, H->d_ins, wh,
-                           kop, (const double *)H->t64, 0, (const double *)nullptr, H->y64, (double *)nullptr,
-                           (const GState *)nullptr);
-        HIPCHECK(hipMemcpyAsync(y, H->y64 + I.x_off, sizeof(double) * s.kS, hipMemcpyDeviceToDevice, st));
-      } else if (precision == SMPM_FP32_IR) {
-        HIPCHECK(hipMemcpyAsync(H->t32 + I.x_off, x, sizeof(float) * s.kS, hipMemcpyDeviceToDevice, st));
-        hipLaunchKernelGGL((k_half_gemv<float, float, float>), dim3(s.nh), dim3(kBlock), 0, st, H->d_sys, H->d_ins, wh,
-                           kop, (const float *)H->t32, 0, (const double *)nullptr, H->y32, (double *)nullptr,
-                           (const GState *)nullptr);
-        HIPCHECK(hipMemcpyAsync(y, H->y32 + I.x_off, sizeof(float) * s.kS, hipMemcpyDeviceToDevice, st));
-      } else {
-        return fail(SMPM_EINVAL, "unknown precision");
+    switch (op) {
+      case SMPM_OP_SCHUR:
+      case SMPM_OP_BJINV: {
+        const int kop = op == SMPM_OP_SCHUR ? 0 : 1;
+        if (precision == SMPM_FP64) {
+          HIPCHECK(hipMemcpyAsync(H->t64 + I.x_off, x, bx, hipMemcpyDeviceToDevice, st));
+          gemv<double, double, double>(H, kop, H->t64, 0, nullptr, H->y64, nullptr, nullptr, st, inst);
+          HIPCHECK(hipMemcpyAsync(y, H->y64 + I.x_off, bx, hipMemcpyDeviceToDevice, st));
+        } else {
+          HIPCHECK(hipMemcpyAsync(H->t32 + I.x_off, x, sizeof(float) * s.kS, hipMemcpyDeviceToDevice, st));
+          gemv<float, float, float>(H, kop, H->t32, 0, nullptr, H->y32, nullptr, nullptr, st, inst);
+          HIPCHECK(hipMemcpyAsync(y, H->y32 + I.x_off, sizeof(float) * s.kS, hipMemcpyDeviceToDevice, st));
+        }
+        break;
       }
-    } else if (precision != SMPM_FP64) {
-      return fail(SMPM_EINVAL, "only SCHUR and BJINV have FP32 variants");
-    } else if (op == SMPM_OP_DEFLATE_P || op == SMPM_OP_DEFLATE_Q) {
-      HIPCHECK(hipMemcpyAsync(H->t64 + I.x_off, x, sizeof(double) * s.kS, hipMemcpyDeviceToDevice, st));
-      const double *src = H->t64;
-      if (op == SMPM_OP_DEFLATE_Q) {   // Q x = x - Z G Z^T S x
-        hipLaunchKernelGGL((k_half_gemv<double, double, double>), dim3(s.nh), dim3(kBlock), 0, st, H->d_sys, H->d_ins, wh,
-                           0, (const double *)H->t64, 0, (const double *)nullptr, H->y64, H->hs, (const GState *)nullptr);
-      } else {                         // P x = x - (S Z) G Z^T x
-        hipLaunchKernelGGL(k_halfsum, dim3(s.nh), dim3(kBlock), 0, st, H->d_sys, H->d_ins, wh, src, H->hs, (double *)nullptr);
-      }
-      hipLaunchKernelGGL(k_coarse, dim3(1), dim3(kBlock), 0, st, H->d_sys, H->d_ins + inst, H->hs, (const double *)nullptr,
-                         (double *)nullptr, H->cv, (const GState *)nullptr);
-      if (op == SMPM_OP_DEFLATE_Q) {
-        // out = x - Z c: negate c by passing through k_xupdate with a = x, c = -c
-        std::vector<double> tmp(s.d);
-        HIPCHECK(hipMemcpyAsync(tmp.data(), H->cv + I.c_off, sizeof(double) * s.d, hipMemcpyDeviceToHost, st));
-        HIPCHECK(hipStreamSynchronize(st));
-        for (auto &a : tmp) a = -a;
-        HIPCHECK(hipMemcpyAsync(H->cv + I.c_off, tmp.data(), sizeof(double) * s.d, hipMemcpyHostToDevice, st));
-        hipLaunchKernelGGL(k_xupdate<double>, dim3(I.nchunk_x), dim3(kBlock), 0, st, H->d_sys, H->d_ins, wx, 0,
+      case SMPM_OP_DEFLATE_P: {   // P x = x - (S Z) G Z^T x
+        HIPCHECK(hipMemcpyAsync(H->t64 + I.x_off, x, bx, hipMemcpyDeviceToDevice, st));
+        hipLaunchKernelGGL(k_halfsum, dim3(nhc), dim3(kBlock), 0, st, H->d_sys, H->d_ins, wh, (const double *)H->t64, H->hs,
+                           (double *)nullptr);
+        hipLaunchKernelGGL(k_coarse, dim3(1), dim3(kBlock), 0, st, H->d_sys, H->d_ins + inst, (const double *)H->hs,
+                           (const double *)nullptr, (double *)nullptr, H->cv, (const GState *)nullptr);
+        hipLaunchKernelGGL(k_xupdate<double>, dim3(nxc), dim3(kBlock), 0, st, H->d_sys, H->d_ins, wx, 3,
                            (const double *)H->t64, (const double *)H->cv, H->y64, (double *)nullptr);
-        HIPCHECK(hipMemcpyAsync(y, H->y64 + I.x_off, sizeof(double) * s.kS, hipMemcpyDeviceToDevice, st));
-        HIPCHECK(hipStreamSynchronize(st));
-      } else {
-        // k_init_basis with the FP64 basis slot 0 as output: use y64 region through V-offset-free copy
-        hipLaunchKernelGGL(k_init_basis<double>, dim3(I.nchunk_x), dim3(kBlock), 0, st, H->d_sys, H->d_ins, wx,
-                           (const double *)H->t64, (const double *)H->cv, H->z64 + I.x_off - I.v_off, H->partn);
-        HIPCHECK(hipMemcpyAsync(y, H->z64 + I.x_off, sizeof(double) * s.kS, hipMemcpyDeviceToDevice, st));
+        HIPCHECK(hipMemcpyAsync(y, H->y64 + I.x_off, bx, hipMemcpyDeviceToDevice, st));
+        break;
       }
-    } else if (op == SMPM_OP_AINV) {
-      HIPCHECK(hipMemcpyAsync(H->F + I.f_off, x, sizeof(double) * s.r, hipMemcpyDeviceToDevice, st));
-      const int2 *wsp = H->w_s + (int64_t)0;
-      // strips of this instance: instances are laid out in order; find the first strip item
-      int sstart = 0;
-      for (int q = 0; q < inst; ++q) sstart += H->sys[H->h_ins[q].sys].mx;
-      hipLaunchKernelGGL(k_strip_solve, dim3(s.mx), dim3(kBlock), 0, st, H->d_sys, H->d_ins, wsp + sstart,
-                         (const double *)H->F, H->v);
-      HIPCHECK(hipMemcpyAsync(y, H->v + I.f_off, sizeof(double) * s.r, hipMemcpyDeviceToDevice, st));
-    } else if (op == SMPM_OP_B) {
-      HIPCHECK(hipMemcpyAsync(H->v + I.f_off, x, sizeof(double) * s.r, hipMemcpyDeviceToDevice, st));
-      hipLaunchKernelGGL(k_bS, dim3(s.nh), dim3(kBlock), 0, st, H->d_sys, H->d_ins, wh, (const double *)H->v, H->y64, H->hs);
-      HIPCHECK(hipMemcpyAsync(y, H->y64 + I.x_off, sizeof(double) * s.kS, hipMemcpyDeviceToDevice, st));
-    } else if (op == SMPM_OP_SCHUR_RHS) {
-      // F given directly (g = 0): projection, A^-1, B, projection.
-      HIPCHECK(hipMemcpyAsync(H->Rr + I.f_off, x, sizeof(double) * s.r, hipMemcpyDeviceToDevice, st));
-      stage_rhs(H, H->Rr, nullptr, st);
-      HIPCHECK(hipMemcpyAsync(y, H->bS + I.x_off, sizeof(double) * s.kS, hipMemcpyDeviceToDevice, st));
-    } else {
-      return fail(SMPM_EINVAL, "unknown operator");
+      case SMPM_OP_DEFLATE_Q: {   // Q x = x - Z G Z^T S x
+        HIPCHECK(hipMemcpyAsync(H->t64 + I.x_off, x, bx, hipMemcpyDeviceToDevice, st));
+        gemv<double, double, double>(H, 0, H->t64, 0, nullptr, H->y64, H->hs, nullptr, st, inst);
+        hipLaunchKernelGGL(k_coarse, dim3(1), dim3(kBlock), 0, st, H->d_sys, H->d_ins + inst, (const double *)H->hs,
+                           (const double *)nullptr, (double *)nullptr, H->cv, (const GState *)nullptr);
+        hipLaunchKernelGGL(k_xupdate<double>, dim3(nxc), dim3(kBlock), 0, st, H->d_sys, H->d_ins, wx, 4,
+                           (const double *)H->t64, (const double *)H->cv, H->z64, (double *)nullptr);
+        HIPCHECK(hipMemcpyAsync(y, H->z64 + I.x_off, bx, hipMemcpyDeviceToDevice, st));
+        break;
+      }
+      case SMPM_OP_AINV:
+        HIPCHECK(hipMemcpyAsync(H->F + I.f_off, x, br, hipMemcpyDeviceToDevice, st));
+        ainv(H, H->F, H->v, st, inst);
+        HIPCHECK(hipMemcpyAsync(y, H->v + I.f_off, br, hipMemcpyDeviceToDevice, st));
+        break;
+      case SMPM_OP_B:
+        HIPCHECK(hipMemcpyAsync(H->v + I.f_off, x, br, hipMemcpyDeviceToDevice, st));
+        hipLaunchKernelGGL(k_bS, dim3(nhc), dim3(kBlock), 0, st, H->d_sys, H->d_ins, wh, (const double *)H->v, H->y64, H->hs);
+        HIPCHECK(hipMemcpyAsync(y, H->y64 + I.x_off, bx, hipMemcpyDeviceToDevice, st));
+        break;
+      case SMPM_OP_SCHUR_RHS:
+        return fail(SMPM_EINVAL, "SCHUR_RHS is applied through smpm_solve's staging only");
+      default:
+        return fail(SMPM_EINVAL, "unknown operator");
     }
     HIPCHECK(hipGetLastError());
     HIPCHECK(hipStreamSynchronize(st));
@@ -605,11 +736,9 @@ smpm_status smpm_schur_apply_all(smpm_handle *H, const void *x, void *y, int32_t
   if (!x || !y) return fail(SMPM_EINVAL, "x or y is NULL");
   hipStream_t st = (hipStream_t)hip_stream;
   if (precision == SMPM_FP64)
-    hipLaunchKernelGGL((k_half_gemv<double, double, double>), dim3(H->n_h), dim3(kBlock), 0, st, H->d_sys, H->d_ins, H->w_h,
-                       0, (const double *)x, 0, (const double *)nullptr, (double *)y, (double *)nullptr, (const GState *)nullptr);
+    gemv<double, double, double>(H, 0, (const double *)x, 0, nullptr, (double *)y, nullptr, nullptr, st);
   else if (precision == SMPM_FP32_IR)
-    hipLaunchKernelGGL((k_half_gemv<float, float, float>), dim3(H->n_h), dim3(kBlock), 0, st, H->d_sys, H->d_ins, H->w_h,
-                       0, (const float *)x, 0, (const double *)nullptr, (float *)y, (double *)nullptr, (const GState *)nullptr);
+    gemv<float, float, float>(H, 0, (const float *)x, 0, nullptr, (float *)y, nullptr, nullptr, st);
   else
     return fail(SMPM_EINVAL, "unknown precision");
   if (hipGetLastError() != hipSuccess) return fail(SMPM_EHIP, "kernel launch failed");
@@ -632,11 +761,8 @@ smpm_status smpm_query(const smpm_handle *H, int32_t sysi, smpm_info *info) {
   }
   o.f_offset = f; o.g_offset = g; o.x_offset = x;
   o.unique_W = s.nW; o.unique_M = s.nM;
-  // Distinct strip blocks streamed by one matvec: every half reads its N x 2N block once.
-  o.bytes_W64 = (int64_t)s.nW * s.N * 2 * s.N * 8;
-  int64_t mb = 0;
-  for (int h = 0; h < s.nh; ++h) mb = std::max<int64_t>(mb, 0);
-  o.bytes_M64 = (int64_t)s.nM * s.N * 4 * s.N * 8;
+  o.bytes_W64 = (int64_t)s.nW * s.N * 2 * s.N * 8;   // distinct Schur half blocks, FP64
+  o.bytes_M64 = (int64_t)s.nM * s.N * 4 * s.N * 8;   // distinct block-Jacobi row chunks, FP64
   *info = o;
   return SMPM_OK;
 }
