@@ -1,14 +1,19 @@
 """Benchmark: Schur matvecs/s and time-to-1e-10 residual, FP64 vs FP32-refined,
 on one MI355X.
 
-Workload (default): the long-domain 2-D Poisson-Neumann problem on
+Default workload (c2): the long-domain 2-D Poisson-Neumann problem on
 [0, 64] x [0, 1], 128 x 8 elements, polynomial order 16 (17 x 17 GLL points),
-manufactured solution plus seeded zero-mean Gaussian forcing.  One step is
-one full solve (Algorithm 2: right-hand side and null-space projection,
+manufactured solution plus seeded zero-mean Gaussian forcing.  One step is one
+full solve (Algorithm 2: right-hand side and null-space projection,
 element-interior elimination, Schur right-hand side, DBJ-GMRES to 1e-10,
 solution assembly and recovery) with the inputs resident in HBM.
 
-Prints one JSON line.
+Other workloads (--config c3 | c4 | c5) time the same path on the stretched
+256 x 16 grid with distinct strips, the 65 Fourier modes x (Re, Im) of the
+64 x 8 grid, and the uneven 32-problem batch.
+
+Prints one JSON line.  --matvec-only runs just the Schur matvec kernel (used
+for the hardware-counter passes).
 """
 import argparse
 import json
@@ -20,6 +25,17 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 import numpy as np
+
+WORKLOADS = {
+    "c2": "2-D Poisson-Neumann [0,64]x[0,1], 128x8 elements, order 16, manufactured + seeded Gaussian "
+          "forcing, DBJ-GMRES to 1e-10",
+    "c3": "2-D stretched grid 256x16 elements, order 12, geometric z-stretch, seeded distinct strip widths, "
+          "f ~ U[0,1], DBJ-GMRES to 1e-10",
+    "c4": "3-D via Fourier in y: 64x8 elements, order 12, 128 y-points -> 65 Helmholtz modes x (Re, Im) = "
+          "130 batched Schur solves, DBJ-GMRES to 1e-10",
+    "c5": "uneven batch of 32 seeded 2-D Poisson/Helmholtz problems, 16x2..256x16 elements, orders 8-16, "
+          "DBJ-GMRES to 1e-10",
+}
 
 
 def gpu_events_time(fn, reps, stream):
@@ -35,10 +51,39 @@ def gpu_events_time(fn, reps, stream):
     return start.elapsed_time(end) / reps   # ms
 
 
-def cpu_baseline(prob, budget_s=25.0):
+def make_solver(cfg, precision):
+    import paper_1512_01756_amd as P
+    from paper_1512_01756_amd import workloads
+    if cfg in ("c2", "c3"):
+        p = workloads.c2() if cfg == "c2" else workloads.c3()
+        return P.Solver(p.xb, p.zb, p.n - 1, precision=precision), p.f.reshape(-1)
+    if cfg == "c4":
+        p = workloads.c4()
+        return P.Solver(p.xb, p.zb, p.n - 1, kwaves=p.kwaves, nrhs=2, precision=precision), p.f.reshape(-1)
+    probs = workloads.c5()
+    grids = [(p.xb, p.zb, p.n - 1, float(p.kwaves[0])) for p in probs]
+    return P.Solver(grids=grids, precision=precision), np.concatenate([p.f.reshape(-1) for p in probs])
+
+
+def matvec_bytes(solver, s_op, s_vec):
+    """Algorithmic bytes of one batched Schur matvec: every distinct N x 2N
+    half block once, the input and output interface vectors of every
+    instance."""
+    tot = 0
+    for info in solver.info:
+        N = info["n"] * info["mz"]
+        tot += info["unique_W"] * N * 2 * N * s_op
+        tot += 2 * info["kS"] * s_vec * info["nrhs"]
+    return tot
+
+
+def cpu_baseline(budget_s=25.0):
     """The oracle as it stands, timed on the host: setup once (reported, not
-    part of the sample), then DBJ solves until ~budget_s of solve time."""
+    part of the sample), then DBJ solves of the same c2 problem until ~budget_s
+    of solve time."""
     from oracle import schur, smpm, solve
+    from paper_1512_01756_amd import workloads
+    prob = workloads.c2()
     grid = smpm.Grid(prob.xb, prob.zb, prob.n)
     t0 = time.perf_counter()
     o = schur.build(grid)
@@ -53,8 +98,8 @@ def cpu_baseline(prob, budget_s=25.0):
     solve_s = float(np.median(times))
     cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     return {"value": float(np.mean(mv) / solve_s), "unit": "matvecs/s", "cores": cores, "kind": "oracle",
-            "sample": f"{len(times)} full DBJ solves of the same workload after a {setup_s:.1f} s oracle setup; "
-                      f"median solve {solve_s * 1e3:.1f} ms, {r.iters} GMRES iterations",
+            "sample": f"{len(times)} full DBJ solves of the c2 workload after a {setup_s:.1f} s oracle setup "
+                      f"(setup not in the sample); median solve {solve_s * 1e3:.1f} ms, {r.iters} GMRES iterations",
             "time_to_1e-10_ms": solve_s * 1e3, "setup_s": setup_s}
 
 
@@ -63,66 +108,69 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--config", default="c2", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--matvec-reps", type=int, default=200)
+    ap.add_argument("--matvec-only", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
-              "(the solver would shard strips across GPUs; see DESIGN.md)", file=sys.stderr)
+              "(strips would shard across GPUs; see DESIGN.md)", file=sys.stderr)
         sys.exit(2)
 
     import torch
     import paper_1512_01756_amd as P
-    from paper_1512_01756_amd import workloads
 
-    prob = workloads.c2(seed=0)
     dev = torch.device("cuda:0")
     stream = torch.cuda.current_stream(dev)
-    f = torch.as_tensor(prob.f.reshape(-1)).to(dev)
-    u = torch.empty_like(f)
+
+    if args.matvec_only:
+        s, _ = make_solver(args.config, P.FP64)
+        x = torch.randn(s.total_kS, dtype=torch.float64, device=dev)
+        y = torch.empty_like(x)
+        ms = gpu_events_time(lambda: s.schur_apply_all(x, y, P.FP64), args.matvec_reps, stream)
+        print(json.dumps({"config": args.config, "matvec_fp64_us": ms * 1e3,
+                          "algorithmic_bytes": matvec_bytes(s, 8, 8)}), flush=True)
+        return
 
     forms = {}
+    fvec = None
     for name, prec in (("fp64", P.FP64), ("fp32_ir", P.FP32_IR)):
         t0 = time.perf_counter()
-        s = P.Solver(prob.xb, prob.zb, prob.n - 1, precision=prec)
+        s, fh = make_solver(args.config, prec)
         setup_s = time.perf_counter() - t0
+        if fvec is None:
+            fvec = torch.as_tensor(fh).to(dev)
+            u = torch.empty_like(fvec)
         for _ in range(args.warmup):
-            s.solve(f, None, u)
+            s.solve(fvec, None, u)
         torch.cuda.synchronize()
         stats_list = []
 
         def step():
-            _, st, _ = s.solve(f, None, u)
+            _, st, _ = s.solve(fvec, None, u)
             stats_list.append(st)
 
         ms = gpu_events_time(step, args.steps, stream)
-        err = float((u - torch.as_tensor(prob.exact - prob.exact.mean(), device=dev)).abs().max())
-        st = stats_list[-1]
-        forms[name] = {"solver": s, "ms": ms, "stats": st, "setup_s": setup_s, "err_vs_manufactured": err}
+        forms[name] = {"solver": s, "ms": ms, "stats": stats_list[-1], "setup_s": setup_s}
 
-    # Schur matvec kernel alone (the batched half-interface GEMV), FP64 and FP32.
+    # The Schur matvec kernel alone (batched half-interface GEMV), both precisions.
     s64 = forms["fp64"]["solver"]
-    info = s64.info[0]
-    kS = info["kS"]
-    x = torch.randn(kS, dtype=torch.float64, device=dev)
+    x = torch.randn(s64.total_kS, dtype=torch.float64, device=dev)
     y = torch.empty_like(x)
     x32, y32 = x.float(), y.float()
     for _ in range(10):
         s64.schur_apply_all(x, y)
     mv64_ms = gpu_events_time(lambda: s64.schur_apply_all(x, y, P.FP64), args.matvec_reps, stream)
     mv32_ms = gpu_events_time(lambda: s64.schur_apply_all(x32, y32, P.FP32_IR), args.matvec_reps, stream)
-    # algorithmic bytes of one matvec: every output half reads its N x 2N block
-    # (distinct blocks are read once from HBM, repeats hit cache: count the
-    # stored unique blocks) plus the input window and the output.
-    N = info["n"] * info["mz"]
-    nh = 2 * (info["mx"] - 1)
-    bytes64 = info["bytes_W64"] + 2 * kS * 8
-    flops = 2.0 * nh * N * 2 * N + kS
-    achieved_gbs = bytes64 / (mv64_ms * 1e-3) / 1e9
+    bytes64 = matvec_bytes(s64, 8, 8)
+    bytes32 = matvec_bytes(s64, 4, 4)
+    gbs64 = bytes64 / (mv64_ms * 1e-3) / 1e9
+    gbs32 = bytes32 / (mv32_ms * 1e-3) / 1e9
 
-    fp64 = forms["fp64"]
-    ir = forms["fp32_ir"]
+    fp64, ir = forms["fp64"], forms["fp32_ir"]
     value = fp64["stats"]["schur_matvecs"] / (fp64["ms"] * 1e-3)
+    i0 = s64.info[0]
     line = {
         "metric": "Schur matvecs/s + time-to-1e-10 residual, FP64 vs FP32-refined, 1 GPU",
         "value": value,
@@ -136,23 +184,25 @@ def main():
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": "c2: 2-D Poisson-Neumann [0,64]x[0,1], 128x8 elements, order 16, "
-                               "manufactured + seeded Gaussian forcing, DBJ-GMRES to 1e-10",
-                   "k_S": kS, "r": info["r"], "d": info["d"]},
+        "config": {"workload": f"{args.config}: {WORKLOADS[args.config]}", "systems": s64.nsys,
+                   "instances": fp64["stats"]["instances"], "k_S_total": s64.total_kS, "r_total": s64.total_r,
+                   "first_system": {"mx": i0["mx"], "mz": i0["mz"], "n": i0["n"], "d": i0["d"]}},
+        "value_definition": "Schur matvecs performed by one full FP64 DBJ solve divided by its wall time",
         "time_to_1e-10_ms": {"fp64": fp64["ms"], "fp32_ir": ir["ms"]},
-        "iterations": {"fp64": fp64["stats"]["iters_max"], "fp32_ir_inner_total": ir["stats"]["iters_total"],
+        "iterations": {"fp64_max": fp64["stats"]["iters_max"], "fp64_total": fp64["stats"]["iters_total"],
+                       "fp32_ir_inner_max": ir["stats"]["iters_max"], "fp32_ir_inner_total": ir["stats"]["iters_total"],
                        "fp32_ir_sweeps": ir["stats"]["sweeps_max"]},
-        "rel_residual": {"fp64": fp64["stats"]["rel_residual_max"], "fp32_ir": ir["stats"]["rel_residual_max"]},
-        "err_vs_manufactured": {"fp64": fp64["err_vs_manufactured"], "fp32_ir": ir["err_vs_manufactured"]},
+        "rel_residual_max": {"fp64": fp64["stats"]["rel_residual_max"], "fp32_ir": ir["stats"]["rel_residual_max"]},
         "setup_s": {"fp64": fp64["setup_s"], "fp32_ir": ir["setup_s"]},
         "matvec_kernel": {"fp64_us": mv64_ms * 1e3, "fp32_us": mv32_ms * 1e3,
-                          "fp64_matvecs_per_s": 1e3 / mv64_ms, "fp32_matvecs_per_s": 1e3 / mv32_ms},
-        "roofline": {"bound": "hbm", "kernel": "k_half_gemv<double> (Schur matvec)", "achieved": achieved_gbs,
-                     "peak": 8000.0, "unit": "GB/s", "frac": achieved_gbs / 8000.0, "traffic": None,
-                     "algorithmic_bytes": bytes64, "flops": flops},
+                          "fp64_matvecs_per_s": 1e3 / mv64_ms, "fp32_matvecs_per_s": 1e3 / mv32_ms,
+                          "fp64_GBps": gbs64, "fp32_GBps": gbs32},
+        "roofline": {"bound": "hbm", "kernel": "k_half_gemv<double> (batched Schur matvec)", "achieved": gbs64,
+                     "peak": 8000.0, "unit": "GB/s", "frac": gbs64 / 8000.0, "traffic": None,
+                     "algorithmic_bytes_per_launch": bytes64},
     }
-    if not args.no_cpu_baseline:
-        line["cpu_baseline"] = cpu_baseline(prob)
+    if not args.no_cpu_baseline and args.config == "c2":
+        line["cpu_baseline"] = cpu_baseline()
     for v in forms.values():
         v["solver"].close()
     print(json.dumps(line), flush=True)

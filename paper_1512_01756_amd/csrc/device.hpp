@@ -14,6 +14,7 @@ constexpr int kMaxRowsPerLane = (kMaxN + 63) / 64;
 // block ([col][row]) so that a wavefront reads consecutive rows of one column.
 struct SysDev {
   int n, mx, mz, n2, N, nh, d, singular;
+  int Np;                // rows of the stored Schur / block-Jacobi blocks (N rounded up to 4)
   int64_t kS, r;
   double tau;
   const double *W64;     // unique Schur half blocks: [blk][2N][N]

@@ -40,25 +40,28 @@ __device__ inline double block_sum(double v, double *lds4) {
 
 // ---------------------------------------------------------------------------
 // Column-split GEMV core: lane `lane` owns row `row` (< R) of a column-major
-// R x K block and accumulates columns [c0, c1) for G right-hand sides held in
-// LDS (xw[g * xs + c]).  Loads are issued UNROLL columns at a time.
+// block with leading dimension ld and accumulates columns [c0, c1) for G
+// right-hand sides held in LDS (xw[g * xs + c]).  Loads are issued UNROLL
+// columns at a time.
 template <typename TO, int G, int UNROLL>
 __device__ inline void colsplit(const TO *__restrict__ blk, int R, int row, int c0, int c1,
-                                const double *xw, int xs, TO (&acc)[G]) {
+                                const double *xw, int xs, TO (&acc)[G], int ld = -1) {
+  if (ld < 0) ld = R;
+  const int Rl = ld;
   const bool live = row < R;
   const TO *col = blk + row;
   int c = c0;
   for (; c + UNROLL <= c1; c += UNROLL) {
     TO v[UNROLL];
 #pragma unroll
-    for (int u = 0; u < UNROLL; ++u) v[u] = live ? col[(size_t)(c + u) * R] : (TO)0;
+    for (int u = 0; u < UNROLL; ++u) v[u] = live ? col[(size_t)(c + u) * Rl] : (TO)0;
 #pragma unroll
     for (int u = 0; u < UNROLL; ++u)
 #pragma unroll
       for (int g = 0; g < G; ++g) acc[g] += v[u] * (TO)xw[g * xs + c + u];
   }
   for (; c < c1; ++c) {
-    const TO v = live ? col[(size_t)c * R] : (TO)0;
+    const TO v = live ? col[(size_t)c * Rl] : (TO)0;
 #pragma unroll
     for (int g = 0; g < G; ++g) acc[g] += v * (TO)xw[g * xs + c];
   }
@@ -97,12 +100,13 @@ __global__ __launch_bounds__(64 * NW) void k_half_gemv(
   const int h0 = hh[0];
   int K;
   const TO *blk;
+  const int Np = S.Np;
   if (op == 0) {
     K = 2 * N;
-    blk = Tab<TO>::W(S) + (size_t)S.w_id[h0] * 2 * N * N;
+    blk = Tab<TO>::W(S) + (size_t)S.w_id[h0] * 2 * N * Np;
   } else {
     K = S.m_K[h0];
-    blk = Tab<TO>::M(S) + (size_t)S.m_id[h0] * 4 * N * N;
+    blk = Tab<TO>::M(S) + (size_t)S.m_id[h0] * 4 * N * Np;
   }
   const int it = gs ? gs[i].iter : 0;
   const TX *x = xbase + (x_vslot ? I.v_off + (int64_t)it * kS : I.x_off);
@@ -124,7 +128,7 @@ __global__ __launch_bounds__(64 * NW) void k_half_gemv(
   TO acc[G];
 #pragma unroll
   for (int g = 0; g < G; ++g) acc[g] = (TO)0;
-  colsplit<TO, G, 8>(blk, N, row, c0, c1, xw, K, acc);
+  colsplit<TO, G, 8>(blk, N, row, c0, c1, xw, K, acc, Np);
 #pragma unroll
   for (int g = 0; g < G; ++g) red[(wave * G + g) * 64 + lane] = (double)acc[g];
   __syncthreads();
@@ -144,6 +148,119 @@ __global__ __launch_bounds__(64 * NW) void k_half_gemv(
     if (hsum) {   // only the first wave holds outputs
       const double sgrp = wave_sum(out_d);
       if (threadIdx.x == 0) hsum[I.hs_off + (int64_t)h * tiles + tile] = sgrp;
+    }
+  }
+}
+
+// Streaming variant for halves whose block is not shared (distinct strips):
+// one half per workgroup row tile, 16-byte loads (VR consecutive rows per
+// lane: 2 in FP64, 4 in FP32) along each column of the padded column-major
+// block, NW waves splitting the columns.  Same operation and outputs as
+// k_half_gemv with one half per item.
+template <typename TO> struct Vec16;
+template <> struct Vec16<double> { using T = double2; static constexpr int R = 2; };
+template <> struct Vec16<float> { using T = float4; static constexpr int R = 4; };
+
+template <typename TO, typename TX, typename TY, int NW>
+__global__ __launch_bounds__(64 * NW) void k_half_gemv_stream(
+    const SysDev *__restrict__ sys, const InstDev *__restrict__ ins, const HWork *__restrict__ work,
+    int op, const TX *__restrict__ xbase, int x_vslot, const double *__restrict__ scale,
+    TY *__restrict__ ybase, double *__restrict__ hsum, const GState *__restrict__ gs) {
+  using V = typename Vec16<TO>::T;
+  constexpr int VR = Vec16<TO>::R;
+  constexpr int TR = 64 * VR;
+  extern __shared__ double sm[];
+  const int i = work[blockIdx.x].inst;
+  if (gs && !gs[i].active) return;
+  const int h = work[blockIdx.x].h[0];
+  const InstDev I = ins[i];
+  const SysDev &S = sys[I.sys];
+  const int N = S.N, Np = S.Np;
+  const int tiles = (N + TR - 1) / TR;
+  const int tile = blockIdx.y;
+  if (tile >= tiles) return;
+  const int64_t kS = S.kS;
+  int K;
+  const TO *blk;
+  int64_t win;
+  if (op == 0) {
+    K = 2 * N;
+    blk = Tab<TO>::W(S) + (size_t)S.w_id[h] * 2 * N * Np;
+    win = (int64_t)S.w_win[h] * N;
+  } else {
+    K = S.m_K[h];
+    blk = Tab<TO>::M(S) + (size_t)S.m_id[h] * 4 * N * Np;
+    win = (int64_t)S.m_win[h] * N;
+  }
+  const int it = gs ? gs[i].iter : 0;
+  const TX *x = xbase + (x_vslot ? I.v_off + (int64_t)it * kS : I.x_off);
+  const double xs = scale ? scale[I.st_off + it] : 1.0;
+  double *xw = sm;                  // [K]
+  double *red = sm + K;             // [NW][TR]
+  for (int c = threadIdx.x; c < K; c += 64 * NW) {
+    const int64_t idx = win + c;
+    xw[c] = (idx >= 0 && idx < kS) ? (double)x[idx] * xs : 0.0;
+  }
+  __syncthreads();
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int row0 = tile * TR + lane * VR;
+  const bool live = row0 < Np;
+  const int c0 = (K * wave) / NW, c1 = (K * (wave + 1)) / NW;
+  TO acc[VR];
+#pragma unroll
+  for (int r = 0; r < VR; ++r) acc[r] = (TO)0;
+  const V *colv = reinterpret_cast<const V *>(blk + row0);
+  const size_t stride = (size_t)Np / VR;
+  int c = c0;
+  for (; c + 8 <= c1; c += 8) {
+    V v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = live ? colv[(size_t)(c + u) * stride] : V{};
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const TO xv = (TO)xw[c + u];
+      const TO *pv = reinterpret_cast<const TO *>(&v[u]);
+#pragma unroll
+      for (int r = 0; r < VR; ++r) acc[r] += pv[r] * xv;
+    }
+  }
+  for (; c < c1; ++c) {
+    const V v = live ? colv[(size_t)c * stride] : V{};
+    const TO xv = (TO)xw[c];
+    const TO *pv = reinterpret_cast<const TO *>(&v);
+#pragma unroll
+    for (int r = 0; r < VR; ++r) acc[r] += pv[r] * xv;
+  }
+#pragma unroll
+  for (int r = 0; r < VR; ++r) red[wave * TR + lane * VR + r] = (double)acc[r];
+  __syncthreads();
+  double out_d = 0.0;
+  for (int rr = threadIdx.x; rr < TR; rr += 64 * NW) {
+    const int row = tile * TR + rr;
+    if (row >= N) continue;
+    TO v = (TO)0;
+#pragma unroll
+    for (int w = 0; w < NW; ++w) v += (TO)red[w * TR + rr];
+    double vd = (double)v;
+    if (op == 0) vd += (double)x[(int64_t)h * N + row] * xs;
+    const TY out = (TY)vd;
+    ybase[I.x_off + (int64_t)h * N + row] = out;
+    out_d += (double)out;
+  }
+  if (hsum) {
+    __shared__ double lds4b[NW];
+    double sv = wave_sum(out_d);
+    if (lane == 0) lds4b[wave] = sv;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double t = 0.0;
+      for (int w = 0; w < NW; ++w) t += lds4b[w];
+      // per-tile partial, in the 64-row tile slots of the half (tiles of TR rows map to
+      // the first ceil(N/TR) slots; the remaining slots are zeroed)
+      const int slots = (N + 63) >> 6;
+      hsum[I.hs_off + (int64_t)h * slots + tile] = t;
+      if (tile == tiles - 1)
+        for (int q = tiles; q < slots; ++q) hsum[I.hs_off + (int64_t)h * slots + q] = 0.0;
     }
   }
 }

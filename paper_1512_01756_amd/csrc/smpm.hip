@@ -68,6 +68,17 @@ std::vector<T> to_colmajor(const std::vector<double> &a, int nb, int rows, int c
   return out;
 }
 
+// Column-major copy with the row count padded to ld (zero rows).
+template <typename T>
+std::vector<T> to_colmajor_padded(const std::vector<double> &a, int nb, int rows, int cols, int ld) {
+  std::vector<T> out((size_t)nb * ld * cols, (T)0);
+  for (int b = 0; b < nb; ++b)
+    for (int r = 0; r < rows; ++r)
+      for (int c = 0; c < cols; ++c)
+        out[(size_t)b * ld * cols + (size_t)c * ld + r] = (T)a[(size_t)b * rows * cols + (size_t)r * cols + c];
+  return out;
+}
+
 constexpr int kStripsPerGroup = 4;
 constexpr int kIterChunk = 4;
 constexpr int kWaves = 16;   // waves per workgroup of the GEMV-shaped kernels
@@ -89,9 +100,15 @@ struct smpm_handle {
   int ninst = 0, Nmax = 0, group = 1, nq_max = 0, n2_max = 0;
   // Work lists: grouped halves for S and M^-1, plain halves, element items,
   // interface and node vector chunks.  Per instance [start, start + count).
-  HWork *w_S = nullptr, *w_M = nullptr;
+  HWork *w_S = nullptr, *w_M = nullptr;     // grouped items (shared blocks)
+  HWork *w_S1 = nullptr, *w_M1 = nullptr;   // single items (streamed blocks)
+  int n_S1 = 0, n_M1 = 0;
+  std::vector<int> S1_start, S1_cnt, M1_start, M1_cnt;
   int2 *w_h = nullptr, *w_x = nullptr, *w_r = nullptr, *w_s = nullptr;
-  int4 *w_E = nullptr;
+  int4 *w_E = nullptr;      // element items with several strips of one class
+  int4 *w_E1 = nullptr;     // element items of a single strip
+  int n_E1 = 0;
+  std::vector<int> E1_start, E1_cnt;
   int n_S = 0, n_M = 0, n_h = 0, n_E = 0, n_x = 0, n_r = 0, n_s = 0;
   std::vector<int> S_start, S_cnt, M_start, M_cnt, h_start, E_start, E_cnt, x_start, r_start, s_start;
   int64_t tot_r = 0, tot_x = 0, tot_g = 0;
@@ -155,18 +172,21 @@ void upload(smpm_handle *H, hipStream_t st) {
     H->n2_max = std::max(H->n2_max, s.n2);
   }
   // Group size bounded by the GEMV's LDS budget (windows + wave partials).
+  // Grouping (up to kGroup halves sharing a block per workgroup) needs the
+  // windows of the group in LDS; above that budget every half is streamed.
   H->group = ((size_t)kGroup * (4 * H->Nmax + kWaves * 64) * sizeof(double) <= 64 * 1024) ? kGroup : 1;
   for (System &s : H->sys) {
     SysDev d{};
     d.n = s.n; d.mx = s.mx; d.mz = s.mz; d.n2 = s.n2; d.N = s.N; d.nh = s.nh; d.d = s.d;
     d.singular = s.singular ? 1 : 0; d.kS = s.kS; d.r = s.r; d.tau = s.tau;
     d.nq = 2 * s.n * (s.mz - 1);
-    d.W64 = dupload(own, to_colmajor<double>(s.Wblk, s.nW, s.N, 2 * s.N), st);
-    d.W32 = dupload(own, to_colmajor<float>(s.Wblk, s.nW, s.N, 2 * s.N), st);
+    d.Np = (s.N + 3) / 4 * 4;
+    d.W64 = dupload(own, to_colmajor_padded<double>(s.Wblk, s.nW, s.N, 2 * s.N, d.Np), st);
+    d.W32 = dupload(own, to_colmajor_padded<float>(s.Wblk, s.nW, s.N, 2 * s.N, d.Np), st);
     d.w_id = dupload(own, s.w_id, st);
     d.w_win = dupload(own, s.w_win, st);
-    d.M64 = dupload(own, to_colmajor<double>(s.Mblk, s.nM, s.N, 4 * s.N), st);
-    d.M32 = dupload(own, to_colmajor<float>(s.Mblk, s.nM, s.N, 4 * s.N), st);
+    d.M64 = dupload(own, to_colmajor_padded<double>(s.Mblk, s.nM, s.N, 4 * s.N, d.Np), st);
+    d.M32 = dupload(own, to_colmajor_padded<float>(s.Mblk, s.nM, s.N, 4 * s.N, d.Np), st);
     d.m_id = dupload(own, s.m_id, st);
     d.m_win = dupload(own, s.m_win, st);
     d.m_K = dupload(own, s.m_K, st);
@@ -194,8 +214,8 @@ void upload(smpm_handle *H, hipStream_t st) {
     H->h_sys.push_back(d);
   }
   H->d_sys = dupload(own, H->h_sys, st);
-  std::vector<HWork> wS, wM;
-  std::vector<int4> wE;
+  std::vector<HWork> wS, wM, wS1, wM1;
+  std::vector<int4> wE, wE1;
   std::vector<int2> wh, wx, wr, ws;
   int64_t f_off = 0, g_off = 0, x_off = 0, v_off = 0, part_off = 0, pr_off = 0, hs_off = 0, c_off = 0,
           st_off = 0, rr_off = 0, lam_off = 0;
@@ -215,22 +235,38 @@ void upload(smpm_handle *H, hipStream_t st) {
       part_off += (int64_t)(maxit + 1) * I.nchunk_x + 2; pr_off += 2LL * I.nchunk_r;
       hs_off += (int64_t)s.nh * ((s.N + 63) / 64); c_off += s.d;
       st_off += maxit + 1; rr_off += (int64_t)maxit * maxit; lam_off += (int64_t)s.mx * nq;
-      H->S_start.push_back((int)wS.size());
-      group_halves(inst, s.w_id, H->group, wS);
-      H->S_cnt.push_back((int)wS.size() - H->S_start.back());
-      H->M_start.push_back((int)wM.size());
-      group_halves(inst, s.m_id, H->group, wM);
-      H->M_cnt.push_back((int)wM.size() - H->M_start.back());
+      {
+        // A system whose halves share blocks runs every half through the
+        // grouped kernel (one launch); a system with no sharing streams.
+        std::vector<HWork> tmp;
+        auto any_shared = [](const std::vector<HWork> &v) {
+          for (const HWork &w : v) if (w.cnt > 1) return true;
+          return false;
+        };
+        group_halves(inst, s.w_id, H->group, tmp);
+        const bool shS = any_shared(tmp);
+        H->S_start.push_back((int)wS.size()); H->S1_start.push_back((int)wS1.size());
+        for (const HWork &w : tmp) (shS ? wS : wS1).push_back(w);
+        H->S_cnt.push_back((int)wS.size() - H->S_start.back()); H->S1_cnt.push_back((int)wS1.size() - H->S1_start.back());
+        tmp.clear();
+        group_halves(inst, s.m_id, H->group, tmp);
+        const bool shM = any_shared(tmp);
+        H->M_start.push_back((int)wM.size()); H->M1_start.push_back((int)wM1.size());
+        for (const HWork &w : tmp) (shM ? wM : wM1).push_back(w);
+        H->M_cnt.push_back((int)wM.size() - H->M_start.back()); H->M1_cnt.push_back((int)wM1.size() - H->M1_start.back());
+      }
       H->h_start.push_back((int)wh.size());
       for (int h = 0; h < s.nh; ++h) wh.push_back(make_int2(inst, h));
       H->E_start.push_back((int)wE.size());
+      H->E1_start.push_back((int)wE1.size());
       for (int j = 0; j < s.mx;) {
         int ng = 1;
         while (ng < kStripsPerGroup && j + ng < s.mx && s.strip_class[j + ng] == s.strip_class[j]) ++ng;
-        for (int e = 0; e < s.mz; ++e) wE.push_back(make_int4(inst, j, ng, e));
+        for (int e = 0; e < s.mz; ++e) (ng > 1 ? wE : wE1).push_back(make_int4(inst, j, ng, e));
         j += ng;
       }
       H->E_cnt.push_back((int)wE.size() - H->E_start.back());
+      H->E1_cnt.push_back((int)wE1.size() - H->E1_start.back());
       H->s_start.push_back((int)ws.size());
       for (int j = 0; j < s.mx; ++j) ws.push_back(make_int2(inst, j));
       H->x_start.push_back((int)wx.size());
@@ -245,8 +281,11 @@ void upload(smpm_handle *H, hipStream_t st) {
   H->d_ins = dupload(own, H->h_ins, st);
   H->w_S = dupload(own, wS, st); H->n_S = (int)wS.size();
   H->w_M = dupload(own, wM, st); H->n_M = (int)wM.size();
+  H->w_S1 = dupload(own, wS1, st); H->n_S1 = (int)wS1.size();
+  H->w_M1 = dupload(own, wM1, st); H->n_M1 = (int)wM1.size();
   H->w_h = dupload(own, wh, st); H->n_h = (int)wh.size();
   H->w_E = dupload(own, wE, st); H->n_E = (int)wE.size();
+  H->w_E1 = dupload(own, wE1, st); H->n_E1 = (int)wE1.size();
   H->w_x = dupload(own, wx, st); H->n_x = (int)wx.size();
   H->w_r = dupload(own, wr, st); H->n_r = (int)wr.size();
   H->w_s = dupload(own, ws, st); H->n_s = (int)ws.size();
@@ -279,23 +318,37 @@ void upload(smpm_handle *H, hipStream_t st) {
 template <typename TO, typename TX, typename TY>
 void gemv(smpm_handle *H, int op, const TX *x, int vslot, const double *scale, TY *y, double *hsum,
           const GState *gs, hipStream_t st, int inst = -1) {
-  const HWork *w = op == 0 ? H->w_S : H->w_M;
-  int count = op == 0 ? H->n_S : H->n_M;
-  if (inst >= 0) {
-    w += op == 0 ? H->S_start[inst] : H->M_start[inst];
-    count = op == 0 ? H->S_cnt[inst] : H->M_cnt[inst];
-  }
-  if (count == 0) return;
   const int Kmax = (op == 0 ? 2 : 4) * H->Nmax;
-  const int tiles = (H->Nmax + 63) / 64;
-  if (H->group == kGroup) {
-    const size_t shm = sizeof(double) * kGroup * (Kmax + kWaves * 64);
-    hipLaunchKernelGGL((k_half_gemv<TO, TX, TY, kGroup, kWaves>), dim3(count, tiles), dim3(64 * kWaves), shm, st, H->d_sys,
-                       H->d_ins, w, op, x, vslot, scale, y, hsum, gs);
-  } else {
-    const size_t shm = sizeof(double) * (Kmax + kWaves * 64);
-    hipLaunchKernelGGL((k_half_gemv<TO, TX, TY, 1, kWaves>), dim3(count, tiles), dim3(64 * kWaves), shm, st, H->d_sys,
-                       H->d_ins, w, op, x, vslot, scale, y, hsum, gs);
+  // halves with a shared block: grouped kernel
+  {
+    const HWork *w = op == 0 ? H->w_S : H->w_M;
+    int count = op == 0 ? H->n_S : H->n_M;
+    if (inst >= 0) {
+      w += op == 0 ? H->S_start[inst] : H->M_start[inst];
+      count = op == 0 ? H->S_cnt[inst] : H->M_cnt[inst];
+    }
+    if (count > 0) {
+      const int tiles = (H->Nmax + 63) / 64;
+      const size_t shm = sizeof(double) * kGroup * (Kmax + kWaves * 64);
+      hipLaunchKernelGGL((k_half_gemv<TO, TX, TY, kGroup, kWaves>), dim3(count, tiles), dim3(64 * kWaves), shm, st,
+                         H->d_sys, H->d_ins, w, op, x, vslot, scale, y, hsum, gs);
+    }
+  }
+  // halves with their own block: streaming kernel
+  {
+    const HWork *w = op == 0 ? H->w_S1 : H->w_M1;
+    int count = op == 0 ? H->n_S1 : H->n_M1;
+    if (inst >= 0) {
+      w += op == 0 ? H->S1_start[inst] : H->M1_start[inst];
+      count = op == 0 ? H->S1_cnt[inst] : H->M1_cnt[inst];
+    }
+    if (count > 0) {
+      constexpr int TR = 64 * Vec16<TO>::R;
+      const int tiles = (H->Nmax + TR - 1) / TR;
+      const size_t shm = sizeof(double) * (Kmax + kWaves * TR);
+      hipLaunchKernelGGL((k_half_gemv_stream<TO, TX, TY, kWaves>), dim3(count, tiles), dim3(64 * kWaves), shm, st,
+                         H->d_sys, H->d_ins, w, op, x, vslot, scale, y, hsum, gs);
+    }
   }
 }
 
@@ -304,19 +357,31 @@ void gemv(smpm_handle *H, int op, const TX *x, int vslot, const double *scale, T
 void ainv(smpm_handle *H, const double *src, double *dst, hipStream_t st, int inst = -1) {
   const int4 *w = H->w_E + (inst >= 0 ? H->E_start[inst] : 0);
   const int count = inst >= 0 ? H->E_cnt[inst] : H->n_E;
-  if (count == 0) return;
+  const int4 *w1 = H->w_E1 + (inst >= 0 ? H->E1_start[inst] : 0);
+  const int count1 = inst >= 0 ? H->E1_cnt[inst] : H->n_E1;
   const int rtiles = (H->n2_max + 63) / 64;
-  const size_t shm1 = sizeof(double) * kStripsPerGroup * (H->n2_max + kWaves * 64);
-  hipLaunchKernelGGL((k_elem_solve<kStripsPerGroup, kWaves>), dim3(count, rtiles), dim3(64 * kWaves), shm1, st, H->d_sys,
-                     H->d_ins, w, src, dst);
+  if (count > 0) {
+    const size_t shm1 = sizeof(double) * kStripsPerGroup * (H->n2_max + kWaves * 64);
+    hipLaunchKernelGGL((k_elem_solve<kStripsPerGroup, kWaves>), dim3(count, rtiles), dim3(64 * kWaves), shm1, st,
+                       H->d_sys, H->d_ins, w, src, dst);
+  }
+  if (count1 > 0) {
+    const size_t shm1 = sizeof(double) * (H->n2_max + kWaves * 64);
+    hipLaunchKernelGGL((k_elem_solve<1, kWaves>), dim3(count1, rtiles), dim3(64 * kWaves), shm1, st, H->d_sys, H->d_ins,
+                       w1, src, dst);
+  }
   if (H->nq_max > 0) {
     const int2 *ws = H->w_s + (inst >= 0 ? H->s_start[inst] : 0);
     const int scount = inst >= 0 ? H->sys[H->h_ins[inst].sys].mx : H->n_s;
     const size_t shm2 = sizeof(double) * (H->nq_max + kWaves * 64);
     hipLaunchKernelGGL((k_strip_q<kWaves>), dim3(scount, (H->nq_max + 63) / 64), dim3(64 * kWaves), shm2, st, H->d_sys,
                        H->d_ins, ws, (const double *)dst, H->lam);
-    hipLaunchKernelGGL(k_elem_correct<kStripsPerGroup>, dim3(count, rtiles), dim3(kBlock), 0, st, H->d_sys, H->d_ins, w,
-                       dst, (const double *)H->lam);
+    if (count > 0)
+      hipLaunchKernelGGL(k_elem_correct<kStripsPerGroup>, dim3(count, rtiles), dim3(kBlock), 0, st, H->d_sys, H->d_ins, w,
+                         dst, (const double *)H->lam);
+    if (count1 > 0)
+      hipLaunchKernelGGL(k_elem_correct<1>, dim3(count1, rtiles), dim3(kBlock), 0, st, H->d_sys, H->d_ins, w1, dst,
+                         (const double *)H->lam);
   }
 }
 
