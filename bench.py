@@ -125,12 +125,20 @@ def main():
     stream = torch.cuda.current_stream(dev)
 
     if args.matvec_only:
+        # The Schur matvec alone, plus a plain device copy of known size that
+        # calibrates the HBM byte counters (FETCH_SIZE / WRITE_SIZE).
         s, _ = make_solver(args.config, P.FP64)
         x = torch.randn(s.total_kS, dtype=torch.float64, device=dev)
         y = torch.empty_like(x)
         ms = gpu_events_time(lambda: s.schur_apply_all(x, y, P.FP64), args.matvec_reps, stream)
+        cbytes = 256 << 20
+        a = torch.ones(cbytes // 8, dtype=torch.float64, device=dev)
+        b = torch.empty_like(a)
+        cms = gpu_events_time(lambda: b.copy_(a), 5, stream)
         print(json.dumps({"config": args.config, "matvec_fp64_us": ms * 1e3,
-                          "algorithmic_bytes": matvec_bytes(s, 8, 8)}), flush=True)
+                          "algorithmic_bytes": matvec_bytes(s, 8, 8),
+                          "copy_bytes_each_way": cbytes, "copy_us": cms * 1e3}), flush=True)
+        s.close()
         return
 
     forms = {}

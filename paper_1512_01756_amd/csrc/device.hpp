@@ -28,7 +28,7 @@ struct SysDev {
   const double *Gc;      // coarse operator, column-major d x d
   const double *uS, *uL; // null vectors (k = 0), else nullptr
   const double *Dinv;    // element inverses: [class][e][col n2][row n2]
-  const double *Kinv;    // z-interface capacitance inverses: [class][nq][nq] row-major
+  const double *Kinv;    // z-interface capacitance inverses: [class][col nq][row nq]
   int nq;                // 2 n (m_z - 1)
   const double *lo, *up; // [e][n]
   const double *beta;    // [class][2][n]: west row, east row
@@ -59,6 +59,29 @@ constexpr int kGroup = 4;
 struct HWork {
   int inst, cnt;
   int h[kGroup];
+};
+
+// Work item of the shared-block GEMM: one stored block (of system sys)
+// applied to `vcount` (instance, half) windows listed from `vstart` in the
+// window table.
+constexpr int kGemmVecs = 32;   // windows per workgroup
+struct GWork {
+  int sys, id, K, vstart, vcount, pad0, pad1, pad2;
+};
+
+// Column-gather GEMM item (element-interior elimination): Y[:, c] (+)= A X[:, c]
+// for the `ccount` columns listed from `cstart`.  A is R x K column-major with
+// leading dimension lda; columns k >= ksplit of the product read A's column
+// k + agap and the second source segment of the column (x2 + k - ksplit).
+constexpr int kColVecs = 64;    // columns per workgroup
+struct CGItem {
+  const double *A;
+  int R, K, lda, ksplit, agap, cstart, ccount, pad;
+};
+// Offsets (elements) of one column: first and second source segment (-1:
+// zeros) and the output.
+struct CGCol {
+  int64_t x1, x2, y;
 };
 
 struct GState {

@@ -71,87 +71,12 @@ __device__ inline void colsplit(const TO *__restrict__ blk, int R, int row, int 
 // Half-interface block GEMV (Sec. 3.1 Schur matvec, Sec. 3.2 block-Jacobi):
 //   op 0:  y_h = x_h + W^_h x[w_win(h) N .. + 2N)      (S = I + sum_j W_j)
 //   op 1:  y_h = Mc_h x[m_win(h) N .. + m_K(h))         (M^-1 row chunk)
-// A workgroup takes a 64-row tile of a group of up to G halves of one
-// instance that share the same column-major block, so one block load feeds
-// G windows.  The windows sit in LDS; the 4 waves split the columns and a
-// lane owns one row; wave partials are summed in LDS.
-// Grid: (group, row tile).  x_vslot: read x from Krylov slot `iter` of the
-// instance, scaled by scale[iter].  hsum: per-tile partial sums of y_h,
-// hsum[hs_off + h * tiles + tile] (for Z^T y).
-template <typename TO, typename TX, typename TY, int G, int NW>
-__global__ __launch_bounds__(64 * NW) void k_half_gemv(
-    const SysDev *__restrict__ sys, const InstDev *__restrict__ ins, const HWork *__restrict__ work,
-    int op, const TX *__restrict__ xbase, int x_vslot, const double *__restrict__ scale,
-    TY *__restrict__ ybase, double *__restrict__ hsum, const GState *__restrict__ gs) {
-  extern __shared__ double sm[];
-  __shared__ double lds4[4];
-  __shared__ int hh[kGroup];
-  const int i = work[blockIdx.x].inst, cnt = work[blockIdx.x].cnt;
-  if (gs && !gs[i].active) return;
-  if (threadIdx.x < kGroup) hh[threadIdx.x] = work[blockIdx.x].h[threadIdx.x];
-  const InstDev I = ins[i];
-  const SysDev &S = sys[I.sys];
-  const int N = S.N;
-  const int tiles = (N + 63) >> 6;
-  const int tile = blockIdx.y;
-  if (tile >= tiles) return;
-  __syncthreads();
-  const int64_t kS = S.kS;
-  const int h0 = hh[0];
-  int K;
-  const TO *blk;
-  const int Np = S.Np;
-  if (op == 0) {
-    K = 2 * N;
-    blk = Tab<TO>::W(S) + (size_t)S.w_id[h0] * 2 * N * Np;
-  } else {
-    K = S.m_K[h0];
-    blk = Tab<TO>::M(S) + (size_t)S.m_id[h0] * 4 * N * Np;
-  }
-  const int it = gs ? gs[i].iter : 0;
-  const TX *x = xbase + (x_vslot ? I.v_off + (int64_t)it * kS : I.x_off);
-  const double xs = scale ? scale[I.st_off + it] : 1.0;
-  double *xw = sm;                 // [G][K]
-  double *red = sm + G * K;        // [NW][G][64]
-  for (int g = 0; g < G; ++g) {
-    const int h = g < cnt ? hh[g] : h0;
-    const int64_t win = (int64_t)(op == 0 ? S.w_win[h] : S.m_win[h]) * N;
-    for (int c = threadIdx.x; c < K; c += 64 * NW) {
-      const int64_t idx = win + c;
-      xw[g * K + c] = (g < cnt && idx >= 0 && idx < kS) ? (double)x[idx] * xs : 0.0;
-    }
-  }
-  __syncthreads();
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int row = tile * 64 + lane;
-  const int c0 = (K * wave) / NW, c1 = (K * (wave + 1)) / NW;
-  TO acc[G];
-#pragma unroll
-  for (int g = 0; g < G; ++g) acc[g] = (TO)0;
-  colsplit<TO, G, 8>(blk, N, row, c0, c1, xw, K, acc, Np);
-#pragma unroll
-  for (int g = 0; g < G; ++g) red[(wave * G + g) * 64 + lane] = (double)acc[g];
-  __syncthreads();
-  for (int g = 0; g < cnt; ++g) {
-    const int h = hh[g];
-    double out_d = 0.0;
-    if (threadIdx.x < 64 && row < N) {
-      TO v = (TO)0;
-#pragma unroll
-      for (int w = 0; w < NW; ++w) v += (TO)red[(w * G + g) * 64 + lane];
-      double vd = (double)v;
-      if (op == 0) vd += (double)x[(int64_t)h * N + row] * xs;
-      const TY out = (TY)vd;
-      ybase[I.x_off + (int64_t)h * N + row] = out;
-      out_d = (double)out;
-    }
-    if (hsum) {   // only the first wave holds outputs
-      const double sgrp = wave_sum(out_d);
-      if (threadIdx.x == 0) hsum[I.hs_off + (int64_t)h * tiles + tile] = sgrp;
-    }
-  }
-}
-
+// Two kernels cover the halves: a streaming GEMV for blocks used by one half
+// (distinct strips, HBM bound) and an MFMA GEMM for blocks shared by many
+// halves (uniform strips).  x_vslot: read x from Krylov slot `iter` of the
+// instance, scaled by scale[iter].  hsum: per-(half, 16-row slot) partial sums
+// of y, hsum[hs_off + h * ceil(N / 16) + slot] (for Z^T y).
+//
 // Streaming variant for halves whose block is not shared (distinct strips):
 // one half per workgroup row tile, 16-byte loads (VR consecutive rows per
 // lane: 2 in FP64, 4 in FP32) along each column of the padded column-major
@@ -255,12 +180,153 @@ __global__ __launch_bounds__(64 * NW) void k_half_gemv_stream(
     if (threadIdx.x == 0) {
       double t = 0.0;
       for (int w = 0; w < NW; ++w) t += lds4b[w];
-      // per-tile partial, in the 64-row tile slots of the half (tiles of TR rows map to
-      // the first ceil(N/TR) slots; the remaining slots are zeroed)
-      const int slots = (N + 63) >> 6;
-      hsum[I.hs_off + (int64_t)h * slots + tile] = t;
-      if (tile == tiles - 1)
-        for (int q = tiles; q < slots; ++q) hsum[I.hs_off + (int64_t)h * slots + q] = 0.0;
+      // the tile's sum goes to its first 16-row slot, its other slots are zeroed
+      const int slots = (N + 15) >> 4;
+      const int q0 = tile * (TR / 16);
+      const int q1 = (tile + 1) * (TR / 16) < slots ? (tile + 1) * (TR / 16) : slots;
+      hsum[I.hs_off + (int64_t)h * slots + q0] = t;
+      for (int q = q0 + 1; q < q1; ++q) hsum[I.hs_off + (int64_t)h * slots + q] = 0.0;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Shared-block GEMM on the matrix cores (Sec. 3.1 Schur matvec, Sec. 3.2
+// block-Jacobi, for grids where strips share their operator): one stored
+// N x K block (column-major, Np rows) applied to up to kGemmVecs windows at
+// once, Y = Blk X (+ the identity for S), with 16x16x4 MFMAs on two 16-window
+// column tiles.
+// Grid (item, group of RT 16-row tiles); 8 waves: RT row tiles x 8/RT parts
+// of the K dimension, whose partial tiles are summed in LDS.  The B operand
+// (the windows) is read straight from global memory, U steps of loads in
+// flight per wave; RT = 2 halves the window re-reads when the launch is
+// large, RT = 1 doubles the parallelism when it is small.
+// MFMA lane layouts (gfx950): A: lane l holds A[l % 16][l / 16];
+// B: lane l holds B[l / 16][l % 16]; D (4 values per lane):
+// FP64: D[l / 16 + 4 j][l % 16];  FP32: D[4 (l / 16) + j][l % 16].
+typedef double mf_d4 __attribute__((ext_vector_type(4)));
+typedef float mf_f4 __attribute__((ext_vector_type(4)));
+
+template <typename TO> struct Mfma;
+template <> struct Mfma<double> {
+  using Acc = mf_d4;
+  __device__ static Acc mac(double a, double b, Acc c) { return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0); }
+  __device__ static int row(int lane, int j) { return (lane >> 4) + 4 * j; }
+};
+template <> struct Mfma<float> {
+  using Acc = mf_f4;
+  __device__ static Acc mac(float a, float b, Acc c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
+  __device__ static int row(int lane, int j) { return 4 * (lane >> 4) + j; }
+};
+
+template <typename TO, typename TX, typename TY, int RT>
+__global__ __launch_bounds__(512) void k_half_gemm(
+    const SysDev *__restrict__ sys, const InstDev *__restrict__ ins, const GWork *__restrict__ work,
+    const int2 *__restrict__ gvec, int op, const TX *__restrict__ xbase, int x_vslot,
+    const double *__restrict__ scale, TY *__restrict__ ybase, double *__restrict__ hsum,
+    const GState *__restrict__ gs) {
+  constexpr int VT = kGemmVecs;
+  constexpr int KP = 8 / RT;                 // waves splitting K
+  constexpr int U = 8;                       // K steps whose loads are issued together
+  __shared__ double red[KP * RT * 16 * VT];
+  __shared__ int64_t v_xoff[VT], v_win[VT], v_yoff[VT];
+  __shared__ double v_scale[VT];
+  __shared__ int v_live[VT], v_h[VT], v_hs[VT];
+  const GWork wk = work[blockIdx.x];
+  const SysDev &S = sys[wk.sys];
+  const int N = S.N, Np = S.Np, K = wk.K;
+  const int64_t kS = S.kS;
+  const int rg = blockIdx.y;                 // group of RT 16-row tiles
+  if (rg * RT * 16 >= Np) return;
+  const int vcount = wk.vcount;
+  if (threadIdx.x < VT) {
+    const int v = threadIdx.x;
+    int live = 0;
+    if (v < vcount) {
+      const int2 e = gvec[wk.vstart + v];
+      const InstDev I = ins[e.x];
+      live = gs ? gs[e.x].active : 1;
+      const int it = gs ? gs[e.x].iter : 0;
+      v_h[v] = e.y;
+      v_hs[v] = (int)I.hs_off;
+      v_xoff[v] = x_vslot ? I.v_off + (int64_t)it * kS : I.x_off;
+      v_win[v] = (int64_t)(op == 0 ? S.w_win[e.y] : S.m_win[e.y]) * N;
+      v_yoff[v] = I.x_off + (int64_t)e.y * N;
+      v_scale[v] = scale ? scale[I.st_off + it] : 1.0;
+    }
+    v_live[v] = live;
+  }
+  __syncthreads();
+  int anylive = 0;
+  for (int v = 0; v < vcount; ++v) anylive |= v_live[v];
+  if (!anylive) return;
+  const TO *blk = (op == 0 ? Tab<TO>::W(S) + (size_t)wk.id * 2 * N * Np : Tab<TO>::M(S) + (size_t)wk.id * 4 * N * Np);
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int rtl = wave % RT, kp = wave / RT;
+  const int arow = (rg * RT + rtl) * 16 + (lane & 15);
+  const bool alive = arow < Np;
+  const int kq = lane >> 4;
+  // this lane's two windows (columns of the two 16-window tiles)
+  const int va = lane & 15, vb = 16 + (lane & 15);
+  const bool la = va < vcount && v_live[va], lb = vb < vcount && v_live[vb];
+  const int64_t xa = v_xoff[va], wa = v_win[va], xb = v_xoff[vb], wb = v_win[vb];
+  const double sa = v_scale[va], sb = v_scale[vb];
+  using Acc = typename Mfma<TO>::Acc;
+  Acc acc0 = {0, 0, 0, 0}, acc1 = {0, 0, 0, 0};
+  const int nsteps = (K + 3) >> 2;
+  const int s0 = (nsteps * kp) / KP, s1 = (nsteps * (kp + 1)) / KP;
+  for (int st = s0; st < s1; st += U) {
+    TO a[U], b0[U], b1[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int k = 4 * (st + u) + kq;
+      const bool kin = st + u < s1 && k < K;
+      const int64_t ga = wa + k, gb = wb + k;
+      a[u] = (alive && kin) ? blk[(size_t)k * Np + arow] : (TO)0;
+      b0[u] = (la && kin && ga >= 0 && ga < kS) ? (TO)((double)xbase[xa + ga] * sa) : (TO)0;
+      b1[u] = (lb && kin && gb >= 0 && gb < kS) ? (TO)((double)xbase[xb + gb] * sb) : (TO)0;
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      acc0 = Mfma<TO>::mac(a[u], b0[u], acc0);
+      acc1 = Mfma<TO>::mac(a[u], b1[u], acc1);
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const int lr = rtl * 16 + Mfma<TO>::row(lane, j);
+    red[(kp * RT * 16 + lr) * VT + va] = (double)acc0[j];
+    red[(kp * RT * 16 + lr) * VT + vb] = (double)acc1[j];
+  }
+  __syncthreads();
+  // outputs: thread -> (row, window); sum the KP partials in a fixed order
+  const int slots = (N + 15) >> 4;
+  for (int idx = threadIdx.x; idx < RT * 16 * VT; idx += 64 * RT * KP) {
+    const int lr = idx / VT, v = idx - lr * VT;
+    const int row = rg * RT * 16 + lr;
+    double outv = 0.0;
+    if (v < vcount && v_live[v] && row < N) {
+      TO t = (TO)red[idx];
+#pragma unroll
+      for (int q = 1; q < KP; ++q) t += (TO)red[q * RT * 16 * VT + idx];
+      double vd = (double)t;
+      if (op == 0) vd += (double)xbase[v_xoff[v] + (int64_t)v_h[v] * N + row] * v_scale[v];
+      const TY out = (TY)vd;
+      ybase[v_yoff[v] + row] = out;
+      outv = (double)out;
+    }
+    red[idx] = outv;   // this thread's own slot of the first partial
+  }
+  if (hsum) {
+    __syncthreads();
+    if (threadIdx.x < RT * VT) {
+      const int t = threadIdx.x / VT, v = threadIdx.x - t * VT;
+      const int slot = rg * RT + t;
+      if (v < vcount && v_live[v] && slot < slots) {
+        double acc = 0.0;
+        for (int lr = 0; lr < 16; ++lr) acc += red[(t * 16 + lr) * VT + v];
+        hsum[v_hs[v] + (int64_t)v_h[v] * slots + slot] = acc;
+      }
     }
   }
 }
@@ -282,7 +348,7 @@ __global__ __launch_bounds__(kBlock) void k_coarse(const SysDev *__restrict__ sy
   const InstDev I = ins[i];
   const SysDev &S = sys[I.sys];
   const int d = S.d;
-  const int tiles = (S.N + 63) >> 6;
+  const int tiles = (S.N + 15) >> 4;
   for (int c = threadIdx.x; c < d; c += kBlock) {
     double v = 0.0;
     for (int q = 0; q < 2 * tiles; ++q) v += hsum[I.hs_off + (int64_t)2 * c * tiles + q];
@@ -331,7 +397,7 @@ __global__ __launch_bounds__(kBlock) void k_pcorr_dot(
   int ilo = 0;
   if (useP) {
     const int d = S.d;
-    const int tiles = (N + 63) >> 6;
+    const int tiles = (N + 15) >> 4;
     for (int c = threadIdx.x; c < d; c += kBlock) {
       double v = 0.0;
       for (int q = 0; q < 2 * tiles; ++q) v += hsum[I.hs_off + (int64_t)2 * c * tiles + q];
@@ -582,73 +648,189 @@ __global__ __launch_bounds__(kBlock) void k_combine(const SysDev *__restrict__ s
 // (with their own Robin terms), P Lambda the coupling across the z-interfaces
 // inside the strip.  By the capacitance (Woodbury) identity
 //   A_j^-1 v = w - D^-1 P q,  w = D^-1 v,  q = K^-1 Lambda w,  K = I + Lambda D^-1 P,
-// every element is solved independently (one dense GEMV with the element
-// inverse) and only the small z-interface system K couples them.
+// every element is solved independently and only the small z-interface
+// system K couples them.  All strips of one class share D^-1 and K^-1, so
+// each of the three products is a GEMM whose columns are the (instance,
+// strip) vectors: k_colgemm below, on FP64 MFMA.
 //
-// k_elem_solve: w = D^-1 v.  Grid (element item, 64-row tile); an item is
-// (inst, first strip, strip count, element e) with strips of one class, so
-// one load of the element inverse feeds up to SG strips.
-template <int SG, int NW>
-__global__ __launch_bounds__(64 * NW) void k_elem_solve(const SysDev *__restrict__ sys,
-                                                       const InstDev *__restrict__ ins,
-                                                       const int4 *__restrict__ work,
-                                                       const double *__restrict__ src,
-                                                       double *__restrict__ dst) {
-  extern __shared__ double sm[];
-  const int4 wk = work[blockIdx.x];
-  const int i = wk.x, j0 = wk.y, ng = wk.z, e = wk.w;
-  const InstDev I = ins[i];
-  const SysDev &S = sys[I.sys];
-  const int n2 = S.n2, mz = S.mz;
-  const int tile = blockIdx.y;
-  if (tile * 64 >= n2) return;
-  const double *Di = S.Dinv + ((size_t)S.strip_class[j0] * mz + e) * n2 * n2;
-  double *vl = sm;              // [SG][n2]
-  double *red = sm + SG * n2;   // [NW][SG][64]
-  for (int idx = threadIdx.x; idx < SG * n2; idx += 64 * NW) {
-    const int sI = idx / n2, l = idx - sI * n2;
-    vl[idx] = sI < ng ? src[I.f_off + ((int64_t)(j0 + sI) * mz + e) * n2 + l] : 0.0;
+// Two schedules of the same product.  k_colgemm (few items: latency-bound
+// launches): grid (item, 16-row tile), 8 waves split K, each multiplies its
+// 16 rows by CT tiles of 16 columns with v_mfma_f64_16x16x4f64, U K-steps of
+// loads in flight, the K parts summed in LDS in a fixed order.
+// k_colgemm_t (many items: throughput-bound launches): grid (item, 64-row
+// tile), 4 waves of 16 rows over all of K; the columns are staged through
+// double-buffered LDS in chunks of 32 K-steps with coalesced loads (each
+// column is contiguous in memory) while the next chunk's operands are in
+// flight.  MODE 0: Y = A X; MODE 1: Y -= A X.  X and Y must not overlap.
+__device__ inline double colval(const double *__restrict__ xb, int64_t x1, int64_t x2, int k, int K, int ks) {
+  if (k >= K) return 0.0;
+  if (k < ks) return x1 >= 0 ? xb[x1 + k] : 0.0;
+  return x2 >= 0 ? xb[x2 + (k - ks)] : 0.0;
+}
+
+template <int CT, int MODE>
+__global__ __launch_bounds__(512) void k_colgemm(const CGItem *__restrict__ items, const CGCol *__restrict__ cols,
+                                                 const double *__restrict__ xb, double *__restrict__ yb) {
+  constexpr int VC = 16 * CT;
+  constexpr int KP = 8;
+  constexpr int U = 4;
+  __shared__ double red[KP * 16 * VC];
+  const CGItem it = items[blockIdx.x];
+  const int rt = blockIdx.y;
+  if (rt * 16 >= it.R) return;
+  const int kp = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int arow = rt * 16 + (lane & 15);
+  const bool alive = arow < it.R;
+  const int kq = lane >> 4, cl = lane & 15;
+  int64_t x1[CT], x2[CT];
+#pragma unroll
+  for (int t = 0; t < CT; ++t) {
+    const int ci = t * 16 + cl;
+    const bool ok = ci < it.ccount;
+    x1[t] = ok ? cols[it.cstart + ci].x1 : -1;
+    x2[t] = ok ? cols[it.cstart + ci].x2 : -1;
+  }
+  using Acc = Mfma<double>::Acc;
+  Acc acc[CT];
+#pragma unroll
+  for (int t = 0; t < CT; ++t) acc[t] = Acc{0, 0, 0, 0};
+  const int K = it.K, ks = it.ksplit;
+  const int nsteps = (K + 3) >> 2;
+  const int s0 = (nsteps * kp) / KP, s1 = (nsteps * (kp + 1)) / KP;
+  for (int st = s0; st < s1; st += U) {
+    double a[U], b[CT][U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int k = 4 * (st + u) + kq;
+      const bool kin = st + u < s1 && k < K;
+      const int ka = k < ks ? k : k + it.agap;
+      a[u] = (alive && kin) ? it.A[(size_t)ka * it.lda + arow] : 0.0;
+#pragma unroll
+      for (int t = 0; t < CT; ++t) b[t][u] = kin ? colval(xb, x1[t], x2[t], k, K, ks) : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+#pragma unroll
+      for (int t = 0; t < CT; ++t) acc[t] = Mfma<double>::mac(a[u], b[t][u], acc[t]);
+  }
+#pragma unroll
+  for (int t = 0; t < CT; ++t)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) red[(kp * 16 + Mfma<double>::row(lane, j)) * VC + t * 16 + cl] = acc[t][j];
+  __syncthreads();
+  for (int idx = threadIdx.x; idx < 16 * VC; idx += 512) {
+    const int lr = idx / VC, ci = idx - lr * VC;
+    const int row = rt * 16 + lr;
+    if (ci < it.ccount && row < it.R) {
+      double v = red[idx];
+#pragma unroll
+      for (int q = 1; q < KP; ++q) v += red[q * 16 * VC + idx];
+      const int64_t yo = cols[it.cstart + ci].y + row;
+      if (MODE == 0) yb[yo] = v;
+      else yb[yo] -= v;
+    }
+  }
+}
+
+template <int CT, int MODE>
+__global__ __launch_bounds__(256) void k_colgemm_t(const CGItem *__restrict__ items, const CGCol *__restrict__ cols,
+                                                   const double *__restrict__ xb, double *__restrict__ yb) {
+  constexpr int VC = 16 * CT, KC = 32, PITCH = VC + 1;
+  constexpr int PV = KC * VC / 256;      // staged values per thread per chunk
+  constexpr int TPC = KC / PV;           // threads per column
+  __shared__ double Bs[2][KC * PITCH];
+  __shared__ int64_t c1[VC], c2[VC];
+  const CGItem it = items[blockIdx.x];
+  const int rg = blockIdx.y;
+  if (rg * 64 >= it.R) return;
+  if (threadIdx.x < VC) {
+    const bool ok = (int)threadIdx.x < it.ccount;
+    c1[threadIdx.x] = ok ? cols[it.cstart + threadIdx.x].x1 : -1;
+    c2[threadIdx.x] = ok ? cols[it.cstart + threadIdx.x].x2 : -1;
   }
   __syncthreads();
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int row = tile * 64 + lane;
-  double acc[SG];
+  const int arow = rg * 64 + wave * 16 + (lane & 15);
+  const bool alive = arow < it.R;
+  const int kq = lane >> 4, cl = lane & 15;
+  const int K = it.K, ks = it.ksplit, lda = it.lda, agap = it.agap;
+  const double *__restrict__ A = it.A;
+  const int scol = threadIdx.x / TPC, sk0 = (threadIdx.x % TPC) * PV;
+  const int64_t sx1 = c1[scol], sx2 = c2[scol];
+  double pre[PV];
+  double a[KC / 4], an[KC / 4];
+  auto load_b = [&](int kc) {
 #pragma unroll
-  for (int q = 0; q < SG; ++q) acc[q] = 0.0;
-  colsplit<double, SG, 8>(Di, n2, row, (n2 * wave) / NW, (n2 * (wave + 1)) / NW, vl, n2, acc);
+    for (int p = 0; p < PV; ++p) pre[p] = colval(xb, sx1, sx2, kc * KC + sk0 + p, K, ks);
+  };
+  auto load_a = [&](int kc, double *dst) {
 #pragma unroll
-  for (int q = 0; q < SG; ++q) red[(wave * SG + q) * 64 + lane] = acc[q];
-  __syncthreads();
-  if (threadIdx.x < 64 && row < n2)
-    for (int q = 0; q < ng; ++q) {
-      double a = 0.0;
-#pragma unroll
-      for (int w = 0; w < NW; ++w) a += red[(w * SG + q) * 64 + lane];
-      dst[I.f_off + ((int64_t)(j0 + q) * mz + e) * n2 + row] = a;
+    for (int s = 0; s < KC / 4; ++s) {
+      const int k = kc * KC + 4 * s + kq;
+      const int ka = k < ks ? k : k + agap;
+      dst[s] = (alive && k < K) ? A[(size_t)ka * lda + arow] : 0.0;
     }
+  };
+  auto store_b = [&](int buf) {
+#pragma unroll
+    for (int p = 0; p < PV; ++p) Bs[buf][(sk0 + p) * PITCH + scol] = pre[p];
+  };
+  using Acc = Mfma<double>::Acc;
+  Acc acc[CT];
+#pragma unroll
+  for (int t = 0; t < CT; ++t) acc[t] = Acc{0, 0, 0, 0};
+  const int nchunks = (K + KC - 1) / KC;
+  load_b(0);
+  load_a(0, a);
+  store_b(0);
+  __syncthreads();
+  for (int kc = 0; kc < nchunks; ++kc) {
+    const int buf = kc & 1;
+    const bool more = kc + 1 < nchunks;
+    if (more) {
+      load_b(kc + 1);
+      load_a(kc + 1, an);
+    }
+    const double *__restrict__ B = Bs[buf];
+#pragma unroll
+    for (int s = 0; s < KC / 4; ++s)
+#pragma unroll
+      for (int t = 0; t < CT; ++t) acc[t] = Mfma<double>::mac(a[s], B[(4 * s + kq) * PITCH + t * 16 + cl], acc[t]);
+    if (more) {
+      store_b(buf ^ 1);
+#pragma unroll
+      for (int s = 0; s < KC / 4; ++s) a[s] = an[s];
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int t = 0; t < CT; ++t) {
+    const int ci = t * 16 + cl;
+    if (ci >= it.ccount) continue;
+    const int64_t y0 = cols[it.cstart + ci].y;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int row = rg * 64 + wave * 16 + Mfma<double>::row(lane, j);
+      if (row < it.R) {
+        if (MODE == 0) yb[y0 + row] = acc[t][j];
+        else yb[y0 + row] -= acc[t][j];
+      }
+    }
+  }
 }
 
-// k_strip_q: lambda = Lambda w for one strip (the lo functional of interface
-// i reads element i, the up functional reads element i+1), then one 64-row
-// tile of q = K^-1 lambda.  Grid (inst * strip, q tile).
-template <int NW>
-__global__ __launch_bounds__(64 * NW) void k_strip_q(const SysDev *__restrict__ sys,
-                                                    const InstDev *__restrict__ ins,
-                                                    const int2 *__restrict__ work,
-                                                    const double *__restrict__ w,
-                                                    double *__restrict__ qout) {
-  extern __shared__ double sm[];
+// lambda = Lambda w for every (instance, strip): the lo functional of
+// z-interface i reads element i, the up functional reads element i+1.
+__global__ __launch_bounds__(kBlock) void k_lambda(const SysDev *__restrict__ sys, const InstDev *__restrict__ ins,
+                                                   const int2 *__restrict__ work, const double *__restrict__ w,
+                                                   double *__restrict__ lam) {
   const int2 wk = work[blockIdx.x];
   const int i = wk.x, j = wk.y;
   const InstDev I = ins[i];
   const SysDev &S = sys[I.sys];
   const int n = S.n, n2 = S.n2, mz = S.mz, nq = S.nq;
-  const int tile = blockIdx.y;
-  if (tile * 64 >= nq) return;
-  double *lamv = sm;            // [nq]
-  double *red = sm + nq;        // [NW][64]
   const double *ws = w + I.f_off + (int64_t)j * mz * n2;
-  for (int idx = threadIdx.x; idx < nq; idx += 64 * NW) {
+  for (int idx = threadIdx.x; idx < nq; idx += kBlock) {
     const int iface = idx / (2 * n), r = idx - iface * 2 * n;
     const int part = r / n, t = r - part * n;
     double a = 0.0;
@@ -659,77 +841,8 @@ __global__ __launch_bounds__(64 * NW) void k_strip_q(const SysDev *__restrict__ 
       const double *we = ws + (int64_t)(iface + 1) * n2;
       for (int c = 0; c < n; ++c) a += S.up[iface * n + c] * we[c * n + t];
     }
-    lamv[idx] = a;
+    lam[I.lam_off + (int64_t)j * nq + idx] = a;
   }
-  __syncthreads();
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int row = tile * 64 + lane;
-  const double *Ki = S.Kinv + (size_t)S.strip_class[j] * nq * nq;   // column-major
-  double acc[1] = {0.0};
-  colsplit<double, 1, 8>(Ki, nq, row, (nq * wave) / NW, (nq * (wave + 1)) / NW, lamv, 0, acc);
-  red[wave * 64 + lane] = acc[0];
-  __syncthreads();
-  if (threadIdx.x < 64 && row < nq) {
-    double a = 0.0;
-#pragma unroll
-    for (int w2 = 0; w2 < NW; ++w2) a += red[w2 * 64 + lane];
-    qout[I.lam_off + (int64_t)j * nq + row] = a;
-  }
-}
-
-// k_elem_correct: u_e = w_e - Dg_e^-1[:, rows (0,t)] q_lo - Dg_e^-1[:, rows
-// (n-1,t)] q_up (in place).  Grid (element item, 64-row tile).
-template <int SG>
-__global__ __launch_bounds__(kBlock) void k_elem_correct(const SysDev *__restrict__ sys,
-                                                         const InstDev *__restrict__ ins,
-                                                         const int4 *__restrict__ work,
-                                                         double *__restrict__ dst,
-                                                         const double *__restrict__ qv) {
-  __shared__ double qs[SG * 64];     // [SG][2n], n <= 32
-  __shared__ double red[4 * SG * 64];
-  const int4 wk = work[blockIdx.x];
-  const int i = wk.x, j0 = wk.y, ng = wk.z, e = wk.w;
-  const InstDev I = ins[i];
-  const SysDev &S = sys[I.sys];
-  const int n = S.n, n2 = S.n2, mz = S.mz, nq = S.nq;
-  if (nq == 0) return;
-  const int tile = blockIdx.y;
-  if (tile * 64 >= n2) return;
-  const double *Di = S.Dinv + ((size_t)S.strip_class[j0] * mz + e) * n2 * n2;
-  for (int idx = threadIdx.x; idx < SG * 2 * n; idx += kBlock) {
-    const int sI = idx / (2 * n), r = idx - sI * 2 * n;
-    const int part = r / n, t = r - part * n;
-    double a = 0.0;
-    if (sI < ng) {
-      if (part == 0 && e >= 1) a = qv[I.lam_off + (int64_t)(j0 + sI) * nq + (2 * (e - 1)) * n + t];
-      if (part == 1 && e + 1 < mz) a = qv[I.lam_off + (int64_t)(j0 + sI) * nq + (2 * e + 1) * n + t];
-    }
-    qs[idx] = a;
-  }
-  __syncthreads();
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int row = tile * 64 + lane;
-  const bool live = row < n2;
-  double acc[SG];
-#pragma unroll
-  for (int q = 0; q < SG; ++q) acc[q] = 0.0;
-  // 2n columns: t < n -> Di column t (row (0,t)); t >= n -> column (n-1)n + t - n
-  const int nc = 2 * n;
-  const int c0 = (nc * wave) >> 2, c1 = (nc * (wave + 1)) >> 2;
-  for (int c = c0; c < c1; ++c) {
-    const int colidx = c < n ? c : (n - 1) * n + (c - n);
-    const double v = live ? Di[(size_t)colidx * n2 + row] : 0.0;
-#pragma unroll
-    for (int q = 0; q < SG; ++q) acc[q] += v * qs[q * 2 * n + c];
-  }
-#pragma unroll
-  for (int q = 0; q < SG; ++q) red[(wave * SG + q) * 64 + lane] = acc[q];
-  __syncthreads();
-  if (threadIdx.x < 64 && live)
-    for (int q = 0; q < ng; ++q)
-      dst[I.f_off + ((int64_t)(j0 + q) * mz + e) * n2 + row] -=
-          (red[(0 * SG + q) * 64 + lane] + red[(1 * SG + q) * 64 + lane]) +
-          (red[(2 * SG + q) * 64 + lane] + red[(3 * SG + q) * 64 + lane]);
 }
 
 // RHS of Eq. (smpm_poisson): F = f + tau g on the physical edges (corners get
@@ -890,7 +1003,7 @@ __global__ __launch_bounds__(kBlock) void k_halfsum(const SysDev *__restrict__ s
   a = block_sum(a, lds4);
   __syncthreads();
   if (hdot) b = block_sum(b, lds4);
-  const int tiles = (N + 63) >> 6;
+  const int tiles = (N + 15) >> 4;
   if (threadIdx.x == 0) {
     hs[I.hs_off + (int64_t)h * tiles] = a;
     if (hdot) hdot[I.hs_off + h] = b;

@@ -79,7 +79,6 @@ std::vector<T> to_colmajor_padded(const std::vector<double> &a, int nb, int rows
   return out;
 }
 
-constexpr int kStripsPerGroup = 4;
 constexpr int kIterChunk = 4;
 constexpr int kWaves = 16;   // waves per workgroup of the GEMV-shaped kernels
 
@@ -100,17 +99,26 @@ struct smpm_handle {
   int ninst = 0, Nmax = 0, group = 1, nq_max = 0, n2_max = 0;
   // Work lists: grouped halves for S and M^-1, plain halves, element items,
   // interface and node vector chunks.  Per instance [start, start + count).
-  HWork *w_S = nullptr, *w_M = nullptr;     // grouped items (shared blocks)
+  // Systems whose strips share blocks use the MFMA GEMM: items over windows
+  // grouped by block id across all instances of a system (batched launches),
+  // and within one instance (single-system applies).
+  GWork *g_S = nullptr, *g_M = nullptr, *g_Si = nullptr, *g_Mi = nullptr;
+  int2 *g_vec = nullptr;
+  int n_gS = 0, n_gM = 0;
+  std::vector<int> gSi_start, gSi_cnt, gMi_start, gMi_cnt;
   HWork *w_S1 = nullptr, *w_M1 = nullptr;   // single items (streamed blocks)
   int n_S1 = 0, n_M1 = 0;
   std::vector<int> S1_start, S1_cnt, M1_start, M1_cnt;
   int2 *w_h = nullptr, *w_x = nullptr, *w_r = nullptr, *w_s = nullptr;
-  int4 *w_E = nullptr;      // element items with several strips of one class
-  int4 *w_E1 = nullptr;     // element items of a single strip
-  int n_E1 = 0;
-  std::vector<int> E1_start, E1_cnt;
-  int n_S = 0, n_M = 0, n_h = 0, n_E = 0, n_x = 0, n_r = 0, n_s = 0;
-  std::vector<int> S_start, S_cnt, M_start, M_cnt, h_start, E_start, E_cnt, x_start, r_start, s_start;
+  // Element-interior GEMM items, kind 0: w = D^-1 v, 1: q = K^-1 lambda,
+  // 2: v -= D^-1 P q; batched over all instances, and per instance.
+  // Index [kind][w]: w = 0 items of at most 16 columns, w = 1 of up to 64.
+  CGItem *cg_all[3][2] = {}, *cg_one[3][2] = {};
+  CGCol *cg_cols = nullptr;
+  int n_cg_all[3][2] = {};
+  std::vector<int> cg_start[3][2], cg_cnt[3][2];
+  int n_h = 0, n_x = 0, n_r = 0, n_s = 0;
+  std::vector<int> h_start, x_start, r_start, s_start;
   int64_t tot_r = 0, tot_x = 0, tot_g = 0;
 
   double *F = nullptr, *v = nullptr, *Rr = nullptr, *bS = nullptr, *xS = nullptr, *rb = nullptr;
@@ -120,7 +128,7 @@ struct smpm_handle {
   float *V32 = nullptr;
   double *part1 = nullptr, *part2 = nullptr, *partn = nullptr, *pr = nullptr, *hs = nullptr;
   double *cv = nullptr, *tb = nullptr, *scale = nullptr, *Rm = nullptr, *cs = nullptr, *sn = nullptr, *g = nullptr;
-  double *ycoef = nullptr, *defect = nullptr, *pairs = nullptr, *lam = nullptr;
+  double *ycoef = nullptr, *defect = nullptr, *pairs = nullptr, *lam = nullptr, *qb = nullptr;
   GState *gs = nullptr;
   GState *h_gs = nullptr;      // pinned
   double *h_pairs = nullptr;   // pinned
@@ -147,6 +155,14 @@ struct smpm_handle {
 
 namespace {
 
+// True if some block id serves more than one half.
+bool shares_blocks(const std::vector<int> &ids) {
+  std::map<int, int> c;
+  for (int id : ids)
+    if (++c[id] > 1) return true;
+  return false;
+}
+
 // Group the halves of one instance that share a block id (up to `group`).
 void group_halves(int inst, const std::vector<int> &ids, int group, std::vector<HWork> &out) {
   std::map<int, std::vector<int>> by;
@@ -172,9 +188,6 @@ void upload(smpm_handle *H, hipStream_t st) {
     H->n2_max = std::max(H->n2_max, s.n2);
   }
   // Group size bounded by the GEMV's LDS budget (windows + wave partials).
-  // Grouping (up to kGroup halves sharing a block per workgroup) needs the
-  // windows of the group in LDS; above that budget every half is streamed.
-  H->group = ((size_t)kGroup * (4 * H->Nmax + kWaves * 64) * sizeof(double) <= 64 * 1024) ? kGroup : 1;
   for (System &s : H->sys) {
     SysDev d{};
     d.n = s.n; d.mx = s.mx; d.mz = s.mz; d.n2 = s.n2; d.N = s.N; d.nh = s.nh; d.d = s.d;
@@ -214,8 +227,7 @@ void upload(smpm_handle *H, hipStream_t st) {
     H->h_sys.push_back(d);
   }
   H->d_sys = dupload(own, H->h_sys, st);
-  std::vector<HWork> wS, wM, wS1, wM1;
-  std::vector<int4> wE, wE1;
+  std::vector<HWork> wS1, wM1;
   std::vector<int2> wh, wx, wr, ws;
   int64_t f_off = 0, g_off = 0, x_off = 0, v_off = 0, part_off = 0, pr_off = 0, hs_off = 0, c_off = 0,
           st_off = 0, rr_off = 0, lam_off = 0;
@@ -233,40 +245,24 @@ void upload(smpm_handle *H, hipStream_t st) {
       I.st_off = st_off; I.rr_off = rr_off; I.lam_off = lam_off;
       f_off += s.r; g_off += 2LL * s.n * (s.mx + s.mz); x_off += s.kS; v_off += (int64_t)(maxit + 1) * s.kS;
       part_off += (int64_t)(maxit + 1) * I.nchunk_x + 2; pr_off += 2LL * I.nchunk_r;
-      hs_off += (int64_t)s.nh * ((s.N + 63) / 64); c_off += s.d;
+      hs_off += (int64_t)s.nh * ((s.N + 15) / 16); c_off += s.d;
       st_off += maxit + 1; rr_off += (int64_t)maxit * maxit; lam_off += (int64_t)s.mx * nq;
+      // Halves of a system whose strips share blocks go through the MFMA GEMM
+      // (items built below); a system with no sharing streams every half.
       {
-        // A system whose halves share blocks runs every half through the
-        // grouped kernel (one launch); a system with no sharing streams.
         std::vector<HWork> tmp;
-        auto any_shared = [](const std::vector<HWork> &v) {
-          for (const HWork &w : v) if (w.cnt > 1) return true;
-          return false;
-        };
-        group_halves(inst, s.w_id, H->group, tmp);
-        const bool shS = any_shared(tmp);
-        H->S_start.push_back((int)wS.size()); H->S1_start.push_back((int)wS1.size());
-        for (const HWork &w : tmp) (shS ? wS : wS1).push_back(w);
-        H->S_cnt.push_back((int)wS.size() - H->S_start.back()); H->S1_cnt.push_back((int)wS1.size() - H->S1_start.back());
+        if (!shares_blocks(s.w_id)) group_halves(inst, s.w_id, 1, tmp);
+        H->S1_start.push_back((int)wS1.size());
+        wS1.insert(wS1.end(), tmp.begin(), tmp.end());
+        H->S1_cnt.push_back((int)wS1.size() - H->S1_start.back());
         tmp.clear();
-        group_halves(inst, s.m_id, H->group, tmp);
-        const bool shM = any_shared(tmp);
-        H->M_start.push_back((int)wM.size()); H->M1_start.push_back((int)wM1.size());
-        for (const HWork &w : tmp) (shM ? wM : wM1).push_back(w);
-        H->M_cnt.push_back((int)wM.size() - H->M_start.back()); H->M1_cnt.push_back((int)wM1.size() - H->M1_start.back());
+        if (!shares_blocks(s.m_id)) group_halves(inst, s.m_id, 1, tmp);
+        H->M1_start.push_back((int)wM1.size());
+        wM1.insert(wM1.end(), tmp.begin(), tmp.end());
+        H->M1_cnt.push_back((int)wM1.size() - H->M1_start.back());
       }
       H->h_start.push_back((int)wh.size());
       for (int h = 0; h < s.nh; ++h) wh.push_back(make_int2(inst, h));
-      H->E_start.push_back((int)wE.size());
-      H->E1_start.push_back((int)wE1.size());
-      for (int j = 0; j < s.mx;) {
-        int ng = 1;
-        while (ng < kStripsPerGroup && j + ng < s.mx && s.strip_class[j + ng] == s.strip_class[j]) ++ng;
-        for (int e = 0; e < s.mz; ++e) (ng > 1 ? wE : wE1).push_back(make_int4(inst, j, ng, e));
-        j += ng;
-      }
-      H->E_cnt.push_back((int)wE.size() - H->E_start.back());
-      H->E1_cnt.push_back((int)wE1.size() - H->E1_start.back());
       H->s_start.push_back((int)ws.size());
       for (int j = 0; j < s.mx; ++j) ws.push_back(make_int2(inst, j));
       H->x_start.push_back((int)wx.size());
@@ -278,14 +274,134 @@ void upload(smpm_handle *H, hipStream_t st) {
   }
   H->ninst = (int)H->h_ins.size();
   H->tot_r = f_off; H->tot_x = x_off; H->tot_g = g_off;
+  // Element-interior GEMM items: per (system, strip class, element) for the
+  // element inverses, per (system, strip class) for the capacitance inverse;
+  // the columns are the (instance, strip) vectors of that class.
+  {
+    std::vector<CGItem> all[3][2], one[3][2];
+    std::vector<CGCol> cols;
+    // chunks of 64 columns; a class (or remainder) of at most 16 columns
+    // goes to the narrow list
+    auto emit = [&](const double *A, int R, int K, int lda, int ksplit, int agap, const std::vector<CGCol> &cv,
+                    std::vector<CGItem> *out) {
+      for (size_t a = 0; a < cv.size();) {
+        const size_t left = cv.size() - a;
+        const int w = left <= 16 ? 0 : 1;
+        CGItem it{};
+        it.A = A; it.R = R; it.K = K; it.lda = lda; it.ksplit = ksplit; it.agap = agap;
+        it.cstart = (int)cols.size();
+        it.ccount = (int)std::min<size_t>(w ? kColVecs : 16, left);
+        cols.insert(cols.end(), cv.begin() + a, cv.begin() + a + it.ccount);
+        out[w].push_back(it);
+        a += it.ccount;
+      }
+    };
+    // items of system si over the instances [i0, i1)
+    auto items = [&](int si, int i0, int i1, std::vector<CGItem> (*out)[2]) {
+      const System &s = H->sys[si];
+      const SysDev &d = H->h_sys[si];
+      const int n = s.n, n2 = s.n2, mz = s.mz, nq = 2 * s.n * (s.mz - 1);
+      for (int c = 0; c < (int)s.classes.size(); ++c) {
+        std::vector<int> strips;
+        for (int j = 0; j < s.mx; ++j)
+          if (s.strip_class[j] == c) strips.push_back(j);
+        for (int e = 0; e < mz; ++e) {
+          const double *A = d.Dinv + ((size_t)c * mz + e) * n2 * n2;
+          std::vector<CGCol> cs, cc;
+          for (int i = i0; i < i1; ++i) {
+            const InstDev &I = H->h_ins[i];
+            for (int j : strips) {
+              const int64_t off = I.f_off + ((int64_t)j * mz + e) * n2;
+              cs.push_back(CGCol{off, -1, off});
+              const int64_t q0 = I.lam_off + (int64_t)j * nq;
+              cc.push_back(CGCol{e >= 1 ? q0 + (int64_t)(2 * (e - 1)) * n : -1,
+                                 e + 1 < mz ? q0 + (int64_t)(2 * e + 1) * n : -1, off});
+            }
+          }
+          emit(A, n2, n2, n2, n2, 0, cs, out[0]);
+          if (nq > 0) emit(A, n2, 2 * n, n2, n, n2 - 2 * n, cc, out[2]);
+        }
+        if (nq > 0) {
+          std::vector<CGCol> cq;
+          for (int i = i0; i < i1; ++i)
+            for (int j : strips) {
+              const int64_t q0 = H->h_ins[i].lam_off + (int64_t)j * nq;
+              cq.push_back(CGCol{q0, -1, q0});
+            }
+          emit(d.Kinv + (size_t)c * nq * nq, nq, nq, nq, nq, 0, cq, out[1]);
+        }
+      }
+    };
+    for (int si = 0; si < (int)H->sys.size(); ++si) items(si, si * H->nrhs, (si + 1) * H->nrhs, all);
+    for (int i = 0; i < H->ninst; ++i) {
+      int st0[3][2];
+      for (int k = 0; k < 3; ++k)
+        for (int w = 0; w < 2; ++w) st0[k][w] = (int)one[k][w].size();
+      items(H->h_ins[i].sys, i, i + 1, one);
+      for (int k = 0; k < 3; ++k)
+        for (int w = 0; w < 2; ++w) {
+          H->cg_start[k][w].push_back(st0[k][w]);
+          H->cg_cnt[k][w].push_back((int)one[k][w].size() - st0[k][w]);
+        }
+    }
+    for (int k = 0; k < 3; ++k)
+      for (int w = 0; w < 2; ++w) {
+        H->cg_all[k][w] = dupload(own, all[k][w], st); H->n_cg_all[k][w] = (int)all[k][w].size();
+        H->cg_one[k][w] = dupload(own, one[k][w], st);
+      }
+    H->cg_cols = dupload(own, cols, st);
+  }
+  // MFMA GEMM items for systems with shared blocks.
+  {
+    std::vector<GWork> gS, gM, gSi, gMi;
+    std::vector<int2> gv;
+    auto emit = [&](int si, int id, int K, const std::vector<int2> &vecs, std::vector<GWork> &out) {
+      for (size_t a = 0; a < vecs.size(); a += kGemmVecs) {
+        GWork w{};
+        w.sys = si; w.id = id; w.K = K; w.vstart = (int)gv.size();
+        w.vcount = (int)std::min<size_t>(kGemmVecs, vecs.size() - a);
+        for (int q = 0; q < w.vcount; ++q) gv.push_back(vecs[a + q]);
+        out.push_back(w);
+      }
+    };
+    for (int si = 0; si < (int)H->sys.size(); ++si) {
+      const System &s = H->sys[si];
+      for (int op = 0; op < 2; ++op) {
+        const std::vector<int> &ids = op == 0 ? s.w_id : s.m_id;
+        if (!shares_blocks(ids)) continue;
+        std::map<int, std::vector<int2>> all;
+        std::vector<std::map<int, std::vector<int2>>> per(H->nrhs);
+        for (int q = 0; q < H->nrhs; ++q)
+          for (int h = 0; h < s.nh; ++h) {
+            const int2 e = make_int2(si * H->nrhs + q, h);
+            all[ids[h]].push_back(e);
+            per[q][ids[h]].push_back(e);
+          }
+        for (auto &kv : all) emit(si, kv.first, op == 0 ? 2 * s.N : s.m_K[kv.second[0].y], kv.second, op == 0 ? gS : gM);
+        for (int q = 0; q < H->nrhs; ++q) {
+          std::vector<int> &st_v = op == 0 ? H->gSi_start : H->gMi_start;
+          std::vector<int> &ct_v = op == 0 ? H->gSi_cnt : H->gMi_cnt;
+          std::vector<GWork> &dst = op == 0 ? gSi : gMi;
+          const int inst = si * H->nrhs + q;
+          if ((int)st_v.size() <= inst) { st_v.resize(inst + 1, 0); ct_v.resize(inst + 1, 0); }
+          st_v[inst] = (int)dst.size();
+          for (auto &kv : per[q]) emit(si, kv.first, op == 0 ? 2 * s.N : s.m_K[kv.second[0].y], kv.second, dst);
+          ct_v[inst] = (int)dst.size() - st_v[inst];
+        }
+      }
+    }
+    H->gSi_start.resize(H->ninst, 0); H->gSi_cnt.resize(H->ninst, 0);
+    H->gMi_start.resize(H->ninst, 0); H->gMi_cnt.resize(H->ninst, 0);
+    H->g_S = dupload(own, gS, st); H->n_gS = (int)gS.size();
+    H->g_M = dupload(own, gM, st); H->n_gM = (int)gM.size();
+    H->g_Si = dupload(own, gSi, st);
+    H->g_Mi = dupload(own, gMi, st);
+    H->g_vec = dupload(own, gv, st);
+  }
   H->d_ins = dupload(own, H->h_ins, st);
-  H->w_S = dupload(own, wS, st); H->n_S = (int)wS.size();
-  H->w_M = dupload(own, wM, st); H->n_M = (int)wM.size();
   H->w_S1 = dupload(own, wS1, st); H->n_S1 = (int)wS1.size();
   H->w_M1 = dupload(own, wM1, st); H->n_M1 = (int)wM1.size();
   H->w_h = dupload(own, wh, st); H->n_h = (int)wh.size();
-  H->w_E = dupload(own, wE, st); H->n_E = (int)wE.size();
-  H->w_E1 = dupload(own, wE1, st); H->n_E1 = (int)wE1.size();
   H->w_x = dupload(own, wx, st); H->n_x = (int)wx.size();
   H->w_r = dupload(own, wr, st); H->n_r = (int)wr.size();
   H->w_s = dupload(own, ws, st); H->n_s = (int)ws.size();
@@ -300,7 +416,7 @@ void upload(smpm_handle *H, hipStream_t st) {
   H->cv = dalloc<double>(own, c_off); H->tb = dalloc<double>(own, c_off);
   H->scale = dalloc<double>(own, st_off); H->cs = dalloc<double>(own, st_off); H->sn = dalloc<double>(own, st_off);
   H->g = dalloc<double>(own, st_off); H->ycoef = dalloc<double>(own, st_off); H->Rm = dalloc<double>(own, rr_off);
-  H->lam = dalloc<double>(own, lam_off);
+  H->lam = dalloc<double>(own, lam_off); H->qb = dalloc<double>(own, lam_off);
   H->defect = dalloc<double>(own, H->ninst); H->pairs = dalloc<double>(own, 2 * H->ninst);
   H->gs = dalloc<GState>(own, H->ninst);
   HIPCHECK(hipHostMalloc((void **)&H->h_gs, sizeof(GState) * H->ninst, hipHostMallocDefault));
@@ -319,19 +435,22 @@ template <typename TO, typename TX, typename TY>
 void gemv(smpm_handle *H, int op, const TX *x, int vslot, const double *scale, TY *y, double *hsum,
           const GState *gs, hipStream_t st, int inst = -1) {
   const int Kmax = (op == 0 ? 2 : 4) * H->Nmax;
-  // halves with a shared block: grouped kernel
+  // halves with a shared block: MFMA GEMM over the windows that share it
   {
-    const HWork *w = op == 0 ? H->w_S : H->w_M;
-    int count = op == 0 ? H->n_S : H->n_M;
+    const GWork *w = op == 0 ? H->g_S : H->g_M;
+    int count = op == 0 ? H->n_gS : H->n_gM;
     if (inst >= 0) {
-      w += op == 0 ? H->S_start[inst] : H->M_start[inst];
-      count = op == 0 ? H->S_cnt[inst] : H->M_cnt[inst];
+      w = (op == 0 ? H->g_Si : H->g_Mi) + (op == 0 ? H->gSi_start[inst] : H->gMi_start[inst]);
+      count = op == 0 ? H->gSi_cnt[inst] : H->gMi_cnt[inst];
     }
     if (count > 0) {
-      const int tiles = (H->Nmax + 63) / 64;
-      const size_t shm = sizeof(double) * kGroup * (Kmax + kWaves * 64);
-      hipLaunchKernelGGL((k_half_gemv<TO, TX, TY, kGroup, kWaves>), dim3(count, tiles), dim3(64 * kWaves), shm, st,
-                         H->d_sys, H->d_ins, w, op, x, vslot, scale, y, hsum, gs);
+      const int rtiles = (H->Nmax + 15) / 16;
+      if ((int64_t)count * rtiles < 2048)
+        hipLaunchKernelGGL((k_half_gemm<TO, TX, TY, 1>), dim3(count, rtiles), dim3(512), 0, st, H->d_sys, H->d_ins,
+                           w, (const int2 *)H->g_vec, op, x, vslot, scale, y, hsum, gs);
+      else
+        hipLaunchKernelGGL((k_half_gemm<TO, TX, TY, 2>), dim3(count, (rtiles + 1) / 2), dim3(512), 0, st, H->d_sys,
+                           H->d_ins, w, (const int2 *)H->g_vec, op, x, vslot, scale, y, hsum, gs);
     }
   }
   // halves with their own block: streaming kernel
@@ -352,36 +471,44 @@ void gemv(smpm_handle *H, int op, const TX *x, int vslot, const double *scale, T
   }
 }
 
-// dst = A(k)^-1 src (node space; src may alias dst): element solves, the
-// per-strip z-interface capacitance solve, element corrections.
+// dst = A(k)^-1 src (node space; src and dst must not overlap): element
+// solves, the per-strip z-interface capacitance solve, element corrections.
+template <int CT>
+void colgemm_w(smpm_handle *H, const CGItem *items, int count, int mode, const double *x, double *y, hipStream_t st) {
+  if (count <= 0) return;
+  const int rmax = std::max(H->n2_max, H->nq_max);
+  const int rt16 = (rmax + 15) / 16;
+  if ((int64_t)count * rt16 < 1024) {     // few items: split K for parallelism
+    const dim3 grid(count, rt16);
+    if (mode == 0) hipLaunchKernelGGL((k_colgemm<CT, 0>), grid, dim3(512), 0, st, items, H->cg_cols, x, y);
+    else hipLaunchKernelGGL((k_colgemm<CT, 1>), grid, dim3(512), 0, st, items, H->cg_cols, x, y);
+  } else {
+    const dim3 grid(count, (rmax + 63) / 64);
+    if (mode == 0) hipLaunchKernelGGL((k_colgemm_t<CT, 0>), grid, dim3(256), 0, st, items, H->cg_cols, x, y);
+    else hipLaunchKernelGGL((k_colgemm_t<CT, 1>), grid, dim3(256), 0, st, items, H->cg_cols, x, y);
+  }
+}
+
+// One element-interior product (kind 0, 1, 2) over all instances or one.
+void colgemm(smpm_handle *H, int kind, int inst, int mode, const double *x, double *y, hipStream_t st) {
+  for (int w = 0; w < 2; ++w) {
+    const CGItem *it = inst >= 0 ? H->cg_one[kind][w] + H->cg_start[kind][w][inst] : H->cg_all[kind][w];
+    const int cnt = inst >= 0 ? H->cg_cnt[kind][w][inst] : H->n_cg_all[kind][w];
+    if (w == 0) colgemm_w<1>(H, it, cnt, mode, x, y, st);
+    else colgemm_w<kColVecs / 16>(H, it, cnt, mode, x, y, st);
+  }
+}
+
+// dst = A(k)^-1 src (node space; src and dst must not overlap): element
+// solves, the per-strip z-interface capacitance solve, element corrections.
 void ainv(smpm_handle *H, const double *src, double *dst, hipStream_t st, int inst = -1) {
-  const int4 *w = H->w_E + (inst >= 0 ? H->E_start[inst] : 0);
-  const int count = inst >= 0 ? H->E_cnt[inst] : H->n_E;
-  const int4 *w1 = H->w_E1 + (inst >= 0 ? H->E1_start[inst] : 0);
-  const int count1 = inst >= 0 ? H->E1_cnt[inst] : H->n_E1;
-  const int rtiles = (H->n2_max + 63) / 64;
-  if (count > 0) {
-    const size_t shm1 = sizeof(double) * kStripsPerGroup * (H->n2_max + kWaves * 64);
-    hipLaunchKernelGGL((k_elem_solve<kStripsPerGroup, kWaves>), dim3(count, rtiles), dim3(64 * kWaves), shm1, st,
-                       H->d_sys, H->d_ins, w, src, dst);
-  }
-  if (count1 > 0) {
-    const size_t shm1 = sizeof(double) * (H->n2_max + kWaves * 64);
-    hipLaunchKernelGGL((k_elem_solve<1, kWaves>), dim3(count1, rtiles), dim3(64 * kWaves), shm1, st, H->d_sys, H->d_ins,
-                       w1, src, dst);
-  }
+  colgemm(H, 0, inst, 0, src, dst, st);
   if (H->nq_max > 0) {
     const int2 *ws = H->w_s + (inst >= 0 ? H->s_start[inst] : 0);
     const int scount = inst >= 0 ? H->sys[H->h_ins[inst].sys].mx : H->n_s;
-    const size_t shm2 = sizeof(double) * (H->nq_max + kWaves * 64);
-    hipLaunchKernelGGL((k_strip_q<kWaves>), dim3(scount, (H->nq_max + 63) / 64), dim3(64 * kWaves), shm2, st, H->d_sys,
-                       H->d_ins, ws, (const double *)dst, H->lam);
-    if (count > 0)
-      hipLaunchKernelGGL(k_elem_correct<kStripsPerGroup>, dim3(count, rtiles), dim3(kBlock), 0, st, H->d_sys, H->d_ins, w,
-                         dst, (const double *)H->lam);
-    if (count1 > 0)
-      hipLaunchKernelGGL(k_elem_correct<1>, dim3(count1, rtiles), dim3(kBlock), 0, st, H->d_sys, H->d_ins, w1, dst,
-                         (const double *)H->lam);
+    hipLaunchKernelGGL(k_lambda, dim3(scount), dim3(kBlock), 0, st, H->d_sys, H->d_ins, ws, (const double *)dst, H->lam);
+    colgemm(H, 1, inst, 0, H->lam, H->qb, st);
+    colgemm(H, 2, inst, 1, H->qb, dst, st);
   }
 }
 
