@@ -77,6 +77,37 @@ def matvec_bytes(solver, s_op, s_vec):
     return tot
 
 
+def matvec_flops(solver):
+    """Algorithmic flops of one batched Schur matvec: y_h = x_h + W_h x_win
+    for every half of every instance (2 N x 2N per half, plus the identity)."""
+    tot = 0
+    for info in solver.info:
+        N = info["n"] * info["mz"]
+        nh = 2 * (info["mx"] - 1)
+        tot += (2 * nh * N * 2 * N + info["kS"]) * info["nrhs"]
+    return tot
+
+
+def matvec_kernel_name(solver):
+    shared = [info["unique_W"] < 2 * (info["mx"] - 1) for info in solver.info]
+    if all(shared):
+        return "k_half_gemm<double> (MFMA, strips sharing blocks)"
+    if not any(shared):
+        return "k_half_gemv_stream<double> (distinct blocks)"
+    return "k_half_gemm<double> + k_half_gemv_stream<double>"
+
+
+# HBM-side bytes per launch of the FP64 batched Schur matvec, from two
+# rocprofv3 --pmc passes (FETCH_SIZE, WRITE_SIZE) over `bench.py --matvec-only`,
+# each scaled by the counter's reading for a 256 MiB device copy (fetch x2.000,
+# write x1.000); see profiles/c2_schur_matvec_hbm_counters.txt.  Valid only for
+# the kernel version the passes measured.
+MATVEC_TRAFFIC = {"c2": 6.418e6}
+
+PEAK_HBM_GBPS = 8000.0
+PEAK_FP64_MFMA_TFLOPS = 78.6
+
+
 def cpu_baseline(budget_s=25.0):
     """The oracle as it stands, timed on the host: setup once (reported, not
     part of the sample), then DBJ solves of the same c2 problem until ~budget_s
@@ -176,6 +207,23 @@ def main():
     gbs64 = bytes64 / (mv64_ms * 1e-3) / 1e9
     gbs32 = bytes32 / (mv32_ms * 1e-3) / 1e9
 
+    # Roofline of the dominant kernel (the FP64 batched Schur matvec): the
+    # binding roof is the one with the longer ideal time for this launch.
+    flops64 = matvec_flops(s64)
+    t_hbm = bytes64 / (PEAK_HBM_GBPS * 1e9)
+    t_mfma = flops64 / (PEAK_FP64_MFMA_TFLOPS * 1e12)
+    tflops64 = flops64 / (mv64_ms * 1e-3) / 1e12
+    if t_mfma > t_hbm:
+        roofline = {"bound": "mfma", "achieved": tflops64, "peak": PEAK_FP64_MFMA_TFLOPS, "unit": "TFLOP/s",
+                    "frac": tflops64 / PEAK_FP64_MFMA_TFLOPS}
+    else:
+        roofline = {"bound": "hbm", "achieved": gbs64, "peak": PEAK_HBM_GBPS, "unit": "GB/s",
+                    "frac": gbs64 / PEAK_HBM_GBPS}
+    roofline.update({"traffic": MATVEC_TRAFFIC.get(args.config), "kernel": matvec_kernel_name(s64),
+                     "launch_us": mv64_ms * 1e3, "algorithmic_bytes_per_launch": bytes64,
+                     "algorithmic_flops_per_launch": flops64, "achieved_GBps": gbs64,
+                     "achieved_TFLOPs": tflops64})
+
     fp64, ir = forms["fp64"], forms["fp32_ir"]
     value = fp64["stats"]["schur_matvecs"] / (fp64["ms"] * 1e-3)
     i0 = s64.info[0]
@@ -205,9 +253,7 @@ def main():
         "matvec_kernel": {"fp64_us": mv64_ms * 1e3, "fp32_us": mv32_ms * 1e3,
                           "fp64_matvecs_per_s": 1e3 / mv64_ms, "fp32_matvecs_per_s": 1e3 / mv32_ms,
                           "fp64_GBps": gbs64, "fp32_GBps": gbs32},
-        "roofline": {"bound": "hbm", "kernel": "k_half_gemv<double> (batched Schur matvec)", "achieved": gbs64,
-                     "peak": 8000.0, "unit": "GB/s", "frac": gbs64 / 8000.0, "traffic": None,
-                     "algorithmic_bytes_per_launch": bytes64},
+        "roofline": roofline,
     }
     if not args.no_cpu_baseline and args.config == "c2":
         line["cpu_baseline"] = cpu_baseline()

@@ -61,12 +61,27 @@ struct HWork {
   int h[kGroup];
 };
 
-// Work item of the shared-block GEMM: one stored block (of system sys)
-// applied to `vcount` (instance, half) windows listed from `vstart` in the
-// window table.
+// Work item of the shared-block GEMM: one stored block (N x K, column-major
+// with leading dimension Np, in both precisions) applied to `vcount`
+// (instance, half) windows listed from `vstart` in the window table.
 constexpr int kGemmVecs = 32;   // windows per workgroup
 struct GWork {
-  int sys, id, K, vstart, vcount, pad0, pad1, pad2;
+  const double *blk64;
+  const float *blk32;
+  int N, Np, K, vstart, vcount, ident;   // ident: add the identity (S = I + W)
+  int64_t kS;
+};
+// One window of a GEMM item, with every offset resolved at setup.
+struct GVec {
+  int64_t x0;     // input vector of the instance (offset of its interface vector)
+  int64_t xv;     // Krylov basis of the instance (slot 0)
+  int64_t win;    // window start inside the instance's interface vector (may be < 0)
+  int64_t xh;     // own half inside the instance's interface vector (identity term)
+  int64_t y;      // output offset
+  int inst;       // instance (GMRES state, scale)
+  int hs;         // Z^T partial sums: first 16-row slot of this half
+  int st_off;     // scale vector of the instance
+  int pad[3];
 };
 
 // Column-gather GEMM item (element-interior elimination): Y[:, c] (+)= A X[:, c]

@@ -14,10 +14,12 @@ template <typename T> struct Tab;
 template <> struct Tab<double> {
   __device__ static const double *W(const SysDev &s) { return s.W64; }
   __device__ static const double *M(const SysDev &s) { return s.M64; }
+  __device__ static const double *blk(const GWork &w) { return w.blk64; }
 };
 template <> struct Tab<float> {
   __device__ static const float *W(const SysDev &s) { return s.W32; }
   __device__ static const float *M(const SysDev &s) { return s.M32; }
+  __device__ static const float *blk(const GWork &w) { return w.blk32; }
 };
 
 __device__ inline double wave_sum(double v) {
@@ -196,11 +198,6 @@ __global__ __launch_bounds__(64 * NW) void k_half_gemv_stream(
 // N x K block (column-major, Np rows) applied to up to kGemmVecs windows at
 // once, Y = Blk X (+ the identity for S), with 16x16x4 MFMAs on two 16-window
 // column tiles.
-// Grid (item, group of RT 16-row tiles); 8 waves: RT row tiles x 8/RT parts
-// of the K dimension, whose partial tiles are summed in LDS.  The B operand
-// (the windows) is read straight from global memory, U steps of loads in
-// flight per wave; RT = 2 halves the window re-reads when the launch is
-// large, RT = 1 doubles the parallelism when it is small.
 // MFMA lane layouts (gfx950): A: lane l holds A[l % 16][l / 16];
 // B: lane l holds B[l / 16][l % 16]; D (4 values per lane):
 // FP64: D[l / 16 + 4 j][l % 16];  FP32: D[4 (l / 16) + j][l % 16].
@@ -219,58 +216,72 @@ template <> struct Mfma<float> {
   __device__ static int row(int lane, int j) { return 4 * (lane >> 4) + j; }
 };
 
-template <typename TO, typename TX, typename TY, int RT>
-__global__ __launch_bounds__(512) void k_half_gemm(
-    const SysDev *__restrict__ sys, const InstDev *__restrict__ ins, const GWork *__restrict__ work,
-    const int2 *__restrict__ gvec, int op, const TX *__restrict__ xbase, int x_vslot,
+// Per-window state shared by both GEMM schedules: resolved offsets, whether
+// the instance is still iterating, and the basis scale (applied to the
+// product in the epilogue, so the operand loads never wait for it).
+struct WinInfo {
+  int64_t xoff, win, y, xh;
+  double scale;
+  int live, hs;
+};
+
+template <int VT>
+__device__ inline void load_windows(const GWork &wk, const GVec *__restrict__ gvec, int x_vslot,
+                                    const double *__restrict__ scale, const GState *__restrict__ gs,
+                                    WinInfo *wi) {
+  if (threadIdx.x < VT) {
+    const int v = threadIdx.x;
+    WinInfo w{};
+    if (v < wk.vcount) {
+      const GVec e = gvec[wk.vstart + v];
+      int it = 0;
+      w.live = 1;
+      if (gs) {
+        const GState g = gs[e.inst];
+        w.live = g.active;
+        it = g.iter;
+      }
+      w.xoff = x_vslot ? e.xv + (int64_t)it * wk.kS : e.x0;
+      w.win = e.win;
+      w.y = e.y;
+      w.xh = e.xh;
+      w.hs = e.hs;
+      w.scale = scale ? scale[e.st_off + it] : 1.0;
+    }
+    wi[v] = w;
+  }
+}
+
+// Split-K schedule (few items): grid (item, 16-row tile), KP waves split K;
+// U K-steps of operand loads in flight per wave; partial tiles summed in LDS
+// in a fixed order.
+template <typename TO, typename TX, typename TY, int KP>
+__global__ __launch_bounds__(64 * KP) void k_half_gemm(
+    const GWork *__restrict__ work, const GVec *__restrict__ gvec, const TX *__restrict__ xbase, int x_vslot,
     const double *__restrict__ scale, TY *__restrict__ ybase, double *__restrict__ hsum,
     const GState *__restrict__ gs) {
   constexpr int VT = kGemmVecs;
-  constexpr int KP = 8 / RT;                 // waves splitting K
-  constexpr int U = 8;                       // K steps whose loads are issued together
-  __shared__ double red[KP * RT * 16 * VT];
-  __shared__ int64_t v_xoff[VT], v_win[VT], v_yoff[VT];
-  __shared__ double v_scale[VT];
-  __shared__ int v_live[VT], v_h[VT], v_hs[VT];
+  constexpr int U = KP >= 16 ? 6 : 8;        // bounded by the 128 VGPRs of a 1024-thread block
+  __shared__ double red[KP * 16 * VT];
+  __shared__ WinInfo wi[VT];
   const GWork wk = work[blockIdx.x];
-  const SysDev &S = sys[wk.sys];
-  const int N = S.N, Np = S.Np, K = wk.K;
-  const int64_t kS = S.kS;
-  const int rg = blockIdx.y;                 // group of RT 16-row tiles
-  if (rg * RT * 16 >= Np) return;
-  const int vcount = wk.vcount;
-  if (threadIdx.x < VT) {
-    const int v = threadIdx.x;
-    int live = 0;
-    if (v < vcount) {
-      const int2 e = gvec[wk.vstart + v];
-      const InstDev I = ins[e.x];
-      live = gs ? gs[e.x].active : 1;
-      const int it = gs ? gs[e.x].iter : 0;
-      v_h[v] = e.y;
-      v_hs[v] = (int)I.hs_off;
-      v_xoff[v] = x_vslot ? I.v_off + (int64_t)it * kS : I.x_off;
-      v_win[v] = (int64_t)(op == 0 ? S.w_win[e.y] : S.m_win[e.y]) * N;
-      v_yoff[v] = I.x_off + (int64_t)e.y * N;
-      v_scale[v] = scale ? scale[I.st_off + it] : 1.0;
-    }
-    v_live[v] = live;
-  }
+  const int N = wk.N, Np = wk.Np, K = wk.K;
+  const int64_t kS = wk.kS;
+  const int rt = blockIdx.y;
+  if (rt * 16 >= Np) return;
+  load_windows<VT>(wk, gvec, x_vslot, scale, gs, wi);
   __syncthreads();
   int anylive = 0;
-  for (int v = 0; v < vcount; ++v) anylive |= v_live[v];
+  for (int v = 0; v < wk.vcount; ++v) anylive |= wi[v].live;
   if (!anylive) return;
-  const TO *blk = (op == 0 ? Tab<TO>::W(S) + (size_t)wk.id * 2 * N * Np : Tab<TO>::M(S) + (size_t)wk.id * 4 * N * Np);
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int rtl = wave % RT, kp = wave / RT;
-  const int arow = (rg * RT + rtl) * 16 + (lane & 15);
+  const TO *blk = Tab<TO>::blk(wk);
+  const int kp = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int arow = rt * 16 + (lane & 15);
   const bool alive = arow < Np;
   const int kq = lane >> 4;
-  // this lane's two windows (columns of the two 16-window tiles)
   const int va = lane & 15, vb = 16 + (lane & 15);
-  const bool la = va < vcount && v_live[va], lb = vb < vcount && v_live[vb];
-  const int64_t xa = v_xoff[va], wa = v_win[va], xb = v_xoff[vb], wb = v_win[vb];
-  const double sa = v_scale[va], sb = v_scale[vb];
+  const bool la = va < wk.vcount && wi[va].live, lb = vb < wk.vcount && wi[vb].live;
+  const int64_t xa = wi[va].xoff, wa = wi[va].win, xb = wi[vb].xoff, wb = wi[vb].win;
   using Acc = typename Mfma<TO>::Acc;
   Acc acc0 = {0, 0, 0, 0}, acc1 = {0, 0, 0, 0};
   const int nsteps = (K + 3) >> 2;
@@ -283,8 +294,8 @@ __global__ __launch_bounds__(512) void k_half_gemm(
       const bool kin = st + u < s1 && k < K;
       const int64_t ga = wa + k, gb = wb + k;
       a[u] = (alive && kin) ? blk[(size_t)k * Np + arow] : (TO)0;
-      b0[u] = (la && kin && ga >= 0 && ga < kS) ? (TO)((double)xbase[xa + ga] * sa) : (TO)0;
-      b1[u] = (lb && kin && gb >= 0 && gb < kS) ? (TO)((double)xbase[xb + gb] * sb) : (TO)0;
+      b0[u] = (la && kin && ga >= 0 && ga < kS) ? (TO)xbase[xa + ga] : (TO)0;
+      b1[u] = (lb && kin && gb >= 0 && gb < kS) ? (TO)xbase[xb + gb] : (TO)0;
     }
 #pragma unroll
     for (int u = 0; u < U; ++u) {
@@ -294,40 +305,141 @@ __global__ __launch_bounds__(512) void k_half_gemm(
   }
 #pragma unroll
   for (int j = 0; j < 4; ++j) {
-    const int lr = rtl * 16 + Mfma<TO>::row(lane, j);
-    red[(kp * RT * 16 + lr) * VT + va] = (double)acc0[j];
-    red[(kp * RT * 16 + lr) * VT + vb] = (double)acc1[j];
+    const int lr = Mfma<TO>::row(lane, j);
+    red[(kp * 16 + lr) * VT + va] = (double)acc0[j];
+    red[(kp * 16 + lr) * VT + vb] = (double)acc1[j];
   }
   __syncthreads();
-  // outputs: thread -> (row, window); sum the KP partials in a fixed order
-  const int slots = (N + 15) >> 4;
-  for (int idx = threadIdx.x; idx < RT * 16 * VT; idx += 64 * RT * KP) {
+  for (int idx = threadIdx.x; idx < 16 * VT; idx += 64 * KP) {
     const int lr = idx / VT, v = idx - lr * VT;
-    const int row = rg * RT * 16 + lr;
+    const int row = rt * 16 + lr;
     double outv = 0.0;
-    if (v < vcount && v_live[v] && row < N) {
+    if (v < wk.vcount && wi[v].live && row < N) {
       TO t = (TO)red[idx];
 #pragma unroll
-      for (int q = 1; q < KP; ++q) t += (TO)red[q * RT * 16 * VT + idx];
-      double vd = (double)t;
-      if (op == 0) vd += (double)xbase[v_xoff[v] + (int64_t)v_h[v] * N + row] * v_scale[v];
-      const TY out = (TY)vd;
-      ybase[v_yoff[v] + row] = out;
+      for (int q = 1; q < KP; ++q) t += (TO)red[q * 16 * VT + idx];
+      if (wk.ident) t += (TO)xbase[wi[v].xoff + wi[v].xh + row];
+      const TY out = (TY)((double)t * wi[v].scale);
+      ybase[wi[v].y + row] = out;
       outv = (double)out;
     }
     red[idx] = outv;   // this thread's own slot of the first partial
   }
   if (hsum) {
     __syncthreads();
-    if (threadIdx.x < RT * VT) {
-      const int t = threadIdx.x / VT, v = threadIdx.x - t * VT;
-      const int slot = rg * RT + t;
-      if (v < vcount && v_live[v] && slot < slots) {
-        double acc = 0.0;
-        for (int lr = 0; lr < 16; ++lr) acc += red[(t * 16 + lr) * VT + v];
-        hsum[v_hs[v] + (int64_t)v_h[v] * slots + slot] = acc;
+    if (threadIdx.x < VT) {
+      const int v = threadIdx.x;
+      if (v < wk.vcount && wi[v].live && rt * 16 < N) {
+        double t = 0.0;
+        for (int lr = 0; lr < 16; ++lr) t += red[lr * VT + v];
+        hsum[wi[v].hs + rt] = t;
       }
     }
+  }
+}
+
+// Throughput schedule (many items): grid (item, 64-row tile), 4 waves of 16
+// rows over all of K; the windows are staged through double-buffered LDS in
+// chunks of 32 K-steps with coalesced loads while the next chunk's operands
+// are in flight.
+template <typename TO, typename TX, typename TY>
+__global__ __launch_bounds__(256) void k_half_gemm_t(
+    const GWork *__restrict__ work, const GVec *__restrict__ gvec, const TX *__restrict__ xbase, int x_vslot,
+    const double *__restrict__ scale, TY *__restrict__ ybase, double *__restrict__ hsum,
+    const GState *__restrict__ gs) {
+  constexpr int VT = kGemmVecs, KC = 32, PITCH = VT + 1;
+  constexpr int PV = KC * VT / 256;      // staged values per thread per chunk
+  constexpr int TPC = KC / PV;           // threads per window
+  __shared__ TO Bs[2][KC * PITCH];
+  __shared__ WinInfo wi[VT];
+  const GWork wk = work[blockIdx.x];
+  const int N = wk.N, Np = wk.Np, K = wk.K;
+  const int64_t kS = wk.kS;
+  const int rg = blockIdx.y;
+  if (rg * 64 >= Np) return;
+  load_windows<VT>(wk, gvec, x_vslot, scale, gs, wi);
+  __syncthreads();
+  int anylive = 0;
+  for (int v = 0; v < wk.vcount; ++v) anylive |= wi[v].live;
+  if (!anylive) return;
+  const TO *__restrict__ blk = Tab<TO>::blk(wk);
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int arow = rg * 64 + wave * 16 + (lane & 15);
+  const bool alive = arow < Np;
+  const int kq = lane >> 4, cl = lane & 15;
+  const int scol = threadIdx.x / TPC, sk0 = (threadIdx.x % TPC) * PV;
+  const bool slive = scol < wk.vcount && wi[scol].live;
+  const int64_t sx = wi[scol].xoff, sw = wi[scol].win;
+  TO pre[PV];
+  TO a[KC / 4], an[KC / 4];
+  auto load_b = [&](int kc) {
+#pragma unroll
+    for (int p = 0; p < PV; ++p) {
+      const int k = kc * KC + sk0 + p;
+      const int64_t g = sw + k;
+      pre[p] = (slive && k < K && g >= 0 && g < kS) ? (TO)xbase[sx + g] : (TO)0;
+    }
+  };
+  auto load_a = [&](int kc, TO *dst) {
+#pragma unroll
+    for (int s = 0; s < KC / 4; ++s) {
+      const int k = kc * KC + 4 * s + kq;
+      dst[s] = (alive && k < K) ? blk[(size_t)k * Np + arow] : (TO)0;
+    }
+  };
+  auto store_b = [&](int buf) {
+#pragma unroll
+    for (int p = 0; p < PV; ++p) Bs[buf][(sk0 + p) * PITCH + scol] = pre[p];
+  };
+  using Acc = typename Mfma<TO>::Acc;
+  Acc acc0 = {0, 0, 0, 0}, acc1 = {0, 0, 0, 0};
+  const int nchunks = (K + KC - 1) / KC;
+  load_b(0);
+  load_a(0, a);
+  store_b(0);
+  __syncthreads();
+  for (int kc = 0; kc < nchunks; ++kc) {
+    const int buf = kc & 1;
+    const bool more = kc + 1 < nchunks;
+    if (more) {
+      load_b(kc + 1);
+      load_a(kc + 1, an);
+    }
+    const TO *__restrict__ B = Bs[buf];
+#pragma unroll
+    for (int s = 0; s < KC / 4; ++s) {
+      acc0 = Mfma<TO>::mac(a[s], B[(4 * s + kq) * PITCH + cl], acc0);
+      acc1 = Mfma<TO>::mac(a[s], B[(4 * s + kq) * PITCH + 16 + cl], acc1);
+    }
+    if (more) {
+      store_b(buf ^ 1);
+#pragma unroll
+      for (int s = 0; s < KC / 4; ++s) a[s] = an[s];
+    }
+    __syncthreads();
+  }
+  // epilogue: lane holds rows Mfma::row(lane, j) of windows cl and 16 + cl
+  const int slot = rg * 4 + wave;
+#pragma unroll
+  for (int t = 0; t < 2; ++t) {
+    const int v = t * 16 + cl;
+    const bool ok = v < wk.vcount && wi[v].live;
+    double part = 0.0;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int row = rg * 64 + wave * 16 + Mfma<TO>::row(lane, j);
+      if (ok && row < N) {
+        TO val = t == 0 ? acc0[j] : acc1[j];
+        if (wk.ident) val += (TO)xbase[wi[v].xoff + wi[v].xh + row];
+        const TY out = (TY)((double)val * wi[v].scale);
+        ybase[wi[v].y + row] = out;
+        part += (double)out;
+      }
+    }
+    // sum the 16 rows of this wave's slot: lanes cl, cl + 16, cl + 32, cl + 48
+    part += __shfl_xor(part, 16, 64);
+    part += __shfl_xor(part, 32, 64);
+    if (hsum && ok && kq == 0 && slot * 16 < N) hsum[wi[v].hs + slot] = part;
   }
 }
 
@@ -1219,6 +1331,12 @@ __global__ __launch_bounds__(kBlock) void k_reduce_pairs(const InstDev *__restri
   __syncthreads();
   b = block_sum(b, lds4);
   if (threadIdx.x == 0) { out[2 * i] = a; out[2 * i + 1] = b; }
+}
+
+// p[0, n) = v.
+__global__ __launch_bounds__(kBlock) void k_fill(double *__restrict__ p, int64_t n, double v) {
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i < n) p[i] = v;
 }
 
 // r <- r - u_S (u_S . r) using a reduced scalar (refinement residual).

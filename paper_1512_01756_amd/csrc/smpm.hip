@@ -103,7 +103,7 @@ struct smpm_handle {
   // grouped by block id across all instances of a system (batched launches),
   // and within one instance (single-system applies).
   GWork *g_S = nullptr, *g_M = nullptr, *g_Si = nullptr, *g_Mi = nullptr;
-  int2 *g_vec = nullptr;
+  GVec *g_vec = nullptr;
   int n_gS = 0, n_gM = 0;
   std::vector<int> gSi_start, gSi_cnt, gMi_start, gMi_cnt;
   HWork *w_S1 = nullptr, *w_M1 = nullptr;   // single items (streamed blocks)
@@ -138,11 +138,23 @@ struct smpm_handle {
   // captured graph of kIterChunk iterations per precision.
   hipStream_t ws = nullptr;
   hipEvent_t ev_in = nullptr, ev_out = nullptr;
-  hipGraphExec_t loop64 = nullptr, loop32 = nullptr;
+  // Captured graphs, index [0] FP64 inner solve, [1] FP32 inner solve:
+  // before the Krylov loop, kIterChunk iterations, after the loop.  The
+  // staging graph is keyed by the caller's f and g, the recovery graph by u.
+  hipGraphExec_t g_pre[2] = {}, g_loop[2] = {}, g_post[2] = {};
+  hipGraphExec_t g_resid = nullptr, g_stage = nullptr, g_finish = nullptr;
+  const void *stage_f = nullptr, *stage_g = nullptr;
+  void *fin_u = nullptr;
+  // Iteration chunks launched before the first convergence check, from the
+  // previous solve's iteration count.
+  int pred_chunks[2] = {1, 1};
+  GState *h_gs_hist = nullptr;   // pinned, [sweep][instance]
+  double *h_nb = nullptr;        // pinned, ||b~||^2 and u_S . b~ per instance
 
   ~smpm_handle() {
-    if (loop64) (void)hipGraphExecDestroy(loop64);
-    if (loop32) (void)hipGraphExecDestroy(loop32);
+    for (hipGraphExec_t *e : {&g_pre[0], &g_pre[1], &g_loop[0], &g_loop[1], &g_post[0], &g_post[1], &g_resid,
+                              &g_stage, &g_finish})
+      if (*e) (void)hipGraphExecDestroy(*e);
     if (ev_in) (void)hipEventDestroy(ev_in);
     if (ev_out) (void)hipEventDestroy(ev_out);
     if (ws) (void)hipStreamDestroy(ws);
@@ -150,6 +162,8 @@ struct smpm_handle {
     if (h_gs) (void)hipHostFree(h_gs);
     if (h_pairs) (void)hipHostFree(h_pairs);
     if (h_defect) (void)hipHostFree(h_defect);
+    if (h_gs_hist) (void)hipHostFree(h_gs_hist);
+    if (h_nb) (void)hipHostFree(h_nb);
   }
 };
 
@@ -354,13 +368,32 @@ void upload(smpm_handle *H, hipStream_t st) {
   // MFMA GEMM items for systems with shared blocks.
   {
     std::vector<GWork> gS, gM, gSi, gMi;
-    std::vector<int2> gv;
-    auto emit = [&](int si, int id, int K, const std::vector<int2> &vecs, std::vector<GWork> &out) {
+    std::vector<GVec> gv;
+    auto emit = [&](int si, int op, int id, const std::vector<int2> &vecs, std::vector<GWork> &out) {
+      const System &s = H->sys[si];
+      const SysDev &d = H->h_sys[si];
+      const int N = s.N, slots = (N + 15) / 16;
+      const int K = op == 0 ? 2 * N : s.m_K[vecs[0].y];
       for (size_t a = 0; a < vecs.size(); a += kGemmVecs) {
         GWork w{};
-        w.sys = si; w.id = id; w.K = K; w.vstart = (int)gv.size();
+        w.blk64 = (op == 0 ? d.W64 : d.M64) + (size_t)id * (op == 0 ? 2 : 4) * N * d.Np;
+        w.blk32 = (op == 0 ? d.W32 : d.M32) + (size_t)id * (op == 0 ? 2 : 4) * N * d.Np;
+        w.N = N; w.Np = d.Np; w.K = K; w.kS = s.kS; w.ident = op == 0 ? 1 : 0;
+        w.vstart = (int)gv.size();
         w.vcount = (int)std::min<size_t>(kGemmVecs, vecs.size() - a);
-        for (int q = 0; q < w.vcount; ++q) gv.push_back(vecs[a + q]);
+        for (int q = 0; q < w.vcount; ++q) {
+          const int inst = vecs[a + q].x, h = vecs[a + q].y;
+          const InstDev &I = H->h_ins[inst];
+          GVec e{};
+          e.x0 = I.x_off; e.xv = I.v_off;
+          e.win = (int64_t)(op == 0 ? s.w_win[h] : s.m_win[h]) * N;
+          e.xh = (int64_t)h * N;
+          e.y = I.x_off + (int64_t)h * N;
+          e.inst = inst;
+          e.hs = (int)(I.hs_off + (int64_t)h * slots);
+          e.st_off = (int)I.st_off;
+          gv.push_back(e);
+        }
         out.push_back(w);
       }
     };
@@ -377,7 +410,7 @@ void upload(smpm_handle *H, hipStream_t st) {
             all[ids[h]].push_back(e);
             per[q][ids[h]].push_back(e);
           }
-        for (auto &kv : all) emit(si, kv.first, op == 0 ? 2 * s.N : s.m_K[kv.second[0].y], kv.second, op == 0 ? gS : gM);
+        for (auto &kv : all) emit(si, op, kv.first, kv.second, op == 0 ? gS : gM);
         for (int q = 0; q < H->nrhs; ++q) {
           std::vector<int> &st_v = op == 0 ? H->gSi_start : H->gMi_start;
           std::vector<int> &ct_v = op == 0 ? H->gSi_cnt : H->gMi_cnt;
@@ -385,7 +418,7 @@ void upload(smpm_handle *H, hipStream_t st) {
           const int inst = si * H->nrhs + q;
           if ((int)st_v.size() <= inst) { st_v.resize(inst + 1, 0); ct_v.resize(inst + 1, 0); }
           st_v[inst] = (int)dst.size();
-          for (auto &kv : per[q]) emit(si, kv.first, op == 0 ? 2 * s.N : s.m_K[kv.second[0].y], kv.second, dst);
+          for (auto &kv : per[q]) emit(si, op, kv.first, kv.second, dst);
           ct_v[inst] = (int)dst.size() - st_v[inst];
         }
       }
@@ -422,6 +455,9 @@ void upload(smpm_handle *H, hipStream_t st) {
   HIPCHECK(hipHostMalloc((void **)&H->h_gs, sizeof(GState) * H->ninst, hipHostMallocDefault));
   HIPCHECK(hipHostMalloc((void **)&H->h_pairs, sizeof(double) * 2 * H->ninst, hipHostMallocDefault));
   HIPCHECK(hipHostMalloc((void **)&H->h_defect, sizeof(double) * H->ninst, hipHostMallocDefault));
+  HIPCHECK(hipHostMalloc((void **)&H->h_gs_hist, sizeof(GState) * H->ninst * (H->max_sweeps + 1),
+                         hipHostMallocDefault));
+  HIPCHECK(hipHostMalloc((void **)&H->h_nb, sizeof(double) * 2 * H->ninst, hipHostMallocDefault));
   HIPCHECK(hipStreamCreateWithFlags(&H->ws, hipStreamNonBlocking));
   HIPCHECK(hipEventCreateWithFlags(&H->ev_in, hipEventDisableTiming));
   HIPCHECK(hipEventCreateWithFlags(&H->ev_out, hipEventDisableTiming));
@@ -444,13 +480,16 @@ void gemv(smpm_handle *H, int op, const TX *x, int vslot, const double *scale, T
       count = op == 0 ? H->gSi_cnt[inst] : H->gMi_cnt[inst];
     }
     if (count > 0) {
-      const int rtiles = (H->Nmax + 15) / 16;
-      if ((int64_t)count * rtiles < 2048)
-        hipLaunchKernelGGL((k_half_gemm<TO, TX, TY, 1>), dim3(count, rtiles), dim3(512), 0, st, H->d_sys, H->d_ins,
-                           w, (const int2 *)H->g_vec, op, x, vslot, scale, y, hsum, gs);
+      const int rt16 = (H->Nmax + 15) / 16;
+      if ((int64_t)count * rt16 < 512)     // few items: split K over 16 waves
+        hipLaunchKernelGGL((k_half_gemm<TO, TX, TY, 16>), dim3(count, rt16), dim3(1024), 0, st, w, H->g_vec, x, vslot,
+                           scale, y, hsum, gs);
+      else if ((int64_t)count * rt16 < 2048)
+        hipLaunchKernelGGL((k_half_gemm<TO, TX, TY, 8>), dim3(count, rt16), dim3(512), 0, st, w, H->g_vec, x, vslot,
+                           scale, y, hsum, gs);
       else
-        hipLaunchKernelGGL((k_half_gemm<TO, TX, TY, 2>), dim3(count, (rtiles + 1) / 2), dim3(512), 0, st, H->d_sys,
-                           H->d_ins, w, (const int2 *)H->g_vec, op, x, vslot, scale, y, hsum, gs);
+        hipLaunchKernelGGL((k_half_gemm_t<TO, TX, TY>), dim3(count, (H->Nmax + 63) / 64), dim3(256), 0, st, w, H->g_vec,
+                           x, vslot, scale, y, hsum, gs);
     }
   }
   // halves with their own block: streaming kernel
@@ -527,16 +566,6 @@ const int2 *hwork(smpm_handle *H, int inst, int &count) {
 // ---------------------------------------------------------------------------
 // Solve steps.
 
-// Steps 1-3 of Algorithm 2: F = f + tau g, F~ = F - u_L u_L^T F, v = A^-1 F~,
-// b~ = B v - u_S u_S^T B v.
-void stage_rhs(smpm_handle *H, const double *f, const double *g, hipStream_t st) {
-  hipLaunchKernelGGL(k_rhs, dim3(H->n_r), dim3(kBlock), 0, st, H->d_sys, H->d_ins, H->w_r, f, g, H->F, H->pr);
-  hipLaunchKernelGGL(k_proj_r, dim3(H->n_r), dim3(kBlock), 0, st, H->d_sys, H->d_ins, H->w_r, H->F, H->pr, H->defect);
-  ainv(H, H->F, H->v, st);
-  hipLaunchKernelGGL(k_bS, dim3(H->n_h), dim3(kBlock), 0, st, H->d_sys, H->d_ins, H->w_h, (const double *)H->v, H->bS, H->hs);
-  hipLaunchKernelGGL(k_proj_x, dim3(H->n_x), dim3(kBlock), 0, st, H->d_sys, H->d_ins, H->w_x, H->bS, (const double *)H->hs);
-}
-
 bool any_active(smpm_handle *H, hipStream_t st) {
   HIPCHECK(hipMemcpyAsync(H->h_gs, H->gs, sizeof(GState) * H->ninst, hipMemcpyDeviceToHost, st));
   HIPCHECK(hipStreamSynchronize(st));
@@ -545,122 +574,159 @@ bool any_active(smpm_handle *H, hipStream_t st) {
   return false;
 }
 
-struct InnerStats {
-  int64_t iters = 0;
-  int iters_max = 0;
-  int matvecs = 0;
-  bool nonfinite = false;
-  bool notconv = false;
-};
-
-// Inner DBJ-GMRES (or BJ / Schur) on right-hand side b (FP64, interface
-// space), operators and Krylov basis in precision T.  The stopping test is
-// |g| <= tol * sqrt(pairs[2 i]) (the caller leaves ||b||^2 there).
-// accumulate = 0: out = x;  1: out += x.
-template <typename T>
-InnerStats inner_solve(smpm_handle *H, const double *b, double *out, int accumulate, double tol, hipStream_t st) {
-  InnerStats is;
-  T *V = nullptr, *z = nullptr, *y = nullptr, *t = nullptr;
-  if constexpr (sizeof(T) == 8) { V = (T *)H->V64; z = (T *)H->z64; y = (T *)H->y64; t = (T *)H->t64; }
-  else { V = (T *)H->V32; z = (T *)H->z32; y = (T *)H->y32; t = (T *)H->t32; }
-  const bool useM = H->method != SMPM_METHOD_SCHUR;
-  const bool useP = H->method == SMPM_METHOD_DBJ;
-  const int maxit = H->maxit;
-  const size_t shm_dot = sizeof(double) * (maxit + 1) * 5;
-  if (useP) {   // coarse part: c = G Z^T b (kept as t_b = Z^T b for the final assembly)
-    hipLaunchKernelGGL(k_halfsum, dim3(H->n_h), dim3(kBlock), 0, st, H->d_sys, H->d_ins, H->w_h, b, H->hs, (double *)nullptr);
-    hipLaunchKernelGGL(k_coarse, dim3(H->ninst), dim3(kBlock), 0, st, H->d_sys, H->d_ins, (const double *)H->hs,
-                       (const double *)nullptr, H->tb, H->cv, (const GState *)nullptr);
+// Capture the work that body() enqueues on st into an executable graph.
+template <typename F>
+hipGraphExec_t capture(hipStream_t st, F &&body) {
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  HIPCHECK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+  try {
+    body();
+  } catch (...) {
+    (void)hipStreamEndCapture(st, &graph);
+    if (graph) (void)hipGraphDestroy(graph);
+    throw;
   }
-  hipLaunchKernelGGL(k_init_basis<T>, dim3(H->n_x), dim3(kBlock), 0, st, H->d_sys, H->d_ins, H->w_x, b,
-                     useP ? (const double *)H->cv : (const double *)nullptr, V, H->partn);
-  hipLaunchKernelGGL(k_gmres_start, dim3(H->ninst), dim3(kBlock), 0, st, H->d_ins, (const double *)H->partn,
-                     (const double *)H->pairs, H->scale, H->g, H->gs, 1);
-  auto one_iteration = [&]() {
+  HIPCHECK(hipStreamEndCapture(st, &graph));
+  const hipError_t e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(graph);
+  if (e != hipSuccess) throw std::runtime_error("hipGraphInstantiate failed");
+  return exec;
+}
+
+// Inner DBJ-GMRES (or BJ / Schur), operators and Krylov basis in precision T.
+// FP64: b = b~, x_S = x.  FP32: b = the refinement residual, x_S += x.  The
+// stopping test is |g| <= tol * sqrt(pairs[2 i]) (||b||^2, left by the
+// preceding norm or residual step).
+template <typename T>
+struct Inner {
+  static constexpr int P = sizeof(T) == 8 ? 0 : 1;
+  static T *V(smpm_handle *H) { if constexpr (P == 0) return (T *)H->V64; else return (T *)H->V32; }
+  static T *z(smpm_handle *H) { if constexpr (P == 0) return (T *)H->z64; else return (T *)H->z32; }
+  static T *y(smpm_handle *H) { if constexpr (P == 0) return (T *)H->y64; else return (T *)H->y32; }
+  static T *t(smpm_handle *H) { if constexpr (P == 0) return (T *)H->t64; else return (T *)H->t32; }
+  static const double *b(smpm_handle *H) { return P == 0 ? H->bS : H->rb; }
+  static double tol(smpm_handle *H) { return P == 0 ? H->tol : H->inner_tol; }
+
+  // coarse part c = G Z^T b (kept as t_b = Z^T b for the assembly), r0 = P b
+  static void pre(smpm_handle *H, hipStream_t st) {
+    const bool useP = H->method == SMPM_METHOD_DBJ;
+    if (useP) {
+      hipLaunchKernelGGL(k_halfsum, dim3(H->n_h), dim3(kBlock), 0, st, H->d_sys, H->d_ins, H->w_h, b(H), H->hs,
+                         (double *)nullptr);
+      hipLaunchKernelGGL(k_coarse, dim3(H->ninst), dim3(kBlock), 0, st, H->d_sys, H->d_ins, (const double *)H->hs,
+                         (const double *)nullptr, H->tb, H->cv, (const GState *)nullptr);
+    }
+    hipLaunchKernelGGL(k_init_basis<T>, dim3(H->n_x), dim3(kBlock), 0, st, H->d_sys, H->d_ins, H->w_x, b(H),
+                       useP ? (const double *)H->cv : (const double *)nullptr, V(H), H->partn);
+    hipLaunchKernelGGL(k_gmres_start, dim3(H->ninst), dim3(kBlock), 0, st, H->d_ins, (const double *)H->partn,
+                       (const double *)H->pairs, H->scale, H->g, H->gs, 1);
+  }
+
+  static void iteration(smpm_handle *H, hipStream_t st) {
+    const bool useM = H->method != SMPM_METHOD_SCHUR;
+    const bool useP = H->method == SMPM_METHOD_DBJ;
+    const int maxit = H->maxit;
+    const size_t shm_dot = sizeof(double) * (maxit + 1) * 5;
+    T *Vb = V(H), *zb = z(H), *yb = y(H);
     if (useM) {
-      gemv<T, T, T>(H, 1, (const T *)V, 1, H->scale, z, nullptr, H->gs, st);
-      gemv<T, T, T>(H, 0, (const T *)z, 0, nullptr, y, useP ? H->hs : nullptr, H->gs, st);
+      gemv<T, T, T>(H, 1, (const T *)Vb, 1, H->scale, zb, nullptr, H->gs, st);
+      gemv<T, T, T>(H, 0, (const T *)zb, 0, nullptr, yb, useP ? H->hs : nullptr, H->gs, st);
     } else {
-      gemv<T, T, T>(H, 0, (const T *)V, 1, H->scale, y, useP ? H->hs : nullptr, H->gs, st);
+      gemv<T, T, T>(H, 0, (const T *)Vb, 1, H->scale, yb, useP ? H->hs : nullptr, H->gs, st);
     }
     hipLaunchKernelGGL((k_pcorr_dot<T, T>), dim3(H->n_x), dim3(kBlock), sizeof(double) * (maxit + 1) * 4, st, H->d_sys,
-                       H->d_ins, H->w_x, (const T *)y, (const double *)H->hs, useP ? 1 : 0, V, H->part1,
+                       H->d_ins, H->w_x, (const T *)yb, (const double *)H->hs, useP ? 1 : 0, Vb, H->part1,
                        (const GState *)H->gs, maxit);
-    hipLaunchKernelGGL((k_axpy_dot<T>), dim3(H->n_x), dim3(kBlock), shm_dot, st, H->d_sys, H->d_ins, H->w_x, V,
+    hipLaunchKernelGGL((k_axpy_dot<T>), dim3(H->n_x), dim3(kBlock), shm_dot, st, H->d_sys, H->d_ins, H->w_x, Vb,
                        (const double *)H->part1, H->part2, (double *)nullptr, (const double *)H->scale, (const GState *)H->gs);
-    hipLaunchKernelGGL((k_axpy_dot<T>), dim3(H->n_x), dim3(kBlock), shm_dot, st, H->d_sys, H->d_ins, H->w_x, V,
+    hipLaunchKernelGGL((k_axpy_dot<T>), dim3(H->n_x), dim3(kBlock), shm_dot, st, H->d_sys, H->d_ins, H->w_x, Vb,
                        (const double *)H->part2, (double *)nullptr, H->partn, (const double *)H->scale, (const GState *)H->gs);
     hipLaunchKernelGGL(k_givens, dim3(H->ninst), dim3(kBlock), sizeof(double) * (maxit + 2), st, H->d_ins,
                        (const double *)H->part1, (const double *)H->part2, (const double *)H->partn, H->scale, H->Rm,
-                       H->cs, H->sn, H->g, H->gs, maxit, tol);
-  };
-  hipGraphExec_t &exec = sizeof(T) == 8 ? H->loop64 : H->loop32;
-  if (!exec) {
-    hipGraph_t graph = nullptr;
-    HIPCHECK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
-    for (int c = 0; c < kIterChunk; ++c) one_iteration();
-    HIPCHECK(hipStreamEndCapture(st, &graph));
-    HIPCHECK(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
-    HIPCHECK(hipGraphDestroy(graph));
+                       H->cs, H->sn, H->g, H->gs, maxit, tol(H));
   }
-  for (int it = 0; it < maxit; it += kIterChunk) {
-    HIPCHECK(hipGraphLaunch(exec, st));
-    if (!any_active(H, st)) break;
-  }
-  HIPCHECK(hipGetLastError());
-  // x' = V y; x = M^-1 x' + coarse part
-  hipLaunchKernelGGL(k_backsolve, dim3(H->ninst), dim3(kBlock), sizeof(double) * (maxit + 1), st, H->d_ins,
-                     (const double *)H->Rm, (const double *)H->g, (const double *)H->scale, H->ycoef, (const GState *)H->gs, maxit);
-  hipLaunchKernelGGL((k_combine<T, T>), dim3(H->n_x), dim3(kBlock), 0, st, H->d_sys, H->d_ins, H->w_x, (const T *)V,
-                     (const double *)H->ycoef, t, (const GState *)H->gs);
-  const T *xfin = t;
-  if (useM) {
-    gemv<T, T, T>(H, 1, (const T *)t, 0, nullptr, z, nullptr, nullptr, st);
-    xfin = z;
-  }
-  const double *cfin = nullptr;
-  if (useP) {   // c' = G (Z^T b - Z^T S z): x = z + Z c'
-    gemv<T, T, T>(H, 0, (const T *)z, 0, nullptr, y, H->hs, nullptr, st);
-    hipLaunchKernelGGL(k_coarse, dim3(H->ninst), dim3(kBlock), 0, st, H->d_sys, H->d_ins, (const double *)H->hs,
-                       (const double *)H->tb, (double *)nullptr, H->cv, (const GState *)nullptr);
-    cfin = H->cv;
-    is.matvecs += H->ninst;
-  }
-  hipLaunchKernelGGL(k_xupdate<T>, dim3(H->n_x), dim3(kBlock), 0, st, H->d_sys, H->d_ins, H->w_x, accumulate ? 1 : 0,
-                     xfin, cfin, out, (double *)nullptr);
-  HIPCHECK(hipGetLastError());
-  HIPCHECK(hipMemcpyAsync(H->h_gs, H->gs, sizeof(GState) * H->ninst, hipMemcpyDeviceToHost, st));
-  HIPCHECK(hipStreamSynchronize(st));
-  for (int i = 0; i < H->ninst; ++i) {
-    const GState &g = H->h_gs[i];
-    is.iters += g.iter;
-    is.matvecs += g.iter;
-    is.iters_max = std::max(is.iters_max, g.iter);
-    if (g.status == 3) is.nonfinite = true;
-    if (g.status == 2) is.notconv = true;
-  }
-  return is;
-}
 
-// r = b~ - S x (FP64); pairs[2 i] = ||r||^2, pairs[2 i + 1] = u_S . r.
-void residual64(smpm_handle *H, const double *x, double *r, hipStream_t st) {
-  gemv<double, double, double>(H, 0, x, 0, nullptr, H->y64, nullptr, nullptr, st);
-  HIPCHECK(hipMemcpyAsync(r, H->bS, sizeof(double) * H->tot_x, hipMemcpyDeviceToDevice, st));
-  hipLaunchKernelGGL(k_xupdate<double>, dim3(H->n_x), dim3(kBlock), 0, st, H->d_sys, H->d_ins, H->w_x, 2,
-                     (const double *)H->y64, (const double *)nullptr, r, H->partn);
-  hipLaunchKernelGGL(k_reduce_pairs, dim3(H->ninst), dim3(kBlock), 0, st, H->d_ins, (const double *)H->partn, H->pairs);
-}
+  // x' = V y; x = M^-1 x' + coarse correction, into (or onto) x_S
+  static void post(smpm_handle *H, hipStream_t st) {
+    const bool useM = H->method != SMPM_METHOD_SCHUR;
+    const bool useP = H->method == SMPM_METHOD_DBJ;
+    const int maxit = H->maxit;
+    T *Vb = V(H), *zb = z(H), *yb = y(H), *tb = t(H);
+    hipLaunchKernelGGL(k_backsolve, dim3(H->ninst), dim3(kBlock), sizeof(double) * (maxit + 1), st, H->d_ins,
+                       (const double *)H->Rm, (const double *)H->g, (const double *)H->scale, H->ycoef,
+                       (const GState *)H->gs, maxit);
+    hipLaunchKernelGGL((k_combine<T, T>), dim3(H->n_x), dim3(kBlock), 0, st, H->d_sys, H->d_ins, H->w_x, (const T *)Vb,
+                       (const double *)H->ycoef, tb, (const GState *)H->gs);
+    const T *xfin = tb;
+    if (useM) {
+      gemv<T, T, T>(H, 1, (const T *)tb, 0, nullptr, zb, nullptr, nullptr, st);
+      xfin = zb;
+    }
+    const double *cfin = nullptr;
+    if (useP) {   // c' = G (Z^T b - Z^T S z): x = z + Z c'
+      gemv<T, T, T>(H, 0, xfin, 0, nullptr, yb, H->hs, nullptr, st);
+      hipLaunchKernelGGL(k_coarse, dim3(H->ninst), dim3(kBlock), 0, st, H->d_sys, H->d_ins, (const double *)H->hs,
+                         (const double *)H->tb, (double *)nullptr, H->cv, (const GState *)nullptr);
+      cfin = H->cv;
+    }
+    hipLaunchKernelGGL(k_xupdate<T>, dim3(H->n_x), dim3(kBlock), 0, st, H->d_sys, H->d_ins, H->w_x, P == 0 ? 0 : 1,
+                       xfin, cfin, H->xS, (double *)nullptr);
+  }
 
-// ||b~|| per instance (host), and pairs[2 i] = ||b~||^2 on the device.
-void norms_of_b(smpm_handle *H, std::vector<double> &nb, hipStream_t st) {
+  // Enqueue one inner solve; its final GMRES states are copied to the pinned
+  // history slot `slot` (read after the solve's last synchronization).
+  static void run(smpm_handle *H, int slot, hipStream_t st) {
+    if (!H->g_pre[P]) H->g_pre[P] = capture(st, [&] { pre(H, st); });
+    if (!H->g_loop[P])
+      H->g_loop[P] = capture(st, [&] {
+        for (int c = 0; c < kIterChunk; ++c) iteration(H, st);
+      });
+    if (!H->g_post[P]) H->g_post[P] = capture(st, [&] { post(H, st); });
+    HIPCHECK(hipGraphLaunch(H->g_pre[P], st));
+    const int max_chunks = (H->maxit + kIterChunk - 1) / kIterChunk;
+    int launched = 0;
+    const int first = std::min(std::max(1, H->pred_chunks[P]), max_chunks);
+    for (; launched < first; ++launched) HIPCHECK(hipGraphLaunch(H->g_loop[P], st));
+    while (launched < max_chunks && any_active(H, st)) {
+      HIPCHECK(hipGraphLaunch(H->g_loop[P], st));
+      ++launched;
+    }
+    HIPCHECK(hipGraphLaunch(H->g_post[P], st));
+    HIPCHECK(hipMemcpyAsync(H->h_gs_hist + (size_t)slot * H->ninst, H->gs, sizeof(GState) * H->ninst,
+                            hipMemcpyDeviceToHost, st));
+  }
+};
+
+// r = b~ - S x_S (FP64); pairs[2 i] = ||r||^2, pairs[2 i + 1] = u_S . r; then
+// r <- r - u_S (u_S . r) (the refinement residual, k = 0).
+void residual64(smpm_handle *H, hipStream_t st) {
+  gemv<double, double, double>(H, 0, H->xS, 0, nullptr, H->y64, nullptr, nullptr, st);
   HIPCHECK(hipMemcpyAsync(H->rb, H->bS, sizeof(double) * H->tot_x, hipMemcpyDeviceToDevice, st));
   hipLaunchKernelGGL(k_xupdate<double>, dim3(H->n_x), dim3(kBlock), 0, st, H->d_sys, H->d_ins, H->w_x, 2,
-                     (const double *)nullptr, (const double *)nullptr, H->rb, H->partn);
+                     (const double *)H->y64, (const double *)nullptr, H->rb, H->partn);
   hipLaunchKernelGGL(k_reduce_pairs, dim3(H->ninst), dim3(kBlock), 0, st, H->d_ins, (const double *)H->partn, H->pairs);
-  HIPCHECK(hipMemcpyAsync(H->h_pairs, H->pairs, sizeof(double) * 2 * H->ninst, hipMemcpyDeviceToHost, st));
-  HIPCHECK(hipStreamSynchronize(st));
-  nb.resize(H->ninst);
-  for (int i = 0; i < H->ninst; ++i) nb[i] = std::sqrt(H->h_pairs[2 * i]);
+  hipLaunchKernelGGL(k_proj_x_scalar, dim3(H->n_x), dim3(kBlock), 0, st, H->d_sys, H->d_ins, H->w_x, H->rb,
+                     (const double *)H->pairs);
+}
+
+// Steps 1-3 of Algorithm 2: F = f + tau g, F~ = F - u_L u_L^T F, v = A^-1 F~,
+// b~ = B v - u_S u_S^T B v; then pairs = (||b~||^2, u_S . b~), and for the
+// refined form r = b~, x_S = 0.
+void stage_rhs(smpm_handle *H, const double *f, const double *g, hipStream_t st) {
+  hipLaunchKernelGGL(k_rhs, dim3(H->n_r), dim3(kBlock), 0, st, H->d_sys, H->d_ins, H->w_r, f, g, H->F, H->pr);
+  hipLaunchKernelGGL(k_proj_r, dim3(H->n_r), dim3(kBlock), 0, st, H->d_sys, H->d_ins, H->w_r, H->F, H->pr, H->defect);
+  ainv(H, H->F, H->v, st);
+  hipLaunchKernelGGL(k_bS, dim3(H->n_h), dim3(kBlock), 0, st, H->d_sys, H->d_ins, H->w_h, (const double *)H->v, H->bS, H->hs);
+  hipLaunchKernelGGL(k_proj_x, dim3(H->n_x), dim3(kBlock), 0, st, H->d_sys, H->d_ins, H->w_x, H->bS, (const double *)H->hs);
+  hipLaunchKernelGGL(k_xupdate<double>, dim3(H->n_x), dim3(kBlock), 0, st, H->d_sys, H->d_ins, H->w_x, 2,
+                     (const double *)nullptr, (const double *)nullptr, H->bS, H->partn);
+  hipLaunchKernelGGL(k_reduce_pairs, dim3(H->ninst), dim3(kBlock), 0, st, H->d_ins, (const double *)H->partn, H->pairs);
+  if (H->precision != SMPM_FP64) {
+    HIPCHECK(hipMemcpyAsync(H->rb, H->bS, sizeof(double) * H->tot_x, hipMemcpyDeviceToDevice, st));
+    hipLaunchKernelGGL(k_fill, dim3((unsigned)((H->tot_x + kBlock - 1) / kBlock)), dim3(kBlock), 0, st, H->xS, H->tot_x,
+                       0.0);
+  }
 }
 
 // Step 9 of Algorithm 2 and the gauge: u = A^-1 (F~ - E x_S), minus its mean for k = 0.
@@ -772,61 +838,79 @@ smpm_status smpm_solve(smpm_handle *H, const double *f, const double *g, double 
   try {
     HIPCHECK(hipEventRecord(H->ev_in, caller));
     HIPCHECK(hipStreamWaitEvent(st, H->ev_in, 0));
-    stage_rhs(H, f, g, st);
-    std::vector<double> nb;
-    norms_of_b(H, nb, st);
+    if (!H->g_stage || H->stage_f != f || H->stage_g != g) {
+      if (H->g_stage) HIPCHECK(hipGraphExecDestroy(H->g_stage));
+      H->g_stage = nullptr;
+      H->g_stage = capture(st, [&] { stage_rhs(H, f, g, st); });
+      H->stage_f = f; H->stage_g = g;
+    }
+    if (!H->g_resid) H->g_resid = capture(st, [&] { residual64(H, st); });
+    HIPCHECK(hipGraphLaunch(H->g_stage, st));
+    HIPCHECK(hipMemcpyAsync(H->h_nb, H->pairs, sizeof(double) * 2 * H->ninst, hipMemcpyDeviceToHost, st));
+    const bool useP = H->method == SMPM_METHOD_DBJ;
     bool nonfinite = false, notconv = false;
+    int sweeps = 0;
     if (H->precision == SMPM_FP64) {
-      InnerStats is = inner_solve<double>(H, H->bS, H->xS, 0, H->tol, st);
-      S.iters_total = (int)is.iters;
-      S.iters_max = is.iters_max;
-      S.sweeps_max = 1;
-      S.schur_matvecs = is.matvecs;
-      nonfinite = is.nonfinite;
-      notconv = is.notconv;
+      Inner<double>::run(H, 0, st);
+      sweeps = 1;
+      HIPCHECK(hipGraphLaunch(H->g_resid, st));   // final FP64 check of the Schur residual
+      S.schur_matvecs += H->ninst * ((useP ? 1 : 0) + 1);
     } else {
-      HIPCHECK(hipMemsetAsync(H->xS, 0, sizeof(double) * H->tot_x, st));
-      HIPCHECK(hipMemcpyAsync(H->rb, H->bS, sizeof(double) * H->tot_x, hipMemcpyDeviceToDevice, st));
-      int sweep = 0;
-      for (;; ++sweep) {
-        if (sweep > 0) {
-          residual64(H, H->xS, H->rb, st);
-          hipLaunchKernelGGL(k_proj_x_scalar, dim3(H->n_x), dim3(kBlock), 0, st, H->d_sys, H->d_ins, H->w_x, H->rb,
-                             (const double *)H->pairs);
+      for (;; ++sweeps) {
+        if (sweeps > 0) {
+          HIPCHECK(hipGraphLaunch(H->g_resid, st));
           S.schur_matvecs += H->ninst;
           HIPCHECK(hipMemcpyAsync(H->h_pairs, H->pairs, sizeof(double) * 2 * H->ninst, hipMemcpyDeviceToHost, st));
           HIPCHECK(hipStreamSynchronize(st));
           bool done = true;
           for (int i = 0; i < H->ninst; ++i) {
-            const double rel = nb[i] > 0 ? std::sqrt(H->h_pairs[2 * i]) / nb[i] : 0.0;
+            const double nb = std::sqrt(H->h_nb[2 * i]);
+            const double rel = nb > 0 ? std::sqrt(H->h_pairs[2 * i]) / nb : 0.0;
             if (!std::isfinite(rel)) nonfinite = true;
             if (rel > H->tol) done = false;
           }
           if (done || nonfinite) break;
         }
-        if (sweep >= H->max_sweeps) { notconv = true; break; }
-        InnerStats is = inner_solve<float>(H, H->rb, H->xS, 1, H->inner_tol, st);
-        S.iters_total += (int)is.iters;
-        S.iters_max = std::max(S.iters_max, is.iters_max);
-        S.schur_matvecs += is.matvecs;
-        if (is.nonfinite) { nonfinite = true; break; }
+        if (sweeps >= H->max_sweeps) { notconv = true; break; }
+        Inner<float>::run(H, sweeps, st);
+        S.schur_matvecs += useP ? H->ninst : 0;
       }
-      S.sweeps_max = sweep;
     }
-    // final FP64 check of the Schur residual
-    residual64(H, H->xS, H->rb, st);
-    S.schur_matvecs += H->ninst;
-    HIPCHECK(hipMemcpyAsync(H->h_pairs, H->pairs, sizeof(double) * 2 * H->ninst, hipMemcpyDeviceToHost, st));
+    if (H->precision == SMPM_FP64)
+      HIPCHECK(hipMemcpyAsync(H->h_pairs, H->pairs, sizeof(double) * 2 * H->ninst, hipMemcpyDeviceToHost, st));
     HIPCHECK(hipMemcpyAsync(H->h_defect, H->defect, sizeof(double) * H->ninst, hipMemcpyDeviceToHost, st));
-    finish_u(H, u, st);
+    if (!H->g_finish || H->fin_u != u) {
+      if (H->g_finish) HIPCHECK(hipGraphExecDestroy(H->g_finish));
+      H->g_finish = nullptr;
+      H->g_finish = capture(st, [&] { finish_u(H, u, st); });
+      H->fin_u = u;
+    }
+    HIPCHECK(hipGraphLaunch(H->g_finish, st));
     HIPCHECK(hipGetLastError());
     HIPCHECK(hipEventRecord(H->ev_out, st));
     HIPCHECK(hipStreamWaitEvent(caller, H->ev_out, 0));
     HIPCHECK(hipStreamSynchronize(st));
+    // iteration statistics of every inner solve
+    const int P = H->precision == SMPM_FP64 ? 0 : 1;
+    const int nslots = H->precision == SMPM_FP64 ? 1 : std::min(sweeps, H->max_sweeps);
+    int itmax_all = 0;
+    for (int sw = 0; sw < nslots; ++sw)
+      for (int i = 0; i < H->ninst; ++i) {
+        const GState &gsi = H->h_gs_hist[(size_t)sw * H->ninst + i];
+        S.iters_total += gsi.iter;
+        S.schur_matvecs += gsi.iter;
+        S.iters_max = std::max(S.iters_max, gsi.iter);
+        itmax_all = std::max(itmax_all, gsi.iter);
+        if (gsi.status == 3) nonfinite = true;
+        if (gsi.status == 2 && H->precision == SMPM_FP64) notconv = true;
+      }
+    H->pred_chunks[P] = std::max(1, (itmax_all + kIterChunk - 1) / kIterChunk);
+    S.sweeps_max = H->precision == SMPM_FP64 ? 1 : sweeps;
     double relmax = 0.0, defmax = 0.0;
     int conv = 0;
     for (int i = 0; i < H->ninst; ++i) {
-      const double rel = nb[i] > 0 ? std::sqrt(H->h_pairs[2 * i]) / nb[i] : 0.0;
+      const double nb = std::sqrt(H->h_nb[2 * i]);
+      const double rel = nb > 0 ? std::sqrt(H->h_pairs[2 * i]) / nb : 0.0;
       if (!std::isfinite(rel)) nonfinite = true;
       relmax = std::max(relmax, rel);
       if (H->sys[H->h_ins[i].sys].singular) defmax = std::max(defmax, H->h_defect[i]);
