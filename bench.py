@@ -51,18 +51,19 @@ def gpu_events_time(fn, reps, stream):
     return start.elapsed_time(end) / reps   # ms
 
 
-def make_solver(cfg, precision):
+def make_solver(cfg, precision, inner_tol=0.0):
     import paper_1512_01756_amd as P
     from paper_1512_01756_amd import workloads
+    kw = {"precision": precision, "inner_tol": inner_tol}
     if cfg in ("c2", "c3"):
         p = workloads.c2() if cfg == "c2" else workloads.c3()
-        return P.Solver(p.xb, p.zb, p.n - 1, precision=precision), p.f.reshape(-1)
+        return P.Solver(p.xb, p.zb, p.n - 1, **kw), p.f.reshape(-1)
     if cfg == "c4":
         p = workloads.c4()
-        return P.Solver(p.xb, p.zb, p.n - 1, kwaves=p.kwaves, nrhs=2, precision=precision), p.f.reshape(-1)
+        return P.Solver(p.xb, p.zb, p.n - 1, kwaves=p.kwaves, nrhs=2, **kw), p.f.reshape(-1)
     probs = workloads.c5()
     grids = [(p.xb, p.zb, p.n - 1, float(p.kwaves[0])) for p in probs]
-    return P.Solver(grids=grids, precision=precision), np.concatenate([p.f.reshape(-1) for p in probs])
+    return P.Solver(grids=grids, **kw), np.concatenate([p.f.reshape(-1) for p in probs])
 
 
 def matvec_bytes(solver, s_op, s_vec):
@@ -143,6 +144,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--matvec-reps", type=int, default=200)
     ap.add_argument("--matvec-only", action="store_true")
+    ap.add_argument("--inner-tol", type=float, default=0.0,
+                    help="FP32-IR inner tolerance floor (0: the library default)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
@@ -176,7 +179,7 @@ def main():
     fvec = None
     for name, prec in (("fp64", P.FP64), ("fp32_ir", P.FP32_IR)):
         t0 = time.perf_counter()
-        s, fh = make_solver(args.config, prec)
+        s, fh = make_solver(args.config, prec, args.inner_tol)
         setup_s = time.perf_counter() - t0
         if fvec is None:
             fvec = torch.as_tensor(fh).to(dev)

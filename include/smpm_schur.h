@@ -99,7 +99,10 @@ typedef struct {
   int32_t nrhs;        /* right-hand sides per system; 0 selects 1 */
   int32_t precision;   /* smpm_precision */
   int32_t method;      /* smpm_method */
-  double inner_tol;    /* FP32_IR inner relative tolerance; 0 selects 1e-5 */
+  double inner_tol;    /* FP32_IR: each sweep's inner GMRES stops at
+                          max(inner_tol * ||r||, 0.5 * tol * ||b~||), r the sweep's
+                          FP64 residual; 0 selects 1e-4 (one sweep gains about
+                          1e-4 to 1e-5 with FP32 operators) */
   int32_t max_sweeps;  /* FP32_IR outer sweeps; 0 selects 12 */
   int32_t flags;       /* SMPM_FLAG_* */
 } smpm_opts;

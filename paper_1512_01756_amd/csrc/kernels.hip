@@ -338,24 +338,32 @@ __global__ __launch_bounds__(64 * KP) void k_half_gemm(
   }
 }
 
-// Throughput schedule (many items): grid (item, 64-row tile), 4 waves of 16
-// rows over all of K; the windows are staged through double-buffered LDS in
-// chunks of 32 K-steps with coalesced loads while the next chunk's operands
-// are in flight.
+// Throughput schedule (many items): one workgroup per (item, 64-row tile),
+// 4 waves of 16 rows over all of K; the windows are staged through
+// double-buffered LDS in chunks of 32 K-steps with coalesced loads while the
+// next chunk's operands are in flight.  The (item, tile) pairs come in an
+// XCD-aware order (`units`): workgroup L runs on XCD L mod 8, and every tile
+// that reads one stored block is placed on the same XCD, so the block and the
+// windows are fetched into one L2 instead of eight.
 template <typename TO, typename TX, typename TY>
 __global__ __launch_bounds__(256) void k_half_gemm_t(
-    const GWork *__restrict__ work, const GVec *__restrict__ gvec, const TX *__restrict__ xbase, int x_vslot,
-    const double *__restrict__ scale, TY *__restrict__ ybase, double *__restrict__ hsum,
-    const GState *__restrict__ gs) {
+    const GWork *__restrict__ work, const int2 *__restrict__ units, const GVec *__restrict__ gvec,
+    const TX *__restrict__ xbase, int x_vslot, const double *__restrict__ scale, TY *__restrict__ ybase,
+    double *__restrict__ hsum, const GState *__restrict__ gs) {
   constexpr int VT = kGemmVecs, KC = 32, PITCH = VT + 1;
   constexpr int PV = KC * VT / 256;      // staged values per thread per chunk
   constexpr int TPC = KC / PV;           // threads per window
   __shared__ TO Bs[2][KC * PITCH];
   __shared__ WinInfo wi[VT];
-  const GWork wk = work[blockIdx.x];
+  int item = blockIdx.x, rg = blockIdx.y;
+  if (units) {   // XCD-ordered (item, 64-row tile) list; x < 0 pads a bucket
+    const int2 u = units[blockIdx.x];
+    if (u.x < 0) return;
+    item = u.x; rg = u.y;
+  }
+  const GWork wk = work[item];
   const int N = wk.N, Np = wk.Np, K = wk.K;
   const int64_t kS = wk.kS;
-  const int rg = blockIdx.y;
   if (rg * 64 >= Np) return;
   load_windows<VT>(wk, gvec, x_vslot, scale, gs, wi);
   __syncthreads();
@@ -845,15 +853,21 @@ __global__ __launch_bounds__(512) void k_colgemm(const CGItem *__restrict__ item
 }
 
 template <int CT, int MODE>
-__global__ __launch_bounds__(256) void k_colgemm_t(const CGItem *__restrict__ items, const CGCol *__restrict__ cols,
-                                                   const double *__restrict__ xb, double *__restrict__ yb) {
+__global__ __launch_bounds__(256) void k_colgemm_t(const CGItem *__restrict__ items, const int2 *__restrict__ units,
+                                                   const CGCol *__restrict__ cols, const double *__restrict__ xb,
+                                                   double *__restrict__ yb) {
   constexpr int VC = 16 * CT, KC = 32, PITCH = VC + 1;
   constexpr int PV = KC * VC / 256;      // staged values per thread per chunk
   constexpr int TPC = KC / PV;           // threads per column
   __shared__ double Bs[2][KC * PITCH];
   __shared__ int64_t c1[VC], c2[VC];
-  const CGItem it = items[blockIdx.x];
-  const int rg = blockIdx.y;
+  int item = blockIdx.x, rg = blockIdx.y;
+  if (units) {   // XCD-ordered (item, 64-row tile) list; x < 0 pads a bucket
+    const int2 u = units[blockIdx.x];
+    if (u.x < 0) return;
+    item = u.x; rg = u.y;
+  }
+  const CGItem it = items[item];
   if (rg * 64 >= it.R) return;
   if (threadIdx.x < VC) {
     const bool ok = (int)threadIdx.x < it.ccount;
@@ -1123,6 +1137,52 @@ __global__ __launch_bounds__(kBlock) void k_halfsum(const SysDev *__restrict__ s
   for (int q = 1 + (int)threadIdx.x; q < tiles; q += kBlock) hs[I.hs_off + (int64_t)h * tiles + q] = 0.0;
 }
 
+// Z^T of an interface vector in precision T (the additive two-level
+// preconditioner, Table 1 "2LAS"): per (instance, half) sum of its N values,
+// times the basis scale when it reads Krylov slot `iter`; same slot layout as
+// k_halfsum.  Stopped instances are skipped.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_halfsum_t(const SysDev *__restrict__ sys,
+                                                      const InstDev *__restrict__ ins,
+                                                      const int2 *__restrict__ work, const T *__restrict__ x,
+                                                      int x_vslot, const double *__restrict__ scale,
+                                                      const GState *__restrict__ gs, double *__restrict__ hs) {
+  __shared__ double lds4[4];
+  const int2 wk = work[blockIdx.x];
+  const int i = wk.x, h = wk.y;
+  if (gs && !gs[i].active) return;
+  const int it = gs ? gs[i].iter : 0;
+  const InstDev I = ins[i];
+  const SysDev &S = sys[I.sys];
+  const int N = S.N;
+  const int64_t off = (x_vslot ? I.v_off + (int64_t)it * S.kS : I.x_off) + (int64_t)h * N;
+  double a = 0.0;
+  for (int row = threadIdx.x; row < N; row += kBlock) a += (double)x[off + row];
+  a = block_sum(a, lds4);
+  const int tiles = (N + 15) >> 4;
+  if (threadIdx.x == 0) hs[I.hs_off + (int64_t)h * tiles] = a * (scale ? scale[I.st_off + it] : 1.0);
+  for (int q = 1 + (int)threadIdx.x; q < tiles; q += kBlock) hs[I.hs_off + (int64_t)h * tiles + q] = 0.0;
+}
+
+// z += Z c in precision T (the coarse term of the two-level preconditioner).
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_add_zc(const SysDev *__restrict__ sys, const InstDev *__restrict__ ins,
+                                                   const int2 *__restrict__ work, T *__restrict__ z,
+                                                   const double *__restrict__ cvec, const GState *__restrict__ gs) {
+  const int2 wk = work[blockIdx.x];
+  const int i = wk.x, ch = wk.y;
+  if (gs && !gs[i].active) return;
+  const InstDev I = ins[i];
+  const SysDev &S = sys[I.sys];
+  const int N = S.N;
+  for (int q = 0; q < kChunk / kBlock; ++q) {
+    const int64_t e = (int64_t)ch * kChunk + threadIdx.x + q * kBlock;
+    if (e >= S.kS) continue;
+    const int iface = (int)(e / N) >> 1;
+    z[I.x_off + e] = (T)((double)z[I.x_off + e] + cvec[I.c_off + iface]);
+  }
+}
+
 // r0 = P b~ = b~ - (S Z) c into Krylov slot 0 (or b~ itself without
 // deflation); partial ||r0||^2.
 template <typename TV>
@@ -1165,7 +1225,7 @@ __global__ __launch_bounds__(kBlock) void k_gmres_start(const InstDev *__restric
                                                         const double *__restrict__ pairs,
                                                         double *__restrict__ scale,
                                                         double *__restrict__ g, GState *__restrict__ gs,
-                                                        int enable) {
+                                                        int enable, const double *__restrict__ nb, double bfrac) {
   __shared__ double lds4[4];
   const int i = blockIdx.x;
   const InstDev I = ins[i];
@@ -1179,7 +1239,12 @@ __global__ __launch_bounds__(kBlock) void k_gmres_start(const InstDev *__restric
     st.r0 = r0;
     st.res = r0;
     st.pad = 0;
-    st.ref = pairs ? sqrt(pairs[2 * i]) : r0;
+    // stopping reference: |g| <= tol * ref.  In a refinement sweep the
+    // reference is also floored at bfrac * ||b~||, so the sweep stops once
+    // the outer tolerance is within reach instead of at a fixed reduction.
+    double ref = pairs ? sqrt(pairs[2 * i]) : r0;
+    if (nb && bfrac > 0.0) ref = fmax(ref, bfrac * sqrt(nb[2 * i]));
+    st.ref = ref;
     if (!isfinite(r0)) { st.active = 0; st.status = 3; }
     else if (r0 == 0.0 || !enable) { st.active = 0; st.status = 1; }
     else { st.active = 1; st.status = 0; }

@@ -80,6 +80,9 @@ std::vector<T> to_colmajor_padded(const std::vector<double> &a, int nb, int rows
 }
 
 constexpr int kIterChunk = 4;
+// A refinement sweep's inner solve stops once its residual is below
+// kSweepSafety * tol * ||b~|| (or inner_tol times its own right-hand side).
+constexpr double kSweepSafety = 0.5;
 constexpr int kWaves = 16;   // waves per workgroup of the GEMV-shaped kernels
 
 }  // namespace
@@ -87,7 +90,7 @@ constexpr int kWaves = 16;   // waves per workgroup of the GEMV-shaped kernels
 struct smpm_handle {
   smpm_opts opts{};
   int nrhs = 1, maxit = 300, precision = SMPM_FP64, method = SMPM_METHOD_DBJ, max_sweeps = 12;
-  double tol = 1e-10, inner_tol = 1e-5;
+  double tol = 1e-10, inner_tol = 1e-4;
   bool host_only = false;
   std::vector<System> sys;
 
@@ -104,6 +107,8 @@ struct smpm_handle {
   // and within one instance (single-system applies).
   GWork *g_S = nullptr, *g_M = nullptr, *g_Si = nullptr, *g_Mi = nullptr;
   GVec *g_vec = nullptr;
+  int2 *u_S = nullptr, *u_M = nullptr;   // XCD-ordered (item, 64-row tile) lists of g_S, g_M
+  int n_uS = 0, n_uM = 0;
   int n_gS = 0, n_gM = 0;
   std::vector<int> gSi_start, gSi_cnt, gMi_start, gMi_cnt;
   HWork *w_S1 = nullptr, *w_M1 = nullptr;   // single items (streamed blocks)
@@ -116,6 +121,8 @@ struct smpm_handle {
   CGItem *cg_all[3][2] = {}, *cg_one[3][2] = {};
   CGCol *cg_cols = nullptr;
   int n_cg_all[3][2] = {};
+  int2 *cg_units[3][2] = {};   // XCD-ordered (item, 64-row tile) lists of cg_all
+  int n_cg_units[3][2] = {};
   std::vector<int> cg_start[3][2], cg_cnt[3][2];
   int n_h = 0, n_x = 0, n_r = 0, n_s = 0;
   std::vector<int> h_start, x_start, r_start, s_start;
@@ -129,6 +136,7 @@ struct smpm_handle {
   double *part1 = nullptr, *part2 = nullptr, *partn = nullptr, *pr = nullptr, *hs = nullptr;
   double *cv = nullptr, *tb = nullptr, *scale = nullptr, *Rm = nullptr, *cs = nullptr, *sn = nullptr, *g = nullptr;
   double *ycoef = nullptr, *defect = nullptr, *pairs = nullptr, *lam = nullptr, *qb = nullptr;
+  double *nb2 = nullptr;   // ||b~||^2 and u_S . b~ per instance, kept from the staging step
   GState *gs = nullptr;
   GState *h_gs = nullptr;      // pinned
   double *h_pairs = nullptr;   // pinned
@@ -168,6 +176,37 @@ struct smpm_handle {
 };
 
 namespace {
+
+// XCD-aware launch order for the throughput GEMMs: workgroup L of a 1-D grid
+// runs on XCD L mod kXcds.  Tiles are bucketed by the block they read (key),
+// blocks are assigned to buckets largest first onto the least loaded bucket,
+// and bucket b fills grid positions b, b + kXcds, ...; short buckets are
+// padded with (-1, 0) entries, which exit at once.
+constexpr int kXcds = 8;
+std::vector<int2> xcd_units(const std::vector<uintptr_t> &key, const std::vector<int> &tiles) {
+  std::map<uintptr_t, std::vector<int>> by;
+  for (int i = 0; i < (int)key.size(); ++i) by[key[i]].push_back(i);
+  std::vector<std::pair<int, uintptr_t>> order;
+  for (auto &kv : by) {
+    int t = 0;
+    for (int i : kv.second) t += tiles[i];
+    order.push_back({t, kv.first});
+  }
+  std::sort(order.begin(), order.end(), [](auto &a, auto &b) { return a.first > b.first; });
+  std::vector<std::vector<int2>> bucket(kXcds);
+  std::vector<int> load(kXcds, 0);
+  for (auto &o : order) {
+    const int b = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+    for (int i : by[o.second])
+      for (int r = 0; r < tiles[i]; ++r) bucket[b].push_back(make_int2(i, r));
+    load[b] += o.first;
+  }
+  const int depth = *std::max_element(load.begin(), load.end());
+  std::vector<int2> u((size_t)depth * kXcds, make_int2(-1, 0));
+  for (int b = 0; b < kXcds; ++b)
+    for (int k = 0; k < (int)bucket[b].size(); ++k) u[(size_t)k * kXcds + b] = bucket[b][k];
+  return u;
+}
 
 // True if some block id serves more than one half.
 bool shares_blocks(const std::vector<int> &ids) {
@@ -362,6 +401,15 @@ void upload(smpm_handle *H, hipStream_t st) {
       for (int w = 0; w < 2; ++w) {
         H->cg_all[k][w] = dupload(own, all[k][w], st); H->n_cg_all[k][w] = (int)all[k][w].size();
         H->cg_one[k][w] = dupload(own, one[k][w], st);
+        std::vector<uintptr_t> key;
+        std::vector<int> tiles;
+        for (const CGItem &it : all[k][w]) {
+          key.push_back((uintptr_t)it.A);
+          tiles.push_back((it.R + 63) / 64);
+        }
+        std::vector<int2> u = xcd_units(key, tiles);
+        H->cg_units[k][w] = dupload(own, u, st);
+        H->n_cg_units[k][w] = (int)u.size();
       }
     H->cg_cols = dupload(own, cols, st);
   }
@@ -427,6 +475,18 @@ void upload(smpm_handle *H, hipStream_t st) {
     H->gMi_start.resize(H->ninst, 0); H->gMi_cnt.resize(H->ninst, 0);
     H->g_S = dupload(own, gS, st); H->n_gS = (int)gS.size();
     H->g_M = dupload(own, gM, st); H->n_gM = (int)gM.size();
+    for (int op = 0; op < 2; ++op) {
+      const std::vector<GWork> &g = op == 0 ? gS : gM;
+      std::vector<uintptr_t> key;
+      std::vector<int> tiles;
+      for (const GWork &w : g) {
+        key.push_back((uintptr_t)w.blk64);
+        tiles.push_back((w.Np + 63) / 64);
+      }
+      std::vector<int2> u = xcd_units(key, tiles);
+      (op == 0 ? H->u_S : H->u_M) = dupload(own, u, st);
+      (op == 0 ? H->n_uS : H->n_uM) = (int)u.size();
+    }
     H->g_Si = dupload(own, gSi, st);
     H->g_Mi = dupload(own, gMi, st);
     H->g_vec = dupload(own, gv, st);
@@ -451,6 +511,7 @@ void upload(smpm_handle *H, hipStream_t st) {
   H->g = dalloc<double>(own, st_off); H->ycoef = dalloc<double>(own, st_off); H->Rm = dalloc<double>(own, rr_off);
   H->lam = dalloc<double>(own, lam_off); H->qb = dalloc<double>(own, lam_off);
   H->defect = dalloc<double>(own, H->ninst); H->pairs = dalloc<double>(own, 2 * H->ninst);
+  H->nb2 = dalloc<double>(own, 2 * H->ninst);
   H->gs = dalloc<GState>(own, H->ninst);
   HIPCHECK(hipHostMalloc((void **)&H->h_gs, sizeof(GState) * H->ninst, hipHostMallocDefault));
   HIPCHECK(hipHostMalloc((void **)&H->h_pairs, sizeof(double) * 2 * H->ninst, hipHostMallocDefault));
@@ -487,9 +548,12 @@ void gemv(smpm_handle *H, int op, const TX *x, int vslot, const double *scale, T
       else if ((int64_t)count * rt16 < 2048)
         hipLaunchKernelGGL((k_half_gemm<TO, TX, TY, 8>), dim3(count, rt16), dim3(512), 0, st, w, H->g_vec, x, vslot,
                            scale, y, hsum, gs);
+      else if (inst < 0)
+        hipLaunchKernelGGL((k_half_gemm_t<TO, TX, TY>), dim3(op == 0 ? H->n_uS : H->n_uM), dim3(256), 0, st, w,
+                           (const int2 *)(op == 0 ? H->u_S : H->u_M), H->g_vec, x, vslot, scale, y, hsum, gs);
       else
-        hipLaunchKernelGGL((k_half_gemm_t<TO, TX, TY>), dim3(count, (H->Nmax + 63) / 64), dim3(256), 0, st, w, H->g_vec,
-                           x, vslot, scale, y, hsum, gs);
+        hipLaunchKernelGGL((k_half_gemm_t<TO, TX, TY>), dim3(count, (H->Nmax + 63) / 64), dim3(256), 0, st, w,
+                           (const int2 *)nullptr, H->g_vec, x, vslot, scale, y, hsum, gs);
     }
   }
   // halves with their own block: streaming kernel
@@ -513,7 +577,8 @@ void gemv(smpm_handle *H, int op, const TX *x, int vslot, const double *scale, T
 // dst = A(k)^-1 src (node space; src and dst must not overlap): element
 // solves, the per-strip z-interface capacitance solve, element corrections.
 template <int CT>
-void colgemm_w(smpm_handle *H, const CGItem *items, int count, int mode, const double *x, double *y, hipStream_t st) {
+void colgemm_w(smpm_handle *H, const CGItem *items, int count, const int2 *units, int nunits, int mode,
+               const double *x, double *y, hipStream_t st) {
   if (count <= 0) return;
   const int rmax = std::max(H->n2_max, H->nq_max);
   const int rt16 = (rmax + 15) / 16;
@@ -522,9 +587,9 @@ void colgemm_w(smpm_handle *H, const CGItem *items, int count, int mode, const d
     if (mode == 0) hipLaunchKernelGGL((k_colgemm<CT, 0>), grid, dim3(512), 0, st, items, H->cg_cols, x, y);
     else hipLaunchKernelGGL((k_colgemm<CT, 1>), grid, dim3(512), 0, st, items, H->cg_cols, x, y);
   } else {
-    const dim3 grid(count, (rmax + 63) / 64);
-    if (mode == 0) hipLaunchKernelGGL((k_colgemm_t<CT, 0>), grid, dim3(256), 0, st, items, H->cg_cols, x, y);
-    else hipLaunchKernelGGL((k_colgemm_t<CT, 1>), grid, dim3(256), 0, st, items, H->cg_cols, x, y);
+    const dim3 grid = units ? dim3(nunits) : dim3(count, (rmax + 63) / 64);
+    if (mode == 0) hipLaunchKernelGGL((k_colgemm_t<CT, 0>), grid, dim3(256), 0, st, items, units, H->cg_cols, x, y);
+    else hipLaunchKernelGGL((k_colgemm_t<CT, 1>), grid, dim3(256), 0, st, items, units, H->cg_cols, x, y);
   }
 }
 
@@ -533,8 +598,10 @@ void colgemm(smpm_handle *H, int kind, int inst, int mode, const double *x, doub
   for (int w = 0; w < 2; ++w) {
     const CGItem *it = inst >= 0 ? H->cg_one[kind][w] + H->cg_start[kind][w][inst] : H->cg_all[kind][w];
     const int cnt = inst >= 0 ? H->cg_cnt[kind][w][inst] : H->n_cg_all[kind][w];
-    if (w == 0) colgemm_w<1>(H, it, cnt, mode, x, y, st);
-    else colgemm_w<kColVecs / 16>(H, it, cnt, mode, x, y, st);
+    const int2 *un = inst >= 0 ? nullptr : H->cg_units[kind][w];
+    const int nun = inst >= 0 ? 0 : H->n_cg_units[kind][w];
+    if (w == 0) colgemm_w<1>(H, it, cnt, un, nun, mode, x, y, st);
+    else colgemm_w<kColVecs / 16>(H, it, cnt, un, nun, mode, x, y, st);
   }
 }
 
@@ -619,8 +686,23 @@ struct Inner {
     }
     hipLaunchKernelGGL(k_init_basis<T>, dim3(H->n_x), dim3(kBlock), 0, st, H->d_sys, H->d_ins, H->w_x, b(H),
                        useP ? (const double *)H->cv : (const double *)nullptr, V(H), H->partn);
+    // refinement sweeps stop at max(inner_tol ||r||, kSweepSafety tol ||b~||)
+    const double bfrac = P == 0 ? 0.0 : kSweepSafety * H->tol / H->inner_tol;
     hipLaunchKernelGGL(k_gmres_start, dim3(H->ninst), dim3(kBlock), 0, st, H->d_ins, (const double *)H->partn,
-                       (const double *)H->pairs, H->scale, H->g, H->gs, 1);
+                       (const double *)H->pairs, H->scale, H->g, H->gs, 1, (const double *)H->nb2, bfrac);
+  }
+
+  // z = (M^-1 + Z G Z^T) x for the additive two-level method (x: Krylov slot
+  // `iter` when vslot, else the interface vector t).
+  static void twolevel(smpm_handle *H, const T *x, int vslot, const double *scale, const GState *g, T *zb,
+                       hipStream_t st) {
+    gemv<T, T, T>(H, 1, x, vslot, scale, zb, nullptr, g, st);
+    hipLaunchKernelGGL(k_halfsum_t<T>, dim3(H->n_h), dim3(kBlock), 0, st, H->d_sys, H->d_ins, H->w_h, x, vslot, scale, g,
+                       H->hs);
+    hipLaunchKernelGGL(k_coarse, dim3(H->ninst), dim3(kBlock), 0, st, H->d_sys, H->d_ins, (const double *)H->hs,
+                       (const double *)nullptr, (double *)nullptr, H->cv, g);
+    hipLaunchKernelGGL(k_add_zc<T>, dim3(H->n_x), dim3(kBlock), 0, st, H->d_sys, H->d_ins, H->w_x, zb,
+                       (const double *)H->cv, g);
   }
 
   static void iteration(smpm_handle *H, hipStream_t st) {
@@ -629,7 +711,10 @@ struct Inner {
     const int maxit = H->maxit;
     const size_t shm_dot = sizeof(double) * (maxit + 1) * 5;
     T *Vb = V(H), *zb = z(H), *yb = y(H);
-    if (useM) {
+    if (H->method == SMPM_METHOD_2LAS) {
+      twolevel(H, (const T *)Vb, 1, H->scale, H->gs, zb, st);
+      gemv<T, T, T>(H, 0, (const T *)zb, 0, nullptr, yb, nullptr, H->gs, st);
+    } else if (useM) {
       gemv<T, T, T>(H, 1, (const T *)Vb, 1, H->scale, zb, nullptr, H->gs, st);
       gemv<T, T, T>(H, 0, (const T *)zb, 0, nullptr, yb, useP ? H->hs : nullptr, H->gs, st);
     } else {
@@ -659,7 +744,10 @@ struct Inner {
     hipLaunchKernelGGL((k_combine<T, T>), dim3(H->n_x), dim3(kBlock), 0, st, H->d_sys, H->d_ins, H->w_x, (const T *)Vb,
                        (const double *)H->ycoef, tb, (const GState *)H->gs);
     const T *xfin = tb;
-    if (useM) {
+    if (H->method == SMPM_METHOD_2LAS) {
+      twolevel(H, (const T *)tb, 0, nullptr, nullptr, zb, st);
+      xfin = zb;
+    } else if (useM) {
       gemv<T, T, T>(H, 1, (const T *)tb, 0, nullptr, zb, nullptr, nullptr, st);
       xfin = zb;
     }
@@ -722,6 +810,7 @@ void stage_rhs(smpm_handle *H, const double *f, const double *g, hipStream_t st)
   hipLaunchKernelGGL(k_xupdate<double>, dim3(H->n_x), dim3(kBlock), 0, st, H->d_sys, H->d_ins, H->w_x, 2,
                      (const double *)nullptr, (const double *)nullptr, H->bS, H->partn);
   hipLaunchKernelGGL(k_reduce_pairs, dim3(H->ninst), dim3(kBlock), 0, st, H->d_ins, (const double *)H->partn, H->pairs);
+  HIPCHECK(hipMemcpyAsync(H->nb2, H->pairs, sizeof(double) * 2 * H->ninst, hipMemcpyDeviceToDevice, st));
   if (H->precision != SMPM_FP64) {
     HIPCHECK(hipMemcpyAsync(H->rb, H->bS, sizeof(double) * H->tot_x, hipMemcpyDeviceToDevice, st));
     hipLaunchKernelGGL(k_fill, dim3((unsigned)((H->tot_x + kBlock - 1) / kBlock)), dim3(kBlock), 0, st, H->xS, H->tot_x,
@@ -747,15 +836,15 @@ smpm_status validate_opts(const smpm_opts *o, smpm_handle *H) {
   H->nrhs = d.nrhs > 0 ? d.nrhs : 1;
   H->precision = d.precision;
   H->method = d.method;
-  H->inner_tol = d.inner_tol > 0 ? d.inner_tol : 1e-5;
+  H->inner_tol = d.inner_tol > 0 ? d.inner_tol : 1e-4;
   H->max_sweeps = d.max_sweeps > 0 ? d.max_sweeps : 12;
   H->host_only = (d.flags & SMPM_FLAG_HOST_ONLY) != 0;
   if (d.tol < 0 || d.max_iter < 0 || d.nrhs < 0 || d.inner_tol < 0 || d.max_sweeps < 0)
     return fail(SMPM_EINVAL, "negative option value");
   if (H->maxit > 2000) return fail(SMPM_EINVAL, "max_iter above 2000");
   if (H->precision != SMPM_FP64 && H->precision != SMPM_FP32_IR) return fail(SMPM_EINVAL, "unknown precision");
-  if (H->method < SMPM_METHOD_DBJ || H->method > SMPM_METHOD_SCHUR)
-    return fail(SMPM_EINVAL, "method not available (DBJ, BJ, SCHUR)");
+  if (H->method < SMPM_METHOD_DBJ || H->method > SMPM_METHOD_2LAS)
+    return fail(SMPM_EINVAL, "unknown method (DBJ, BJ, SCHUR, 2LAS)");
   return SMPM_OK;
 }
 

@@ -90,6 +90,29 @@ def test_fourier_modes_batched_match_oracle():
             assert _rel(u[m, q], ref.u) <= 1e-9, (m, q)
 
 
+@pytest.mark.parametrize("method,name", [(P.METHOD_DBJ, "dbj"), (P.METHOD_BJ, "bj"), (P.METHOD_SCHUR, "schur"),
+                                         (P.METHOD_2LAS, "2las")])
+@pytest.mark.parametrize("k", [0.0, 1.7])
+def test_methods_match_oracle(method, name, k):
+    # Table 1's four methods: same solution, iteration counts within one of
+    # the oracle's (Householder GMRES on the same operator).
+    p = workloads.random_problem(10, 2, 6, kwaves=(k,), seed=21, stretch=True, with_g=True)
+    s, u, st = _gpu_solve(p, method=method)
+    o, ref = _oracle(p, 0, 0, method=name)
+    print(name, k, "stats", st, "oracle iters", ref.iters, "rel", _rel(u, ref.u))
+    assert st["rel_residual_max"] <= ACCEPT
+    assert abs(st["iters_max"] - ref.iters) <= 1
+    assert _rel(u, ref.u) <= 1e-9
+
+
+def test_2las_fp32_refinement():
+    p = workloads.random_problem(12, 3, 7, seed=5, stretch=True)
+    s, u, st = _gpu_solve(p, precision=P.FP32_IR, method=P.METHOD_2LAS)
+    o, ref = _oracle(p, 0, 0, tol=1e-12)
+    assert st["rel_residual_max"] <= ACCEPT
+    assert _rel(u, ref.u) <= 1e-8
+
+
 def test_fp32_refinement_reaches_fp64_solution():
     p = workloads.random_problem(12, 3, 7, seed=5, stretch=True)
     s, u, st = _gpu_solve(p, precision=P.FP32_IR)
