@@ -253,6 +253,9 @@ def main():
                        "fp32_ir_sweeps": ir["stats"]["sweeps_max"]},
         "rel_residual_max": {"fp64": fp64["stats"]["rel_residual_max"], "fp32_ir": ir["stats"]["rel_residual_max"]},
         "setup_s": {"fp64": fp64["setup_s"], "fp32_ir": ir["setup_s"]},
+        "gemm_schedules": {"matvec_S64_S32_M64_M32": i0["gemm_sched"], "element": i0["elem_sched"],
+                           "legend": "0 split-K 16 waves, 1 split-K 8 waves, 2 LDS-staged XCD-ordered, "
+                                     "3 LDS-staged plain, -1 unused; picked by timing at setup"},
         "matvec_kernel": {"fp64_us": mv64_ms * 1e3, "fp32_us": mv32_ms * 1e3,
                           "fp64_matvecs_per_s": 1e3 / mv64_ms, "fp32_matvecs_per_s": 1e3 / mv32_ms,
                           "fp64_GBps": gbs64, "fp32_GBps": gbs32},

@@ -84,6 +84,9 @@ typedef enum {
 } smpm_method;
 
 #define SMPM_FLAG_HOST_ONLY 1  /* build the host tables only; no GPU is touched */
+#define SMPM_FLAG_NO_TUNE 2    /* skip the setup-time GEMM schedule tuning; pick
+                                  schedules by launch size (reproducible across
+                                  handles) */
 
 typedef struct {
   int32_t mx, mz;      /* elements in x (>= 2) and z (>= 1) */
@@ -134,6 +137,12 @@ typedef struct {
   int32_t unique_M;        /* distinct block-Jacobi blocks stored */
   int64_t bytes_W64;       /* algorithmic bytes of one FP64 Schur matvec's operator */
   int64_t bytes_M64;       /* same for one block-Jacobi apply */
+  int32_t gemm_sched[4];   /* handle-wide GEMM schedules of the batched shared-block
+                              matvecs: S FP64, S FP32, M^-1 FP64, M^-1 FP32
+                              (0 split-K 16 waves, 1 split-K 8 waves, 2 LDS-staged
+                              XCD-ordered, 3 LDS-staged plain; -1 no shared blocks) */
+  int32_t elem_sched[6];   /* same for the element-interior GEMM lists
+                              (D^-1, K^-1, correction) x (<= 16, <= 64 columns) */
 } smpm_info;
 
 typedef struct smpm_handle smpm_handle;

@@ -20,6 +20,7 @@ OK, EINVAL, ENOMEM, EHIP, ESINGULAR, ENOTCONV, ENONFINITE, EUNSUPPORTED = 0, -1,
 FP64, FP32_IR = 0, 1
 METHOD_DBJ, METHOD_BJ, METHOD_SCHUR, METHOD_2LAS = 0, 1, 2, 3
 FLAG_HOST_ONLY = 1
+FLAG_NO_TUNE = 2
 OP_SCHUR, OP_BJINV, OP_DEFLATE_P, OP_DEFLATE_Q, OP_AINV, OP_B, OP_SCHUR_RHS = range(7)
 TABLE_SCHUR_DENSE, TABLE_BJINV_DENSE, TABLE_COARSE_C, TABLE_U_S, TABLE_U_L, TABLE_U_C, TABLE_SZ = range(7)
 
@@ -59,10 +60,15 @@ class Info(ctypes.Structure):
                 ("r", ctypes.c_int64), ("kS", ctypes.c_int64), ("d", ctypes.c_int32), ("kwave", ctypes.c_double),
                 ("tau", ctypes.c_double), ("f_offset", ctypes.c_int64), ("g_offset", ctypes.c_int64),
                 ("x_offset", ctypes.c_int64), ("unique_W", ctypes.c_int32), ("unique_M", ctypes.c_int32),
-                ("bytes_W64", ctypes.c_int64), ("bytes_M64", ctypes.c_int64)]
+                ("bytes_W64", ctypes.c_int64), ("bytes_M64", ctypes.c_int64),
+                ("gemm_sched", ctypes.c_int32 * 4), ("elem_sched", ctypes.c_int32 * 6)]
 
     def as_dict(self):
-        return {name: getattr(self, name) for name, _ in self._fields_}
+        out = {}
+        for name, _ in self._fields_:
+            v = getattr(self, name)
+            out[name] = list(v) if isinstance(v, ctypes.Array) else v
+        return out
 
 
 EXPORTED = ["smpm_setup", "smpm_setup_batch", "smpm_solve", "smpm_apply", "smpm_schur_apply_all",
@@ -124,12 +130,12 @@ class Solver:
 
     def __init__(self, xb=None, zb=None, order=None, kwaves=(0.0,), grids=None, tau=0.0, tol=1e-10,
                  max_iter=300, nrhs=1, precision=FP64, method=METHOD_DBJ, inner_tol=0.0, max_sweeps=0,
-                 host_only=False, stream=None):
+                 host_only=False, tune=True, stream=None):
         lib = load()
         self._lib = lib
         self.host_only = host_only
         opts = Opts(tau, tol, max_iter, nrhs, precision, method, inner_tol, max_sweeps,
-                    FLAG_HOST_ONLY if host_only else 0)
+                    (FLAG_HOST_ONLY if host_only else 0) | (0 if tune else FLAG_NO_TUNE))
         self.opts = opts
         self._keep = []
         h = ctypes.c_void_p()

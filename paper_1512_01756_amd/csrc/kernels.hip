@@ -339,18 +339,19 @@ __global__ __launch_bounds__(64 * KP) void k_half_gemm(
 }
 
 // Throughput schedule (many items): one workgroup per (item, 64-row tile),
-// 4 waves of 16 rows over all of K; the windows are staged through
+// items of up to 16 CT windows (CT = 4, or 1 for blocks that serve at most
+// 16 halves), 4 waves of 16 rows over all of K; the windows are staged through
 // double-buffered LDS in chunks of 32 K-steps with coalesced loads while the
 // next chunk's operands are in flight.  The (item, tile) pairs come in an
 // XCD-aware order (`units`): workgroup L runs on XCD L mod 8, and every tile
 // that reads one stored block is placed on the same XCD, so the block and the
 // windows are fetched into one L2 instead of eight.
-template <typename TO, typename TX, typename TY>
+template <typename TO, typename TX, typename TY, int CT>
 __global__ __launch_bounds__(256) void k_half_gemm_t(
     const GWork *__restrict__ work, const int2 *__restrict__ units, const GVec *__restrict__ gvec,
     const TX *__restrict__ xbase, int x_vslot, const double *__restrict__ scale, TY *__restrict__ ybase,
     double *__restrict__ hsum, const GState *__restrict__ gs) {
-  constexpr int VT = kGemmVecs, KC = 32, PITCH = VT + 1;
+  constexpr int VT = 16 * CT, KC = 32, PITCH = VT + 1;
   constexpr int PV = KC * VT / 256;      // staged values per thread per chunk
   constexpr int TPC = KC / PV;           // threads per window
   __shared__ TO Bs[2][KC * PITCH];
@@ -400,7 +401,9 @@ __global__ __launch_bounds__(256) void k_half_gemm_t(
     for (int p = 0; p < PV; ++p) Bs[buf][(sk0 + p) * PITCH + scol] = pre[p];
   };
   using Acc = typename Mfma<TO>::Acc;
-  Acc acc0 = {0, 0, 0, 0}, acc1 = {0, 0, 0, 0};
+  Acc acc[CT];
+#pragma unroll
+  for (int t = 0; t < CT; ++t) acc[t] = Acc{0, 0, 0, 0};
   const int nchunks = (K + KC - 1) / KC;
   load_b(0);
   load_a(0, a);
@@ -415,10 +418,9 @@ __global__ __launch_bounds__(256) void k_half_gemm_t(
     }
     const TO *__restrict__ B = Bs[buf];
 #pragma unroll
-    for (int s = 0; s < KC / 4; ++s) {
-      acc0 = Mfma<TO>::mac(a[s], B[(4 * s + kq) * PITCH + cl], acc0);
-      acc1 = Mfma<TO>::mac(a[s], B[(4 * s + kq) * PITCH + 16 + cl], acc1);
-    }
+    for (int s = 0; s < KC / 4; ++s)
+#pragma unroll
+      for (int t = 0; t < CT; ++t) acc[t] = Mfma<TO>::mac(a[s], B[(4 * s + kq) * PITCH + t * 16 + cl], acc[t]);
     if (more) {
       store_b(buf ^ 1);
 #pragma unroll
@@ -426,10 +428,10 @@ __global__ __launch_bounds__(256) void k_half_gemm_t(
     }
     __syncthreads();
   }
-  // epilogue: lane holds rows Mfma::row(lane, j) of windows cl and 16 + cl
+  // epilogue: lane holds rows Mfma::row(lane, j) of windows t * 16 + cl
   const int slot = rg * 4 + wave;
 #pragma unroll
-  for (int t = 0; t < 2; ++t) {
+  for (int t = 0; t < CT; ++t) {
     const int v = t * 16 + cl;
     const bool ok = v < wk.vcount && wi[v].live;
     double part = 0.0;
@@ -437,7 +439,7 @@ __global__ __launch_bounds__(256) void k_half_gemm_t(
     for (int j = 0; j < 4; ++j) {
       const int row = rg * 64 + wave * 16 + Mfma<TO>::row(lane, j);
       if (ok && row < N) {
-        TO val = t == 0 ? acc0[j] : acc1[j];
+        TO val = acc[t][j];
         if (wk.ident) val += (TO)xbase[wi[v].xoff + wi[v].xh + row];
         const TY out = (TY)((double)val * wi[v].scale);
         ybase[wi[v].y + row] = out;

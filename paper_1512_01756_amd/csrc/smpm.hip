@@ -91,7 +91,7 @@ struct smpm_handle {
   smpm_opts opts{};
   int nrhs = 1, maxit = 300, precision = SMPM_FP64, method = SMPM_METHOD_DBJ, max_sweeps = 12;
   double tol = 1e-10, inner_tol = 1e-4;
-  bool host_only = false;
+  bool host_only = false, no_tune = false;
   std::vector<System> sys;
 
   std::vector<void *> owned;
@@ -109,6 +109,11 @@ struct smpm_handle {
   GVec *g_vec = nullptr;
   int2 *u_S = nullptr, *u_M = nullptr;   // XCD-ordered (item, 64-row tile) lists of g_S, g_M
   int n_uS = 0, n_uM = 0;
+  // GEMM schedule of each batched list, picked at setup by timing every
+  // candidate: [op][precision] for the matvec lists, [kind][width] for the
+  // element-interior lists.
+  int sched[2][2] = {};
+  int cg_sched[3][2] = {};
   int n_gS = 0, n_gM = 0;
   std::vector<int> gSi_start, gSi_cnt, gMi_start, gMi_cnt;
   HWork *w_S1 = nullptr, *w_M1 = nullptr;   // single items (streamed blocks)
@@ -417,12 +422,13 @@ void upload(smpm_handle *H, hipStream_t st) {
   {
     std::vector<GWork> gS, gM, gSi, gMi;
     std::vector<GVec> gv;
+    // items of one stored block over its windows, kGemmVecs windows each
     auto emit = [&](int si, int op, int id, const std::vector<int2> &vecs, std::vector<GWork> &out) {
       const System &s = H->sys[si];
       const SysDev &d = H->h_sys[si];
       const int N = s.N, slots = (N + 15) / 16;
       const int K = op == 0 ? 2 * N : s.m_K[vecs[0].y];
-      for (size_t a = 0; a < vecs.size(); a += kGemmVecs) {
+      for (size_t a = 0; a < vecs.size();) {
         GWork w{};
         w.blk64 = (op == 0 ? d.W64 : d.M64) + (size_t)id * (op == 0 ? 2 : 4) * N * d.Np;
         w.blk32 = (op == 0 ? d.W32 : d.M32) + (size_t)id * (op == 0 ? 2 : 4) * N * d.Np;
@@ -443,8 +449,10 @@ void upload(smpm_handle *H, hipStream_t st) {
           gv.push_back(e);
         }
         out.push_back(w);
+        a += w.vcount;
       }
     };
+
     for (int si = 0; si < (int)H->sys.size(); ++si) {
       const System &s = H->sys[si];
       for (int op = 0; op < 2; ++op) {
@@ -528,6 +536,44 @@ void upload(smpm_handle *H, hipStream_t st) {
 // ---------------------------------------------------------------------------
 // Launch helpers.  `inst` >= 0 restricts a launch to one instance's items.
 
+// GEMM schedules of the shared-block matvec (see the kernels): split K over
+// 16 or 8 waves per 16-row tile, or the LDS-staged 64-row tile in XCD-aware
+// or plain order.
+enum GemmSched { kSplit16 = 0, kSplit8 = 1, kThrXcd = 2, kThrPlain = 3, kNumSched = 4 };
+
+// Default schedule when none was tuned (per-instance lists): by launch size.
+int gemm_default(int count, int rt16) {
+  if ((int64_t)count * rt16 < 512) return kSplit16;
+  if ((int64_t)count * rt16 < 2048) return kSplit8;
+  return kThrPlain;
+}
+
+template <typename TO, typename TX, typename TY>
+void gemm_launch(smpm_handle *H, int sched, const GWork *w, int count, const int2 *units, int nunits, const TX *x,
+                 int vslot, const double *scale, TY *y, double *hsum, const GState *gs, hipStream_t st) {
+  const int rt16 = (H->Nmax + 15) / 16;
+  switch (sched) {
+    case kSplit16:
+      hipLaunchKernelGGL((k_half_gemm<TO, TX, TY, 16>), dim3(count, rt16), dim3(1024), 0, st, w, H->g_vec, x, vslot,
+                         scale, y, hsum, gs);
+      break;
+    case kSplit8:
+      hipLaunchKernelGGL((k_half_gemm<TO, TX, TY, 8>), dim3(count, rt16), dim3(512), 0, st, w, H->g_vec, x, vslot,
+                         scale, y, hsum, gs);
+      break;
+    case kThrXcd:
+      if (units) {
+        hipLaunchKernelGGL((k_half_gemm_t<TO, TX, TY, 2>), dim3(nunits), dim3(256), 0, st, w, units, H->g_vec, x, vslot,
+                           scale, y, hsum, gs);
+        break;
+      }
+      [[fallthrough]];
+    default:
+      hipLaunchKernelGGL((k_half_gemm_t<TO, TX, TY, 2>), dim3(count, (H->Nmax + 63) / 64), dim3(256), 0, st, w,
+                         (const int2 *)nullptr, H->g_vec, x, vslot, scale, y, hsum, gs);
+  }
+}
+
 template <typename TO, typename TX, typename TY>
 void gemv(smpm_handle *H, int op, const TX *x, int vslot, const double *scale, TY *y, double *hsum,
           const GState *gs, hipStream_t st, int inst = -1) {
@@ -541,19 +587,10 @@ void gemv(smpm_handle *H, int op, const TX *x, int vslot, const double *scale, T
       count = op == 0 ? H->gSi_cnt[inst] : H->gMi_cnt[inst];
     }
     if (count > 0) {
-      const int rt16 = (H->Nmax + 15) / 16;
-      if ((int64_t)count * rt16 < 512)     // few items: split K over 16 waves
-        hipLaunchKernelGGL((k_half_gemm<TO, TX, TY, 16>), dim3(count, rt16), dim3(1024), 0, st, w, H->g_vec, x, vslot,
-                           scale, y, hsum, gs);
-      else if ((int64_t)count * rt16 < 2048)
-        hipLaunchKernelGGL((k_half_gemm<TO, TX, TY, 8>), dim3(count, rt16), dim3(512), 0, st, w, H->g_vec, x, vslot,
-                           scale, y, hsum, gs);
-      else if (inst < 0)
-        hipLaunchKernelGGL((k_half_gemm_t<TO, TX, TY>), dim3(op == 0 ? H->n_uS : H->n_uM), dim3(256), 0, st, w,
-                           (const int2 *)(op == 0 ? H->u_S : H->u_M), H->g_vec, x, vslot, scale, y, hsum, gs);
-      else
-        hipLaunchKernelGGL((k_half_gemm_t<TO, TX, TY>), dim3(count, (H->Nmax + 63) / 64), dim3(256), 0, st, w,
-                           (const int2 *)nullptr, H->g_vec, x, vslot, scale, y, hsum, gs);
+      const int prec = sizeof(TO) == 8 ? 0 : 1;
+      const int sched = inst < 0 ? H->sched[op][prec] : gemm_default(count, (H->Nmax + 15) / 16);
+      gemm_launch<TO, TX, TY>(H, sched, w, count, inst < 0 ? (op == 0 ? H->u_S : H->u_M) : nullptr,
+                              op == 0 ? H->n_uS : H->n_uM, x, vslot, scale, y, hsum, gs, st);
     }
   }
   // halves with their own block: streaming kernel
@@ -576,13 +613,17 @@ void gemv(smpm_handle *H, int op, const TX *x, int vslot, const double *scale, T
 
 // dst = A(k)^-1 src (node space; src and dst must not overlap): element
 // solves, the per-strip z-interface capacitance solve, element corrections.
+// Element-interior GEMM schedules: split K (kSplit8) or the LDS-staged
+// 64-row tile (kThrXcd with units, kThrPlain without).  sched < 0: by size.
 template <int CT>
 void colgemm_w(smpm_handle *H, const CGItem *items, int count, const int2 *units, int nunits, int mode,
-               const double *x, double *y, hipStream_t st) {
+               const double *x, double *y, hipStream_t st, int sched = -1) {
   if (count <= 0) return;
   const int rmax = std::max(H->n2_max, H->nq_max);
   const int rt16 = (rmax + 15) / 16;
-  if ((int64_t)count * rt16 < 1024) {     // few items: split K for parallelism
+  if (sched < 0) sched = (int64_t)count * rt16 < 1024 ? kSplit8 : kThrXcd;
+  if (sched == kThrPlain) units = nullptr;
+  if (sched == kSplit8 || sched == kSplit16) {     // split K for parallelism
     const dim3 grid(count, rt16);
     if (mode == 0) hipLaunchKernelGGL((k_colgemm<CT, 0>), grid, dim3(512), 0, st, items, H->cg_cols, x, y);
     else hipLaunchKernelGGL((k_colgemm<CT, 1>), grid, dim3(512), 0, st, items, H->cg_cols, x, y);
@@ -600,8 +641,9 @@ void colgemm(smpm_handle *H, int kind, int inst, int mode, const double *x, doub
     const int cnt = inst >= 0 ? H->cg_cnt[kind][w][inst] : H->n_cg_all[kind][w];
     const int2 *un = inst >= 0 ? nullptr : H->cg_units[kind][w];
     const int nun = inst >= 0 ? 0 : H->n_cg_units[kind][w];
-    if (w == 0) colgemm_w<1>(H, it, cnt, un, nun, mode, x, y, st);
-    else colgemm_w<kColVecs / 16>(H, it, cnt, un, nun, mode, x, y, st);
+    const int sc = inst >= 0 ? -1 : H->cg_sched[kind][w];
+    if (w == 0) colgemm_w<1>(H, it, cnt, un, nun, mode, x, y, st, sc);
+    else colgemm_w<kColVecs / 16>(H, it, cnt, un, nun, mode, x, y, st, sc);
   }
 }
 
@@ -616,6 +658,95 @@ void ainv(smpm_handle *H, const double *src, double *dst, hipStream_t st, int in
     colgemm(H, 1, inst, 0, H->lam, H->qb, st);
     colgemm(H, 2, inst, 1, H->qb, dst, st);
   }
+}
+
+// Setup-time autotuning of the GEMM schedules: every candidate schedule of
+// every batched list is timed with HIP events on zeroed operands (2 warm-up
+// and 5 timed launches) and the fastest is kept for the handle's lifetime.
+// Without tuning, schedules follow the launch size.
+template <typename F>
+float time_launch(hipStream_t st, hipEvent_t e0, hipEvent_t e1, F &&fn) {
+  for (int r = 0; r < 2; ++r) fn();
+  HIPCHECK(hipEventRecord(e0, st));
+  for (int r = 0; r < 5; ++r) fn();
+  HIPCHECK(hipEventRecord(e1, st));
+  HIPCHECK(hipEventSynchronize(e1));
+  float ms = 0.f;
+  HIPCHECK(hipEventElapsedTime(&ms, e0, e1));
+  return ms;
+}
+
+void tune(smpm_handle *H, hipStream_t st) {
+  const int rt16 = (H->Nmax + 15) / 16;
+  for (int op = 0; op < 2; ++op)
+    for (int pr = 0; pr < 2; ++pr) H->sched[op][pr] = gemm_default(op == 0 ? H->n_gS : H->n_gM, rt16);
+  for (int k = 0; k < 3; ++k)
+    for (int w = 0; w < 2; ++w) H->cg_sched[k][w] = -1;
+  if (H->no_tune) return;
+  const int rmax = std::max(H->n2_max, H->nq_max);
+  for (int k = 0; k < 3; ++k)
+    for (int w = 0; w < 2; ++w)
+      H->cg_sched[k][w] = (int64_t)H->n_cg_all[k][w] * ((rmax + 15) / 16) < 1024 ? kSplit8 : kThrXcd;
+  hipEvent_t e0, e1;
+  HIPCHECK(hipEventCreate(&e0));
+  HIPCHECK(hipEventCreate(&e1));
+  try {
+    HIPCHECK(hipMemsetAsync(H->t64, 0, sizeof(double) * H->tot_x, st));
+    HIPCHECK(hipMemsetAsync(H->t32, 0, sizeof(float) * H->tot_x, st));
+    HIPCHECK(hipMemsetAsync(H->F, 0, sizeof(double) * H->tot_r, st));
+    HIPCHECK(hipMemsetAsync(H->v, 0, sizeof(double) * H->tot_r, st));
+    if (H->nq_max > 0) {
+      int64_t nl = 0;
+      for (const InstDev &I : H->h_ins) nl = std::max<int64_t>(nl, I.lam_off + (int64_t)H->sys[I.sys].mx * H->h_sys[I.sys].nq);
+      HIPCHECK(hipMemsetAsync(H->lam, 0, sizeof(double) * nl, st));
+      HIPCHECK(hipMemsetAsync(H->qb, 0, sizeof(double) * nl, st));
+    }
+    for (int op = 0; op < 2; ++op) {
+      const int count = op == 0 ? H->n_gS : H->n_gM;
+      if (count == 0) continue;
+      const GWork *w = op == 0 ? H->g_S : H->g_M;
+      const int2 *u = op == 0 ? H->u_S : H->u_M;
+      const int nu = op == 0 ? H->n_uS : H->n_uM;
+      for (int pr = 0; pr < 2; ++pr) {
+        float best = 1e30f;
+        for (int sc = 0; sc < kNumSched; ++sc) {
+          const float ms = pr == 0
+              ? time_launch(st, e0, e1, [&] {
+                  gemm_launch<double, double, double>(H, sc, w, count, u, nu, H->t64, 0, nullptr, H->y64,
+                                                      op == 0 ? H->hs : nullptr, nullptr, st);
+                })
+              : time_launch(st, e0, e1, [&] {
+                  gemm_launch<float, float, float>(H, sc, w, count, u, nu, H->t32, 0, nullptr, H->y32,
+                                                   op == 0 ? H->hs : nullptr, nullptr, st);
+                });
+          if (ms < best) { best = ms; H->sched[op][pr] = sc; }
+        }
+      }
+    }
+    const int cand[3] = {kSplit8, kThrXcd, kThrPlain};
+    for (int k = 0; k < 3; ++k)
+      for (int w = 0; w < 2; ++w) {
+        const int cnt = H->n_cg_all[k][w];
+        if (cnt == 0) continue;
+        const double *x = k == 0 ? H->F : (k == 1 ? H->lam : H->qb);
+        double *y = k == 0 ? H->v : (k == 1 ? H->qb : H->v);
+        float best = 1e30f;
+        for (int sc : cand) {
+          const float ms = time_launch(st, e0, e1, [&] {
+            if (w == 0) colgemm_w<1>(H, H->cg_all[k][w], cnt, H->cg_units[k][w], H->n_cg_units[k][w], k == 2 ? 1 : 0, x, y, st, sc);
+            else colgemm_w<kColVecs / 16>(H, H->cg_all[k][w], cnt, H->cg_units[k][w], H->n_cg_units[k][w], k == 2 ? 1 : 0, x, y, st, sc);
+          });
+          if (ms < best) { best = ms; H->cg_sched[k][w] = sc; }
+        }
+      }
+    HIPCHECK(hipGetLastError());
+  } catch (...) {
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    throw;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
 }
 
 const int2 *xwork(smpm_handle *H, int inst, int &count) {
@@ -839,6 +970,7 @@ smpm_status validate_opts(const smpm_opts *o, smpm_handle *H) {
   H->inner_tol = d.inner_tol > 0 ? d.inner_tol : 1e-4;
   H->max_sweeps = d.max_sweeps > 0 ? d.max_sweeps : 12;
   H->host_only = (d.flags & SMPM_FLAG_HOST_ONLY) != 0;
+  H->no_tune = (d.flags & SMPM_FLAG_NO_TUNE) != 0;
   if (d.tol < 0 || d.max_iter < 0 || d.nrhs < 0 || d.inner_tol < 0 || d.max_sweeps < 0)
     return fail(SMPM_EINVAL, "negative option value");
   if (H->maxit > 2000) return fail(SMPM_EINVAL, "max_iter above 2000");
@@ -890,6 +1022,7 @@ smpm_status setup_common(const smpm_grid *grids, const double *k, int nsys, bool
   if (!H->host_only) {
     try {
       upload(H.get(), (hipStream_t)stream);
+      tune(H.get(), (hipStream_t)stream);
     } catch (const std::bad_alloc &) {
       return fail(SMPM_ENOMEM, "device allocation failed in setup");
     } catch (const std::exception &e) {
@@ -1128,6 +1261,11 @@ smpm_status smpm_query(const smpm_handle *H, int32_t sysi, smpm_info *info) {
   o.unique_W = s.nW; o.unique_M = s.nM;
   o.bytes_W64 = (int64_t)s.nW * s.N * 2 * s.N * 8;   // distinct Schur half blocks, FP64
   o.bytes_M64 = (int64_t)s.nM * s.N * 4 * s.N * 8;   // distinct block-Jacobi row chunks, FP64
+  for (int op = 0; op < 2; ++op)
+    for (int pr = 0; pr < 2; ++pr)
+      o.gemm_sched[2 * op + pr] = (op == 0 ? H->n_gS : H->n_gM) > 0 ? H->sched[op][pr] : -1;
+  for (int k = 0; k < 3; ++k)
+    for (int w = 0; w < 2; ++w) o.elem_sched[2 * k + w] = H->n_cg_all[k][w] > 0 ? H->cg_sched[k][w] : -1;
   *info = o;
   return SMPM_OK;
 }
