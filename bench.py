@@ -149,7 +149,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
-              "(strips would shard across GPUs; see DESIGN.md)", file=sys.stderr)
+              "(the 2-D path would shard its strips across GPUs)", file=sys.stderr)
         sys.exit(2)
 
     import torch

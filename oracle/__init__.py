@@ -22,6 +22,8 @@ schur    strip blocks of S = I + B A^-1 E (Eq. operator_decomp), block-Jacobi
 gmres    GMRES with Householder Arnoldi (Sec. 3.1)
 solve    Algorithm 2 (DBJ-Schur), per-mode Helmholtz (Sec. 5), the dense direct
          solve used to pin it, and FP32-inner iterative refinement emulation
+fourier  the 3-D problem through a Fourier series in y (Sec. 5): transforms
+         and the mode-by-mode solve
 
 Parity status: every function is pinned by a test in ``tests/test_oracle_*``
 (printed GLL nodes, closed forms, manufactured solutions, dense direct solves,

@@ -1,0 +1,64 @@
+"""The 3-D problem through a Fourier series in the periodic y direction
+(Sec. 5) (oracle).
+
+Test infrastructure: see the package docstring.
+
+With u(x, y, z) = sum_m u_m(x, z) exp(i k_m y), k_m = 2 pi m / L_y, on m_y
+equispaced points y_j = j L_y / m_y, every mode solves the 2-D Helmholtz
+problem (L - k_m^2 I) u_m = f_m (Sec. 5).  The field is real, so only
+m = 0 .. m_y/2 are solved and Re, Im of each mode are two real right-hand
+sides of the same real operator.  Coefficients are normalized by 1/m_y:
+
+  f_m = (1/m_y) sum_j f(y_j) exp(-2 pi i m j / m_y)      (forward)
+  u(y_j) = sum over m of u_m exp(2 pi i m j / m_y)       (inverse, with
+           u_{-m} = conj(u_m))
+
+Both directions use numpy's real FFT.
+"""
+import numpy as np
+
+from . import schur, smpm, solve
+
+
+def wavenumbers(my, ly):
+    """k_m = 2 pi m / L_y for m = 0 .. m_y // 2."""
+    return 2.0 * np.pi * np.arange(my // 2 + 1) / ly
+
+
+def forward(fphys):
+    """(m_y, ...) physical samples -> (m_y//2 + 1, 2, ...) [Re, Im] coefficients."""
+    my = fphys.shape[0]
+    fh = np.fft.rfft(fphys, axis=0) / my
+    return np.stack([fh.real, fh.imag], axis=1)
+
+
+def inverse(uhat, my):
+    """(m_y//2 + 1, 2, ...) [Re, Im] coefficients -> (m_y, ...) physical samples."""
+    c = (uhat[:, 0] + 1j * uhat[:, 1]) * my
+    return np.fft.irfft(c, n=my, axis=0)
+
+
+def solve3d(xb, zb, n, fphys, ly, gphys=None, method="dbj", tol=1e-10):
+    """Solve the 3-D Poisson-Neumann problem mode by mode (Alg. 2 per mode).
+
+    fphys: (m_y, r) node values per y-plane; gphys: None or a dict of side
+    arrays (m_y, m_x or m_z, n) for S, N, W, E.  Returns (u, results) with u of
+    shape (m_y, r); the k = 0 mode carries the zero-mean gauge."""
+    my = fphys.shape[0]
+    grid = smpm.Grid(np.asarray(xb, float), np.asarray(zb, float), n)
+    fh = forward(fphys)
+    gh = {side: forward(arr) for side, arr in gphys.items()} if gphys else None
+    uh = np.zeros_like(fh)
+    results = []
+    for m, k in enumerate(wavenumbers(my, ly)):
+        o = schur.build(grid, kwave=float(k))
+        for q in range(2):
+            g = {side: arr[m, q] for side, arr in gh.items()} if gh else None
+            F = smpm.rhs(grid, o.tau, fh[m, q], g)
+            if not np.any(F):
+                results.append(None)
+                continue
+            res = solve.dbj_solve(o, F, method=method, tol=tol)
+            uh[m, q] = res.u
+            results.append(res)
+    return inverse(uh, my), results

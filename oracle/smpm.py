@@ -97,7 +97,7 @@ class Grid:
 
 
 def default_tau(grid):
-    """One global penalty value (readings): tau = -n(n-1)/h_min,
+    """One global penalty value, a reading of Sec. 2.2: tau = -n(n-1)/h_min,
     h_min the smallest element width or height."""
     n = grid.n
     hmin = min(np.min(np.diff(grid.xb)), np.min(np.diff(grid.zb)))
