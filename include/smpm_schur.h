@@ -159,6 +159,24 @@ smpm_status smpm_setup(const smpm_grid *grid, const double *k, int32_t nk,
 smpm_status smpm_setup_batch(const smpm_grid *grids, const double *k, int32_t nprob,
                              const smpm_opts *opts, void *hip_stream, smpm_handle **out);
 
+/* The 3-D problem, periodic in y (Sec. 5, Alg. 3): m_y equispaced planes
+ * y_j = j l_y / m_y.  One system per Fourier mode m = 0 .. m_y/2 with
+ * k_m = 2 pi m / l_y, and two real right-hand sides (Re, Im) per mode (the
+ * operator is real), so opts->nrhs must be 0 or 2.  m_y >= 2, l_y > 0. */
+smpm_status smpm_setup_fourier(const smpm_grid *grid, int32_t my, double ly, const smpm_opts *opts,
+                               void *hip_stream, smpm_handle **out);
+
+/* Physical-space solve on a handle from smpm_setup_fourier.  f_dev: FP64
+ * [m_y][r], plane j in the node layout; g_dev: FP64 [m_y][2 n (m_x + m_z)],
+ * plane j in the side layout (S | N | W | E), or NULL; u_dev: FP64 [m_y][r].
+ * The coefficients f_m = (1/m_y) sum_j f_j exp(-2 pi i m j / m_y) are solved
+ * mode by mode with smpm_solve's Algorithm 2 (batched), and u_j is the real
+ * Fourier series at y_j.  The k = 0 mode carries the zero-mean gauge.
+ * Statuses and stats as for smpm_solve (counted over the 2 (m_y/2 + 1) real
+ * instances); EINVAL on a handle not made by smpm_setup_fourier. */
+smpm_status smpm_solve_fourier(smpm_handle *h, const double *f_dev, const double *g_dev, double *u_dev,
+                               void *hip_stream, smpm_stats *stats);
+
 /* Algorithm 2 for every instance: f_dev (FP64, batched node layout), g_dev
  * (FP64, batched side layout, or NULL for g = 0) -> u_dev (FP64, batched node
  * layout, zero nodal mean for k = 0).  stats (host, nullable) is filled after

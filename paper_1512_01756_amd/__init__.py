@@ -71,8 +71,9 @@ class Info(ctypes.Structure):
         return out
 
 
-EXPORTED = ["smpm_setup", "smpm_setup_batch", "smpm_solve", "smpm_apply", "smpm_schur_apply_all",
-            "smpm_query", "smpm_num_systems", "smpm_export", "smpm_destroy", "smpm_last_error"]
+EXPORTED = ["smpm_setup", "smpm_setup_batch", "smpm_setup_fourier", "smpm_solve", "smpm_solve_fourier",
+            "smpm_apply", "smpm_schur_apply_all", "smpm_query", "smpm_num_systems", "smpm_export", "smpm_destroy",
+            "smpm_last_error"]
 
 _lib = None
 
@@ -91,7 +92,10 @@ def load():
     lib.smpm_setup.argtypes = [ctypes.POINTER(Grid), ctypes.POINTER(ctypes.c_double), ctypes.c_int32,
                                ctypes.POINTER(Opts), P, ctypes.POINTER(P)]
     lib.smpm_setup_batch.argtypes = lib.smpm_setup.argtypes
+    lib.smpm_setup_fourier.argtypes = [ctypes.POINTER(Grid), ctypes.c_int32, ctypes.c_double, ctypes.POINTER(Opts),
+                                       P, ctypes.POINTER(P)]
     lib.smpm_solve.argtypes = [P, P, P, P, P, ctypes.POINTER(Stats)]
+    lib.smpm_solve_fourier.argtypes = lib.smpm_solve.argtypes
     lib.smpm_apply.argtypes = [P, ctypes.c_int32, ctypes.c_int32, P, P, ctypes.c_int32, P]
     lib.smpm_schur_apply_all.argtypes = [P, P, P, ctypes.c_int32, P]
     lib.smpm_query.argtypes = [P, ctypes.c_int32, ctypes.POINTER(Info)]
@@ -101,8 +105,8 @@ def load():
     lib.smpm_destroy.argtypes = [P]
     lib.smpm_destroy.restype = None
     lib.smpm_last_error.restype = ctypes.c_char_p
-    for name in ("smpm_setup", "smpm_setup_batch", "smpm_solve", "smpm_apply", "smpm_schur_apply_all",
-                 "smpm_query", "smpm_export"):
+    for name in ("smpm_setup", "smpm_setup_batch", "smpm_setup_fourier", "smpm_solve", "smpm_solve_fourier",
+                 "smpm_apply", "smpm_schur_apply_all", "smpm_query", "smpm_export"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -125,12 +129,16 @@ def _stream(stream):
 
 
 class Solver:
-    """One handle: one grid with several wavenumbers (`kwaves`), or a batch of
-    independent problems (`grids` list with one wavenumber each)."""
+    """One handle: one grid with several wavenumbers (`kwaves`), a batch of
+    independent problems (`grids` list with one wavenumber each), or a 3-D
+    problem periodic in y (`fourier=(m_y, l_y)`: modes k_m = 2 pi m / l_y,
+    m = 0 .. m_y/2, Re and Im as two right-hand sides)."""
 
     def __init__(self, xb=None, zb=None, order=None, kwaves=(0.0,), grids=None, tau=0.0, tol=1e-10,
                  max_iter=300, nrhs=1, precision=FP64, method=METHOD_DBJ, inner_tol=0.0, max_sweeps=0,
-                 host_only=False, tune=True, stream=None):
+                 host_only=False, tune=True, fourier=None, stream=None):
+        if fourier is not None:
+            nrhs = 2
         lib = load()
         self._lib = lib
         self.host_only = host_only
@@ -140,7 +148,12 @@ class Solver:
         self._keep = []
         h = ctypes.c_void_p()
         st = ctypes.c_void_p(0) if host_only else _stream(stream)
-        if grids is None:
+        self.fourier = fourier
+        if fourier is not None:
+            g = self._grid(xb, zb, order)
+            _check(lib.smpm_setup_fourier(ctypes.byref(g), int(fourier[0]), float(fourier[1]), ctypes.byref(opts),
+                                          st, ctypes.byref(h)))
+        elif grids is None:
             g = self._grid(xb, zb, order)
             k = np.ascontiguousarray(np.asarray(kwaves, dtype=np.float64))
             self._keep.append(k)
@@ -189,6 +202,18 @@ class Solver:
             u = torch.empty_like(f)
         stats = Stats()
         status = self._lib.smpm_solve(self.h, _ptr(f), _ptr(g), _ptr(u), _stream(stream), ctypes.byref(stats))
+        if check:
+            _check(status)
+        return u, stats.as_dict(), status
+
+    def solve_fourier(self, f, g=None, u=None, stream=None, check=True):
+        """Physical-space 3-D solve: f, u torch float64 CUDA tensors [m_y, r];
+        g None or [m_y, 2 n (m_x + m_z)]."""
+        import torch
+        if u is None:
+            u = torch.empty_like(f)
+        stats = Stats()
+        status = self._lib.smpm_solve_fourier(self.h, _ptr(f), _ptr(g), _ptr(u), _stream(stream), ctypes.byref(stats))
         if check:
             _check(status)
         return u, stats.as_dict(), status

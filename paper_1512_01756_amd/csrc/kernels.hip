@@ -1400,6 +1400,72 @@ __global__ __launch_bounds__(kBlock) void k_reduce_pairs(const InstDev *__restri
   if (threadIdx.x == 0) { out[2 * i] = a; out[2 * i + 1] = b; }
 }
 
+// The transform in the periodic y direction of the 3-D problem (Sec. 5) as a
+// dense product: C[M x ncol] = A[M x K] B[K x ncol], all row-major FP64.  A is
+// the small real DFT (or inverse DFT) matrix, B and C stream one row per y
+// plane (or per mode and Re/Im part), so the kernel is bound by HBM.  Grid
+// (ceil(ncol / 64), ceil(M / (16 kDftTiles))); wave w owns 16 columns, lane
+// layout as for the other MFMA kernels; up to kDftTiles row tiles per wave.
+// K runs in chunks of 32: the chunk of A is staged in LDS, and the next
+// chunk's B values are loaded into registers while this chunk's MFMAs run.
+constexpr int kDftTiles = 10;
+__global__ __launch_bounds__(256) void k_dft_gemm(const double *__restrict__ A, int M, int K,
+                                                  const double *__restrict__ B, double *__restrict__ C, int64_t ncol) {
+  constexpr int KC = 32, PA = KC + 1;
+  __shared__ double As[kDftTiles * 16 * PA];
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int kq = lane >> 4, cl = lane & 15;
+  const int64_t col = (int64_t)blockIdx.x * 64 + wave * 16 + cl;
+  const bool cin = col < ncol;
+  const int t0 = blockIdx.y * kDftTiles;
+  const int nt = min(kDftTiles, (M + 15) / 16 - t0);
+  if (nt <= 0) return;
+  const int row0 = t0 * 16;
+  using Acc = Mfma<double>::Acc;
+  Acc acc[kDftTiles];
+#pragma unroll
+  for (int t = 0; t < kDftTiles; ++t) acc[t] = Acc{0, 0, 0, 0};
+  double bv[KC / 4], bn[KC / 4];
+  auto load_b = [&](int k0, double *dst) {
+#pragma unroll
+    for (int s = 0; s < KC / 4; ++s) {
+      const int k = k0 + 4 * s + kq;
+      dst[s] = (cin && k < K) ? B[(int64_t)k * ncol + col] : 0.0;
+    }
+  };
+  load_b(0, bv);
+  for (int k0 = 0; k0 < K; k0 += KC) {
+    __syncthreads();
+    for (int idx = threadIdx.x; idx < nt * 16 * KC; idx += 256) {
+      const int rr = idx / KC, kk = idx - rr * KC;
+      const int row = row0 + rr, k = k0 + kk;
+      As[rr * PA + kk] = (row < M && k < K) ? A[(int64_t)row * K + k] : 0.0;
+    }
+    __syncthreads();
+    const bool more = k0 + KC < K;
+    if (more) load_b(k0 + KC, bn);
+#pragma unroll
+    for (int s = 0; s < KC / 4; ++s) {
+#pragma unroll
+      for (int t = 0; t < kDftTiles; ++t)
+        if (t < nt) acc[t] = Mfma<double>::mac(As[(t * 16 + cl) * PA + 4 * s + kq], bv[s], acc[t]);
+    }
+    if (more) {
+#pragma unroll
+      for (int s = 0; s < KC / 4; ++s) bv[s] = bn[s];
+    }
+  }
+#pragma unroll
+  for (int t = 0; t < kDftTiles; ++t) {
+    if (t >= nt) continue;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int row = (t0 + t) * 16 + Mfma<double>::row(lane, j);
+      if (row < M && cin) C[(int64_t)row * ncol + col] = acc[t][j];
+    }
+  }
+}
+
 // p[0, n) = v.
 __global__ __launch_bounds__(kBlock) void k_fill(double *__restrict__ p, int64_t n, double v) {
   const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;

@@ -161,6 +161,12 @@ struct smpm_handle {
   // Iteration chunks launched before the first convergence check, from the
   // previous solve's iteration count.
   int pred_chunks[2] = {1, 1};
+  // 3-D problems (smpm_setup_fourier): m_y planes, the forward and inverse
+  // real DFT matrices ([2 nk][m_y] and [m_y][2 nk], row-major), and the
+  // coefficient buffers of f, g, u in the batched layouts.
+  int my = 0;
+  double ly = 0.0;
+  double *dft_f = nullptr, *dft_i = nullptr, *fhat = nullptr, *ghat = nullptr, *uhat = nullptr;
   GState *h_gs_hist = nullptr;   // pinned, [sweep][instance]
   double *h_nb = nullptr;        // pinned, ||b~||^2 and u_S . b~ per instance
 
@@ -1045,6 +1051,80 @@ smpm_status smpm_setup(const smpm_grid *grid, const double *k, int32_t nk, const
 smpm_status smpm_setup_batch(const smpm_grid *grids, const double *k, int32_t nprob, const smpm_opts *opts,
                              void *hip_stream, smpm_handle **out) {
   return setup_common(grids, k, nprob, false, opts, hip_stream, out);
+}
+
+smpm_status smpm_setup_fourier(const smpm_grid *grid, int32_t my, double ly, const smpm_opts *opts,
+                               void *hip_stream, smpm_handle **out) {
+  if (!out) return fail(SMPM_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (my < 2 || !(ly > 0.0) || !std::isfinite(ly)) return fail(SMPM_EINVAL, "need m_y >= 2 and l_y > 0");
+  smpm_opts o{};
+  if (opts) o = *opts;
+  if (o.nrhs != 0 && o.nrhs != 2) return fail(SMPM_EINVAL, "a Fourier handle has nrhs = 2 (Re, Im)");
+  o.nrhs = 2;
+  const int nk = my / 2 + 1;
+  std::vector<double> k(nk);
+  for (int m = 0; m < nk; ++m) k[m] = 2.0 * M_PI * m / ly;
+  smpm_handle *H = nullptr;
+  smpm_status st = setup_common(grid, k.data(), nk, true, &o, hip_stream, &H);
+  if (st != SMPM_OK) return st;
+  H->my = my;
+  H->ly = ly;
+  if (!H->host_only) {
+    try {
+      // forward: f_m = (1/m_y) sum_j f_j (cos - i sin)(2 pi m j / m_y)
+      // inverse: u_j = sum_m w_m (Re u_m cos - Im u_m sin)(2 pi m j / m_y),
+      //          w_0 = 1, w_{m_y/2} = 1 for even m_y, else 2
+      std::vector<double> F((size_t)2 * nk * my), I((size_t)my * 2 * nk);
+      for (int m = 0; m < nk; ++m) {
+        const double w = (m == 0 || (my % 2 == 0 && m == my / 2)) ? 1.0 : 2.0;
+        for (int j = 0; j < my; ++j) {
+          const double th = 2.0 * M_PI * (double)(((int64_t)m * j) % my) / my;
+          F[(size_t)(2 * m) * my + j] = std::cos(th) / my;
+          F[(size_t)(2 * m + 1) * my + j] = -std::sin(th) / my;
+          I[(size_t)j * 2 * nk + 2 * m] = w * std::cos(th);
+          I[(size_t)j * 2 * nk + 2 * m + 1] = -w * std::sin(th);
+        }
+      }
+      hipStream_t s0 = (hipStream_t)hip_stream;
+      H->dft_f = dupload(H->owned, F, s0);
+      H->dft_i = dupload(H->owned, I, s0);
+      H->fhat = dalloc<double>(H->owned, H->tot_r);
+      H->uhat = dalloc<double>(H->owned, H->tot_r);
+      H->ghat = dalloc<double>(H->owned, H->tot_g);
+      HIPCHECK(hipStreamSynchronize(s0));
+    } catch (const std::exception &e) {
+      delete H;
+      return fail(SMPM_ENOMEM, e.what());
+    }
+  }
+  *out = H;
+  return SMPM_OK;
+}
+
+smpm_status smpm_solve_fourier(smpm_handle *H, const double *f, const double *g, double *u, void *hip_stream,
+                               smpm_stats *stats) {
+  if (!H) return fail(SMPM_EINVAL, "handle is NULL");
+  if (H->my == 0) return fail(SMPM_EINVAL, "not a Fourier handle (smpm_setup_fourier)");
+  if (H->host_only) return fail(SMPM_EUNSUPPORTED, "host-only handle");
+  if (!f || !u) return fail(SMPM_EINVAL, "f or u is NULL");
+  hipStream_t st = (hipStream_t)hip_stream;
+  const int nk2 = 2 * (H->my / 2 + 1);
+  const System &s0 = H->sys[0];
+  const int64_t r = s0.r, gsz = 2LL * s0.n * (s0.mx + s0.mz);
+  auto dft = [&](const double *A, int M, int K, const double *B, double *C, int64_t ncol) {
+    const dim3 grid((unsigned)((ncol + 63) / 64), (unsigned)(((M + 15) / 16 + kDftTiles - 1) / kDftTiles));
+    hipLaunchKernelGGL(k_dft_gemm, grid, dim3(256), 0, st, A, M, K, B, C, ncol);
+  };
+  dft(H->dft_f, nk2, H->my, f, H->fhat, r);
+  if (g) dft(H->dft_f, nk2, H->my, g, H->ghat, gsz);
+  if (hipGetLastError() != hipSuccess) return fail(SMPM_EHIP, "transform launch failed");
+  const smpm_status status = smpm_solve(H, H->fhat, g ? H->ghat : nullptr, H->uhat, hip_stream, stats);
+  if (status == SMPM_OK || status == SMPM_ENOTCONV || status == SMPM_ENONFINITE) {
+    dft(H->dft_i, H->my, nk2, H->uhat, u, r);
+    if (hipGetLastError() != hipSuccess) return fail(SMPM_EHIP, "transform launch failed");
+  }
+  return status;
 }
 
 smpm_status smpm_solve(smpm_handle *H, const double *f, const double *g, double *u, void *hip_stream,

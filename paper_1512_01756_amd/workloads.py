@@ -126,13 +126,18 @@ def c3(seed=0, mx=256, mz=16, n=13):
     return Problem("c3", xb, zb, n, np.zeros(1), f[None, None, :])
 
 
+def fourier_field(seed, r, my):
+    """The seeded U[0, 1] 3-D forcing: [m_y][r], one 2-D node field per y plane."""
+    return np.ascontiguousarray(np.random.default_rng(seed).uniform(0.0, 1.0, (r, my)).T)
+
+
 def fourier_problem(name, lx, mx, mz, n, my, ly, seed=0):
-    """rfft in y (normalized by 1/m_y) of a seeded U[0, 1] field on m_y points:
+    """rfft in y (normalized by 1/m_y) of the seeded U[0, 1] field on m_y points:
     modes m = 0 .. m_y/2, k_m = 2 pi m / l_y, RHS [Re, Im] per mode."""
     xb = np.linspace(0.0, lx, mx + 1)
     zb = np.linspace(0.0, 1.0, mz + 1)
     r = n * n * mx * mz
-    field3 = np.random.default_rng(seed).uniform(0.0, 1.0, (r, my))
+    field3 = fourier_field(seed, r, my).T
     fh = np.fft.rfft(field3, axis=1) / my             # (r, my/2 + 1)
     nk = fh.shape[1]
     f = np.empty((nk, 2, r))
