@@ -206,11 +206,17 @@ def main():
         fphys = torch.as_tensor(workloads.fourier_field(0, p4.r, my)).to(dev)
         uphys = torch.empty_like(fphys)
         physical = {}
-        for name, prec in (("fp64", P.FP64), ("fp32_ir", P.FP32_IR)):
-            sf = P.Solver(p4.xb, p4.zb, p4.n - 1, fourier=(my, ly), precision=prec, inner_tol=args.inner_tol)
+        for name, prec, one in (("fp64", P.FP64, False), ("fp32_ir", P.FP32_IR, False),
+                                ("fp64_one_krylov", P.FP64, True)):
+            sf = P.Solver(p4.xb, p4.zb, p4.n - 1, fourier=(my, ly), precision=prec, inner_tol=args.inner_tol,
+                          one_krylov=one)
             for _ in range(args.warmup):
                 sf.solve_fourier(fphys, None, uphys)
             physical[name] = gpu_events_time(lambda: sf.solve_fourier(fphys, None, uphys), args.steps, stream)
+            if one:
+                _, st1, _ = sf.solve_fourier(fphys, None, uphys)
+                physical["one_krylov_iterations"] = st1["iters_max"]
+                physical["one_krylov_rel_residual_max"] = st1["rel_residual_max"]
             sf.close()
 
     # The Schur matvec kernel alone (batched half-interface GEMV), both precisions.

@@ -87,6 +87,10 @@ typedef enum {
 #define SMPM_FLAG_NO_TUNE 2    /* skip the setup-time GEMM schedule tuning; pick
                                   schedules by launch size (reproducible across
                                   handles) */
+#define SMPM_FLAG_ONE_KRYLOV 4 /* one DBJ-GMRES over every instance of the handle:
+                                  the block-diagonal operator of Sec. 5.2 / Alg. 3,
+                                  stopping on the norm of the stacked residual;
+                                  DBJ only (else EINVAL) */
 
 typedef struct {
   int32_t mx, mz;      /* elements in x (>= 2) and z (>= 1) */

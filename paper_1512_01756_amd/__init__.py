@@ -21,6 +21,7 @@ FP64, FP32_IR = 0, 1
 METHOD_DBJ, METHOD_BJ, METHOD_SCHUR, METHOD_2LAS = 0, 1, 2, 3
 FLAG_HOST_ONLY = 1
 FLAG_NO_TUNE = 2
+FLAG_ONE_KRYLOV = 4
 OP_SCHUR, OP_BJINV, OP_DEFLATE_P, OP_DEFLATE_Q, OP_AINV, OP_B, OP_SCHUR_RHS = range(7)
 TABLE_SCHUR_DENSE, TABLE_BJINV_DENSE, TABLE_COARSE_C, TABLE_U_S, TABLE_U_L, TABLE_U_C, TABLE_SZ = range(7)
 
@@ -136,14 +137,15 @@ class Solver:
 
     def __init__(self, xb=None, zb=None, order=None, kwaves=(0.0,), grids=None, tau=0.0, tol=1e-10,
                  max_iter=300, nrhs=1, precision=FP64, method=METHOD_DBJ, inner_tol=0.0, max_sweeps=0,
-                 host_only=False, tune=True, fourier=None, stream=None):
+                 host_only=False, tune=True, fourier=None, one_krylov=False, stream=None):
         if fourier is not None:
             nrhs = 2
         lib = load()
         self._lib = lib
         self.host_only = host_only
         opts = Opts(tau, tol, max_iter, nrhs, precision, method, inner_tol, max_sweeps,
-                    (FLAG_HOST_ONLY if host_only else 0) | (0 if tune else FLAG_NO_TUNE))
+                    (FLAG_HOST_ONLY if host_only else 0) | (0 if tune else FLAG_NO_TUNE)
+                    | (FLAG_ONE_KRYLOV if one_krylov else 0))
         self.opts = opts
         self._keep = []
         h = ctypes.c_void_p()

@@ -51,6 +51,10 @@ struct InstDev {
   int64_t st_off;        // GMRES scalars: [maxit + 1]
   int64_t rr_off;        // R factor: [maxit][maxit]
   int64_t lam_off;       // z-interface functionals: [m_x][nq]
+  // Krylov segment: instances seg_first .. seg_first + seg_count - 1 share one
+  // GMRES (one Krylov space over all of them, Sec. 5.2); every member then
+  // has the leader's st_off and rr_off.  A plain instance is its own segment.
+  int seg_first, seg_count;
 };
 
 // Work item of the half-interface GEMV: up to kGroup halves of one instance

@@ -598,7 +598,8 @@ template <typename TV>
 __global__ __launch_bounds__(kBlock) void k_axpy_dot(
     const SysDev *__restrict__ sys, const InstDev *__restrict__ ins, const int2 *__restrict__ work,
     TV *__restrict__ V, const double *__restrict__ part_in, double *__restrict__ part_out,
-    double *__restrict__ partn, const double *__restrict__ scale, const GState *__restrict__ gs) {
+    double *__restrict__ partn, const double *__restrict__ scale, const GState *__restrict__ gs,
+    const double *__restrict__ coefr) {
   extern __shared__ double sh[];   // coef[maxit + 1] then red[(maxit + 1) * 4]
   const int2 wk = work[blockIdx.x];
   const int i = wk.x, ch = wk.y;
@@ -609,7 +610,15 @@ __global__ __launch_bounds__(kBlock) void k_axpy_dot(
   const int j = gs[i].iter;
   double *coef = sh;
   double *red = sh + (j + 1);
-  reduce_coef(I, part_in, scale, j, coef);
+  if (coefr) {   // segment sums reduced by k_seg_reduce
+    for (int t = threadIdx.x; t <= j; t += kBlock) {
+      const double s = scale[I.st_off + t];
+      coef[t] = s * s * coefr[I.st_off + t];
+    }
+    __syncthreads();
+  } else {
+    reduce_coef(I, part_in, scale, j, coef);
+  }
   const int64_t e0 = (int64_t)ch * kChunk;
   TV *w = V + I.v_off + (int64_t)(j + 1) * kS;
   double wv[kChunk / kBlock];
@@ -656,30 +665,60 @@ __global__ __launch_bounds__(kBlock) void k_axpy_dot(
 
 // Hessenberg column, Givens rotations and the residual estimate (one
 // workgroup per instance).  h_t = s_t (sum part1 + sum part2), h_{j+1} = ||w||.
+// Segment-wide sums of per-chunk partials, for instances that share one
+// Krylov space: out[st_off + t] = sum over the segment's instances and
+// chunks of part[part_off + t nchunk_x + c], t = 0 .. iter (dots), or of
+// part[part_off + c] (norm).  Grid (coefficient, instance); only segment
+// leaders work.  Fixed summation order.
+__global__ __launch_bounds__(kBlock) void k_seg_reduce(const InstDev *__restrict__ ins,
+                                                       const double *__restrict__ part, double *__restrict__ out,
+                                                       const GState *__restrict__ gs, int norm) {
+  __shared__ double lds4[4];
+  const int i = blockIdx.y, t = blockIdx.x;
+  const InstDev L = ins[i];
+  if (L.seg_first != i || !gs[i].active) return;
+  if (norm ? t > 0 : t > gs[i].iter) return;
+  double a = 0.0;
+  for (int m = i; m < i + L.seg_count; ++m) {
+    const InstDev M = ins[m];
+    const double *p = part + M.part_off + (norm ? 0 : (int64_t)t * M.nchunk_x);
+    for (int c = threadIdx.x; c < M.nchunk_x; c += kBlock) a += p[c];
+  }
+  a = block_sum(a, lds4);
+  if (threadIdx.x == 0) out[L.st_off + t] = a;
+}
+
 __global__ __launch_bounds__(kBlock) void k_givens(
     const InstDev *__restrict__ ins, const double *__restrict__ part1, const double *__restrict__ part2,
     const double *__restrict__ partn, double *__restrict__ scale, double *__restrict__ R,
     double *__restrict__ cs, double *__restrict__ sn, double *__restrict__ g, GState *__restrict__ gs,
-    int maxit, double tol) {
+    int maxit, double tol, const double *__restrict__ r1, const double *__restrict__ r2,
+    const double *__restrict__ rn) {
   extern __shared__ double h[];   // maxit + 2
   __shared__ double lds4[4];
   const int i = blockIdx.x;
-  if (!gs[i].active) return;
   const InstDev I = ins[i];
+  if (I.seg_first != i) return;   // a segment's Givens step runs once, on its leader
+  if (!gs[i].active) return;
   const int j = gs[i].iter;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  for (int t = wave; t <= j; t += 4) {
-    const double *p1 = part1 + I.part_off + (int64_t)t * I.nchunk_x;
-    const double *p2 = part2 + I.part_off + (int64_t)t * I.nchunk_x;
-    double a = 0.0, b = 0.0;
-    for (int c = lane; c < I.nchunk_x; c += 64) { a += p1[c]; b += p2[c]; }
-    a = wave_sum(a);
-    b = wave_sum(b);
-    if (lane == 0) h[t] = scale[I.st_off + t] * (a + b);
-  }
   double nn = 0.0;
-  for (int c = threadIdx.x; c < I.nchunk_x; c += kBlock) nn += partn[I.part_off + c];
-  nn = block_sum(nn, lds4);
+  if (r1) {   // segment sums reduced by k_seg_reduce
+    for (int t = threadIdx.x; t <= j; t += kBlock) h[t] = scale[I.st_off + t] * (r1[I.st_off + t] + r2[I.st_off + t]);
+    nn = rn[I.st_off];
+  } else {
+    for (int t = wave; t <= j; t += 4) {
+      const double *p1 = part1 + I.part_off + (int64_t)t * I.nchunk_x;
+      const double *p2 = part2 + I.part_off + (int64_t)t * I.nchunk_x;
+      double a = 0.0, b = 0.0;
+      for (int c = lane; c < I.nchunk_x; c += 64) { a += p1[c]; b += p2[c]; }
+      a = wave_sum(a);
+      b = wave_sum(b);
+      if (lane == 0) h[t] = scale[I.st_off + t] * (a + b);
+    }
+    for (int c = threadIdx.x; c < I.nchunk_x; c += kBlock) nn += partn[I.part_off + c];
+    nn = block_sum(nn, lds4);
+  }
   __syncthreads();
   if (threadIdx.x == 0) {
     const double beta = sqrt(nn);
@@ -713,7 +752,7 @@ __global__ __launch_bounds__(kBlock) void k_givens(
     } else {
       scale[I.st_off + j + 1] = 1.0 / beta;
     }
-    gs[i] = st;
+    for (int m = i; m < i + I.seg_count; ++m) gs[m] = st;
   }
 }
 
@@ -728,6 +767,7 @@ __global__ __launch_bounds__(kBlock) void k_backsolve(const InstDev *__restrict_
   extern __shared__ double rhs[];
   const int i = blockIdx.x;
   const InstDev I = ins[i];
+  if (I.seg_first != i) return;   // one least-squares solve per segment
   const int m = gs[i].iter;
   for (int t = threadIdx.x; t < m; t += kBlock) rhs[t] = g[I.st_off + t];
   __syncthreads();
@@ -1231,8 +1271,14 @@ __global__ __launch_bounds__(kBlock) void k_gmres_start(const InstDev *__restric
   __shared__ double lds4[4];
   const int i = blockIdx.x;
   const InstDev I = ins[i];
-  double nn = 0.0;
-  for (int c = threadIdx.x; c < I.nchunk_x; c += kBlock) nn += partn[I.part_off + c];
+  if (I.seg_first != i) return;   // a segment starts once, on its leader
+  double nn = 0.0, pb = 0.0, nbb = 0.0;
+  for (int m = i; m < i + I.seg_count; ++m) {
+    const InstDev M = ins[m];
+    for (int c = threadIdx.x; c < M.nchunk_x; c += kBlock) nn += partn[M.part_off + c];
+    if (pairs) pb += pairs[2 * m];
+    if (nb) nbb += nb[2 * m];
+  }
   nn = block_sum(nn, lds4);
   if (threadIdx.x == 0) {
     const double r0 = sqrt(nn);
@@ -1244,13 +1290,13 @@ __global__ __launch_bounds__(kBlock) void k_gmres_start(const InstDev *__restric
     // stopping reference: |g| <= tol * ref.  In a refinement sweep the
     // reference is also floored at bfrac * ||b~||, so the sweep stops once
     // the outer tolerance is within reach instead of at a fixed reduction.
-    double ref = pairs ? sqrt(pairs[2 * i]) : r0;
-    if (nb && bfrac > 0.0) ref = fmax(ref, bfrac * sqrt(nb[2 * i]));
+    double ref = pairs ? sqrt(pb) : r0;
+    if (nb && bfrac > 0.0) ref = fmax(ref, bfrac * sqrt(nbb));
     st.ref = ref;
     if (!isfinite(r0)) { st.active = 0; st.status = 3; }
     else if (r0 == 0.0 || !enable) { st.active = 0; st.status = 1; }
     else { st.active = 1; st.status = 0; }
-    gs[i] = st;
+    for (int m = i; m < i + I.seg_count; ++m) gs[m] = st;
     scale[I.st_off] = r0 > 0.0 ? 1.0 / r0 : 0.0;
     g[I.st_off] = r0;
   }

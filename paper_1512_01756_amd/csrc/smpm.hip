@@ -142,6 +142,8 @@ struct smpm_handle {
   double *cv = nullptr, *tb = nullptr, *scale = nullptr, *Rm = nullptr, *cs = nullptr, *sn = nullptr, *g = nullptr;
   double *ycoef = nullptr, *defect = nullptr, *pairs = nullptr, *lam = nullptr, *qb = nullptr;
   double *nb2 = nullptr;   // ||b~||^2 and u_S . b~ per instance, kept from the staging step
+  bool one_krylov = false; // one GMRES over every instance (SMPM_FLAG_ONE_KRYLOV)
+  double *sr1 = nullptr, *sr2 = nullptr, *srn = nullptr;   // segment sums (st_off layout)
   GState *gs = nullptr;
   GState *h_gs = nullptr;      // pinned
   double *h_pairs = nullptr;   // pinned
@@ -307,6 +309,12 @@ void upload(smpm_handle *H, hipStream_t st) {
       I.f_off = f_off; I.g_off = g_off; I.x_off = x_off; I.v_off = v_off;
       I.part_off = part_off; I.pr_off = pr_off; I.hs_off = hs_off; I.c_off = c_off;
       I.st_off = st_off; I.rr_off = rr_off; I.lam_off = lam_off;
+      I.seg_first = inst; I.seg_count = 1;
+      if (H->one_krylov) {   // the leader's GMRES scalars serve every instance
+        I.seg_first = 0;
+        I.st_off = 0;
+        I.rr_off = 0;
+      }
       f_off += s.r; g_off += 2LL * s.n * (s.mx + s.mz); x_off += s.kS; v_off += (int64_t)(maxit + 1) * s.kS;
       part_off += (int64_t)(maxit + 1) * I.nchunk_x + 2; pr_off += 2LL * I.nchunk_r;
       hs_off += (int64_t)s.nh * ((s.N + 15) / 16); c_off += s.d;
@@ -338,6 +346,8 @@ void upload(smpm_handle *H, hipStream_t st) {
   }
   H->ninst = (int)H->h_ins.size();
   H->tot_r = f_off; H->tot_x = x_off; H->tot_g = g_off;
+  if (H->one_krylov)
+    for (InstDev &I : H->h_ins) I.seg_count = H->ninst;
   // Element-interior GEMM items: per (system, strip class, element) for the
   // element inverses, per (system, strip class) for the capacitance inverse;
   // the columns are the (instance, strip) vectors of that class.
@@ -526,6 +536,9 @@ void upload(smpm_handle *H, hipStream_t st) {
   H->lam = dalloc<double>(own, lam_off); H->qb = dalloc<double>(own, lam_off);
   H->defect = dalloc<double>(own, H->ninst); H->pairs = dalloc<double>(own, 2 * H->ninst);
   H->nb2 = dalloc<double>(own, 2 * H->ninst);
+  if (H->one_krylov) {
+    H->sr1 = dalloc<double>(own, st_off); H->sr2 = dalloc<double>(own, st_off); H->srn = dalloc<double>(own, st_off);
+  }
   H->gs = dalloc<GState>(own, H->ninst);
   HIPCHECK(hipHostMalloc((void **)&H->h_gs, sizeof(GState) * H->ninst, hipHostMallocDefault));
   HIPCHECK(hipHostMalloc((void **)&H->h_pairs, sizeof(double) * 2 * H->ninst, hipHostMallocDefault));
@@ -860,13 +873,26 @@ struct Inner {
     hipLaunchKernelGGL((k_pcorr_dot<T, T>), dim3(H->n_x), dim3(kBlock), sizeof(double) * (maxit + 1) * 4, st, H->d_sys,
                        H->d_ins, H->w_x, (const T *)yb, (const double *)H->hs, useP ? 1 : 0, Vb, H->part1,
                        (const GState *)H->gs, maxit);
+    // One Krylov space over all instances (Sec. 5.2): every reduction spans
+    // the segment, so the partials go through k_seg_reduce first.
+    const bool seg = H->one_krylov;
+    auto seg_reduce = [&](const double *part, double *out, int norm) {
+      hipLaunchKernelGGL(k_seg_reduce, dim3(norm ? 1 : maxit + 1, H->ninst), dim3(kBlock), 0, st, H->d_ins, part, out,
+                         (const GState *)H->gs, norm);
+    };
+    if (seg) seg_reduce(H->part1, H->sr1, 0);
     hipLaunchKernelGGL((k_axpy_dot<T>), dim3(H->n_x), dim3(kBlock), shm_dot, st, H->d_sys, H->d_ins, H->w_x, Vb,
-                       (const double *)H->part1, H->part2, (double *)nullptr, (const double *)H->scale, (const GState *)H->gs);
+                       (const double *)H->part1, H->part2, (double *)nullptr, (const double *)H->scale, (const GState *)H->gs,
+                       seg ? (const double *)H->sr1 : nullptr);
+    if (seg) seg_reduce(H->part2, H->sr2, 0);
     hipLaunchKernelGGL((k_axpy_dot<T>), dim3(H->n_x), dim3(kBlock), shm_dot, st, H->d_sys, H->d_ins, H->w_x, Vb,
-                       (const double *)H->part2, (double *)nullptr, H->partn, (const double *)H->scale, (const GState *)H->gs);
+                       (const double *)H->part2, (double *)nullptr, H->partn, (const double *)H->scale, (const GState *)H->gs,
+                       seg ? (const double *)H->sr2 : nullptr);
+    if (seg) seg_reduce(H->partn, H->srn, 1);
     hipLaunchKernelGGL(k_givens, dim3(H->ninst), dim3(kBlock), sizeof(double) * (maxit + 2), st, H->d_ins,
                        (const double *)H->part1, (const double *)H->part2, (const double *)H->partn, H->scale, H->Rm,
-                       H->cs, H->sn, H->g, H->gs, maxit, tol(H));
+                       H->cs, H->sn, H->g, H->gs, maxit, tol(H), seg ? (const double *)H->sr1 : nullptr,
+                       seg ? (const double *)H->sr2 : nullptr, seg ? (const double *)H->srn : nullptr);
   }
 
   // x' = V y; x = M^-1 x' + coarse correction, into (or onto) x_S
@@ -977,6 +1003,8 @@ smpm_status validate_opts(const smpm_opts *o, smpm_handle *H) {
   H->max_sweeps = d.max_sweeps > 0 ? d.max_sweeps : 12;
   H->host_only = (d.flags & SMPM_FLAG_HOST_ONLY) != 0;
   H->no_tune = (d.flags & SMPM_FLAG_NO_TUNE) != 0;
+  H->one_krylov = (d.flags & SMPM_FLAG_ONE_KRYLOV) != 0;
+  if (H->one_krylov && H->method != SMPM_METHOD_DBJ) return fail(SMPM_EINVAL, "one Krylov space needs the DBJ method");
   if (d.tol < 0 || d.max_iter < 0 || d.nrhs < 0 || d.inner_tol < 0 || d.max_sweeps < 0)
     return fail(SMPM_EINVAL, "negative option value");
   if (H->maxit > 2000) return fail(SMPM_EINVAL, "max_iter above 2000");

@@ -75,3 +75,33 @@ def test_solve_fourier_rejects_plain_handles():
     f = torch.zeros((4, s.info[0]["r"]), dtype=torch.float64, device="cuda")
     with pytest.raises(P.SmpmError):
         s.solve_fourier(f)
+
+
+@pytest.mark.parametrize("precision", [P.FP64, P.FP32_IR])
+def test_one_krylov_over_all_modes_matches_oracle(precision):
+    # Sec. 5.2 / Alg. 3: one DBJ-GMRES over the block-diagonal operator of
+    # every (mode, Re/Im) instance; same solution, iteration count within one.
+    xb = np.array([0.0, 0.6, 1.1, 1.9, 2.4, 3.0])
+    zb = np.array([0.0, 0.5, 1.0])
+    n, my, ly = 5, 6, 2.0
+    grid = smpm.Grid(xb, zb, n)
+    f = np.random.default_rng(5).uniform(0, 1, (my, grid.r))
+    u_ref, (it_ref, ok) = fourier.solve3d(xb, zb, n, f, ly, one_krylov=True)
+    s = P.Solver(xb, zb, n - 1, fourier=(my, ly), one_krylov=True, precision=precision)
+    u, st, _ = s.solve_fourier(_dev(f))
+    u = u.cpu().numpy()
+    print("one krylov", st, "oracle iters", it_ref, _rel(u, u_ref))
+    assert ok
+    if precision == P.FP64:
+        assert abs(st["iters_max"] - it_ref) <= 1
+        assert st["iters_total"] == st["iters_max"] * st["instances"]
+        assert _rel(u, u_ref) <= 1e-9
+    else:
+        assert st["rel_residual_max"] <= 1.001e-10 * 10   # the stacked residual is controlled, not each mode's
+        assert _rel(u, u_ref) <= 1e-8
+
+
+def test_one_krylov_needs_dbj():
+    with pytest.raises(P.SmpmError):
+        P.Solver(np.linspace(0, 3, 5), np.linspace(0, 1, 2), 4, fourier=(4, 1.0), one_krylov=True,
+                 method=P.METHOD_BJ)
