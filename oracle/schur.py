@@ -13,7 +13,8 @@ Sec. 3.2: block-Jacobi blocks are the principal submatrices of S on two
 consecutive interfaces (Gamma_{2b}, Gamma_{2b+1}); the last block holds a
 single interface when the interface count is odd.
 Sec. 3.3, Eqs. (projection1), (projection2): Z holds one indicator column
-per interface, C = Z^T S Z, P = I - S Z C^-1 Z^T, Q = I - Z C^-1 Z^T S; for
+per interface (or, as a richer space, per element segment of an interface),
+C = Z^T S Z, P = I - S Z C^-1 Z^T, Q = I - Z C^-1 Z^T S; for
 the singular Poisson case the coarse division is C \\ (I - u_C u_C^T) with u_C
 the unit left null vector of C.
 Sec. 2.4, Claim 1: u_S = E^T u_L and u_L = A^-T B^T u_S (up to scale).
@@ -90,7 +91,7 @@ class SchurSystem:
         return y
 
     def Zt(self, x):
-        return np.bincount(self.labels, weights=x, minlength=self.grid.mx - 1)
+        return np.bincount(self.labels, weights=x, minlength=self.C.shape[0])
 
     def Z(self, c):
         return c[self.labels]
@@ -127,8 +128,22 @@ def _strip(grid, A, B, E, j):
     return lu, B[ridx][:, sidx] @ X, ridx, cidx
 
 
-def build(grid, tau=None, kwave=0.0):
-    """Assemble every operator of the Schur method for one 2-D problem."""
+def z_labels(grid, zlabel=0):
+    """Label map of the deflation space Z (Sec. 3.3): Gamma index -> coarse
+    unknown.  zlabel 0: one indicator per interface Gamma_i (the paper's Z,
+    d = m_x - 1); zlabel 1: one per element segment of an interface, the n
+    nodes of element e on both sides of Gamma_i (d = (m_x - 1) m_z)."""
+    nif = grid.mx - 1
+    if zlabel == 0:
+        return np.repeat(np.arange(nif), 2 * grid.nhalf)
+    h = np.repeat(np.arange(2 * nif), grid.nhalf)                    # half of each Gamma index
+    e = np.tile(np.repeat(np.arange(grid.mz), grid.n), 2 * nif)      # element of each Gamma index
+    return (h // 2) * grid.mz + e
+
+
+def build(grid, tau=None, kwave=0.0, zlabel=0):
+    """Assemble every operator of the Schur method for one 2-D problem.
+    zlabel selects the deflation space (see z_labels)."""
     if tau is None:
         tau = smpm.default_tau(grid)
     A = smpm.assemble_A(grid, tau, kwave)
@@ -152,8 +167,9 @@ def build(grid, tau=None, kwave=0.0):
         bj_index.append(np.concatenate([np.concatenate([half_range(grid, 2 * i),
                                                         half_range(grid, 2 * i + 1)]) for i in ifs]))
     bj_inv = [np.linalg.inv(S[idx][:, idx].toarray()) for idx in bj_index]
-    labels = np.repeat(np.arange(nif), 2 * grid.nhalf)
-    Zs = sp.coo_matrix((np.ones(k), (np.arange(k), labels)), shape=(k, nif)).tocsr()
+    labels = z_labels(grid, zlabel)
+    d = int(labels.max()) + 1
+    Zs = sp.coo_matrix((np.ones(k), (np.arange(k), labels)), shape=(k, d)).tocsr()
     SZ = (S @ Zs).toarray()
     C = (Zs.T @ SZ)
     sysm = SchurSystem(grid, tau, float(kwave), A, B, E, lus, W, S, bj_index, bj_inv,

@@ -6,7 +6,7 @@ import pytest
 from oracle import schur, smpm, solve
 
 
-def _sys(mx=5, mz=2, n=5, k=0.0, stretch=False):
+def _sys(mx=5, mz=2, n=5, k=0.0, stretch=False, zlabel=0):
     if stretch:
         xb = np.array([0.0, 0.4, 0.9, 1.2, 1.9, 2.3, 2.8][:mx + 1])
         zb = np.array([0.0, 0.15, 0.45, 1.0][:mz + 1])
@@ -15,7 +15,7 @@ def _sys(mx=5, mz=2, n=5, k=0.0, stretch=False):
         xb = np.linspace(0, mx / 2.0, mx + 1)
         zb = np.linspace(0, 1, mz + 1)
     grid = smpm.Grid(xb, zb, n)
-    return schur.build(grid, kwave=k)
+    return schur.build(grid, kwave=k, zlabel=zlabel)
 
 
 @pytest.mark.parametrize("k", [0.0, 2.5])
@@ -75,8 +75,9 @@ def test_claim2_bound_on_perturbed_solutions():
 
 
 @pytest.mark.parametrize("k", [0.0, 1.7])
-def test_deflation_identities(k):
-    s = _sys(7, 2, 5, k)
+@pytest.mark.parametrize("zlabel", [0, 1])
+def test_deflation_identities(k, zlabel):
+    s = _sys(7, 2, 5, k, zlabel=zlabel)
     rng = np.random.default_rng(1)
     Sd = s.S.toarray()
     for _ in range(3):
@@ -90,9 +91,48 @@ def test_deflation_identities(k):
         ZtP = s.Zt(Py)
         expect = s.uC * (s.uC @ s.Zt(y)) if k == 0.0 else np.zeros_like(ZtP)
         np.testing.assert_allclose(ZtP, expect, atol=1e-10 * np.linalg.norm(y))
-    for c in range(s.grid.mx - 1):
-        e = np.zeros(s.grid.mx - 1); e[c] = 1
+    d = s.C.shape[0]
+    for c in range(d):
+        e = np.zeros(d); e[c] = 1
         np.testing.assert_allclose(s.P_apply(s.SZ @ e), 0, atol=1e-10 * np.linalg.norm(s.SZ @ e))
+
+
+@pytest.mark.parametrize("k", [0.0, 1.3])
+def test_per_element_deflation_space(k):
+    # Z with one column per element segment of an interface: d = (m_x - 1) m_z
+    # columns of 2n ones each; C couples only neighbouring interfaces (block
+    # tridiagonal with m_z x m_z blocks); the per-interface space is the sum of
+    # the segment columns, so it is deflated too: P_el S Z_if = 0.
+    mx, mz, n = 6, 3, 4
+    s1 = _sys(mx, mz, n, k, stretch=True, zlabel=1)
+    s0 = _sys(mx, mz, n, k, stretch=True, zlabel=0)
+    d = (mx - 1) * mz
+    assert s1.C.shape == (d, d)
+    assert np.all(np.bincount(s1.labels, minlength=d) == 2 * n)
+    C = s1.C
+    for a in range(mx - 1):
+        for b in range(mx - 1):
+            if abs(a - b) > 1:
+                assert np.abs(C[a * mz:(a + 1) * mz, b * mz:(b + 1) * mz]).max() < 1e-12 * np.abs(C).max()
+    if k == 0.0:
+        assert np.abs(C @ np.ones(d)).max() < 1e-10 * np.abs(C).max()
+        assert np.sum(np.linalg.svd(C, compute_uv=False) < 1e-10 * np.abs(C).max()) == 1
+    for c in range(mx - 1):
+        e = np.zeros(mx - 1); e[c] = 1
+        v = s0.SZ @ e
+        np.testing.assert_allclose(s1.P_apply(v), 0, atol=1e-10 * np.linalg.norm(v))
+
+
+def test_per_element_deflation_solves_the_same_problem():
+    xb = np.array([0.0, 0.4, 0.9, 1.2, 1.9, 2.3, 2.8])
+    zb = np.array([0.0, 0.3, 1.0])
+    grid = smpm.Grid(xb, zb, 5)
+    F = np.random.default_rng(2).uniform(0, 1, grid.r)
+    s1 = schur.build(grid, zlabel=1)
+    r1 = solve.dbj_solve(s1, smpm.rhs(grid, s1.tau, F))
+    ud = solve.direct_solve(grid, s1.tau, smpm.rhs(grid, s1.tau, F))
+    assert r1.converged
+    assert np.abs(r1.u - ud).max() <= 1e-9 * np.abs(ud).max()
 
 
 def test_coarse_matrix_structure():
