@@ -112,6 +112,9 @@ typedef struct {
                           1e-4 to 1e-5 with FP32 operators) */
   int32_t max_sweeps;  /* FP32_IR outer sweeps; 0 selects 12 */
   int32_t flags;       /* SMPM_FLAG_* */
+  int32_t zlabel;      /* deflation space Z (Sec. 3.3): 0 one column per interface
+                          (the paper's, d = m_x - 1), 1 one column per element
+                          segment of an interface (d = (m_x - 1) m_z <= 4096) */
 } smpm_opts;
 
 typedef struct {

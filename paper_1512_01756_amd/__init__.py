@@ -43,7 +43,8 @@ class Grid(ctypes.Structure):
 class Opts(ctypes.Structure):
     _fields_ = [("tau", ctypes.c_double), ("tol", ctypes.c_double), ("max_iter", ctypes.c_int32),
                 ("nrhs", ctypes.c_int32), ("precision", ctypes.c_int32), ("method", ctypes.c_int32),
-                ("inner_tol", ctypes.c_double), ("max_sweeps", ctypes.c_int32), ("flags", ctypes.c_int32)]
+                ("inner_tol", ctypes.c_double), ("max_sweeps", ctypes.c_int32), ("flags", ctypes.c_int32),
+                ("zlabel", ctypes.c_int32)]
 
 
 class Stats(ctypes.Structure):
@@ -137,7 +138,7 @@ class Solver:
 
     def __init__(self, xb=None, zb=None, order=None, kwaves=(0.0,), grids=None, tau=0.0, tol=1e-10,
                  max_iter=300, nrhs=1, precision=FP64, method=METHOD_DBJ, inner_tol=0.0, max_sweeps=0,
-                 host_only=False, tune=True, fourier=None, one_krylov=False, stream=None):
+                 host_only=False, tune=True, fourier=None, one_krylov=False, zlabel=0, stream=None):
         if fourier is not None:
             nrhs = 2
         lib = load()
@@ -145,7 +146,7 @@ class Solver:
         self.host_only = host_only
         opts = Opts(tau, tol, max_iter, nrhs, precision, method, inner_tol, max_sweeps,
                     (FLAG_HOST_ONLY if host_only else 0) | (0 if tune else FLAG_NO_TUNE)
-                    | (FLAG_ONE_KRYLOV if one_krylov else 0))
+                    | (FLAG_ONE_KRYLOV if one_krylov else 0), zlabel)
         self.opts = opts
         self._keep = []
         h = ctypes.c_void_p()

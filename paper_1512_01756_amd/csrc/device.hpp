@@ -15,6 +15,9 @@ constexpr int kMaxRowsPerLane = (kMaxN + 63) / 64;
 struct SysDev {
   int n, mx, mz, n2, N, nh, d, singular;
   int Np;                // rows of the stored Schur / block-Jacobi blocks (N rounded up to 4)
+  int zm;                // coarse columns per interface: 1, or m_z (one per element segment)
+  const int *sz_col;     // per half: [2 zm] coarse columns of its S Z rows (-1: none)
+  const double *SZh;     // per half: [2 zm][N]
   int64_t kS, r;
   double tau;
   const double *W64;     // unique Schur half blocks: [blk][2N][N]
@@ -23,8 +26,6 @@ struct SysDev {
   const double *M64;     // unique block-Jacobi row chunks: [chunk][4N][N]
   const float *M32;
   const int *m_id, *m_win, *m_K;
-  const int *sz_col;     // [h][2]
-  const double *SZh;     // [h][2][N]
   const double *Gc;      // coarse operator, column-major d x d
   const double *uS, *uL; // null vectors (k = 0), else nullptr
   const double *Dinv;    // element inverses: [class][e][col n2][row n2]

@@ -56,6 +56,7 @@ struct StripClass {
 // ---- one system: a grid and one wavenumber ---------------------------------
 struct System {
   int n = 0, mx = 0, mz = 0, n2 = 0, N = 0, nh = 0, d = 0;
+  int zm = 1;   // coarse columns per interface: 1, or m_z (one per element segment)
   int64_t r = 0, kS = 0;
   double kwave = 0.0, tau = 0.0;
   bool singular = false;
@@ -73,9 +74,10 @@ struct System {
   std::vector<int> m_id, m_win, m_K;     // per half
   std::vector<double> Mblk;              // unique chunks, N x 4N row-major (zero padded)
   int nM = 0, nMblocks = 0;
-  // Deflation: S Z restricted per half to its two coarse columns.
-  std::vector<int> sz_col;               // per half: [2] coarse columns (-1 if none)
-  std::vector<double> SZh;               // per half: [2][N]
+  // Deflation: S Z restricted per half to the coarse columns of the two
+  // interfaces its window touches (2 zm columns).
+  std::vector<int> sz_col;               // per half: [2 zm] coarse columns (-1 if none)
+  std::vector<double> SZh;               // per half: [2 zm][N]
   std::vector<double> C;                 // d x d row-major
   std::vector<double> Gc;                // coarse operator C^dagger (I - u_C u_C^T), d x d row-major
   // Null vectors (k = 0 only).
@@ -87,6 +89,7 @@ struct System {
 struct SetupOptions {
   double tau = 0.0;
   int threads = 0;
+  int zlabel = 0;   // deflation space: 0 one column per interface, 1 per element segment
 };
 
 // Build every host table of one system.  Throws std::runtime_error with a

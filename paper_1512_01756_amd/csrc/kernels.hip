@@ -22,6 +22,30 @@ template <> struct Tab<float> {
   __device__ static const float *blk(const GWork &w) { return w.blk32; }
 };
 
+// Deflation space Z (Sec. 3.3): coarse column of interface row `row` of half
+// h (one column per interface, or one per element segment of n rows), and
+// (S Z c) at that row from the half's 2 zm columns of S Z; c is indexed from
+// coarse column `c0`.
+__device__ inline int z_col(const SysDev &S, int h, int row) {
+  return (h >> 1) * S.zm + (S.zm > 1 ? row / S.n : 0);
+}
+__device__ inline double sz_c(const SysDev &S, int h, int row, const double *__restrict__ c, int c0) {
+  const int m = 2 * S.zm;
+  double a = 0.0;
+  for (int p = 0; p < m; ++p) {
+    const int col = S.sz_col[(size_t)h * m + p];
+    if (col >= 0) a += S.SZh[((size_t)h * m + p) * S.N + row] * c[col - c0];
+  }
+  return a;
+}
+// Z^T partial sums of one half: index of coarse column e of half h in the
+// half-sum array.  With zm = 1 the array holds per-16-row slots (the GEMM
+// epilogues write them), summed over the half; else one sum per segment.
+__device__ inline int hs_slots(const SysDev &S) {
+  const int tiles = (S.N + 15) >> 4;
+  return S.zm > 1 ? S.zm : tiles;
+}
+
 __device__ inline double wave_sum(double v) {
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
@@ -464,16 +488,21 @@ __global__ __launch_bounds__(kBlock) void k_coarse(const SysDev *__restrict__ sy
                                                    double *__restrict__ tout,
                                                    double *__restrict__ cout,
                                                    const GState *__restrict__ gs) {
-  __shared__ double t[1024];
+  extern __shared__ double t[];   // d
   const int i = blockIdx.x;
   if (gs && !gs[i].active) return;
   const InstDev I = ins[i];
   const SysDev &S = sys[I.sys];
   const int d = S.d;
-  const int tiles = (S.N + 15) >> 4;
+  const int sl = hs_slots(S);
   for (int c = threadIdx.x; c < d; c += kBlock) {
     double v = 0.0;
-    for (int q = 0; q < 2 * tiles; ++q) v += hsum[I.hs_off + (int64_t)2 * c * tiles + q];
+    if (S.zm == 1) {
+      for (int q = 0; q < 2 * sl; ++q) v += hsum[I.hs_off + (int64_t)2 * c * sl + q];
+    } else {
+      const int a = c / S.zm, e = c - a * S.zm;
+      v = hsum[I.hs_off + (int64_t)(2 * a) * sl + e] + hsum[I.hs_off + (int64_t)(2 * a + 1) * sl + e];
+    }
     if (tsub) v = tsub[I.c_off + c] - v;
     t[c] = v;
     if (tout) tout[I.c_off + c] = v;
@@ -503,8 +532,7 @@ __global__ __launch_bounds__(kBlock) void k_pcorr_dot(
     const SysDev *__restrict__ sys, const InstDev *__restrict__ ins, const int2 *__restrict__ work,
     const TY *__restrict__ ybase, const double *__restrict__ hsum, int useP, TV *__restrict__ V,
     double *__restrict__ part, const GState *__restrict__ gs, int maxit) {
-  extern __shared__ double red[];   // (maxit + 1) * 4
-  __shared__ double t_s[1024];
+  extern __shared__ double red[];   // (maxit + 1) * 4, then t_s[d]
   __shared__ double c_s[kChunk / 2 + 8];
   const int2 wk = work[blockIdx.x];
   const int i = wk.x, ch = wk.y;
@@ -516,23 +544,32 @@ __global__ __launch_bounds__(kBlock) void k_pcorr_dot(
   const int j = gs[i].iter;
   const int64_t e0 = (int64_t)ch * kChunk;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  int ilo = 0;
+  int c0 = 0;
   if (useP) {
-    const int d = S.d;
-    const int tiles = (N + 15) >> 4;
+    double *t_s = red + (size_t)(maxit + 1) * 4;
+    const int d = S.d, zm = S.zm, nif = S.mx - 1;
+    const int sl = hs_slots(S);
     for (int c = threadIdx.x; c < d; c += kBlock) {
       double v = 0.0;
-      for (int q = 0; q < 2 * tiles; ++q) v += hsum[I.hs_off + (int64_t)2 * c * tiles + q];
+      if (zm == 1) {
+        for (int q = 0; q < 2 * sl; ++q) v += hsum[I.hs_off + (int64_t)2 * c * sl + q];
+      } else {
+        const int a = c / zm, e = c - a * zm;
+        v = hsum[I.hs_off + (int64_t)(2 * a) * sl + e] + hsum[I.hs_off + (int64_t)(2 * a + 1) * sl + e];
+      }
       t_s[c] = v;
     }
+    // the coarse values this chunk needs: interfaces ilo .. ihi
     const int64_t elast = (e0 + kChunk < kS ? e0 + kChunk : kS) - 1;
     const int hlo = (int)(e0 / N), hhi = (int)(elast / N);
-    ilo = hlo / 2 - 1 < 0 ? 0 : hlo / 2 - 1;
-    const int ihi = hhi / 2 + 1 > d - 1 ? d - 1 : hhi / 2 + 1;
+    const int ilo = hlo / 2 - 1 < 0 ? 0 : hlo / 2 - 1;
+    const int ihi = hhi / 2 + 1 > nif - 1 ? nif - 1 : hhi / 2 + 1;
+    c0 = ilo * zm;
+    const int ncol = (ihi - ilo + 1) * zm;
     __syncthreads();
-    for (int r = wave; r <= ihi - ilo; r += 4) {
+    for (int r = wave; r < ncol; r += 4) {
       double a = 0.0;
-      for (int l = lane; l < d; l += 64) a += S.Gc[(size_t)l * d + ilo + r] * t_s[l];
+      for (int l = lane; l < d; l += 64) a += S.Gc[(size_t)l * d + c0 + r] * t_s[l];
       a = wave_sum(a);
       if (lane == 0) c_s[r] = a;
     }
@@ -547,9 +584,7 @@ __global__ __launch_bounds__(kBlock) void k_pcorr_dot(
       w = (double)ybase[I.x_off + e];
       if (useP) {
         const int h = (int)(e / N), row = (int)(e - (int64_t)h * N);
-        const int ca = S.sz_col[2 * h], cb = S.sz_col[2 * h + 1];
-        if (ca >= 0) w -= S.SZh[((size_t)2 * h) * N + row] * c_s[ca - ilo];
-        if (cb >= 0) w -= S.SZh[((size_t)2 * h + 1) * N + row] * c_s[cb - ilo];
+        w -= sz_c(S, h, row, c_s, c0);
       }
       const TV wt = (TV)w;
       V[I.v_off + (int64_t)(j + 1) * kS + e] = wt;
@@ -1148,47 +1183,17 @@ __global__ __launch_bounds__(kBlock) void k_proj_x(const SysDev *__restrict__ sy
   }
 }
 
-// Sum of each half of an interface vector (Z^T x, two halves per
-// interface), and optionally the partial of u_S . x.
-__global__ __launch_bounds__(kBlock) void k_halfsum(const SysDev *__restrict__ sys,
-                                                    const InstDev *__restrict__ ins,
-                                                    const int2 *__restrict__ work,
-                                                    const double *__restrict__ x,
-                                                    double *__restrict__ hs,
-                                                    double *__restrict__ hdot) {
-  __shared__ double lds4[4];
-  const int2 wk = work[blockIdx.x];
-  const int i = wk.x, h = wk.y;
-  const InstDev I = ins[i];
-  const SysDev &S = sys[I.sys];
-  const int N = S.N;
-  double a = 0.0, b = 0.0;
-  for (int row = threadIdx.x; row < N; row += kBlock) {
-    const double v = x[I.x_off + (int64_t)h * N + row];
-    a += v;
-    if (hdot && S.singular) b += S.uS[(int64_t)h * N + row] * v;
-  }
-  a = block_sum(a, lds4);
-  __syncthreads();
-  if (hdot) b = block_sum(b, lds4);
-  const int tiles = (N + 15) >> 4;
-  if (threadIdx.x == 0) {
-    hs[I.hs_off + (int64_t)h * tiles] = a;
-    if (hdot) hdot[I.hs_off + h] = b;
-  }
-  for (int q = 1 + (int)threadIdx.x; q < tiles; q += kBlock) hs[I.hs_off + (int64_t)h * tiles + q] = 0.0;
-}
-
-// Z^T of an interface vector in precision T (the additive two-level
-// preconditioner, Table 1 "2LAS"): per (instance, half) sum of its N values,
-// times the basis scale when it reads Krylov slot `iter`; same slot layout as
-// k_halfsum.  Stopped instances are skipped.
+// Z^T partial sums of an interface vector in precision T (Sec. 3.3): per
+// (instance, half) either the whole half's sum in its first 16-row slot
+// (zm = 1, the layout of the GEMM epilogues; other slots zeroed) or one sum
+// per element segment (zm = m_z).  Reads Krylov slot `iter` times the basis
+// scale when x_vslot is set (the two-level preconditioner).  Stopped
+// instances are skipped when gs is given.
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_halfsum_t(const SysDev *__restrict__ sys,
-                                                      const InstDev *__restrict__ ins,
-                                                      const int2 *__restrict__ work, const T *__restrict__ x,
-                                                      int x_vslot, const double *__restrict__ scale,
-                                                      const GState *__restrict__ gs, double *__restrict__ hs) {
+__global__ __launch_bounds__(kBlock) void k_zt(const SysDev *__restrict__ sys, const InstDev *__restrict__ ins,
+                                               const int2 *__restrict__ work, const T *__restrict__ x, int x_vslot,
+                                               const double *__restrict__ scale, const GState *__restrict__ gs,
+                                               double *__restrict__ hs) {
   __shared__ double lds4[4];
   const int2 wk = work[blockIdx.x];
   const int i = wk.x, h = wk.y;
@@ -1198,12 +1203,24 @@ __global__ __launch_bounds__(kBlock) void k_halfsum_t(const SysDev *__restrict__
   const SysDev &S = sys[I.sys];
   const int N = S.N;
   const int64_t off = (x_vslot ? I.v_off + (int64_t)it * S.kS : I.x_off) + (int64_t)h * N;
-  double a = 0.0;
-  for (int row = threadIdx.x; row < N; row += kBlock) a += (double)x[off + row];
-  a = block_sum(a, lds4);
-  const int tiles = (N + 15) >> 4;
-  if (threadIdx.x == 0) hs[I.hs_off + (int64_t)h * tiles] = a * (scale ? scale[I.st_off + it] : 1.0);
-  for (int q = 1 + (int)threadIdx.x; q < tiles; q += kBlock) hs[I.hs_off + (int64_t)h * tiles + q] = 0.0;
+  const double sc = scale ? scale[I.st_off + it] : 1.0;
+  const int sl = hs_slots(S);
+  double *out = hs + I.hs_off + (int64_t)h * sl;
+  if (S.zm == 1) {
+    double a = 0.0;
+    for (int row = threadIdx.x; row < N; row += kBlock) a += (double)x[off + row];
+    a = block_sum(a, lds4);
+    if (threadIdx.x == 0) out[0] = a * sc;
+    for (int q = 1 + (int)threadIdx.x; q < sl; q += kBlock) out[q] = 0.0;
+  } else {
+    // wave w sums segments w, w + 4, ...: one row per lane (n <= 64)
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    for (int e = wave; e < S.zm; e += 4) {
+      double a = lane < S.n ? (double)x[off + (int64_t)e * S.n + lane] : 0.0;
+      a = wave_sum(a);
+      if (lane == 0) out[e] = a * sc;
+    }
+  }
 }
 
 // z += Z c in precision T (the coarse term of the two-level preconditioner).
@@ -1220,8 +1237,8 @@ __global__ __launch_bounds__(kBlock) void k_add_zc(const SysDev *__restrict__ sy
   for (int q = 0; q < kChunk / kBlock; ++q) {
     const int64_t e = (int64_t)ch * kChunk + threadIdx.x + q * kBlock;
     if (e >= S.kS) continue;
-    const int iface = (int)(e / N) >> 1;
-    z[I.x_off + e] = (T)((double)z[I.x_off + e] + cvec[I.c_off + iface]);
+    const int h = (int)(e / N);
+    z[I.x_off + e] = (T)((double)z[I.x_off + e] + cvec[I.c_off + z_col(S, h, (int)(e - (int64_t)h * N))]);
   }
 }
 
@@ -1247,9 +1264,7 @@ __global__ __launch_bounds__(kBlock) void k_init_basis(const SysDev *__restrict_
     double w = b[I.x_off + e];
     if (cvec) {
       const int h = (int)(e / N), row = (int)(e - (int64_t)h * N);
-      const int ca = S.sz_col[2 * h], cb = S.sz_col[2 * h + 1];
-      if (ca >= 0) w -= S.SZh[((size_t)2 * h) * N + row] * cvec[I.c_off + ca];
-      if (cb >= 0) w -= S.SZh[((size_t)2 * h + 1) * N + row] * cvec[I.c_off + cb];
+      w -= sz_c(S, h, row, cvec + I.c_off, 0);
     }
     const TV wt = (TV)w;
     V[I.v_off + e] = wt;
@@ -1327,7 +1342,8 @@ __global__ __launch_bounds__(kBlock) void k_xupdate(const SysDev *__restrict__ s
     const int64_t e = (int64_t)ch * kChunk + threadIdx.x + q * kBlock;
     if (e >= S.kS) continue;
     const int h = (int)(e / N);
-    const int iface = h >> 1;
+    const int row = (int)(e - (int64_t)h * N);
+    const int zc = z_col(S, h, row);
     double v = a ? (double)a[I.x_off + e] : 0.0;
     if (mode == 2) {
       v = out[I.x_off + e] - v;
@@ -1337,14 +1353,11 @@ __global__ __launch_bounds__(kBlock) void k_xupdate(const SysDev *__restrict__ s
       continue;
     }
     if (mode == 3) {
-      const int row = (int)(e - (int64_t)h * N);
-      const int ca = S.sz_col[2 * h], cb = S.sz_col[2 * h + 1];
-      if (ca >= 0) v -= S.SZh[((size_t)2 * h) * N + row] * cvec[I.c_off + ca];
-      if (cb >= 0) v -= S.SZh[((size_t)2 * h + 1) * N + row] * cvec[I.c_off + cb];
+      v -= sz_c(S, h, row, cvec + I.c_off, 0);
     } else if (mode == 4) {
-      v -= cvec[I.c_off + iface];
+      v -= cvec[I.c_off + zc];
     } else {
-      if (cvec) v += cvec[I.c_off + iface];
+      if (cvec) v += cvec[I.c_off + zc];
       if (mode == 1) v += out[I.x_off + e];
     }
     out[I.x_off + e] = v;

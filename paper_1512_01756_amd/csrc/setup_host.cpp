@@ -405,7 +405,7 @@ static double norm2(const std::vector<double> &v) {
 // shifted transpose is factored by block elimination, the diagonal blocks
 // with partial pivoting.
 static void left_null_schur(System &s) {
-  const int N = s.N, M = 2 * N, d = s.d;
+  const int N = s.N, M = 2 * N, d = s.mx - 1;   // d: interfaces
   // Interface blocks of S: Sd[i] (M x M), Su[i] = S[i][i+1] (upper-left N x N
   // of rows of half 2i, cols of half 2i+2), Sl[i] = S[i][i-1] (rows of half
   // 2i+1, cols of half 2i-1).
@@ -519,7 +519,9 @@ void build_system(System &s, int mx, int mz, int order, const double *xb, const 
   if (mx < 2 || mz < 1 || order < 1) throw std::invalid_argument("need mx >= 2, mz >= 1, order >= 1");
   if (!(kwave >= 0.0) || !std::isfinite(kwave)) throw std::invalid_argument("wavenumber must be finite and >= 0");
   s.n = order + 1; s.mx = mx; s.mz = mz;
-  s.n2 = s.n * s.n; s.N = s.n * mz; s.nh = 2 * (mx - 1); s.d = mx - 1;
+  if (opt.zlabel != 0 && opt.zlabel != 1) throw std::invalid_argument("zlabel must be 0 or 1");
+  s.zm = opt.zlabel == 1 ? mz : 1;
+  s.n2 = s.n * s.n; s.N = s.n * mz; s.nh = 2 * (mx - 1); s.d = (mx - 1) * s.zm;
   s.r = (int64_t)s.n2 * mx * mz; s.kS = (int64_t)s.N * s.nh;
   s.kwave = kwave; s.singular = (kwave == 0.0);
   s.xb.assign(xb, xb + mx + 1); s.zb.assign(zb, zb + mz + 1);
@@ -617,7 +619,7 @@ void build_system(System &s, int mx, int mz, int order, const double *xb, const 
   }
   // Block-Jacobi: blocks over interfaces (2b, 2b+1), deduplicated.
   s.m_id.assign(s.nh, -1); s.m_win.assign(s.nh, 0); s.m_K.assign(s.nh, 0);
-  const int nblocks = (s.d + 1) / 2;
+  const int nblocks = s.mx / 2;   // pairs of the m_x - 1 interfaces
   s.nMblocks = nblocks;
   std::map<std::vector<int>, int> mmap;
   std::vector<int> mfirst;   // representative block of each unique M
@@ -674,28 +676,34 @@ void build_system(System &s, int mx, int mz, int order, const double *xb, const 
     }
   }
   // Deflation tables: S Z per half (two coarse columns), C = Z^T S Z.
-  s.sz_col.assign((size_t)s.nh * 2, -1);
-  s.SZh.assign((size_t)s.nh * 2 * N, 0.0);
+  // Z column (interface a, segment e) is the indicator of rows e*seg .. (e+1)*seg-1
+  // of both halves of interface a (seg = N / zm).  Half h's window is halves
+  // (w, w+1) of interfaces (ca, cb); its own half belongs to ca (even h) or cb.
+  const int zm = s.zm, seg = N / zm, nif = mx - 1;
+  s.sz_col.assign((size_t)s.nh * 2 * zm, -1);
+  s.SZh.assign((size_t)s.nh * 2 * zm * N, 0.0);
   s.C.assign((size_t)s.d * s.d, 0.0);
   for (int h = 0; h < s.nh; ++h) {
     const int i = h / 2;
     const bool even = (h % 2 == 0);
     const int ca = even ? i : i - 1, cb = even ? i + 1 : i;
-    s.sz_col[(size_t)h * 2 + 0] = (ca >= 0 && ca < s.d) ? ca : -1;
-    s.sz_col[(size_t)h * 2 + 1] = (cb >= 0 && cb < s.d) ? cb : -1;
     const double *W = &s.Wblk[(size_t)s.w_id[h] * N * 2 * N];
     for (int p = 0; p < 2; ++p) {
-      const int col = s.sz_col[(size_t)h * 2 + p];
-      if (col < 0) continue;
-      double tot = 0.0;
-      for (int r = 0; r < N; ++r) {
-        double rs = 0.0;
-        for (int c = 0; c < N; ++c) rs += W[(size_t)r * 2 * N + p * N + c];
-        if ((p == 0 && even) || (p == 1 && !even)) rs += 1.0;
-        s.SZh[((size_t)h * 2 + p) * N + r] = rs;
-        tot += rs;
+      const int iface = p == 0 ? ca : cb;
+      if (iface < 0 || iface >= nif) continue;
+      const bool own = (p == 0 && even) || (p == 1 && !even);
+      for (int e = 0; e < zm; ++e) {
+        const int col = iface * zm + e;
+        s.sz_col[((size_t)h * 2 + p) * zm + e] = col;
+        double *sz = &s.SZh[(((size_t)h * 2 + p) * zm + e) * N];
+        for (int r = 0; r < N; ++r) {
+          double rs = 0.0;
+          for (int c = e * seg; c < (e + 1) * seg; ++c) rs += W[(size_t)r * 2 * N + p * N + c];
+          if (own && r / seg == e) rs += 1.0;
+          sz[r] = rs;
+          s.C[(size_t)(i * zm + r / seg) * s.d + col] += rs;
+        }
       }
-      s.C[(size_t)i * s.d + col] += tot;
     }
   }
   // Coarse operator.

@@ -143,6 +143,8 @@ struct smpm_handle {
   double *ycoef = nullptr, *defect = nullptr, *pairs = nullptr, *lam = nullptr, *qb = nullptr;
   double *nb2 = nullptr;   // ||b~||^2 and u_S . b~ per instance, kept from the staging step
   bool one_krylov = false; // one GMRES over every instance (SMPM_FLAG_ONE_KRYLOV)
+  int zlabel = 0;          // deflation space: 0 per interface, 1 per element segment
+  int dmax = 1;            // largest coarse dimension d over the systems
   double *sr1 = nullptr, *sr2 = nullptr, *srn = nullptr;   // segment sums (st_off layout)
   GState *gs = nullptr;
   GState *h_gs = nullptr;      // pinned
@@ -256,7 +258,8 @@ void upload(smpm_handle *H, hipStream_t st) {
   // Group size bounded by the GEMV's LDS budget (windows + wave partials).
   for (System &s : H->sys) {
     SysDev d{};
-    d.n = s.n; d.mx = s.mx; d.mz = s.mz; d.n2 = s.n2; d.N = s.N; d.nh = s.nh; d.d = s.d;
+    d.n = s.n; d.mx = s.mx; d.mz = s.mz; d.n2 = s.n2; d.N = s.N; d.nh = s.nh; d.d = s.d; d.zm = s.zm;
+    H->dmax = std::max(H->dmax, s.d);
     d.singular = s.singular ? 1 : 0; d.kS = s.kS; d.r = s.r; d.tau = s.tau;
     d.nq = 2 * s.n * (s.mz - 1);
     d.Np = (s.N + 3) / 4 * 4;
@@ -317,7 +320,7 @@ void upload(smpm_handle *H, hipStream_t st) {
       }
       f_off += s.r; g_off += 2LL * s.n * (s.mx + s.mz); x_off += s.kS; v_off += (int64_t)(maxit + 1) * s.kS;
       part_off += (int64_t)(maxit + 1) * I.nchunk_x + 2; pr_off += 2LL * I.nchunk_r;
-      hs_off += (int64_t)s.nh * ((s.N + 15) / 16); c_off += s.d;
+      hs_off += (int64_t)s.nh * (s.zm > 1 ? s.zm : (s.N + 15) / 16); c_off += s.d;
       st_off += maxit + 1; rr_off += (int64_t)maxit * maxit; lam_off += (int64_t)s.mx * nq;
       // Halves of a system whose strips share blocks go through the MFMA GEMM
       // (items built below); a system with no sharing streams every half.
@@ -829,9 +832,9 @@ struct Inner {
   static void pre(smpm_handle *H, hipStream_t st) {
     const bool useP = H->method == SMPM_METHOD_DBJ;
     if (useP) {
-      hipLaunchKernelGGL(k_halfsum, dim3(H->n_h), dim3(kBlock), 0, st, H->d_sys, H->d_ins, H->w_h, b(H), H->hs,
-                         (double *)nullptr);
-      hipLaunchKernelGGL(k_coarse, dim3(H->ninst), dim3(kBlock), 0, st, H->d_sys, H->d_ins, (const double *)H->hs,
+      hipLaunchKernelGGL(k_zt<double>, dim3(H->n_h), dim3(kBlock), 0, st, H->d_sys, H->d_ins, H->w_h, b(H), 0,
+                         (const double *)nullptr, (const GState *)nullptr, H->hs);
+      hipLaunchKernelGGL(k_coarse, dim3(H->ninst), dim3(kBlock), sizeof(double) * H->dmax, st, H->d_sys, H->d_ins, (const double *)H->hs,
                          (const double *)nullptr, H->tb, H->cv, (const GState *)nullptr);
     }
     hipLaunchKernelGGL(k_init_basis<T>, dim3(H->n_x), dim3(kBlock), 0, st, H->d_sys, H->d_ins, H->w_x, b(H),
@@ -847,9 +850,9 @@ struct Inner {
   static void twolevel(smpm_handle *H, const T *x, int vslot, const double *scale, const GState *g, T *zb,
                        hipStream_t st) {
     gemv<T, T, T>(H, 1, x, vslot, scale, zb, nullptr, g, st);
-    hipLaunchKernelGGL(k_halfsum_t<T>, dim3(H->n_h), dim3(kBlock), 0, st, H->d_sys, H->d_ins, H->w_h, x, vslot, scale, g,
+    hipLaunchKernelGGL(k_zt<T>, dim3(H->n_h), dim3(kBlock), 0, st, H->d_sys, H->d_ins, H->w_h, x, vslot, scale, g,
                        H->hs);
-    hipLaunchKernelGGL(k_coarse, dim3(H->ninst), dim3(kBlock), 0, st, H->d_sys, H->d_ins, (const double *)H->hs,
+    hipLaunchKernelGGL(k_coarse, dim3(H->ninst), dim3(kBlock), sizeof(double) * H->dmax, st, H->d_sys, H->d_ins, (const double *)H->hs,
                        (const double *)nullptr, (double *)nullptr, H->cv, g);
     hipLaunchKernelGGL(k_add_zc<T>, dim3(H->n_x), dim3(kBlock), 0, st, H->d_sys, H->d_ins, H->w_x, zb,
                        (const double *)H->cv, g);
@@ -861,16 +864,23 @@ struct Inner {
     const int maxit = H->maxit;
     const size_t shm_dot = sizeof(double) * (maxit + 1) * 5;
     T *Vb = V(H), *zb = z(H), *yb = y(H);
+    // Z^T y for P: from the matvec's epilogue (one column per interface) or
+    // a segment-sum pass (one column per element segment)
+    double *hsum = useP && H->zlabel == 0 ? H->hs : nullptr;
     if (H->method == SMPM_METHOD_2LAS) {
       twolevel(H, (const T *)Vb, 1, H->scale, H->gs, zb, st);
       gemv<T, T, T>(H, 0, (const T *)zb, 0, nullptr, yb, nullptr, H->gs, st);
     } else if (useM) {
       gemv<T, T, T>(H, 1, (const T *)Vb, 1, H->scale, zb, nullptr, H->gs, st);
-      gemv<T, T, T>(H, 0, (const T *)zb, 0, nullptr, yb, useP ? H->hs : nullptr, H->gs, st);
+      gemv<T, T, T>(H, 0, (const T *)zb, 0, nullptr, yb, hsum, H->gs, st);
     } else {
-      gemv<T, T, T>(H, 0, (const T *)Vb, 1, H->scale, yb, useP ? H->hs : nullptr, H->gs, st);
+      gemv<T, T, T>(H, 0, (const T *)Vb, 1, H->scale, yb, hsum, H->gs, st);
     }
-    hipLaunchKernelGGL((k_pcorr_dot<T, T>), dim3(H->n_x), dim3(kBlock), sizeof(double) * (maxit + 1) * 4, st, H->d_sys,
+    if (useP && H->zlabel != 0)
+      hipLaunchKernelGGL(k_zt<T>, dim3(H->n_h), dim3(kBlock), 0, st, H->d_sys, H->d_ins, H->w_h, (const T *)yb, 0,
+                         (const double *)nullptr, (const GState *)H->gs, H->hs);
+    hipLaunchKernelGGL((k_pcorr_dot<T, T>), dim3(H->n_x), dim3(kBlock), sizeof(double) * ((maxit + 1) * 4 + H->dmax), st,
+                       H->d_sys,
                        H->d_ins, H->w_x, (const T *)yb, (const double *)H->hs, useP ? 1 : 0, Vb, H->part1,
                        (const GState *)H->gs, maxit);
     // One Krylov space over all instances (Sec. 5.2): every reduction spans
@@ -916,8 +926,11 @@ struct Inner {
     }
     const double *cfin = nullptr;
     if (useP) {   // c' = G (Z^T b - Z^T S z): x = z + Z c'
-      gemv<T, T, T>(H, 0, xfin, 0, nullptr, yb, H->hs, nullptr, st);
-      hipLaunchKernelGGL(k_coarse, dim3(H->ninst), dim3(kBlock), 0, st, H->d_sys, H->d_ins, (const double *)H->hs,
+      gemv<T, T, T>(H, 0, xfin, 0, nullptr, yb, H->zlabel == 0 ? H->hs : nullptr, nullptr, st);
+      if (H->zlabel != 0)
+        hipLaunchKernelGGL(k_zt<T>, dim3(H->n_h), dim3(kBlock), 0, st, H->d_sys, H->d_ins, H->w_h, (const T *)yb, 0,
+                           (const double *)nullptr, (const GState *)nullptr, H->hs);
+      hipLaunchKernelGGL(k_coarse, dim3(H->ninst), dim3(kBlock), sizeof(double) * H->dmax, st, H->d_sys, H->d_ins, (const double *)H->hs,
                          (const double *)H->tb, (double *)nullptr, H->cv, (const GState *)nullptr);
       cfin = H->cv;
     }
@@ -1004,6 +1017,8 @@ smpm_status validate_opts(const smpm_opts *o, smpm_handle *H) {
   H->host_only = (d.flags & SMPM_FLAG_HOST_ONLY) != 0;
   H->no_tune = (d.flags & SMPM_FLAG_NO_TUNE) != 0;
   H->one_krylov = (d.flags & SMPM_FLAG_ONE_KRYLOV) != 0;
+  H->zlabel = d.zlabel;
+  if (d.zlabel != 0 && d.zlabel != 1) return fail(SMPM_EINVAL, "zlabel must be 0 (per interface) or 1 (per element)");
   if (H->one_krylov && H->method != SMPM_METHOD_DBJ) return fail(SMPM_EINVAL, "one Krylov space needs the DBJ method");
   if (d.tol < 0 || d.max_iter < 0 || d.nrhs < 0 || d.inner_tol < 0 || d.max_sweeps < 0)
     return fail(SMPM_EINVAL, "negative option value");
@@ -1029,6 +1044,8 @@ smpm_status setup_common(const smpm_grid *grids, const double *k, int nsys, bool
     if ((int64_t)(g.order + 1) * g.mz > kMaxN) return fail(SMPM_EINVAL, "n * m_z above the supported 544");
     if (g.order + 1 > 22) return fail(SMPM_EINVAL, "order above 21 is not supported");
     if (g.mx - 1 > 1024) return fail(SMPM_EINVAL, "more than 1025 strips");
+    if ((int64_t)(g.mx - 1) * (H->zlabel ? g.mz : 1) > 4096)
+      return fail(SMPM_EINVAL, "coarse space above 4096 unknowns");
     if (!(k[i] >= 0.0) || !std::isfinite(k[i])) return fail(SMPM_EINVAL, "wavenumbers must be finite and >= 0");
   }
   H->sys.resize(nsys);
@@ -1036,6 +1053,7 @@ smpm_status setup_common(const smpm_grid *grids, const double *k, int nsys, bool
   std::vector<int> codes(nsys, SMPM_OK);
   SetupOptions so;
   so.tau = H->opts.tau;
+  so.zlabel = H->zlabel;
   so.threads = nsys > 1 ? 1 : 0;   // parallel over systems, or over strip classes of one system
   parallel_for(nsys, nsys > 1 ? 0 : 1, [&](int i) {
     const smpm_grid &g = one_grid ? grids[0] : grids[i];
@@ -1294,9 +1312,9 @@ smpm_status smpm_apply(smpm_handle *H, smpm_op op, int32_t sysi, const void *x, 
       }
       case SMPM_OP_DEFLATE_P: {   // P x = x - (S Z) G Z^T x
         HIPCHECK(hipMemcpyAsync(H->t64 + I.x_off, x, bx, hipMemcpyDeviceToDevice, st));
-        hipLaunchKernelGGL(k_halfsum, dim3(nhc), dim3(kBlock), 0, st, H->d_sys, H->d_ins, wh, (const double *)H->t64, H->hs,
-                           (double *)nullptr);
-        hipLaunchKernelGGL(k_coarse, dim3(1), dim3(kBlock), 0, st, H->d_sys, H->d_ins + inst, (const double *)H->hs,
+        hipLaunchKernelGGL(k_zt<double>, dim3(nhc), dim3(kBlock), 0, st, H->d_sys, H->d_ins, wh, (const double *)H->t64, 0,
+                           (const double *)nullptr, (const GState *)nullptr, H->hs);
+        hipLaunchKernelGGL(k_coarse, dim3(1), dim3(kBlock), sizeof(double) * H->dmax, st, H->d_sys, H->d_ins + inst, (const double *)H->hs,
                            (const double *)nullptr, (double *)nullptr, H->cv, (const GState *)nullptr);
         hipLaunchKernelGGL(k_xupdate<double>, dim3(nxc), dim3(kBlock), 0, st, H->d_sys, H->d_ins, wx, 3,
                            (const double *)H->t64, (const double *)H->cv, H->y64, (double *)nullptr);
@@ -1305,8 +1323,12 @@ smpm_status smpm_apply(smpm_handle *H, smpm_op op, int32_t sysi, const void *x, 
       }
       case SMPM_OP_DEFLATE_Q: {   // Q x = x - Z G Z^T S x
         HIPCHECK(hipMemcpyAsync(H->t64 + I.x_off, x, bx, hipMemcpyDeviceToDevice, st));
-        gemv<double, double, double>(H, 0, H->t64, 0, nullptr, H->y64, H->hs, nullptr, st, inst);
-        hipLaunchKernelGGL(k_coarse, dim3(1), dim3(kBlock), 0, st, H->d_sys, H->d_ins + inst, (const double *)H->hs,
+        gemv<double, double, double>(H, 0, H->t64, 0, nullptr, H->y64, H->zlabel == 0 ? H->hs : nullptr, nullptr, st,
+                                     inst);
+        if (H->zlabel != 0)
+          hipLaunchKernelGGL(k_zt<double>, dim3(nhc), dim3(kBlock), 0, st, H->d_sys, H->d_ins, wh,
+                             (const double *)H->y64, 0, (const double *)nullptr, (const GState *)nullptr, H->hs);
+        hipLaunchKernelGGL(k_coarse, dim3(1), dim3(kBlock), sizeof(double) * H->dmax, st, H->d_sys, H->d_ins + inst, (const double *)H->hs,
                            (const double *)nullptr, (double *)nullptr, H->cv, (const GState *)nullptr);
         hipLaunchKernelGGL(k_xupdate<double>, dim3(nxc), dim3(kBlock), 0, st, H->d_sys, H->d_ins, wx, 4,
                            (const double *)H->t64, (const double *)H->cv, H->z64, (double *)nullptr);
@@ -1429,10 +1451,11 @@ smpm_status smpm_export(const smpm_handle *H, smpm_table what, int32_t sysi, dou
       if (!need(s.kS * s.d)) return fail(SMPM_EINVAL, "count must be k_S * d");
       std::fill(out, out + count, 0.0);
       for (int h = 0; h < s.nh; ++h)
-        for (int p = 0; p < 2; ++p) {
-          const int col = s.sz_col[(size_t)h * 2 + p];
+        for (int p = 0; p < 2 * s.zm; ++p) {
+          const int col = s.sz_col[(size_t)h * 2 * s.zm + p];
           if (col < 0) continue;
-          for (int i = 0; i < s.N; ++i) out[((int64_t)h * s.N + i) * s.d + col] = s.SZh[((size_t)h * 2 + p) * s.N + i];
+          for (int i = 0; i < s.N; ++i)
+            out[((int64_t)h * s.N + i) * s.d + col] = s.SZh[((size_t)h * 2 * s.zm + p) * s.N + i];
         }
       return SMPM_OK;
     }

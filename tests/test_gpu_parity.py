@@ -28,10 +28,10 @@ def _dev(a):
     return torch.as_tensor(np.ascontiguousarray(a, dtype=np.float64)).cuda()
 
 
-def _oracle(prob, s_idx, q, tol=1e-10, method="dbj"):
+def _oracle(prob, s_idx, q, tol=1e-10, method="dbj", zlabel=0):
     grid = smpm.Grid(prob.xb, prob.zb, prob.n)
     k = float(prob.kwaves[s_idx])
-    o = schur.build(grid, kwave=k)
+    o = schur.build(grid, kwave=k, zlabel=zlabel)
     g = {side: arr[s_idx, q] for side, arr in prob.g.items()} if prob.g else None
     F = smpm.rhs(grid, o.tau, prob.f[s_idx, q], g)
     return o, solve.dbj_solve(o, F, method=method, tol=tol)
@@ -103,6 +103,38 @@ def test_methods_match_oracle(method, name, k):
     assert st["rel_residual_max"] <= ACCEPT
     assert abs(st["iters_max"] - ref.iters) <= 1
     assert _rel(u, ref.u) <= 1e-9
+
+
+@pytest.mark.parametrize("method,name", [(P.METHOD_DBJ, "dbj"), (P.METHOD_2LAS, "2las")])
+@pytest.mark.parametrize("k", [0.0, 1.7])
+def test_per_element_deflation_matches_oracle(method, name, k):
+    # Z with one column per element segment of an interface (d = (m_x - 1) m_z)
+    p = workloads.random_problem(10, 3, 6, kwaves=(k,), seed=23, stretch=True, with_g=True)
+    s, u, st = _gpu_solve(p, method=method, zlabel=1)
+    assert s.info[0]["d"] == 9 * 3
+    o, ref = _oracle(p, 0, 0, method=name, zlabel=1)
+    print("zlabel 1", name, k, st, "oracle iters", ref.iters, "rel", _rel(u, ref.u))
+    assert st["rel_residual_max"] <= ACCEPT
+    assert abs(st["iters_max"] - ref.iters) <= 1
+    assert _rel(u, ref.u) <= 1e-9
+
+
+def test_per_element_deflation_fp32_refinement_and_operators():
+    p = workloads.random_problem(12, 3, 7, seed=5, stretch=True)
+    s, u, st = _gpu_solve(p, precision=P.FP32_IR, zlabel=1)
+    o, ref = _oracle(p, 0, 0, tol=1e-12, zlabel=1)
+    assert st["rel_residual_max"] <= ACCEPT
+    assert _rel(u, ref.u) <= 1e-8
+    s64 = P.Solver(p.xb, p.zb, p.n - 1, zlabel=1)
+    x = np.random.default_rng(8).standard_normal(o.grid.k)
+    xd = _dev(x)
+    y = torch.empty_like(xd)
+    s64.apply(P.OP_DEFLATE_P, 0, xd, y)
+    assert _rel(y.cpu().numpy(), o.P_apply(x)) <= 1e-11
+    s64.apply(P.OP_DEFLATE_Q, 0, xd, y)
+    dq = y.cpu().numpy() - o.Q_apply(x)
+    dq = dq - dq.mean()                    # Q x is defined modulo the interface constant (k = 0)
+    assert np.abs(dq).max() <= 1e-9 * np.abs(o.Q_apply(x)).max()
 
 
 def test_2las_fp32_refinement():

@@ -47,12 +47,13 @@ CASES = [
 ]
 
 
+@pytest.mark.parametrize("zlabel", [0, 1])
 @pytest.mark.parametrize("xb,zb,n,k", CASES)
-def test_host_setup_matches_oracle(lib, xb, zb, n, k):
-    s = P.Solver(xb, zb, n - 1, kwaves=[k], host_only=True)
+def test_host_setup_matches_oracle(lib, xb, zb, n, k, zlabel):
+    s = P.Solver(xb, zb, n - 1, kwaves=[k], host_only=True, zlabel=zlabel)
     grid = smpm.Grid(xb, zb, n)
-    o = schur.build(grid, kwave=k)
-    kS, d = grid.k, grid.mx - 1
+    o = schur.build(grid, kwave=k, zlabel=zlabel)
+    kS, d = grid.k, (grid.mx - 1) * (grid.mz if zlabel else 1)
     assert s.info[0]["kS"] == kS and s.info[0]["r"] == grid.r and s.info[0]["d"] == d
     assert s.info[0]["tau"] == pytest.approx(o.tau, rel=1e-15)
     S = s.export(P.TABLE_SCHUR_DENSE).reshape(kS, kS)
