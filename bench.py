@@ -51,10 +51,10 @@ def gpu_events_time(fn, reps, stream):
     return start.elapsed_time(end) / reps   # ms
 
 
-def make_solver(cfg, precision, inner_tol=0.0):
+def make_solver(cfg, precision, inner_tol=0.0, zlabel=0):
     import paper_1512_01756_amd as P
     from paper_1512_01756_amd import workloads
-    kw = {"precision": precision, "inner_tol": inner_tol}
+    kw = {"precision": precision, "inner_tol": inner_tol, "zlabel": zlabel}
     if cfg in ("c2", "c3"):
         p = workloads.c2() if cfg == "c2" else workloads.c3()
         return P.Solver(p.xb, p.zb, p.n - 1, **kw), p.f.reshape(-1)
@@ -144,6 +144,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--matvec-reps", type=int, default=200)
     ap.add_argument("--matvec-only", action="store_true")
+    ap.add_argument("--zlabel", type=int, default=0, choices=(0, 1),
+                    help="deflation space: 0 one column per interface (the paper's), 1 per element segment")
     ap.add_argument("--inner-tol", type=float, default=0.0,
                     help="FP32-IR inner tolerance floor (0: the library default)")
     args = ap.parse_args()
@@ -179,7 +181,7 @@ def main():
     fvec = None
     for name, prec in (("fp64", P.FP64), ("fp32_ir", P.FP32_IR)):
         t0 = time.perf_counter()
-        s, fh = make_solver(args.config, prec, args.inner_tol)
+        s, fh = make_solver(args.config, prec, args.inner_tol, args.zlabel)
         setup_s = time.perf_counter() - t0
         if fvec is None:
             fvec = torch.as_tensor(fh).to(dev)
@@ -267,6 +269,7 @@ def main():
         "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": f"{args.config}: {WORKLOADS[args.config]}", "systems": s64.nsys,
+                   "deflation": "per element segment" if args.zlabel else "per interface",
                    "instances": fp64["stats"]["instances"], "k_S_total": s64.total_kS, "r_total": s64.total_r,
                    "first_system": {"mx": i0["mx"], "mz": i0["mz"], "n": i0["n"], "d": i0["d"]}},
         "value_definition": "Schur matvecs performed by one full FP64 DBJ solve divided by its wall time",
