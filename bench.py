@@ -179,7 +179,7 @@ def main():
 
     forms = {}
     fvec = None
-    for name, prec in (("fp64", P.FP64), ("fp32_ir", P.FP32_IR)):
+    for name, prec in (("fp64", P.FP64), ("fp32_ir", P.FP32_IR), ("fp16s_ir", P.FP16S_IR)):
         t0 = time.perf_counter()
         s, fh = make_solver(args.config, prec, args.inner_tol, args.zlabel)
         setup_s = time.perf_counter() - t0
@@ -187,16 +187,19 @@ def main():
             fvec = torch.as_tensor(fh).to(dev)
             u = torch.empty_like(fvec)
         for _ in range(args.warmup):
-            s.solve(fvec, None, u)
+            s.solve(fvec, None, u, check=False)
         torch.cuda.synchronize()
         stats_list = []
+        status_list = []
 
         def step():
-            _, st, _ = s.solve(fvec, None, u)
+            _, st, status = s.solve(fvec, None, u, check=(prec != P.FP16S_IR))
             stats_list.append(st)
+            status_list.append(status)
 
         ms = gpu_events_time(step, args.steps, stream)
-        forms[name] = {"solver": s, "ms": ms, "stats": stats_list[-1], "setup_s": setup_s}
+        forms[name] = {"solver": s, "ms": ms, "stats": stats_list[-1], "setup_s": setup_s,
+                       "status": "ok" if status_list[-1] == 0 else f"status {status_list[-1]}"}
 
     # c4 also end to end from the physical 3-D field: transform in y, the
     # batched mode solves, inverse transform (Sec. 5).
@@ -252,7 +255,10 @@ def main():
                      "algorithmic_flops_per_launch": flops64, "achieved_GBps": gbs64,
                      "achieved_TFLOPs": tflops64})
 
-    fp64, ir = forms["fp64"], forms["fp32_ir"]
+    fp64, ir, ir16 = forms["fp64"], forms["fp32_ir"], forms["fp16s_ir"]
+    s16 = ir16["solver"]
+    mv16_ms = gpu_events_time(lambda: s16.schur_apply_all(x32, y32, P.FP16S_IR), args.matvec_reps, stream)
+    bytes16 = matvec_bytes(s64, 2, 4)
     value = fp64["stats"]["schur_matvecs"] / (fp64["ms"] * 1e-3)
     i0 = s64.info[0]
     line = {
@@ -273,19 +279,23 @@ def main():
                    "instances": fp64["stats"]["instances"], "k_S_total": s64.total_kS, "r_total": s64.total_r,
                    "first_system": {"mx": i0["mx"], "mz": i0["mz"], "n": i0["n"], "d": i0["d"]}},
         "value_definition": "Schur matvecs performed by one full FP64 DBJ solve divided by its wall time",
-        "time_to_1e-10_ms": {"fp64": fp64["ms"], "fp32_ir": ir["ms"]},
+        "time_to_1e-10_ms": {"fp64": fp64["ms"], "fp32_ir": ir["ms"], "fp16s_ir": ir16["ms"]},
         "time_to_1e-10_ms_from_physical_field": physical,
         "iterations": {"fp64_max": fp64["stats"]["iters_max"], "fp64_total": fp64["stats"]["iters_total"],
                        "fp32_ir_inner_max": ir["stats"]["iters_max"], "fp32_ir_inner_total": ir["stats"]["iters_total"],
-                       "fp32_ir_sweeps": ir["stats"]["sweeps_max"]},
-        "rel_residual_max": {"fp64": fp64["stats"]["rel_residual_max"], "fp32_ir": ir["stats"]["rel_residual_max"]},
-        "setup_s": {"fp64": fp64["setup_s"], "fp32_ir": ir["setup_s"]},
+                       "fp32_ir_sweeps": ir["stats"]["sweeps_max"],
+                       "fp16s_ir_inner_max": ir16["stats"]["iters_max"], "fp16s_ir_inner_total": ir16["stats"]["iters_total"],
+                       "fp16s_ir_sweeps": ir16["stats"]["sweeps_max"], "fp16s_ir_status": ir16["status"]},
+        "rel_residual_max": {"fp64": fp64["stats"]["rel_residual_max"], "fp32_ir": ir["stats"]["rel_residual_max"],
+                             "fp16s_ir": ir16["stats"]["rel_residual_max"]},
+        "setup_s": {"fp64": fp64["setup_s"], "fp32_ir": ir["setup_s"], "fp16s_ir": ir16["setup_s"]},
         "gemm_schedules": {"matvec_S64_S32_M64_M32": i0["gemm_sched"], "element": i0["elem_sched"],
                            "legend": "0 split-K 16 waves, 1 split-K 8 waves, 2 LDS-staged XCD-ordered, "
                                      "3 LDS-staged plain, -1 unused; picked by timing at setup"},
         "matvec_kernel": {"fp64_us": mv64_ms * 1e3, "fp32_us": mv32_ms * 1e3,
                           "fp64_matvecs_per_s": 1e3 / mv64_ms, "fp32_matvecs_per_s": 1e3 / mv32_ms,
-                          "fp64_GBps": gbs64, "fp32_GBps": gbs32},
+                          "fp64_GBps": gbs64, "fp32_GBps": gbs32, "fp16s_us": mv16_ms * 1e3,
+                          "fp16s_GBps": bytes16 / (mv16_ms * 1e-3) / 1e9},
         "roofline": roofline,
     }
     if not args.no_cpu_baseline and args.config == "c2":

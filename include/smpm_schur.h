@@ -64,16 +64,21 @@ typedef enum {
   SMPM_ENOMEM = -2,      /* host or device allocation failed */
   SMPM_EHIP = -3,        /* HIP runtime error */
   SMPM_ESINGULAR = -4,   /* k = 0 with m_x < 4, or a factorization failed */
-  SMPM_ENOTCONV = -5,    /* max_iter / sweeps reached; u holds the last iterate */
+  SMPM_ENOTCONV = -5,    /* max_iter / sweeps reached, or a refinement sweep failed
+                            to cut the residual by 10%; u holds the last iterate */
   SMPM_ENONFINITE = -6,  /* NaN or Inf in the inputs or the iterates */
   SMPM_EUNSUPPORTED = -7 /* the call needs a GPU but the handle is host-only */
 } smpm_status;
 
 typedef enum {
   SMPM_FP64 = 0,     /* every step in FP64 */
-  SMPM_FP32_IR = 1   /* FP32 inner DBJ-GMRES (operators, Krylov basis) inside
+  SMPM_FP32_IR = 1,  /* FP32 inner DBJ-GMRES (operators, Krylov basis) inside
                         FP64 iterative refinement: outer residual, projections,
                         coarse solve and least squares stay FP64 */
+  SMPM_FP16S_IR = 2  /* as FP32_IR, with the Schur and block-Jacobi operators of
+                        the inner solve stored in FP16, each element's row
+                        segment of a block scaled by its largest magnitude
+                        (FP32 scales, FP32 arithmetic) */
 } smpm_precision;
 
 typedef enum {
@@ -110,7 +115,7 @@ typedef struct {
                           max(inner_tol * ||r||, 0.5 * tol * ||b~||), r the sweep's
                           FP64 residual; 0 selects 1e-4 (one sweep gains about
                           1e-4 to 1e-5 with FP32 operators) */
-  int32_t max_sweeps;  /* FP32_IR outer sweeps; 0 selects 12 */
+  int32_t max_sweeps;  /* refinement sweeps; 0 selects 12 (FP32_IR) or 40 (FP16S_IR) */
   int32_t flags;       /* SMPM_FLAG_* */
   int32_t zlabel;      /* deflation space Z (Sec. 3.3): 0 one column per interface
                           (the paper's, d = m_x - 1), 1 one column per element

@@ -17,7 +17,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libsmpm_schur.so")
 
 OK, EINVAL, ENOMEM, EHIP, ESINGULAR, ENOTCONV, ENONFINITE, EUNSUPPORTED = 0, -1, -2, -3, -4, -5, -6, -7
-FP64, FP32_IR = 0, 1
+FP64, FP32_IR, FP16S_IR = 0, 1, 2
 METHOD_DBJ, METHOD_BJ, METHOD_SCHUR, METHOD_2LAS = 0, 1, 2, 3
 FLAG_HOST_ONLY = 1
 FLAG_NO_TUNE = 2

@@ -14,7 +14,7 @@ constexpr int kMaxRowsPerLane = (kMaxN + 63) / 64;
 // block ([col][row]) so that a wavefront reads consecutive rows of one column.
 struct SysDev {
   int n, mx, mz, n2, N, nh, d, singular;
-  int Np;                // rows of the stored Schur / block-Jacobi blocks (N rounded up to 4)
+  int Np;                // rows of the stored Schur / block-Jacobi blocks (N rounded up to 8)
   int zm;                // coarse columns per interface: 1, or m_z (one per element segment)
   const int *sz_col;     // per half: [2 zm] coarse columns of its S Z rows (-1: none)
   const double *SZh;     // per half: [2 zm][N]
@@ -25,6 +25,11 @@ struct SysDev {
   const int *w_id, *w_win;
   const double *M64;     // unique block-Jacobi row chunks: [chunk][4N][N]
   const float *M32;
+  // FP16 copies (SMPM_FP16S_IR handles only): each row segment of n rows
+  // (one element) of a block stored divided by its largest magnitude;
+  // scales [blk][m_z].
+  const _Float16 *W16, *M16;
+  const float *W16s, *M16s;
   const int *m_id, *m_win, *m_K;
   const double *Gc;      // coarse operator, column-major d x d
   const double *uS, *uL; // null vectors (k = 0), else nullptr
@@ -73,7 +78,10 @@ constexpr int kGemmVecs = 32;   // windows per workgroup
 struct GWork {
   const double *blk64;
   const float *blk32;
+  const _Float16 *blk16;   // FP16 copy (or nullptr) and its row-segment scales [m_z]
+  const float *sc16;
   int N, Np, K, vstart, vcount, ident;   // ident: add the identity (S = I + W)
+  int n, pad;                            // n: rows per scale segment (one element)
   int64_t kS;
 };
 // One window of a GEMM item, with every offset resolved at setup.

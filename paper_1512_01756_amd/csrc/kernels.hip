@@ -11,15 +11,30 @@
 namespace smpm {
 
 template <typename T> struct Tab;
+// Operator tables by storage type.  FP16 rows carry a per-(block, element
+// segment) scale, applied to the product row in the epilogue.
 template <> struct Tab<double> {
   __device__ static const double *W(const SysDev &s) { return s.W64; }
   __device__ static const double *M(const SysDev &s) { return s.M64; }
   __device__ static const double *blk(const GWork &w) { return w.blk64; }
+  __device__ static float rs(const GWork &, int) { return 1.0f; }
+  __device__ static float rs(const SysDev &, int, int, int) { return 1.0f; }
 };
 template <> struct Tab<float> {
   __device__ static const float *W(const SysDev &s) { return s.W32; }
   __device__ static const float *M(const SysDev &s) { return s.M32; }
   __device__ static const float *blk(const GWork &w) { return w.blk32; }
+  __device__ static float rs(const GWork &, int) { return 1.0f; }
+  __device__ static float rs(const SysDev &, int, int, int) { return 1.0f; }
+};
+template <> struct Tab<_Float16> {
+  __device__ static const _Float16 *W(const SysDev &s) { return s.W16; }
+  __device__ static const _Float16 *M(const SysDev &s) { return s.M16; }
+  __device__ static const _Float16 *blk(const GWork &w) { return w.blk16; }
+  __device__ static float rs(const GWork &w, int row) { return w.sc16[row / w.n]; }
+  __device__ static float rs(const SysDev &s, int op, int id, int row) {
+    return (op == 0 ? s.W16s : s.M16s)[(size_t)id * s.mz + row / s.n];
+  }
 };
 
 // Deflation space Z (Sec. 3.3): coarse column of interface row `row` of half
@@ -108,17 +123,24 @@ __device__ inline void colsplit(const TO *__restrict__ blk, int R, int row, int 
 // lane: 2 in FP64, 4 in FP32) along each column of the padded column-major
 // block, NW waves splitting the columns.  Same operation and outputs as
 // k_half_gemv with one half per item.
-template <typename TO> struct Vec16;
+// Vector load of VR consecutive rows of one column: 16 bytes in FP64 and FP32,
+// 8 bytes in FP16 (so a tile stays 256 rows and its LDS partials fit).
+struct alignas(8) half4 {
+  _Float16 v[4];
+};
+template <typename TS> struct Vec16;
 template <> struct Vec16<double> { using T = double2; static constexpr int R = 2; };
 template <> struct Vec16<float> { using T = float4; static constexpr int R = 4; };
+template <> struct Vec16<_Float16> { using T = half4; static constexpr int R = 4; };
 
-template <typename TO, typename TX, typename TY, int NW>
+// TS: storage type of the operator tables; TO: arithmetic type.
+template <typename TS, typename TO, typename TX, typename TY, int NW>
 __global__ __launch_bounds__(64 * NW) void k_half_gemv_stream(
     const SysDev *__restrict__ sys, const InstDev *__restrict__ ins, const HWork *__restrict__ work,
     int op, const TX *__restrict__ xbase, int x_vslot, const double *__restrict__ scale,
     TY *__restrict__ ybase, double *__restrict__ hsum, const GState *__restrict__ gs) {
-  using V = typename Vec16<TO>::T;
-  constexpr int VR = Vec16<TO>::R;
+  using V = typename Vec16<TS>::T;
+  constexpr int VR = Vec16<TS>::R;
   constexpr int TR = 64 * VR;
   extern __shared__ double sm[];
   const int i = work[blockIdx.x].inst;
@@ -131,16 +153,18 @@ __global__ __launch_bounds__(64 * NW) void k_half_gemv_stream(
   const int tile = blockIdx.y;
   if (tile >= tiles) return;
   const int64_t kS = S.kS;
-  int K;
-  const TO *blk;
+  int K, bid;
+  const TS *blk;
   int64_t win;
   if (op == 0) {
     K = 2 * N;
-    blk = Tab<TO>::W(S) + (size_t)S.w_id[h] * 2 * N * Np;
+    bid = S.w_id[h];
+    blk = Tab<TS>::W(S) + (size_t)bid * 2 * N * Np;
     win = (int64_t)S.w_win[h] * N;
   } else {
     K = S.m_K[h];
-    blk = Tab<TO>::M(S) + (size_t)S.m_id[h] * 4 * N * Np;
+    bid = S.m_id[h];
+    blk = Tab<TS>::M(S) + (size_t)bid * 4 * N * Np;
     win = (int64_t)S.m_win[h] * N;
   }
   const int it = gs ? gs[i].iter : 0;
@@ -170,17 +194,17 @@ __global__ __launch_bounds__(64 * NW) void k_half_gemv_stream(
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
       const TO xv = (TO)xw[c + u];
-      const TO *pv = reinterpret_cast<const TO *>(&v[u]);
+      const TS *pv = reinterpret_cast<const TS *>(&v[u]);
 #pragma unroll
-      for (int r = 0; r < VR; ++r) acc[r] += pv[r] * xv;
+      for (int r = 0; r < VR; ++r) acc[r] += (TO)pv[r] * xv;
     }
   }
   for (; c < c1; ++c) {
     const V v = live ? colv[(size_t)c * stride] : V{};
     const TO xv = (TO)xw[c];
-    const TO *pv = reinterpret_cast<const TO *>(&v);
+    const TS *pv = reinterpret_cast<const TS *>(&v);
 #pragma unroll
-    for (int r = 0; r < VR; ++r) acc[r] += pv[r] * xv;
+    for (int r = 0; r < VR; ++r) acc[r] += (TO)pv[r] * xv;
   }
 #pragma unroll
   for (int r = 0; r < VR; ++r) red[wave * TR + lane * VR + r] = (double)acc[r];
@@ -192,7 +216,7 @@ __global__ __launch_bounds__(64 * NW) void k_half_gemv_stream(
     TO v = (TO)0;
 #pragma unroll
     for (int w = 0; w < NW; ++w) v += (TO)red[w * TR + rr];
-    double vd = (double)v;
+    double vd = (double)(v * (TO)Tab<TS>::rs(S, op, bid, row));
     if (op == 0) vd += (double)x[(int64_t)h * N + row] * xs;
     const TY out = (TY)vd;
     ybase[I.x_off + (int64_t)h * N + row] = out;
@@ -279,7 +303,7 @@ __device__ inline void load_windows(const GWork &wk, const GVec *__restrict__ gv
 // Split-K schedule (few items): grid (item, 16-row tile), KP waves split K;
 // U K-steps of operand loads in flight per wave; partial tiles summed in LDS
 // in a fixed order.
-template <typename TO, typename TX, typename TY, int KP>
+template <typename TS, typename TO, typename TX, typename TY, int KP>
 __global__ __launch_bounds__(64 * KP) void k_half_gemm(
     const GWork *__restrict__ work, const GVec *__restrict__ gvec, const TX *__restrict__ xbase, int x_vslot,
     const double *__restrict__ scale, TY *__restrict__ ybase, double *__restrict__ hsum,
@@ -298,7 +322,7 @@ __global__ __launch_bounds__(64 * KP) void k_half_gemm(
   int anylive = 0;
   for (int v = 0; v < wk.vcount; ++v) anylive |= wi[v].live;
   if (!anylive) return;
-  const TO *blk = Tab<TO>::blk(wk);
+  const TS *blk = Tab<TS>::blk(wk);
   const int kp = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int arow = rt * 16 + (lane & 15);
   const bool alive = arow < Np;
@@ -317,7 +341,7 @@ __global__ __launch_bounds__(64 * KP) void k_half_gemm(
       const int k = 4 * (st + u) + kq;
       const bool kin = st + u < s1 && k < K;
       const int64_t ga = wa + k, gb = wb + k;
-      a[u] = (alive && kin) ? blk[(size_t)k * Np + arow] : (TO)0;
+      a[u] = (alive && kin) ? (TO)blk[(size_t)k * Np + arow] : (TO)0;
       b0[u] = (la && kin && ga >= 0 && ga < kS) ? (TO)xbase[xa + ga] : (TO)0;
       b1[u] = (lb && kin && gb >= 0 && gb < kS) ? (TO)xbase[xb + gb] : (TO)0;
     }
@@ -342,6 +366,7 @@ __global__ __launch_bounds__(64 * KP) void k_half_gemm(
       TO t = (TO)red[idx];
 #pragma unroll
       for (int q = 1; q < KP; ++q) t += (TO)red[q * 16 * VT + idx];
+      t *= (TO)Tab<TS>::rs(wk, row);
       if (wk.ident) t += (TO)xbase[wi[v].xoff + wi[v].xh + row];
       const TY out = (TY)((double)t * wi[v].scale);
       ybase[wi[v].y + row] = out;
@@ -370,7 +395,7 @@ __global__ __launch_bounds__(64 * KP) void k_half_gemm(
 // XCD-aware order (`units`): workgroup L runs on XCD L mod 8, and every tile
 // that reads one stored block is placed on the same XCD, so the block and the
 // windows are fetched into one L2 instead of eight.
-template <typename TO, typename TX, typename TY, int CT>
+template <typename TS, typename TO, typename TX, typename TY, int CT>
 __global__ __launch_bounds__(256) void k_half_gemm_t(
     const GWork *__restrict__ work, const int2 *__restrict__ units, const GVec *__restrict__ gvec,
     const TX *__restrict__ xbase, int x_vslot, const double *__restrict__ scale, TY *__restrict__ ybase,
@@ -395,7 +420,7 @@ __global__ __launch_bounds__(256) void k_half_gemm_t(
   int anylive = 0;
   for (int v = 0; v < wk.vcount; ++v) anylive |= wi[v].live;
   if (!anylive) return;
-  const TO *__restrict__ blk = Tab<TO>::blk(wk);
+  const TS *__restrict__ blk = Tab<TS>::blk(wk);
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int arow = rg * 64 + wave * 16 + (lane & 15);
   const bool alive = arow < Np;
@@ -417,7 +442,7 @@ __global__ __launch_bounds__(256) void k_half_gemm_t(
 #pragma unroll
     for (int s = 0; s < KC / 4; ++s) {
       const int k = kc * KC + 4 * s + kq;
-      dst[s] = (alive && k < K) ? blk[(size_t)k * Np + arow] : (TO)0;
+      dst[s] = (alive && k < K) ? (TO)blk[(size_t)k * Np + arow] : (TO)0;
     }
   };
   auto store_b = [&](int buf) {
@@ -463,7 +488,7 @@ __global__ __launch_bounds__(256) void k_half_gemm_t(
     for (int j = 0; j < 4; ++j) {
       const int row = rg * 64 + wave * 16 + Mfma<TO>::row(lane, j);
       if (ok && row < N) {
-        TO val = acc[t][j];
+        TO val = acc[t][j] * (TO)Tab<TS>::rs(wk, row);
         if (wk.ident) val += (TO)xbase[wi[v].xoff + wi[v].xh + row];
         const TY out = (TY)((double)val * wi[v].scale);
         ybase[wi[v].y + row] = out;

@@ -79,10 +79,36 @@ std::vector<T> to_colmajor_padded(const std::vector<double> &a, int nb, int rows
   return out;
 }
 
+// FP16 copy of nb row-major rows x cols blocks, column-major with leading
+// dimension ld: every segment of `seg` rows (one element's nodes) is divided by
+// its largest magnitude, which goes to scale[b][row / seg].
+std::vector<_Float16> to_half_scaled(const std::vector<double> &a, int nb, int rows, int cols, int ld, int seg,
+                                     std::vector<float> &scale) {
+  const int nseg = rows / seg;
+  std::vector<_Float16> out((size_t)nb * ld * cols, (_Float16)0.0f);
+  scale.assign((size_t)nb * nseg, 1.0f);
+  for (int b = 0; b < nb; ++b)
+    for (int e = 0; e < nseg; ++e) {
+      double mx = 0.0;
+      for (int r = e * seg; r < (e + 1) * seg; ++r)
+        for (int c = 0; c < cols; ++c) mx = std::max(mx, std::fabs(a[(size_t)b * rows * cols + (size_t)r * cols + c]));
+      const double sc = mx > 0.0 ? mx : 1.0;
+      scale[(size_t)b * nseg + e] = (float)sc;
+      for (int r = e * seg; r < (e + 1) * seg; ++r)
+        for (int c = 0; c < cols; ++c)
+          out[(size_t)b * ld * cols + (size_t)c * ld + r] =
+              (_Float16)(float)(a[(size_t)b * rows * cols + (size_t)r * cols + c] / sc);
+    }
+  return out;
+}
+
 constexpr int kIterChunk = 4;
 // A refinement sweep's inner solve stops once its residual is below
 // kSweepSafety * tol * ||b~|| (or inner_tol times its own right-hand side).
 constexpr double kSweepSafety = 0.5;
+// Refinement stops with ENOTCONV when a sweep leaves the worst relative
+// residual above this fraction of the previous sweep's.
+constexpr double kStagnation = 0.9;
 constexpr int kWaves = 16;   // waves per workgroup of the GEMV-shaped kernels
 
 }  // namespace
@@ -112,7 +138,7 @@ struct smpm_handle {
   // GEMM schedule of each batched list, picked at setup by timing every
   // candidate: [op][precision] for the matvec lists, [kind][width] for the
   // element-interior lists.
-  int sched[2][2] = {};
+  int sched[2][3] = {};   // [op][FP64, FP32, FP16 storage]
   int cg_sched[3][2] = {};
   int n_gS = 0, n_gM = 0;
   std::vector<int> gSi_start, gSi_cnt, gMi_start, gMi_cnt;
@@ -144,6 +170,7 @@ struct smpm_handle {
   double *nb2 = nullptr;   // ||b~||^2 and u_S . b~ per instance, kept from the staging step
   bool one_krylov = false; // one GMRES over every instance (SMPM_FLAG_ONE_KRYLOV)
   int zlabel = 0;          // deflation space: 0 per interface, 1 per element segment
+  bool op16 = false;       // FP16 operator copies for the refinement's inner solve
   int dmax = 1;            // largest coarse dimension d over the systems
   double *sr1 = nullptr, *sr2 = nullptr, *srn = nullptr;   // segment sums (st_off layout)
   GState *gs = nullptr;
@@ -262,9 +289,16 @@ void upload(smpm_handle *H, hipStream_t st) {
     H->dmax = std::max(H->dmax, s.d);
     d.singular = s.singular ? 1 : 0; d.kS = s.kS; d.r = s.r; d.tau = s.tau;
     d.nq = 2 * s.n * (s.mz - 1);
-    d.Np = (s.N + 3) / 4 * 4;
+    d.Np = (s.N + 7) / 8 * 8;   // 16-byte columns in FP64, FP32 and FP16
     d.W64 = dupload(own, to_colmajor_padded<double>(s.Wblk, s.nW, s.N, 2 * s.N, d.Np), st);
     d.W32 = dupload(own, to_colmajor_padded<float>(s.Wblk, s.nW, s.N, 2 * s.N, d.Np), st);
+    if (H->op16) {
+      std::vector<float> sc;
+      d.W16 = dupload(own, to_half_scaled(s.Wblk, s.nW, s.N, 2 * s.N, d.Np, s.n, sc), st);
+      d.W16s = dupload(own, sc, st);
+      d.M16 = dupload(own, to_half_scaled(s.Mblk, s.nM, s.N, 4 * s.N, d.Np, s.n, sc), st);
+      d.M16s = dupload(own, sc, st);
+    }
     d.w_id = dupload(own, s.w_id, st);
     d.w_win = dupload(own, s.w_win, st);
     d.M64 = dupload(own, to_colmajor_padded<double>(s.Mblk, s.nM, s.N, 4 * s.N, d.Np), st);
@@ -451,6 +485,11 @@ void upload(smpm_handle *H, hipStream_t st) {
         GWork w{};
         w.blk64 = (op == 0 ? d.W64 : d.M64) + (size_t)id * (op == 0 ? 2 : 4) * N * d.Np;
         w.blk32 = (op == 0 ? d.W32 : d.M32) + (size_t)id * (op == 0 ? 2 : 4) * N * d.Np;
+        if (H->op16) {
+          w.blk16 = (op == 0 ? d.W16 : d.M16) + (size_t)id * (op == 0 ? 2 : 4) * N * d.Np;
+          w.sc16 = (op == 0 ? d.W16s : d.M16s) + (size_t)id * s.mz;
+        }
+        w.n = s.n;
         w.N = N; w.Np = d.Np; w.K = K; w.kS = s.kS; w.ident = op == 0 ? 1 : 0;
         w.vstart = (int)gv.size();
         w.vcount = (int)std::min<size_t>(kGemmVecs, vecs.size() - a);
@@ -570,35 +609,35 @@ int gemm_default(int count, int rt16) {
   return kThrPlain;
 }
 
-template <typename TO, typename TX, typename TY>
+template <typename TS, typename TO, typename TX, typename TY>
 void gemm_launch(smpm_handle *H, int sched, const GWork *w, int count, const int2 *units, int nunits, const TX *x,
                  int vslot, const double *scale, TY *y, double *hsum, const GState *gs, hipStream_t st) {
   const int rt16 = (H->Nmax + 15) / 16;
   switch (sched) {
     case kSplit16:
-      hipLaunchKernelGGL((k_half_gemm<TO, TX, TY, 16>), dim3(count, rt16), dim3(1024), 0, st, w, H->g_vec, x, vslot,
+      hipLaunchKernelGGL((k_half_gemm<TS, TO, TX, TY, 16>), dim3(count, rt16), dim3(1024), 0, st, w, H->g_vec, x, vslot,
                          scale, y, hsum, gs);
       break;
     case kSplit8:
-      hipLaunchKernelGGL((k_half_gemm<TO, TX, TY, 8>), dim3(count, rt16), dim3(512), 0, st, w, H->g_vec, x, vslot,
+      hipLaunchKernelGGL((k_half_gemm<TS, TO, TX, TY, 8>), dim3(count, rt16), dim3(512), 0, st, w, H->g_vec, x, vslot,
                          scale, y, hsum, gs);
       break;
     case kThrXcd:
       if (units) {
-        hipLaunchKernelGGL((k_half_gemm_t<TO, TX, TY, 2>), dim3(nunits), dim3(256), 0, st, w, units, H->g_vec, x, vslot,
+        hipLaunchKernelGGL((k_half_gemm_t<TS, TO, TX, TY, 2>), dim3(nunits), dim3(256), 0, st, w, units, H->g_vec, x, vslot,
                            scale, y, hsum, gs);
         break;
       }
       [[fallthrough]];
     default:
-      hipLaunchKernelGGL((k_half_gemm_t<TO, TX, TY, 2>), dim3(count, (H->Nmax + 63) / 64), dim3(256), 0, st, w,
+      hipLaunchKernelGGL((k_half_gemm_t<TS, TO, TX, TY, 2>), dim3(count, (H->Nmax + 63) / 64), dim3(256), 0, st, w,
                          (const int2 *)nullptr, H->g_vec, x, vslot, scale, y, hsum, gs);
   }
 }
 
-template <typename TO, typename TX, typename TY>
-void gemv(smpm_handle *H, int op, const TX *x, int vslot, const double *scale, TY *y, double *hsum,
-          const GState *gs, hipStream_t st, int inst = -1) {
+template <typename TS, typename TO, typename TX, typename TY>
+void gemv_ts(smpm_handle *H, int op, const TX *x, int vslot, const double *scale, TY *y, double *hsum,
+             const GState *gs, hipStream_t st, int inst) {
   const int Kmax = (op == 0 ? 2 : 4) * H->Nmax;
   // halves with a shared block: MFMA GEMM over the windows that share it
   {
@@ -609,10 +648,10 @@ void gemv(smpm_handle *H, int op, const TX *x, int vslot, const double *scale, T
       count = op == 0 ? H->gSi_cnt[inst] : H->gMi_cnt[inst];
     }
     if (count > 0) {
-      const int prec = sizeof(TO) == 8 ? 0 : 1;
+      const int prec = sizeof(TS) == 8 ? 0 : (sizeof(TS) == 4 ? 1 : 2);
       const int sched = inst < 0 ? H->sched[op][prec] : gemm_default(count, (H->Nmax + 15) / 16);
-      gemm_launch<TO, TX, TY>(H, sched, w, count, inst < 0 ? (op == 0 ? H->u_S : H->u_M) : nullptr,
-                              op == 0 ? H->n_uS : H->n_uM, x, vslot, scale, y, hsum, gs, st);
+      gemm_launch<TS, TO, TX, TY>(H, sched, w, count, inst < 0 ? (op == 0 ? H->u_S : H->u_M) : nullptr,
+                                  op == 0 ? H->n_uS : H->n_uM, x, vslot, scale, y, hsum, gs, st);
     }
   }
   // halves with their own block: streaming kernel
@@ -624,17 +663,28 @@ void gemv(smpm_handle *H, int op, const TX *x, int vslot, const double *scale, T
       count = op == 0 ? H->S1_cnt[inst] : H->M1_cnt[inst];
     }
     if (count > 0) {
-      constexpr int TR = 64 * Vec16<TO>::R;
+      constexpr int TR = 64 * Vec16<TS>::R;
       const int tiles = (H->Nmax + TR - 1) / TR;
       const size_t shm = sizeof(double) * (Kmax + kWaves * TR);
-      hipLaunchKernelGGL((k_half_gemv_stream<TO, TX, TY, kWaves>), dim3(count, tiles), dim3(64 * kWaves), shm, st,
+      hipLaunchKernelGGL((k_half_gemv_stream<TS, TO, TX, TY, kWaves>), dim3(count, tiles), dim3(64 * kWaves), shm, st,
                          H->d_sys, H->d_ins, w, op, x, vslot, scale, y, hsum, gs);
     }
   }
 }
 
-// dst = A(k)^-1 src (node space; src and dst must not overlap): element
-// solves, the per-strip z-interface capacitance solve, element corrections.
+// y = S x (op 0) or M^-1 x (op 1) for every instance (or one), arithmetic in
+// TO; FP32 arithmetic reads the FP16 tables when h16 is set.
+template <typename TO, typename TX, typename TY>
+void gemv(smpm_handle *H, int op, const TX *x, int vslot, const double *scale, TY *y, double *hsum,
+          const GState *gs, hipStream_t st, int inst = -1, bool h16 = false) {
+  if constexpr (sizeof(TO) == 8) {
+    gemv_ts<double, TO, TX, TY>(H, op, x, vslot, scale, y, hsum, gs, st, inst);
+  } else {
+    if (h16) gemv_ts<_Float16, TO, TX, TY>(H, op, x, vslot, scale, y, hsum, gs, st, inst);
+    else gemv_ts<float, TO, TX, TY>(H, op, x, vslot, scale, y, hsum, gs, st, inst);
+  }
+}
+
 // Element-interior GEMM schedules: split K (kSplit8) or the LDS-staged
 // 64-row tile (kThrXcd with units, kThrPlain without).  sched < 0: by size.
 template <int CT>
@@ -701,7 +751,7 @@ float time_launch(hipStream_t st, hipEvent_t e0, hipEvent_t e1, F &&fn) {
 void tune(smpm_handle *H, hipStream_t st) {
   const int rt16 = (H->Nmax + 15) / 16;
   for (int op = 0; op < 2; ++op)
-    for (int pr = 0; pr < 2; ++pr) H->sched[op][pr] = gemm_default(op == 0 ? H->n_gS : H->n_gM, rt16);
+    for (int pr = 0; pr < 3; ++pr) H->sched[op][pr] = gemm_default(op == 0 ? H->n_gS : H->n_gM, rt16);
   for (int k = 0; k < 3; ++k)
     for (int w = 0; w < 2; ++w) H->cg_sched[k][w] = -1;
   if (H->no_tune) return;
@@ -729,17 +779,21 @@ void tune(smpm_handle *H, hipStream_t st) {
       const GWork *w = op == 0 ? H->g_S : H->g_M;
       const int2 *u = op == 0 ? H->u_S : H->u_M;
       const int nu = op == 0 ? H->n_uS : H->n_uM;
-      for (int pr = 0; pr < 2; ++pr) {
+      for (int pr = 0; pr < (H->op16 ? 3 : 2); ++pr) {
         float best = 1e30f;
         for (int sc = 0; sc < kNumSched; ++sc) {
           const float ms = pr == 0
               ? time_launch(st, e0, e1, [&] {
-                  gemm_launch<double, double, double>(H, sc, w, count, u, nu, H->t64, 0, nullptr, H->y64,
-                                                      op == 0 ? H->hs : nullptr, nullptr, st);
+                  gemm_launch<double, double, double, double>(H, sc, w, count, u, nu, H->t64, 0, nullptr, H->y64,
+                                                              op == 0 ? H->hs : nullptr, nullptr, st);
+                })
+              : pr == 1 ? time_launch(st, e0, e1, [&] {
+                  gemm_launch<float, float, float, float>(H, sc, w, count, u, nu, H->t32, 0, nullptr, H->y32,
+                                                          op == 0 ? H->hs : nullptr, nullptr, st);
                 })
               : time_launch(st, e0, e1, [&] {
-                  gemm_launch<float, float, float>(H, sc, w, count, u, nu, H->t32, 0, nullptr, H->y32,
-                                                   op == 0 ? H->hs : nullptr, nullptr, st);
+                  gemm_launch<_Float16, float, float, float>(H, sc, w, count, u, nu, H->t32, 0, nullptr, H->y32,
+                                                             op == 0 ? H->hs : nullptr, nullptr, st);
                 });
           if (ms < best) { best = ms; H->sched[op][pr] = sc; }
         }
@@ -827,6 +881,7 @@ struct Inner {
   static T *t(smpm_handle *H) { if constexpr (P == 0) return (T *)H->t64; else return (T *)H->t32; }
   static const double *b(smpm_handle *H) { return P == 0 ? H->bS : H->rb; }
   static double tol(smpm_handle *H) { return P == 0 ? H->tol : H->inner_tol; }
+  static bool h16(smpm_handle *H) { return P == 1 && H->op16; }
 
   // coarse part c = G Z^T b (kept as t_b = Z^T b for the assembly), r0 = P b
   static void pre(smpm_handle *H, hipStream_t st) {
@@ -849,7 +904,7 @@ struct Inner {
   // `iter` when vslot, else the interface vector t).
   static void twolevel(smpm_handle *H, const T *x, int vslot, const double *scale, const GState *g, T *zb,
                        hipStream_t st) {
-    gemv<T, T, T>(H, 1, x, vslot, scale, zb, nullptr, g, st);
+    gemv<T, T, T>(H, 1, x, vslot, scale, zb, nullptr, g, st, -1, h16(H));
     hipLaunchKernelGGL(k_zt<T>, dim3(H->n_h), dim3(kBlock), 0, st, H->d_sys, H->d_ins, H->w_h, x, vslot, scale, g,
                        H->hs);
     hipLaunchKernelGGL(k_coarse, dim3(H->ninst), dim3(kBlock), sizeof(double) * H->dmax, st, H->d_sys, H->d_ins, (const double *)H->hs,
@@ -869,12 +924,12 @@ struct Inner {
     double *hsum = useP && H->zlabel == 0 ? H->hs : nullptr;
     if (H->method == SMPM_METHOD_2LAS) {
       twolevel(H, (const T *)Vb, 1, H->scale, H->gs, zb, st);
-      gemv<T, T, T>(H, 0, (const T *)zb, 0, nullptr, yb, nullptr, H->gs, st);
+      gemv<T, T, T>(H, 0, (const T *)zb, 0, nullptr, yb, nullptr, H->gs, st, -1, h16(H));
     } else if (useM) {
-      gemv<T, T, T>(H, 1, (const T *)Vb, 1, H->scale, zb, nullptr, H->gs, st);
-      gemv<T, T, T>(H, 0, (const T *)zb, 0, nullptr, yb, hsum, H->gs, st);
+      gemv<T, T, T>(H, 1, (const T *)Vb, 1, H->scale, zb, nullptr, H->gs, st, -1, h16(H));
+      gemv<T, T, T>(H, 0, (const T *)zb, 0, nullptr, yb, hsum, H->gs, st, -1, h16(H));
     } else {
-      gemv<T, T, T>(H, 0, (const T *)Vb, 1, H->scale, yb, hsum, H->gs, st);
+      gemv<T, T, T>(H, 0, (const T *)Vb, 1, H->scale, yb, hsum, H->gs, st, -1, h16(H));
     }
     if (useP && H->zlabel != 0)
       hipLaunchKernelGGL(k_zt<T>, dim3(H->n_h), dim3(kBlock), 0, st, H->d_sys, H->d_ins, H->w_h, (const T *)yb, 0,
@@ -921,12 +976,12 @@ struct Inner {
       twolevel(H, (const T *)tb, 0, nullptr, nullptr, zb, st);
       xfin = zb;
     } else if (useM) {
-      gemv<T, T, T>(H, 1, (const T *)tb, 0, nullptr, zb, nullptr, nullptr, st);
+      gemv<T, T, T>(H, 1, (const T *)tb, 0, nullptr, zb, nullptr, nullptr, st, -1, h16(H));
       xfin = zb;
     }
     const double *cfin = nullptr;
     if (useP) {   // c' = G (Z^T b - Z^T S z): x = z + Z c'
-      gemv<T, T, T>(H, 0, xfin, 0, nullptr, yb, H->zlabel == 0 ? H->hs : nullptr, nullptr, st);
+      gemv<T, T, T>(H, 0, xfin, 0, nullptr, yb, H->zlabel == 0 ? H->hs : nullptr, nullptr, st, -1, h16(H));
       if (H->zlabel != 0)
         hipLaunchKernelGGL(k_zt<T>, dim3(H->n_h), dim3(kBlock), 0, st, H->d_sys, H->d_ins, H->w_h, (const T *)yb, 0,
                            (const double *)nullptr, (const GState *)nullptr, H->hs);
@@ -1013,7 +1068,7 @@ smpm_status validate_opts(const smpm_opts *o, smpm_handle *H) {
   H->precision = d.precision;
   H->method = d.method;
   H->inner_tol = d.inner_tol > 0 ? d.inner_tol : 1e-4;
-  H->max_sweeps = d.max_sweeps > 0 ? d.max_sweeps : 12;
+  H->max_sweeps = d.max_sweeps > 0 ? d.max_sweeps : (d.precision == SMPM_FP16S_IR ? 40 : 12);
   H->host_only = (d.flags & SMPM_FLAG_HOST_ONLY) != 0;
   H->no_tune = (d.flags & SMPM_FLAG_NO_TUNE) != 0;
   H->one_krylov = (d.flags & SMPM_FLAG_ONE_KRYLOV) != 0;
@@ -1023,7 +1078,9 @@ smpm_status validate_opts(const smpm_opts *o, smpm_handle *H) {
   if (d.tol < 0 || d.max_iter < 0 || d.nrhs < 0 || d.inner_tol < 0 || d.max_sweeps < 0)
     return fail(SMPM_EINVAL, "negative option value");
   if (H->maxit > 2000) return fail(SMPM_EINVAL, "max_iter above 2000");
-  if (H->precision != SMPM_FP64 && H->precision != SMPM_FP32_IR) return fail(SMPM_EINVAL, "unknown precision");
+  if (H->precision != SMPM_FP64 && H->precision != SMPM_FP32_IR && H->precision != SMPM_FP16S_IR)
+    return fail(SMPM_EINVAL, "unknown precision");
+  H->op16 = H->precision == SMPM_FP16S_IR;
   if (H->method < SMPM_METHOD_DBJ || H->method > SMPM_METHOD_2LAS)
     return fail(SMPM_EINVAL, "unknown method (DBJ, BJ, SCHUR, 2LAS)");
   return SMPM_OK;
@@ -1204,6 +1261,7 @@ smpm_status smpm_solve(smpm_handle *H, const double *f, const double *g, double 
       HIPCHECK(hipGraphLaunch(H->g_resid, st));   // final FP64 check of the Schur residual
       S.schur_matvecs += H->ninst * ((useP ? 1 : 0) + 1);
     } else {
+      double prev_worst = 1.0;
       for (;; ++sweeps) {
         if (sweeps > 0) {
           HIPCHECK(hipGraphLaunch(H->g_resid, st));
@@ -1211,13 +1269,19 @@ smpm_status smpm_solve(smpm_handle *H, const double *f, const double *g, double 
           HIPCHECK(hipMemcpyAsync(H->h_pairs, H->pairs, sizeof(double) * 2 * H->ninst, hipMemcpyDeviceToHost, st));
           HIPCHECK(hipStreamSynchronize(st));
           bool done = true;
+          double worst = 0.0;
           for (int i = 0; i < H->ninst; ++i) {
             const double nb = std::sqrt(H->h_nb[2 * i]);
             const double rel = nb > 0 ? std::sqrt(H->h_pairs[2 * i]) / nb : 0.0;
             if (!std::isfinite(rel)) nonfinite = true;
             if (rel > H->tol) done = false;
+            worst = std::max(worst, rel);
           }
           if (done || nonfinite) break;
+          // stagnation: a sweep that does not cut the worst residual by 10%
+          // will not reach the tolerance (the inner operator is too inexact)
+          if (worst > kStagnation * prev_worst) { notconv = true; break; }
+          prev_worst = worst;
         }
         if (sweeps >= H->max_sweeps) { notconv = true; break; }
         Inner<float>::run(H, sweeps, st);
@@ -1367,6 +1431,8 @@ smpm_status smpm_schur_apply_all(smpm_handle *H, const void *x, void *y, int32_t
     gemv<double, double, double>(H, 0, (const double *)x, 0, nullptr, (double *)y, nullptr, nullptr, st);
   else if (precision == SMPM_FP32_IR)
     gemv<float, float, float>(H, 0, (const float *)x, 0, nullptr, (float *)y, nullptr, nullptr, st);
+  else if (precision == SMPM_FP16S_IR && H->op16)
+    gemv<float, float, float>(H, 0, (const float *)x, 0, nullptr, (float *)y, nullptr, nullptr, st, -1, true);
   else
     return fail(SMPM_EINVAL, "unknown precision");
   if (hipGetLastError() != hipSuccess) return fail(SMPM_EHIP, "kernel launch failed");
@@ -1393,7 +1459,7 @@ smpm_status smpm_query(const smpm_handle *H, int32_t sysi, smpm_info *info) {
   o.bytes_M64 = (int64_t)s.nM * s.N * 4 * s.N * 8;   // distinct block-Jacobi row chunks, FP64
   for (int op = 0; op < 2; ++op)
     for (int pr = 0; pr < 2; ++pr)
-      o.gemm_sched[2 * op + pr] = (op == 0 ? H->n_gS : H->n_gM) > 0 ? H->sched[op][pr] : -1;
+      o.gemm_sched[2 * op + pr] = (op == 0 ? H->n_gS : H->n_gM) > 0 ? H->sched[op][pr == 1 && H->op16 ? 2 : pr] : -1;
   for (int k = 0; k < 3; ++k)
     for (int w = 0; w < 2; ++w) o.elem_sched[2 * k + w] = H->n_cg_all[k][w] > 0 ? H->cg_sched[k][w] : -1;
   *info = o;

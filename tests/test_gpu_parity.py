@@ -145,6 +145,26 @@ def test_2las_fp32_refinement():
     assert _rel(u, ref.u) <= 1e-8
 
 
+@pytest.mark.parametrize("stretch", [False, True])
+def test_fp16_scaled_refinement_reaches_fp64_solution(stretch):
+    # FP16 operator tables with per-element row-segment scales (shared blocks
+    # through the MFMA GEMM without stretch, distinct strips through the
+    # streaming kernel with it), FP32 inner GMRES, FP64 refinement.
+    p = workloads.random_problem(12, 3, 7, seed=6, stretch=stretch)
+    s, u, st = _gpu_solve(p, precision=P.FP16S_IR)
+    o, ref = _oracle(p, 0, 0, tol=1e-12)
+    print("fp16s stats", st)
+    assert st["rel_residual_max"] <= ACCEPT
+    assert st["sweeps_max"] >= 2
+    assert _rel(u, ref.u) <= 1e-8
+    # the FP16 matvec itself: within FP16 rounding of the FP64 product
+    x = np.random.default_rng(4).standard_normal(o.grid.k)
+    x32 = _dev(x).float()
+    y32 = torch.empty_like(x32)
+    s.schur_apply_all(x32, y32, P.FP16S_IR)
+    assert _rel(y32.double().cpu().numpy(), o.S @ x) <= 5e-3
+
+
 def test_fp32_refinement_reaches_fp64_solution():
     p = workloads.random_problem(12, 3, 7, seed=5, stretch=True)
     s, u, st = _gpu_solve(p, precision=P.FP32_IR)
