@@ -5,7 +5,8 @@
 
 namespace smpm {
 
-constexpr int kBlock = 256;         // threads per workgroup (4 wave64)
+constexpr int kBlock = 256;
+constexpr int kMaxNodes = 22;   // GLL points per direction (polynomial order <= 21)         // threads per workgroup (4 wave64)
 constexpr int kChunk = 512;         // interface/node elements per workgroup in vector kernels
 constexpr int kMaxN = 544;          // largest n * m_z supported (half-interface length)
 constexpr int kMaxRowsPerLane = (kMaxN + 63) / 64;

@@ -1061,14 +1061,18 @@ __global__ __launch_bounds__(kBlock) void k_lambda(const SysDev *__restrict__ sy
   for (int idx = threadIdx.x; idx < nq; idx += kBlock) {
     const int iface = idx / (2 * n), r = idx - iface * 2 * n;
     const int part = r / n, t = r - part * n;
-    double a = 0.0;
-    if (part == 0) {
-      const double *we = ws + (int64_t)iface * n2;
-      for (int c = 0; c < n; ++c) a += S.lo[(iface + 1) * n + c] * we[c * n + t];
-    } else {
-      const double *we = ws + (int64_t)(iface + 1) * n2;
-      for (int c = 0; c < n; ++c) a += S.up[iface * n + c] * we[c * n + t];
+    const double *coef = part == 0 ? S.lo + (iface + 1) * n : S.up + iface * n;
+    const double *we = ws + (int64_t)(part == 0 ? iface : iface + 1) * n2 + t;
+    // fully unrolled to the largest n so that every load is issued at once
+    double cv[kMaxNodes], wv[kMaxNodes];
+#pragma unroll
+    for (int c = 0; c < kMaxNodes; ++c) {
+      cv[c] = c < n ? coef[c] : 0.0;
+      wv[c] = c < n ? we[c * n] : 0.0;
     }
+    double a = 0.0;
+#pragma unroll
+    for (int c = 0; c < kMaxNodes; ++c) a += cv[c] * wv[c];
     lam[I.lam_off + (int64_t)j * nq + idx] = a;
   }
 }

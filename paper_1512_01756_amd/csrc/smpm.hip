@@ -1099,7 +1099,7 @@ smpm_status setup_common(const smpm_grid *grids, const double *k, int nsys, bool
     if (!g.xb || !g.zb) return fail(SMPM_EINVAL, "grid breakpoints NULL");
     if (g.mx < 2 || g.mz < 1 || g.order < 1) return fail(SMPM_EINVAL, "need mx >= 2, mz >= 1, order >= 1");
     if ((int64_t)(g.order + 1) * g.mz > kMaxN) return fail(SMPM_EINVAL, "n * m_z above the supported 544");
-    if (g.order + 1 > 22) return fail(SMPM_EINVAL, "order above 21 is not supported");
+    if (g.order + 1 > kMaxNodes) return fail(SMPM_EINVAL, "order above 21 is not supported");
     if (g.mx - 1 > 1024) return fail(SMPM_EINVAL, "more than 1025 strips");
     if ((int64_t)(g.mx - 1) * (H->zlabel ? g.mz : 1) > 4096)
       return fail(SMPM_EINVAL, "coarse space above 4096 unknowns");

@@ -2,6 +2,7 @@
 the same seeded inputs."""
 import numpy as np
 import pytest
+import scipy.sparse.linalg as spla
 
 import paper_1512_01756_amd as P
 from paper_1512_01756_amd import workloads
@@ -163,6 +164,36 @@ def test_fp16_scaled_refinement_reaches_fp64_solution(stretch):
     y32 = torch.empty_like(x32)
     s.schur_apply_all(x32, y32, P.FP16S_IR)
     assert _rel(y32.double().cpu().numpy(), o.S @ x) <= 5e-3
+
+
+@pytest.mark.parametrize("n,mz,mx,precision", [(17, 32, 6, P.FP64), (17, 32, 6, P.FP32_IR), (22, 24, 5, P.FP64)])
+def test_largest_supported_interface_half(n, mz, mx, precision):
+    # N = n m_z at the limit (544 = 17 x 32) and the largest order (n = 22):
+    # the widest operator blocks, the most row tiles per half, the longest K
+    # in every GEMM schedule, the largest element blocks.  Too large for the
+    # oracle's dense strip factorization, so the check is the defining
+    # property (k > 0): u = A^-1 (F - E x_S) makes L u - F = E (b_S - S x_S),
+    # so the residual of the oracle's sparse SMPM system L(k) u = F must be
+    # the Schur tolerance times |b_S|, with b_S = B A^-1 F from a sparse
+    # factorization of the strip-block-diagonal A(k).
+    xb = np.linspace(0.0, 0.6 * mx, mx + 1)
+    zb = np.concatenate([[0.0], np.cumsum(1.06 ** np.arange(mz))])
+    zb = zb / zb[-1]
+    k = 1.3
+    rng = np.random.default_rng(n + mz)
+    f = rng.uniform(0, 1, n * n * mx * mz)
+    p = workloads.Problem("max", xb, zb, n, np.array([k]), f[None, None, :])
+    s, u, st = _gpu_solve(p, precision=precision)
+    assert s.info[0]["n"] * s.info[0]["mz"] == n * mz
+    grid = smpm.Grid(xb, zb, n)
+    tau = smpm.default_tau(grid)
+    F = smpm.rhs(grid, tau, f)
+    L = smpm.assemble_L(grid, tau, k)
+    bS = smpm.assemble_B(grid, tau) @ spla.splu(smpm.assemble_A(grid, tau, k).tocsc()).solve(F)
+    res = np.linalg.norm(L @ u - F) / np.linalg.norm(bS)
+    print("max size", n, mz, st, "full residual / |b_S|", res)
+    assert st["rel_residual_max"] <= ACCEPT
+    assert res <= 1e-9
 
 
 def test_fp32_refinement_reaches_fp64_solution():
