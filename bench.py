@@ -290,6 +290,8 @@ def main():
                              "fp16s_ir": ir16["stats"]["rel_residual_max"]},
         "setup_s": {"fp64": fp64["setup_s"], "fp32_ir": ir["setup_s"], "fp16s_ir": ir16["setup_s"]},
         "gemm_schedules": {"matvec_S64_S32_M64_M32": i0["gemm_sched"], "element": i0["elem_sched"],
+                           "fused_S_Minv_fp64_fp32": [fp64["solver"].info[0]["fused_op"][0],
+                                                      ir["solver"].info[0]["fused_op"][1]],
                            "legend": "0 split-K 16 waves, 1 split-K 8 waves, 2 LDS-staged XCD-ordered, "
                                      "3 LDS-staged plain, -1 unused; picked by timing at setup"},
         "matvec_kernel": {"fp64_us": mv64_ms * 1e3, "fp32_us": mv32_ms * 1e3,

@@ -155,6 +155,10 @@ typedef struct {
                               XCD-ordered, 3 LDS-staged plain; -1 no shared blocks) */
   int32_t elem_sched[6];   /* same for the element-interior GEMM lists
                               (D^-1, K^-1, correction) x (<= 16, <= 64 columns) */
+  int32_t fused_op[3];     /* 1 if the GMRES iteration applies S M^-1 as one stored
+                              block per half (FP64, FP32, FP16 storage): chosen at
+                              setup when faster than M^-1 then S; grids whose strips
+                              share blocks only */
 } smpm_info;
 
 typedef struct smpm_handle smpm_handle;
@@ -229,7 +233,9 @@ typedef enum {
   SMPM_TABLE_U_S = 3,         /* k_S, left null vector of S (k = 0) */
   SMPM_TABLE_U_L = 4,         /* r, left null vector of L (k = 0) */
   SMPM_TABLE_U_C = 5,         /* d, left null vector of C (k = 0) */
-  SMPM_TABLE_SZ = 6           /* k_S x d row-major S Z */
+  SMPM_TABLE_SZ = 6,          /* k_S x d row-major S Z */
+  SMPM_TABLE_SMINV_DENSE = 7  /* k_S x k_S row-major S M^-1 from the fused blocks
+                                 (EUNSUPPORTED for grids without shared blocks) */
 } smpm_table;
 
 /* Copy a host-side operator table of system `sys` into host_out (count

@@ -23,7 +23,8 @@ FLAG_HOST_ONLY = 1
 FLAG_NO_TUNE = 2
 FLAG_ONE_KRYLOV = 4
 OP_SCHUR, OP_BJINV, OP_DEFLATE_P, OP_DEFLATE_Q, OP_AINV, OP_B, OP_SCHUR_RHS = range(7)
-TABLE_SCHUR_DENSE, TABLE_BJINV_DENSE, TABLE_COARSE_C, TABLE_U_S, TABLE_U_L, TABLE_U_C, TABLE_SZ = range(7)
+(TABLE_SCHUR_DENSE, TABLE_BJINV_DENSE, TABLE_COARSE_C, TABLE_U_S, TABLE_U_L, TABLE_U_C, TABLE_SZ,
+ TABLE_SMINV_DENSE) = range(8)
 
 STATUS_NAMES = {OK: "OK", EINVAL: "EINVAL", ENOMEM: "ENOMEM", EHIP: "EHIP", ESINGULAR: "ESINGULAR",
                 ENOTCONV: "ENOTCONV", ENONFINITE: "ENONFINITE", EUNSUPPORTED: "EUNSUPPORTED"}
@@ -63,7 +64,8 @@ class Info(ctypes.Structure):
                 ("tau", ctypes.c_double), ("f_offset", ctypes.c_int64), ("g_offset", ctypes.c_int64),
                 ("x_offset", ctypes.c_int64), ("unique_W", ctypes.c_int32), ("unique_M", ctypes.c_int32),
                 ("bytes_W64", ctypes.c_int64), ("bytes_M64", ctypes.c_int64),
-                ("gemm_sched", ctypes.c_int32 * 4), ("elem_sched", ctypes.c_int32 * 6)]
+                ("gemm_sched", ctypes.c_int32 * 4), ("elem_sched", ctypes.c_int32 * 6),
+                ("fused_op", ctypes.c_int32 * 3)]
 
     def as_dict(self):
         out = {}
@@ -232,7 +234,8 @@ class Solver:
     def export(self, table, sys=0):
         i = self.info[sys]
         sizes = {TABLE_SCHUR_DENSE: i["kS"] ** 2, TABLE_BJINV_DENSE: i["kS"] ** 2, TABLE_COARSE_C: i["d"] ** 2,
-                 TABLE_U_S: i["kS"], TABLE_U_L: i["r"], TABLE_U_C: i["d"], TABLE_SZ: i["kS"] * i["d"]}
+                 TABLE_U_S: i["kS"], TABLE_U_L: i["r"], TABLE_U_C: i["d"], TABLE_SZ: i["kS"] * i["d"],
+                 TABLE_SMINV_DENSE: i["kS"] ** 2}
         n = sizes[table]
         out = np.empty(n, dtype=np.float64)
         _check(self._lib.smpm_export(self.h, table, sys, out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), n))

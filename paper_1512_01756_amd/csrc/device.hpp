@@ -31,6 +31,12 @@ struct SysDev {
   // scales [blk][m_z].
   const _Float16 *W16, *M16;
   const float *W16s, *M16s;
+  // S M^-1 per half (grids whose strips share blocks): [blk][8N][Np] in each
+  // precision, FP16 scales [blk][m_z]
+  const double *F64;
+  const float *F32;
+  const _Float16 *F16;
+  const float *F16s;
   const int *m_id, *m_win, *m_K;
   const double *Gc;      // coarse operator, column-major d x d
   const double *uS, *uL; // null vectors (k = 0), else nullptr

@@ -74,6 +74,13 @@ struct System {
   std::vector<int> m_id, m_win, m_K;     // per half
   std::vector<double> Mblk;              // unique chunks, N x 4N row-major (zero padded)
   int nM = 0, nMblocks = 0;
+  // Fused operator S M^-1 for grids whose strips share blocks (built when
+  // some Schur block serves two halves): y_h = Fblk[f_id] x[f_win N .. + f_K),
+  // an N x f_K block (f_K <= 8N, zero padded to 8N) over the one or two
+  // block-Jacobi blocks that half h and its window touch.
+  std::vector<int> f_id, f_win, f_K;
+  std::vector<double> Fblk;              // unique blocks, N x 8N row-major
+  int nF = 0;
   // Deflation: S Z restricted per half to the coarse columns of the two
   // interfaces its window touches (2 zm columns).
   std::vector<int> sz_col;               // per half: [2 zm] coarse columns (-1 if none)

@@ -514,6 +514,60 @@ static void left_null_schur(System &s) {
   s.uS = u;
 }
 
+// S M^-1 per half (shared-block grids): F_h = E_h M^-1 + W_h [M^-1 rows of the
+// window halves w, w + 1], over the contiguous column range of the block-Jacobi
+// blocks of h, w and w + 1.  Identical (W, M, offsets) combinations share one
+// stored block.
+static void build_fused(System &s, const SetupOptions &opt) {
+  s.f_id.assign(s.nh, -1); s.f_win.assign(s.nh, 0); s.f_K.assign(s.nh, 0);
+  s.Fblk.clear(); s.nF = 0;
+  if (s.nW >= s.nh) return;   // no shared blocks: the two-step apply streams W and M
+  const int N = s.N, nh = s.nh, F8 = 8 * N;
+  std::map<std::vector<int>, int> fmap;
+  std::vector<int> first;
+  for (int h = 0; h < nh; ++h) {
+    const int w0 = s.w_win[h];
+    int blo = h / 4, bhi = h / 4;
+    for (int p = 0; p < 2; ++p) {
+      const int wh = w0 + p;
+      if (wh < 0 || wh >= nh) continue;
+      blo = std::min(blo, wh / 4); bhi = std::max(bhi, wh / 4);
+    }
+    const int start = 4 * blo, end = std::min(nh, 4 * (bhi + 1));
+    s.f_win[h] = start;
+    s.f_K[h] = (end - start) * N;
+    std::vector<int> key = {s.f_K[h], s.w_id[h], s.m_id[h], s.m_win[h] - start};
+    for (int p = 0; p < 2; ++p) {
+      const int wh = w0 + p;
+      if (wh < 0 || wh >= nh) { key.push_back(-1); key.push_back(0); continue; }
+      key.push_back(s.m_id[wh]); key.push_back(s.m_win[wh] - start);
+    }
+    auto it = fmap.find(key);
+    if (it == fmap.end()) { it = fmap.emplace(key, (int)first.size()).first; first.push_back(h); }
+    s.f_id[h] = it->second;
+  }
+  s.nF = (int)first.size();
+  s.Fblk.assign((size_t)s.nF * N * F8, 0.0);
+  parallel_for(s.nF, opt.threads, [&](int u) {
+    const int h = first[u], start = s.f_win[h];
+    double *F = &s.Fblk[(size_t)u * N * F8];
+    // E_h M^-1: the half's own row chunk of M^-1
+    const double *Mh = &s.Mblk[(size_t)s.m_id[h] * N * 4 * N];
+    const int oh = (s.m_win[h] - start) * N;
+    for (int i = 0; i < N; ++i)
+      for (int c = 0; c < s.m_K[h]; ++c) F[(size_t)i * F8 + oh + c] += Mh[(size_t)i * 4 * N + c];
+    // W_h [M^-1 rows of the window halves]
+    const double *W = &s.Wblk[(size_t)s.w_id[h] * N * 2 * N];
+    for (int p = 0; p < 2; ++p) {
+      const int wh = s.w_win[h] + p;
+      if (wh < 0 || wh >= s.nh) continue;
+      const double *Mw = &s.Mblk[(size_t)s.m_id[wh] * N * 4 * N];
+      const int ow = (s.m_win[wh] - start) * N;
+      gemm(N, s.m_K[wh], N, 1.0, W + p * N, 2 * N, Mw, 4 * N, 1.0, F + ow, F8);
+    }
+  });
+}
+
 void build_system(System &s, int mx, int mz, int order, const double *xb, const double *zb,
                   double kwave, const SetupOptions &opt) {
   if (mx < 2 || mz < 1 || order < 1) throw std::invalid_argument("need mx >= 2, mz >= 1, order >= 1");
@@ -675,6 +729,7 @@ void build_system(System &s, int mx, int mz, int order, const double *xb, const 
       s.m_K[h0 + q] = nhb * N;
     }
   }
+  build_fused(s, opt);
   // Deflation tables: S Z per half (two coarse columns), C = Z^T S Z.
   // Z column (interface a, segment e) is the indicator of rows e*seg .. (e+1)*seg-1
   // of both halves of interface a (seg = N / zm).  Half h's window is halves

@@ -131,17 +131,20 @@ struct smpm_handle {
   // Systems whose strips share blocks use the MFMA GEMM: items over windows
   // grouped by block id across all instances of a system (batched launches),
   // and within one instance (single-system applies).
-  GWork *g_S = nullptr, *g_M = nullptr, *g_Si = nullptr, *g_Mi = nullptr;
+  // Per operator: 0 S, 1 M^-1, 2 S M^-1 (fused, grids whose strips share blocks).
+  GWork *g_all[3] = {}, *g_one[3] = {};
   GVec *g_vec = nullptr;
-  int2 *u_S = nullptr, *u_M = nullptr;   // XCD-ordered (item, 64-row tile) lists of g_S, g_M
-  int n_uS = 0, n_uM = 0;
+  int2 *u_all[3] = {};   // XCD-ordered (item, 64-row tile) lists of g_all
+  int n_u_all[3] = {};
+  bool fused = false;    // every system has S M^-1 blocks
+  bool use_fused[3] = {}; // per precision: one S M^-1 GEMM per iteration beat M^-1 then S at setup
   // GEMM schedule of each batched list, picked at setup by timing every
   // candidate: [op][precision] for the matvec lists, [kind][width] for the
   // element-interior lists.
-  int sched[2][3] = {};   // [op][FP64, FP32, FP16 storage]
+  int sched[3][3] = {};   // [op][FP64, FP32, FP16 storage]
   int cg_sched[3][2] = {};
-  int n_gS = 0, n_gM = 0;
-  std::vector<int> gSi_start, gSi_cnt, gMi_start, gMi_cnt;
+  int n_g_all[3] = {};
+  std::vector<int> g_start[3], g_cnt[3];
   HWork *w_S1 = nullptr, *w_M1 = nullptr;   // single items (streamed blocks)
   int n_S1 = 0, n_M1 = 0;
   std::vector<int> S1_start, S1_cnt, M1_start, M1_cnt;
@@ -292,8 +295,16 @@ void upload(smpm_handle *H, hipStream_t st) {
     d.Np = (s.N + 7) / 8 * 8;   // 16-byte columns in FP64, FP32 and FP16
     d.W64 = dupload(own, to_colmajor_padded<double>(s.Wblk, s.nW, s.N, 2 * s.N, d.Np), st);
     d.W32 = dupload(own, to_colmajor_padded<float>(s.Wblk, s.nW, s.N, 2 * s.N, d.Np), st);
+    if (s.nF > 0) {
+      d.F64 = dupload(own, to_colmajor_padded<double>(s.Fblk, s.nF, s.N, 8 * s.N, d.Np), st);
+      d.F32 = dupload(own, to_colmajor_padded<float>(s.Fblk, s.nF, s.N, 8 * s.N, d.Np), st);
+    }
     if (H->op16) {
       std::vector<float> sc;
+      if (s.nF > 0) {
+        d.F16 = dupload(own, to_half_scaled(s.Fblk, s.nF, s.N, 8 * s.N, d.Np, s.n, sc), st);
+        d.F16s = dupload(own, sc, st);
+      }
       d.W16 = dupload(own, to_half_scaled(s.Wblk, s.nW, s.N, 2 * s.N, d.Np, s.n, sc), st);
       d.W16s = dupload(own, sc, st);
       d.M16 = dupload(own, to_half_scaled(s.Mblk, s.nM, s.N, 4 * s.N, d.Np, s.n, sc), st);
@@ -473,21 +484,24 @@ void upload(smpm_handle *H, hipStream_t st) {
   }
   // MFMA GEMM items for systems with shared blocks.
   {
-    std::vector<GWork> gS, gM, gSi, gMi;
+    std::vector<GWork> ga[3], go[3];
     std::vector<GVec> gv;
     // items of one stored block over its windows, kGemmVecs windows each
     auto emit = [&](int si, int op, int id, const std::vector<int2> &vecs, std::vector<GWork> &out) {
       const System &s = H->sys[si];
       const SysDev &d = H->h_sys[si];
       const int N = s.N, slots = (N + 15) / 16;
-      const int K = op == 0 ? 2 * N : s.m_K[vecs[0].y];
+      const int h0 = vecs[0].y;
+      const int K = op == 0 ? 2 * N : (op == 1 ? s.m_K[h0] : s.f_K[h0]);
+      const int cols = op == 0 ? 2 * N : (op == 1 ? 4 * N : 8 * N);
+      const size_t boff = (size_t)id * cols * d.Np;
       for (size_t a = 0; a < vecs.size();) {
         GWork w{};
-        w.blk64 = (op == 0 ? d.W64 : d.M64) + (size_t)id * (op == 0 ? 2 : 4) * N * d.Np;
-        w.blk32 = (op == 0 ? d.W32 : d.M32) + (size_t)id * (op == 0 ? 2 : 4) * N * d.Np;
+        w.blk64 = (op == 0 ? d.W64 : op == 1 ? d.M64 : d.F64) + boff;
+        w.blk32 = (op == 0 ? d.W32 : op == 1 ? d.M32 : d.F32) + boff;
         if (H->op16) {
-          w.blk16 = (op == 0 ? d.W16 : d.M16) + (size_t)id * (op == 0 ? 2 : 4) * N * d.Np;
-          w.sc16 = (op == 0 ? d.W16s : d.M16s) + (size_t)id * s.mz;
+          w.blk16 = (op == 0 ? d.W16 : op == 1 ? d.M16 : d.F16) + boff;
+          w.sc16 = (op == 0 ? d.W16s : op == 1 ? d.M16s : d.F16s) + (size_t)id * s.mz;
         }
         w.n = s.n;
         w.N = N; w.Np = d.Np; w.K = K; w.kS = s.kS; w.ident = op == 0 ? 1 : 0;
@@ -498,7 +512,7 @@ void upload(smpm_handle *H, hipStream_t st) {
           const InstDev &I = H->h_ins[inst];
           GVec e{};
           e.x0 = I.x_off; e.xv = I.v_off;
-          e.win = (int64_t)(op == 0 ? s.w_win[h] : s.m_win[h]) * N;
+          e.win = (int64_t)(op == 0 ? s.w_win[h] : op == 1 ? s.m_win[h] : s.f_win[h]) * N;
           e.xh = (int64_t)h * N;
           e.y = I.x_off + (int64_t)h * N;
           e.inst = inst;
@@ -510,12 +524,13 @@ void upload(smpm_handle *H, hipStream_t st) {
         a += w.vcount;
       }
     };
-
+    H->fused = true;
     for (int si = 0; si < (int)H->sys.size(); ++si) {
       const System &s = H->sys[si];
-      for (int op = 0; op < 2; ++op) {
-        const std::vector<int> &ids = op == 0 ? s.w_id : s.m_id;
-        if (!shares_blocks(ids)) continue;
+      if (s.nF == 0) H->fused = false;
+      for (int op = 0; op < 3; ++op) {
+        const std::vector<int> &ids = op == 0 ? s.w_id : op == 1 ? s.m_id : s.f_id;
+        if (op < 2 ? !shares_blocks(ids) : s.nF == 0) continue;
         std::map<int, std::vector<int2>> all;
         std::vector<std::map<int, std::vector<int2>>> per(H->nrhs);
         for (int q = 0; q < H->nrhs; ++q)
@@ -524,37 +539,31 @@ void upload(smpm_handle *H, hipStream_t st) {
             all[ids[h]].push_back(e);
             per[q][ids[h]].push_back(e);
           }
-        for (auto &kv : all) emit(si, op, kv.first, kv.second, op == 0 ? gS : gM);
+        for (auto &kv : all) emit(si, op, kv.first, kv.second, ga[op]);
         for (int q = 0; q < H->nrhs; ++q) {
-          std::vector<int> &st_v = op == 0 ? H->gSi_start : H->gMi_start;
-          std::vector<int> &ct_v = op == 0 ? H->gSi_cnt : H->gMi_cnt;
-          std::vector<GWork> &dst = op == 0 ? gSi : gMi;
           const int inst = si * H->nrhs + q;
+          std::vector<int> &st_v = H->g_start[op], &ct_v = H->g_cnt[op];
           if ((int)st_v.size() <= inst) { st_v.resize(inst + 1, 0); ct_v.resize(inst + 1, 0); }
-          st_v[inst] = (int)dst.size();
-          for (auto &kv : per[q]) emit(si, op, kv.first, kv.second, dst);
-          ct_v[inst] = (int)dst.size() - st_v[inst];
+          st_v[inst] = (int)go[op].size();
+          for (auto &kv : per[q]) emit(si, op, kv.first, kv.second, go[op]);
+          ct_v[inst] = (int)go[op].size() - st_v[inst];
         }
       }
     }
-    H->gSi_start.resize(H->ninst, 0); H->gSi_cnt.resize(H->ninst, 0);
-    H->gMi_start.resize(H->ninst, 0); H->gMi_cnt.resize(H->ninst, 0);
-    H->g_S = dupload(own, gS, st); H->n_gS = (int)gS.size();
-    H->g_M = dupload(own, gM, st); H->n_gM = (int)gM.size();
-    for (int op = 0; op < 2; ++op) {
-      const std::vector<GWork> &g = op == 0 ? gS : gM;
+    for (int op = 0; op < 3; ++op) {
+      H->g_start[op].resize(H->ninst, 0); H->g_cnt[op].resize(H->ninst, 0);
+      H->g_all[op] = dupload(own, ga[op], st); H->n_g_all[op] = (int)ga[op].size();
+      H->g_one[op] = dupload(own, go[op], st);
       std::vector<uintptr_t> key;
       std::vector<int> tiles;
-      for (const GWork &w : g) {
+      for (const GWork &w : ga[op]) {
         key.push_back((uintptr_t)w.blk64);
         tiles.push_back((w.Np + 63) / 64);
       }
       std::vector<int2> u = xcd_units(key, tiles);
-      (op == 0 ? H->u_S : H->u_M) = dupload(own, u, st);
-      (op == 0 ? H->n_uS : H->n_uM) = (int)u.size();
+      H->u_all[op] = dupload(own, u, st);
+      H->n_u_all[op] = (int)u.size();
     }
-    H->g_Si = dupload(own, gSi, st);
-    H->g_Mi = dupload(own, gMi, st);
     H->g_vec = dupload(own, gv, st);
   }
   H->d_ins = dupload(own, H->h_ins, st);
@@ -641,21 +650,21 @@ void gemv_ts(smpm_handle *H, int op, const TX *x, int vslot, const double *scale
   const int Kmax = (op == 0 ? 2 : 4) * H->Nmax;
   // halves with a shared block: MFMA GEMM over the windows that share it
   {
-    const GWork *w = op == 0 ? H->g_S : H->g_M;
-    int count = op == 0 ? H->n_gS : H->n_gM;
+    const GWork *w = H->g_all[op];
+    int count = H->n_g_all[op];
     if (inst >= 0) {
-      w = (op == 0 ? H->g_Si : H->g_Mi) + (op == 0 ? H->gSi_start[inst] : H->gMi_start[inst]);
-      count = op == 0 ? H->gSi_cnt[inst] : H->gMi_cnt[inst];
+      w = H->g_one[op] + H->g_start[op][inst];
+      count = H->g_cnt[op][inst];
     }
     if (count > 0) {
       const int prec = sizeof(TS) == 8 ? 0 : (sizeof(TS) == 4 ? 1 : 2);
       const int sched = inst < 0 ? H->sched[op][prec] : gemm_default(count, (H->Nmax + 15) / 16);
-      gemm_launch<TS, TO, TX, TY>(H, sched, w, count, inst < 0 ? (op == 0 ? H->u_S : H->u_M) : nullptr,
-                                  op == 0 ? H->n_uS : H->n_uM, x, vslot, scale, y, hsum, gs, st);
+      gemm_launch<TS, TO, TX, TY>(H, sched, w, count, inst < 0 ? H->u_all[op] : nullptr, H->n_u_all[op], x, vslot,
+                                  scale, y, hsum, gs, st);
     }
   }
-  // halves with their own block: streaming kernel
-  {
+  // halves with their own block: streaming kernel (S or M^-1 only)
+  if (op < 2) {
     const HWork *w = op == 0 ? H->w_S1 : H->w_M1;
     int count = op == 0 ? H->n_S1 : H->n_M1;
     if (inst >= 0) {
@@ -750,10 +759,11 @@ float time_launch(hipStream_t st, hipEvent_t e0, hipEvent_t e1, F &&fn) {
 
 void tune(smpm_handle *H, hipStream_t st) {
   const int rt16 = (H->Nmax + 15) / 16;
-  for (int op = 0; op < 2; ++op)
-    for (int pr = 0; pr < 3; ++pr) H->sched[op][pr] = gemm_default(op == 0 ? H->n_gS : H->n_gM, rt16);
+  for (int op = 0; op < 3; ++op)
+    for (int pr = 0; pr < 3; ++pr) H->sched[op][pr] = gemm_default(H->n_g_all[op], rt16);
   for (int k = 0; k < 3; ++k)
     for (int w = 0; w < 2; ++w) H->cg_sched[k][w] = -1;
+  for (int pr = 0; pr < 3; ++pr) H->use_fused[pr] = H->fused && (int64_t)H->n_g_all[2] * rt16 < 2048;
   if (H->no_tune) return;
   const int rmax = std::max(H->n2_max, H->nq_max);
   for (int k = 0; k < 3; ++k)
@@ -773,12 +783,12 @@ void tune(smpm_handle *H, hipStream_t st) {
       HIPCHECK(hipMemsetAsync(H->lam, 0, sizeof(double) * nl, st));
       HIPCHECK(hipMemsetAsync(H->qb, 0, sizeof(double) * nl, st));
     }
-    for (int op = 0; op < 2; ++op) {
-      const int count = op == 0 ? H->n_gS : H->n_gM;
+    for (int op = 0; op < 3; ++op) {
+      const int count = H->n_g_all[op];
       if (count == 0) continue;
-      const GWork *w = op == 0 ? H->g_S : H->g_M;
-      const int2 *u = op == 0 ? H->u_S : H->u_M;
-      const int nu = op == 0 ? H->n_uS : H->n_uM;
+      const GWork *w = H->g_all[op];
+      const int2 *u = H->u_all[op];
+      const int nu = H->n_u_all[op];
       for (int pr = 0; pr < (H->op16 ? 3 : 2); ++pr) {
         float best = 1e30f;
         for (int sc = 0; sc < kNumSched; ++sc) {
@@ -799,6 +809,25 @@ void tune(smpm_handle *H, hipStream_t st) {
         }
       }
     }
+    // one fused S M^-1 GEMM per iteration, or M^-1 then S: whichever is faster
+    if (H->fused)
+      for (int pr = 0; pr < (H->op16 ? 3 : 2); ++pr) {
+        // full operator applications (shared-block GEMMs and streamed blocks)
+        auto two = [&](int op, const void *x, void *y) {
+          if (pr == 0)
+            gemv<double, double, double>(H, op, (const double *)x, 0, nullptr, (double *)y, op != 1 ? H->hs : nullptr,
+                                         nullptr, st);
+          else
+            gemv<float, float, float>(H, op, (const float *)x, 0, nullptr, (float *)y, op != 1 ? H->hs : nullptr,
+                                      nullptr, st, -1, pr == 2);
+        };
+        const void *x = pr == 0 ? (const void *)H->t64 : (const void *)H->t32;
+        void *z = pr == 0 ? (void *)H->z64 : (void *)H->z32;
+        void *y = pr == 0 ? (void *)H->y64 : (void *)H->y32;
+        const float tf = time_launch(st, e0, e1, [&] { two(2, x, y); });
+        const float t2 = time_launch(st, e0, e1, [&] { two(1, x, z); two(0, z, y); });
+        H->use_fused[pr] = tf < t2;
+      }
     const int cand[3] = {kSplit8, kThrXcd, kThrPlain};
     for (int k = 0; k < 3; ++k)
       for (int w = 0; w < 2; ++w) {
@@ -925,6 +954,8 @@ struct Inner {
     if (H->method == SMPM_METHOD_2LAS) {
       twolevel(H, (const T *)Vb, 1, H->scale, H->gs, zb, st);
       gemv<T, T, T>(H, 0, (const T *)zb, 0, nullptr, yb, nullptr, H->gs, st, -1, h16(H));
+    } else if (useM && H->use_fused[sizeof(T) == 8 ? 0 : (h16(H) ? 2 : 1)]) {   // y = (S M^-1) v in one GEMM
+      gemv<T, T, T>(H, 2, (const T *)Vb, 1, H->scale, yb, hsum, H->gs, st, -1, h16(H));
     } else if (useM) {
       gemv<T, T, T>(H, 1, (const T *)Vb, 1, H->scale, zb, nullptr, H->gs, st, -1, h16(H));
       gemv<T, T, T>(H, 0, (const T *)zb, 0, nullptr, yb, hsum, H->gs, st, -1, h16(H));
@@ -1459,9 +1490,10 @@ smpm_status smpm_query(const smpm_handle *H, int32_t sysi, smpm_info *info) {
   o.bytes_M64 = (int64_t)s.nM * s.N * 4 * s.N * 8;   // distinct block-Jacobi row chunks, FP64
   for (int op = 0; op < 2; ++op)
     for (int pr = 0; pr < 2; ++pr)
-      o.gemm_sched[2 * op + pr] = (op == 0 ? H->n_gS : H->n_gM) > 0 ? H->sched[op][pr == 1 && H->op16 ? 2 : pr] : -1;
+      o.gemm_sched[2 * op + pr] = H->n_g_all[op] > 0 ? H->sched[op][pr == 1 && H->op16 ? 2 : pr] : -1;
   for (int k = 0; k < 3; ++k)
     for (int w = 0; w < 2; ++w) o.elem_sched[2 * k + w] = H->n_cg_all[k][w] > 0 ? H->cg_sched[k][w] : -1;
+  for (int pr = 0; pr < 3; ++pr) o.fused_op[pr] = H->use_fused[pr] ? 1 : 0;
   *info = o;
   return SMPM_OK;
 }
@@ -1497,6 +1529,18 @@ smpm_status smpm_export(const smpm_handle *H, smpm_table what, int32_t sysi, dou
             const int64_t col = (int64_t)s.m_win[h] * s.N + c;
             out[row * s.kS + col] = s.Mblk[(size_t)s.m_id[h] * s.N * 4 * s.N + (size_t)i * 4 * s.N + c];
           }
+        }
+      return SMPM_OK;
+    }
+    case SMPM_TABLE_SMINV_DENSE: {
+      if (s.nF == 0) return fail(SMPM_EUNSUPPORTED, "no fused S M^-1 blocks (strips do not share blocks)");
+      if (!need(s.kS * s.kS)) return fail(SMPM_EINVAL, "count must be k_S^2");
+      std::fill(out, out + count, 0.0);
+      for (int h = 0; h < s.nh; ++h)
+        for (int i = 0; i < s.N; ++i) {
+          const int64_t row = (int64_t)h * s.N + i;
+          for (int c = 0; c < s.f_K[h]; ++c)
+            out[row * s.kS + (int64_t)s.f_win[h] * s.N + c] = s.Fblk[((size_t)s.f_id[h] * s.N + i) * 8 * s.N + c];
         }
       return SMPM_OK;
     }

@@ -75,6 +75,27 @@ def test_host_setup_matches_oracle(lib, xb, zb, n, k, zlabel):
     s.close()
 
 
+@pytest.mark.parametrize("k", [0.0, 1.7])
+def test_fused_schur_times_bj_inverse_matches_oracle(lib, k):
+    # uniform strips share blocks, so the setup also stores S M^-1 per half
+    xb, zb, n = np.linspace(0, 6, 13), np.linspace(0, 1, 3), 5
+    s = P.Solver(xb, zb, n - 1, kwaves=[k], host_only=True)
+    o = schur.build(smpm.Grid(xb, zb, n), kwave=k)
+    kS = o.grid.k
+    Mo = np.zeros((kS, kS))
+    for idx, Mb in zip(o.bj_index, o.bj_inv):
+        Mo[np.ix_(idx, idx)] = Mb
+    ref = o.S.toarray() @ Mo
+    F = s.export(P.TABLE_SMINV_DENSE).reshape(kS, kS)
+    assert np.abs(F - ref).max() <= 1e-11 * np.abs(ref).max()
+    s.close()
+    # distinct strips: no fused blocks
+    s2 = P.Solver(np.array([0, 0.4, 0.9, 1.2, 1.9, 2.3, 2.8]), zb, n - 1, host_only=True)
+    with pytest.raises(P.SmpmError):
+        s2.export(P.TABLE_SMINV_DENSE)
+    s2.close()
+
+
 def test_uniform_strips_are_deduplicated(lib):
     s = P.Solver(np.linspace(0, 32, 65), np.linspace(0, 1, 5), 6, host_only=True)
     # first strip, interior strips, last strip -> at most 4 distinct half blocks
