@@ -193,6 +193,18 @@ smpm_status smpm_setup_fourier(const smpm_grid *grid, int32_t my, double ly, con
 smpm_status smpm_solve_fourier(smpm_handle *h, const double *f_dev, const double *g_dev, double *u_dev,
                                void *hip_stream, smpm_stats *stats);
 
+/* Save every host table of a handle (its systems' operators, factors, coarse
+ * operators and null vectors) to `path`, so that smpm_load can rebuild the
+ * handle without the setup.  Works on host-only handles too.  EINVAL when
+ * the file cannot be written. */
+smpm_status smpm_save(const smpm_handle *h, const char *path);
+
+/* Rebuild a handle from a file written by smpm_save: upload, schedule tuning
+ * and the Fourier tables as in setup, no factorization.  opts NULL takes the
+ * defaults with the saved deflation space; opts->zlabel must match the saved
+ * one.  EINVAL for a missing, foreign or truncated file. */
+smpm_status smpm_load(const char *path, const smpm_opts *opts, void *hip_stream, smpm_handle **out);
+
 /* Algorithm 2 for every instance: f_dev (FP64, batched node layout), g_dev
  * (FP64, batched side layout, or NULL for g = 0) -> u_dev (FP64, batched node
  * layout, zero nodal mean for k = 0).  stats (host, nullable) is filled after

@@ -75,7 +75,8 @@ class Info(ctypes.Structure):
         return out
 
 
-EXPORTED = ["smpm_setup", "smpm_setup_batch", "smpm_setup_fourier", "smpm_solve", "smpm_solve_fourier",
+EXPORTED = ["smpm_setup", "smpm_setup_batch", "smpm_setup_fourier", "smpm_save", "smpm_load", "smpm_solve",
+            "smpm_solve_fourier",
             "smpm_apply", "smpm_schur_apply_all", "smpm_query", "smpm_num_systems", "smpm_export", "smpm_destroy",
             "smpm_last_error"]
 
@@ -98,6 +99,8 @@ def load():
     lib.smpm_setup_batch.argtypes = lib.smpm_setup.argtypes
     lib.smpm_setup_fourier.argtypes = [ctypes.POINTER(Grid), ctypes.c_int32, ctypes.c_double, ctypes.POINTER(Opts),
                                        P, ctypes.POINTER(P)]
+    lib.smpm_save.argtypes = [P, ctypes.c_char_p]
+    lib.smpm_load.argtypes = [ctypes.c_char_p, ctypes.POINTER(Opts), P, ctypes.POINTER(P)]
     lib.smpm_solve.argtypes = [P, P, P, P, P, ctypes.POINTER(Stats)]
     lib.smpm_solve_fourier.argtypes = lib.smpm_solve.argtypes
     lib.smpm_apply.argtypes = [P, ctypes.c_int32, ctypes.c_int32, P, P, ctypes.c_int32, P]
@@ -109,7 +112,8 @@ def load():
     lib.smpm_destroy.argtypes = [P]
     lib.smpm_destroy.restype = None
     lib.smpm_last_error.restype = ctypes.c_char_p
-    for name in ("smpm_setup", "smpm_setup_batch", "smpm_setup_fourier", "smpm_solve", "smpm_solve_fourier",
+    for name in ("smpm_setup", "smpm_setup_batch", "smpm_setup_fourier", "smpm_save", "smpm_load", "smpm_solve",
+                 "smpm_solve_fourier",
                  "smpm_apply", "smpm_schur_apply_all", "smpm_query", "smpm_export"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
@@ -140,7 +144,8 @@ class Solver:
 
     def __init__(self, xb=None, zb=None, order=None, kwaves=(0.0,), grids=None, tau=0.0, tol=1e-10,
                  max_iter=300, nrhs=1, precision=FP64, method=METHOD_DBJ, inner_tol=0.0, max_sweeps=0,
-                 host_only=False, tune=True, fourier=None, one_krylov=False, zlabel=0, stream=None):
+                 host_only=False, tune=True, fourier=None, one_krylov=False, zlabel=0, load_path=None,
+                 stream=None):
         if fourier is not None:
             nrhs = 2
         lib = load()
@@ -154,7 +159,11 @@ class Solver:
         h = ctypes.c_void_p()
         st = ctypes.c_void_p(0) if host_only else _stream(stream)
         self.fourier = fourier
-        if fourier is not None:
+        if load_path is not None:
+            if nrhs == 1:
+                opts.nrhs = 0          # the library default (2 for a saved Fourier handle)
+            _check(lib.smpm_load(os.fsencode(load_path), ctypes.byref(opts), st, ctypes.byref(h)))
+        elif fourier is not None:
             g = self._grid(xb, zb, order)
             _check(lib.smpm_setup_fourier(ctypes.byref(g), int(fourier[0]), float(fourier[1]), ctypes.byref(opts),
                                           st, ctypes.byref(h)))
@@ -173,7 +182,7 @@ class Solver:
         self.h = h
         self.nsys = lib.smpm_num_systems(h)
         self.info = [self.query(s) for s in range(self.nsys)]
-        self.nrhs = max(nrhs, 1)
+        self.nrhs = self.info[0]["nrhs"]
 
     def _grid(self, xb, zb, order):
         xb = np.ascontiguousarray(np.asarray(xb, dtype=np.float64))
@@ -210,6 +219,11 @@ class Solver:
         if check:
             _check(status)
         return u, stats.as_dict(), status
+
+    def save(self, path):
+        """Write the handle's host tables (smpm_save); Solver(load_path=path)
+        rebuilds an equal handle without the setup."""
+        _check(self._lib.smpm_save(self.h, os.fsencode(path)))
 
     def solve_fourier(self, f, g=None, u=None, stream=None, check=True):
         """Physical-space 3-D solve: f, u torch float64 CUDA tensors [m_y, r];

@@ -11,7 +11,7 @@ ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libsmpm_schur.so")
 BUILD = os.path.join(HERE, "_build")
 
-HOST_SOURCES = ["dense.cpp", "setup_host.cpp"]
+HOST_SOURCES = ["dense.cpp", "setup_host.cpp", "persist.cpp"]
 DEVICE_SOURCES = ["smpm.hip"]
 ARCH = os.environ.get("SMPM_OFFLOAD_ARCH", "gfx950")
 

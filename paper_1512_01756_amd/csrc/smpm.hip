@@ -17,6 +17,7 @@
 #include "../../include/smpm_schur.h"
 #include "device.hpp"
 #include "host.hpp"
+#include "persist.hpp"
 #include "kernels.hip"
 
 using namespace smpm;
@@ -1089,6 +1090,31 @@ void finish_u(smpm_handle *H, double *u, hipStream_t st) {
   hipLaunchKernelGGL(k_sub_mean, dim3(H->n_r), dim3(kBlock), 0, st, H->d_sys, H->d_ins, H->w_r, u, (const double *)H->pr);
 }
 
+// Real DFT matrices and coefficient buffers of a Fourier handle:
+// forward  f_m = (1/m_y) sum_j f_j (cos - i sin)(2 pi m j / m_y);
+// inverse  u_j = sum_m w_m (Re u_m cos - Im u_m sin)(2 pi m j / m_y),
+//          w_0 = 1, w_{m_y/2} = 1 for even m_y, else 2.
+void fourier_tables(smpm_handle *H, hipStream_t s0) {
+  const int my = H->my, nk = my / 2 + 1;
+  std::vector<double> F((size_t)2 * nk * my), I((size_t)my * 2 * nk);
+  for (int m = 0; m < nk; ++m) {
+    const double w = (m == 0 || (my % 2 == 0 && m == my / 2)) ? 1.0 : 2.0;
+    for (int j = 0; j < my; ++j) {
+      const double th = 2.0 * M_PI * (double)(((int64_t)m * j) % my) / my;
+      F[(size_t)(2 * m) * my + j] = std::cos(th) / my;
+      F[(size_t)(2 * m + 1) * my + j] = -std::sin(th) / my;
+      I[(size_t)j * 2 * nk + 2 * m] = w * std::cos(th);
+      I[(size_t)j * 2 * nk + 2 * m + 1] = -w * std::sin(th);
+    }
+  }
+  H->dft_f = dupload(H->owned, F, s0);
+  H->dft_i = dupload(H->owned, I, s0);
+  H->fhat = dalloc<double>(H->owned, H->tot_r);
+  H->uhat = dalloc<double>(H->owned, H->tot_r);
+  H->ghat = dalloc<double>(H->owned, H->tot_g);
+  HIPCHECK(hipStreamSynchronize(s0));
+}
+
 smpm_status validate_opts(const smpm_opts *o, smpm_handle *H) {
   smpm_opts d{};
   if (o) d = *o;
@@ -1206,33 +1232,68 @@ smpm_status smpm_setup_fourier(const smpm_grid *grid, int32_t my, double ly, con
   H->ly = ly;
   if (!H->host_only) {
     try {
-      // forward: f_m = (1/m_y) sum_j f_j (cos - i sin)(2 pi m j / m_y)
-      // inverse: u_j = sum_m w_m (Re u_m cos - Im u_m sin)(2 pi m j / m_y),
-      //          w_0 = 1, w_{m_y/2} = 1 for even m_y, else 2
-      std::vector<double> F((size_t)2 * nk * my), I((size_t)my * 2 * nk);
-      for (int m = 0; m < nk; ++m) {
-        const double w = (m == 0 || (my % 2 == 0 && m == my / 2)) ? 1.0 : 2.0;
-        for (int j = 0; j < my; ++j) {
-          const double th = 2.0 * M_PI * (double)(((int64_t)m * j) % my) / my;
-          F[(size_t)(2 * m) * my + j] = std::cos(th) / my;
-          F[(size_t)(2 * m + 1) * my + j] = -std::sin(th) / my;
-          I[(size_t)j * 2 * nk + 2 * m] = w * std::cos(th);
-          I[(size_t)j * 2 * nk + 2 * m + 1] = -w * std::sin(th);
-        }
-      }
-      hipStream_t s0 = (hipStream_t)hip_stream;
-      H->dft_f = dupload(H->owned, F, s0);
-      H->dft_i = dupload(H->owned, I, s0);
-      H->fhat = dalloc<double>(H->owned, H->tot_r);
-      H->uhat = dalloc<double>(H->owned, H->tot_r);
-      H->ghat = dalloc<double>(H->owned, H->tot_g);
-      HIPCHECK(hipStreamSynchronize(s0));
+      fourier_tables(H, (hipStream_t)hip_stream);
     } catch (const std::exception &e) {
       delete H;
       return fail(SMPM_ENOMEM, e.what());
     }
   }
   *out = H;
+  return SMPM_OK;
+}
+
+smpm_status smpm_save(const smpm_handle *H, const char *path) {
+  if (!H || !path) return fail(SMPM_EINVAL, "handle or path is NULL");
+  try {
+    TableHeader h;
+    h.zlabel = H->zlabel;
+    h.my = H->my;
+    h.ly = H->ly;
+    save_tables(path, h, H->sys);
+  } catch (const std::exception &e) {
+    return fail(SMPM_EINVAL, e.what());
+  }
+  return SMPM_OK;
+}
+
+smpm_status smpm_load(const char *path, const smpm_opts *opts, void *hip_stream, smpm_handle **out) {
+  if (!out || !path) return fail(SMPM_EINVAL, "out or path is NULL");
+  *out = nullptr;
+  TableHeader h;
+  std::vector<System> sys;
+  try {
+    load_tables(path, h, sys);
+  } catch (const std::bad_alloc &) {
+    return fail(SMPM_ENOMEM, "host allocation failed while loading tables");
+  } catch (const std::exception &e) {
+    return fail(SMPM_EINVAL, e.what());
+  }
+  smpm_opts o{};
+  if (opts) o = *opts;
+  else o.zlabel = h.zlabel;
+  if (o.zlabel != h.zlabel) return fail(SMPM_EINVAL, "zlabel differs from the one the tables were built for");
+  if (h.my > 0) {
+    if (o.nrhs != 0 && o.nrhs != 2) return fail(SMPM_EINVAL, "a Fourier handle has nrhs = 2 (Re, Im)");
+    o.nrhs = 2;
+  }
+  std::unique_ptr<smpm_handle> H(new smpm_handle());
+  smpm_status st = validate_opts(&o, H.get());
+  if (st != SMPM_OK) return st;
+  H->sys = std::move(sys);
+  H->my = h.my;
+  H->ly = h.ly;
+  if (!H->host_only) {
+    try {
+      upload(H.get(), (hipStream_t)hip_stream);
+      tune(H.get(), (hipStream_t)hip_stream);
+      if (H->my > 0) fourier_tables(H.get(), (hipStream_t)hip_stream);
+    } catch (const std::bad_alloc &) {
+      return fail(SMPM_ENOMEM, "device allocation failed while loading tables");
+    } catch (const std::exception &e) {
+      return fail(SMPM_EHIP, e.what());
+    }
+  }
+  *out = H.release();
   return SMPM_OK;
 }
 

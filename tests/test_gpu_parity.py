@@ -278,3 +278,32 @@ def test_notconv_and_nonfinite_statuses():
     fbad[3] = float("nan")
     u, st, status = s2.solve(fbad, check=False)
     assert status == P.ENONFINITE
+
+
+def test_loaded_handle_solves_bitwise_like_the_saved_one(tmp_path):
+    p = workloads.random_problem(9, 3, 6, seed=31, stretch=True, with_g=True)
+    s = P.Solver(p.xb, p.zb, p.n - 1, tune=False)
+    path = str(tmp_path / "tables.bin")
+    s.save(path)
+    t = P.Solver(load_path=path, tune=False)
+    f = _dev(p.f.reshape(-1))
+    g = _dev(P.pack_g(p.g, s.info, 1))
+    u1, st1, _ = s.solve(f, g)
+    u2, st2, _ = t.solve(f, g)
+    torch.cuda.synchronize()
+    assert torch.equal(u1, u2)
+    assert st1["iters_max"] == st2["iters_max"]
+
+
+def test_loaded_fourier_handle(tmp_path):
+    xb, zb, n, my, ly = np.linspace(0, 3, 6), np.array([0.0, 0.4, 1.0]), 5, 6, 2.0
+    s = P.Solver(xb, zb, n - 1, fourier=(my, ly), tune=False)
+    path = str(tmp_path / "fourier.bin")
+    s.save(path)
+    t = P.Solver(load_path=path, tune=False)
+    assert t.nsys == my // 2 + 1 and t.nrhs == 2
+    f = _dev(np.random.default_rng(2).uniform(0, 1, (my, s.info[0]["r"])))
+    u1, _, _ = s.solve_fourier(f)
+    u2, _, _ = t.solve_fourier(f)
+    torch.cuda.synchronize()
+    assert torch.equal(u1, u2)

@@ -96,6 +96,34 @@ def test_fused_schur_times_bj_inverse_matches_oracle(lib, k):
     s2.close()
 
 
+@pytest.mark.parametrize("zlabel,k", [(0, 0.0), (1, 1.7)])
+def test_saved_tables_load_back_identically(lib, tmp_path, zlabel, k):
+    xb = np.array([0, 0.4, 0.9, 1.2, 1.9, 2.3, 2.8])
+    zb = np.array([0, 0.15, 0.45, 1.0])
+    s = P.Solver(xb, zb, 4, kwaves=[k, 2 * k + 0.5], host_only=True, zlabel=zlabel)
+    path = str(tmp_path / "tables.bin")
+    s.save(path)
+    t = P.Solver(load_path=path, host_only=True, zlabel=zlabel)
+    assert t.nsys == 2 and t.info == s.info
+    for sys in range(2):
+        tables = [P.TABLE_SCHUR_DENSE, P.TABLE_BJINV_DENSE, P.TABLE_COARSE_C, P.TABLE_SZ]
+        if s.info[sys]["kwave"] == 0.0:
+            tables += [P.TABLE_U_S, P.TABLE_U_L, P.TABLE_U_C]
+        for table in tables:
+            assert np.array_equal(s.export(table, sys), t.export(table, sys)), table
+    # a different deflation space, a foreign file and a truncated file are rejected
+    with pytest.raises(P.SmpmError):
+        P.Solver(load_path=path, host_only=True, zlabel=1 - zlabel)
+    bad = tmp_path / "bad.bin"
+    bad.write_bytes(b"not a table file")
+    with pytest.raises(P.SmpmError):
+        P.Solver(load_path=str(bad), host_only=True)
+    data = open(path, "rb").read()
+    (tmp_path / "short.bin").write_bytes(data[: len(data) // 2])
+    with pytest.raises(P.SmpmError):
+        P.Solver(load_path=str(tmp_path / "short.bin"), host_only=True, zlabel=zlabel)
+
+
 def test_uniform_strips_are_deduplicated(lib):
     s = P.Solver(np.linspace(0, 32, 65), np.linspace(0, 1, 5), 6, host_only=True)
     # first strip, interior strips, last strip -> at most 4 distinct half blocks
