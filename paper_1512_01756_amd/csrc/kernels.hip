@@ -651,6 +651,81 @@ __device__ inline void reduce_coef(const InstDev &I, const double *__restrict__ 
   __syncthreads();
 }
 
+// One Givens step of instance (segment leader) i at Arnoldi column j: the
+// Hessenberg column h_t = s_t (sum part1 + sum part2), h_{j+1} = ||w|| from
+// the per-chunk partials (or from the segment sums r1, r2, rn), the earlier
+// rotations applied to it, a new rotation, the residual estimate |g_{j+1}|,
+// the next basis scale and the GMRES state (written to every instance of the
+// segment).  Called by a whole workgroup; h has maxit + 2 entries.
+__device__ inline void givens_step(const InstDev &I, int i, int j, const double *__restrict__ part1,
+                                   const double *__restrict__ part2, const double *__restrict__ partn,
+                                   const double *__restrict__ r1, const double *__restrict__ r2,
+                                   const double *__restrict__ rn, double *__restrict__ scale, double *__restrict__ R,
+                                   double *__restrict__ cs, double *__restrict__ sn, double *__restrict__ g,
+                                   GState *__restrict__ gs, int maxit, double tol, double *h, double *lds4) {
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  double nn = 0.0;
+  if (r1) {   // segment sums reduced by k_seg_reduce
+    for (int t = threadIdx.x; t <= j; t += kBlock) h[t] = scale[I.st_off + t] * (r1[I.st_off + t] + r2[I.st_off + t]);
+    nn = rn[I.st_off];
+  } else {
+    for (int t = wave; t <= j; t += 4) {
+      const double *p1 = part1 + I.part_off + (int64_t)t * I.nchunk_x;
+      const double *p2 = part2 + I.part_off + (int64_t)t * I.nchunk_x;
+      double a = 0.0, b = 0.0;
+      for (int c = lane; c < I.nchunk_x; c += 64) { a += p1[c]; b += p2[c]; }
+      a = wave_sum(a);
+      b = wave_sum(b);
+      if (lane == 0) h[t] = scale[I.st_off + t] * (a + b);
+    }
+    for (int c = threadIdx.x; c < I.nchunk_x; c += kBlock) nn += partn[I.part_off + c];
+    nn = block_sum(nn, lds4);
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const double beta = sqrt(nn);
+    h[j + 1] = beta;
+    double *csI = cs + I.st_off, *snI = sn + I.st_off, *gI = g + I.st_off;
+    for (int t = 0; t < j; ++t) {
+      const double a = csI[t] * h[t] + snI[t] * h[t + 1];
+      h[t + 1] = -snI[t] * h[t] + csI[t] * h[t + 1];
+      h[t] = a;
+    }
+    const double den = hypot(h[j], h[j + 1]);
+    const double c = den != 0.0 ? h[j] / den : 1.0;
+    const double s = den != 0.0 ? h[j + 1] / den : 0.0;
+    csI[j] = c;
+    snI[j] = s;
+    h[j] = den;
+    gI[j + 1] = -s * gI[j];
+    gI[j] = c * gI[j];
+    double *Rc = R + I.rr_off + (int64_t)j * maxit;
+    for (int t = 0; t <= j; ++t) Rc[t] = h[t];
+    const double res = fabs(gI[j + 1]);
+    const double r0 = gs[i].r0, ref = gs[i].ref;
+    int active = 0, status = 0;
+    if (!isfinite(res) || !isfinite(den)) {
+      status = 3;
+    } else if (res <= tol * ref || beta == 0.0) {
+      status = 1;
+    } else if (j + 1 >= maxit) {
+      status = 2;
+    } else {
+      active = 1;
+      scale[I.st_off + j + 1] = 1.0 / beta;
+    }
+    // field by field: a whole-struct copy is kept in scratch by the compiler
+    for (int m = i; m < i + I.seg_count; ++m) {
+      gs[m].iter = j + 1;
+      gs[m].active = active;
+      gs[m].status = status;
+      gs[m].r0 = r0;
+      gs[m].res = res;
+      gs[m].ref = ref;
+    }
+  }
+}
+
 // Classical Gram-Schmidt pass: w -= sum_t coef_t V_t (coef from the partials
 // of the previous pass); then either the next pass's partial dots
 // (part_out) or the partial squared norm (partn).
@@ -723,8 +798,6 @@ __global__ __launch_bounds__(kBlock) void k_axpy_dot(
   }
 }
 
-// Hessenberg column, Givens rotations and the residual estimate (one
-// workgroup per instance).  h_t = s_t (sum part1 + sum part2), h_{j+1} = ||w||.
 // Segment-wide sums of per-chunk partials, for instances that share one
 // Krylov space: out[st_off + t] = sum over the segment's instances and
 // chunks of part[part_off + t nchunk_x + c], t = 0 .. iter (dots), or of
@@ -760,60 +833,7 @@ __global__ __launch_bounds__(kBlock) void k_givens(
   const InstDev I = ins[i];
   if (I.seg_first != i) return;   // a segment's Givens step runs once, on its leader
   if (!gs[i].active) return;
-  const int j = gs[i].iter;
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  double nn = 0.0;
-  if (r1) {   // segment sums reduced by k_seg_reduce
-    for (int t = threadIdx.x; t <= j; t += kBlock) h[t] = scale[I.st_off + t] * (r1[I.st_off + t] + r2[I.st_off + t]);
-    nn = rn[I.st_off];
-  } else {
-    for (int t = wave; t <= j; t += 4) {
-      const double *p1 = part1 + I.part_off + (int64_t)t * I.nchunk_x;
-      const double *p2 = part2 + I.part_off + (int64_t)t * I.nchunk_x;
-      double a = 0.0, b = 0.0;
-      for (int c = lane; c < I.nchunk_x; c += 64) { a += p1[c]; b += p2[c]; }
-      a = wave_sum(a);
-      b = wave_sum(b);
-      if (lane == 0) h[t] = scale[I.st_off + t] * (a + b);
-    }
-    for (int c = threadIdx.x; c < I.nchunk_x; c += kBlock) nn += partn[I.part_off + c];
-    nn = block_sum(nn, lds4);
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    const double beta = sqrt(nn);
-    h[j + 1] = beta;
-    double *csI = cs + I.st_off, *snI = sn + I.st_off, *gI = g + I.st_off;
-    for (int t = 0; t < j; ++t) {
-      const double a = csI[t] * h[t] + snI[t] * h[t + 1];
-      h[t + 1] = -snI[t] * h[t] + csI[t] * h[t + 1];
-      h[t] = a;
-    }
-    const double den = hypot(h[j], h[j + 1]);
-    const double c = den != 0.0 ? h[j] / den : 1.0;
-    const double s = den != 0.0 ? h[j + 1] / den : 0.0;
-    csI[j] = c;
-    snI[j] = s;
-    h[j] = den;
-    gI[j + 1] = -s * gI[j];
-    gI[j] = c * gI[j];
-    double *Rc = R + I.rr_off + (int64_t)j * maxit;
-    for (int t = 0; t <= j; ++t) Rc[t] = h[t];
-    const double res = fabs(gI[j + 1]);
-    GState st = gs[i];
-    st.iter = j + 1;
-    st.res = res;
-    if (!isfinite(res) || !isfinite(den)) {
-      st.active = 0; st.status = 3;
-    } else if (res <= tol * st.ref || beta == 0.0) {
-      st.active = 0; st.status = 1;
-    } else if (j + 1 >= maxit) {
-      st.active = 0; st.status = 2;
-    } else {
-      scale[I.st_off + j + 1] = 1.0 / beta;
-    }
-    for (int m = i; m < i + I.seg_count; ++m) gs[m] = st;
-  }
+  givens_step(I, i, gs[i].iter, part1, part2, partn, r1, r2, rn, scale, R, cs, sn, g, gs, maxit, tol, h, lds4);
 }
 
 // Least squares R y = g (upper triangular, m = iter columns); writes
