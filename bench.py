@@ -89,13 +89,20 @@ def matvec_flops(solver):
     return tot
 
 
+GEMM_KERNELS = {0: "k_half_gemm<double, 16> (split-K, 16 waves)", 1: "k_half_gemm<double, 8> (split-K, 8 waves)",
+                2: "k_half_gemm_t<double> (LDS-staged, XCD-ordered)", 3: "k_half_gemm_t<double> (LDS-staged)"}
+
+
 def matvec_kernel_name(solver):
-    shared = [info["unique_W"] < 2 * (info["mx"] - 1) for info in solver.info]
-    if all(shared):
-        return "k_half_gemm<double> (MFMA, strips sharing blocks)"
-    if not any(shared):
-        return "k_half_gemv_stream<double> (distinct blocks)"
-    return "k_half_gemm<double> + k_half_gemv_stream<double>"
+    """The kernel the FP64 matvec runs: the MFMA GEMM schedule the setup timed
+    fastest where strips share blocks, the streaming GEMV where they do not."""
+    names = set()
+    for info in solver.info:
+        if info["unique_W"] < 2 * (info["mx"] - 1):
+            names.add(GEMM_KERNELS.get(info["gemm_sched"][0], "k_half_gemm<double>"))
+        else:
+            names.add("k_half_gemv_stream<double> (distinct blocks)")
+    return " + ".join(sorted(names))
 
 
 # HBM-side bytes per launch of the FP64 batched Schur matvec, from two

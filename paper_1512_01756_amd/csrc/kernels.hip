@@ -317,38 +317,51 @@ __global__ __launch_bounds__(64 * KP) void k_half_gemm(
   const int64_t kS = wk.kS;
   const int rt = blockIdx.y;
   if (rt * 16 >= Np) return;
-  load_windows<VT>(wk, gvec, x_vslot, scale, gs, wi);
-  __syncthreads();
-  int anylive = 0;
-  for (int v = 0; v < wk.vcount; ++v) anylive |= wi[v].live;
-  if (!anylive) return;
   const TS *blk = Tab<TS>::blk(wk);
   const int kp = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int arow = rt * 16 + (lane & 15);
   const bool alive = arow < Np;
   const int kq = lane >> 4;
+  const int nsteps = (K + 3) >> 2;
+  const int s0 = (nsteps * kp) / KP, s1 = (nsteps * (kp + 1)) / KP;
+  // The first block values do not depend on the windows: in flight while
+  // the window table is read.
+  TO a[U];
+  auto load_a = [&](int st) {
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int k = 4 * (st + u) + kq;
+      a[u] = (alive && st + u < s1 && k < K) ? (TO)blk[(size_t)k * Np + arow] : (TO)0;
+    }
+  };
+  load_a(s0);
+  load_windows<VT>(wk, gvec, x_vslot, scale, gs, wi);
+  __syncthreads();
+  int anylive = 0;
+  for (int v = 0; v < wk.vcount; ++v) anylive |= wi[v].live;
+  if (!anylive) return;
+  const bool two = wk.vcount > 16;   // second 16-window operand in use
   const int va = lane & 15, vb = 16 + (lane & 15);
   const bool la = va < wk.vcount && wi[va].live, lb = vb < wk.vcount && wi[vb].live;
   const int64_t xa = wi[va].xoff, wa = wi[va].win, xb = wi[vb].xoff, wb = wi[vb].win;
   using Acc = typename Mfma<TO>::Acc;
   Acc acc0 = {0, 0, 0, 0}, acc1 = {0, 0, 0, 0};
-  const int nsteps = (K + 3) >> 2;
-  const int s0 = (nsteps * kp) / KP, s1 = (nsteps * (kp + 1)) / KP;
   for (int st = s0; st < s1; st += U) {
-    TO a[U], b0[U], b1[U];
+    if (st != s0) load_a(st);
+    TO b0[U], b1[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const int k = 4 * (st + u) + kq;
       const bool kin = st + u < s1 && k < K;
       const int64_t ga = wa + k, gb = wb + k;
-      a[u] = (alive && kin) ? (TO)blk[(size_t)k * Np + arow] : (TO)0;
       b0[u] = (la && kin && ga >= 0 && ga < kS) ? (TO)xbase[xa + ga] : (TO)0;
-      b1[u] = (lb && kin && gb >= 0 && gb < kS) ? (TO)xbase[xb + gb] : (TO)0;
+      b1[u] = (two && lb && kin && gb >= 0 && gb < kS) ? (TO)xbase[xb + gb] : (TO)0;
     }
 #pragma unroll
-    for (int u = 0; u < U; ++u) {
-      acc0 = Mfma<TO>::mac(a[u], b0[u], acc0);
-      acc1 = Mfma<TO>::mac(a[u], b1[u], acc1);
+    for (int u = 0; u < U; ++u) acc0 = Mfma<TO>::mac(a[u], b0[u], acc0);
+    if (two) {
+#pragma unroll
+      for (int u = 0; u < U; ++u) acc1 = Mfma<TO>::mac(a[u], b1[u], acc1);
     }
   }
 #pragma unroll
@@ -547,6 +560,45 @@ __global__ __launch_bounds__(kBlock) void k_coarse(const SysDev *__restrict__ sy
   }
 }
 
+// Partial dots V_t . w over one chunk, t = 0 .. j, written to
+// part[t * nchunk + ch].  The chunk of w is in LDS (ws, zero past k_S); wave
+// q takes t = q, q + 4, ... two at a time over all kChunk elements (8
+// coalesced loads per lane per t), so a reduction serves two dots and no
+// cross-wave step is needed.
+template <typename TV>
+__device__ inline void chunk_dots(const TV *__restrict__ V, int64_t kS, int64_t e0, int j,
+                                  const double *__restrict__ ws, double *__restrict__ part, int nchunk, int ch) {
+  constexpr int Q = kChunk / 64;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  double wl[Q];
+  bool in[Q];
+#pragma unroll
+  for (int q = 0; q < Q; ++q) {
+    wl[q] = ws[lane + 64 * q];
+    in[q] = e0 + lane + 64 * q < kS;
+  }
+  for (int t = wave; t <= j; t += 8) {
+    const int t2 = t + 4;
+    const bool two = t2 <= j;
+    const TV *Va = V + (int64_t)t * kS + e0 + lane;
+    const TV *Vb = V + (int64_t)(two ? t2 : t) * kS + e0 + lane;
+    double a = 0.0, b = 0.0;
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+      if (in[q]) {
+        a += (double)Va[64 * q] * wl[q];
+        b += (double)Vb[64 * q] * wl[q];
+      }
+    }
+    a = wave_sum(a);
+    b = wave_sum(b);
+    if (lane == 0) {
+      part[(int64_t)t * nchunk + ch] = a;
+      if (two) part[(int64_t)t2 * nchunk + ch] = b;
+    }
+  }
+}
+
 // Arnoldi step, part 1: w = y - (S Z) c with c = G Z^T y (the deflation P,
 // Sec. 3.3; useP = 0 skips it), stored in Krylov slot iter + 1; partial dots
 // V_t . w for t <= iter.  The coarse solve is fused: every workgroup forms
@@ -557,8 +609,9 @@ __global__ __launch_bounds__(kBlock) void k_pcorr_dot(
     const SysDev *__restrict__ sys, const InstDev *__restrict__ ins, const int2 *__restrict__ work,
     const TY *__restrict__ ybase, const double *__restrict__ hsum, int useP, TV *__restrict__ V,
     double *__restrict__ part, const GState *__restrict__ gs, int maxit) {
-  extern __shared__ double red[];   // (maxit + 1) * 4, then t_s[d]
+  extern __shared__ double t_s[];   // d
   __shared__ double c_s[kChunk / 2 + 8];
+  __shared__ double ws[kChunk];
   const int2 wk = work[blockIdx.x];
   const int i = wk.x, ch = wk.y;
   if (!gs[i].active) return;
@@ -571,7 +624,6 @@ __global__ __launch_bounds__(kBlock) void k_pcorr_dot(
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   int c0 = 0;
   if (useP) {
-    double *t_s = red + (size_t)(maxit + 1) * 4;
     const int d = S.d, zm = S.zm, nif = S.mx - 1;
     const int sl = hs_slots(S);
     for (int c = threadIdx.x; c < d; c += kBlock) {
@@ -600,7 +652,6 @@ __global__ __launch_bounds__(kBlock) void k_pcorr_dot(
     }
     __syncthreads();
   }
-  double wv[kChunk / kBlock];
 #pragma unroll
   for (int q = 0; q < kChunk / kBlock; ++q) {
     const int64_t e = e0 + threadIdx.x + q * kBlock;
@@ -615,22 +666,10 @@ __global__ __launch_bounds__(kBlock) void k_pcorr_dot(
       V[I.v_off + (int64_t)(j + 1) * kS + e] = wt;
       w = (double)wt;
     }
-    wv[q] = w;
-  }
-  for (int t = 0; t <= j; ++t) {
-    const TV *Vt = V + I.v_off + (int64_t)t * kS;
-    double a = 0.0;
-#pragma unroll
-    for (int q = 0; q < kChunk / kBlock; ++q) {
-      const int64_t e = e0 + threadIdx.x + q * kBlock;
-      if (e < kS) a += (double)Vt[e] * wv[q];
-    }
-    a = wave_sum(a);
-    if (lane == 0) red[t * 4 + wave] = a;
+    ws[threadIdx.x + q * kBlock] = w;
   }
   __syncthreads();
-  for (int t = threadIdx.x; t <= j; t += kBlock)
-    part[I.part_off + (int64_t)t * I.nchunk_x + ch] = (red[t * 4] + red[t * 4 + 1]) + (red[t * 4 + 2] + red[t * 4 + 3]);
+  chunk_dots(V + I.v_off, kS, e0, j, ws, part + I.part_off, I.nchunk_x, ch);
 }
 
 // Reduce the chunk partials of pass `part` into coef[t] = s_t^2 sum(...)
@@ -638,14 +677,25 @@ __global__ __launch_bounds__(kBlock) void k_pcorr_dot(
 __device__ inline void reduce_coef(const InstDev &I, const double *__restrict__ part,
                                    const double *__restrict__ scale, int j, double *coef) {
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  for (int t = wave; t <= j; t += 4) {
+  for (int t = wave; t <= j; t += 8) {   // two coefficients per reduction pass
+    const int t2 = t + 4;
+    const bool two = t2 <= j;
     const double *p = part + I.part_off + (int64_t)t * I.nchunk_x;
-    double a = 0.0;
-    for (int c = lane; c < I.nchunk_x; c += 64) a += p[c];
+    const double *p2 = part + I.part_off + (int64_t)(two ? t2 : t) * I.nchunk_x;
+    double a = 0.0, b = 0.0;
+    for (int c = lane; c < I.nchunk_x; c += 64) {
+      a += p[c];
+      b += p2[c];
+    }
     a = wave_sum(a);
+    b = wave_sum(b);
     if (lane == 0) {
       const double s = scale[I.st_off + t];
       coef[t] = s * s * a;
+      if (two) {
+        const double s2 = scale[I.st_off + t2];
+        coef[t2] = s2 * s2 * b;
+      }
     }
   }
   __syncthreads();
@@ -735,7 +785,9 @@ __global__ __launch_bounds__(kBlock) void k_axpy_dot(
     TV *__restrict__ V, const double *__restrict__ part_in, double *__restrict__ part_out,
     double *__restrict__ partn, const double *__restrict__ scale, const GState *__restrict__ gs,
     const double *__restrict__ coefr) {
-  extern __shared__ double sh[];   // coef[maxit + 1] then red[(maxit + 1) * 4]
+  extern __shared__ double coef[];   // maxit + 1
+  __shared__ double ws[kChunk];
+  __shared__ double red[4];
   const int2 wk = work[blockIdx.x];
   const int i = wk.x, ch = wk.y;
   if (!gs[i].active) return;
@@ -743,8 +795,6 @@ __global__ __launch_bounds__(kBlock) void k_axpy_dot(
   const SysDev &S = sys[I.sys];
   const int64_t kS = S.kS;
   const int j = gs[i].iter;
-  double *coef = sh;
-  double *red = sh + (j + 1);
   if (coefr) {   // segment sums reduced by k_seg_reduce
     for (int t = threadIdx.x; t <= j; t += kBlock) {
       const double s = scale[I.st_off + t];
@@ -754,43 +804,40 @@ __global__ __launch_bounds__(kBlock) void k_axpy_dot(
   } else {
     reduce_coef(I, part_in, scale, j, coef);
   }
+  static_assert(kChunk == 2 * kBlock, "two elements per thread");
   const int64_t e0 = (int64_t)ch * kChunk;
+  const int64_t ea = e0 + threadIdx.x, eb = ea + kBlock;
+  const bool ina = ea < kS, inb = eb < kS;
   TV *w = V + I.v_off + (int64_t)(j + 1) * kS;
-  double wv[kChunk / kBlock];
-#pragma unroll
-  for (int q = 0; q < kChunk / kBlock; ++q) {
-    const int64_t e = e0 + threadIdx.x + q * kBlock;
-    double a = 0.0;
-    if (e < kS) {
-      a = (double)w[e];
-      for (int t = 0; t <= j; ++t) a -= coef[t] * (double)V[I.v_off + (int64_t)t * kS + e];
-      const TV at = (TV)a;
-      w[e] = at;
-      a = (double)at;
-    }
-    wv[q] = a;
+  double a0 = ina ? (double)w[ea] : 0.0, a1 = inb ? (double)w[eb] : 0.0;
+  const TV *Vt = V + I.v_off + ea;
+#pragma unroll 4
+  for (int t = 0; t <= j; ++t, Vt += kS) {
+    const double c = coef[t];
+    if (ina) a0 -= c * (double)Vt[0];
+    if (inb) a1 -= c * (double)Vt[kBlock];
   }
+  if (ina) {
+    const TV at = (TV)a0;
+    w[ea] = at;
+    a0 = (double)at;
+  }
+  if (inb) {
+    const TV at = (TV)a1;
+    w[eb] = at;
+    a1 = (double)at;
+  }
+  const double wv[2] = {a0, a1};
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   if (part_out) {
-    for (int t = 0; t <= j; ++t) {
-      const TV *Vt = V + I.v_off + (int64_t)t * kS;
-      double a = 0.0;
-#pragma unroll
-      for (int q = 0; q < kChunk / kBlock; ++q) {
-        const int64_t e = e0 + threadIdx.x + q * kBlock;
-        if (e < kS) a += (double)Vt[e] * wv[q];
-      }
-      a = wave_sum(a);
-      if (lane == 0) red[t * 4 + wave] = a;
-    }
+    ws[threadIdx.x] = a0;
+    ws[threadIdx.x + kBlock] = a1;
     __syncthreads();
-    for (int t = threadIdx.x; t <= j; t += kBlock)
-      part_out[I.part_off + (int64_t)t * I.nchunk_x + ch] =
-          (red[t * 4] + red[t * 4 + 1]) + (red[t * 4 + 2] + red[t * 4 + 3]);
+    chunk_dots(V + I.v_off, kS, e0, j, ws, part_out + I.part_off, I.nchunk_x, ch);
   } else {
     double a = 0.0;
 #pragma unroll
-    for (int q = 0; q < kChunk / kBlock; ++q) a += wv[q] * wv[q];
+    for (int q = 0; q < 2; ++q) a += wv[q] * wv[q];
     a = wave_sum(a);
     if (lane == 0) red[wave] = a;
     __syncthreads();
@@ -1369,7 +1416,8 @@ __global__ __launch_bounds__(kBlock) void k_gmres_start(const InstDev *__restric
 // Elementwise interface-space helpers.
 // mode 0: out = a + Z c          (x_S = z + Z c')
 // mode 1: out = out + a + Z c    (refinement update)
-// mode 2: out = out - a          (residual r = b - S x with out holding b), partials ||r||^2 and u_S . r
+// mode 2: out = base - a         (residual r = b - S x; base = nullptr: out
+//                                holds b), partials ||r||^2 and u_S . r
 // mode 3: out = a - (S Z) c      (deflation P)
 // mode 4: out = a - Z c          (deflation Q after c = G Z^T S a)
 template <typename TA>
@@ -1379,7 +1427,8 @@ __global__ __launch_bounds__(kBlock) void k_xupdate(const SysDev *__restrict__ s
                                                     const TA *__restrict__ a,
                                                     const double *__restrict__ cvec,
                                                     double *__restrict__ out,
-                                                    double *__restrict__ partn) {
+                                                    double *__restrict__ partn,
+                                                    const double *__restrict__ base) {
   __shared__ double lds4[4];
   const int2 wk = work[blockIdx.x];
   const int i = wk.x, ch = wk.y;
@@ -1395,7 +1444,7 @@ __global__ __launch_bounds__(kBlock) void k_xupdate(const SysDev *__restrict__ s
     const int zc = z_col(S, h, row);
     double v = a ? (double)a[I.x_off + e] : 0.0;
     if (mode == 2) {
-      v = out[I.x_off + e] - v;
+      v = (base ? base[I.x_off + e] : out[I.x_off + e]) - v;
       out[I.x_off + e] = v;
       nn += v * v;
       if (S.singular) ud += S.uS[e] * v;
@@ -1493,10 +1542,10 @@ __global__ __launch_bounds__(kBlock) void k_sub_mean(const SysDev *__restrict__ 
 }
 
 // Reduce interface-space partial pairs (||r||^2, u_S . r) to one instance
-// scalar pair: out[2 i], out[2 i + 1].
+// scalar pair: out[2 i], out[2 i + 1] (and the same into out2 if given).
 __global__ __launch_bounds__(kBlock) void k_reduce_pairs(const InstDev *__restrict__ ins,
                                                          const double *__restrict__ partn,
-                                                         double *__restrict__ out) {
+                                                         double *__restrict__ out, double *__restrict__ out2) {
   __shared__ double lds4[4];
   const int i = blockIdx.x;
   const InstDev I = ins[i];
@@ -1505,7 +1554,14 @@ __global__ __launch_bounds__(kBlock) void k_reduce_pairs(const InstDev *__restri
   a = block_sum(a, lds4);
   __syncthreads();
   b = block_sum(b, lds4);
-  if (threadIdx.x == 0) { out[2 * i] = a; out[2 * i + 1] = b; }
+  if (threadIdx.x == 0) {
+    out[2 * i] = a;
+    out[2 * i + 1] = b;
+    if (out2) {
+      out2[2 * i] = a;
+      out2[2 * i + 1] = b;
+    }
+  }
 }
 
 // The transform in the periodic y direction of the 3-D problem (Sec. 5) as a

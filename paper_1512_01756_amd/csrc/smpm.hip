@@ -187,15 +187,25 @@ struct smpm_handle {
   hipStream_t ws = nullptr;
   hipEvent_t ev_in = nullptr, ev_out = nullptr;
   // Captured graphs, index [0] FP64 inner solve, [1] FP32 inner solve:
-  // before the Krylov loop, kIterChunk iterations, after the loop.  The
-  // staging graph is keyed by the caller's f and g, the recovery graph by u.
+  // before the Krylov loop, kIterChunk iterations (g_rem: 1 .. kIterChunk - 1
+  // iterations), after the loop.  The staging graph is keyed by the caller's
+  // f and g, the recovery graph by u; the FP64 solve runs as a head graph
+  // (staging and the loop set-up, keyed by f and g) and a tail graph (the
+  // loop's end, the residual check and the recovery, keyed by u).
   hipGraphExec_t g_pre[2] = {}, g_loop[2] = {}, g_post[2] = {};
+  hipGraphExec_t g_rem[2][kIterChunk] = {};
   hipGraphExec_t g_resid = nullptr, g_stage = nullptr, g_finish = nullptr;
-  const void *stage_f = nullptr, *stage_g = nullptr;
-  void *fin_u = nullptr;
-  // Iteration chunks launched before the first convergence check, from the
-  // previous solve's iteration count.
-  int pred_chunks[2] = {1, 1};
+  hipGraphExec_t g_head = nullptr, g_tail = nullptr;
+  const void *stage_f = nullptr, *stage_g = nullptr, *head_f = nullptr, *head_g = nullptr;
+  void *fin_u = nullptr, *tail_u = nullptr;
+  // Iterations launched before the first convergence check: the previous
+  // solve's count (-1: none yet, one chunk).
+  int pred_iters[2] = {-1, -1};
+  // The FP64 solve's report, read back with one copy: GMRES states, then
+  // (||r||^2, u_S . r), the compatibility defects and (||b~||^2, u_S . b~)
+  // per instance (gs, pairs, defect and nb2 point into it).
+  size_t rep_bytes = 0;
+  char *h_rep = nullptr;       // pinned
   // 3-D problems (smpm_setup_fourier): m_y planes, the forward and inverse
   // real DFT matrices ([2 nk][m_y] and [m_y][2 nk], row-major), and the
   // coefficient buffers of f, g, u in the batched layouts.
@@ -207,8 +217,11 @@ struct smpm_handle {
 
   ~smpm_handle() {
     for (hipGraphExec_t *e : {&g_pre[0], &g_pre[1], &g_loop[0], &g_loop[1], &g_post[0], &g_post[1], &g_resid,
-                              &g_stage, &g_finish})
+                              &g_stage, &g_finish, &g_head, &g_tail})
       if (*e) (void)hipGraphExecDestroy(*e);
+    for (auto &r : g_rem)
+      for (hipGraphExec_t e : r)
+        if (e) (void)hipGraphExecDestroy(e);
     if (ev_in) (void)hipEventDestroy(ev_in);
     if (ev_out) (void)hipEventDestroy(ev_out);
     if (ws) (void)hipStreamDestroy(ws);
@@ -218,6 +231,7 @@ struct smpm_handle {
     if (h_defect) (void)hipHostFree(h_defect);
     if (h_gs_hist) (void)hipHostFree(h_gs_hist);
     if (h_nb) (void)hipHostFree(h_nb);
+    if (h_rep) (void)hipHostFree(h_rep);
   }
 };
 
@@ -586,12 +600,20 @@ void upload(smpm_handle *H, hipStream_t st) {
   H->scale = dalloc<double>(own, st_off); H->cs = dalloc<double>(own, st_off); H->sn = dalloc<double>(own, st_off);
   H->g = dalloc<double>(own, st_off); H->ycoef = dalloc<double>(own, st_off); H->Rm = dalloc<double>(own, rr_off);
   H->lam = dalloc<double>(own, lam_off); H->qb = dalloc<double>(own, lam_off);
-  H->defect = dalloc<double>(own, H->ninst); H->pairs = dalloc<double>(own, 2 * H->ninst);
-  H->nb2 = dalloc<double>(own, 2 * H->ninst);
+  {
+    static_assert(sizeof(GState) % sizeof(double) == 0, "GState packs into doubles");
+    const size_t gs_d = sizeof(GState) / sizeof(double) * H->ninst;
+    double *rep = dalloc<double>(own, gs_d + 5 * (size_t)H->ninst);
+    H->gs = reinterpret_cast<GState *>(rep);
+    H->pairs = rep + gs_d;
+    H->defect = H->pairs + 2 * H->ninst;
+    H->nb2 = H->defect + H->ninst;
+    H->rep_bytes = sizeof(double) * (gs_d + 5 * (size_t)H->ninst);
+    HIPCHECK(hipHostMalloc((void **)&H->h_rep, H->rep_bytes, hipHostMallocDefault));
+  }
   if (H->one_krylov) {
     H->sr1 = dalloc<double>(own, st_off); H->sr2 = dalloc<double>(own, st_off); H->srn = dalloc<double>(own, st_off);
   }
-  H->gs = dalloc<GState>(own, H->ninst);
   HIPCHECK(hipHostMalloc((void **)&H->h_gs, sizeof(GState) * H->ninst, hipHostMallocDefault));
   HIPCHECK(hipHostMalloc((void **)&H->h_pairs, sizeof(double) * 2 * H->ninst, hipHostMallocDefault));
   HIPCHECK(hipHostMalloc((void **)&H->h_defect, sizeof(double) * H->ninst, hipHostMallocDefault));
@@ -947,7 +969,7 @@ struct Inner {
     const bool useM = H->method != SMPM_METHOD_SCHUR;
     const bool useP = H->method == SMPM_METHOD_DBJ;
     const int maxit = H->maxit;
-    const size_t shm_dot = sizeof(double) * (maxit + 1) * 5;
+    const size_t shm_dot = sizeof(double) * (maxit + 1);
     T *Vb = V(H), *zb = z(H), *yb = y(H);
     // Z^T y for P: from the matvec's epilogue (one column per interface) or
     // a segment-sum pass (one column per element segment)
@@ -966,7 +988,7 @@ struct Inner {
     if (useP && H->zlabel != 0)
       hipLaunchKernelGGL(k_zt<T>, dim3(H->n_h), dim3(kBlock), 0, st, H->d_sys, H->d_ins, H->w_h, (const T *)yb, 0,
                          (const double *)nullptr, (const GState *)H->gs, H->hs);
-    hipLaunchKernelGGL((k_pcorr_dot<T, T>), dim3(H->n_x), dim3(kBlock), sizeof(double) * ((maxit + 1) * 4 + H->dmax), st,
+    hipLaunchKernelGGL((k_pcorr_dot<T, T>), dim3(H->n_x), dim3(kBlock), sizeof(double) * H->dmax, st,
                        H->d_sys,
                        H->d_ins, H->w_x, (const T *)yb, (const double *)H->hs, useP ? 1 : 0, Vb, H->part1,
                        (const GState *)H->gs, maxit);
@@ -1022,27 +1044,51 @@ struct Inner {
       cfin = H->cv;
     }
     hipLaunchKernelGGL(k_xupdate<T>, dim3(H->n_x), dim3(kBlock), 0, st, H->d_sys, H->d_ins, H->w_x, P == 0 ? 0 : 1,
-                       xfin, cfin, H->xS, (double *)nullptr);
+                       xfin, cfin, H->xS, (double *)nullptr, (const double *)nullptr);
+  }
+
+  // Enqueue n GMRES iterations: whole chunks, then one graph of the rest.
+  static void iterations(smpm_handle *H, int n, hipStream_t st) {
+    if (!H->g_loop[P])
+      H->g_loop[P] = capture(st, [&] {
+        for (int c = 0; c < kIterChunk; ++c) iteration(H, st);
+      });
+    for (; n >= kIterChunk; n -= kIterChunk) HIPCHECK(hipGraphLaunch(H->g_loop[P], st));
+    if (n > 0) {
+      if (!H->g_rem[P][n])
+        H->g_rem[P][n] = capture(st, [&] {
+          for (int c = 0; c < n; ++c) iteration(H, st);
+        });
+      HIPCHECK(hipGraphLaunch(H->g_rem[P][n], st));
+    }
+  }
+
+  // The predicted iterations (the previous solve's count, one chunk for the
+  // first solve), capped at maxit; returns how many were enqueued.
+  static int predicted(smpm_handle *H, hipStream_t st) {
+    const int pred = H->pred_iters[P] < 0 ? kIterChunk : H->pred_iters[P];
+    const int n = std::min(pred, H->maxit);
+    iterations(H, n, st);
+    return n;
+  }
+
+  // Further chunks while an instance is still iterating (one host check per
+  // chunk).
+  static void until_done(smpm_handle *H, int launched, hipStream_t st) {
+    while (launched < H->maxit && any_active(H, st)) {
+      const int n = std::min(kIterChunk, H->maxit - launched);
+      iterations(H, n, st);
+      launched += n;
+    }
   }
 
   // Enqueue one inner solve; its final GMRES states are copied to the pinned
   // history slot `slot` (read after the solve's last synchronization).
   static void run(smpm_handle *H, int slot, hipStream_t st) {
     if (!H->g_pre[P]) H->g_pre[P] = capture(st, [&] { pre(H, st); });
-    if (!H->g_loop[P])
-      H->g_loop[P] = capture(st, [&] {
-        for (int c = 0; c < kIterChunk; ++c) iteration(H, st);
-      });
     if (!H->g_post[P]) H->g_post[P] = capture(st, [&] { post(H, st); });
     HIPCHECK(hipGraphLaunch(H->g_pre[P], st));
-    const int max_chunks = (H->maxit + kIterChunk - 1) / kIterChunk;
-    int launched = 0;
-    const int first = std::min(std::max(1, H->pred_chunks[P]), max_chunks);
-    for (; launched < first; ++launched) HIPCHECK(hipGraphLaunch(H->g_loop[P], st));
-    while (launched < max_chunks && any_active(H, st)) {
-      HIPCHECK(hipGraphLaunch(H->g_loop[P], st));
-      ++launched;
-    }
+    until_done(H, predicted(H, st), st);
     HIPCHECK(hipGraphLaunch(H->g_post[P], st));
     HIPCHECK(hipMemcpyAsync(H->h_gs_hist + (size_t)slot * H->ninst, H->gs, sizeof(GState) * H->ninst,
                             hipMemcpyDeviceToHost, st));
@@ -1053,10 +1099,10 @@ struct Inner {
 // r <- r - u_S (u_S . r) (the refinement residual, k = 0).
 void residual64(smpm_handle *H, hipStream_t st) {
   gemv<double, double, double>(H, 0, H->xS, 0, nullptr, H->y64, nullptr, nullptr, st);
-  HIPCHECK(hipMemcpyAsync(H->rb, H->bS, sizeof(double) * H->tot_x, hipMemcpyDeviceToDevice, st));
   hipLaunchKernelGGL(k_xupdate<double>, dim3(H->n_x), dim3(kBlock), 0, st, H->d_sys, H->d_ins, H->w_x, 2,
-                     (const double *)H->y64, (const double *)nullptr, H->rb, H->partn);
-  hipLaunchKernelGGL(k_reduce_pairs, dim3(H->ninst), dim3(kBlock), 0, st, H->d_ins, (const double *)H->partn, H->pairs);
+                     (const double *)H->y64, (const double *)nullptr, H->rb, H->partn, (const double *)H->bS);
+  hipLaunchKernelGGL(k_reduce_pairs, dim3(H->ninst), dim3(kBlock), 0, st, H->d_ins, (const double *)H->partn, H->pairs,
+                     (double *)nullptr);
   hipLaunchKernelGGL(k_proj_x_scalar, dim3(H->n_x), dim3(kBlock), 0, st, H->d_sys, H->d_ins, H->w_x, H->rb,
                      (const double *)H->pairs);
 }
@@ -1071,11 +1117,13 @@ void stage_rhs(smpm_handle *H, const double *f, const double *g, hipStream_t st)
   hipLaunchKernelGGL(k_bS, dim3(H->n_h), dim3(kBlock), 0, st, H->d_sys, H->d_ins, H->w_h, (const double *)H->v, H->bS, H->hs);
   hipLaunchKernelGGL(k_proj_x, dim3(H->n_x), dim3(kBlock), 0, st, H->d_sys, H->d_ins, H->w_x, H->bS, (const double *)H->hs);
   hipLaunchKernelGGL(k_xupdate<double>, dim3(H->n_x), dim3(kBlock), 0, st, H->d_sys, H->d_ins, H->w_x, 2,
-                     (const double *)nullptr, (const double *)nullptr, H->bS, H->partn);
-  hipLaunchKernelGGL(k_reduce_pairs, dim3(H->ninst), dim3(kBlock), 0, st, H->d_ins, (const double *)H->partn, H->pairs);
-  HIPCHECK(hipMemcpyAsync(H->nb2, H->pairs, sizeof(double) * 2 * H->ninst, hipMemcpyDeviceToDevice, st));
-  if (H->precision != SMPM_FP64) {
-    HIPCHECK(hipMemcpyAsync(H->rb, H->bS, sizeof(double) * H->tot_x, hipMemcpyDeviceToDevice, st));
+                     (const double *)nullptr, (const double *)nullptr, H->bS, H->partn, (const double *)nullptr);
+  hipLaunchKernelGGL(k_reduce_pairs, dim3(H->ninst), dim3(kBlock), 0, st, H->d_ins, (const double *)H->partn, H->pairs,
+                     H->nb2);
+  if (H->precision != SMPM_FP64) {   // r = b~ (a copy through mode 0), x_S = 0
+    hipLaunchKernelGGL(k_xupdate<double>, dim3(H->n_x), dim3(kBlock), 0, st, H->d_sys, H->d_ins, H->w_x, 0,
+                       (const double *)H->bS, (const double *)nullptr, H->rb, (double *)nullptr,
+                       (const double *)nullptr);
     hipLaunchKernelGGL(k_fill, dim3((unsigned)((H->tot_x + kBlock - 1) / kBlock)), dim3(kBlock), 0, st, H->xS, H->tot_x,
                        0.0);
   }
@@ -1335,24 +1383,67 @@ smpm_status smpm_solve(smpm_handle *H, const double *f, const double *g, double 
   try {
     HIPCHECK(hipEventRecord(H->ev_in, caller));
     HIPCHECK(hipStreamWaitEvent(st, H->ev_in, 0));
-    if (!H->g_stage || H->stage_f != f || H->stage_g != g) {
-      if (H->g_stage) HIPCHECK(hipGraphExecDestroy(H->g_stage));
-      H->g_stage = nullptr;
-      H->g_stage = capture(st, [&] { stage_rhs(H, f, g, st); });
-      H->stage_f = f; H->stage_g = g;
-    }
-    if (!H->g_resid) H->g_resid = capture(st, [&] { residual64(H, st); });
-    HIPCHECK(hipGraphLaunch(H->g_stage, st));
-    HIPCHECK(hipMemcpyAsync(H->h_nb, H->pairs, sizeof(double) * 2 * H->ninst, hipMemcpyDeviceToHost, st));
     const bool useP = H->method == SMPM_METHOD_DBJ;
     bool nonfinite = false, notconv = false;
     int sweeps = 0;
     if (H->precision == SMPM_FP64) {
-      Inner<double>::run(H, 0, st);
+      // Head graph, the predicted iterations, then the tail graph (the
+      // loop's end, the final FP64 check of the Schur residual, the
+      // recovery of u) and the report, with one synchronization.  The tail
+      // only overwrites its outputs and leaves the Krylov state alone, so
+      // if an instance is still iterating the loop resumes and the tail is
+      // enqueued again.
+      if (!H->g_head || H->head_f != f || H->head_g != g) {
+        if (H->g_head) HIPCHECK(hipGraphExecDestroy(H->g_head));
+        H->g_head = nullptr;
+        H->g_head = capture(st, [&] {
+          stage_rhs(H, f, g, st);
+          Inner<double>::pre(H, st);
+        });
+        H->head_f = f; H->head_g = g;
+      }
+      if (!H->g_tail || H->tail_u != u) {
+        if (H->g_tail) HIPCHECK(hipGraphExecDestroy(H->g_tail));
+        H->g_tail = nullptr;
+        H->g_tail = capture(st, [&] {
+          Inner<double>::post(H, st);
+          residual64(H, st);
+          finish_u(H, u, st);
+        });
+        H->tail_u = u;
+      }
+      HIPCHECK(hipGraphLaunch(H->g_head, st));
+      int launched = Inner<double>::predicted(H, st);
+      for (;;) {
+        HIPCHECK(hipGraphLaunch(H->g_tail, st));
+        HIPCHECK(hipMemcpyAsync(H->h_rep, H->gs, H->rep_bytes, hipMemcpyDeviceToHost, st));
+        HIPCHECK(hipStreamSynchronize(st));
+        const GState *hg = reinterpret_cast<const GState *>(H->h_rep);
+        bool active = false;
+        for (int i = 0; i < H->ninst; ++i) active |= hg[i].active != 0;
+        if (!active || launched >= H->maxit) break;
+        const int n = std::min(kIterChunk, H->maxit - launched);
+        Inner<double>::iterations(H, n, st);
+        Inner<double>::until_done(H, launched + n, st);
+        launched = H->maxit;   // every instance has stopped: this tail is the last
+      }
+      const size_t gs_b = sizeof(GState) * H->ninst;
+      std::memcpy(H->h_gs_hist, H->h_rep, gs_b);
+      std::memcpy(H->h_pairs, H->h_rep + gs_b, sizeof(double) * 2 * H->ninst);
+      std::memcpy(H->h_defect, H->h_rep + gs_b + sizeof(double) * 2 * H->ninst, sizeof(double) * H->ninst);
+      std::memcpy(H->h_nb, H->h_rep + gs_b + sizeof(double) * 3 * H->ninst, sizeof(double) * 2 * H->ninst);
       sweeps = 1;
-      HIPCHECK(hipGraphLaunch(H->g_resid, st));   // final FP64 check of the Schur residual
       S.schur_matvecs += H->ninst * ((useP ? 1 : 0) + 1);
     } else {
+      if (!H->g_stage || H->stage_f != f || H->stage_g != g) {
+        if (H->g_stage) HIPCHECK(hipGraphExecDestroy(H->g_stage));
+        H->g_stage = nullptr;
+        H->g_stage = capture(st, [&] { stage_rhs(H, f, g, st); });
+        H->stage_f = f; H->stage_g = g;
+      }
+      if (!H->g_resid) H->g_resid = capture(st, [&] { residual64(H, st); });
+      HIPCHECK(hipGraphLaunch(H->g_stage, st));
+      HIPCHECK(hipMemcpyAsync(H->h_nb, H->pairs, sizeof(double) * 2 * H->ninst, hipMemcpyDeviceToHost, st));
       double prev_worst = 1.0;
       for (;; ++sweeps) {
         if (sweeps > 0) {
@@ -1379,17 +1470,15 @@ smpm_status smpm_solve(smpm_handle *H, const double *f, const double *g, double 
         Inner<float>::run(H, sweeps, st);
         S.schur_matvecs += useP ? H->ninst : 0;
       }
+      HIPCHECK(hipMemcpyAsync(H->h_defect, H->defect, sizeof(double) * H->ninst, hipMemcpyDeviceToHost, st));
+      if (!H->g_finish || H->fin_u != u) {
+        if (H->g_finish) HIPCHECK(hipGraphExecDestroy(H->g_finish));
+        H->g_finish = nullptr;
+        H->g_finish = capture(st, [&] { finish_u(H, u, st); });
+        H->fin_u = u;
+      }
+      HIPCHECK(hipGraphLaunch(H->g_finish, st));
     }
-    if (H->precision == SMPM_FP64)
-      HIPCHECK(hipMemcpyAsync(H->h_pairs, H->pairs, sizeof(double) * 2 * H->ninst, hipMemcpyDeviceToHost, st));
-    HIPCHECK(hipMemcpyAsync(H->h_defect, H->defect, sizeof(double) * H->ninst, hipMemcpyDeviceToHost, st));
-    if (!H->g_finish || H->fin_u != u) {
-      if (H->g_finish) HIPCHECK(hipGraphExecDestroy(H->g_finish));
-      H->g_finish = nullptr;
-      H->g_finish = capture(st, [&] { finish_u(H, u, st); });
-      H->fin_u = u;
-    }
-    HIPCHECK(hipGraphLaunch(H->g_finish, st));
     HIPCHECK(hipGetLastError());
     HIPCHECK(hipEventRecord(H->ev_out, st));
     HIPCHECK(hipStreamWaitEvent(caller, H->ev_out, 0));
@@ -1408,7 +1497,7 @@ smpm_status smpm_solve(smpm_handle *H, const double *f, const double *g, double 
         if (gsi.status == 3) nonfinite = true;
         if (gsi.status == 2 && H->precision == SMPM_FP64) notconv = true;
       }
-    H->pred_chunks[P] = std::max(1, (itmax_all + kIterChunk - 1) / kIterChunk);
+    H->pred_iters[P] = itmax_all;
     S.sweeps_max = H->precision == SMPM_FP64 ? 1 : sweeps;
     double relmax = 0.0, defmax = 0.0;
     int conv = 0;
@@ -1473,7 +1562,8 @@ smpm_status smpm_apply(smpm_handle *H, smpm_op op, int32_t sysi, const void *x, 
         hipLaunchKernelGGL(k_coarse, dim3(1), dim3(kBlock), sizeof(double) * H->dmax, st, H->d_sys, H->d_ins + inst, (const double *)H->hs,
                            (const double *)nullptr, (double *)nullptr, H->cv, (const GState *)nullptr);
         hipLaunchKernelGGL(k_xupdate<double>, dim3(nxc), dim3(kBlock), 0, st, H->d_sys, H->d_ins, wx, 3,
-                           (const double *)H->t64, (const double *)H->cv, H->y64, (double *)nullptr);
+                           (const double *)H->t64, (const double *)H->cv, H->y64, (double *)nullptr,
+                           (const double *)nullptr);
         HIPCHECK(hipMemcpyAsync(y, H->y64 + I.x_off, bx, hipMemcpyDeviceToDevice, st));
         break;
       }
@@ -1487,7 +1577,8 @@ smpm_status smpm_apply(smpm_handle *H, smpm_op op, int32_t sysi, const void *x, 
         hipLaunchKernelGGL(k_coarse, dim3(1), dim3(kBlock), sizeof(double) * H->dmax, st, H->d_sys, H->d_ins + inst, (const double *)H->hs,
                            (const double *)nullptr, (double *)nullptr, H->cv, (const GState *)nullptr);
         hipLaunchKernelGGL(k_xupdate<double>, dim3(nxc), dim3(kBlock), 0, st, H->d_sys, H->d_ins, wx, 4,
-                           (const double *)H->t64, (const double *)H->cv, H->z64, (double *)nullptr);
+                           (const double *)H->t64, (const double *)H->cv, H->z64, (double *)nullptr,
+                           (const double *)nullptr);
         HIPCHECK(hipMemcpyAsync(y, H->z64 + I.x_off, bx, hipMemcpyDeviceToDevice, st));
         break;
       }
