@@ -502,6 +502,7 @@ void upload(smpm_handle *H, hipStream_t st) {
     std::vector<GWork> ga[3], go[3];
     std::vector<GVec> gv;
     // items of one stored block over its windows, kGemmVecs windows each
+    // (half as many for the fused S M^-1 blocks)
     auto emit = [&](int si, int op, int id, const std::vector<int2> &vecs, std::vector<GWork> &out) {
       const System &s = H->sys[si];
       const SysDev &d = H->h_sys[si];
@@ -521,7 +522,10 @@ void upload(smpm_handle *H, hipStream_t st) {
         w.n = s.n;
         w.N = N; w.Np = d.Np; w.K = K; w.kS = s.kS; w.ident = op == 0 ? 1 : 0;
         w.vstart = (int)gv.size();
-        w.vcount = (int)std::min<size_t>(kGemmVecs, vecs.size() - a);
+        // S M^-1 blocks are up to 4x wider than S blocks: items of 16
+        // windows give twice the workgroups at half the columns each.
+        const size_t width = op == 2 ? kGemmVecs / 2 : kGemmVecs;
+        w.vcount = (int)std::min<size_t>(width, vecs.size() - a);
         for (int q = 0; q < w.vcount; ++q) {
           const int inst = vecs[a + q].x, h = vecs[a + q].y;
           const InstDev &I = H->h_ins[inst];
