@@ -614,14 +614,22 @@ __global__ __launch_bounds__(kBlock) void k_pcorr_dot(
   __shared__ double ws[kChunk];
   const int2 wk = work[blockIdx.x];
   const int i = wk.x, ch = wk.y;
-  if (!gs[i].active) return;
-  const InstDev I = ins[i];
+  const InstDev I = ins[i];   // loaded with the state, not after its test
+  const GState G = gs[i];
+  if (!G.active) return;
   const SysDev &S = sys[I.sys];
   const int N = S.N;
   const int64_t kS = S.kS;
-  const int j = gs[i].iter;
+  const int j = G.iter;
   const int64_t e0 = (int64_t)ch * kChunk;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  // y of this chunk, in flight during the coarse solve
+  double yv[kChunk / kBlock];
+#pragma unroll
+  for (int q = 0; q < kChunk / kBlock; ++q) {
+    const int64_t e = e0 + threadIdx.x + q * kBlock;
+    yv[q] = e < kS ? (double)ybase[I.x_off + e] : 0.0;
+  }
   int c0 = 0;
   if (useP) {
     const int d = S.d, zm = S.zm, nif = S.mx - 1;
@@ -657,7 +665,7 @@ __global__ __launch_bounds__(kBlock) void k_pcorr_dot(
     const int64_t e = e0 + threadIdx.x + q * kBlock;
     double w = 0.0;
     if (e < kS) {
-      w = (double)ybase[I.x_off + e];
+      w = yv[q];
       if (useP) {
         const int h = (int)(e / N), row = (int)(e - (int64_t)h * N);
         w -= sz_c(S, h, row, c_s, c0);
@@ -706,46 +714,66 @@ __device__ inline void reduce_coef(const InstDev &I, const double *__restrict__ 
 // the per-chunk partials (or from the segment sums r1, r2, rn), the earlier
 // rotations applied to it, a new rotation, the residual estimate |g_{j+1}|,
 // the next basis scale and the GMRES state (written to every instance of the
-// segment).  Called by a whole workgroup; h has maxit + 2 entries.
+// segment).  Called by a whole workgroup; sh holds 3 maxit + 2 doubles: h,
+// then the earlier rotations, read into LDS while the sums are formed.
 __device__ inline void givens_step(const InstDev &I, int i, int j, const double *__restrict__ part1,
                                    const double *__restrict__ part2, const double *__restrict__ partn,
                                    const double *__restrict__ r1, const double *__restrict__ r2,
                                    const double *__restrict__ rn, double *__restrict__ scale, double *__restrict__ R,
                                    double *__restrict__ cs, double *__restrict__ sn, double *__restrict__ g,
-                                   GState *__restrict__ gs, int maxit, double tol, double *h, double *lds4) {
+                                   GState *__restrict__ gs, int maxit, double tol, double *sh, double *lds4) {
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  double *h = sh, *cl = sh + maxit + 2, *sl = cl + maxit;
+  for (int t = threadIdx.x; t < j; t += kBlock) {
+    cl[t] = cs[I.st_off + t];
+    sl[t] = sn[I.st_off + t];
+  }
   double nn = 0.0;
   if (r1) {   // segment sums reduced by k_seg_reduce
     for (int t = threadIdx.x; t <= j; t += kBlock) h[t] = scale[I.st_off + t] * (r1[I.st_off + t] + r2[I.st_off + t]);
     nn = rn[I.st_off];
   } else {
-    for (int t = wave; t <= j; t += 4) {
+    for (int t = wave; t <= j; t += 8) {   // two columns per reduction pass
+      const int t2 = t + 4;
+      const bool two = t2 <= j;
       const double *p1 = part1 + I.part_off + (int64_t)t * I.nchunk_x;
       const double *p2 = part2 + I.part_off + (int64_t)t * I.nchunk_x;
-      double a = 0.0, b = 0.0;
-      for (int c = lane; c < I.nchunk_x; c += 64) { a += p1[c]; b += p2[c]; }
+      const double *q1 = part1 + I.part_off + (int64_t)(two ? t2 : t) * I.nchunk_x;
+      const double *q2 = part2 + I.part_off + (int64_t)(two ? t2 : t) * I.nchunk_x;
+      double a = 0.0, b = 0.0, c = 0.0, d = 0.0;
+      for (int k = lane; k < I.nchunk_x; k += 64) {
+        a += p1[k];
+        b += p2[k];
+        c += q1[k];
+        d += q2[k];
+      }
       a = wave_sum(a);
       b = wave_sum(b);
-      if (lane == 0) h[t] = scale[I.st_off + t] * (a + b);
+      c = wave_sum(c);
+      d = wave_sum(d);
+      if (lane == 0) {
+        h[t] = scale[I.st_off + t] * (a + b);
+        if (two) h[t2] = scale[I.st_off + t2] * (c + d);
+      }
     }
-    for (int c = threadIdx.x; c < I.nchunk_x; c += kBlock) nn += partn[I.part_off + c];
+    for (int k = threadIdx.x; k < I.nchunk_x; k += kBlock) nn += partn[I.part_off + k];
     nn = block_sum(nn, lds4);
   }
   __syncthreads();
   if (threadIdx.x == 0) {
     const double beta = sqrt(nn);
     h[j + 1] = beta;
-    double *csI = cs + I.st_off, *snI = sn + I.st_off, *gI = g + I.st_off;
+    double *gI = g + I.st_off;
     for (int t = 0; t < j; ++t) {
-      const double a = csI[t] * h[t] + snI[t] * h[t + 1];
-      h[t + 1] = -snI[t] * h[t] + csI[t] * h[t + 1];
+      const double a = cl[t] * h[t] + sl[t] * h[t + 1];
+      h[t + 1] = -sl[t] * h[t] + cl[t] * h[t + 1];
       h[t] = a;
     }
     const double den = hypot(h[j], h[j + 1]);
     const double c = den != 0.0 ? h[j] / den : 1.0;
     const double s = den != 0.0 ? h[j + 1] / den : 0.0;
-    csI[j] = c;
-    snI[j] = s;
+    cs[I.st_off + j] = c;
+    sn[I.st_off + j] = s;
     h[j] = den;
     gI[j + 1] = -s * gI[j];
     gI[j] = c * gI[j];
@@ -790,11 +818,12 @@ __global__ __launch_bounds__(kBlock) void k_axpy_dot(
   __shared__ double red[4];
   const int2 wk = work[blockIdx.x];
   const int i = wk.x, ch = wk.y;
-  if (!gs[i].active) return;
-  const InstDev I = ins[i];
+  const InstDev I = ins[i];   // loaded with the state, not after its test
+  const GState G = gs[i];
+  if (!G.active) return;
   const SysDev &S = sys[I.sys];
   const int64_t kS = S.kS;
-  const int j = gs[i].iter;
+  const int j = G.iter;
   if (coefr) {   // segment sums reduced by k_seg_reduce
     for (int t = threadIdx.x; t <= j; t += kBlock) {
       const double s = scale[I.st_off + t];
@@ -874,32 +903,47 @@ __global__ __launch_bounds__(kBlock) void k_givens(
     double *__restrict__ cs, double *__restrict__ sn, double *__restrict__ g, GState *__restrict__ gs,
     int maxit, double tol, const double *__restrict__ r1, const double *__restrict__ r2,
     const double *__restrict__ rn) {
-  extern __shared__ double h[];   // maxit + 2
+  extern __shared__ double sh[];   // 3 maxit + 2
   __shared__ double lds4[4];
   const int i = blockIdx.x;
   const InstDev I = ins[i];
+  const GState G = gs[i];
   if (I.seg_first != i) return;   // a segment's Givens step runs once, on its leader
-  if (!gs[i].active) return;
-  givens_step(I, i, gs[i].iter, part1, part2, partn, r1, r2, rn, scale, R, cs, sn, g, gs, maxit, tol, h, lds4);
+  if (!G.active) return;
+  givens_step(I, i, G.iter, part1, part2, partn, r1, r2, rn, scale, R, cs, sn, g, gs, maxit, tol, sh, lds4);
 }
 
 // Least squares R y = g (upper triangular, m = iter columns); writes
-// ycoef[t] = y_t s_t for the basis combination.
+// ycoef[t] = y_t s_t for the basis combination.  A triangle of at most
+// kTriLds entries is first read into LDS in one parallel pass (column c
+// packed at c (c + 1) / 2), so the column sweep waits on no global load.
+constexpr int kTriLds = 4096;
 __global__ __launch_bounds__(kBlock) void k_backsolve(const InstDev *__restrict__ ins,
                                                       const double *__restrict__ R,
                                                       const double *__restrict__ g,
                                                       const double *__restrict__ scale,
                                                       double *__restrict__ ycoef,
                                                       const GState *__restrict__ gs, int maxit) {
-  extern __shared__ double rhs[];
+  extern __shared__ double rhs[];   // maxit, then the packed triangle
+  double *tri = rhs + maxit;
   const int i = blockIdx.x;
   const InstDev I = ins[i];
   if (I.seg_first != i) return;   // one least-squares solve per segment
   const int m = gs[i].iter;
+  const int ntri = m * (m + 1) / 2;
+  const bool staged = ntri <= kTriLds;
   for (int t = threadIdx.x; t < m; t += kBlock) rhs[t] = g[I.st_off + t];
+  if (staged) {
+    for (int q = threadIdx.x; q < ntri; q += kBlock) {
+      int c = (int)((sqrt(8.0 * q + 1.0) - 1.0) * 0.5);
+      if (c * (c + 1) / 2 > q) --c;                 // guard the rounding of the root
+      if ((c + 1) * (c + 2) / 2 <= q) ++c;
+      tri[q] = R[I.rr_off + (int64_t)c * maxit + (q - c * (c + 1) / 2)];
+    }
+  }
   __syncthreads();
   for (int c = m - 1; c >= 0; --c) {
-    const double *Rc = R + I.rr_off + (int64_t)c * maxit;
+    const double *Rc = staged ? tri + c * (c + 1) / 2 : R + I.rr_off + (int64_t)c * maxit;
     const double yc = rhs[c] / Rc[c];
     __syncthreads();
     for (int t = threadIdx.x; t < c; t += kBlock) rhs[t] -= Rc[t] * yc;

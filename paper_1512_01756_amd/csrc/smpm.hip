@@ -1012,7 +1012,7 @@ struct Inner {
                        (const double *)H->part2, (double *)nullptr, H->partn, (const double *)H->scale, (const GState *)H->gs,
                        seg ? (const double *)H->sr2 : nullptr);
     if (seg) seg_reduce(H->partn, H->srn, 1);
-    hipLaunchKernelGGL(k_givens, dim3(H->ninst), dim3(kBlock), sizeof(double) * (maxit + 2), st, H->d_ins,
+    hipLaunchKernelGGL(k_givens, dim3(H->ninst), dim3(kBlock), sizeof(double) * (3 * maxit + 2), st, H->d_ins,
                        (const double *)H->part1, (const double *)H->part2, (const double *)H->partn, H->scale, H->Rm,
                        H->cs, H->sn, H->g, H->gs, maxit, tol(H), seg ? (const double *)H->sr1 : nullptr,
                        seg ? (const double *)H->sr2 : nullptr, seg ? (const double *)H->srn : nullptr);
@@ -1024,7 +1024,7 @@ struct Inner {
     const bool useP = H->method == SMPM_METHOD_DBJ;
     const int maxit = H->maxit;
     T *Vb = V(H), *zb = z(H), *yb = y(H), *tb = t(H);
-    hipLaunchKernelGGL(k_backsolve, dim3(H->ninst), dim3(kBlock), sizeof(double) * (maxit + 1), st, H->d_ins,
+    hipLaunchKernelGGL(k_backsolve, dim3(H->ninst), dim3(kBlock), sizeof(double) * (maxit + 1 + kTriLds), st, H->d_ins,
                        (const double *)H->Rm, (const double *)H->g, (const double *)H->scale, H->ycoef,
                        (const GState *)H->gs, maxit);
     hipLaunchKernelGGL((k_combine<T, T>), dim3(H->n_x), dim3(kBlock), 0, st, H->d_sys, H->d_ins, H->w_x, (const T *)Vb,
