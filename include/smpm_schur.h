@@ -96,6 +96,16 @@ typedef enum {
                                   the block-diagonal operator of Sec. 5.2 / Alg. 3,
                                   stopping on the norm of the stacked residual;
                                   DBJ only (else EINVAL) */
+#define SMPM_FLAG_HOST_SETUP 8 /* run every setup step on the host threads, also
+                                  on a GPU handle (by default the large dense
+                                  steps of Sec. 2.4 / 3.2 -- the u_S elimination,
+                                  block-Jacobi and coarse inverses -- run on the
+                                  device through rocSOLVER / rocBLAS) */
+#define SMPM_FLAG_DEVICE_SETUP 16 /* take the device path for those steps whatever
+                                  their size (default: from 2e10 flops of work per
+                                  host thread on: the sequential u_S elimination
+                                  of large grids, a large coarse inverse);
+                                  ignored with HOST_ONLY or HOST_SETUP */
 
 typedef struct {
   int32_t mx, mz;      /* elements in x (>= 2) and z (>= 1) */
@@ -159,6 +169,9 @@ typedef struct {
                               block per half (FP64, FP32, FP16 storage): chosen at
                               setup when faster than M^-1 then S; grids whose strips
                               share blocks only */
+  int32_t setup_device;    /* setup steps of this system that ran on the device
+                              (rocSOLVER / rocBLAS): 1 the u_S elimination, 2 the
+                              block-Jacobi inverses, 4 the coarse inverse */
 } smpm_info;
 
 typedef struct smpm_handle smpm_handle;

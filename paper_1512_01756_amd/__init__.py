@@ -22,6 +22,9 @@ METHOD_DBJ, METHOD_BJ, METHOD_SCHUR, METHOD_2LAS = 0, 1, 2, 3
 FLAG_HOST_ONLY = 1
 FLAG_NO_TUNE = 2
 FLAG_ONE_KRYLOV = 4
+FLAG_HOST_SETUP = 8
+FLAG_DEVICE_SETUP = 16
+_SETUP_FLAGS = {"auto": 0, "host": FLAG_HOST_SETUP, "device": FLAG_DEVICE_SETUP}
 OP_SCHUR, OP_BJINV, OP_DEFLATE_P, OP_DEFLATE_Q, OP_AINV, OP_B, OP_SCHUR_RHS = range(7)
 (TABLE_SCHUR_DENSE, TABLE_BJINV_DENSE, TABLE_COARSE_C, TABLE_U_S, TABLE_U_L, TABLE_U_C, TABLE_SZ,
  TABLE_SMINV_DENSE) = range(8)
@@ -65,7 +68,7 @@ class Info(ctypes.Structure):
                 ("x_offset", ctypes.c_int64), ("unique_W", ctypes.c_int32), ("unique_M", ctypes.c_int32),
                 ("bytes_W64", ctypes.c_int64), ("bytes_M64", ctypes.c_int64),
                 ("gemm_sched", ctypes.c_int32 * 4), ("elem_sched", ctypes.c_int32 * 6),
-                ("fused_op", ctypes.c_int32 * 3)]
+                ("fused_op", ctypes.c_int32 * 3), ("setup_device", ctypes.c_int32)]
 
     def as_dict(self):
         out = {}
@@ -140,12 +143,14 @@ class Solver:
     """One handle: one grid with several wavenumbers (`kwaves`), a batch of
     independent problems (`grids` list with one wavenumber each), or a 3-D
     problem periodic in y (`fourier=(m_y, l_y)`: modes k_m = 2 pi m / l_y,
-    m = 0 .. m_y/2, Re and Im as two right-hand sides)."""
+    m = 0 .. m_y/2, Re and Im as two right-hand sides).  setup: where the
+    large dense setup steps run on a GPU handle -- "auto" (the device from a
+    few GFLOP of work on), "host" or "device" (always)."""
 
     def __init__(self, xb=None, zb=None, order=None, kwaves=(0.0,), grids=None, tau=0.0, tol=1e-10,
                  max_iter=300, nrhs=1, precision=FP64, method=METHOD_DBJ, inner_tol=0.0, max_sweeps=0,
                  host_only=False, tune=True, fourier=None, one_krylov=False, zlabel=0, load_path=None,
-                 stream=None):
+                 stream=None, setup="auto"):
         if fourier is not None:
             nrhs = 2
         lib = load()
@@ -153,7 +158,7 @@ class Solver:
         self.host_only = host_only
         opts = Opts(tau, tol, max_iter, nrhs, precision, method, inner_tol, max_sweeps,
                     (FLAG_HOST_ONLY if host_only else 0) | (0 if tune else FLAG_NO_TUNE)
-                    | (FLAG_ONE_KRYLOV if one_krylov else 0), zlabel)
+                    | (FLAG_ONE_KRYLOV if one_krylov else 0) | _SETUP_FLAGS[setup], zlabel)
         self.opts = opts
         self._keep = []
         h = ctypes.c_void_p()

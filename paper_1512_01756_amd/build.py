@@ -12,7 +12,7 @@ LIB = os.path.join(HERE, "libsmpm_schur.so")
 BUILD = os.path.join(HERE, "_build")
 
 HOST_SOURCES = ["dense.cpp", "setup_host.cpp", "persist.cpp"]
-DEVICE_SOURCES = ["smpm.hip"]
+DEVICE_SOURCES = ["smpm.hip", "setup_dev.hip"]
 ARCH = os.environ.get("SMPM_OFFLOAD_ARCH", "gfx950")
 
 
@@ -46,7 +46,8 @@ def build(verbose=True):
         _run([hipcc, *dev_flags, "-c", os.path.join(CSRC, src), "-o", obj])
         objs.append(obj)
     tmp = LIB + ".tmp"
-    _run([hipcc, "-shared", "-fPIC", f"--offload-arch={ARCH}", "-o", tmp, *objs, "-lpthread"])
+    _run([hipcc, "-shared", "-fPIC", f"--offload-arch={ARCH}", "-o", tmp, *objs, "-lrocsolver", "-lrocblas",
+          "-lpthread"])
     os.replace(tmp, LIB)
     return LIB
 

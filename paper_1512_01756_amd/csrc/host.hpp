@@ -89,14 +89,40 @@ struct System {
   std::vector<double> Gc;                // coarse operator C^dagger (I - u_C u_C^T), d x d row-major
   // Null vectors (k = 0 only).
   std::vector<double> uS, uL, uC;
+  // Setup steps that ran on the device back end: 1 the u_S elimination,
+  // 2 the block-Jacobi inverses, 4 the coarse inverse.
+  int dev_steps = 0;
   // Offsets into batched arrays.
   int64_t f_off = 0, g_off = 0, x_off = 0;
+};
+
+// Optional device back end of the heavy dense setup steps; an empty member
+// means the host code runs that step.
+struct DenseBackend {
+  // Take the device path for every step below whatever its size (else from
+  // 2e10 flops of work per host thread on, where it pays for the transfers
+  // and the library start-up).
+  bool always = false;
+  // In-place inverses of `count` n x n row-major matrices; throws
+  // std::domain_error if one is singular.
+  std::function<void(int n, int count, double *const *mats)> invert;
+  // Block-tridiagonal T over d interfaces (blocks M = 2N square, row-major):
+  // diagonal blocks Td[i] (M x M), sub-diagonal Lo[i] (i >= 1: the N x N block
+  // at rows 0..N of i, columns 0..N of i - 1), super-diagonal Up[i]
+  // (i + 1 < d: the N x N block at rows N..2N of i, columns N..2N of i + 1).
+  // tri_factor eliminates it and returns an opaque factorization (throws
+  // std::runtime_error on a singular block); tri_solve overwrites v (d M)
+  // with T^-1 v; tri_free releases the factorization.
+  std::function<void *(int d, int N, const double *Td, const double *Lo, const double *Up)> tri_factor;
+  std::function<void(void *fact, double *v)> tri_solve;
+  std::function<void(void *fact)> tri_free;
 };
 
 struct SetupOptions {
   double tau = 0.0;
   int threads = 0;
   int zlabel = 0;   // deflation space: 0 one column per interface, 1 per element segment
+  const DenseBackend *dense = nullptr;
 };
 
 // Build every host table of one system.  Throws std::runtime_error with a

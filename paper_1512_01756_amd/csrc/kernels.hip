@@ -1680,6 +1680,13 @@ __global__ __launch_bounds__(kBlock) void k_fill(double *__restrict__ p, int64_t
   if (i < n) p[i] = v;
 }
 
+// out[0, n) = (float)in[0, n): the FP32 operator tables from the uploaded
+// FP64 ones (same padded layout), at setup.
+__global__ __launch_bounds__(kBlock) void k_to_f32(const double *__restrict__ in, float *__restrict__ out, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i < n) out[i] = (float)in[i];
+}
+
 // r <- r - u_S (u_S . r) using a reduced scalar (refinement residual).
 __global__ __launch_bounds__(kBlock) void k_proj_x_scalar(const SysDev *__restrict__ sys,
                                                           const InstDev *__restrict__ ins,

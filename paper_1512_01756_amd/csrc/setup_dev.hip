@@ -1,0 +1,216 @@
+// Device back end of the heavy dense setup steps (Sec. 2.4 and 3.2 tables):
+// batched in-place inverses (block-Jacobi blocks, the coarse matrix) and the
+// block-tridiagonal elimination and solves of the u_S inverse iteration, on
+// rocSOLVER / rocBLAS.  The host setup calls it through DenseBackend; every
+// input and result stays in the host tables' row-major layout, so the two
+// paths are interchangeable step by step.
+#include <hip/hip_runtime.h>
+#include <rocblas/rocblas.h>
+#include <rocsolver/rocsolver.h>
+
+#include <algorithm>
+#include <cstring>
+#include <mutex>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "host.hpp"
+#include "setup_dev.hpp"
+
+namespace smpm {
+
+namespace {
+
+void hcheck(hipError_t e, const char *what) {
+  if (e != hipSuccess) throw std::runtime_error(std::string(what) + ": " + hipGetErrorString(e));
+}
+
+void rcheck(rocblas_status s, const char *what) {
+  if (s != rocblas_status_success)
+    throw std::runtime_error(std::string(what) + ": rocBLAS status " + std::to_string((int)s));
+}
+
+template <typename T>
+struct DBuf {
+  T *p = nullptr;
+  explicit DBuf(size_t n) { hcheck(hipMalloc((void **)&p, sizeof(T) * std::max<size_t>(n, 1)), "hipMalloc"); }
+  ~DBuf() {
+    if (p) (void)hipFree(p);
+  }
+  DBuf(const DBuf &) = delete;
+  DBuf &operator=(const DBuf &) = delete;
+};
+
+// Factors of the block-tridiagonal T, all column-major on the device:
+// T~_i (M x M, LU with pivots), Lo_i (N x N), X_i = T~_i^-1 T[i][i+1]
+// (the M x N nonzero columns).
+struct TriFact {
+  int d, N, M;
+  DBuf<double> T, Lo, X, v, tmp;
+  DBuf<rocblas_int> ipiv, info;
+  TriFact(int d_, int N_)
+      : d(d_), N(N_), M(2 * N_), T((size_t)d_ * 4 * N_ * N_), Lo((size_t)d_ * N_ * N_),
+        X((size_t)d_ * 2 * N_ * N_), v((size_t)d_ * 2 * N_), tmp(2 * N_), ipiv((size_t)d_ * 2 * N_), info(d_) {}
+};
+
+}  // namespace
+
+struct DeviceDense {
+  std::mutex mu;
+  hipStream_t st = nullptr;
+  rocblas_handle h = nullptr;
+  DenseBackend be;
+
+  // The stream and the rocBLAS handle are made on first use, so setups that
+  // never reach the device back end do not pay for them.
+  void ensure() {
+    if (h) return;
+    hcheck(hipStreamCreate(&st), "hipStreamCreate");
+    rcheck(rocblas_create_handle(&h), "rocblas_create_handle");
+    rcheck(rocblas_set_stream(h, st), "rocblas_set_stream");
+  }
+
+  ~DeviceDense() {
+    if (h) (void)rocblas_destroy_handle(h);
+    if (st) (void)hipStreamDestroy(st);
+  }
+
+  // Row-major A is column-major A^T, and inv(A^T) = inv(A)^T: inverting the
+  // column-major view in place leaves inv(A) in the row-major layout.
+  void invert(int n, int count, double *const *mats) {
+    std::lock_guard<std::mutex> lk(mu);
+    ensure();
+    const size_t nn = (size_t)n * n;
+    const int chunk = (int)std::max<int64_t>(1, std::min<int64_t>(count, (int64_t)(1ull << 30) / (int64_t)(nn * 8)));
+    DBuf<double> A(nn * chunk);
+    DBuf<rocblas_int> ipiv((size_t)n * chunk), info(chunk);
+    std::vector<rocblas_int> hinfo(chunk);
+    for (int c0 = 0; c0 < count; c0 += chunk) {
+      const int cn = std::min(chunk, count - c0);
+      for (int q = 0; q < cn; ++q)
+        hcheck(hipMemcpyAsync(A.p + q * nn, mats[c0 + q], nn * 8, hipMemcpyHostToDevice, st), "upload");
+      rcheck(rocsolver_dgetrf_strided_batched(h, n, n, A.p, n, (rocblas_stride)nn, ipiv.p, n, info.p, cn), "getrf");
+      hcheck(hipMemcpyAsync(hinfo.data(), info.p, sizeof(rocblas_int) * cn, hipMemcpyDeviceToHost, st), "info");
+      hcheck(hipStreamSynchronize(st), "getrf");
+      for (int q = 0; q < cn; ++q)
+        if (hinfo[q] != 0) throw std::domain_error("singular matrix in the setup");
+      rcheck(rocsolver_dgetri_strided_batched(h, n, A.p, n, (rocblas_stride)nn, ipiv.p, n, info.p, cn), "getri");
+      hcheck(hipMemcpyAsync(hinfo.data(), info.p, sizeof(rocblas_int) * cn, hipMemcpyDeviceToHost, st), "info");
+      for (int q = 0; q < cn; ++q)
+        hcheck(hipMemcpyAsync(mats[c0 + q], A.p + q * nn, nn * 8, hipMemcpyDeviceToHost, st), "download");
+      hcheck(hipStreamSynchronize(st), "getri");
+      for (int q = 0; q < cn; ++q)
+        if (hinfo[q] != 0) throw std::domain_error("singular matrix in the setup");
+    }
+  }
+
+  // Block elimination T~_0 = T_0, T~_i = T_i - Lo_i X_{i-1}[0..N], X_i =
+  // T~_i^-1 [0; Up_i], in order over the interfaces (each step needs the
+  // previous one); the d steps are enqueued back to back on one stream.
+  void *tri_factor(int d, int N, const double *Td, const double *Lo, const double *Up) {
+    std::lock_guard<std::mutex> lk(mu);
+    ensure();
+    const int M = 2 * N;
+    TriFact *f = new TriFact(d, N);
+    try {
+      std::vector<double> buf((size_t)M * M), bl((size_t)N * N), bx((size_t)M * N);
+      for (int i = 0; i < d; ++i) {
+        const double *t = Td + (size_t)i * M * M;
+        for (int r = 0; r < M; ++r)
+          for (int c = 0; c < M; ++c) buf[(size_t)c * M + r] = t[(size_t)r * M + c];
+        hcheck(hipMemcpy(f->T.p + (size_t)i * M * M, buf.data(), sizeof(double) * M * M, hipMemcpyHostToDevice),
+               "upload T");
+        const double *l = Lo + (size_t)i * N * N;
+        for (int r = 0; r < N; ++r)
+          for (int c = 0; c < N; ++c) bl[(size_t)c * N + r] = l[(size_t)r * N + c];
+        hcheck(hipMemcpy(f->Lo.p + (size_t)i * N * N, bl.data(), sizeof(double) * N * N, hipMemcpyHostToDevice),
+               "upload Lo");
+        std::fill(bx.begin(), bx.end(), 0.0);
+        if (i + 1 < d) {
+          const double *u = Up + (size_t)i * N * N;
+          for (int r = 0; r < N; ++r)
+            for (int c = 0; c < N; ++c) bx[(size_t)c * M + N + r] = u[(size_t)r * N + c];
+        }
+        hcheck(hipMemcpy(f->X.p + (size_t)i * M * N, bx.data(), sizeof(double) * M * N, hipMemcpyHostToDevice),
+               "upload X");
+      }
+      const double one = 1.0, minus = -1.0;
+      for (int i = 0; i < d; ++i) {
+        double *T = f->T.p + (size_t)i * M * M;
+        if (i > 0)
+          rcheck(rocblas_dgemm(h, rocblas_operation_none, rocblas_operation_none, N, N, N, &minus,
+                               f->Lo.p + (size_t)i * N * N, N, f->X.p + (size_t)(i - 1) * M * N, M, &one, T + (size_t)N * M,
+                               M),
+                 "gemm");
+        rcheck(rocsolver_dgetrf(h, M, M, T, M, f->ipiv.p + (size_t)i * M, f->info.p + i), "getrf");
+        if (i + 1 < d)
+          rcheck(rocsolver_dgetrs(h, rocblas_operation_none, M, N, T, M, f->ipiv.p + (size_t)i * M,
+                                  f->X.p + (size_t)i * M * N, M),
+                 "getrs");
+      }
+      std::vector<rocblas_int> hinfo(d);
+      hcheck(hipMemcpyAsync(hinfo.data(), f->info.p, sizeof(rocblas_int) * d, hipMemcpyDeviceToHost, st), "info");
+      hcheck(hipStreamSynchronize(st), "elimination");
+      for (int i = 0; i < d; ++i)
+        if (hinfo[i] != 0) throw std::runtime_error("singular block in the inverse iteration for u_S");
+    } catch (...) {
+      delete f;
+      throw;
+    }
+    return f;
+  }
+
+  // v <- T^-1 v: forward y_i = v_i - Lo_i T~_{i-1}^-1 y_{i-1} (first N rows),
+  // backward x_i = T~_i^-1 y_i - X_i x_{i+1}[N..2N].
+  void tri_solve(void *fp, double *v) {
+    std::lock_guard<std::mutex> lk(mu);
+    TriFact *f = static_cast<TriFact *>(fp);
+    const int d = f->d, N = f->N, M = f->M;
+    const double one = 1.0, minus = -1.0;
+    double *dv = f->v.p;
+    hcheck(hipMemcpy(dv, v, sizeof(double) * d * M, hipMemcpyHostToDevice), "upload v");
+    for (int i = 1; i < d; ++i) {
+      hcheck(hipMemcpyAsync(f->tmp.p, dv + (size_t)(i - 1) * M, sizeof(double) * M, hipMemcpyDeviceToDevice, st),
+             "copy");
+      rcheck(rocsolver_dgetrs(h, rocblas_operation_none, M, 1, f->T.p + (size_t)(i - 1) * M * M, M,
+                              f->ipiv.p + (size_t)(i - 1) * M, f->tmp.p, M),
+             "getrs");
+      rcheck(rocblas_dgemv(h, rocblas_operation_none, N, N, &minus, f->Lo.p + (size_t)i * N * N, N, f->tmp.p, 1, &one,
+                           dv + (size_t)i * M, 1),
+             "gemv");
+    }
+    for (int i = d - 1; i >= 0; --i) {
+      rcheck(rocsolver_dgetrs(h, rocblas_operation_none, M, 1, f->T.p + (size_t)i * M * M, M, f->ipiv.p + (size_t)i * M,
+                              dv + (size_t)i * M, M),
+             "getrs");
+      if (i + 1 < d)
+        rcheck(rocblas_dgemv(h, rocblas_operation_none, M, N, &minus, f->X.p + (size_t)i * M * N, M,
+                             dv + (size_t)(i + 1) * M + N, 1, &one, dv + (size_t)i * M, 1),
+               "gemv");
+    }
+    hcheck(hipMemcpyAsync(v, dv, sizeof(double) * d * M, hipMemcpyDeviceToHost, st), "download v");
+    hcheck(hipStreamSynchronize(st), "solve");
+  }
+};
+
+DeviceDense *device_dense_create(bool always) {
+  DeviceDense *dd = new DeviceDense();
+  dd->be.always = always;
+  dd->be.invert = [dd](int n, int count, double *const *mats) { dd->invert(n, count, mats); };
+  dd->be.tri_factor = [dd](int d, int N, const double *Td, const double *Lo, const double *Up) {
+    return dd->tri_factor(d, N, Td, Lo, Up);
+  };
+  dd->be.tri_solve = [dd](void *f, double *v) { dd->tri_solve(f, v); };
+  dd->be.tri_free = [dd](void *f) {
+    std::lock_guard<std::mutex> lk(dd->mu);
+    delete static_cast<TriFact *>(f);
+  };
+  return dd;
+}
+
+void device_dense_destroy(DeviceDense *dd) { delete dd; }
+
+const DenseBackend *device_dense_backend(const DeviceDense *dd) { return dd ? &dd->be : nullptr; }
+
+}  // namespace smpm

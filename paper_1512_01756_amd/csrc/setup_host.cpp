@@ -400,11 +400,34 @@ static double norm2(const std::vector<double> &v) {
   return std::sqrt(s);
 }
 
+// Work per host thread from which the device back end is used: below it the
+// transfers and the library start-up cost more than the host threads take
+// (measured on the c2 and c3 grids).
+constexpr double kDeviceWork = 2e10;
+
+// In-place inverses of row-major n x n matrices: through the device back end
+// when one is given and the work per host thread is large (2 n^3 per matrix;
+// the host inverts matrices on separate threads), else on the host threads.
+// Returns true when the device ran them.
+static bool invert_many(const SetupOptions &opt, int n, const std::vector<double *> &mats) {
+  if (mats.empty()) return false;
+  const int threads = std::max(1, std::min<int>((int)mats.size(), opt.threads > 0 ? opt.threads : default_threads()));
+  const double per_thread = 2.0 * (double)n * n * n * (double)mats.size() / threads;
+  if (opt.dense && opt.dense->invert && (per_thread >= kDeviceWork || opt.dense->always)) {
+    opt.dense->invert(n, (int)mats.size(), mats.data());
+    return true;
+  }
+  parallel_for((int)mats.size(), opt.threads, [&](int q) {
+    if (!invert(n, mats[q], n)) throw std::domain_error("singular matrix in the setup");
+  });
+  return false;
+}
+
 // Left null vector of S (k = 0) by shifted inverse iteration on S^T - sigma I
 // (Sec. 2.4).  S is block tridiagonal over interfaces (2N x 2N blocks); the
-// shifted transpose is factored by block elimination, the diagonal blocks
-// with partial pivoting.
-static void left_null_schur(System &s) {
+// shifted transpose T is factored by block elimination, the diagonal blocks
+// with partial pivoting, on the host or through opt.dense.
+static void left_null_schur(System &s, const SetupOptions &opt) {
   const int N = s.N, M = 2 * N, d = s.mx - 1;   // d: interfaces
   // Interface blocks of S: Sd[i] (M x M), Su[i] = S[i][i+1] (upper-left N x N
   // of rows of half 2i, cols of half 2i+2), Sl[i] = S[i][i-1] (rows of half
@@ -420,13 +443,12 @@ static void left_null_schur(System &s) {
       snorm = std::max(snorm, rs);
     }
   const double sigma = 1e-10 * snorm;
-  // T = S^T - sigma I; blocks: T[i][i] = Sd[i]^T - sigma, T[i][i+1] = Sl[i+1]^T,
-  // T[i][i-1] = Su[i-1]^T.
-  std::vector<double> LU((size_t)d * M * M), X((size_t)d * M * N);
-  std::vector<int> piv((size_t)d * M);
+  // T = S^T - sigma I; blocks: Td[i] = Sd[i]^T - sigma, T[i][i+1] = Sl[i+1]^T
+  // (nonzero at rows N..2N, cols N..2N: Up[i]), T[i][i-1] = Su[i-1]^T (rows
+  // 0..N, cols 0..N: Lo[i]).
+  std::vector<double> Td((size_t)d * M * M, 0.0), Lo((size_t)d * N * N, 0.0), Up((size_t)d * N * N, 0.0);
   for (int i = 0; i < d; ++i) {
-    double *T = &LU[(size_t)i * M * M];
-    std::fill(T, T + (size_t)M * M, 0.0);
+    double *T = &Td[(size_t)i * M * M];
     // Sd[i] rows 0..N (half 2i): cols N..2N (half 2i+1) = W^_{2i} part 0.
     // rows N..2N (half 2i+1): cols 0..N (half 2i) = W^_{2i+1} part 1.
     for (int a = 0; a < M; ++a) T[(size_t)a * M + a] = 1.0 - sigma;
@@ -436,78 +458,99 @@ static void left_null_schur(System &s) {
         T[(size_t)(N + c) * M + r] += Wpart(2 * i, 0, r, c);
         T[(size_t)c * M + (N + r)] += Wpart(2 * i + 1, 1, r, c);
       }
-    if (i > 0) {
-      // T_i -= T[i][i-1] X_{i-1}, T[i][i-1] = Su[i-1]^T: Su[i-1] has rows of
-      // half 2i-2 (0..N) and cols of half 2i (0..N) = W^_{2i-2} part 1.
-      // X_{i-1} = T~_{i-1}^-1 T[i-1][i] has nonzero columns N..2N only.
-      const double *Xp = &X[(size_t)(i - 1) * M * N];
-      std::vector<double> SuT((size_t)N * N);
+    // Su[i-1] has rows of half 2i-2 and cols of half 2i = W^_{2i-2} part 1.
+    if (i > 0)
       for (int r = 0; r < N; ++r)
-        for (int c = 0; c < N; ++c) SuT[(size_t)c * N + r] = Wpart(2 * i - 2, 1, r, c);
-      // T[0..N][N..2N] -= SuT (N x N) * Xp[0..N][0..N]
-      gemm(N, N, N, -1.0, SuT.data(), N, Xp, N, 1.0, T + N, M);
-    }
-    if (!getrf(M, T, M, &piv[(size_t)i * M]))
-      throw std::runtime_error("singular block in the inverse iteration for u_S");
-    if (i + 1 < d) {
-      // X_i = T~_i^-1 T[i][i+1]; T[i][i+1] = Sl[i+1]^T: Sl[i+1] rows of half
-      // 2i+3 (N..2N of interface i+1), cols of half 2i+1 (N..2N of interface i)
-      // = W^_{2i+3} part 0.  Nonzero block at rows N..2N, cols N..2N.
-      std::vector<double> B((size_t)M * N, 0.0);   // only the N nonzero columns
+        for (int c = 0; c < N; ++c) Lo[(size_t)i * N * N + (size_t)c * N + r] = Wpart(2 * i - 2, 1, r, c);
+    // Sl[i+1] rows of half 2i+3, cols of half 2i+1 = W^_{2i+3} part 0.
+    if (i + 1 < d)
       for (int r = 0; r < N; ++r)
-        for (int c = 0; c < N; ++c) B[(size_t)(N + c) * N + r] = Wpart(2 * i + 3, 0, r, c);
-      getrs(M, N, T, M, &piv[(size_t)i * M], B.data(), N);
-      std::memcpy(&X[(size_t)i * M * N], B.data(), sizeof(double) * M * N);
-    }
+        for (int c = 0; c < N; ++c) Up[(size_t)i * N * N + (size_t)c * N + r] = Wpart(2 * i + 3, 0, r, c);
   }
-  auto solve = [&](std::vector<double> &v) {
-    // forward: y_i = v_i - T[i][i-1] T~_{i-1}^-1 y_{i-1}
-    std::vector<double> tmp(M);
-    for (int i = 1; i < d; ++i) {
-      std::memcpy(tmp.data(), &v[(size_t)(i - 1) * M], sizeof(double) * M);
-      getrs(M, 1, &LU[(size_t)(i - 1) * M * M], M, &piv[(size_t)(i - 1) * M], tmp.data(), 1);
-      for (int r = 0; r < N; ++r) {
-        double acc = 0.0;   // (Su[i-1]^T tmp[0..N])_r = sum_c Su[i-1][c][r] tmp[c]
-        for (int c = 0; c < N; ++c) acc += Wpart(2 * i - 2, 1, c, r) * tmp[c];
-        v[(size_t)i * M + r] -= acc;
+  std::function<void(std::vector<double> &)> solve;
+  void *dev_fact = nullptr;
+  std::vector<int> piv;
+  std::vector<double> X;
+  // the elimination is sequential over the interfaces: one host thread
+  const double elim = (double)d * (2.0 / 3.0 * M * M * M + 2.0 * M * M * N + 2.0 * N * N * N);
+  if (opt.dense && opt.dense->tri_factor && (elim >= kDeviceWork || opt.dense->always)) {
+    dev_fact = opt.dense->tri_factor(d, N, Td.data(), Lo.data(), Up.data());
+    s.dev_steps |= 1;
+    solve = [&](std::vector<double> &v) { opt.dense->tri_solve(dev_fact, v.data()); };
+  } else {
+    // Block elimination: T~_i = Td[i] - T[i][i-1] X_{i-1}, X_i = T~_i^-1 T[i][i+1]
+    // (X_i: the M x N nonzero columns N..2N).
+    piv.assign((size_t)d * M, 0);
+    X.assign((size_t)d * M * N, 0.0);
+    for (int i = 0; i < d; ++i) {
+      double *T = &Td[(size_t)i * M * M];
+      if (i > 0)   // T~[0..N][N..2N] -= Lo[i] X_{i-1}[0..N][0..N]
+        gemm(N, N, N, -1.0, &Lo[(size_t)i * N * N], N, &X[(size_t)(i - 1) * M * N], N, 1.0, T + N, M);
+      if (!getrf(M, T, M, &piv[(size_t)i * M]))
+        throw std::runtime_error("singular block in the inverse iteration for u_S");
+      if (i + 1 < d) {
+        double *B = &X[(size_t)i * M * N];
+        for (int r = 0; r < N; ++r)
+          std::memcpy(B + (size_t)(N + r) * N, &Up[(size_t)i * N * N + (size_t)r * N], sizeof(double) * N);
+        getrs(M, N, T, M, &piv[(size_t)i * M], B, N);
       }
     }
-    // backward: x_i = T~_i^-1 y_i - X_i x_{i+1}[N..2N]
-    for (int i = d - 1; i >= 0; --i) {
-      double *vi = &v[(size_t)i * M];
-      getrs(M, 1, &LU[(size_t)i * M * M], M, &piv[(size_t)i * M], vi, 1);
-      if (i + 1 < d) {
-        const double *xn = &v[(size_t)(i + 1) * M + N];
-        const double *Xi = &X[(size_t)i * M * N];
-        for (int r = 0; r < M; ++r) {
+    solve = [&](std::vector<double> &v) {
+      // forward: y_i = v_i - T[i][i-1] T~_{i-1}^-1 y_{i-1}
+      std::vector<double> tmp(M);
+      for (int i = 1; i < d; ++i) {
+        std::memcpy(tmp.data(), &v[(size_t)(i - 1) * M], sizeof(double) * M);
+        getrs(M, 1, &Td[(size_t)(i - 1) * M * M], M, &piv[(size_t)(i - 1) * M], tmp.data(), 1);
+        const double *L = &Lo[(size_t)i * N * N];
+        for (int r = 0; r < N; ++r) {
           double acc = 0.0;
-          for (int c = 0; c < N; ++c) acc += Xi[(size_t)r * N + c] * xn[c];
-          vi[r] -= acc;
+          for (int c = 0; c < N; ++c) acc += L[(size_t)r * N + c] * tmp[c];
+          v[(size_t)i * M + r] -= acc;
         }
       }
-    }
-  };
+      // backward: x_i = T~_i^-1 y_i - X_i x_{i+1}[N..2N]
+      for (int i = d - 1; i >= 0; --i) {
+        double *vi = &v[(size_t)i * M];
+        getrs(M, 1, &Td[(size_t)i * M * M], M, &piv[(size_t)i * M], vi, 1);
+        if (i + 1 < d) {
+          const double *xn = &v[(size_t)(i + 1) * M + N];
+          const double *Xi = &X[(size_t)i * M * N];
+          for (int r = 0; r < M; ++r) {
+            double acc = 0.0;
+            for (int c = 0; c < N; ++c) acc += Xi[(size_t)r * N + c] * xn[c];
+            vi[r] -= acc;
+          }
+        }
+      }
+    };
+  }
   std::vector<double> u(s.kS, 1.0 / std::sqrt((double)s.kS));
   std::vector<double> Stu(s.kS);
-  for (int it = 0; it < 6; ++it) {
-    solve(u);
-    const double nu = norm2(u);
-    if (!(nu > 0.0) || !std::isfinite(nu)) throw std::runtime_error("inverse iteration for u_S failed");
-    for (auto &a : u) a /= nu;
-    // residual ||S^T u|| / ||S||
-    std::fill(Stu.begin(), Stu.end(), 0.0);
-    for (int h = 0; h < s.nh; ++h)
-      for (int i = 0; i < N; ++i) {
-        const double ui = u[(size_t)h * N + i];
-        Stu[(size_t)h * N + i] += ui;
-        for (int c = 0; c < 2 * N; ++c) {
-          const int64_t idx = (int64_t)s.w_win[h] * N + c;
-          if (idx < 0 || idx >= s.kS) continue;
-          Stu[idx] += Wpart(h, 0, i, c) * ui;
+  try {
+    for (int it = 0; it < 6; ++it) {
+      solve(u);
+      const double nu = norm2(u);
+      if (!(nu > 0.0) || !std::isfinite(nu)) throw std::runtime_error("inverse iteration for u_S failed");
+      for (auto &a : u) a /= nu;
+      // residual ||S^T u|| / ||S||
+      std::fill(Stu.begin(), Stu.end(), 0.0);
+      for (int h = 0; h < s.nh; ++h)
+        for (int i = 0; i < N; ++i) {
+          const double ui = u[(size_t)h * N + i];
+          Stu[(size_t)h * N + i] += ui;
+          for (int c = 0; c < 2 * N; ++c) {
+            const int64_t idx = (int64_t)s.w_win[h] * N + c;
+            if (idx < 0 || idx >= s.kS) continue;
+            Stu[idx] += Wpart(h, 0, i, c) * ui;
+          }
         }
-      }
-    if (norm2(Stu) <= 1e-13 * snorm && it >= 1) break;
+      if (norm2(Stu) <= 1e-13 * snorm && it >= 1) break;
+    }
+  } catch (...) {
+    if (dev_fact) opt.dense->tri_free(dev_fact);
+    throw;
   }
+  if (dev_fact) opt.dense->tri_free(dev_fact);
   double sum = 0.0;
   for (double a : u) sum += a;
   if (sum < 0) for (auto &a : u) a = -a;
@@ -689,7 +732,7 @@ void build_system(System &s, int mx, int mz, int order, const double *xb, const 
   }
   const int nMu = (int)mfirst.size();
   std::vector<std::vector<double>> Minv(nMu);
-  parallel_for(nMu, opt.threads, [&](int u) {
+  parallel_for(nMu, opt.threads, [&](int u) {   // assemble; inverted below
     const int b = mfirst[u];
     const int h0 = 4 * b;
     const int nhb = std::min(4, s.nh - h0);
@@ -707,9 +750,21 @@ void build_system(System &s, int mx, int mz, int order, const double *xb, const 
           for (int c = 0; c < N; ++c) Mb[(size_t)(q * N + i) * K + lc * N + c] += W[(size_t)i * 2 * N + p * N + c];
       }
     }
-    if (!invert(K, Mb.data(), K)) throw std::domain_error("singular block-Jacobi block");
     Minv[u] = std::move(Mb);
   });
+  {
+    std::map<int, std::vector<double *>> byK;   // the last block may be narrower
+    for (int u = 0; u < nMu; ++u) {
+      const int K = std::min(4, s.nh - 4 * mfirst[u]) * N;
+      byK[K].push_back(Minv[u].data());
+    }
+    try {
+      for (auto &kv : byK)
+        if (invert_many(opt, kv.first, kv.second)) s.dev_steps |= 2;
+    } catch (const std::domain_error &) {
+      throw std::domain_error("singular block-Jacobi block");
+    }
+  }
   s.nM = nMu * 4;
   s.Mblk.assign((size_t)s.nM * N * 4 * N, 0.0);
   for (int u = 0; u < nMu; ++u) {
@@ -766,20 +821,30 @@ void build_system(System &s, int mx, int mz, int order, const double *xb, const 
   s.Gc.assign((size_t)d * d, 0.0);
   if (!s.singular) {
     std::vector<double> Ci = s.C;
-    if (!invert(d, Ci.data(), d)) throw std::domain_error("singular coarse matrix C(k)");
+    try {
+      if (invert_many(opt, d, {Ci.data()})) s.dev_steps |= 4;
+    } catch (const std::domain_error &) {
+      throw std::domain_error("singular coarse matrix C(k)");
+    }
     s.Gc = Ci;
   } else {
-    // u_C: C^T u = 0 with u_{d-1} = 1 (the leading (d-1) block is invertible).
+    // u_C: C^T u = 0 with u_{d-1} = 1 (the leading (d-1) block C_m is
+    // invertible): u_m = C_m^-T b with b = -(row d-1 of C)[0..m).
     const int m = d - 1;
-    std::vector<double> Cm((size_t)m * m), rhs(m);
+    std::vector<double> Cinv((size_t)m * m);
     for (int i = 0; i < m; ++i)
-      for (int j = 0; j < m; ++j) Cm[(size_t)i * m + j] = s.C[(size_t)i * d + j];
-    std::vector<int> piv(m);
-    if (!getrf(m, Cm.data(), m, piv.data())) throw std::domain_error("singular leading block of C");
-    for (int i = 0; i < m; ++i) rhs[i] = -s.C[(size_t)(d - 1) * d + i];
-    getrs_t(m, 1, Cm.data(), m, piv.data(), rhs.data(), 1);
+      for (int j = 0; j < m; ++j) Cinv[(size_t)i * m + j] = s.C[(size_t)i * d + j];
+    try {
+      if (invert_many(opt, m, {Cinv.data()})) s.dev_steps |= 4;
+    } catch (const std::domain_error &) {
+      throw std::domain_error("singular leading block of C");
+    }
     std::vector<double> uC(d, 1.0);
-    for (int i = 0; i < m; ++i) uC[i] = rhs[i];
+    for (int i = 0; i < m; ++i) {
+      double acc = 0.0;
+      for (int k = 0; k < m; ++k) acc += Cinv[(size_t)k * m + i] * -s.C[(size_t)(d - 1) * d + k];
+      uC[i] = acc;
+    }
     const double nu = norm2(uC);
     double sum = 0.0;
     for (auto &a : uC) { a /= nu; sum += a; }
@@ -787,18 +852,16 @@ void build_system(System &s, int mx, int mz, int order, const double *xb, const 
     s.uC = uC;
     // G = [[C_m^-1, 0], [0, 0]] (I - u_C u_C^T): the last coarse unknown is
     // pinned to zero (any solution of the consistent system works, P is
-    // unchanged by a shift along 1_d).
-    std::vector<double> Cinv((size_t)m * m, 0.0);
-    for (int i = 0; i < m; ++i) Cinv[(size_t)i * m + i] = 1.0;
-    getrs(m, m, Cm.data(), m, piv.data(), Cinv.data(), m);
-    for (int i = 0; i < m; ++i)
-      for (int j = 0; j < d; ++j) {
-        double acc = 0.0;
-        for (int l = 0; l < m; ++l) acc += Cinv[(size_t)i * m + l] * ((l == j ? 1.0 : 0.0) - uC[l] * uC[j]);
-        s.Gc[(size_t)i * d + j] = acc;
-      }
+    // unchanged by a shift along 1_d).  A rank-one update of C_m^-1:
+    // G[i][j] = C_m^-1[i][j] - w_i u_C[j] with w = C_m^-1 u_C[0..m).
+    for (int i = 0; i < m; ++i) {
+      const double *ci = &Cinv[(size_t)i * m];
+      double w = 0.0;
+      for (int l = 0; l < m; ++l) w += ci[l] * uC[l];
+      for (int j = 0; j < d; ++j) s.Gc[(size_t)i * d + j] = (j < m ? ci[j] : 0.0) - w * uC[j];
+    }
     // Null vectors of S and L.
-    left_null_schur(s);
+    left_null_schur(s, opt);
     // u_L = A^-T B^T u_S (Claim 1, part 2)
     std::vector<double> uL(s.r, 0.0);
     const int n2 = s.n2;

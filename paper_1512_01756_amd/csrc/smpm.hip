@@ -17,6 +17,7 @@
 #include "../../include/smpm_schur.h"
 #include "device.hpp"
 #include "host.hpp"
+#include "setup_dev.hpp"
 #include "persist.hpp"
 #include "kernels.hip"
 
@@ -58,26 +59,45 @@ T *dupload(std::vector<void *> &owned, const std::vector<T> &v, hipStream_t st) 
   return p;
 }
 
-// Column-major copy of row-major blocks: nb blocks of rows x cols.
+// Columns [c0, c1) of one row-major rows x cols block into column-major
+// storage with leading dimension ld, in 32 x 32 tiles.
 template <typename T>
-std::vector<T> to_colmajor(const std::vector<double> &a, int nb, int rows, int cols) {
-  std::vector<T> out((size_t)nb * rows * cols);
-  for (int b = 0; b < nb; ++b)
-    for (int r = 0; r < rows; ++r)
-      for (int c = 0; c < cols; ++c)
-        out[(size_t)b * rows * cols + (size_t)c * rows + r] = (T)a[(size_t)b * rows * cols + (size_t)r * cols + c];
-  return out;
+void colmajor_cols(const double *ab, int rows, int cols, int ld, int c0, int c1, T *ob) {
+  constexpr int TB = 32;
+  for (int r0 = 0; r0 < rows; r0 += TB) {
+    const int r1 = std::min(rows, r0 + TB);
+    for (int c = c0; c < c1; ++c)
+      for (int r = r0; r < r1; ++r) ob[(size_t)c * ld + r] = (T)ab[(size_t)r * cols + c];
+  }
 }
 
-// Column-major copy with the row count padded to ld (zero rows).
+// Column-major copy with the row count padded to ld (zero rows) of nb
+// row-major blocks of rows x cols, on the host threads over (block, 32-column
+// slice): the tables reach a GB on distinct-strip grids.
 template <typename T>
 std::vector<T> to_colmajor_padded(const std::vector<double> &a, int nb, int rows, int cols, int ld) {
   std::vector<T> out((size_t)nb * ld * cols, (T)0);
-  for (int b = 0; b < nb; ++b)
-    for (int r = 0; r < rows; ++r)
-      for (int c = 0; c < cols; ++c)
-        out[(size_t)b * ld * cols + (size_t)c * ld + r] = (T)a[(size_t)b * rows * cols + (size_t)r * cols + c];
+  const int ct = (cols + 31) / 32;
+  parallel_for(nb * ct, 0, [&](int q) {
+    const int b = q / ct, c0 = (q % ct) * 32;
+    colmajor_cols(a.data() + (size_t)b * rows * cols, rows, cols, ld, c0, std::min(cols, c0 + 32),
+                  out.data() + (size_t)b * ld * cols);
+  });
   return out;
+}
+
+// Column-major copy of row-major blocks: nb blocks of rows x cols.
+template <typename T>
+std::vector<T> to_colmajor(const std::vector<double> &a, int nb, int rows, int cols) {
+  return to_colmajor_padded<T>(a, nb, rows, cols, rows);
+}
+
+// FP32 copy on the device of an uploaded FP64 table (the same layout).
+float *dconvert32(std::vector<void *> &owned, const double *src, size_t n, hipStream_t st) {
+  float *p = dalloc<float>(owned, n);
+  if (n > 0)
+    hipLaunchKernelGGL(k_to_f32, dim3((unsigned)((n + kBlock - 1) / kBlock)), dim3(kBlock), 0, st, src, p, (int64_t)n);
+  return p;
 }
 
 // FP16 copy of nb row-major rows x cols blocks, column-major with leading
@@ -88,7 +108,7 @@ std::vector<_Float16> to_half_scaled(const std::vector<double> &a, int nb, int r
   const int nseg = rows / seg;
   std::vector<_Float16> out((size_t)nb * ld * cols, (_Float16)0.0f);
   scale.assign((size_t)nb * nseg, 1.0f);
-  for (int b = 0; b < nb; ++b)
+  parallel_for(nb, 0, [&](int b) {
     for (int e = 0; e < nseg; ++e) {
       double mx = 0.0;
       for (int r = e * seg; r < (e + 1) * seg; ++r)
@@ -100,6 +120,7 @@ std::vector<_Float16> to_half_scaled(const std::vector<double> &a, int nb, int r
           out[(size_t)b * ld * cols + (size_t)c * ld + r] =
               (_Float16)(float)(a[(size_t)b * rows * cols + (size_t)r * cols + c] / sc);
     }
+  });
   return out;
 }
 
@@ -309,10 +330,10 @@ void upload(smpm_handle *H, hipStream_t st) {
     d.nq = 2 * s.n * (s.mz - 1);
     d.Np = (s.N + 7) / 8 * 8;   // 16-byte columns in FP64, FP32 and FP16
     d.W64 = dupload(own, to_colmajor_padded<double>(s.Wblk, s.nW, s.N, 2 * s.N, d.Np), st);
-    d.W32 = dupload(own, to_colmajor_padded<float>(s.Wblk, s.nW, s.N, 2 * s.N, d.Np), st);
+    d.W32 = dconvert32(own, d.W64, (size_t)s.nW * 2 * s.N * d.Np, st);
     if (s.nF > 0) {
       d.F64 = dupload(own, to_colmajor_padded<double>(s.Fblk, s.nF, s.N, 8 * s.N, d.Np), st);
-      d.F32 = dupload(own, to_colmajor_padded<float>(s.Fblk, s.nF, s.N, 8 * s.N, d.Np), st);
+      d.F32 = dconvert32(own, d.F64, (size_t)s.nF * 8 * s.N * d.Np, st);
     }
     if (H->op16) {
       std::vector<float> sc;
@@ -328,7 +349,7 @@ void upload(smpm_handle *H, hipStream_t st) {
     d.w_id = dupload(own, s.w_id, st);
     d.w_win = dupload(own, s.w_win, st);
     d.M64 = dupload(own, to_colmajor_padded<double>(s.Mblk, s.nM, s.N, 4 * s.N, d.Np), st);
-    d.M32 = dupload(own, to_colmajor_padded<float>(s.Mblk, s.nM, s.N, 4 * s.N, d.Np), st);
+    d.M32 = dconvert32(own, d.M64, (size_t)s.nM * 4 * s.N * d.Np, st);
     d.m_id = dupload(own, s.m_id, st);
     d.m_win = dupload(own, s.m_win, st);
     d.m_K = dupload(own, s.m_K, st);
@@ -337,13 +358,23 @@ void upload(smpm_handle *H, hipStream_t st) {
     d.Gc = dupload(own, to_colmajor<double>(s.Gc, 1, s.d, s.d), st);
     d.uS = s.singular ? dupload(own, s.uS, st) : nullptr;
     d.uL = s.singular ? dupload(own, s.uL, st) : nullptr;
-    std::vector<double> Dinv, Kinv, beta;
+    // element inverses (class, element) and capacitance inverses (class),
+    // column-major, on the host threads over 32-column slices
+    const int ncl = (int)s.classes.size(), n2 = s.n2, nq = 2 * s.n * (s.mz - 1);
+    std::vector<double> Dinv((size_t)ncl * s.mz * n2 * n2), Kinv((size_t)ncl * nq * nq), beta;
+    const int ct2 = (n2 + 31) / 32, ctq = (nq + 31) / 32;
+    parallel_for(ncl * s.mz * ct2, 0, [&](int q) {
+      const int be = q / ct2, c0 = (q % ct2) * 32, ci = be / s.mz, e = be % s.mz;
+      colmajor_cols(s.classes[ci].Dinv.data() + (size_t)e * n2 * n2, n2, n2, n2, c0, std::min(n2, c0 + 32),
+                    Dinv.data() + (size_t)be * n2 * n2);
+    });
+    if (nq > 0)
+      parallel_for(ncl * ctq, 0, [&](int q) {
+        const int ci = q / ctq, c0 = (q % ctq) * 32;
+        colmajor_cols(s.classes[ci].Kinv.data(), nq, nq, nq, c0, std::min(nq, c0 + 32),
+                      Kinv.data() + (size_t)ci * nq * nq);
+      });
     for (const StripClass &c : s.classes) {
-      std::vector<double> cm = to_colmajor<double>(c.Dinv, s.mz, s.n2, s.n2);
-      Dinv.insert(Dinv.end(), cm.begin(), cm.end());
-      const int nq = 2 * s.n * (s.mz - 1);
-      std::vector<double> kc = to_colmajor<double>(c.Kinv, 1, nq, nq);
-      Kinv.insert(Kinv.end(), kc.begin(), kc.end());
       beta.insert(beta.end(), c.betaW.begin(), c.betaW.end());
       beta.insert(beta.end(), c.betaE.begin(), c.betaE.end());
     }
@@ -1221,6 +1252,13 @@ smpm_status setup_common(const smpm_grid *grids, const double *k, int nsys, bool
   so.tau = H->opts.tau;
   so.zlabel = H->zlabel;
   so.threads = nsys > 1 ? 1 : 0;   // parallel over systems, or over strip classes of one system
+  // the large dense setup steps on the device, unless asked not to
+  std::unique_ptr<DeviceDense, void (*)(DeviceDense *)> dense(
+      H->host_only || (H->opts.flags & SMPM_FLAG_HOST_SETUP)
+          ? nullptr
+          : device_dense_create((H->opts.flags & SMPM_FLAG_DEVICE_SETUP) != 0),
+      device_dense_destroy);
+  so.dense = device_dense_backend(dense.get());
   parallel_for(nsys, nsys > 1 ? 0 : 1, [&](int i) {
     const smpm_grid &g = one_grid ? grids[0] : grids[i];
     try {
@@ -1650,6 +1688,7 @@ smpm_status smpm_query(const smpm_handle *H, int32_t sysi, smpm_info *info) {
   for (int k = 0; k < 3; ++k)
     for (int w = 0; w < 2; ++w) o.elem_sched[2 * k + w] = H->n_cg_all[k][w] > 0 ? H->cg_sched[k][w] : -1;
   for (int pr = 0; pr < 3; ++pr) o.fused_op[pr] = H->use_fused[pr] ? 1 : 0;
+  o.setup_device = s.dev_steps;
   *info = o;
   return SMPM_OK;
 }
