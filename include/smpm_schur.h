@@ -65,7 +65,9 @@ typedef enum {
   SMPM_EHIP = -3,        /* HIP runtime error */
   SMPM_ESINGULAR = -4,   /* k = 0 with m_x < 4, or a factorization failed */
   SMPM_ENOTCONV = -5,    /* max_iter / sweeps reached, or a refinement sweep failed
-                            to cut the residual by 10%; u holds the last iterate */
+                            to cut the residual by 10%, or the rate of the last
+                            sweep would need more sweeps than are left; u holds
+                            the last iterate */
   SMPM_ENONFINITE = -6,  /* NaN or Inf in the inputs or the iterates */
   SMPM_EUNSUPPORTED = -7 /* the call needs a GPU but the handle is host-only */
 } smpm_status;

@@ -1486,7 +1486,7 @@ smpm_status smpm_solve(smpm_handle *H, const double *f, const double *g, double 
       if (!H->g_resid) H->g_resid = capture(st, [&] { residual64(H, st); });
       HIPCHECK(hipGraphLaunch(H->g_stage, st));
       HIPCHECK(hipMemcpyAsync(H->h_nb, H->pairs, sizeof(double) * 2 * H->ninst, hipMemcpyDeviceToHost, st));
-      double prev_worst = 1.0;
+      double prev_worst = 1.0, prev2_worst = 1.0;
       for (;; ++sweeps) {
         if (sweeps > 0) {
           HIPCHECK(hipGraphLaunch(H->g_resid, st));
@@ -1506,6 +1506,13 @@ smpm_status smpm_solve(smpm_handle *H, const double *f, const double *g, double 
           // stagnation: a sweep that does not cut the worst residual by 10%
           // will not reach the tolerance (the inner operator is too inexact)
           if (worst > kStagnation * prev_worst) { notconv = true; break; }
+          // nor will one whose rate over the last two sweeps, kept up, needs
+          // more sweeps than are left
+          if (sweeps >= 3 && worst > 0.0) {
+            const double need = 2.0 * std::log(H->tol / worst) / std::log(worst / prev2_worst);
+            if (sweeps + need > H->max_sweeps) { notconv = true; break; }
+          }
+          prev2_worst = prev_worst;
           prev_worst = worst;
         }
         if (sweeps >= H->max_sweeps) { notconv = true; break; }
