@@ -300,9 +300,31 @@ __device__ inline void load_windows(const GWork &wk, const GVec *__restrict__ gv
   }
 }
 
+// Two consecutive vector entries x[i0], x[i0 + 1] (each only if wanted, else
+// 0) with one 2-wide load when both are wanted and the pair is aligned to its
+// width; else two scalar loads.
+template <typename TX> struct Vec2;
+template <> struct Vec2<double> { using T = double2; };
+template <> struct Vec2<float> { using T = float2; };
+template <typename TX, typename TO>
+__device__ inline void load_pair(const TX *__restrict__ x, int64_t i0, bool in0, bool in1, TO &v0, TO &v1) {
+  using V2 = typename Vec2<TX>::T;
+  if (in0 && in1 && ((uintptr_t)(x + i0) & (sizeof(V2) - 1)) == 0) {
+    const V2 p = *reinterpret_cast<const V2 *>(x + i0);
+    v0 = (TO)p.x;
+    v1 = (TO)p.y;
+  } else {
+    v0 = in0 ? (TO)x[i0] : (TO)0;
+    v1 = in1 ? (TO)x[i0 + 1] : (TO)0;
+  }
+}
+
 // Split-K schedule (few items): grid (item, 16-row tile), KP waves split K;
 // U K-steps of operand loads in flight per wave; partial tiles summed in LDS
-// in a fixed order.
+// in a fixed order.  K-steps go in pairs: in steps 2p and 2p + 1, lane group
+// q (lanes 16q .. 16q + 15) takes k = 8p + 2q and 8p + 2q + 1, so each lane
+// reads its two window values of a pair with one 2-wide load (the windows are
+// contiguous in k; the block rows are read per k as before).
 template <typename TS, typename TO, typename TX, typename TY, int KP>
 __global__ __launch_bounds__(64 * KP) void k_half_gemm(
     const GWork *__restrict__ work, const GVec *__restrict__ gvec, const TX *__restrict__ xbase, int x_vslot,
@@ -322,15 +344,17 @@ __global__ __launch_bounds__(64 * KP) void k_half_gemm(
   const int arow = rt * 16 + (lane & 15);
   const bool alive = arow < Np;
   const int kq = lane >> 4;
-  const int nsteps = (K + 3) >> 2;
-  const int s0 = (nsteps * kp) / KP, s1 = (nsteps * (kp + 1)) / KP;
+  static_assert(U % 2 == 0, "K-steps go in pairs");
+  const int npairs = (((K + 3) >> 2) + 1) >> 1;
+  const int s0 = 2 * ((npairs * kp) / KP), s1 = 2 * ((npairs * (kp + 1)) / KP);
+  auto kof = [&](int t) { return 8 * (t >> 1) + 2 * kq + (t & 1); };
   // The first block values do not depend on the windows: in flight while
   // the window table is read.
   TO a[U];
   auto load_a = [&](int st) {
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      const int k = 4 * (st + u) + kq;
+      const int k = kof(st + u);
       a[u] = (alive && st + u < s1 && k < K) ? (TO)blk[(size_t)k * Np + arow] : (TO)0;
     }
   };
@@ -350,12 +374,14 @@ __global__ __launch_bounds__(64 * KP) void k_half_gemm(
     if (st != s0) load_a(st);
     TO b0[U], b1[U];
 #pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const int k = 4 * (st + u) + kq;
-      const bool kin = st + u < s1 && k < K;
+    for (int u = 0; u < U; u += 2) {
+      const int k = kof(st + u);   // this lane's k in step st + u; k + 1 in the next
+      const bool kin0 = st + u < s1 && k < K, kin1 = st + u < s1 && k + 1 < K;
       const int64_t ga = wa + k, gb = wb + k;
-      b0[u] = (la && kin && ga >= 0 && ga < kS) ? (TO)xbase[xa + ga] : (TO)0;
-      b1[u] = (two && lb && kin && gb >= 0 && gb < kS) ? (TO)xbase[xb + gb] : (TO)0;
+      load_pair(xbase, xa + ga, la && kin0 && ga >= 0 && ga < kS, la && kin1 && ga + 1 >= 0 && ga + 1 < kS, b0[u],
+                b0[u + 1]);
+      load_pair(xbase, xb + gb, two && lb && kin0 && gb >= 0 && gb < kS,
+                two && lb && kin1 && gb + 1 >= 0 && gb + 1 < kS, b1[u], b1[u + 1]);
     }
 #pragma unroll
     for (int u = 0; u < U; ++u) acc0 = Mfma<TO>::mac(a[u], b0[u], acc0);
