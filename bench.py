@@ -109,8 +109,9 @@ def matvec_kernel_name(solver):
 # rocprofv3 --pmc passes (FETCH_SIZE, WRITE_SIZE) over `bench.py --matvec-only`,
 # each scaled by the counter's reading for a 256 MiB device copy (fetch x2.000,
 # write x1.000); see profiles/c2_schur_matvec_hbm_counters.txt.  Valid only for
-# the kernel version the passes measured (split-K k_half_gemm<double, 16>).
-MATVEC_TRAFFIC = {"c2": 6.447e6}
+# the kernel version the passes measured (split-K k_half_gemm<double, 8> with
+# paired K-steps; the 16-wave variant reads the same tiles).
+MATVEC_TRAFFIC = {"c2": 6.494e6}
 
 PEAK_HBM_GBPS = 8000.0
 PEAK_FP64_MFMA_TFLOPS = 78.6
