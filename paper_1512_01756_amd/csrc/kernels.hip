@@ -640,22 +640,14 @@ __global__ __launch_bounds__(kBlock) void k_pcorr_dot(
   __shared__ double ws[kChunk];
   const int2 wk = work[blockIdx.x];
   const int i = wk.x, ch = wk.y;
-  const InstDev I = ins[i];   // loaded with the state, not after its test
-  const GState G = gs[i];
-  if (!G.active) return;
+  if (!gs[i].active) return;
+  const InstDev I = ins[i];
   const SysDev &S = sys[I.sys];
   const int N = S.N;
   const int64_t kS = S.kS;
-  const int j = G.iter;
+  const int j = gs[i].iter;
   const int64_t e0 = (int64_t)ch * kChunk;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  // y of this chunk, in flight during the coarse solve
-  double yv[kChunk / kBlock];
-#pragma unroll
-  for (int q = 0; q < kChunk / kBlock; ++q) {
-    const int64_t e = e0 + threadIdx.x + q * kBlock;
-    yv[q] = e < kS ? (double)ybase[I.x_off + e] : 0.0;
-  }
   int c0 = 0;
   if (useP) {
     const int d = S.d, zm = S.zm, nif = S.mx - 1;
@@ -691,7 +683,7 @@ __global__ __launch_bounds__(kBlock) void k_pcorr_dot(
     const int64_t e = e0 + threadIdx.x + q * kBlock;
     double w = 0.0;
     if (e < kS) {
-      w = yv[q];
+      w = (double)ybase[I.x_off + e];
       if (useP) {
         const int h = (int)(e / N), row = (int)(e - (int64_t)h * N);
         w -= sz_c(S, h, row, c_s, c0);
