@@ -634,7 +634,7 @@ template <typename TV, typename TY>
 __global__ __launch_bounds__(kBlock) void k_pcorr_dot(
     const SysDev *__restrict__ sys, const InstDev *__restrict__ ins, const int2 *__restrict__ work,
     const TY *__restrict__ ybase, const double *__restrict__ hsum, int useP, TV *__restrict__ V,
-    double *__restrict__ part, const GState *__restrict__ gs, int maxit) {
+    double *__restrict__ part, const GState *__restrict__ gs) {
   extern __shared__ double t_s[];   // d
   __shared__ double c_s[kChunk / 2 + 8];
   __shared__ double ws[kChunk];
@@ -1720,22 +1720,6 @@ __global__ __launch_bounds__(kBlock) void k_proj_x_scalar(const SysDev *__restri
   for (int q = 0; q < kChunk / kBlock; ++q) {
     const int64_t e = (int64_t)ch * kChunk + threadIdx.x + q * kBlock;
     if (e < S.kS) x[I.x_off + e] -= alpha * S.uS[e];
-  }
-}
-
-// Precision conversion of an interface vector (double -> float etc.).
-template <typename TA, typename TB>
-__global__ __launch_bounds__(kBlock) void k_convert(const SysDev *__restrict__ sys,
-                                                    const InstDev *__restrict__ ins,
-                                                    const int2 *__restrict__ work,
-                                                    const TA *__restrict__ a, TB *__restrict__ b) {
-  const int2 wk = work[blockIdx.x];
-  const int i = wk.x, ch = wk.y;
-  const InstDev I = ins[i];
-  const SysDev &S = sys[I.sys];
-  for (int q = 0; q < kChunk / kBlock; ++q) {
-    const int64_t e = (int64_t)ch * kChunk + threadIdx.x + q * kBlock;
-    if (e < S.kS) b[I.x_off + e] = (TB)a[I.x_off + e];
   }
 }
 

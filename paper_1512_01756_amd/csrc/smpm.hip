@@ -1026,7 +1026,7 @@ struct Inner {
     hipLaunchKernelGGL((k_pcorr_dot<T, T>), dim3(H->n_x), dim3(kBlock), sizeof(double) * H->dmax, st,
                        H->d_sys,
                        H->d_ins, H->w_x, (const T *)yb, (const double *)H->hs, useP ? 1 : 0, Vb, H->part1,
-                       (const GState *)H->gs, maxit);
+                       (const GState *)H->gs);
     // One Krylov space over all instances (Sec. 5.2): every reduction spans
     // the segment, so the partials go through k_seg_reduce first.
     const bool seg = H->one_krylov;
