@@ -501,6 +501,16 @@ void upload(smpm_handle *H, hipStream_t st) {
       }
     };
     for (int si = 0; si < (int)H->sys.size(); ++si) items(si, si * H->nrhs, (si + 1) * H->nrhs, all);
+    // Where a product has wide items and only a few narrow ones (a launch of
+    // fewer than 1024 row tiles, bound by latency), the 64-column kernel takes
+    // the narrow ones too: one launch instead of two.  Many narrow items stay
+    // apart, as 16-column tiles.
+    const int64_t rt16 = (std::max(H->n2_max, H->nq_max) + 15) / 16;
+    for (int k = 0; k < 3; ++k)
+      if (!all[k][0].empty() && !all[k][1].empty() && (int64_t)all[k][0].size() * rt16 < 1024) {
+        all[k][1].insert(all[k][1].end(), all[k][0].begin(), all[k][0].end());
+        all[k][0].clear();
+      }
     for (int i = 0; i < H->ninst; ++i) {
       int st0[3][2];
       for (int k = 0; k < 3; ++k)
