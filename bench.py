@@ -51,10 +51,10 @@ def gpu_events_time(fn, reps, stream):
     return start.elapsed_time(end) / reps   # ms
 
 
-def make_solver(cfg, precision, inner_tol=0.0, zlabel=0):
+def make_solver(cfg, precision, inner_tol=0.0, zlabel=0, setup="auto"):
     import paper_1512_01756_amd as P
     from paper_1512_01756_amd import workloads
-    kw = {"precision": precision, "inner_tol": inner_tol, "zlabel": zlabel}
+    kw = {"precision": precision, "inner_tol": inner_tol, "zlabel": zlabel, "setup": setup}
     if cfg in ("c2", "c3"):
         p = workloads.c2() if cfg == "c2" else workloads.c3()
         return P.Solver(p.xb, p.zb, p.n - 1, **kw), p.f.reshape(-1)
@@ -109,9 +109,10 @@ def matvec_kernel_name(solver):
 # rocprofv3 --pmc passes (FETCH_SIZE, WRITE_SIZE) over `bench.py --matvec-only`,
 # each scaled by the counter's reading for a 256 MiB device copy (fetch x2.000,
 # write x1.000); see profiles/c2_schur_matvec_hbm_counters.txt.  Valid only for
-# the kernel version the passes measured (split-K k_half_gemm<double, 8> with
-# paired K-steps; the 16-wave variant reads the same tiles).
-MATVEC_TRAFFIC = {"c2": 6.494e6}
+# the kernel version the passes measured (c2: split-K k_half_gemm<double, 8>
+# with paired K-steps, the 16-wave variant reads the same tiles; c3: the
+# streaming k_half_gemv_stream<double>, profiles/c3_schur_matvec_hbm_counters.txt).
+MATVEC_TRAFFIC = {"c2": 6.494e6, "c3": 3.584e8}
 
 PEAK_HBM_GBPS = 8000.0
 PEAK_FP64_MFMA_TFLOPS = 78.6
@@ -154,6 +155,8 @@ def main():
     ap.add_argument("--matvec-only", action="store_true")
     ap.add_argument("--zlabel", type=int, default=0, choices=(0, 1),
                     help="deflation space: 0 one column per interface (the paper's), 1 per element segment")
+    ap.add_argument("--setup", default="auto", choices=("auto", "host", "device"),
+                    help="where the large dense setup steps run (setup is not timed)")
     ap.add_argument("--inner-tol", type=float, default=0.0,
                     help="FP32-IR inner tolerance floor (0: the library default)")
     args = ap.parse_args()
@@ -171,7 +174,7 @@ def main():
     if args.matvec_only:
         # The Schur matvec alone, plus a plain device copy of known size that
         # calibrates the HBM byte counters (FETCH_SIZE / WRITE_SIZE).
-        s, _ = make_solver(args.config, P.FP64)
+        s, _ = make_solver(args.config, P.FP64, setup=args.setup)
         x = torch.randn(s.total_kS, dtype=torch.float64, device=dev)
         y = torch.empty_like(x)
         ms = gpu_events_time(lambda: s.schur_apply_all(x, y, P.FP64), args.matvec_reps, stream)
@@ -189,7 +192,7 @@ def main():
     fvec = None
     for name, prec in (("fp64", P.FP64), ("fp32_ir", P.FP32_IR), ("fp16s_ir", P.FP16S_IR)):
         t0 = time.perf_counter()
-        s, fh = make_solver(args.config, prec, args.inner_tol, args.zlabel)
+        s, fh = make_solver(args.config, prec, args.inner_tol, args.zlabel, args.setup)
         setup_s = time.perf_counter() - t0
         if fvec is None:
             fvec = torch.as_tensor(fh).to(dev)
