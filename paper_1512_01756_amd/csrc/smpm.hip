@@ -222,6 +222,9 @@ struct smpm_handle {
   // Iterations launched before the first convergence check: the previous
   // solve's count (-1: none yet, one chunk).
   int pred_iters[2] = {-1, -1};
+  // The refinement's inner solves, per sweep index (later sweeps need fewer
+  // iterations): the previous solve's count of that sweep, -1 if none.
+  std::vector<int> pred_sweep;
   // The FP64 solve's report, read back with one copy: GMRES states, then
   // (||r||^2, u_S . r), the compatibility defects and (||b~||^2, u_S . b~)
   // per instance (gs, pairs, defect and nb2 point into it).
@@ -1108,10 +1111,13 @@ struct Inner {
     }
   }
 
-  // The predicted iterations (the previous solve's count, one chunk for the
-  // first solve), capped at maxit; returns how many were enqueued.
-  static int predicted(smpm_handle *H, hipStream_t st) {
-    const int pred = H->pred_iters[P] < 0 ? kIterChunk : H->pred_iters[P];
+  // The predicted iterations (the previous solve's count, of the same sweep
+  // for the refinement; one chunk for the first solve), capped at maxit;
+  // returns how many were enqueued.
+  static int predicted(smpm_handle *H, int slot, hipStream_t st) {
+    int pred = H->pred_iters[P];
+    if (P == 1 && slot < (int)H->pred_sweep.size() && H->pred_sweep[slot] >= 0) pred = H->pred_sweep[slot];
+    if (pred < 0) pred = kIterChunk;
     const int n = std::min(pred, H->maxit);
     iterations(H, n, st);
     return n;
@@ -1133,7 +1139,7 @@ struct Inner {
     if (!H->g_pre[P]) H->g_pre[P] = capture(st, [&] { pre(H, st); });
     if (!H->g_post[P]) H->g_post[P] = capture(st, [&] { post(H, st); });
     HIPCHECK(hipGraphLaunch(H->g_pre[P], st));
-    until_done(H, predicted(H, st), st);
+    until_done(H, predicted(H, slot, st), st);
     HIPCHECK(hipGraphLaunch(H->g_post[P], st));
     HIPCHECK(hipMemcpyAsync(H->h_gs_hist + (size_t)slot * H->ninst, H->gs, sizeof(GState) * H->ninst,
                             hipMemcpyDeviceToHost, st));
@@ -1465,7 +1471,7 @@ smpm_status smpm_solve(smpm_handle *H, const double *f, const double *g, double 
         H->tail_u = u;
       }
       HIPCHECK(hipGraphLaunch(H->g_head, st));
-      int launched = Inner<double>::predicted(H, st);
+      int launched = Inner<double>::predicted(H, 0, st);
       for (;;) {
         HIPCHECK(hipGraphLaunch(H->g_tail, st));
         HIPCHECK(hipMemcpyAsync(H->h_rep, H->gs, H->rep_bytes, hipMemcpyDeviceToHost, st));
@@ -1546,6 +1552,7 @@ smpm_status smpm_solve(smpm_handle *H, const double *f, const double *g, double 
     const int P = H->precision == SMPM_FP64 ? 0 : 1;
     const int nslots = H->precision == SMPM_FP64 ? 1 : std::min(sweeps, H->max_sweeps);
     int itmax_all = 0;
+    if (P == 1) H->pred_sweep.assign(nslots, -1);
     for (int sw = 0; sw < nslots; ++sw)
       for (int i = 0; i < H->ninst; ++i) {
         const GState &gsi = H->h_gs_hist[(size_t)sw * H->ninst + i];
@@ -1553,6 +1560,7 @@ smpm_status smpm_solve(smpm_handle *H, const double *f, const double *g, double 
         S.schur_matvecs += gsi.iter;
         S.iters_max = std::max(S.iters_max, gsi.iter);
         itmax_all = std::max(itmax_all, gsi.iter);
+        if (P == 1) H->pred_sweep[sw] = std::max(H->pred_sweep[sw], gsi.iter);
         if (gsi.status == 3) nonfinite = true;
         if (gsi.status == 2 && H->precision == SMPM_FP64) notconv = true;
       }
