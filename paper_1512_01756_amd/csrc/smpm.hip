@@ -223,8 +223,10 @@ struct smpm_handle {
   // solve's count (-1: none yet, one chunk).
   int pred_iters[2] = {-1, -1};
   // The refinement's inner solves, per sweep index (later sweeps need fewer
-  // iterations): the previous solve's count of that sweep, -1 if none.
+  // iterations): the previous solve's count of that sweep, -1 if none; and
+  // the previous solve's number of sweeps (0: none yet).
   std::vector<int> pred_sweep;
+  int pred_nsweeps = 0;
   // The FP64 solve's report, read back with one copy: GMRES states, then
   // (||r||^2, u_S . r), the compatibility defects and (||b~||^2, u_S . b~)
   // per instance (gs, pairs, defect and nb2 point into it).
@@ -1133,6 +1135,19 @@ struct Inner {
     }
   }
 
+  // One inner solve of exactly the predicted iterations, with no host check:
+  // an instance still iterating then yields a less accurate correction,
+  // which the refinement's later sweeps make up for.  States to slot `slot`.
+  static void run_fixed(smpm_handle *H, int slot, hipStream_t st) {
+    if (!H->g_pre[P]) H->g_pre[P] = capture(st, [&] { pre(H, st); });
+    if (!H->g_post[P]) H->g_post[P] = capture(st, [&] { post(H, st); });
+    HIPCHECK(hipGraphLaunch(H->g_pre[P], st));
+    predicted(H, slot, st);
+    HIPCHECK(hipGraphLaunch(H->g_post[P], st));
+    HIPCHECK(hipMemcpyAsync(H->h_gs_hist + (size_t)slot * H->ninst, H->gs, sizeof(GState) * H->ninst,
+                            hipMemcpyDeviceToHost, st));
+  }
+
   // Enqueue one inner solve; its final GMRES states are copied to the pinned
   // history slot `slot` (read after the solve's last synchronization).
   static void run(smpm_handle *H, int slot, hipStream_t st) {
@@ -1502,6 +1517,19 @@ smpm_status smpm_solve(smpm_handle *H, const double *f, const double *g, double 
       if (!H->g_resid) H->g_resid = capture(st, [&] { residual64(H, st); });
       HIPCHECK(hipGraphLaunch(H->g_stage, st));
       HIPCHECK(hipMemcpyAsync(H->h_nb, H->pairs, sizeof(double) * 2 * H->ninst, hipMemcpyDeviceToHost, st));
+      // As many sweeps as the previous solve took, each with its predicted
+      // inner iterations, enqueued back to back without a host check; the
+      // residual is checked after them and the checked sweeps below go on
+      // if it is not small enough.
+      const int batch = std::min(H->pred_nsweeps, H->max_sweeps);
+      for (; sweeps < batch; ++sweeps) {
+        if (sweeps > 0) {
+          HIPCHECK(hipGraphLaunch(H->g_resid, st));
+          S.schur_matvecs += H->ninst;
+        }
+        Inner<float>::run_fixed(H, sweeps, st);
+        S.schur_matvecs += useP ? H->ninst : 0;
+      }
       double prev_worst = 1.0, prev2_worst = 1.0;
       for (;; ++sweeps) {
         if (sweeps > 0) {
@@ -1560,7 +1588,8 @@ smpm_status smpm_solve(smpm_handle *H, const double *f, const double *g, double 
         S.schur_matvecs += gsi.iter;
         S.iters_max = std::max(S.iters_max, gsi.iter);
         itmax_all = std::max(itmax_all, gsi.iter);
-        if (P == 1) H->pred_sweep[sw] = std::max(H->pred_sweep[sw], gsi.iter);
+        // an inner solve cut short by its prediction gets a chunk more next time
+        if (P == 1) H->pred_sweep[sw] = std::max(H->pred_sweep[sw], gsi.iter + (gsi.active ? kIterChunk : 0));
         if (gsi.status == 3) nonfinite = true;
         if (gsi.status == 2 && H->precision == SMPM_FP64) notconv = true;
       }
@@ -1581,6 +1610,9 @@ smpm_status smpm_solve(smpm_handle *H, const double *f, const double *g, double 
     S.converged = conv;
     S.solve_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     if (stats) *stats = S;
+    // the next refinement solve runs this many sweeps unchecked: only after
+    // a converged one
+    if (P == 1) H->pred_nsweeps = (nonfinite || notconv) ? 0 : nslots;
     if (nonfinite) return fail(SMPM_ENONFINITE, "non-finite value in the inputs or iterates");
     if (notconv) return fail(SMPM_ENOTCONV, "iteration limit reached before the tolerance");
   } catch (const std::exception &e) {

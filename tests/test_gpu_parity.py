@@ -206,6 +206,30 @@ def test_fp32_refinement_reaches_fp64_solution():
     assert _rel(u, ref.u) <= 1e-8
 
 
+@pytest.mark.parametrize("precision", [P.FP32_IR, P.FP16S_IR])
+def test_repeated_refinement_solves(precision):
+    # The second and later solves of a handle run the previous solve's sweeps
+    # (and per-sweep inner iterations) without host checks, then check and go
+    # on if needed: same right-hand side (exact prediction), then a harder one
+    # (a 40x larger random part, prediction too short), then the first again.
+    p = workloads.random_problem(12, 3, 7, seed=5, stretch=True)
+    s = P.Solver(p.xb, p.zb, p.n - 1, precision=precision, tune=False)
+    f1 = p.f.reshape(-1)
+    f2 = f1 + 40.0 * np.random.default_rng(9).standard_normal(f1.size)
+    grid = smpm.Grid(p.xb, p.zb, p.n)
+    o = schur.build(grid)
+    refs = {}
+    for name, f in (("f1", f1), ("f1", f1), ("f2", f2), ("f1", f1)):
+        u, st, status = s.solve(_dev(f))
+        torch.cuda.synchronize()
+        if name not in refs:
+            refs[name] = solve.dbj_solve(o, smpm.rhs(grid, o.tau, f), tol=1e-12).u
+        print(name, st)
+        assert status == P.OK
+        assert st["rel_residual_max"] <= ACCEPT
+        assert _rel(u.cpu().numpy(), refs[name]) <= 1e-8
+
+
 @pytest.mark.parametrize("k", [0.0, 2.3])
 def test_operator_applies_match_oracle(k):
     xb = np.array([0, 0.4, 0.9, 1.2, 1.9, 2.3, 2.8, 3.5])
