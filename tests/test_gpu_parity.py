@@ -206,6 +206,41 @@ def test_fp32_refinement_reaches_fp64_solution():
     assert _rel(u, ref.u) <= 1e-8
 
 
+@pytest.mark.parametrize("batched", [False, True])
+def test_repeated_fp64_solves_resume_after_a_short_prediction(batched):
+    # An FP64 solve runs the previous solve's iteration count, then the tail
+    # (epilogue, residual, recovery) and one check.  An easy right-hand side
+    # first (few iterations predicted), then one that needs more: the loop
+    # resumes after the tail and the tail runs again.
+    if batched:
+        p = workloads.fourier_problem("f", 4.0, 8, 2, 5, my=8, ly=2.0, seed=3)
+        s = P.Solver(p.xb, p.zb, p.n - 1, kwaves=p.kwaves, nrhs=2, tune=False)
+    else:
+        p = workloads.random_problem(10, 3, 6, seed=17, stretch=True)
+        s = P.Solver(p.xb, p.zb, p.n - 1, tune=False)
+    f_hard = p.f.reshape(-1)
+    f_easy = np.zeros_like(f_hard)
+    if batched:   # per-mode counts differ from the random forcing's
+        f_easy[::7] = 1.0
+    # (one system: f = 0 stops at once, so the next solve predicts 0 iterations)
+    its = []
+    for f in (f_easy, f_hard, f_easy, f_hard):
+        u, st, status = s.solve(_dev(f))
+        torch.cuda.synchronize()
+        assert status == P.OK
+        assert st["rel_residual_max"] <= ACCEPT
+        its.append(st["iters_max"])
+    print("iterations", its)
+    # the same right-hand side gives the same counts whatever came before,
+    # and the two differ (so one of them resumes after its tail)
+    assert its[0] == its[2] and its[1] == its[3] and its[0] != its[1]
+    if not batched:
+        grid = smpm.Grid(p.xb, p.zb, p.n)
+        o = schur.build(grid)
+        ref = solve.dbj_solve(o, smpm.rhs(grid, o.tau, f_hard)).u
+        assert _rel(u.cpu().numpy(), ref) <= 1e-9
+
+
 @pytest.mark.parametrize("precision", [P.FP32_IR, P.FP16S_IR])
 def test_repeated_refinement_solves(precision):
     # The second and later solves of a handle run the previous solve's sweeps
