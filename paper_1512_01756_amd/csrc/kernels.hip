@@ -439,7 +439,11 @@ __global__ __launch_bounds__(256) void k_half_gemm_t(
     const GWork *__restrict__ work, const int2 *__restrict__ units, const GVec *__restrict__ gvec,
     const TX *__restrict__ xbase, int x_vslot, const double *__restrict__ scale, TY *__restrict__ ybase,
     double *__restrict__ hsum, const GState *__restrict__ gs) {
-  constexpr int VT = 16 * CT, KC = 32, PITCH = VT + 1;
+  // Staging as in k_colgemm_t: the TPC threads of a window read its chunk
+  // interleaved (thread j takes k = j + TPC p), and the row pitch puts the
+  // lanes that the LDS serves together (16 for 8-byte, 32 for 4-byte values)
+  // in distinct bank slots for the stores and the MFMA operand reads.
+  constexpr int VT = 16 * CT, KC = 32, PITCH = VT + (sizeof(TO) == 8 ? CT : 2 * CT);
   constexpr int PV = KC * VT / 256;      // staged values per thread per chunk
   constexpr int TPC = KC / PV;           // threads per window
   __shared__ TO Bs[2][KC * PITCH];
@@ -464,7 +468,7 @@ __global__ __launch_bounds__(256) void k_half_gemm_t(
   const int arow = rg * 64 + wave * 16 + (lane & 15);
   const bool alive = arow < Np;
   const int kq = lane >> 4, cl = lane & 15;
-  const int scol = threadIdx.x / TPC, sk0 = (threadIdx.x % TPC) * PV;
+  const int scol = threadIdx.x / TPC, sj = threadIdx.x % TPC;
   const bool slive = scol < wk.vcount && wi[scol].live;
   const int64_t sx = wi[scol].xoff, sw = wi[scol].win;
   TO pre[PV];
@@ -472,7 +476,7 @@ __global__ __launch_bounds__(256) void k_half_gemm_t(
   auto load_b = [&](int kc) {
 #pragma unroll
     for (int p = 0; p < PV; ++p) {
-      const int k = kc * KC + sk0 + p;
+      const int k = kc * KC + sj + TPC * p;
       const int64_t g = sw + k;
       pre[p] = (slive && k < K && g >= 0 && g < kS) ? (TO)xbase[sx + g] : (TO)0;
     }
@@ -486,7 +490,7 @@ __global__ __launch_bounds__(256) void k_half_gemm_t(
   };
   auto store_b = [&](int buf) {
 #pragma unroll
-    for (int p = 0; p < PV; ++p) Bs[buf][(sk0 + p) * PITCH + scol] = pre[p];
+    for (int p = 0; p < PV; ++p) Bs[buf][(sj + TPC * p) * PITCH + scol] = pre[p];
   };
   using Acc = typename Mfma<TO>::Acc;
   Acc acc[CT];
@@ -1087,7 +1091,13 @@ template <int CT, int MODE>
 __global__ __launch_bounds__(256) void k_colgemm_t(const CGItem *__restrict__ items, const int2 *__restrict__ units,
                                                    const CGCol *__restrict__ cols, const double *__restrict__ xb,
                                                    double *__restrict__ yb) {
-  constexpr int VC = 16 * CT, KC = 32, PITCH = VC + 1;
+  // Staging: the TPC = 16 / CT threads of a column read its chunk interleaved
+  // (thread j takes k = j + TPC p), so one load instruction covers TPC
+  // consecutive values of each column.  The LDS serves 8-byte accesses 16
+  // lanes at a time; a row pitch of CT mod 16 doubles puts those 16 lanes in
+  // distinct bank slots, for the stores (TPC rows x CT columns) and for the
+  // MFMA operand reads (16 columns of one row).
+  constexpr int VC = 16 * CT, KC = 32, PITCH = VC + CT;
   constexpr int PV = KC * VC / 256;      // staged values per thread per chunk
   constexpr int TPC = KC / PV;           // threads per column
   __shared__ double Bs[2][KC * PITCH];
@@ -1112,13 +1122,13 @@ __global__ __launch_bounds__(256) void k_colgemm_t(const CGItem *__restrict__ it
   const int kq = lane >> 4, cl = lane & 15;
   const int K = it.K, ks = it.ksplit, lda = it.lda, agap = it.agap;
   const double *__restrict__ A = it.A;
-  const int scol = threadIdx.x / TPC, sk0 = (threadIdx.x % TPC) * PV;
+  const int scol = threadIdx.x / TPC, sj = threadIdx.x % TPC;
   const int64_t sx1 = c1[scol], sx2 = c2[scol];
   double pre[PV];
   double a[KC / 4], an[KC / 4];
   auto load_b = [&](int kc) {
 #pragma unroll
-    for (int p = 0; p < PV; ++p) pre[p] = colval(xb, sx1, sx2, kc * KC + sk0 + p, K, ks);
+    for (int p = 0; p < PV; ++p) pre[p] = colval(xb, sx1, sx2, kc * KC + sj + TPC * p, K, ks);
   };
   auto load_a = [&](int kc, double *dst) {
 #pragma unroll
@@ -1130,7 +1140,7 @@ __global__ __launch_bounds__(256) void k_colgemm_t(const CGItem *__restrict__ it
   };
   auto store_b = [&](int buf) {
 #pragma unroll
-    for (int p = 0; p < PV; ++p) Bs[buf][(sk0 + p) * PITCH + scol] = pre[p];
+    for (int p = 0; p < PV; ++p) Bs[buf][(sj + TPC * p) * PITCH + scol] = pre[p];
   };
   using Acc = Mfma<double>::Acc;
   Acc acc[CT];
