@@ -466,7 +466,7 @@ __global__ __launch_bounds__(256) void k_half_gemm_t(
   const TS *__restrict__ blk = Tab<TS>::blk(wk);
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int arow = rg * 64 + wave * 16 + (lane & 15);
-  const bool alive = arow < Np;
+  const bool alive = arow < Np, wlive = rg * 64 + wave * 16 < N;
   const int kq = lane >> 4, cl = lane & 15;
   const int scol = threadIdx.x / TPC, sj = threadIdx.x % TPC;
   const bool slive = scol < wk.vcount && wi[scol].live;
@@ -509,10 +509,12 @@ __global__ __launch_bounds__(256) void k_half_gemm_t(
       load_a(kc + 1, an);
     }
     const TO *__restrict__ B = Bs[buf];
+    if (wlive) {   // a wave whose 16 rows all lie past the block stages only
 #pragma unroll
-    for (int s = 0; s < KC / 4; ++s)
+      for (int s = 0; s < KC / 4; ++s)
 #pragma unroll
-      for (int t = 0; t < CT; ++t) acc[t] = Mfma<TO>::mac(a[s], B[(4 * s + kq) * PITCH + t * 16 + cl], acc[t]);
+        for (int t = 0; t < CT; ++t) acc[t] = Mfma<TO>::mac(a[s], B[(4 * s + kq) * PITCH + t * 16 + cl], acc[t]);
+    }
     if (more) {
       store_b(buf ^ 1);
 #pragma unroll
@@ -1118,7 +1120,7 @@ __global__ __launch_bounds__(256) void k_colgemm_t(const CGItem *__restrict__ it
   __syncthreads();
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int arow = rg * 64 + wave * 16 + (lane & 15);
-  const bool alive = arow < it.R;
+  const bool alive = arow < it.R, wlive = rg * 64 + wave * 16 < it.R;
   const int kq = lane >> 4, cl = lane & 15;
   const int K = it.K, ks = it.ksplit, lda = it.lda, agap = it.agap;
   const double *__restrict__ A = it.A;
@@ -1159,10 +1161,12 @@ __global__ __launch_bounds__(256) void k_colgemm_t(const CGItem *__restrict__ it
       load_a(kc + 1, an);
     }
     const double *__restrict__ B = Bs[buf];
+    if (wlive) {   // a wave whose 16 rows all lie past the block stages only
 #pragma unroll
-    for (int s = 0; s < KC / 4; ++s)
+      for (int s = 0; s < KC / 4; ++s)
 #pragma unroll
-      for (int t = 0; t < CT; ++t) acc[t] = Mfma<double>::mac(a[s], B[(4 * s + kq) * PITCH + t * 16 + cl], acc[t]);
+        for (int t = 0; t < CT; ++t) acc[t] = Mfma<double>::mac(a[s], B[(4 * s + kq) * PITCH + t * 16 + cl], acc[t]);
+    }
     if (more) {
       store_b(buf ^ 1);
 #pragma unroll
