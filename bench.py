@@ -109,10 +109,10 @@ def matvec_kernel_name(solver):
 # rocprofv3 --pmc passes (FETCH_SIZE, WRITE_SIZE) over `bench.py --matvec-only`,
 # each scaled by the counter's reading for a 256 MiB device copy (fetch x2.000,
 # write x1.000); see profiles/c2_schur_matvec_hbm_counters.txt.  Valid only for
-# the kernel version the passes measured (c2: split-K k_half_gemm<double, 8>
-# with paired K-steps, the 16-wave variant reads the same tiles; c3: the
-# streaming k_half_gemv_stream<double>, profiles/c3_schur_matvec_hbm_counters.txt).
-MATVEC_TRAFFIC = {"c2": 6.494e6, "c3": 3.584e8}
+# the kernel version the passes measured (c2: the split-K k_half_gemm<double>
+# with paired K-steps, 16 and 8 waves read the same tiles; c3: the streaming
+# k_half_gemv_stream<double>, profiles/c3_schur_matvec_hbm_counters.txt).
+MATVEC_TRAFFIC = {"c2": 6.458e6, "c3": 3.584e8}
 
 PEAK_HBM_GBPS = 8000.0
 PEAK_FP64_MFMA_TFLOPS = 78.6
