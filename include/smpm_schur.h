@@ -166,7 +166,11 @@ typedef struct {
                               (0 split-K 16 waves, 1 split-K 8 waves, 2 LDS-staged
                               XCD-ordered, 3 LDS-staged plain; -1 no shared blocks) */
   int32_t elem_sched[6];   /* same for the element-interior GEMM lists
-                              (D^-1, K^-1, correction) x (<= 16, <= 64 columns) */
+                              (D^-1, K^-1, correction) x (<= 16, <= 64 columns),
+                              with two more: 4 LDS-staged 32-row tiles, 5 16-row
+                              tiles, their waves splitting K.  The environment
+                              variable SMPM_ELEM_SCHED = 1..5, read at setup and
+                              load, pins all six (tests, experiments) */
   int32_t fused_op[3];     /* 1 if the GMRES iteration applies S M^-1 as one stored
                               block per half (FP64, FP32, FP16 storage): chosen at
                               setup when faster than M^-1 then S; grids whose strips

@@ -1014,11 +1014,15 @@ __global__ __launch_bounds__(kBlock) void k_combine(const SysDev *__restrict__ s
 // launches): grid (item, 16-row tile), 8 waves split K, each multiplies its
 // 16 rows by CT tiles of 16 columns with v_mfma_f64_16x16x4f64, U K-steps of
 // loads in flight, the K parts summed in LDS in a fixed order.
-// k_colgemm_t (many items: throughput-bound launches): grid (item, 64-row
-// tile), 4 waves of 16 rows over all of K; the columns are staged through
-// double-buffered LDS in chunks of 32 K-steps with coalesced loads (each
-// column is contiguous in memory) while the next chunk's operands are in
-// flight.  MODE 0: Y = A X; MODE 1: Y -= A X.  X and Y must not overlap.
+// k_colgemm_t (LDS-staged): grid (item, 16 RW-row tile), 4 waves; the
+// columns are staged through double-buffered LDS in chunks of 32 K-values
+// with coalesced loads (each column is contiguous in memory) while the next
+// chunk's operands are in flight.  RW = 4: each wave owns 16 rows over all of
+// K (many items: throughput-bound launches).  RW = 2 or 1: 4 / RW waves share
+// each 16 rows and split every chunk's K-steps between them, their sums added
+// in LDS in a fixed order; this shortens each wave's chain of dependent MFMAs
+// and spreads one item over more CUs (few items: latency-bound launches).
+// MODE 0: Y = A X; MODE 1: Y -= A X.  X and Y must not overlap.
 __device__ inline double colval(const double *__restrict__ xb, int64_t x1, int64_t x2, int k, int K, int ks) {
   if (k >= K) return 0.0;
   if (k < ks) return x1 >= 0 ? xb[x1 + k] : 0.0;
@@ -1089,7 +1093,7 @@ __global__ __launch_bounds__(512) void k_colgemm(const CGItem *__restrict__ item
   }
 }
 
-template <int CT, int MODE>
+template <int CT, int MODE, int RW>
 __global__ __launch_bounds__(256) void k_colgemm_t(const CGItem *__restrict__ items, const int2 *__restrict__ units,
                                                    const CGCol *__restrict__ cols, const double *__restrict__ xb,
                                                    double *__restrict__ yb) {
@@ -1102,6 +1106,11 @@ __global__ __launch_bounds__(256) void k_colgemm_t(const CGItem *__restrict__ it
   constexpr int VC = 16 * CT, KC = 32, PITCH = VC + CT;
   constexpr int PV = KC * VC / 256;      // staged values per thread per chunk
   constexpr int TPC = KC / PV;           // threads per column
+  constexpr int KW = 4 / RW;             // waves splitting the K-steps of 16 rows
+  constexpr int TR = 16 * RW;            // rows per tile
+  constexpr int SW = KC / 4 / KW;        // K-steps per wave per chunk
+  static_assert(RW == 1 || RW == 2 || RW == 4, "4 waves per workgroup");
+  static_assert((KW - 1) * RW * 4 * CT * 64 <= 2 * KC * PITCH, "K-split sums fit in the staging buffers");
   __shared__ double Bs[2][KC * PITCH];
   __shared__ int64_t c1[VC], c2[VC];
   int item = blockIdx.x, rg = blockIdx.y;
@@ -1111,7 +1120,7 @@ __global__ __launch_bounds__(256) void k_colgemm_t(const CGItem *__restrict__ it
     item = u.x; rg = u.y;
   }
   const CGItem it = items[item];
-  if (rg * 64 >= it.R) return;
+  if (rg * TR >= it.R) return;
   if (threadIdx.x < VC) {
     const bool ok = (int)threadIdx.x < it.ccount;
     c1[threadIdx.x] = ok ? cols[it.cstart + threadIdx.x].x1 : -1;
@@ -1119,23 +1128,25 @@ __global__ __launch_bounds__(256) void k_colgemm_t(const CGItem *__restrict__ it
   }
   __syncthreads();
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int arow = rg * 64 + wave * 16 + (lane & 15);
-  const bool alive = arow < it.R, wlive = rg * 64 + wave * 16 < it.R;
+  const int rw = wave % RW, kw = wave / RW;
+  const int arow = rg * TR + rw * 16 + (lane & 15);
+  const bool alive = arow < it.R, wlive = rg * TR + rw * 16 < it.R;
   const int kq = lane >> 4, cl = lane & 15;
+  const int ctl = (it.ccount + 15) >> 4;   // column tiles holding columns
   const int K = it.K, ks = it.ksplit, lda = it.lda, agap = it.agap;
   const double *__restrict__ A = it.A;
   const int scol = threadIdx.x / TPC, sj = threadIdx.x % TPC;
   const int64_t sx1 = c1[scol], sx2 = c2[scol];
   double pre[PV];
-  double a[KC / 4], an[KC / 4];
+  double a[SW], an[SW];
   auto load_b = [&](int kc) {
 #pragma unroll
     for (int p = 0; p < PV; ++p) pre[p] = colval(xb, sx1, sx2, kc * KC + sj + TPC * p, K, ks);
   };
-  auto load_a = [&](int kc, double *dst) {
+  auto load_a = [&](int kc, double *dst) {   // this wave's K-steps s KW + kw
 #pragma unroll
-    for (int s = 0; s < KC / 4; ++s) {
-      const int k = kc * KC + 4 * s + kq;
+    for (int s = 0; s < SW; ++s) {
+      const int k = kc * KC + 4 * (s * KW + kw) + kq;
       const int ka = k < ks ? k : k + agap;
       dst[s] = (alive && k < K) ? A[(size_t)ka * lda + arow] : 0.0;
     }
@@ -1161,18 +1172,40 @@ __global__ __launch_bounds__(256) void k_colgemm_t(const CGItem *__restrict__ it
       load_a(kc + 1, an);
     }
     const double *__restrict__ B = Bs[buf];
-    if (wlive) {   // a wave whose 16 rows all lie past the block stages only
+    // A wave whose 16 rows all lie past the block stages only; an item of at
+    // most 16 columns multiplies one column tile.
+    if (wlive && ctl > 1) {
 #pragma unroll
-      for (int s = 0; s < KC / 4; ++s)
+      for (int s = 0; s < SW; ++s)
 #pragma unroll
-        for (int t = 0; t < CT; ++t) acc[t] = Mfma<double>::mac(a[s], B[(4 * s + kq) * PITCH + t * 16 + cl], acc[t]);
+        for (int t = 0; t < CT; ++t)
+          acc[t] = Mfma<double>::mac(a[s], B[(4 * (s * KW + kw) + kq) * PITCH + t * 16 + cl], acc[t]);
+    } else if (wlive) {
+#pragma unroll
+      for (int s = 0; s < SW; ++s) acc[0] = Mfma<double>::mac(a[s], B[(4 * (s * KW + kw) + kq) * PITCH + cl], acc[0]);
     }
     if (more) {
       store_b(buf ^ 1);
 #pragma unroll
-      for (int s = 0; s < KC / 4; ++s) a[s] = an[s];
+      for (int s = 0; s < SW; ++s) a[s] = an[s];
     }
     __syncthreads();
+  }
+  if constexpr (KW > 1) {   // add the K parts; the staging buffers are free
+    double *red = &Bs[0][0];
+    if (kw > 0)
+#pragma unroll
+      for (int t = 0; t < CT; ++t)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) red[((((kw - 1) * RW + rw) * CT + t) * 4 + j) * 64 + lane] = acc[t][j];
+    __syncthreads();
+    if (kw > 0) return;
+#pragma unroll
+    for (int q = 1; q < KW; ++q)
+#pragma unroll
+      for (int t = 0; t < CT; ++t)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[t][j] += red[((((q - 1) * RW + rw) * CT + t) * 4 + j) * 64 + lane];
   }
 #pragma unroll
   for (int t = 0; t < CT; ++t) {
@@ -1181,7 +1214,7 @@ __global__ __launch_bounds__(256) void k_colgemm_t(const CGItem *__restrict__ it
     const int64_t y0 = cols[it.cstart + ci].y;
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
-      const int row = rg * 64 + wave * 16 + Mfma<double>::row(lane, j);
+      const int row = rg * TR + rw * 16 + Mfma<double>::row(lane, j);
       if (row < it.R) {
         if (MODE == 0) yb[y0 + row] = acc[t][j];
         else yb[y0 + row] -= acc[t][j];

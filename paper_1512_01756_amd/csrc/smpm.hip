@@ -7,6 +7,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <memory>
@@ -447,9 +448,10 @@ void upload(smpm_handle *H, hipStream_t st) {
   H->tot_r = f_off; H->tot_x = x_off; H->tot_g = g_off;
   if (H->one_krylov)
     for (InstDev &I : H->h_ins) I.seg_count = H->ninst;
-  // Element-interior GEMM items: per (system, strip class, element) for the
-  // element inverses, per (system, strip class) for the capacitance inverse;
-  // the columns are the (instance, strip) vectors of that class.
+  // Element-interior GEMM items: per (system, strip class, distinct element
+  // inverse) for the element inverses, per (system, strip class) for the
+  // capacitance inverse; the columns are the (instance, strip, element)
+  // vectors that the block multiplies.
   {
     std::vector<CGItem> all[3][2], one[3][2];
     std::vector<CGCol> cols;
@@ -478,17 +480,35 @@ void upload(smpm_handle *H, hipStream_t st) {
         std::vector<int> strips;
         for (int j = 0; j < s.mx; ++j)
           if (s.strip_class[j] == c) strips.push_back(j);
+        // Elements of the class with bitwise equal inverses (on a uniform
+        // z-grid every element between the two physical edges) share one
+        // item list: one stored block multiplies the columns of all of them.
+        const double *Dh = s.classes[c].Dinv.data();
+        const size_t bsz = (size_t)n2 * n2;
+        std::vector<int> rep(mz);
         for (int e = 0; e < mz; ++e) {
-          const double *A = d.Dinv + ((size_t)c * mz + e) * n2 * n2;
+          rep[e] = e;
+          for (int f = 0; f < e; ++f)
+            if (rep[f] == f && !std::memcmp(Dh + f * bsz, Dh + e * bsz, sizeof(double) * bsz)) {
+              rep[e] = f;
+              break;
+            }
+        }
+        for (int e0 = 0; e0 < mz; ++e0) {
+          if (rep[e0] != e0) continue;
+          const double *A = d.Dinv + ((size_t)c * mz + e0) * bsz;
           std::vector<CGCol> cs, cc;
           for (int i = i0; i < i1; ++i) {
             const InstDev &I = H->h_ins[i];
-            for (int j : strips) {
-              const int64_t off = I.f_off + ((int64_t)j * mz + e) * n2;
-              cs.push_back(CGCol{off, -1, off});
-              const int64_t q0 = I.lam_off + (int64_t)j * nq;
-              cc.push_back(CGCol{e >= 1 ? q0 + (int64_t)(2 * (e - 1)) * n : -1,
-                                 e + 1 < mz ? q0 + (int64_t)(2 * e + 1) * n : -1, off});
+            for (int e = e0; e < mz; ++e) {
+              if (rep[e] != e0) continue;
+              for (int j : strips) {
+                const int64_t off = I.f_off + ((int64_t)j * mz + e) * n2;
+                cs.push_back(CGCol{off, -1, off});
+                const int64_t q0 = I.lam_off + (int64_t)j * nq;
+                cc.push_back(CGCol{e >= 1 ? q0 + (int64_t)(2 * (e - 1)) * n : -1,
+                                   e + 1 < mz ? q0 + (int64_t)(2 * e + 1) * n : -1, off});
+              }
             }
           }
           emit(A, n2, n2, n2, n2, 0, cs, out[0]);
@@ -768,7 +788,17 @@ void gemv(smpm_handle *H, int op, const TX *x, int vslot, const double *scale, T
 }
 
 // Element-interior GEMM schedules: split K (kSplit8) or the LDS-staged
-// 64-row tile (kThrXcd with units, kThrPlain without).  sched < 0: by size.
+// 64-row tile (kThrXcd with units, kThrPlain without), or the LDS-staged
+// 32- or 16-row tile whose waves split K (kCol32, kCol16).  sched < 0: by size.
+enum ColSched { kCol32 = 4, kCol16 = 5 };
+
+template <int CT, int MODE, int RW>
+void colgemm_t_launch(smpm_handle *H, const CGItem *items, int count, const int2 *units, int nunits,
+                      const double *x, double *y, hipStream_t st, int rmax) {
+  const dim3 grid = units ? dim3(nunits) : dim3(count, (rmax + 16 * RW - 1) / (16 * RW));
+  hipLaunchKernelGGL((k_colgemm_t<CT, MODE, RW>), grid, dim3(256), 0, st, items, units, H->cg_cols, x, y);
+}
+
 template <int CT>
 void colgemm_w(smpm_handle *H, const CGItem *items, int count, const int2 *units, int nunits, int mode,
                const double *x, double *y, hipStream_t st, int sched = -1) {
@@ -776,15 +806,20 @@ void colgemm_w(smpm_handle *H, const CGItem *items, int count, const int2 *units
   const int rmax = std::max(H->n2_max, H->nq_max);
   const int rt16 = (rmax + 15) / 16;
   if (sched < 0) sched = (int64_t)count * rt16 < 1024 ? kSplit8 : kThrXcd;
-  if (sched == kThrPlain) units = nullptr;
+  if (sched != kThrXcd) units = nullptr;
   if (sched == kSplit8 || sched == kSplit16) {     // split K for parallelism
     const dim3 grid(count, rt16);
     if (mode == 0) hipLaunchKernelGGL((k_colgemm<CT, 0>), grid, dim3(512), 0, st, items, H->cg_cols, x, y);
     else hipLaunchKernelGGL((k_colgemm<CT, 1>), grid, dim3(512), 0, st, items, H->cg_cols, x, y);
+  } else if (sched == kCol16) {
+    if (mode == 0) colgemm_t_launch<CT, 0, 1>(H, items, count, units, nunits, x, y, st, rmax);
+    else colgemm_t_launch<CT, 1, 1>(H, items, count, units, nunits, x, y, st, rmax);
+  } else if (sched == kCol32) {
+    if (mode == 0) colgemm_t_launch<CT, 0, 2>(H, items, count, units, nunits, x, y, st, rmax);
+    else colgemm_t_launch<CT, 1, 2>(H, items, count, units, nunits, x, y, st, rmax);
   } else {
-    const dim3 grid = units ? dim3(nunits) : dim3(count, (rmax + 63) / 64);
-    if (mode == 0) hipLaunchKernelGGL((k_colgemm_t<CT, 0>), grid, dim3(256), 0, st, items, units, H->cg_cols, x, y);
-    else hipLaunchKernelGGL((k_colgemm_t<CT, 1>), grid, dim3(256), 0, st, items, units, H->cg_cols, x, y);
+    if (mode == 0) colgemm_t_launch<CT, 0, 4>(H, items, count, units, nunits, x, y, st, rmax);
+    else colgemm_t_launch<CT, 1, 4>(H, items, count, units, nunits, x, y, st, rmax);
   }
 }
 
@@ -830,7 +865,7 @@ float time_launch(hipStream_t st, hipEvent_t e0, hipEvent_t e1, F &&fn) {
   return ms;
 }
 
-void tune(smpm_handle *H, hipStream_t st) {
+void tune_schedules(smpm_handle *H, hipStream_t st) {
   const int rt16 = (H->Nmax + 15) / 16;
   for (int op = 0; op < 3; ++op)
     for (int pr = 0; pr < 3; ++pr) H->sched[op][pr] = gemm_default(H->n_g_all[op], rt16);
@@ -901,7 +936,7 @@ void tune(smpm_handle *H, hipStream_t st) {
         const float t2 = time_launch(st, e0, e1, [&] { two(1, x, z); two(0, z, y); });
         H->use_fused[pr] = tf < t2;
       }
-    const int cand[3] = {kSplit8, kThrXcd, kThrPlain};
+    const int cand[5] = {kSplit8, kThrXcd, kThrPlain, kCol32, kCol16};
     for (int k = 0; k < 3; ++k)
       for (int w = 0; w < 2; ++w) {
         const int cnt = H->n_cg_all[k][w];
@@ -925,6 +960,20 @@ void tune(smpm_handle *H, hipStream_t st) {
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
+}
+
+// Schedules of the handle's GEMM lists, timed at setup (or by size).  The
+// environment variable SMPM_ELEM_SCHED = 1..5 then pins every element-interior
+// list to one schedule (split K, LDS-staged XCD-ordered, plain, 32-row or
+// 16-row K-split tiles), for tests and experiments.
+void tune(smpm_handle *H, hipStream_t st) {
+  tune_schedules(H, st);
+  if (const char *e = std::getenv("SMPM_ELEM_SCHED")) {
+    const int v = std::atoi(e);
+    if (v >= kSplit8 && v <= kCol16)
+      for (int k = 0; k < 3; ++k)
+        for (int w = 0; w < 2; ++w) H->cg_sched[k][w] = v;
+  }
 }
 
 const int2 *xwork(smpm_handle *H, int inst, int &count) {

@@ -196,6 +196,36 @@ def test_largest_supported_interface_half(n, mz, mx, precision):
     assert res <= 1e-9
 
 
+def _sched_problem():
+    return workloads.random_problem(12, 4, 7, kwaves=(0.0, 1.3), nrhs=2, seed=31)
+
+
+@pytest.fixture(scope="module")
+def sched_refs():
+    p = _sched_problem()
+    return {(m, q): _oracle(p, m, q, tol=1e-12)[1].u for m in range(2) for q in range(2)}
+
+
+@pytest.mark.parametrize("sched", [1, 2, 3, 4, 5])
+def test_element_gemm_schedules_match_oracle(sched, monkeypatch, sched_refs):
+    # Every element-interior GEMM schedule, pinned for all lists: split K, the
+    # LDS-staged 64-row tile (XCD-ordered and plain) and the 32- and 16-row
+    # tiles whose waves split K.  A uniform grid, so the elements between the
+    # physical z-edges share one inverse and one item list; two systems of two
+    # right-hand sides give items of 1 to 3 column tiles (the last one partial)
+    # and one-column items in the same launch.  Both sides solve to 1e-12, so
+    # at k > 0 the comparison sees the GEMMs' rounding, not the stopping
+    # test's error; at k = 0 the Neumann problem's conditioning leaves more.
+    monkeypatch.setenv("SMPM_ELEM_SCHED", str(sched))
+    p = _sched_problem()
+    s, u, st = _gpu_solve(p, tol=1e-12)
+    assert all(v == sched for i in s.info for v in i["elem_sched"] if v >= 0)
+    assert st["rel_residual_max"] <= ACCEPT
+    u = u.reshape(2, 2, p.r)
+    for (m, q), ref in sched_refs.items():
+        assert _rel(u[m, q], ref) <= (1e-9 if m == 0 else 1e-11), (sched, m, q)
+
+
 def test_fp32_refinement_reaches_fp64_solution():
     p = workloads.random_problem(12, 3, 7, seed=5, stretch=True)
     s, u, st = _gpu_solve(p, precision=P.FP32_IR)
