@@ -549,8 +549,12 @@ __global__ __launch_bounds__(256) void k_half_gemm_t(
 
 // Coarse solve of the deflation (Sec. 3.3): t_c = sum of the two halves of
 // interface c (= Z^T y), optionally t = tsub - t; c = G t with G the
-// precomputed C^dagger (I - u_C u_C^T) (C^-1 for k > 0).  One workgroup per
-// instance.
+// precomputed C^dagger (I - u_C u_C^T) (C^-1 for k > 0).  Grid (instance,
+// 16-row tile of c): every workgroup forms all of t in LDS and multiplies its
+// 16 rows of G, so one apply reads G once, spread over many CUs.  Thread
+// (row, g) sums columns g, g + 16, ... of its row (16 rows of a column are
+// one 128-byte segment); the 16 partial sums of a row are added in a fixed
+// order.
 __global__ __launch_bounds__(kBlock) void k_coarse(const SysDev *__restrict__ sys,
                                                    const InstDev *__restrict__ ins,
                                                    const double *__restrict__ hsum,
@@ -559,11 +563,14 @@ __global__ __launch_bounds__(kBlock) void k_coarse(const SysDev *__restrict__ sy
                                                    double *__restrict__ cout,
                                                    const GState *__restrict__ gs) {
   extern __shared__ double t[];   // d
+  __shared__ double red[16 * 17];
   const int i = blockIdx.x;
   if (gs && !gs[i].active) return;
   const InstDev I = ins[i];
   const SysDev &S = sys[I.sys];
   const int d = S.d;
+  const int r0 = blockIdx.y * 16;
+  if (r0 >= d) return;
   const int sl = hs_slots(S);
   for (int c = threadIdx.x; c < d; c += kBlock) {
     double v = 0.0;
@@ -575,20 +582,25 @@ __global__ __launch_bounds__(kBlock) void k_coarse(const SysDev *__restrict__ sy
     }
     if (tsub) v = tsub[I.c_off + c] - v;
     t[c] = v;
-    if (tout) tout[I.c_off + c] = v;
+    if (tout && c >= r0 && c < r0 + 16) tout[I.c_off + c] = v;
   }
   __syncthreads();
-  // c = G t: column-split over the 4 waves, lanes over rows.
-  __shared__ double red[4 * 64];
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  for (int r0 = 0; r0 < d; r0 += 64) {
-    double acc[1] = {0.0};
-    colsplit<double, 1, 8>(S.Gc + r0, d, r0 + lane < d ? lane : d, (d * wave) >> 2, (d * (wave + 1)) >> 2, t, 0, acc);
-    red[wave * 64 + lane] = acc[0];
-    __syncthreads();
-    if (threadIdx.x < 64 && r0 + lane < d)
-      cout[I.c_off + r0 + lane] = (red[lane] + red[64 + lane]) + (red[128 + lane] + red[192 + lane]);
-    __syncthreads();
+  const int row = threadIdx.x & 15, g = threadIdx.x >> 4;
+  const double *__restrict__ col = S.Gc + r0 + (r0 + row < d ? row : 0);
+  double a0 = 0.0, a1 = 0.0;
+  int c = g;
+#pragma unroll 4
+  for (; c + 16 < d; c += 32) {
+    a0 += col[(size_t)c * d] * t[c];
+    a1 += col[(size_t)(c + 16) * d] * t[c + 16];
+  }
+  if (c < d) a0 += col[(size_t)c * d] * t[c];
+  red[g * 17 + row] = a0 + a1;
+  __syncthreads();
+  if (threadIdx.x < 16 && r0 + (int)threadIdx.x < d) {
+    double v = 0.0;
+    for (int q = 0; q < 16; ++q) v += red[q * 17 + threadIdx.x];
+    cout[I.c_off + r0 + threadIdx.x] = v;
   }
 }
 
@@ -635,12 +647,14 @@ __device__ inline void chunk_dots(const TV *__restrict__ V, int64_t kS, int64_t 
 // Sec. 3.3; useP = 0 skips it), stored in Krylov slot iter + 1; partial dots
 // V_t . w for t <= iter.  The coarse solve is fused: every workgroup forms
 // t = Z^T y from the per-tile half sums and computes only the coarse values
-// its chunk needs.
+// its chunk needs, against all d values of t.  With cpre (large d, where the
+// workgroups' G rows would add up to several reads of G) it takes them from
+// c = G Z^T y formed beforehand by k_coarse.
 template <typename TV, typename TY>
 __global__ __launch_bounds__(kBlock) void k_pcorr_dot(
     const SysDev *__restrict__ sys, const InstDev *__restrict__ ins, const int2 *__restrict__ work,
     const TY *__restrict__ ybase, const double *__restrict__ hsum, int useP, TV *__restrict__ V,
-    double *__restrict__ part, const GState *__restrict__ gs) {
+    double *__restrict__ part, const GState *__restrict__ gs, const double *__restrict__ cpre) {
   extern __shared__ double t_s[];   // d
   __shared__ double c_s[kChunk / 2 + 8];
   __shared__ double ws[kChunk];
@@ -658,16 +672,6 @@ __global__ __launch_bounds__(kBlock) void k_pcorr_dot(
   if (useP) {
     const int d = S.d, zm = S.zm, nif = S.mx - 1;
     const int sl = hs_slots(S);
-    for (int c = threadIdx.x; c < d; c += kBlock) {
-      double v = 0.0;
-      if (zm == 1) {
-        for (int q = 0; q < 2 * sl; ++q) v += hsum[I.hs_off + (int64_t)2 * c * sl + q];
-      } else {
-        const int a = c / zm, e = c - a * zm;
-        v = hsum[I.hs_off + (int64_t)(2 * a) * sl + e] + hsum[I.hs_off + (int64_t)(2 * a + 1) * sl + e];
-      }
-      t_s[c] = v;
-    }
     // the coarse values this chunk needs: interfaces ilo .. ihi
     const int64_t elast = (e0 + kChunk < kS ? e0 + kChunk : kS) - 1;
     const int hlo = (int)(e0 / N), hhi = (int)(elast / N);
@@ -675,12 +679,26 @@ __global__ __launch_bounds__(kBlock) void k_pcorr_dot(
     const int ihi = hhi / 2 + 1 > nif - 1 ? nif - 1 : hhi / 2 + 1;
     c0 = ilo * zm;
     const int ncol = (ihi - ilo + 1) * zm;
-    __syncthreads();
-    for (int r = wave; r < ncol; r += 4) {
-      double a = 0.0;
-      for (int l = lane; l < d; l += 64) a += S.Gc[(size_t)l * d + c0 + r] * t_s[l];
-      a = wave_sum(a);
-      if (lane == 0) c_s[r] = a;
+    if (cpre) {   // c = G Z^T y already formed (large d: G read once)
+      for (int r = threadIdx.x; r < ncol; r += kBlock) c_s[r] = cpre[I.c_off + c0 + r];
+    } else {
+      for (int c = threadIdx.x; c < d; c += kBlock) {
+        double v = 0.0;
+        if (zm == 1) {
+          for (int q = 0; q < 2 * sl; ++q) v += hsum[I.hs_off + (int64_t)2 * c * sl + q];
+        } else {
+          const int a = c / zm, e = c - a * zm;
+          v = hsum[I.hs_off + (int64_t)(2 * a) * sl + e] + hsum[I.hs_off + (int64_t)(2 * a + 1) * sl + e];
+        }
+        t_s[c] = v;
+      }
+      __syncthreads();
+      for (int r = wave; r < ncol; r += 4) {
+        double a = 0.0;
+        for (int l = lane; l < d; l += 64) a += S.Gc[(size_t)l * d + c0 + r] * t_s[l];
+        a = wave_sum(a);
+        if (lane == 0) c_s[r] = a;
+      }
     }
     __syncthreads();
   }
@@ -1103,7 +1121,9 @@ __global__ __launch_bounds__(256) void k_colgemm_t(const CGItem *__restrict__ it
   // lanes at a time; a row pitch of CT mod 16 doubles puts those 16 lanes in
   // distinct bank slots, for the stores (TPC rows x CT columns) and for the
   // MFMA operand reads (16 columns of one row).
-  constexpr int VC = 16 * CT, KC = 32, PITCH = VC + CT;
+  // chunks of 64 K-values where the waves split K: half as many chunks, each
+  // one staged while the last is multiplied
+  constexpr int VC = 16 * CT, KC = RW == 4 ? 32 : 64, PITCH = VC + CT;
   constexpr int PV = KC * VC / 256;      // staged values per thread per chunk
   constexpr int TPC = KC / PV;           // threads per column
   constexpr int KW = 4 / RW;             // waves splitting the K-steps of 16 rows

@@ -1019,6 +1019,9 @@ hipGraphExec_t capture(hipStream_t st, F &&body) {
   return exec;
 }
 
+// 16-row tiles of the coarse vector: the second grid dimension of k_coarse
+inline int ctiles(const smpm_handle *H) { return (H->dmax + 15) / 16; }
+
 // Inner DBJ-GMRES (or BJ / Schur), operators and Krylov basis in precision T.
 // FP64: b = b~, x_S = x.  FP32: b = the refinement residual, x_S += x.  The
 // stopping test is |g| <= tol * sqrt(pairs[2 i]) (||b||^2, left by the
@@ -1040,7 +1043,7 @@ struct Inner {
     if (useP) {
       hipLaunchKernelGGL(k_zt<double>, dim3(H->n_h), dim3(kBlock), 0, st, H->d_sys, H->d_ins, H->w_h, b(H), 0,
                          (const double *)nullptr, (const GState *)nullptr, H->hs);
-      hipLaunchKernelGGL(k_coarse, dim3(H->ninst), dim3(kBlock), sizeof(double) * H->dmax, st, H->d_sys, H->d_ins, (const double *)H->hs,
+      hipLaunchKernelGGL(k_coarse, dim3(H->ninst, ctiles(H)), dim3(kBlock), sizeof(double) * H->dmax, st, H->d_sys, H->d_ins, (const double *)H->hs,
                          (const double *)nullptr, H->tb, H->cv, (const GState *)nullptr);
     }
     hipLaunchKernelGGL(k_init_basis<T>, dim3(H->n_x), dim3(kBlock), 0, st, H->d_sys, H->d_ins, H->w_x, b(H),
@@ -1058,7 +1061,7 @@ struct Inner {
     gemv<T, T, T>(H, 1, x, vslot, scale, zb, nullptr, g, st, -1, h16(H));
     hipLaunchKernelGGL(k_zt<T>, dim3(H->n_h), dim3(kBlock), 0, st, H->d_sys, H->d_ins, H->w_h, x, vslot, scale, g,
                        H->hs);
-    hipLaunchKernelGGL(k_coarse, dim3(H->ninst), dim3(kBlock), sizeof(double) * H->dmax, st, H->d_sys, H->d_ins, (const double *)H->hs,
+    hipLaunchKernelGGL(k_coarse, dim3(H->ninst, ctiles(H)), dim3(kBlock), sizeof(double) * H->dmax, st, H->d_sys, H->d_ins, (const double *)H->hs,
                        (const double *)nullptr, (double *)nullptr, H->cv, g);
     hipLaunchKernelGGL(k_add_zc<T>, dim3(H->n_x), dim3(kBlock), 0, st, H->d_sys, H->d_ins, H->w_x, zb,
                        (const double *)H->cv, g);
@@ -1084,13 +1087,19 @@ struct Inner {
     } else {
       gemv<T, T, T>(H, 0, (const T *)Vb, 1, H->scale, yb, hsum, H->gs, st, -1, h16(H));
     }
-    if (useP && H->zlabel != 0)
+    // one coarse column per element segment: d up to (m_x - 1) m_z, so the
+    // coarse values are formed once (G read once) instead of per workgroup
+    const bool cpre = useP && H->zlabel != 0;
+    if (cpre) {
       hipLaunchKernelGGL(k_zt<T>, dim3(H->n_h), dim3(kBlock), 0, st, H->d_sys, H->d_ins, H->w_h, (const T *)yb, 0,
                          (const double *)nullptr, (const GState *)H->gs, H->hs);
-    hipLaunchKernelGGL((k_pcorr_dot<T, T>), dim3(H->n_x), dim3(kBlock), sizeof(double) * H->dmax, st,
-                       H->d_sys,
-                       H->d_ins, H->w_x, (const T *)yb, (const double *)H->hs, useP ? 1 : 0, Vb, H->part1,
-                       (const GState *)H->gs);
+      hipLaunchKernelGGL(k_coarse, dim3(H->ninst, ctiles(H)), dim3(kBlock), sizeof(double) * H->dmax, st, H->d_sys,
+                         H->d_ins, (const double *)H->hs, (const double *)nullptr, (double *)nullptr, H->cv,
+                         (const GState *)H->gs);
+    }
+    hipLaunchKernelGGL((k_pcorr_dot<T, T>), dim3(H->n_x), dim3(kBlock), cpre ? 0 : sizeof(double) * H->dmax, st,
+                       H->d_sys, H->d_ins, H->w_x, (const T *)yb, (const double *)H->hs, useP ? 1 : 0, Vb, H->part1,
+                       (const GState *)H->gs, cpre ? (const double *)H->cv : (const double *)nullptr);
     // One Krylov space over all instances (Sec. 5.2): every reduction spans
     // the segment, so the partials go through k_seg_reduce first.
     const bool seg = H->one_krylov;
@@ -1138,7 +1147,7 @@ struct Inner {
       if (H->zlabel != 0)
         hipLaunchKernelGGL(k_zt<T>, dim3(H->n_h), dim3(kBlock), 0, st, H->d_sys, H->d_ins, H->w_h, (const T *)yb, 0,
                            (const double *)nullptr, (const GState *)nullptr, H->hs);
-      hipLaunchKernelGGL(k_coarse, dim3(H->ninst), dim3(kBlock), sizeof(double) * H->dmax, st, H->d_sys, H->d_ins, (const double *)H->hs,
+      hipLaunchKernelGGL(k_coarse, dim3(H->ninst, ctiles(H)), dim3(kBlock), sizeof(double) * H->dmax, st, H->d_sys, H->d_ins, (const double *)H->hs,
                          (const double *)H->tb, (double *)nullptr, H->cv, (const GState *)nullptr);
       cfin = H->cv;
     }
@@ -1707,7 +1716,7 @@ smpm_status smpm_apply(smpm_handle *H, smpm_op op, int32_t sysi, const void *x, 
         HIPCHECK(hipMemcpyAsync(H->t64 + I.x_off, x, bx, hipMemcpyDeviceToDevice, st));
         hipLaunchKernelGGL(k_zt<double>, dim3(nhc), dim3(kBlock), 0, st, H->d_sys, H->d_ins, wh, (const double *)H->t64, 0,
                            (const double *)nullptr, (const GState *)nullptr, H->hs);
-        hipLaunchKernelGGL(k_coarse, dim3(1), dim3(kBlock), sizeof(double) * H->dmax, st, H->d_sys, H->d_ins + inst, (const double *)H->hs,
+        hipLaunchKernelGGL(k_coarse, dim3(1, ctiles(H)), dim3(kBlock), sizeof(double) * H->dmax, st, H->d_sys, H->d_ins + inst, (const double *)H->hs,
                            (const double *)nullptr, (double *)nullptr, H->cv, (const GState *)nullptr);
         hipLaunchKernelGGL(k_xupdate<double>, dim3(nxc), dim3(kBlock), 0, st, H->d_sys, H->d_ins, wx, 3,
                            (const double *)H->t64, (const double *)H->cv, H->y64, (double *)nullptr,
@@ -1722,7 +1731,7 @@ smpm_status smpm_apply(smpm_handle *H, smpm_op op, int32_t sysi, const void *x, 
         if (H->zlabel != 0)
           hipLaunchKernelGGL(k_zt<double>, dim3(nhc), dim3(kBlock), 0, st, H->d_sys, H->d_ins, wh,
                              (const double *)H->y64, 0, (const double *)nullptr, (const GState *)nullptr, H->hs);
-        hipLaunchKernelGGL(k_coarse, dim3(1), dim3(kBlock), sizeof(double) * H->dmax, st, H->d_sys, H->d_ins + inst, (const double *)H->hs,
+        hipLaunchKernelGGL(k_coarse, dim3(1, ctiles(H)), dim3(kBlock), sizeof(double) * H->dmax, st, H->d_sys, H->d_ins + inst, (const double *)H->hs,
                            (const double *)nullptr, (double *)nullptr, H->cv, (const GState *)nullptr);
         hipLaunchKernelGGL(k_xupdate<double>, dim3(nxc), dim3(kBlock), 0, st, H->d_sys, H->d_ins, wx, 4,
                            (const double *)H->t64, (const double *)H->cv, H->z64, (double *)nullptr,
