@@ -39,6 +39,7 @@ struct SysDev {
   const float *F16s;
   const int *m_id, *m_win, *m_K;
   const double *Gc;      // coarse operator, column-major d x d
+  const double *GcR;     // the same row-major (one coarse column per interface only)
   const double *uS, *uL; // null vectors (k = 0), else nullptr
   const double *Dinv;    // element inverses: [class][e][col n2][row n2]
   const double *Kinv;    // z-interface capacitance inverses: [class][col nq][row nq]
@@ -99,9 +100,10 @@ struct GVec {
   int64_t xh;     // own half inside the instance's interface vector (identity term)
   int64_t y;      // output offset
   int inst;       // instance (GMRES state, scale)
-  int hs;         // Z^T partial sums: first 16-row slot of this half
+  int hs;         // Z^T partial sums: slot 0 of this half (slot q at hs + q hn)
   int st_off;     // scale vector of the instance
-  int pad[3];
+  int hn;         // stride between the 16-row slots of the partial sums (halves)
+  int pad[2];
 };
 
 // Column-gather GEMM item (element-interior elimination): Y[:, c] (+)= A X[:, c]

@@ -53,9 +53,12 @@ __device__ inline double sz_c(const SysDev &S, int h, int row, const double *__r
   }
   return a;
 }
-// Z^T partial sums of one half: index of coarse column e of half h in the
-// half-sum array.  With zm = 1 the array holds per-16-row slots (the GEMM
-// epilogues write them), summed over the half; else one sum per segment.
+// Z^T partial sums.  With zm = 1 the array holds per-(16-row slot, half)
+// sums, slot-major: [slot q][half h] (the GEMM epilogues write them; a
+// half's sum is the sum over its slots, and the halves 2c, 2c + 1 of
+// interface c sit side by side, so a thread per interface reads 16 bytes per
+// slot and neighbouring threads read neighbouring bytes).  Else [half][e],
+// one sum per element segment.
 __device__ inline int hs_slots(const SysDev &S) {
   const int tiles = (S.N + 15) >> 4;
   return S.zm > 1 ? S.zm : tiles;
@@ -115,8 +118,8 @@ __device__ inline void colsplit(const TO *__restrict__ blk, int R, int row, int 
 // Two kernels cover the halves: a streaming GEMV for blocks used by one half
 // (distinct strips, HBM bound) and an MFMA GEMM for blocks shared by many
 // halves (uniform strips).  x_vslot: read x from Krylov slot `iter` of the
-// instance, scaled by scale[iter].  hsum: per-(half, 16-row slot) partial sums
-// of y, hsum[hs_off + h * ceil(N / 16) + slot] (for Z^T y).
+// instance, scaled by scale[iter].  hsum: per-(16-row slot, half) partial sums
+// of y, hsum[hs_off + slot * nh + h] (for Z^T y).
 //
 // Streaming variant for halves whose block is not shared (distinct strips):
 // one half per workgroup row tile, 16-byte loads (VR consecutive rows per
@@ -234,8 +237,8 @@ __global__ __launch_bounds__(64 * NW) void k_half_gemv_stream(
       const int slots = (N + 15) >> 4;
       const int q0 = tile * (TR / 16);
       const int q1 = (tile + 1) * (TR / 16) < slots ? (tile + 1) * (TR / 16) : slots;
-      hsum[I.hs_off + (int64_t)h * slots + q0] = t;
-      for (int q = q0 + 1; q < q1; ++q) hsum[I.hs_off + (int64_t)h * slots + q] = 0.0;
+      hsum[I.hs_off + (int64_t)q0 * S.nh + h] = t;
+      for (int q = q0 + 1; q < q1; ++q) hsum[I.hs_off + (int64_t)q * S.nh + h] = 0.0;
     }
   }
 }
@@ -270,7 +273,7 @@ template <> struct Mfma<float> {
 struct WinInfo {
   int64_t xoff, win, y, xh;
   double scale;
-  int live, hs;
+  int live, hs, hn;
 };
 
 template <int VT>
@@ -294,6 +297,7 @@ __device__ inline void load_windows(const GWork &wk, const GVec *__restrict__ gv
       w.y = e.y;
       w.xh = e.xh;
       w.hs = e.hs;
+      w.hn = e.hn;
       w.scale = scale ? scale[e.st_off + it] : 1.0;
     }
     wi[v] = w;
@@ -420,7 +424,7 @@ __global__ __launch_bounds__(64 * KP) void k_half_gemm(
       if (v < wk.vcount && wi[v].live && rt * 16 < N) {
         double t = 0.0;
         for (int lr = 0; lr < 16; ++lr) t += red[lr * VT + v];
-        hsum[wi[v].hs + rt] = t;
+        hsum[wi[v].hs + (int64_t)rt * wi[v].hn] = t;
       }
     }
   }
@@ -543,7 +547,7 @@ __global__ __launch_bounds__(256) void k_half_gemm_t(
     // sum the 16 rows of this wave's slot: lanes cl, cl + 16, cl + 32, cl + 48
     part += __shfl_xor(part, 16, 64);
     part += __shfl_xor(part, 32, 64);
-    if (hsum && ok && kq == 0 && slot * 16 < N) hsum[wi[v].hs + slot] = part;
+    if (hsum && ok && kq == 0 && slot * 16 < N) hsum[wi[v].hs + (int64_t)slot * wi[v].hn] = part;
   }
 }
 
@@ -575,7 +579,10 @@ __global__ __launch_bounds__(kBlock) void k_coarse(const SysDev *__restrict__ sy
   for (int c = threadIdx.x; c < d; c += kBlock) {
     double v = 0.0;
     if (S.zm == 1) {
-      for (int q = 0; q < 2 * sl; ++q) v += hsum[I.hs_off + (int64_t)2 * c * sl + q];
+      for (int q = 0; q < sl; ++q) {
+        const double2 p = *reinterpret_cast<const double2 *>(hsum + I.hs_off + (int64_t)q * S.nh + 2 * c);
+        v += p.x + p.y;
+      }
     } else {
       const int a = c / S.zm, e = c - a * S.zm;
       v = hsum[I.hs_off + (int64_t)(2 * a) * sl + e] + hsum[I.hs_off + (int64_t)(2 * a + 1) * sl + e];
@@ -647,14 +654,19 @@ __device__ inline void chunk_dots(const TV *__restrict__ V, int64_t kS, int64_t 
 // Sec. 3.3; useP = 0 skips it), stored in Krylov slot iter + 1; partial dots
 // V_t . w for t <= iter.  The coarse solve is fused: every workgroup forms
 // t = Z^T y from the per-tile half sums and computes only the coarse values
-// its chunk needs, against all d values of t.  With cpre (large d, where the
-// workgroups' G rows would add up to several reads of G) it takes them from
+// its chunk needs, against all d values of t.  With one coarse column per
+// interface, the loads that do not depend on t (the chunk's y values, its
+// S Z rows, the first 8 G rows it needs, from the row-major copy of G) go
+// out before t is formed, so the kernel waits on memory once before its
+// dots instead of three times.  With cpre (large d, where the workgroups' G
+// rows would add up to several reads of G) it takes the coarse values from
 // c = G Z^T y formed beforehand by k_coarse.
 template <typename TV, typename TY>
 __global__ __launch_bounds__(kBlock) void k_pcorr_dot(
     const SysDev *__restrict__ sys, const InstDev *__restrict__ ins, const int2 *__restrict__ work,
     const TY *__restrict__ ybase, const double *__restrict__ hsum, int useP, TV *__restrict__ V,
     double *__restrict__ part, const GState *__restrict__ gs, const double *__restrict__ cpre) {
+  constexpr int Q = kChunk / kBlock;
   extern __shared__ double t_s[];   // d
   __shared__ double c_s[kChunk / 2 + 8];
   __shared__ double ws[kChunk];
@@ -668,24 +680,57 @@ __global__ __launch_bounds__(kBlock) void k_pcorr_dot(
   const int j = gs[i].iter;
   const int64_t e0 = (int64_t)ch * kChunk;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  int c0 = 0;
-  if (useP) {
-    const int d = S.d, zm = S.zm, nif = S.mx - 1;
-    const int sl = hs_slots(S);
-    // the coarse values this chunk needs: interfaces ilo .. ihi
+  const bool pre = useP && S.zm == 1 && !cpre;
+  int c0 = 0, ncol = 0;
+  if (useP) {   // the coarse values this chunk needs: interfaces ilo .. ihi
+    const int nif = S.mx - 1;
     const int64_t elast = (e0 + kChunk < kS ? e0 + kChunk : kS) - 1;
     const int hlo = (int)(e0 / N), hhi = (int)(elast / N);
     const int ilo = hlo / 2 - 1 < 0 ? 0 : hlo / 2 - 1;
     const int ihi = hhi / 2 + 1 > nif - 1 ? nif - 1 : hhi / 2 + 1;
-    c0 = ilo * zm;
-    const int ncol = (ihi - ilo + 1) * zm;
+    c0 = ilo * S.zm;
+    ncol = (ihi - ilo + 1) * S.zm;
+  }
+  double yv[Q], szv[Q][2], gv[2][4];
+  int szc[Q][2];
+#pragma unroll
+  for (int q = 0; q < Q; ++q) {
+    const int64_t e = e0 + threadIdx.x + q * kBlock;
+    const bool in = e < kS;
+    yv[q] = in ? (double)ybase[I.x_off + e] : 0.0;
+    szc[q][0] = szc[q][1] = -1;
+    szv[q][0] = szv[q][1] = 0.0;
+    if (pre && in) {
+      const int h = (int)(e / N), row = (int)(e - (int64_t)h * N);
+#pragma unroll
+      for (int p = 0; p < 2; ++p) {
+        szc[q][p] = S.sz_col[(size_t)h * 2 + p];
+        szv[q][p] = S.SZh[((size_t)h * 2 + p) * N + row];
+      }
+    }
+  }
+  if (pre) {
+#pragma unroll
+    for (int rr = 0; rr < 2; ++rr)
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const int r = wave + 4 * rr, l = lane + 64 * k;
+        gv[rr][k] = r < ncol && l < S.d ? S.GcR[(size_t)(c0 + r) * S.d + l] : 0.0;
+      }
+  }
+  if (useP) {
+    const int d = S.d, zm = S.zm;
+    const int sl = hs_slots(S);
     if (cpre) {   // c = G Z^T y already formed (large d: G read once)
       for (int r = threadIdx.x; r < ncol; r += kBlock) c_s[r] = cpre[I.c_off + c0 + r];
     } else {
       for (int c = threadIdx.x; c < d; c += kBlock) {
         double v = 0.0;
         if (zm == 1) {
-          for (int q = 0; q < 2 * sl; ++q) v += hsum[I.hs_off + (int64_t)2 * c * sl + q];
+          for (int q = 0; q < sl; ++q) {
+            const double2 p = *reinterpret_cast<const double2 *>(hsum + I.hs_off + (int64_t)q * S.nh + 2 * c);
+            v += p.x + p.y;
+          }
         } else {
           const int a = c / zm, e = c - a * zm;
           v = hsum[I.hs_off + (int64_t)(2 * a) * sl + e] + hsum[I.hs_off + (int64_t)(2 * a + 1) * sl + e];
@@ -693,22 +738,49 @@ __global__ __launch_bounds__(kBlock) void k_pcorr_dot(
         t_s[c] = v;
       }
       __syncthreads();
-      for (int r = wave; r < ncol; r += 4) {
-        double a = 0.0;
-        for (int l = lane; l < d; l += 64) a += S.Gc[(size_t)l * d + c0 + r] * t_s[l];
-        a = wave_sum(a);
-        if (lane == 0) c_s[r] = a;
+      if (pre) {
+#pragma unroll
+        for (int rr = 0; rr < 2; ++rr) {
+          const int r = wave + 4 * rr;
+          if (r >= ncol) continue;
+          double a = 0.0;
+#pragma unroll
+          for (int k = 0; k < 4; ++k)
+            if (lane + 64 * k < d) a += gv[rr][k] * t_s[lane + 64 * k];
+          for (int l = lane + 256; l < d; l += 64) a += S.GcR[(size_t)(c0 + r) * d + l] * t_s[l];
+          a = wave_sum(a);
+          if (lane == 0) c_s[r] = a;
+        }
+        for (int r = wave + 8; r < ncol; r += 4) {
+          double a = 0.0;
+          for (int l = lane; l < d; l += 64) a += S.GcR[(size_t)(c0 + r) * d + l] * t_s[l];
+          a = wave_sum(a);
+          if (lane == 0) c_s[r] = a;
+        }
+      } else {
+        for (int r = wave; r < ncol; r += 4) {
+          double a = 0.0;
+          for (int l = lane; l < d; l += 64) a += S.Gc[(size_t)l * d + c0 + r] * t_s[l];
+          a = wave_sum(a);
+          if (lane == 0) c_s[r] = a;
+        }
       }
     }
     __syncthreads();
   }
 #pragma unroll
-  for (int q = 0; q < kChunk / kBlock; ++q) {
+  for (int q = 0; q < Q; ++q) {
     const int64_t e = e0 + threadIdx.x + q * kBlock;
     double w = 0.0;
     if (e < kS) {
-      w = (double)ybase[I.x_off + e];
-      if (useP) {
+      w = yv[q];
+      if (pre) {
+        double a = 0.0;
+#pragma unroll
+        for (int p = 0; p < 2; ++p)
+          if (szc[q][p] >= 0) a += szv[q][p] * c_s[szc[q][p] - c0];
+        w -= a;
+      } else if (useP) {
         const int h = (int)(e / N), row = (int)(e - (int64_t)h * N);
         w -= sz_c(S, h, row, c_s, c0);
       }
@@ -1430,14 +1502,15 @@ __global__ __launch_bounds__(kBlock) void k_zt(const SysDev *__restrict__ sys, c
   const int64_t off = (x_vslot ? I.v_off + (int64_t)it * S.kS : I.x_off) + (int64_t)h * N;
   const double sc = scale ? scale[I.st_off + it] : 1.0;
   const int sl = hs_slots(S);
-  double *out = hs + I.hs_off + (int64_t)h * sl;
   if (S.zm == 1) {
+    double *out = hs + I.hs_off + h;   // slot q at out[q nh]
     double a = 0.0;
     for (int row = threadIdx.x; row < N; row += kBlock) a += (double)x[off + row];
     a = block_sum(a, lds4);
     if (threadIdx.x == 0) out[0] = a * sc;
-    for (int q = 1 + (int)threadIdx.x; q < sl; q += kBlock) out[q] = 0.0;
+    for (int q = 1 + (int)threadIdx.x; q < sl; q += kBlock) out[(int64_t)q * S.nh] = 0.0;
   } else {
+    double *out = hs + I.hs_off + (int64_t)h * sl;
     // wave w sums segments w, w + 4, ...: one row per lane (n <= 64)
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     for (int e = wave; e < S.zm; e += 4) {

@@ -362,6 +362,7 @@ void upload(smpm_handle *H, hipStream_t st) {
     d.sz_col = dupload(own, s.sz_col, st);
     d.SZh = dupload(own, s.SZh, st);
     d.Gc = dupload(own, to_colmajor<double>(s.Gc, 1, s.d, s.d), st);
+    d.GcR = s.zm == 1 ? dupload(own, s.Gc, st) : nullptr;
     d.uS = s.singular ? dupload(own, s.uS, st) : nullptr;
     d.uL = s.singular ? dupload(own, s.uL, st) : nullptr;
     // element inverses (class, element) and capacitance inverses (class),
@@ -601,7 +602,8 @@ void upload(smpm_handle *H, hipStream_t st) {
           e.xh = (int64_t)h * N;
           e.y = I.x_off + (int64_t)h * N;
           e.inst = inst;
-          e.hs = (int)(I.hs_off + (int64_t)h * slots);
+          e.hs = (int)(I.hs_off + h);
+          e.hn = s.nh;
           e.st_off = (int)I.st_off;
           gv.push_back(e);
         }
