@@ -126,13 +126,18 @@ __device__ inline void colsplit(const TO *__restrict__ blk, int R, int row, int 
 // lane: 2 in FP64, 4 in FP32) along each column of the padded column-major
 // block, NW waves splitting the columns.  Same operation and outputs as
 // k_half_gemv with one half per item.
-// Vector load of VR consecutive rows of one column: 16 bytes in FP64 and FP32,
-// 8 bytes in FP16 (so a tile stays 256 rows and its LDS partials fit).
+// Vector load of VR = 4 consecutive rows of one column: 32 bytes (two 16-byte
+// loads) in FP64, 16 in FP32, 8 in FP16, so a tile is 256 rows in every
+// precision and one tile covers a half of up to 256 rows: the workgroup then
+// reads each column's rows as one contiguous run.
 struct alignas(8) half4 {
   _Float16 v[4];
 };
+struct alignas(32) dbl4 {
+  double v[4];
+};
 template <typename TS> struct Vec16;
-template <> struct Vec16<double> { using T = double2; static constexpr int R = 2; };
+template <> struct Vec16<double> { using T = dbl4; static constexpr int R = 4; };
 template <> struct Vec16<float> { using T = float4; static constexpr int R = 4; };
 template <> struct Vec16<_Float16> { using T = half4; static constexpr int R = 4; };
 
@@ -189,13 +194,14 @@ __global__ __launch_bounds__(64 * NW) void k_half_gemv_stream(
   for (int r = 0; r < VR; ++r) acc[r] = (TO)0;
   const V *colv = reinterpret_cast<const V *>(blk + row0);
   const size_t stride = (size_t)Np / VR;
+  constexpr int U = sizeof(V) > 16 ? 4 : 8;   // columns in flight per lane
   int c = c0;
-  for (; c + 8 <= c1; c += 8) {
-    V v[8];
+  for (; c + U <= c1; c += U) {
+    V v[U];
 #pragma unroll
-    for (int u = 0; u < 8; ++u) v[u] = live ? colv[(size_t)(c + u) * stride] : V{};
+    for (int u = 0; u < U; ++u) v[u] = live ? colv[(size_t)(c + u) * stride] : V{};
 #pragma unroll
-    for (int u = 0; u < 8; ++u) {
+    for (int u = 0; u < U; ++u) {
       const TO xv = (TO)xw[c + u];
       const TS *pv = reinterpret_cast<const TS *>(&v[u]);
 #pragma unroll
