@@ -852,19 +852,27 @@ void ainv(smpm_handle *H, const double *src, double *dst, hipStream_t st, int in
 }
 
 // Setup-time autotuning of the GEMM schedules: every candidate schedule of
-// every batched list is timed with HIP events on zeroed operands (2 warm-up
-// and 5 timed launches) and the fastest is kept for the handle's lifetime.
-// Without tuning, schedules follow the launch size.
+// every batched list is timed with HIP events on zeroed operands and the
+// fastest is kept for the handle's lifetime.  The candidates are timed in
+// three interleaved rounds of 1 warm-up and 10 timed launches each, and each
+// keeps its best round: clock ramps and cold caches then hit every candidate
+// alike, not the first one timed.  Without tuning, schedules follow the
+// launch size.
 template <typename F>
-float time_launch(hipStream_t st, hipEvent_t e0, hipEvent_t e1, F &&fn) {
-  for (int r = 0; r < 2; ++r) fn();
-  HIPCHECK(hipEventRecord(e0, st));
-  for (int r = 0; r < 5; ++r) fn();
-  HIPCHECK(hipEventRecord(e1, st));
-  HIPCHECK(hipEventSynchronize(e1));
-  float ms = 0.f;
-  HIPCHECK(hipEventElapsedTime(&ms, e0, e1));
-  return ms;
+int fastest(hipStream_t st, hipEvent_t e0, hipEvent_t e1, int ncand, F &&fn) {
+  std::vector<float> best(ncand, 1e30f);
+  for (int round = 0; round < 3; ++round)
+    for (int c = 0; c < ncand; ++c) {
+      fn(c);
+      HIPCHECK(hipEventRecord(e0, st));
+      for (int r = 0; r < 10; ++r) fn(c);
+      HIPCHECK(hipEventRecord(e1, st));
+      HIPCHECK(hipEventSynchronize(e1));
+      float ms = 0.f;
+      HIPCHECK(hipEventElapsedTime(&ms, e0, e1));
+      best[c] = std::min(best[c], ms);
+    }
+  return (int)(std::min_element(best.begin(), best.end()) - best.begin());
 }
 
 void tune_schedules(smpm_handle *H, hipStream_t st) {
@@ -899,25 +907,18 @@ void tune_schedules(smpm_handle *H, hipStream_t st) {
       const GWork *w = H->g_all[op];
       const int2 *u = H->u_all[op];
       const int nu = H->n_u_all[op];
-      for (int pr = 0; pr < (H->op16 ? 3 : 2); ++pr) {
-        float best = 1e30f;
-        for (int sc = 0; sc < kNumSched; ++sc) {
-          const float ms = pr == 0
-              ? time_launch(st, e0, e1, [&] {
-                  gemm_launch<double, double, double, double>(H, sc, w, count, u, nu, H->t64, 0, nullptr, H->y64,
-                                                              op == 0 ? H->hs : nullptr, nullptr, st);
-                })
-              : pr == 1 ? time_launch(st, e0, e1, [&] {
-                  gemm_launch<float, float, float, float>(H, sc, w, count, u, nu, H->t32, 0, nullptr, H->y32,
-                                                          op == 0 ? H->hs : nullptr, nullptr, st);
-                })
-              : time_launch(st, e0, e1, [&] {
-                  gemm_launch<_Float16, float, float, float>(H, sc, w, count, u, nu, H->t32, 0, nullptr, H->y32,
-                                                             op == 0 ? H->hs : nullptr, nullptr, st);
-                });
-          if (ms < best) { best = ms; H->sched[op][pr] = sc; }
-        }
-      }
+      for (int pr = 0; pr < (H->op16 ? 3 : 2); ++pr)
+        H->sched[op][pr] = fastest(st, e0, e1, kNumSched, [&](int sc) {
+          if (pr == 0)
+            gemm_launch<double, double, double, double>(H, sc, w, count, u, nu, H->t64, 0, nullptr, H->y64,
+                                                        op == 0 ? H->hs : nullptr, nullptr, st);
+          else if (pr == 1)
+            gemm_launch<float, float, float, float>(H, sc, w, count, u, nu, H->t32, 0, nullptr, H->y32,
+                                                    op == 0 ? H->hs : nullptr, nullptr, st);
+          else
+            gemm_launch<_Float16, float, float, float>(H, sc, w, count, u, nu, H->t32, 0, nullptr, H->y32,
+                                                       op == 0 ? H->hs : nullptr, nullptr, st);
+        });
     }
     // one fused S M^-1 GEMM per iteration, or M^-1 then S: whichever is faster
     if (H->fused)
@@ -934,9 +935,14 @@ void tune_schedules(smpm_handle *H, hipStream_t st) {
         const void *x = pr == 0 ? (const void *)H->t64 : (const void *)H->t32;
         void *z = pr == 0 ? (void *)H->z64 : (void *)H->z32;
         void *y = pr == 0 ? (void *)H->y64 : (void *)H->y32;
-        const float tf = time_launch(st, e0, e1, [&] { two(2, x, y); });
-        const float t2 = time_launch(st, e0, e1, [&] { two(1, x, z); two(0, z, y); });
-        H->use_fused[pr] = tf < t2;
+        H->use_fused[pr] = fastest(st, e0, e1, 2, [&](int c) {
+          if (c == 0) {
+            two(2, x, y);
+          } else {
+            two(1, x, z);
+            two(0, z, y);
+          }
+        }) == 0;
       }
     const int cand[5] = {kSplit8, kThrXcd, kThrPlain, kCol32, kCol16};
     for (int k = 0; k < 3; ++k)
@@ -945,14 +951,11 @@ void tune_schedules(smpm_handle *H, hipStream_t st) {
         if (cnt == 0) continue;
         const double *x = k == 0 ? H->F : (k == 1 ? H->lam : H->qb);
         double *y = k == 0 ? H->v : (k == 1 ? H->qb : H->v);
-        float best = 1e30f;
-        for (int sc : cand) {
-          const float ms = time_launch(st, e0, e1, [&] {
-            if (w == 0) colgemm_w<1>(H, H->cg_all[k][w], cnt, H->cg_units[k][w], H->n_cg_units[k][w], k == 2 ? 1 : 0, x, y, st, sc);
-            else colgemm_w<kColVecs / 16>(H, H->cg_all[k][w], cnt, H->cg_units[k][w], H->n_cg_units[k][w], k == 2 ? 1 : 0, x, y, st, sc);
-          });
-          if (ms < best) { best = ms; H->cg_sched[k][w] = sc; }
-        }
+        H->cg_sched[k][w] = cand[fastest(st, e0, e1, 5, [&](int c) {
+          const int sc = cand[c];
+          if (w == 0) colgemm_w<1>(H, H->cg_all[k][w], cnt, H->cg_units[k][w], H->n_cg_units[k][w], k == 2 ? 1 : 0, x, y, st, sc);
+          else colgemm_w<kColVecs / 16>(H, H->cg_all[k][w], cnt, H->cg_units[k][w], H->n_cg_units[k][w], k == 2 ? 1 : 0, x, y, st, sc);
+        })];
       }
     HIPCHECK(hipGetLastError());
   } catch (...) {
