@@ -110,9 +110,9 @@ def matvec_kernel_name(solver):
 # each scaled by the counter's reading for a 256 MiB device copy (fetch x2.000,
 # write x1.000); see profiles/c2_schur_matvec_hbm_counters.txt.  Valid only for
 # the kernel version the passes measured (c2: the split-K k_half_gemm<double>
-# with paired K-steps, 16 and 8 waves read the same tiles; c3: the streaming
+# with paired K-steps, 16 waves; c3: the streaming
 # k_half_gemv_stream<double>, profiles/c3_schur_matvec_hbm_counters.txt).
-MATVEC_TRAFFIC = {"c2": 6.458e6, "c3": 3.584e8}
+MATVEC_TRAFFIC = {"c2": 6.482e6, "c3": 3.568e8}
 
 PEAK_HBM_GBPS = 8000.0
 PEAK_FP64_MFMA_TFLOPS = 78.6
