@@ -177,7 +177,8 @@ typedef struct {
                               share blocks only */
   int32_t setup_device;    /* setup steps of this system that ran on the device
                               (rocSOLVER / rocBLAS): 1 the u_S elimination, 2 the
-                              block-Jacobi inverses, 4 the coarse inverse */
+                              block-Jacobi inverses, 4 the coarse inverse, 8 the
+                              strip solves behind the Schur blocks W */
 } smpm_info;
 
 typedef struct smpm_handle smpm_handle;

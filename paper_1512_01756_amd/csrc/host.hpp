@@ -116,6 +116,15 @@ struct DenseBackend {
   std::function<void *(int d, int N, const double *Td, const double *Lo, const double *Up)> tri_factor;
   std::function<void(void *fact, double *v)> tri_solve;
   std::function<void(void *fact)> tri_free;
+  // Schur quarter blocks of ncl strip classes (the multi-right-hand-side strip
+  // solve with the 2N boundary injections): from each class's block-Thomas
+  // factors G[c] (m_z blocks n2 x n2, row-major, as StripClass::G), the shared
+  // z couplings lo, up (m_z x n) and the class's B-row functionals betaW[c],
+  // betaE[c] (n each), writes Wq[4 c + 2 r + col] (N x N row-major, as
+  // StripClass::Wq[r][col]).
+  std::function<void(int ncl, int n, int mz, const double *const *G, const double *lo, const double *up,
+                     const double *const *betaW, const double *const *betaE, double *const *Wq)>
+      strip_schur;
 };
 
 struct SetupOptions {

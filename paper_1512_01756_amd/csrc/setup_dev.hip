@@ -1,4 +1,5 @@
-// Device back end of the heavy dense setup steps (Sec. 2.4 and 3.2 tables):
+// Device back end of the heavy dense setup steps (Sec. 2.3, 2.4 and 3.2
+// tables): the multi-right-hand-side strip solves behind the Schur blocks W,
 // batched in-place inverses (block-Jacobi blocks, the coarse matrix) and the
 // block-tridiagonal elimination and solves of the u_S inverse iteration, on
 // rocSOLVER / rocBLAS.  The host setup calls it through DenseBackend; every
@@ -53,6 +54,24 @@ struct TriFact {
       : d(d_), N(N_), M(2 * N_), T((size_t)d_ * 4 * N_ * N_), Lo((size_t)d_ * N_ * N_),
         X((size_t)d_ * 2 * N_ * N_), v((size_t)d_ * 2 * N_), tmp(2 * N_), ipiv((size_t)d_ * 2 * N_), info(d_) {}
 };
+
+// Right-hand sides of element e's boundary injections for cn classes, laid
+// out like the host strip solve's X rows of element e ([node l][column j],
+// j fastest): 1 at (l = b n, j = e n + b) and (l = b n + n - 1, j = N + e n + b),
+// 0 elsewhere.
+__global__ void k_inject(double *__restrict__ R, int64_t total, int n, int N, int e) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= total) return;
+  const int nr = 2 * N, n2 = n * n;
+  const int64_t per = (int64_t)n2 * nr;
+  const int64_t rem = idx % per;
+  const int l = (int)(rem / nr), j = (int)(rem % nr);
+  const int b = l / n, a = l - b * n;
+  double v = 0.0;
+  if (a == 0 && j == e * n + b) v = 1.0;
+  if (a == n - 1 && j == N + e * n + b) v = 1.0;
+  R[idx] = v;
+}
 
 }  // namespace
 
@@ -192,6 +211,84 @@ struct DeviceDense {
     hcheck(hipMemcpyAsync(v, dv, sizeof(double) * d * M, hipMemcpyDeviceToHost, st), "download v");
     hcheck(hipStreamSynchronize(st), "solve");
   }
+
+  // W quarter blocks (DenseBackend::strip_schur), batched over classes.  The
+  // host's row-major X (node rows x 2N columns) is the column-major X^T with
+  // leading dimension 2N, and a row-major G_e is the column-major G_e^T, so
+  // each step of the block-Thomas solve is one strided-batched call:
+  //   forward, e = 0 .. m_z - 1:  R = injections of e;  R[(0, t)] -= sum_c
+  //     lo_e[c] X_{e-1}[(c, t)] (a GEMV over the n row groups);  X_e = G_e R;
+  //   backward, e = m_z - 2 .. 0:  q[t] = sum_c up_e[c] X_{e+1}[(c, t)];
+  //     X_e -= G_e[:, (n-1, t)] q[t];
+  // then Wq[r][col][(e, b)][.] = sum_a beta_r[a] X[(e, b, a)][col N + .], one
+  // GEMV per element row (e, b).
+  void strip_schur(int ncl, int n, int mz, const double *const *G, const double *lo, const double *up,
+                   const double *const *betaW, const double *const *betaE, double *const *Wq) {
+    std::lock_guard<std::mutex> lk(mu);
+    ensure();
+    const int n2 = n * n, N = n * mz, nr = 2 * N;
+    const size_t gsz = (size_t)mz * n2 * n2, xsz = (size_t)mz * n2 * nr, rsz = (size_t)n2 * nr;
+    const size_t per = (gsz + xsz + rsz + (size_t)n * nr + (size_t)N * nr + 2 * n) * sizeof(double);
+    const int chunk = (int)std::max<size_t>(1, std::min<size_t>(ncl, (size_t)(2ull << 30) / per));
+    DBuf<double> dG(gsz * chunk), dX(xsz * chunk), dR(rsz * chunk), dQ((size_t)n * nr * chunk),
+        dY((size_t)N * nr * chunk), dlo((size_t)mz * n), dup((size_t)mz * n), dbeta((size_t)2 * n * chunk);
+    hcheck(hipMemcpyAsync(dlo.p, lo, sizeof(double) * mz * n, hipMemcpyHostToDevice, st), "upload lo");
+    hcheck(hipMemcpyAsync(dup.p, up, sizeof(double) * mz * n, hipMemcpyHostToDevice, st), "upload up");
+    std::vector<double> hY((size_t)N * nr * chunk);
+    const double one = 1.0, zero = 0.0, minus = -1.0;
+    for (int c0 = 0; c0 < ncl; c0 += chunk) {
+      const int cn = std::min(chunk, ncl - c0);
+      for (int q = 0; q < cn; ++q) {
+        hcheck(hipMemcpyAsync(dG.p + q * gsz, G[c0 + q], sizeof(double) * gsz, hipMemcpyHostToDevice, st), "upload G");
+        hcheck(hipMemcpyAsync(dbeta.p + (size_t)2 * n * q, betaW[c0 + q], sizeof(double) * n, hipMemcpyHostToDevice, st),
+               "upload beta");
+        hcheck(hipMemcpyAsync(dbeta.p + (size_t)2 * n * q + n, betaE[c0 + q], sizeof(double) * n,
+                              hipMemcpyHostToDevice, st),
+               "upload beta");
+      }
+      const int64_t rtot = (int64_t)rsz * cn;
+      for (int e = 0; e < mz; ++e) {
+        hipLaunchKernelGGL(k_inject, dim3((unsigned)((rtot + 255) / 256)), dim3(256), 0, st, dR.p, rtot, n, N, e);
+        hcheck(hipGetLastError(), "inject");
+        if (e > 0)
+          rcheck(rocblas_dgemv_strided_batched(h, rocblas_operation_none, n * nr, n, &minus, dX.p + (size_t)(e - 1) * rsz,
+                                               n * nr, (rocblas_stride)xsz, dlo.p + (size_t)e * n, 1, 0, &one, dR.p, 1,
+                                               (rocblas_stride)rsz, cn),
+                 "gemv lo");
+        rcheck(rocblas_dgemm_strided_batched(h, rocblas_operation_none, rocblas_operation_none, nr, n2, n2, &one, dR.p,
+                                             nr, (rocblas_stride)rsz, dG.p + (size_t)e * n2 * n2, n2,
+                                             (rocblas_stride)gsz, &zero, dX.p + (size_t)e * rsz, nr,
+                                             (rocblas_stride)xsz, cn),
+               "gemm forward");
+      }
+      for (int e = mz - 2; e >= 0; --e) {
+        rcheck(rocblas_dgemv_strided_batched(h, rocblas_operation_none, n * nr, n, &one, dX.p + (size_t)(e + 1) * rsz,
+                                             n * nr, (rocblas_stride)xsz, dup.p + (size_t)e * n, 1, 0, &zero, dQ.p, 1,
+                                             (rocblas_stride)((size_t)n * nr), cn),
+               "gemv up");
+        rcheck(rocblas_dgemm_strided_batched(h, rocblas_operation_none, rocblas_operation_none, nr, n2, n, &minus, dQ.p,
+                                             nr, (rocblas_stride)((size_t)n * nr),
+                                             dG.p + (size_t)e * n2 * n2 + (size_t)(n - 1) * n, n2, (rocblas_stride)gsz,
+                                             &one, dX.p + (size_t)e * rsz, nr, (rocblas_stride)xsz, cn),
+               "gemm backward");
+      }
+      for (int r = 0; r < 2; ++r) {
+        for (int q = 0; q < cn; ++q)
+          rcheck(rocblas_dgemv_strided_batched(h, rocblas_operation_none, nr, n, &one, dX.p + q * xsz, nr,
+                                               (rocblas_stride)((size_t)n * nr), dbeta.p + (size_t)2 * n * q + r * n, 1,
+                                               0, &zero, dY.p + (size_t)q * N * nr, 1, (rocblas_stride)nr, N),
+                 "gemv beta");
+        hcheck(hipMemcpyAsync(hY.data(), dY.p, sizeof(double) * N * nr * cn, hipMemcpyDeviceToHost, st), "download W");
+        hcheck(hipStreamSynchronize(st), "W blocks");
+        for (int q = 0; q < cn; ++q)
+          for (int col = 0; col < 2; ++col) {
+            double *dst = Wq[4 * (c0 + q) + 2 * r + col];
+            for (int p = 0; p < N; ++p)
+              std::memcpy(dst + (size_t)p * N, &hY[((size_t)q * N + p) * nr + (size_t)col * N], sizeof(double) * N);
+          }
+      }
+    }
+  }
 };
 
 DeviceDense *device_dense_create(bool always) {
@@ -205,6 +302,10 @@ DeviceDense *device_dense_create(bool always) {
   dd->be.tri_free = [dd](void *f) {
     std::lock_guard<std::mutex> lk(dd->mu);
     delete static_cast<TriFact *>(f);
+  };
+  dd->be.strip_schur = [dd](int ncl, int n, int mz, const double *const *G, const double *lo, const double *up,
+                            const double *const *bw, const double *const *be, double *const *Wq) {
+    dd->strip_schur(ncl, n, mz, G, lo, up, bw, be, Wq);
   };
   return dd;
 }

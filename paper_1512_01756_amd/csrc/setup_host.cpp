@@ -678,11 +678,33 @@ void build_system(System &s, int mx, int mz, int order, const double *xb, const 
     }
     s.strip_class[j] = found;
   }
-  parallel_for((int)s.classes.size(), opt.threads, [&](int c) {
+  // The W blocks' strip solves (2 n2^2 2N flops per element and class) go
+  // to the device back end from a quarter of the usual work per host thread:
+  // they are GEMMs with little to transfer back.
+  const int ncl = (int)s.classes.size();
+  const int wthreads = std::max(1, std::min(ncl, opt.threads > 0 ? opt.threads : default_threads()));
+  const double wwork = 4.0 * mz * (double)s.n2 * s.n2 * N * ncl / wthreads;
+  const bool dev_w = opt.dense && opt.dense->strip_schur && (opt.dense->always || wwork >= 0.25 * kDeviceWork);
+  parallel_for(ncl, opt.threads, [&](int c) {
     factor_class(s, g, s.classes[c]);
-    class_schur_blocks(s, s.classes[c]);
+    if (!dev_w) class_schur_blocks(s, s.classes[c]);
     element_woodbury(s, g, s.classes[c]);
   });
+  if (dev_w) {
+    std::vector<const double *> Gp(ncl), bw(ncl), be(ncl);
+    std::vector<double *> Wp(4 * ncl);
+    for (int c = 0; c < ncl; ++c) {
+      StripClass &cl = s.classes[c];
+      Gp[c] = cl.G.data(); bw[c] = cl.betaW.data(); be[c] = cl.betaE.data();
+      for (int r = 0; r < 2; ++r)
+        for (int q = 0; q < 2; ++q) {
+          cl.Wq[r][q].assign((size_t)N * N, 0.0);
+          Wp[4 * c + 2 * r + q] = cl.Wq[r][q].data();
+        }
+    }
+    opt.dense->strip_schur(ncl, n, mz, Gp.data(), s.lo.data(), s.up.data(), bw.data(), be.data(), Wp.data());
+    s.dev_steps |= 8;
+  }
   // Schur blocks per output half, deduplicated by (strip class, row side).
   s.w_id.assign(s.nh, -1); s.w_win.assign(s.nh, 0);
   std::map<std::pair<int, int>, int> wmap;

@@ -1,7 +1,8 @@
-"""Device-side setup: the u_S block elimination and inverse iteration and the
-block-Jacobi and coarse inverses on rocSOLVER / rocBLAS, against the host
-setup (the same steps on the host threads, pinned to the oracle by the CPU
-tests) and against the oracle's solution."""
+"""Device-side setup: the strip solves behind the Schur blocks W, the u_S
+block elimination and inverse iteration and the block-Jacobi and coarse
+inverses on rocSOLVER / rocBLAS, against the host setup (the same steps on
+the host threads, pinned to the oracle by the CPU tests) and against the
+oracle's solution."""
 import numpy as np
 import pytest
 
@@ -38,8 +39,10 @@ def test_device_setup_matches_host_setup_and_oracle(k, zlabel):
     sh = P.Solver(p.xb, p.zb, p.n - 1, kwaves=p.kwaves, tune=False, zlabel=zlabel, setup="host")
     sd = P.Solver(p.xb, p.zb, p.n - 1, kwaves=p.kwaves, tune=False, zlabel=zlabel, setup="device")
     assert sh.info[0]["setup_device"] == 0
-    # every supported step ran on the device: u_S (k = 0 only), M inverses, coarse
-    assert sd.info[0]["setup_device"] == (7 if k == 0 else 6)
+    # every supported step ran on the device: u_S (k = 0 only), M inverses,
+    # coarse, W blocks
+    assert sd.info[0]["setup_device"] == (15 if k == 0 else 14)
+    assert _rel(sd.export(P.TABLE_SCHUR_DENSE), sh.export(P.TABLE_SCHUR_DENSE)) <= 1e-12
     assert _rel(sd.export(P.TABLE_BJINV_DENSE), sh.export(P.TABLE_BJINV_DENSE)) <= 1e-11
     if k == 0:
         assert _rel(sd.export(P.TABLE_U_S), sh.export(P.TABLE_U_S)) <= 1e-9
@@ -64,12 +67,14 @@ def test_device_setup_matches_host_setup_and_oracle(k, zlabel):
 def test_automatic_device_setup_on_a_large_grid():
     # 160 distinct strips of 16 elements, order 12: the u_S elimination
     # (159 sequential steps of 2N = 416, 2.2e10 flops) takes the device path by
-    # default; the batched block-Jacobi inverses stay on the host threads.
+    # default; the batched block-Jacobi inverses stay on the host threads (the
+    # W blocks' strip solves go either way with the host's thread count).
     p = workloads.random_problem(160, 16, 13, seed=7, stretch=True)
     sa = P.Solver(p.xb, p.zb, p.n - 1, tune=False)
     sh = P.Solver(p.xb, p.zb, p.n - 1, tune=False, setup="host")
     print("device steps", sa.info[0]["setup_device"])
-    assert sa.info[0]["setup_device"] == 1 and sh.info[0]["setup_device"] == 0
+    assert sa.info[0]["setup_device"] & 1 and not sa.info[0]["setup_device"] & 2
+    assert sh.info[0]["setup_device"] == 0
     assert _rel(sa.export(P.TABLE_U_S), sh.export(P.TABLE_U_S)) <= 1e-9
     f = _dev(p.f.reshape(-1))
     ua, sta, _ = sa.solve(f)
