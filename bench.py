@@ -304,8 +304,9 @@ def main():
                            "fused_S_Minv_fp64_fp32": [fp64["solver"].info[0]["fused_op"][0],
                                                       ir["solver"].info[0]["fused_op"][1]],
                            "legend": "0 split-K 16 waves, 1 split-K 8 waves, 2 LDS-staged XCD-ordered, "
-                                     "3 LDS-staged plain, 4 / 5 LDS-staged 32- / 16-row tiles with K split "
-                                     "over the waves (element lists), -1 unused; picked by timing at setup"},
+                                     "3 LDS-staged plain; matvec lists: 4 / 5 = 2 / 3 with 64-value chunks; "
+                                     "element lists: 4 / 5 LDS-staged 32- / 16-row tiles with K split over "
+                                     "the waves; -1 unused; picked by timing at setup"},
         "matvec_kernel": {"fp64_us": mv64_ms * 1e3, "fp32_us": mv32_ms * 1e3,
                           "fp64_matvecs_per_s": 1e3 / mv64_ms, "fp32_matvecs_per_s": 1e3 / mv32_ms,
                           "fp64_GBps": gbs64, "fp32_GBps": gbs32, "fp16s_us": mv16_ms * 1e3,

@@ -164,7 +164,10 @@ typedef struct {
   int32_t gemm_sched[4];   /* handle-wide GEMM schedules of the batched shared-block
                               matvecs: S FP64, S FP32, M^-1 FP64, M^-1 FP32
                               (0 split-K 16 waves, 1 split-K 8 waves, 2 LDS-staged
-                              XCD-ordered, 3 LDS-staged plain; -1 no shared blocks) */
+                              XCD-ordered, 3 LDS-staged plain, 4 / 5 the same two
+                              staging 64 K-values per chunk; -1 no shared blocks).
+                              SMPM_GEMM_SCHED = 0..5 in the environment, read at
+                              setup and load, pins them all (tests, experiments) */
   int32_t elem_sched[6];   /* same for the element-interior GEMM lists
                               (D^-1, K^-1, correction) x (<= 16, <= 64 columns),
                               with two more: 4 LDS-staged 32-row tiles, 5 16-row

@@ -444,7 +444,7 @@ __global__ __launch_bounds__(64 * KP) void k_half_gemm(
 // XCD-aware order (`units`): workgroup L runs on XCD L mod 8, and every tile
 // that reads one stored block is placed on the same XCD, so the block and the
 // windows are fetched into one L2 instead of eight.
-template <typename TS, typename TO, typename TX, typename TY, int CT>
+template <typename TS, typename TO, typename TX, typename TY, int CT, int KC>
 __global__ __launch_bounds__(256) void k_half_gemm_t(
     const GWork *__restrict__ work, const int2 *__restrict__ units, const GVec *__restrict__ gvec,
     const TX *__restrict__ xbase, int x_vslot, const double *__restrict__ scale, TY *__restrict__ ybase,
@@ -453,7 +453,7 @@ __global__ __launch_bounds__(256) void k_half_gemm_t(
   // interleaved (thread j takes k = j + TPC p), and the row pitch puts the
   // lanes that the LDS serves together (16 for 8-byte, 32 for 4-byte values)
   // in distinct bank slots for the stores and the MFMA operand reads.
-  constexpr int VT = 16 * CT, KC = 32, PITCH = VT + (sizeof(TO) == 8 ? CT : 2 * CT);
+  constexpr int VT = 16 * CT, PITCH = VT + (sizeof(TO) == 8 ? CT : 2 * CT);
   constexpr int PV = KC * VT / 256;      // staged values per thread per chunk
   constexpr int TPC = KC / PV;           // threads per window
   __shared__ TO Bs[2][KC * PITCH];

@@ -703,8 +703,9 @@ void upload(smpm_handle *H, hipStream_t st) {
 
 // GEMM schedules of the shared-block matvec (see the kernels): split K over
 // 16 or 8 waves per 16-row tile, or the LDS-staged 64-row tile in XCD-aware
-// or plain order.
-enum GemmSched { kSplit16 = 0, kSplit8 = 1, kThrXcd = 2, kThrPlain = 3, kNumSched = 4 };
+// or plain order, staging 32 K-values per chunk (or 64: kThrXcd64,
+// kThrPlain64, twice the work between the chunk barriers).
+enum GemmSched { kSplit16 = 0, kSplit8 = 1, kThrXcd = 2, kThrPlain = 3, kThrXcd64 = 4, kThrPlain64 = 5, kNumSched = 6 };
 
 // Default schedule when none was tuned (per-instance lists): by launch size.
 int gemm_default(int count, int rt16) {
@@ -726,15 +727,26 @@ void gemm_launch(smpm_handle *H, int sched, const GWork *w, int count, const int
       hipLaunchKernelGGL((k_half_gemm<TS, TO, TX, TY, 8>), dim3(count, rt16), dim3(512), 0, st, w, H->g_vec, x, vslot,
                          scale, y, hsum, gs);
       break;
+    case kThrXcd64:
+      if (units) {
+        hipLaunchKernelGGL((k_half_gemm_t<TS, TO, TX, TY, 2, 64>), dim3(nunits), dim3(256), 0, st, w, units, H->g_vec, x,
+                           vslot, scale, y, hsum, gs);
+        break;
+      }
+      [[fallthrough]];
+    case kThrPlain64:
+      hipLaunchKernelGGL((k_half_gemm_t<TS, TO, TX, TY, 2, 64>), dim3(count, (H->Nmax + 63) / 64), dim3(256), 0, st, w,
+                         (const int2 *)nullptr, H->g_vec, x, vslot, scale, y, hsum, gs);
+      break;
     case kThrXcd:
       if (units) {
-        hipLaunchKernelGGL((k_half_gemm_t<TS, TO, TX, TY, 2>), dim3(nunits), dim3(256), 0, st, w, units, H->g_vec, x, vslot,
-                           scale, y, hsum, gs);
+        hipLaunchKernelGGL((k_half_gemm_t<TS, TO, TX, TY, 2, 32>), dim3(nunits), dim3(256), 0, st, w, units, H->g_vec, x,
+                           vslot, scale, y, hsum, gs);
         break;
       }
       [[fallthrough]];
     default:
-      hipLaunchKernelGGL((k_half_gemm_t<TS, TO, TX, TY, 2>), dim3(count, (H->Nmax + 63) / 64), dim3(256), 0, st, w,
+      hipLaunchKernelGGL((k_half_gemm_t<TS, TO, TX, TY, 2, 32>), dim3(count, (H->Nmax + 63) / 64), dim3(256), 0, st, w,
                          (const int2 *)nullptr, H->g_vec, x, vslot, scale, y, hsum, gs);
   }
 }
@@ -968,11 +980,19 @@ void tune_schedules(smpm_handle *H, hipStream_t st) {
 }
 
 // Schedules of the handle's GEMM lists, timed at setup (or by size).  The
-// environment variable SMPM_ELEM_SCHED = 1..5 then pins every element-interior
-// list to one schedule (split K, LDS-staged XCD-ordered, plain, 32-row or
-// 16-row K-split tiles), for tests and experiments.
+// environment variables SMPM_GEMM_SCHED = 0..5 and SMPM_ELEM_SCHED = 1..5 then
+// pin every shared-block matvec list (split K over 16 or 8 waves, LDS-staged
+// XCD-ordered or plain, with 32- or 64-value chunks) or every element-interior
+// list (split K, LDS-staged XCD-ordered, plain, 32-row or 16-row K-split
+// tiles) to one schedule, for tests and experiments.
 void tune(smpm_handle *H, hipStream_t st) {
   tune_schedules(H, st);
+  if (const char *e = std::getenv("SMPM_GEMM_SCHED")) {
+    const int v = std::atoi(e);
+    if (v >= 0 && v < kNumSched)
+      for (int op = 0; op < 3; ++op)
+        for (int pr = 0; pr < 3; ++pr) H->sched[op][pr] = v;
+  }
   if (const char *e = std::getenv("SMPM_ELEM_SCHED")) {
     const int v = std::atoi(e);
     if (v >= kSplit8 && v <= kCol16)

@@ -226,6 +226,23 @@ def test_element_gemm_schedules_match_oracle(sched, monkeypatch, sched_refs):
         assert _rel(u[m, q], ref) <= (1e-9 if m == 0 else 1e-11), (sched, m, q)
 
 
+@pytest.mark.parametrize("sched", [0, 1, 2, 3, 4, 5])
+@pytest.mark.parametrize("precision", [P.FP64, P.FP32_IR])
+def test_shared_block_gemm_schedules_match_oracle(sched, precision, monkeypatch, sched_refs):
+    # Every schedule of the shared-block S and M^-1 GEMMs, pinned for all lists
+    # (the fused S M^-1 block included): split K over 16 or 8 waves, and the
+    # LDS-staged 64-row tile, XCD-ordered or plain, staging 32 or 64 K-values
+    # per chunk.  FP32 refinement reaches the same FP64 solution.
+    monkeypatch.setenv("SMPM_GEMM_SCHED", str(sched))
+    p = _sched_problem()
+    s, u, st = _gpu_solve(p, precision=precision, tol=1e-12)
+    assert all(v == sched for i in s.info for v in i["gemm_sched"] if v >= 0)
+    assert st["rel_residual_max"] <= 1e-12 * 1.001
+    u = u.reshape(2, 2, p.r)
+    for (m, q), ref in sched_refs.items():
+        assert _rel(u[m, q], ref) <= (1e-9 if m == 0 else 1e-11), (sched, m, q)
+
+
 def test_fp32_refinement_reaches_fp64_solution():
     p = workloads.random_problem(12, 3, 7, seed=5, stretch=True)
     s, u, st = _gpu_solve(p, precision=P.FP32_IR)
