@@ -90,7 +90,9 @@ def matvec_flops(solver):
 
 
 GEMM_KERNELS = {0: "k_half_gemm<double, 16> (split-K, 16 waves)", 1: "k_half_gemm<double, 8> (split-K, 8 waves)",
-                2: "k_half_gemm_t<double> (LDS-staged, XCD-ordered)", 3: "k_half_gemm_t<double> (LDS-staged)"}
+                2: "k_half_gemm_t<double> (LDS-staged, XCD-ordered)", 3: "k_half_gemm_t<double> (LDS-staged)",
+                4: "k_half_gemm_t<double> (LDS-staged, XCD-ordered, 64-value chunks)",
+                5: "k_half_gemm_t<double> (LDS-staged, 64-value chunks)"}
 
 
 def matvec_kernel_name(solver):
@@ -111,8 +113,9 @@ def matvec_kernel_name(solver):
 # write x1.000); see profiles/c2_schur_matvec_hbm_counters.txt.  Valid only for
 # the kernel version the passes measured (c2: the split-K k_half_gemm<double>
 # with paired K-steps, 16 waves; c3: the streaming
-# k_half_gemv_stream<double>, profiles/c3_schur_matvec_hbm_counters.txt).
-MATVEC_TRAFFIC = {"c2": 6.482e6, "c3": 3.568e8}
+# k_half_gemv_stream<double>, profiles/c3_schur_matvec_hbm_counters.txt); a run
+# whose tuner picked another kernel reports no traffic.
+MATVEC_TRAFFIC = {"c2": (GEMM_KERNELS[0], 6.482e6), "c3": ("k_half_gemv_stream<double> (distinct blocks)", 3.568e8)}
 
 PEAK_HBM_GBPS = 8000.0
 PEAK_FP64_MFMA_TFLOPS = 78.6
@@ -261,7 +264,9 @@ def main():
     else:
         roofline = {"bound": "hbm", "achieved": gbs64, "peak": PEAK_HBM_GBPS, "unit": "GB/s",
                     "frac": gbs64 / PEAK_HBM_GBPS}
-    roofline.update({"traffic": MATVEC_TRAFFIC.get(args.config), "kernel": matvec_kernel_name(s64),
+    kname = matvec_kernel_name(s64)
+    measured = MATVEC_TRAFFIC.get(args.config)
+    roofline.update({"traffic": measured[1] if measured and measured[0] == kname else None, "kernel": kname,
                      "launch_us": mv64_ms * 1e3, "algorithmic_bytes_per_launch": bytes64,
                      "algorithmic_flops_per_launch": flops64, "achieved_GBps": gbs64,
                      "achieved_TFLOPs": tflops64})
