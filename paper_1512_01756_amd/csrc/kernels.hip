@@ -122,10 +122,10 @@ __device__ inline void colsplit(const TO *__restrict__ blk, int R, int row, int 
 // of y, hsum[hs_off + slot * nh + h] (for Z^T y).
 //
 // Streaming variant for halves whose block is not shared (distinct strips):
-// one half per workgroup row tile, 16-byte loads (VR consecutive rows per
-// lane: 2 in FP64, 4 in FP32) along each column of the padded column-major
-// block, NW waves splitting the columns.  Same operation and outputs as
-// k_half_gemv with one half per item.
+// one half per workgroup row tile, vector loads of VR consecutive rows per
+// lane along each column of the padded column-major block, NW waves splitting
+// the columns.  Same operation and outputs as the MFMA GEMM with one half per
+// item.
 // Vector load of VR = 4 consecutive rows of one column: 32 bytes (two 16-byte
 // loads) in FP64, 16 in FP32, 8 in FP16, so a tile is 256 rows in every
 // precision and one tile covers a half of up to 256 rows: the workgroup then
