@@ -77,6 +77,21 @@ def test_random_poisson_matches_oracle(mx, mz, n, stretch, with_g):
     assert _rel(u, ref.u) <= 1e-9
 
 
+@pytest.mark.parametrize("mx,mz,n,k", [(4, 1, 2, 0.0), (4, 1, 3, 0.0), (5, 1, 4, 2.0), (4, 2, 2, 0.0),
+                                        (6, 1, 5, 0.0)])
+@pytest.mark.parametrize("precision", [P.FP64, P.FP32_IR])
+def test_degenerate_grids_match_oracle(mx, mz, n, k, precision):
+    # The smallest cases the method has: m_x = 4 at k = 0 (two block-Jacobi
+    # blocks, the second one short), one element per strip (no z-interface:
+    # an empty capacitance system), order 1 (n = 2 nodes per direction).
+    p = workloads.random_problem(mx, mz, n, kwaves=(k,), seed=3 + mx + n, stretch=True, with_g=True)
+    s, u, st = _gpu_solve(p, precision=precision)
+    o, ref = _oracle(p, 0, 0, tol=1e-12)
+    print(mx, mz, n, k, "stats", st, "oracle iters", ref.iters, "rel", _rel(u, ref.u))
+    assert st["rel_residual_max"] <= ACCEPT
+    assert _rel(u, ref.u) <= 1e-9
+
+
 def test_fourier_modes_batched_match_oracle():
     p = workloads.fourier_problem("f", 4.0, 8, 2, 5, my=8, ly=2.0, seed=3)
     s, u, st = _gpu_solve(p)
