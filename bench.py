@@ -144,7 +144,7 @@ def cpu_baseline(budget_s=25.0):
     return {"value": float(np.mean(mv) / solve_s), "unit": "matvecs/s", "cores": cores, "kind": "oracle",
             "sample": f"{len(times)} full DBJ solves of the c2 workload after a {setup_s:.1f} s oracle setup "
                       f"(setup not in the sample); median solve {solve_s * 1e3:.1f} ms, {r.iters} GMRES iterations",
-            "time_to_1e-10_ms": solve_s * 1e3, "setup_s": setup_s}
+            "time_to_1e-10_ms": solve_s * 1e3, "setup_s": setup_s}, r.u
 
 
 def main():
@@ -213,7 +213,8 @@ def main():
 
         ms = gpu_events_time(step, args.steps, stream)
         forms[name] = {"solver": s, "ms": ms, "stats": stats_list[-1], "setup_s": setup_s,
-                       "status": "ok" if status_list[-1] == 0 else f"status {status_list[-1]}"}
+                       "status": "ok" if status_list[-1] == 0 else f"status {status_list[-1]}",
+                       "u": u.cpu().numpy().copy()}
 
     # c4 also end to end from the physical 3-D field: transform in y, the
     # batched mode solves, inverse transform (Sec. 5).
@@ -319,7 +320,11 @@ def main():
         "roofline": roofline,
     }
     if not args.no_cpu_baseline and args.config == "c2":
-        line["cpu_baseline"] = cpu_baseline()
+        line["cpu_baseline"], u_oracle = cpu_baseline()
+        # the same right-hand side on both sides: each form's solution against
+        # the oracle's (max abs difference over max |u|, after both gauges)
+        scale = float(np.abs(u_oracle).max())
+        line["error_vs_oracle"] = {k: float(np.abs(v["u"] - u_oracle).max() / scale) for k, v in forms.items()}
     for v in forms.values():
         v["solver"].close()
     print(json.dumps(line), flush=True)

@@ -182,18 +182,23 @@ def build(grid, tau=None, kwave=0.0, zlabel=0):
 def null_vectors(sysm):
     """Left null vectors for the Poisson (k = 0) case.
 
-    u_S: S^T u = 0 with the last component pinned to 1 and the last equation
-    dropped; the remaining (k-1) x (k-1) system is the transpose of a proper
-    principal submatrix of S, invertible (Sec. 3.1), and the dropped equation
-    is the negative sum of the others because S 1 = 0.
+    u_S: the bordered system [[S^T, 1], [1^T, 0]] [u; lam] = [0; 1], solved
+    by a sparse LU.  It is nonsingular because 1^T u_S != 0 (Sec. 3.1), and
+    lam = 0 in exact arithmetic (S 1 = 0); every equation of S^T u = 0 is
+    kept, so u is as accurate as S itself (dropping one equation and pinning
+    one component instead leaves that equation satisfied only to the rounding
+    of S 1 = 0, amplified by the conditioning of the pinned system).
     u_L = A^-T B^T u_S (Claim 1, part 2), normalized.
     u_C: the unit left singular vector of the smallest singular value of C.
     Signs: each vector is scaled to have a positive sum.
     """
     S = sysm.S
     k = S.shape[0]
-    lu = spla.splu(S[:-1, :-1].T.tocsc())
-    u = np.append(lu.solve(-np.asarray(S[k - 1, :-1].todense()).ravel()), 1.0)
+    one = sp.csc_matrix(np.ones((k, 1)))
+    border = sp.bmat([[S.T.tocsc(), one], [one.T, None]], format="csc")
+    rhs = np.zeros(k + 1)
+    rhs[k] = 1.0
+    u = spla.splu(border).solve(rhs)[:k]
     uS = u / np.linalg.norm(u)
     uS *= np.sign(uS.sum())
     uL = sysm.A_solve(sysm.B.T @ uS, trans=True)
