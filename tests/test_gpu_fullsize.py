@@ -128,6 +128,33 @@ def test_c3_reduced_matches_oracle_solve(precision):
     assert err <= 1e-7
 
 
+@pytest.fixture(scope="module")
+def c2_oracle():
+    p = workloads.c2()
+    grid = smpm.Grid(p.xb, p.zb, p.n)
+    o = schur.build(grid)
+    F = smpm.rhs(grid, o.tau, p.f[0, 0])
+    return p, solve.dbj_solve(o, F, tol=1e-12), solve.dbj_solve(o, F).iters
+
+
+@pytest.mark.parametrize("precision", [P.FP64, P.FP32_IR])
+def test_c2_full_size_matches_oracle_solve(precision, c2_oracle):
+    # The benchmark's own input (128 x 8 elements, order 16, manufactured
+    # solution plus seeded forcing) against the oracle's Algorithm 2 solve of
+    # the same right-hand side, element by element.
+    p, ref, iters10 = c2_oracle
+    s = P.Solver(p.xb, p.zb, p.n - 1, precision=precision)
+    u, st, status = s.solve(torch.as_tensor(p.f.reshape(-1)).cuda())
+    u = u.cpu().numpy()
+    err = np.abs(u - ref.u).max() / np.abs(ref.u).max()
+    print("c2 full size", st, "oracle iters at 1e-10", iters10, "err", err)
+    assert status == P.OK and st["rel_residual_max"] <= ACCEPT
+    if precision == P.FP64:
+        assert abs(st["iters_max"] - iters10) <= 1
+    assert err <= 1e-9
+    s.close()
+
+
 def test_sampled_schur_blocks_full_size_c3():
     # The oracle computes W_j for a few strips of the full 256 x 16 grid and
     # the GPU matvec must reproduce the rows those strips write.
