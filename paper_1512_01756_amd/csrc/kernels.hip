@@ -707,7 +707,7 @@ __global__ __launch_bounds__(kBlock) void k_pcorr_dot(
     szc[q][0] = szc[q][1] = -1;
     szv[q][0] = szv[q][1] = 0.0;
     if (pre && in) {
-      const int h = (int)(e / N), row = (int)(e - (int64_t)h * N);
+      const int h = (int)e / N, row = (int)e - h * N;
 #pragma unroll
       for (int p = 0; p < 2; ++p) {
         szc[q][p] = S.sz_col[(size_t)h * 2 + p];
@@ -787,7 +787,7 @@ __global__ __launch_bounds__(kBlock) void k_pcorr_dot(
           if (szc[q][p] >= 0) a += szv[q][p] * c_s[szc[q][p] - c0];
         w -= a;
       } else if (useP) {
-        const int h = (int)(e / N), row = (int)(e - (int64_t)h * N);
+        const int h = (int)e / N, row = (int)e - h * N;
         w -= sz_c(S, h, row, c_s, c0);
       }
       const TV wt = (TV)w;
@@ -1369,13 +1369,13 @@ __global__ __launch_bounds__(kBlock) void k_rhs(const SysDev *__restrict__ sys,
   for (int q = 0; q < kChunk / kBlock; ++q) {
     const int64_t e = (int64_t)ch * kChunk + threadIdx.x + q * kBlock;
     if (e >= S.r) continue;
-    int64_t rem = e;
-    const int a = (int)(rem % n); rem /= n;
-    const int b = (int)(rem % n); rem /= n;
-    const int el = (int)(rem % mz);
-    const int j = (int)(rem / mz);
     double v = f[I.f_off + e];
-    if (g) {
+    if (g) {   // node (a, b) of element el of strip j; instance-local, 32-bit
+      int rem = (int)e;
+      const int a = rem % n; rem /= n;
+      const int b = rem % n; rem /= n;
+      const int el = rem % mz;
+      const int j = rem / mz;
       const double *gg = g + I.g_off;
       const double *gS = gg, *gN = gg + (size_t)mx * n, *gW = gg + (size_t)2 * mx * n, *gE = gW + (size_t)mz * n;
       double add = 0.0;
@@ -1541,8 +1541,8 @@ __global__ __launch_bounds__(kBlock) void k_add_zc(const SysDev *__restrict__ sy
   for (int q = 0; q < kChunk / kBlock; ++q) {
     const int64_t e = (int64_t)ch * kChunk + threadIdx.x + q * kBlock;
     if (e >= S.kS) continue;
-    const int h = (int)(e / N);
-    z[I.x_off + e] = (T)((double)z[I.x_off + e] + cvec[I.c_off + z_col(S, h, (int)(e - (int64_t)h * N))]);
+    const int h = (int)e / N;
+    z[I.x_off + e] = (T)((double)z[I.x_off + e] + cvec[I.c_off + z_col(S, h, (int)e - h * N)]);
   }
 }
 
@@ -1567,7 +1567,7 @@ __global__ __launch_bounds__(kBlock) void k_init_basis(const SysDev *__restrict_
     if (e >= S.kS) continue;
     double w = b[I.x_off + e];
     if (cvec) {
-      const int h = (int)(e / N), row = (int)(e - (int64_t)h * N);
+      const int h = (int)e / N, row = (int)e - h * N;
       w -= sz_c(S, h, row, cvec + I.c_off, 0);
     }
     const TV wt = (TV)w;
@@ -1647,8 +1647,8 @@ __global__ __launch_bounds__(kBlock) void k_xupdate(const SysDev *__restrict__ s
   for (int q = 0; q < kChunk / kBlock; ++q) {
     const int64_t e = (int64_t)ch * kChunk + threadIdx.x + q * kBlock;
     if (e >= S.kS) continue;
-    const int h = (int)(e / N);
-    const int row = (int)(e - (int64_t)h * N);
+    const int h = (int)e / N;
+    const int row = (int)e - h * N;
     const int zc = z_col(S, h, row);
     double v = a ? (double)a[I.x_off + e] : 0.0;
     if (mode == 2) {
@@ -1694,11 +1694,11 @@ __global__ __launch_bounds__(kBlock) void k_recover_rhs(const SysDev *__restrict
   for (int q = 0; q < kChunk / kBlock; ++q) {
     const int64_t e = (int64_t)ch * kChunk + threadIdx.x + q * kBlock;
     if (e >= S.r) continue;
-    int64_t rem = e;
-    const int a = (int)(rem % n); rem /= n;
-    const int b = (int)(rem % n); rem /= n;
-    const int el = (int)(rem % mz);
-    const int j = (int)(rem / mz);
+    int rem = (int)e;   // instance-local node index: 32-bit arithmetic
+    const int a = rem % n; rem /= n;
+    const int b = rem % n; rem /= n;
+    const int el = rem % mz;
+    const int j = rem / mz;
     double v = F[I.f_off + e];
     const int row = el * n + b;
     if (a == n - 1 && j <= mx - 2) v -= xS[I.x_off + (int64_t)(2 * j) * N + row];
