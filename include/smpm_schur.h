@@ -181,7 +181,9 @@ typedef struct {
   int32_t setup_device;    /* setup steps of this system that ran on the device
                               (rocSOLVER / rocBLAS): 1 the u_S elimination, 2 the
                               block-Jacobi inverses, 4 the coarse inverse, 8 the
-                              strip solves behind the Schur blocks W */
+                              strip solves behind the Schur blocks W, 16 the
+                              element and z-capacitance inverses of the
+                              interior elimination */
 } smpm_info;
 
 typedef struct smpm_handle smpm_handle;

@@ -154,52 +154,67 @@ static void factor_class(const System &s, const GLL &g, StripClass &cl) {
   }
 }
 
-// Element inverses and the z-interface capacitance matrix of one class:
-// A_j^-1 = D^-1 - D^-1 P K^-1 Lambda D^-1, K = I + Lambda D^-1 P.
-static void element_woodbury(const System &s, const GLL &g, StripClass &cl) {
+// Element inverses and the z-interface capacitance matrices of every class:
+// A_j^-1 = D^-1 - D^-1 P K^-1 Lambda D^-1, K = I + Lambda D^-1 P.  The
+// element operators are assembled on the host threads and inverted as one
+// batch, then the capacitance matrices (which need D^-1) likewise; each batch
+// goes to the device back end when it is large (invert_many).
+static bool invert_many(const SetupOptions &opt, int n, const std::vector<double *> &mats);
+
+static void element_woodbury_all(System &s, const GLL &g, const SetupOptions &opt) {
   const int n = s.n, n2 = s.n2, mz = s.mz;
   const int nq = 2 * n * (mz - 1);
-  cl.Dinv.assign((size_t)mz * n2 * n2, 0.0);
-  std::vector<double> Dg;
-  for (int e = 0; e < mz; ++e) {
-    const double hz = s.zb[e + 1] - s.zb[e];
-    element_diag_block(s, g, cl.hx, hz, cl.west_if, cl.east_if, e > 0, e < mz - 1, Dg);
-    if (!invert(n2, Dg.data(), n2)) throw std::runtime_error("singular element operator");
-    std::memcpy(&cl.Dinv[(size_t)e * n2 * n2], Dg.data(), sizeof(double) * n2 * n2);
+  const int ncl = (int)s.classes.size();
+  std::vector<double *> mats((size_t)ncl * mz);
+  for (int c = 0; c < ncl; ++c) {
+    s.classes[c].Dinv.assign((size_t)mz * n2 * n2, 0.0);
+    for (int e = 0; e < mz; ++e) mats[(size_t)c * mz + e] = &s.classes[c].Dinv[(size_t)e * n2 * n2];
   }
-  cl.Kinv.assign((size_t)nq * nq, 0.0);
+  parallel_for(ncl * mz, opt.threads, [&](int q) {
+    const int c = q / mz, e = q % mz;
+    const StripClass &cl = s.classes[c];
+    std::vector<double> Dg;
+    element_diag_block(s, g, cl.hx, s.zb[e + 1] - s.zb[e], cl.west_if, cl.east_if, e > 0, e < mz - 1, Dg);
+    std::memcpy(mats[q], Dg.data(), sizeof(double) * n2 * n2);
+  });
+  if (invert_many(opt, n2, mats)) s.dev_steps |= 16;
+  for (StripClass &cl : s.classes) cl.Kinv.assign((size_t)nq * nq, 0.0);
   if (nq == 0) return;
-  std::vector<double> K((size_t)nq * nq, 0.0);
-  for (int a = 0; a < nq; ++a) K[(size_t)a * nq + a] = 1.0;
   // column (interface i, part p, t): P puts a unit at element e_c, local l_c
-  for (int i = 0; i + 1 < mz; ++i)
-    for (int p = 0; p < 2; ++p)
-      for (int t = 0; t < n; ++t) {
-        const int col = (2 * i + p) * n + t;
-        const int ec = p == 0 ? i + 1 : i;
-        const int lc = p == 0 ? t : (n - 1) * n + t;
-        const double *Di = &cl.Dinv[(size_t)ec * n2 * n2];
-        // rows reading element ec: lo of interface ec (reads element ec, i.e.
-        // lo_{ec+1}) and up of interface ec-1 (reads element ec, up_{ec-1}).
-        if (ec + 1 < mz) {
-          const double *lo = &s.lo[(size_t)(ec + 1) * n];
-          for (int tr = 0; tr < n; ++tr) {
-            double a = 0.0;
-            for (int c = 0; c < n; ++c) a += lo[c] * Di[(size_t)(c * n + tr) * n2 + lc];
-            K[(size_t)((2 * ec + 0) * n + tr) * nq + col] += a;
+  parallel_for(ncl, opt.threads, [&](int c) {
+    StripClass &cl = s.classes[c];
+    std::vector<double> &K = cl.Kinv;
+    for (int a = 0; a < nq; ++a) K[(size_t)a * nq + a] = 1.0;
+    for (int i = 0; i + 1 < mz; ++i)
+      for (int p = 0; p < 2; ++p)
+        for (int t = 0; t < n; ++t) {
+          const int col = (2 * i + p) * n + t;
+          const int ec = p == 0 ? i + 1 : i;
+          const int lc = p == 0 ? t : (n - 1) * n + t;
+          const double *Di = &cl.Dinv[(size_t)ec * n2 * n2];
+          // rows reading element ec: lo of interface ec (reads element ec, i.e.
+          // lo_{ec+1}) and up of interface ec-1 (reads element ec, up_{ec-1}).
+          if (ec + 1 < mz) {
+            const double *lo = &s.lo[(size_t)(ec + 1) * n];
+            for (int tr = 0; tr < n; ++tr) {
+              double acc = 0.0;
+              for (int cc = 0; cc < n; ++cc) acc += lo[cc] * Di[(size_t)(cc * n + tr) * n2 + lc];
+              K[(size_t)((2 * ec + 0) * n + tr) * nq + col] += acc;
+            }
+          }
+          if (ec >= 1) {
+            const double *up = &s.up[(size_t)(ec - 1) * n];
+            for (int tr = 0; tr < n; ++tr) {
+              double acc = 0.0;
+              for (int cc = 0; cc < n; ++cc) acc += up[cc] * Di[(size_t)(cc * n + tr) * n2 + lc];
+              K[(size_t)((2 * (ec - 1) + 1) * n + tr) * nq + col] += acc;
+            }
           }
         }
-        if (ec >= 1) {
-          const double *up = &s.up[(size_t)(ec - 1) * n];
-          for (int tr = 0; tr < n; ++tr) {
-            double a = 0.0;
-            for (int c = 0; c < n; ++c) a += up[c] * Di[(size_t)(c * n + tr) * n2 + lc];
-            K[(size_t)((2 * (ec - 1) + 1) * n + tr) * nq + col] += a;
-          }
-        }
-      }
-  if (!invert(nq, K.data(), nq)) throw std::runtime_error("singular z-interface capacitance matrix");
-  cl.Kinv = std::move(K);
+  });
+  std::vector<double *> kmats(ncl);
+  for (int c = 0; c < ncl; ++c) kmats[c] = s.classes[c].Kinv.data();
+  if (invert_many(opt, nq, kmats)) s.dev_steps |= 16;
 }
 
 void strip_solve_woodbury(const System &s, const StripClass &cl, double *x) {
@@ -688,8 +703,8 @@ void build_system(System &s, int mx, int mz, int order, const double *xb, const 
   parallel_for(ncl, opt.threads, [&](int c) {
     factor_class(s, g, s.classes[c]);
     if (!dev_w) class_schur_blocks(s, s.classes[c]);
-    element_woodbury(s, g, s.classes[c]);
   });
+  element_woodbury_all(s, g, opt);
   if (dev_w) {
     std::vector<const double *> Gp(ncl), bw(ncl), be(ncl);
     std::vector<double *> Wp(4 * ncl);

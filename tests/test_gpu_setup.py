@@ -40,8 +40,8 @@ def test_device_setup_matches_host_setup_and_oracle(k, zlabel):
     sd = P.Solver(p.xb, p.zb, p.n - 1, kwaves=p.kwaves, tune=False, zlabel=zlabel, setup="device")
     assert sh.info[0]["setup_device"] == 0
     # every supported step ran on the device: u_S (k = 0 only), M inverses,
-    # coarse, W blocks
-    assert sd.info[0]["setup_device"] == (15 if k == 0 else 14)
+    # coarse, W blocks, element and capacitance inverses
+    assert sd.info[0]["setup_device"] == (31 if k == 0 else 30)
     assert _rel(sd.export(P.TABLE_SCHUR_DENSE), sh.export(P.TABLE_SCHUR_DENSE)) <= 1e-12
     assert _rel(sd.export(P.TABLE_BJINV_DENSE), sh.export(P.TABLE_BJINV_DENSE)) <= 1e-11
     if k == 0:
