@@ -48,6 +48,20 @@ def test_schur_rank_and_left_null_vector():
     assert abs(s.uS.sum()) > 0.1
 
 
+def test_left_null_vector_on_a_long_grid():
+    # A 24 x 4 grid of order 6 (12:1), where the slow modes make the null
+    # space hard to resolve: u_S must match the left singular vector of the
+    # smallest singular value of the dense S (a library route), and leave a
+    # residual at the rounding of S itself.  (Pinning one component and
+    # dropping one equation instead leaves 5.6e-13 here.)
+    s = _sys(24, 4, 7)
+    Sd = s.S.toarray()
+    U, sv, Vt = np.linalg.svd(Sd)
+    u_svd = U[:, -1] * np.sign(U[:, -1].sum())
+    assert 1 - abs(u_svd @ s.uS) < 1e-12
+    assert np.linalg.norm(s.uS @ Sd) < 1e-13 * np.abs(Sd).sum(axis=0).max()
+
+
 def test_claim1_relations():
     # Claim 1: u_S = E^T u_L and u_L = A^-T B^T u_S, up to scale.
     s = _sys(5, 3, 5, stretch=True)
