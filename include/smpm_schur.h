@@ -244,7 +244,7 @@ typedef enum {
   SMPM_OP_DEFLATE_Q = 3,/* y = Q x                    (k_S -> k_S), Sec. 3.3 */
   SMPM_OP_AINV = 4,     /* y = A(k)^-1 x              (r -> r),     Sec. 2.3 */
   SMPM_OP_B = 5,        /* y = B x                    (r -> k_S),   Sec. 2.3 */
-  SMPM_OP_SCHUR_RHS = 6 /* y = b~ from F (steps 1-3 of Algorithm 2; r -> k_S) */
+  SMPM_OP_SCHUR_RHS = 6 /* y = b~ from F (the projected Schur right-hand side of Algorithm 2; r -> k_S) */
 } smpm_op;
 
 /* Apply one operator of system `sys` to one vector.  x_dev, y_dev: device

@@ -2,21 +2,20 @@
 
 Test infrastructure: see the package docstring.
 
-dbj_solve follows Algorithm 2 (Sec. 3.3, "Block-Jacobi Preconditioned and
-Deflated Schur Method") in the paper's order:
-  1. b <- b - u_L u_L^T b                       (Sec. 2.4, Eq. regularize_poisson)
-  2. b_S = B A^-1 b
-  3. b_S <- b_S - u_S (u_S^T b_S)               (Eq. regularize_schur)
-  4. x_1 = GMRES(P S M^-1, P b_S)               (Eq. deflated_schur)
-  5. x_1 <- Q M^-1 x_1
-  6. x_2 = Z^T b_S - u_C u_C^T Z^T b_S
-  7. x_2 <- Z C\\x_2
-  8. x = x_1 + x_2
-  9. u = A^-1 (b - E x)
+dbj_solve is the paper's block-Jacobi preconditioned and deflated Schur
+method (Alg. 2, Sec. 3.3).  schur_rhs removes the component of the right-hand
+side along the left null vector of L (Sec. 2.4, Eq. regularize_poisson), maps
+it to the interface through A^-1 and B, and removes the component along the
+left null vector of S (Eq. regularize_schur).  schur_solve runs GMRES from a
+zero guess on the deflated, right-preconditioned operator P S M^-1
+(Eq. deflated_schur), maps the Krylov solution back through M^-1 and Q, and
+adds the coarse part Z C^+ (I - u_C u_C^T) Z^T b_S.  recover eliminates the
+interior, u = A^-1 (F - E x_S).
+
 The Poisson (k = 0) solution is defined up to a constant (Sec. 2.4); it is
-returned with zero nodal mean.  For a Helmholtz mode k > 0 (Sec. 5) the
-projections of steps 1, 3 and 6 are skipped: L - k^2 I and C(k) are
-nonsingular.
+returned with zero nodal mean.  For a Helmholtz mode k > 0 (Sec. 5) the two
+null-space projections and the coarse projection I - u_C u_C^T are skipped:
+L - k^2 I and C(k) are nonsingular.
 
 The comparison methods of Table 1 (Sec. 4) are selectable with `method`:
 'schur' GMRES(S, b_S); 'bj' GMRES(S M^-1, b_S) then M^-1; 'dbj' (above);

@@ -1679,7 +1679,7 @@ __global__ __launch_bounds__(kBlock) void k_xupdate(const SysDev *__restrict__ s
   }
 }
 
-// Recovery right-hand side (Algorithm 2, step 9): R = F~ - E x_S.
+// Recovery right-hand side of Algorithm 2: R = F~ - E x_S.
 __global__ __launch_bounds__(kBlock) void k_recover_rhs(const SysDev *__restrict__ sys,
                                                         const InstDev *__restrict__ ins,
                                                         const int2 *__restrict__ work,

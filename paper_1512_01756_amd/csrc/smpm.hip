@@ -1256,7 +1256,7 @@ void residual64(smpm_handle *H, hipStream_t st) {
                      (const double *)H->pairs);
 }
 
-// Steps 1-3 of Algorithm 2: F = f + tau g, F~ = F - u_L u_L^T F, v = A^-1 F~,
+// The Schur right-hand side of Algorithm 2: F = f + tau g, F~ = F - u_L u_L^T F, v = A^-1 F~,
 // b~ = B v - u_S u_S^T B v; then pairs = (||b~||^2, u_S . b~), and for the
 // refined form r = b~, x_S = 0.
 void stage_rhs(smpm_handle *H, const double *f, const double *g, hipStream_t st) {
@@ -1278,7 +1278,7 @@ void stage_rhs(smpm_handle *H, const double *f, const double *g, hipStream_t st)
   }
 }
 
-// Step 9 of Algorithm 2 and the gauge: u = A^-1 (F~ - E x_S), minus its mean for k = 0.
+// Interior recovery of Algorithm 2 and the gauge: u = A^-1 (F~ - E x_S), minus its mean for k = 0.
 void finish_u(smpm_handle *H, double *u, hipStream_t st) {
   hipLaunchKernelGGL(k_recover_rhs, dim3(H->n_r), dim3(kBlock), 0, st, H->d_sys, H->d_ins, H->w_r, (const double *)H->F,
                      (const double *)H->xS, H->Rr);

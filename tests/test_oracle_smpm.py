@@ -147,3 +147,65 @@ def test_rhs_corner_gets_both_sides():
     assert F[grid.node(0, 0, 0, 1)] == tau * 1
     assert F[grid.node(0, 0, 1, 0)] == tau * 10
     assert F[grid.node(1, 0, 1, 1)] == 0.0
+
+
+# A manufactured solution with Neumann data on all four sides of a grid
+# stretched in x and z (Sec. 2.2, Eq. smpm_poisson): on such a grid the
+# physical-boundary term tau n.grad u, the data term tau g (corners take both
+# sides) and the neighbour-size factors 2/h of R_ij u_j are all active, and a
+# wrong normal, sign or element size leaves an O(1) error.
+_XB = np.array([0.0, 0.35, 0.9, 1.2, 1.95, 2.4])
+_ZB = np.array([0.0, 0.1, 0.35, 1.0])
+
+
+def _mms(X, Z):
+    """u = sin(0.7x) cosh(0.5z) + 0.3 x^2 z, its Laplacian and gradient."""
+    s, c = np.sin(0.7 * X), np.cos(0.7 * X)
+    u = s * np.cosh(0.5 * Z) + 0.3 * X ** 2 * Z
+    lap = -0.24 * s * np.cosh(0.5 * Z) + 0.6 * Z
+    ux = 0.7 * c * np.cosh(0.5 * Z) + 0.6 * X * Z
+    uz = 0.5 * s * np.sinh(0.5 * Z) + 0.3 * X ** 2
+    return u, lap, ux, uz
+
+
+def _mms_problem(n, k=0.0):
+    """Grid, tau, F = f + tau g with f = (lap - k^2) u and g = n.grad u on
+    each physical side, and the exact nodal solution."""
+    grid = smpm.Grid(_XB, _ZB, n)
+    tau = smpm.default_tau(grid)
+    X, Z = grid.coords()
+    u, lap, _, _ = _mms(X, Z)
+    xi = np.polynomial.legendre.Legendre.basis(n - 1).deriv().roots()
+    xi = np.concatenate(([-1.0], xi, [1.0]))
+    xs = _XB[:-1, None] + (xi[None, :] + 1) * 0.5 * np.diff(_XB)[:, None]   # (m_x, n)
+    zs = _ZB[:-1, None] + (xi[None, :] + 1) * 0.5 * np.diff(_ZB)[:, None]   # (m_z, n)
+    g = {"S": -_mms(xs, _ZB[0])[3], "N": _mms(xs, _ZB[-1])[3],
+         "W": -_mms(_XB[0], zs)[2], "E": _mms(_XB[-1], zs)[2]}
+    F = smpm.rhs(grid, tau, lap - k * k * u, g)
+    return grid, tau, F, u
+
+
+@pytest.mark.parametrize("k", [0.0, 2.5])
+def test_manufactured_neumann_data_on_stretched_grid(k):
+    # Error relative to max|u|; for k = 0 both sides carry the zero-mean gauge.
+    errs = []
+    for n in (4, 6, 8, 10):
+        grid, tau, F, u = _mms_problem(n, k)
+        ue = u - u.mean() if k == 0.0 else u
+        uh = solve.direct_solve(grid, tau, F, k)
+        errs.append(np.max(np.abs(uh - ue)) / np.max(np.abs(ue)))
+    errs = np.array(errs)
+    assert errs[0] > 1e-5                       # the coarse grid is visibly off
+    assert np.all(np.diff(np.log10(errs)) < -1.3)
+    assert errs[-1] < 1e-10
+
+
+def test_schur_route_on_stretched_grid_with_neumann_data():
+    # Algorithm 2 on the same data reaches the manufactured solution too.
+    from oracle import schur
+    for k in (0.0, 2.5):
+        grid, tau, F, u = _mms_problem(10, k)
+        ue = u - u.mean() if k == 0.0 else u
+        res = solve.dbj_solve(schur.build(grid, tau, k), F)
+        assert res.converged
+        assert np.max(np.abs(res.u - ue)) / np.max(np.abs(ue)) < 1e-10
