@@ -151,3 +151,54 @@ def test_errors(lib):
     st = lib_.smpm_solve(s.h, None, None, None, None, None)
     assert st == P.EUNSUPPORTED
     s.close()
+
+
+def _system_offsets(data):
+    """Byte offsets of the first system's n and of its Schur block id table
+    (w_id) in a saved table file: magic, layout version, header, then the
+    fields in declaration order (vectors as a u64 length and the values)."""
+    import struct
+    pos = 8 + 4 + 24
+    off_n = pos
+    pos += 8 * 4 + 2 * 8 + 2 * 8 + 1          # n .. zm, r, kS, kwave, tau, singular
+
+    def vec(pos, size):
+        (cnt,) = struct.unpack_from("<Q", data, pos)
+        return pos + 8 + cnt * size, pos + 8
+
+    for size in (8, 8, 8, 8, 4):                # xb, zb, lo, up, strip_class
+        pos, _ = vec(pos, size)
+    (ncl,) = struct.unpack_from("<Q", data, pos)
+    pos += 8
+    for _ in range(ncl):
+        pos += 8 + 1 + 1                        # hx, west_if, east_if
+        for _ in range(5 + 4):                  # G, Dinv, Kinv, betaW, betaE, Wq[2][2]
+            pos, _ = vec(pos, 8)
+    _, off_wid = vec(pos, 4)
+    return off_n, off_wid
+
+
+def test_corrupt_table_fields_are_rejected(lib, tmp_path):
+    # A file with the right magic whose grid size or block ids were changed
+    # must be refused (EINVAL) before anything is uploaded.
+    import struct
+    xb = np.array([0, 0.4, 0.9, 1.2, 1.9, 2.3, 2.8])
+    zb = np.array([0, 0.15, 0.45, 1.0])
+    s = P.Solver(xb, zb, 4, host_only=True)
+    path = tmp_path / "tables.bin"
+    s.save(str(path))
+    s.close()
+    data = path.read_bytes()
+    off_n, off_wid = _system_offsets(data)
+    assert struct.unpack_from("<i", data, off_n)[0] == 5
+    assert 0 <= struct.unpack_from("<i", data, off_wid)[0] < 12
+    t = P.Solver(load_path=str(path), host_only=True)   # the untouched file loads
+    t.close()
+    for off, value in ((off_n, 6), (off_n, 40), (off_wid, 4096), (off_wid, -1), (8, 1)):
+        bad = bytearray(data)
+        struct.pack_into("<i", bad, off, value)
+        p2 = tmp_path / "bad.bin"
+        p2.write_bytes(bytes(bad))
+        with pytest.raises(P.SmpmError) as e:
+            P.Solver(load_path=str(p2), host_only=True)
+        assert e.value.status == P.EINVAL, (off, value)
