@@ -39,7 +39,10 @@
  * Memory: pointers named *_dev are device pointers (hipMalloc'ed, or torch
  * CUDA tensors); every other pointer is host memory.  The caller owns all
  * buffers it passes; the handle owns every operator table and workspace,
- * allocated in setup.  smpm_solve and smpm_apply allocate nothing.
+ * allocated in setup, which also captures and instantiates every HIP graph
+ * a solve launches (they hold only the handle's own buffers).  smpm_solve,
+ * smpm_solve_fourier and smpm_apply allocate nothing, whatever buffers the
+ * caller passes.
  *
  * Streams: every device call enqueues on the caller's hipStream_t (NULL = the
  * default stream).  Calls that fill host-side results synchronize that
@@ -141,9 +144,14 @@ typedef struct {
   int32_t iters_max;       /* largest per-instance GMRES iteration count */
   int32_t sweeps_max;      /* refinement sweeps (1 for FP64) */
   int32_t schur_matvecs;   /* S applications in the solve, summed over instances */
-  double rel_residual_max; /* max over instances of ||S x_S - b~|| / ||b~|| (FP64) */
+  double rel_residual_max; /* max over instances of ||P_u (S x_S - b~)|| / ||b~|| (FP64),
+                              P_u = I - u_S u_S^T at k = 0 (the identity at k > 0): the
+                              residual of the regularized system within range(S) */
   double compat_defect_max;/* max over k = 0 instances of |u_L^T F| / ||F|| */
   double solve_ms;         /* wall time of the solve (host clock, synchronized) */
+  double null_residual_max;/* max over k = 0 instances of |u_S^T (S x_S - b~)| / ||b~||:
+                              the residual's component along u_S, which no x_S reduces
+                              (the rounding of u_S and of S x_S); 0 at k > 0 */
 } smpm_stats;
 
 typedef struct {
@@ -165,9 +173,12 @@ typedef struct {
                               matvecs: S FP64, S FP32, M^-1 FP64, M^-1 FP32
                               (0 split-K 16 waves, 1 split-K 8 waves, 2 LDS-staged
                               XCD-ordered, 3 LDS-staged plain, 4 / 5 the same two
-                              staging 64 K-values per chunk; -1 no shared blocks).
-                              SMPM_GEMM_SCHED = 0..5 in the environment, read at
-                              setup and load, pins them all (tests, experiments) */
+                              staging 64 K-values per chunk, 6 / 7 split-K 8 / 16
+                              waves with a wave's K range in flight at once, for
+                              lists of at most 16 windows per item; -1 no shared
+                              blocks).  SMPM_GEMM_SCHED = 0..7 in the environment,
+                              read at setup and load, pins them all (tests,
+                              experiments) */
   int32_t elem_sched[6];   /* same for the element-interior GEMM lists
                               (D^-1, K^-1, correction) x (<= 16, <= 64 columns),
                               with two more: 4 LDS-staged 32-row tiles, 5 16-row
@@ -184,6 +195,18 @@ typedef struct {
                               strip solves behind the Schur blocks W, 16 the
                               element and z-capacitance inverses of the
                               interior elimination */
+  /* Algorithmic operator sizes (nonzero entries; "unique" counts each
+     distinct stored block once, "total" sums over the halves of one
+     instance): the Schur blocks W (Sec. 3.1), the block-Jacobi inverses
+     (Sec. 3.2), the stored S M^-1 blocks (0 when the grid has none), the
+     strip classes and the distinct element inverses of the interior
+     elimination (Sec. 2.3). */
+  int64_t nnz_W_unique, nnz_W_total;
+  int64_t nnz_M_unique, nnz_M_total;
+  int64_t nnz_F_unique, nnz_F_total;
+  int32_t strip_classes, elem_unique;
+  int32_t fused_sched[3];  /* schedule of the S M^-1 GEMM list (FP64, FP32, FP16
+                              storage; -1 none), numbered as gemm_sched */
 } smpm_info;
 
 typedef struct smpm_handle smpm_handle;
@@ -196,7 +219,9 @@ smpm_status smpm_setup(const smpm_grid *grid, const double *k, int32_t nk,
                        const smpm_opts *opts, void *hip_stream, smpm_handle **out);
 
 /* nprob independent problems, each with its own grid and one wavenumber
- * k[p] (host arrays), solved as one batch. */
+ * k[p] (host arrays), solved as one batch.  Each problem is the 2-D system
+ * of Sec. 2.2 (k = 0) or one Helmholtz mode of Sec. 5 (k > 0); batching
+ * unrelated problems is not in the paper, whose modes share one grid. */
 smpm_status smpm_setup_batch(const smpm_grid *grids, const double *k, int32_t nprob,
                              const smpm_opts *opts, void *hip_stream, smpm_handle **out);
 
@@ -217,6 +242,16 @@ smpm_status smpm_setup_fourier(const smpm_grid *grid, int32_t my, double ly, con
  * instances); EINVAL on a handle not made by smpm_setup_fourier. */
 smpm_status smpm_solve_fourier(smpm_handle *h, const double *f_dev, const double *g_dev, double *u_dev,
                                void *hip_stream, smpm_stats *stats);
+
+/* The transform in y of Sec. 5 (Alg. 3) alone, on a handle from
+ * smpm_setup_fourier: forward (inverse = 0) in_dev [m_y][r] planes ->
+ * out_dev [m_y/2 + 1][2][r], the Re and Im parts of (1/m_y) sum_j f_j
+ * exp(-2 pi i m j / m_y); inverse (inverse != 0) the other way, u_j = the
+ * real Fourier series at y_j.  A radix-2 FFT when m_y is a power of two, else
+ * a dense real DFT product.  Enqueued on hip_stream; in_dev and out_dev must
+ * not overlap. */
+smpm_status smpm_transform_y(smpm_handle *h, int32_t inverse, const double *in_dev, double *out_dev,
+                             void *hip_stream);
 
 /* Save every host table of a handle (its systems' operators, factors, coarse
  * operators and null vectors) to `path`, so that smpm_load can rebuild the
@@ -244,7 +279,10 @@ typedef enum {
   SMPM_OP_DEFLATE_Q = 3,/* y = Q x                    (k_S -> k_S), Sec. 3.3 */
   SMPM_OP_AINV = 4,     /* y = A(k)^-1 x              (r -> r),     Sec. 2.3 */
   SMPM_OP_B = 5,        /* y = B x                    (r -> k_S),   Sec. 2.3 */
-  SMPM_OP_SCHUR_RHS = 6 /* y = b~ from F (the projected Schur right-hand side of Algorithm 2; r -> k_S) */
+  SMPM_OP_SCHUR_RHS = 6,/* y = b~ from F (the projected Schur right-hand side of Algorithm 2; r -> k_S) */
+  SMPM_OP_SCHUR_BJINV = 7 /* y = S M^-1 x (k_S -> k_S), the right-preconditioned
+                           operator of Eq. (deflated_schur) without P;
+                           smpm_apply_all only */
 } smpm_op;
 
 /* Apply one operator of system `sys` to one vector.  x_dev, y_dev: device
@@ -254,13 +292,38 @@ typedef enum {
 smpm_status smpm_apply(smpm_handle *h, smpm_op op, int32_t sys, const void *x_dev,
                        void *y_dev, int32_t precision, void *hip_stream);
 
-/* Batched Schur matvec over every instance: x_dev, y_dev hold the interface
- * vectors of all instances back to back (smpm_info.x_offset * nrhs layout).
- * This is the kernel the matvec rate is measured on. */
+/* Batched Schur matvec over every instance (Sec. 3.1: S applied as a sum of
+ * per-strip block products): x_dev, y_dev hold the interface vectors of all
+ * instances back to back (smpm_info.x_offset * nrhs layout), double for
+ * SMPM_FP64, float for SMPM_FP32_IR and SMPM_FP16S_IR (the FP16 tables of an
+ * FP16S_IR handle).  Enqueued on hip_stream without a synchronization.  This
+ * is the kernel the matvec rate is measured on. */
 smpm_status smpm_schur_apply_all(smpm_handle *h, const void *x_dev, void *y_dev,
                                  int32_t precision, void *hip_stream);
 
+/* One operator over every instance at once, with the kernels and schedules
+ * the solve uses, enqueued on hip_stream without a synchronization (for
+ * timing a kernel of the solve on its own):
+ *   SMPM_OP_SCHUR        y = S x             (Sec. 3.1),  as smpm_schur_apply_all;
+ *   SMPM_OP_BJINV        y = M^-1 x          (Sec. 3.2);
+ *   SMPM_OP_SCHUR_BJINV  y = S M^-1 x        (Eq. deflated_schur without P): one
+ *                        GEMM over the stored S M^-1 blocks where the setup
+ *                        chose them (smpm_info.fused_op), else M^-1 then S
+ *                        through the handle's workspace;
+ *   SMPM_OP_AINV         y = A(k)^-1 x       (Sec. 2.3; FP64, node layout, all
+ *                        instances back to back).
+ * Interface vectors as for smpm_schur_apply_all.  x_dev and y_dev must not
+ * overlap (EINVAL when they are the same array).  EINVAL for other ops, an
+ * unknown precision, FP16 on a handle without FP16 tables, or AINV in a
+ * reduced precision. */
+smpm_status smpm_apply_all(smpm_handle *h, smpm_op op, const void *x_dev, void *y_dev,
+                           int32_t precision, void *hip_stream);
+
+/* Sizes, offsets, table counts and the schedules picked at setup of system
+ * `sys` (host struct).  Not a computation of the paper: bookkeeping for
+ * callers that lay out batched vectors (offsets) and for measurement. */
 smpm_status smpm_query(const smpm_handle *h, int32_t sys, smpm_info *info);
+/* Systems of a handle (0 for NULL). */
 int32_t smpm_num_systems(const smpm_handle *h);
 
 typedef enum {

@@ -179,6 +179,95 @@ def build(grid, tau=None, kwave=0.0, zlabel=0):
     return sysm
 
 
+# Above this Schur dimension the sparse LU of the bordered system runs out of
+# room (SuperLU's fill on the 256 x 16 grid), and the banded route is taken.
+BORDERED_MAX_K = 60000
+
+
+def _left_null_banded(S, N):
+    """u with S^T u = 0 and 1^T u = 1 (the bordered system below), through a
+    banded LU of M = S^T + e_p e_p^T.
+
+    S couples each half-interface only to the halves of its window, at most
+    two halves away, so S^T is banded with 3N - 1 sub- and super-diagonals
+    (N nodes per half).  Adding 1 to one diagonal entry p keeps every
+    equation of S^T and makes M nonsingular whenever u_S[p] != 0: if
+    M v = 0 then S^T v = -v_p e_p, whose left side is orthogonal to 1
+    (S 1 = 0) while e_p is not, so v_p = 0, and v is a null vector with a
+    zero entry at p, hence v = 0.  c = M^-1 e_p is u_S / u_S[p].
+
+    The bordered equations S^T u + lam 1 = 0, 1^T u = 1 are then solved by
+    iterative refinement with M standing in for S^T: a correction (du, dl)
+    for the residuals (r1, r2) solves S^T du + dl 1 = r1, 1^T du = r2;
+    writing S^T du = M du - e_p du_p gives du = a - dl b + du_p c with
+    a = M^-1 r1 and b = M^-1 1, where row p (c_p = 1) fixes dl = a_p / b_p
+    and 1^T du = r2 fixes du_p.  The residuals are formed with S itself, so
+    the refined u keeps every equation to the rounding of S, like the
+    bordered LU (the first solve alone leaves row p satisfied only to the
+    rounding of S 1 = 0).  p starts mid-vector and moves to the largest
+    entry of c if c_p came out small against c."""
+    k = S.shape[0]
+    bw = 3 * N - 1
+    St = S.T.tocsr()
+    coo = St.tocoo()
+    assert np.all(np.abs(coo.row - coo.col) <= bw)
+    ones = np.ones(k)
+    p = k // 2
+    for _ in range(2):
+        ab = np.zeros((3 * bw + 1, k))     # LAPACK band storage with room for the fill
+        ab[2 * bw + coo.row - coo.col, coo.col] = coo.data
+        ab[2 * bw, p] += 1.0
+        lu, piv, info = sla.lapack.dgbtrf(ab, bw, bw)
+        assert info == 0
+
+        def msolve(rhs):
+            x, inf = sla.lapack.dgbtrs(lu, bw, bw, rhs, piv)
+            assert inf == 0
+            return x
+
+        ep = np.zeros(k)
+        ep[p] = 1.0
+        c = msolve(ep)
+        if abs(c[p]) >= 1e-2 * np.abs(c).max():
+            break
+        p = int(np.argmax(np.abs(c)))
+    b = msolve(ones)
+    u = c / c.sum()
+    lam = 0.0
+    for _ in range(3):
+        r1 = -(St @ u + lam * ones)
+        r2 = 1.0 - u.sum()
+        a = msolve(r1)
+        dl = a[p] / b[p]
+        dup = (r2 - a.sum() + dl * b.sum()) / c.sum()
+        u = u + a - dl * b + dup * c
+        lam += dl
+    return u
+
+
+def left_null_S(S, N):
+    """Unit left null vector of S with a positive sum (see null_vectors);
+    N nodes per half-interface."""
+    k = S.shape[0]
+    if k > BORDERED_MAX_K:
+        u = _left_null_banded(S, N)
+    else:
+        one = sp.csc_matrix(np.ones((k, 1)))
+        border = sp.bmat([[S.T.tocsc(), one], [one.T, None]], format="csc")
+        rhs = np.zeros(k + 1)
+        rhs[k] = 1.0
+        u = spla.splu(border).solve(rhs)[:k]
+    uS = u / np.linalg.norm(u)
+    return uS * np.sign(uS.sum())
+
+
+def left_null_L(sysm, uS):
+    """u_L = A^-T B^T u_S (Claim 1, part 2), unit, positive sum."""
+    uL = sysm.A_solve(sysm.B.T @ uS, trans=True)
+    uL /= np.linalg.norm(uL)
+    return uL * np.sign(uL.sum())
+
+
 def null_vectors(sysm):
     """Left null vectors for the Poisson (k = 0) case.
 
@@ -187,23 +276,15 @@ def null_vectors(sysm):
     lam = 0 in exact arithmetic (S 1 = 0); every equation of S^T u = 0 is
     kept, so u is as accurate as S itself (dropping one equation and pinning
     one component instead leaves that equation satisfied only to the rounding
-    of S 1 = 0, amplified by the conditioning of the pinned system).
+    of S 1 = 0, amplified by the conditioning of the pinned system).  Above
+    BORDERED_MAX_K unknowns a banded LU of S^T with one diagonal entry
+    raised by 1, which also keeps every equation (_left_null_banded).
     u_L = A^-T B^T u_S (Claim 1, part 2), normalized.
     u_C: the unit left singular vector of the smallest singular value of C.
     Signs: each vector is scaled to have a positive sum.
     """
-    S = sysm.S
-    k = S.shape[0]
-    one = sp.csc_matrix(np.ones((k, 1)))
-    border = sp.bmat([[S.T.tocsc(), one], [one.T, None]], format="csc")
-    rhs = np.zeros(k + 1)
-    rhs[k] = 1.0
-    u = spla.splu(border).solve(rhs)[:k]
-    uS = u / np.linalg.norm(u)
-    uS *= np.sign(uS.sum())
-    uL = sysm.A_solve(sysm.B.T @ uS, trans=True)
-    uL /= np.linalg.norm(uL)
-    uL *= np.sign(uL.sum())
+    uS = left_null_S(sysm.S, sysm.grid.nhalf)
+    uL = left_null_L(sysm, uS)
     U, s, Vt = np.linalg.svd(sysm.C)
     sysm.extra["C_svd"] = (U, s, Vt)
     uC = U[:, -1] * np.sign(U[:, -1].sum())

@@ -106,6 +106,41 @@ def dbj_solve(sysm, F, method="dbj", tol=1e-10, maxit=300):
     return Result(u, xS, bS, it, ok, res, hist, compat)
 
 
+def null_vector_floor(sysm, F, rho=2e-13, samples=2, seed=0, tol=1e-12):
+    """How far the k = 0 solution moves when its left null vectors come from
+    S perturbed at the rounding level: the largest relative change of u (max
+    norm) over `samples` seeded perturbations S -> S (1 + rho xi) entrywise,
+    xi ~ N(0, 1), with u_S recomputed from the perturbed S and u_L from
+    Claim 1, every other operator unchanged, both solves to `tol`.
+
+    For incompatible data (u_L^T F != 0) the projected right-hand side
+    F - u_L u_L^T F moves with u_L, and u_L is determined only to about
+    rho |S| / sigma_{k-1}(S), the rounding residual of a null vector route
+    over the gap to the next singular value (Sec. 2.4 defines the solution
+    through these projections).  Two correct routes to the null vectors,
+    each leaving a residual of order rho |S|, can therefore give solutions
+    this far apart; rho = 2e-13 matches the residual either side's route
+    leaves relative to |S|_1.  The result is a floor for comparisons of
+    k = 0 solutions, not a property of either implementation."""
+    from . import schur as _sch
+    base = dbj_solve(sysm, F, tol=tol).u
+    scale = np.abs(base).max()
+    uS0, uL0 = sysm.uS, sysm.uL
+    rng = np.random.default_rng(seed)
+    worst = 0.0
+    try:
+        for _ in range(samples):
+            Sp = sysm.S.copy()
+            Sp.data = Sp.data * (1.0 + rho * rng.standard_normal(Sp.data.size))
+            sysm.uS = _sch.left_null_S(Sp, sysm.grid.nhalf)
+            sysm.uL = _sch.left_null_L(sysm, sysm.uS)
+            u = dbj_solve(sysm, F, tol=tol).u
+            worst = max(worst, float(np.abs(u - base).max() / scale))
+    finally:
+        sysm.uS, sysm.uL = uS0, uL0
+    return worst
+
+
 def direct_solve(grid, tau, F, kwave=0.0):
     """Dense least-squares solve of L(k) u = F - u_L u_L^T F (tiny grids)."""
     L = smpm.assemble_L(grid, tau, kwave).toarray()
@@ -147,12 +182,17 @@ def dense_schur_solve(grid, tau, F, kwave=0.0):
 
 
 def refine_solve(sysm, F, inner_tol=1e-6, tol=1e-10, maxit=300, max_sweeps=20,
-                 dtype=np.float32):
+                 dtype=np.float32, floor=0.0):
     """FP64 iterative refinement around a reduced-precision DBJ inner solve
     (the mixed-precision form; not in the paper).  The inner solve rounds the
     Schur blocks, the block-Jacobi inverses and every inner vector to `dtype`;
     the outer residual b_S - S x, the projections and the coarse solve stay
-    FP64.  Returns (Result, sweeps, total inner iterations)."""
+    FP64.  Each sweep starts from a zero correction and its inner GMRES stops
+    once the residual estimate is at most max(inner_tol |r|, floor tol |b_S|),
+    r the sweep's FP64 residual (floor = 0: inner_tol |r| alone).  Returns
+    (Result, sweeps, total inner iterations); Result.history holds the
+    relative FP64 residual before each sweep and extra "inner" the inner
+    iteration count of each sweep."""
     Ft, bS, compat = schur_rhs(sysm, F)
     S_lo = sysm.S.astype(dtype)
     Mi_lo = [m.astype(dtype) for m in sysm.bj_inv]
@@ -179,6 +219,7 @@ def refine_solve(sysm, F, inner_tol=1e-6, tol=1e-10, maxit=300, max_sweeps=20,
     total = 0
     sweeps = 0
     hist = []
+    inner = []
     for sweeps in range(1, max_sweeps + 1):
         r = bS - sysm.S_apply(x)
         if sysm.singular:
@@ -189,11 +230,15 @@ def refine_solve(sysm, F, inner_tol=1e-6, tol=1e-10, maxit=300, max_sweeps=20,
             sweeps -= 1
             break
         op = lambda v: P_lo(S_lo_apply(Minv_lo(v)))
-        xp, it, ok, _ = _gmres.gmres(op, P_lo(r), inner_tol, maxit, np.linalg.norm(r))
+        ref = max(np.linalg.norm(r), floor * tol * nb / inner_tol)
+        xp, it, ok, _ = _gmres.gmres(op, P_lo(r), inner_tol, maxit, ref)
         total += it
+        inner.append(it)
         d1 = sysm.Q_apply(Minv_lo(xp))
         d2 = sysm.Z(sysm.coarse(sysm.Zt(r)))
         x = x + d1 + d2
     res = np.linalg.norm(sysm.S_apply(x) - bS) / nb
     u = recover(sysm, Ft, x)
-    return Result(u, x, bS, total, res <= tol, res, hist, compat), sweeps, total
+    out = Result(u, x, bS, total, res <= tol, res, hist, compat)
+    out.inner = inner
+    return out, sweeps, total

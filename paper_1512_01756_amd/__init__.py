@@ -25,7 +25,7 @@ FLAG_ONE_KRYLOV = 4
 FLAG_HOST_SETUP = 8
 FLAG_DEVICE_SETUP = 16
 _SETUP_FLAGS = {"auto": 0, "host": FLAG_HOST_SETUP, "device": FLAG_DEVICE_SETUP}
-OP_SCHUR, OP_BJINV, OP_DEFLATE_P, OP_DEFLATE_Q, OP_AINV, OP_B, OP_SCHUR_RHS = range(7)
+OP_SCHUR, OP_BJINV, OP_DEFLATE_P, OP_DEFLATE_Q, OP_AINV, OP_B, OP_SCHUR_RHS, OP_SCHUR_BJINV = range(8)
 (TABLE_SCHUR_DENSE, TABLE_BJINV_DENSE, TABLE_COARSE_C, TABLE_U_S, TABLE_U_L, TABLE_U_C, TABLE_SZ,
  TABLE_SMINV_DENSE) = range(8)
 
@@ -55,7 +55,7 @@ class Stats(ctypes.Structure):
     _fields_ = [("instances", ctypes.c_int32), ("converged", ctypes.c_int32), ("iters_total", ctypes.c_int32),
                 ("iters_max", ctypes.c_int32), ("sweeps_max", ctypes.c_int32), ("schur_matvecs", ctypes.c_int32),
                 ("rel_residual_max", ctypes.c_double), ("compat_defect_max", ctypes.c_double),
-                ("solve_ms", ctypes.c_double)]
+                ("solve_ms", ctypes.c_double), ("null_residual_max", ctypes.c_double)]
 
     def as_dict(self):
         return {name: getattr(self, name) for name, _ in self._fields_}
@@ -68,7 +68,12 @@ class Info(ctypes.Structure):
                 ("x_offset", ctypes.c_int64), ("unique_W", ctypes.c_int32), ("unique_M", ctypes.c_int32),
                 ("bytes_W64", ctypes.c_int64), ("bytes_M64", ctypes.c_int64),
                 ("gemm_sched", ctypes.c_int32 * 4), ("elem_sched", ctypes.c_int32 * 6),
-                ("fused_op", ctypes.c_int32 * 3), ("setup_device", ctypes.c_int32)]
+                ("fused_op", ctypes.c_int32 * 3), ("setup_device", ctypes.c_int32),
+                ("nnz_W_unique", ctypes.c_int64), ("nnz_W_total", ctypes.c_int64),
+                ("nnz_M_unique", ctypes.c_int64), ("nnz_M_total", ctypes.c_int64),
+                ("nnz_F_unique", ctypes.c_int64), ("nnz_F_total", ctypes.c_int64),
+                ("strip_classes", ctypes.c_int32), ("elem_unique", ctypes.c_int32),
+                ("fused_sched", ctypes.c_int32 * 3)]
 
     def as_dict(self):
         out = {}
@@ -79,9 +84,9 @@ class Info(ctypes.Structure):
 
 
 EXPORTED = ["smpm_setup", "smpm_setup_batch", "smpm_setup_fourier", "smpm_save", "smpm_load", "smpm_solve",
-            "smpm_solve_fourier",
-            "smpm_apply", "smpm_schur_apply_all", "smpm_query", "smpm_num_systems", "smpm_export", "smpm_destroy",
-            "smpm_last_error"]
+            "smpm_solve_fourier", "smpm_transform_y",
+            "smpm_apply", "smpm_schur_apply_all", "smpm_apply_all", "smpm_query",
+            "smpm_num_systems", "smpm_export", "smpm_destroy", "smpm_last_error"]
 
 _lib = None
 
@@ -106,8 +111,10 @@ def load():
     lib.smpm_load.argtypes = [ctypes.c_char_p, ctypes.POINTER(Opts), P, ctypes.POINTER(P)]
     lib.smpm_solve.argtypes = [P, P, P, P, P, ctypes.POINTER(Stats)]
     lib.smpm_solve_fourier.argtypes = lib.smpm_solve.argtypes
+    lib.smpm_transform_y.argtypes = [P, ctypes.c_int32, P, P, P]
     lib.smpm_apply.argtypes = [P, ctypes.c_int32, ctypes.c_int32, P, P, ctypes.c_int32, P]
     lib.smpm_schur_apply_all.argtypes = [P, P, P, ctypes.c_int32, P]
+    lib.smpm_apply_all.argtypes = [P, ctypes.c_int32, P, P, ctypes.c_int32, P]
     lib.smpm_query.argtypes = [P, ctypes.c_int32, ctypes.POINTER(Info)]
     lib.smpm_num_systems.argtypes = [P]
     lib.smpm_num_systems.restype = ctypes.c_int32
@@ -116,8 +123,9 @@ def load():
     lib.smpm_destroy.restype = None
     lib.smpm_last_error.restype = ctypes.c_char_p
     for name in ("smpm_setup", "smpm_setup_batch", "smpm_setup_fourier", "smpm_save", "smpm_load", "smpm_solve",
-                 "smpm_solve_fourier",
-                 "smpm_apply", "smpm_schur_apply_all", "smpm_query", "smpm_export"):
+                 "smpm_solve_fourier", "smpm_transform_y",
+                 "smpm_apply", "smpm_schur_apply_all", "smpm_apply_all", "smpm_query",
+                 "smpm_export"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -242,12 +250,21 @@ class Solver:
             _check(status)
         return u, stats.as_dict(), status
 
+    def transform_y(self, x, y, inverse=False, stream=None):
+        """smpm_transform_y: planes [m_y, r] <-> modes [m_y/2 + 1, 2, r]."""
+        _check(self._lib.smpm_transform_y(self.h, 1 if inverse else 0, _ptr(x), _ptr(y), _stream(stream)))
+        return y
+
     def apply(self, op, sys, x, y, precision=FP64, stream=None):
         _check(self._lib.smpm_apply(self.h, op, sys, _ptr(x), _ptr(y), precision, _stream(stream)))
         return y
 
     def schur_apply_all(self, x, y, precision=FP64, stream=None):
         _check(self._lib.smpm_schur_apply_all(self.h, _ptr(x), _ptr(y), precision, _stream(stream)))
+        return y
+
+    def apply_all(self, op, x, y, precision=FP64, stream=None):
+        _check(self._lib.smpm_apply_all(self.h, op, _ptr(x), _ptr(y), precision, _stream(stream)))
         return y
 
     def export(self, table, sys=0):

@@ -144,5 +144,7 @@ void strip_solve(const System &s, const StripClass &c, double *X, int nrhs);    
 void strip_solve_woodbury(const System &s, const StripClass &c, double *x);     // A_j^-1 x (one rhs)
 void strip_solve_t(const System &s, const StripClass &c, double *X, int nrhs);  // A_j^-T X (in place)
 void schur_apply_host(const System &s, const double *x, double *y);             // y = S x
+// B A_j^-1 of a strip class: [side][row][node], 2 x N x (m_z n^2) row-major.
+void class_rhs_blocks(const System &s, const StripClass &cl, std::vector<double> &out);
 
 }  // namespace smpm

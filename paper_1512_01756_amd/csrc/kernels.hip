@@ -334,14 +334,16 @@ __device__ inline void load_pair(const TX *__restrict__ x, int64_t i0, bool in0,
 // in a fixed order.  K-steps go in pairs: in steps 2p and 2p + 1, lane group
 // q (lanes 16q .. 16q + 15) takes k = 8p + 2q and 8p + 2q + 1, so each lane
 // reads its two window values of a pair with one 2-wide load (the windows are
-// contiguous in k; the block rows are read per k as before).
-template <typename TS, typename TO, typename TX, typename TY, int KP>
+// contiguous in k; the block rows are read per k as before).  TWO: items may
+// hold more than 16 windows (a second 16-window operand); without it the
+// registers of that operand are free for a deeper U, which on short launches
+// puts a wave's whole K range in flight at once (one wait on memory).
+template <typename TS, typename TO, typename TX, typename TY, int KP, int U = (KP >= 16 ? 6 : 8), bool TWO = true>
 __global__ __launch_bounds__(64 * KP) void k_half_gemm(
     const GWork *__restrict__ work, const GVec *__restrict__ gvec, const TX *__restrict__ xbase, int x_vslot,
     const double *__restrict__ scale, TY *__restrict__ ybase, double *__restrict__ hsum,
     const GState *__restrict__ gs) {
   constexpr int VT = kGemmVecs;
-  constexpr int U = KP >= 16 ? 6 : 8;        // bounded by the 128 VGPRs of a 1024-thread block
   __shared__ double red[KP * 16 * VT];
   __shared__ WinInfo wi[VT];
   const GWork wk = work[blockIdx.x];
@@ -374,7 +376,7 @@ __global__ __launch_bounds__(64 * KP) void k_half_gemm(
   int anylive = 0;
   for (int v = 0; v < wk.vcount; ++v) anylive |= wi[v].live;
   if (!anylive) return;
-  const bool two = wk.vcount > 16;   // second 16-window operand in use
+  const bool two = TWO && wk.vcount > 16;   // second 16-window operand in use
   const int va = lane & 15, vb = 16 + (lane & 15);
   const bool la = va < wk.vcount && wi[va].live, lb = vb < wk.vcount && wi[vb].live;
   const int64_t xa = wi[va].xoff, wa = wi[va].win, xb = wi[vb].xoff, wb = wi[vb].win;
@@ -382,7 +384,7 @@ __global__ __launch_bounds__(64 * KP) void k_half_gemm(
   Acc acc0 = {0, 0, 0, 0}, acc1 = {0, 0, 0, 0};
   for (int st = s0; st < s1; st += U) {
     if (st != s0) load_a(st);
-    TO b0[U], b1[U];
+    TO b0[U], b1[TWO ? U : 1];
 #pragma unroll
     for (int u = 0; u < U; u += 2) {
       const int k = kof(st + u);   // this lane's k in step st + u; k + 1 in the next
@@ -390,14 +392,17 @@ __global__ __launch_bounds__(64 * KP) void k_half_gemm(
       const int64_t ga = wa + k, gb = wb + k;
       load_pair(xbase, xa + ga, la && kin0 && ga >= 0 && ga < kS, la && kin1 && ga + 1 >= 0 && ga + 1 < kS, b0[u],
                 b0[u + 1]);
-      load_pair(xbase, xb + gb, two && lb && kin0 && gb >= 0 && gb < kS,
-                two && lb && kin1 && gb + 1 >= 0 && gb + 1 < kS, b1[u], b1[u + 1]);
+      if constexpr (TWO)
+        load_pair(xbase, xb + gb, two && lb && kin0 && gb >= 0 && gb < kS,
+                  two && lb && kin1 && gb + 1 >= 0 && gb + 1 < kS, b1[u], b1[u + 1]);
     }
 #pragma unroll
     for (int u = 0; u < U; ++u) acc0 = Mfma<TO>::mac(a[u], b0[u], acc0);
-    if (two) {
+    if constexpr (TWO) {
+      if (two) {
 #pragma unroll
-      for (int u = 0; u < U; ++u) acc1 = Mfma<TO>::mac(a[u], b1[u], acc1);
+        for (int u = 0; u < U; ++u) acc1 = Mfma<TO>::mac(a[u], b1[u], acc1);
+      }
     }
   }
 #pragma unroll
@@ -839,11 +844,18 @@ __device__ inline void reduce_coef(const InstDev &I, const double *__restrict__ 
 __device__ inline void givens_step(const InstDev &I, int i, int j, const double *__restrict__ part1,
                                    const double *__restrict__ part2, const double *__restrict__ partn,
                                    const double *__restrict__ r1, const double *__restrict__ r2,
-                                   const double *__restrict__ rn, double *__restrict__ scale, double *__restrict__ R,
+                                   const double *__restrict__ rn, double *scale, double *__restrict__ R,
                                    double *__restrict__ cs, double *__restrict__ sn, double *__restrict__ g,
-                                   GState *__restrict__ gs, int maxit, double tol, double *sh, double *lds4) {
+                                   GState *gs, int maxit, double tol, double *sh, double *lds4,
+                                   bool pyth = false) {
+  // pyth: partn holds the partial squared norms of w after the first CGS
+  // pass; the second pass removes sum_t h2_t^2 (h2_t = s_t sum(part2_t), the
+  // second-pass coefficients of the orthonormal v_t), so |w|^2 after it is
+  // the difference (sh then holds 4 maxit + 3 doubles: h2_t^2 after the
+  // rotations).  The second pass removes only rounding-level components, so
+  // the difference loses nothing.
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  double *h = sh, *cl = sh + maxit + 2, *sl = cl + maxit;
+  double *h = sh, *cl = sh + maxit + 2, *sl = cl + maxit, *h2sq = sl + maxit;
   for (int t = threadIdx.x; t < j; t += kBlock) {
     cl[t] = cs[I.st_off + t];
     sl[t] = sn[I.st_off + t];
@@ -872,8 +884,14 @@ __device__ inline void givens_step(const InstDev &I, int i, int j, const double 
       c = wave_sum(c);
       d = wave_sum(d);
       if (lane == 0) {
-        h[t] = scale[I.st_off + t] * (a + b);
-        if (two) h[t2] = scale[I.st_off + t2] * (c + d);
+        const double st = scale[I.st_off + t];
+        h[t] = st * (a + b);
+        if (pyth) h2sq[t] = (st * b) * (st * b);
+        if (two) {
+          const double st2 = scale[I.st_off + t2];
+          h[t2] = st2 * (c + d);
+          if (pyth) h2sq[t2] = (st2 * d) * (st2 * d);
+        }
       }
     }
     for (int k = threadIdx.x; k < I.nchunk_x; k += kBlock) nn += partn[I.part_off + k];
@@ -881,6 +899,10 @@ __device__ inline void givens_step(const InstDev &I, int i, int j, const double 
   }
   __syncthreads();
   if (threadIdx.x == 0) {
+    if (pyth) {
+      for (int t = 0; t <= j; ++t) nn -= h2sq[t];
+      nn = nn > 0.0 ? nn : 0.0;
+    }
     const double beta = sqrt(nn);
     h[j + 1] = beta;
     double *gI = g + I.st_off;
@@ -981,7 +1003,15 @@ __global__ __launch_bounds__(kBlock) void k_axpy_dot(
   if (part_out) {
     ws[threadIdx.x] = a0;
     ws[threadIdx.x + kBlock] = a1;
+    if (partn) {   // |w|^2 after this pass, for the Pythagorean norm of the next
+      double a = 0.0;
+#pragma unroll
+      for (int q = 0; q < 2; ++q) a += wv[q] * wv[q];
+      a = wave_sum(a);
+      if (lane == 0) red[wave] = a;
+    }
     __syncthreads();
+    if (partn && threadIdx.x == 0) partn[I.part_off + ch] = (red[0] + red[1]) + (red[2] + red[3]);
     chunk_dots(V + I.v_off, kS, e0, j, ws, part_out + I.part_off, I.nchunk_x, ch);
   } else {
     double a = 0.0;
@@ -992,6 +1022,61 @@ __global__ __launch_bounds__(kBlock) void k_axpy_dot(
     __syncthreads();
     if (threadIdx.x == 0) partn[I.part_off + ch] = (red[0] + red[1]) + (red[2] + red[3]);
   }
+}
+
+// Classical Gram-Schmidt, second pass, with the Givens step: w -= sum_t
+// coef_t V_t (coef from the second-pass partials `part2`),
+// then the instance's last workgroup to finish (an arrival counter) takes the
+// Givens step (givens_step with the Pythagorean norm: the first pass left
+// the partial |w|^2 in partn).  The step needs only partials written by the
+// kernels before this one, so no workgroup waits for another's stores; and
+// every other workgroup has read the GMRES state before it counts itself, so
+// the last one may advance it.  Saves the separate Givens launch per
+// iteration.  Instances of one Krylov space over several instances (segments)
+// keep the separate launch.
+template <typename TV>
+__global__ __launch_bounds__(kBlock) void k_axpy_givens(
+    const SysDev *__restrict__ sys, const InstDev *__restrict__ ins, const int2 *__restrict__ work,
+    TV *__restrict__ V, const double *__restrict__ part1, const double *__restrict__ part2,
+    const double *__restrict__ partn, double *scale, double *__restrict__ R, double *__restrict__ cs,
+    double *__restrict__ sn, double *__restrict__ g, GState *gs, int *__restrict__ arrive, int maxit, double tol) {
+  extern __shared__ double dyn[];   // coef[maxit + 1], then the Givens scratch (4 maxit + 3)
+  __shared__ double lds4[4];
+  __shared__ int last_s;
+  double *coef = dyn, *sh = dyn + maxit + 1;
+  const int2 wk = work[blockIdx.x];
+  const int i = wk.x, ch = wk.y;
+  const InstDev I = ins[i];
+  const GState G = gs[i];
+  if (!G.active) return;
+  const SysDev &S = sys[I.sys];
+  const int64_t kS = S.kS;
+  const int j = G.iter;
+  reduce_coef(I, part2, scale, j, coef);
+  const int64_t e0 = (int64_t)ch * kChunk;
+  const int64_t ea = e0 + threadIdx.x, eb = ea + kBlock;
+  const bool ina = ea < kS, inb = eb < kS;
+  TV *w = V + I.v_off + (int64_t)(j + 1) * kS;
+  double a0 = ina ? (double)w[ea] : 0.0, a1 = inb ? (double)w[eb] : 0.0;
+  const TV *Vt = V + I.v_off + ea;
+#pragma unroll 4
+  for (int t = 0; t <= j; ++t, Vt += kS) {
+    const double c = coef[t];
+    if (ina) a0 -= c * (double)Vt[0];
+    if (inb) a1 -= c * (double)Vt[kBlock];
+  }
+  if (ina) w[ea] = (TV)a0;
+  if (inb) w[eb] = (TV)a1;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const int prev = atomicAdd(&arrive[i], 1);
+    last_s = prev == I.nchunk_x - 1;
+    if (last_s) arrive[i] = 0;   // ready for the next iteration's launch
+  }
+  __syncthreads();
+  if (!last_s) return;
+  givens_step(I, i, j, part1, part2, partn, nullptr, nullptr, nullptr, scale, R, cs, sn, g, gs, maxit, tol, sh, lds4,
+              true);
 }
 
 // Segment-wide sums of per-chunk partials, for instances that share one
@@ -1450,11 +1535,16 @@ __global__ __launch_bounds__(kBlock) void k_bS(const SysDev *__restrict__ sys,
   const double *beta = S.beta + (size_t)S.strip_class[strip] * 2 * n + (even ? 0 : n);
   double pd = 0.0;
   for (int row = threadIdx.x; row < N; row += kBlock) {
-    const int e = row / n, b = row - e * n;
-    const double *vr = v + I.f_off + ((int64_t)strip * mz + e) * n2 + (int64_t)b * n;
-    double a = 0.0;
-    for (int c = 0; c < n; ++c) a += beta[c] * vr[c];
-    bS[I.x_off + (int64_t)h * N + row] = a;
+    double a;
+    if (v) {
+      const int e = row / n, b = row - e * n;
+      const double *vr = v + I.f_off + ((int64_t)strip * mz + e) * n2 + (int64_t)b * n;
+      a = 0.0;
+      for (int c = 0; c < n; ++c) a += beta[c] * vr[c];
+      bS[I.x_off + (int64_t)h * N + row] = a;
+    } else {   // b_S formed already (B A^-1 GEMM): the u_S partial sums only
+      a = bS[I.x_off + (int64_t)h * N + row];
+    }
     if (S.singular) pd += S.uS[(int64_t)h * N + row] * a;
   }
   pd = block_sum(pd, lds4);
@@ -1651,7 +1741,8 @@ __global__ __launch_bounds__(kBlock) void k_xupdate(const SysDev *__restrict__ s
     const int row = (int)e - h * N;
     const int zc = z_col(S, h, row);
     double v = a ? (double)a[I.x_off + e] : 0.0;
-    if (mode == 2) {
+    if (mode == 2) {   // residual: base - a (- (S Z) c when cvec is given)
+      if (cvec) v += sz_c(S, h, row, cvec + I.c_off, 0);
       v = (base ? base[I.x_off + e] : out[I.x_off + e]) - v;
       out[I.x_off + e] = v;
       nn += v * v;
@@ -1729,23 +1820,26 @@ __global__ __launch_bounds__(kBlock) void k_sum_r(const SysDev *__restrict__ sys
 __global__ __launch_bounds__(kBlock) void k_sub_mean(const SysDev *__restrict__ sys,
                                                      const InstDev *__restrict__ ins,
                                                      const int2 *__restrict__ work,
-                                                     double *__restrict__ u, const double *__restrict__ pr) {
+                                                     const double *__restrict__ v, double *__restrict__ u,
+                                                     const double *__restrict__ pr) {
   __shared__ double lds4[4];
   __shared__ double mean_s;
   const int2 wk = work[blockIdx.x];
   const int i = wk.x, ch = wk.y;
   const InstDev I = ins[i];
   const SysDev &S = sys[I.sys];
-  if (!S.singular) return;
-  double a = 0.0;
-  for (int c = threadIdx.x; c < I.nchunk_r; c += kBlock) a += pr[I.pr_off + 2 * c];
-  a = block_sum(a, lds4);
-  if (threadIdx.x == 0) mean_s = a / (double)S.r;
-  __syncthreads();
-  const double mean = mean_s;
+  double mean = 0.0;
+  if (S.singular) {   // zero nodal mean (the Neumann problem's gauge)
+    double a = 0.0;
+    for (int c = threadIdx.x; c < I.nchunk_r; c += kBlock) a += pr[I.pr_off + 2 * c];
+    a = block_sum(a, lds4);
+    if (threadIdx.x == 0) mean_s = a / (double)S.r;
+    __syncthreads();
+    mean = mean_s;
+  }
   for (int q = 0; q < kChunk / kBlock; ++q) {
     const int64_t e = (int64_t)ch * kChunk + threadIdx.x + q * kBlock;
-    if (e < S.r) u[I.f_off + e] -= mean;
+    if (e < S.r) u[I.f_off + e] = v[I.f_off + e] - mean;
   }
 }
 
@@ -1839,6 +1933,78 @@ __global__ __launch_bounds__(256) void k_dft_gemm(const double *__restrict__ A, 
 }
 
 // p[0, n) = v.
+// The transform in y of Sec. 5 (Alg. 3) as a radix-2 FFT, for m_y a power of
+// two.  Each workgroup takes CT = kFftSlots / m_y consecutive columns (nodes
+// of the 2-D section) with all m_y planes, staged in LDS as complex values in
+// bit-reversed plane order, and runs the log2(m_y) butterfly stages there
+// (decimation in time); every column is read and written once.
+//   forward: out[(2m + q) ncol + c] = (1/m_y) sum_j in[j ncol + c] (cos, -sin)(2 pi m j / m_y),
+//            m = 0 .. m_y/2, q = 0 (Re), 1 (Im);
+//   inverse: out[j ncol + c] = sum_m w_m (Re_m cos - Im_m sin)(2 pi m j / m_y), w_0 = w_{m_y/2} = 1,
+//            else 2: the inverse transform of the Hermitian spectrum X_{m_y - m} = conj(X_m).
+// tw[k] = exp(-2 pi i k / m_y), k < m_y / 2 (the inverse uses the conjugates).
+constexpr int kFftSlots = 4096;   // complex values staged per workgroup (64 KiB)
+template <bool INV>
+__global__ __launch_bounds__(256) void k_fft_y(const double *__restrict__ in, double *__restrict__ out, int my,
+                                               int logmy, int64_t ncol, const double2 *__restrict__ tw) {
+  extern __shared__ double2 fb[];   // [m_y][CT]
+  const int CT = kFftSlots / my;
+  const int64_t c0 = (int64_t)blockIdx.x * CT;
+  const int nc = (int)min<int64_t>(CT, ncol - c0);
+  const int nk = my / 2 + 1;
+  auto brev = [&](int j) { return (int)(__brev((unsigned)j) >> (32 - logmy)); };
+  if (!INV) {
+    for (int idx = threadIdx.x; idx < my * CT; idx += blockDim.x) {
+      const int j = idx / CT, c = idx - j * CT;
+      const double v = c < nc ? in[(int64_t)j * ncol + c0 + c] : 0.0;
+      fb[brev(j) * CT + c] = make_double2(v, 0.0);
+    }
+  } else {
+    for (int idx = threadIdx.x; idx < nk * CT; idx += blockDim.x) {
+      const int m = idx / CT, c = idx - m * CT;
+      double re = 0.0, im = 0.0;
+      if (c < nc) {
+        re = in[(int64_t)(2 * m) * ncol + c0 + c];
+        im = in[(int64_t)(2 * m + 1) * ncol + c0 + c];
+      }
+      if (m == 0 || m == my / 2) im = 0.0;   // real modes
+      fb[brev(m) * CT + c] = make_double2(re, im);
+      if (m > 0 && m < my / 2) fb[brev(my - m) * CT + c] = make_double2(re, -im);
+    }
+  }
+  __syncthreads();
+  const int nb = (my / 2) * CT;   // butterflies per stage
+  for (int s = 0; s < logmy; ++s) {
+    const int half = 1 << s, stride = (my / 2) >> s;   // twiddle step for this stage
+    for (int idx = threadIdx.x; idx < nb; idx += blockDim.x) {
+      const int p = idx / CT, c = idx - p * CT;
+      const int k = p & (half - 1);
+      const int i0 = ((p >> s) << (s + 1)) + k, i1 = i0 + half;
+      double2 w = tw[k * stride];
+      if (INV) w.y = -w.y;
+      const double2 a = fb[i0 * CT + c], b = fb[i1 * CT + c];
+      const double2 t = make_double2(w.x * b.x - w.y * b.y, w.x * b.y + w.y * b.x);
+      fb[i0 * CT + c] = make_double2(a.x + t.x, a.y + t.y);
+      fb[i1 * CT + c] = make_double2(a.x - t.x, a.y - t.y);
+    }
+    __syncthreads();
+  }
+  if (!INV) {
+    const double sc = 1.0 / my;
+    for (int idx = threadIdx.x; idx < 2 * nk * CT; idx += blockDim.x) {
+      const int row = idx / CT, c = idx - row * CT;
+      if (c >= nc) continue;
+      const double2 v = fb[(row >> 1) * CT + c];
+      out[(int64_t)row * ncol + c0 + c] = ((row & 1) ? v.y : v.x) * sc;
+    }
+  } else {
+    for (int idx = threadIdx.x; idx < my * CT; idx += blockDim.x) {
+      const int j = idx / CT, c = idx - j * CT;
+      if (c < nc) out[(int64_t)j * ncol + c0 + c] = fb[j * CT + c].x;
+    }
+  }
+}
+
 __global__ __launch_bounds__(kBlock) void k_fill(double *__restrict__ p, int64_t n, double v) {
   const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (i < n) p[i] = v;

@@ -15,7 +15,10 @@
 // vectors (Sec. 2.4: shifted inverse iteration on S^T - sigma I, then
 // Claim 1 for u_L) follow.
 #include <algorithm>
+#include <chrono>
 #include <cmath>
+#include <cstdlib>
+#include <cstdio>
 #include <cstring>
 #include <map>
 #include <stdexcept>
@@ -392,6 +395,28 @@ static void class_schur_blocks(const System &s, StripClass &cl) {
     }
 }
 
+// The Schur right-hand side operator of one strip class, B A_j^-1 (Sec. 2.3:
+// b_S = B A^-1 F~, and B reads a strip only through the functionals of its
+// west and east edge rows): the functionals' rows through A_j^-T, i.e.
+// out[side][row][node] = (B A_j^-1)[row of that side][node], side 0 the
+// west rows (read by the half west of the strip), 1 the east rows; row =
+// e n + b, node the strip's local node index; 2 x N x (m_z n^2) row-major.
+void class_rhs_blocks(const System &s, const StripClass &cl, std::vector<double> &out) {
+  const int n = s.n, n2 = s.n2, mz = s.mz, N = s.N, K = mz * n2, nr = 2 * N;
+  std::vector<double> X((size_t)K * nr, 0.0);
+  for (int e = 0; e < mz; ++e)
+    for (int b = 0; b < n; ++b)
+      for (int c = 0; c < n; ++c) {
+        const size_t node = (size_t)e * n2 + b * n + c;
+        X[node * nr + e * n + b] = cl.betaW[c];
+        X[node * nr + N + e * n + b] = cl.betaE[c];
+      }
+  strip_solve_t(s, cl, X.data(), nr);
+  out.assign((size_t)2 * N * K, 0.0);
+  for (size_t node = 0; node < (size_t)K; ++node)
+    for (int q = 0; q < nr; ++q) out[(size_t)q * K + node] = X[node * nr + q];
+}
+
 // ---------------------------------------------------------------------------
 void schur_apply_host(const System &s, const double *x, double *y) {
   const int N = s.N;
@@ -626,8 +651,24 @@ static void build_fused(System &s, const SetupOptions &opt) {
   });
 }
 
+// With SMPM_SETUP_TIMES set in the environment, each step of build_system
+// prints its wall time to stderr (for measurement; the tables are the same).
+namespace {
+struct StepTimer {
+  bool on = std::getenv("SMPM_SETUP_TIMES") != nullptr;
+  std::chrono::steady_clock::time_point t = std::chrono::steady_clock::now();
+  void lap(const char *what) {
+    if (!on) return;
+    const auto now = std::chrono::steady_clock::now();
+    std::fprintf(stderr, "setup %-28s %8.1f ms\n", what, std::chrono::duration<double, std::milli>(now - t).count());
+    t = now;
+  }
+};
+}  // namespace
+
 void build_system(System &s, int mx, int mz, int order, const double *xb, const double *zb,
                   double kwave, const SetupOptions &opt) {
+  StepTimer timer;
   if (mx < 2 || mz < 1 || order < 1) throw std::invalid_argument("need mx >= 2, mz >= 1, order >= 1");
   if (!(kwave >= 0.0) || !std::isfinite(kwave)) throw std::invalid_argument("wavenumber must be finite and >= 0");
   s.n = order + 1; s.mx = mx; s.mz = mz;
@@ -704,7 +745,9 @@ void build_system(System &s, int mx, int mz, int order, const double *xb, const 
     factor_class(s, g, s.classes[c]);
     if (!dev_w) class_schur_blocks(s, s.classes[c]);
   });
+  timer.lap(dev_w ? "strip factorizations" : "strip factorizations, W");
   element_woodbury_all(s, g, opt);
+  timer.lap("element inverses");
   if (dev_w) {
     std::vector<const double *> Gp(ncl), bw(ncl), be(ncl);
     std::vector<double *> Wp(4 * ncl);
@@ -719,6 +762,7 @@ void build_system(System &s, int mx, int mz, int order, const double *xb, const 
     }
     opt.dense->strip_schur(ncl, n, mz, Gp.data(), s.lo.data(), s.up.data(), bw.data(), be.data(), Wp.data());
     s.dev_steps |= 8;
+    timer.lap("W strip solves (device)");
   }
   // Schur blocks per output half, deduplicated by (strip class, row side).
   s.w_id.assign(s.nh, -1); s.w_win.assign(s.nh, 0);
@@ -821,7 +865,9 @@ void build_system(System &s, int mx, int mz, int order, const double *xb, const 
       s.m_K[h0 + q] = nhb * N;
     }
   }
+  timer.lap("block-Jacobi");
   build_fused(s, opt);
+  timer.lap("S M^-1 blocks");
   // Deflation tables: S Z per half (two coarse columns), C = Z^T S Z.
   // Z column (interface a, segment e) is the indicator of rows e*seg .. (e+1)*seg-1
   // of both halves of interface a (seg = N / zm).  Half h's window is halves
@@ -897,8 +943,10 @@ void build_system(System &s, int mx, int mz, int order, const double *xb, const 
       for (int l = 0; l < m; ++l) w += ci[l] * uC[l];
       for (int j = 0; j < d; ++j) s.Gc[(size_t)i * d + j] = (j < m ? ci[j] : 0.0) - w * uC[j];
     }
+    timer.lap("deflation, coarse");
     // Null vectors of S and L.
     left_null_schur(s, opt);
+    timer.lap("u_S");
     // u_L = A^-T B^T u_S (Claim 1, part 2)
     std::vector<double> uL(s.r, 0.0);
     const int n2 = s.n2;
@@ -926,6 +974,7 @@ void build_system(System &s, int mx, int mz, int order, const double *xb, const 
     for (auto &a : uL) { a /= nl; sl += a; }
     if (sl < 0) for (auto &a : uL) a = -a;
     s.uL = uL;
+    timer.lap("u_L");
   }
 }
 

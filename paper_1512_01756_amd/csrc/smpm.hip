@@ -11,6 +11,7 @@
 #include <cstring>
 #include <map>
 #include <memory>
+#include <mutex>
 #include <stdexcept>
 #include <string>
 #include <vector>
@@ -167,6 +168,12 @@ struct smpm_handle {
   int sched[3][3] = {};   // [op][FP64, FP32, FP16 storage]
   int cg_sched[3][2] = {};
   int n_g_all[3] = {};
+  int g_maxv[3] = {};      // most windows in one item of each list
+  // B A^-1 per strip class (the Schur right-hand side as one GEMM), for
+  // handles whose systems all share strip classes
+  bool use_ba = false;
+  const GWork *g_ba = nullptr;
+  int n_ba = 0, ba_maxv = 0, ba_sched = 0;
   std::vector<int> g_start[3], g_cnt[3];
   HWork *w_S1 = nullptr, *w_M1 = nullptr;   // single items (streamed blocks)
   int n_S1 = 0, n_M1 = 0;
@@ -191,6 +198,7 @@ struct smpm_handle {
   double *V64 = nullptr;
   float *V32 = nullptr;
   double *part1 = nullptr, *part2 = nullptr, *partn = nullptr, *pr = nullptr, *hs = nullptr;
+  int *arrive = nullptr;   // per instance: workgroups of the second CGS pass that have finished
   double *cv = nullptr, *tb = nullptr, *scale = nullptr, *Rm = nullptr, *cs = nullptr, *sn = nullptr, *g = nullptr;
   double *ycoef = nullptr, *defect = nullptr, *pairs = nullptr, *lam = nullptr, *qb = nullptr;
   double *nb2 = nullptr;   // ||b~||^2 and u_S . b~ per instance, kept from the staging step
@@ -218,8 +226,6 @@ struct smpm_handle {
   hipGraphExec_t g_rem[2][kIterChunk] = {};
   hipGraphExec_t g_resid = nullptr, g_stage = nullptr, g_finish = nullptr;
   hipGraphExec_t g_head = nullptr, g_tail = nullptr;
-  const void *stage_f = nullptr, *stage_g = nullptr, *head_f = nullptr, *head_g = nullptr;
-  void *fin_u = nullptr, *tail_u = nullptr;
   // Iterations launched before the first convergence check: the previous
   // solve's count (-1: none yet, one chunk).
   int pred_iters[2] = {-1, -1};
@@ -239,6 +245,7 @@ struct smpm_handle {
   int my = 0;
   double ly = 0.0;
   double *dft_f = nullptr, *dft_i = nullptr, *fhat = nullptr, *ghat = nullptr, *uhat = nullptr;
+  double2 *fft_tw = nullptr;   // exp(-2 pi i k / m_y), k < m_y / 2 (m_y a power of two)
   GState *h_gs_hist = nullptr;   // pinned, [sweep][instance]
   double *h_nb = nullptr;        // pinned, ||b~||^2 and u_S . b~ per instance
 
@@ -638,6 +645,8 @@ void upload(smpm_handle *H, hipStream_t st) {
       }
     }
     for (int op = 0; op < 3; ++op) {
+      H->g_maxv[op] = 0;
+      for (const GWork &w : ga[op]) H->g_maxv[op] = std::max(H->g_maxv[op], w.vcount);
       H->g_start[op].resize(H->ninst, 0); H->g_cnt[op].resize(H->ninst, 0);
       H->g_all[op] = dupload(own, ga[op], st); H->n_g_all[op] = (int)ga[op].size();
       H->g_one[op] = dupload(own, go[op], st);
@@ -650,6 +659,62 @@ void upload(smpm_handle *H, hipStream_t st) {
       std::vector<int2> u = xcd_units(key, tiles);
       H->u_all[op] = dupload(own, u, st);
       H->n_u_all[op] = (int)u.size();
+    }
+    // B A^-1 per strip class, for the Schur right-hand side of every
+    // system in one GEMM over the strips (grids whose strips share classes:
+    // then the blocks are few and small, and the GEMM replaces the element
+    // solves of A^-1 and the B row functionals).
+    H->use_ba = H->fused;
+    if (H->use_ba) {
+      std::vector<GWork> ba;
+      for (int si = 0; si < (int)H->sys.size(); ++si) {
+        const System &s = H->sys[si];
+        const SysDev &d = H->h_sys[si];
+        const int N = s.N, K = s.mz * s.n2, ncl = (int)s.classes.size();
+        std::vector<std::vector<double>> blocks(ncl);
+        parallel_for(ncl, 0, [&](int c) { class_rhs_blocks(s, s.classes[c], blocks[c]); });
+        std::vector<double> all;
+        all.reserve((size_t)ncl * 2 * N * K);
+        for (auto &b : blocks) all.insert(all.end(), b.begin(), b.end());
+        const double *dba = dupload(own, to_colmajor_padded<double>(all, 2 * ncl, N, K, d.Np), st);
+        std::map<int, std::vector<int2>> byblk;   // block id -> (instance, strip * 2 + side)
+        for (int q = 0; q < H->nrhs; ++q)
+          for (int j = 0; j < s.mx; ++j) {
+            const int inst = si * H->nrhs + q, cls = s.strip_class[j];
+            if (j >= 1) byblk[2 * cls].push_back(make_int2(inst, 2 * j));           // west rows -> half 2 (j - 1)
+            if (j + 1 < s.mx) byblk[2 * cls + 1].push_back(make_int2(inst, 2 * j + 1));   // east rows -> half 2 j + 1
+          }
+        for (auto &kv : byblk) {
+          const std::vector<int2> &vecs = kv.second;
+          for (size_t a = 0; a < vecs.size();) {
+            GWork w{};
+            w.blk64 = dba + (size_t)kv.first * K * d.Np;
+            w.n = s.n;
+            w.N = N; w.Np = d.Np; w.K = K; w.kS = s.r; w.ident = 0;
+            w.vstart = (int)gv.size();
+            w.vcount = (int)std::min<size_t>(kGemmVecs, vecs.size() - a);
+            for (int qq = 0; qq < w.vcount; ++qq) {
+              const int inst = vecs[a + qq].x, j = vecs[a + qq].y / 2, side = vecs[a + qq].y % 2;
+              const int h = side == 0 ? 2 * (j - 1) : 2 * j + 1;
+              const InstDev &I = H->h_ins[inst];
+              GVec e{};
+              e.x0 = I.f_off;
+              e.win = (int64_t)j * K;
+              e.y = I.x_off + (int64_t)h * N;
+              e.inst = inst;
+              e.hs = (int)(I.hs_off + h);
+              e.hn = s.nh;
+              e.st_off = (int)I.st_off;
+              gv.push_back(e);
+            }
+            ba.push_back(w);
+            a += w.vcount;
+          }
+        }
+      }
+      H->g_ba = dupload(own, ba, st);
+      H->n_ba = (int)ba.size();
+      for (const GWork &w : ba) H->ba_maxv = std::max(H->ba_maxv, w.vcount);
     }
     H->g_vec = dupload(own, gv, st);
   }
@@ -667,6 +732,8 @@ void upload(smpm_handle *H, hipStream_t st) {
   if (H->precision == SMPM_FP64) H->V64 = dalloc<double>(own, v_off);
   else H->V32 = dalloc<float>(own, v_off);
   H->part1 = dalloc<double>(own, part_off); H->part2 = dalloc<double>(own, part_off); H->partn = dalloc<double>(own, part_off);
+  H->arrive = dalloc<int>(own, H->ninst);
+  HIPCHECK(hipMemsetAsync(H->arrive, 0, sizeof(int) * H->ninst, st));
   H->pr = dalloc<double>(own, pr_off); H->hs = dalloc<double>(own, hs_off);
   H->cv = dalloc<double>(own, c_off); H->tb = dalloc<double>(own, c_off);
   H->scale = dalloc<double>(own, st_off); H->cs = dalloc<double>(own, st_off); H->sn = dalloc<double>(own, st_off);
@@ -705,7 +772,13 @@ void upload(smpm_handle *H, hipStream_t st) {
 // 16 or 8 waves per 16-row tile, or the LDS-staged 64-row tile in XCD-aware
 // or plain order, staging 32 K-values per chunk (or 64: kThrXcd64,
 // kThrPlain64, twice the work between the chunk barriers).
-enum GemmSched { kSplit16 = 0, kSplit8 = 1, kThrXcd = 2, kThrPlain = 3, kThrXcd64 = 4, kThrPlain64 = 5, kNumSched = 6 };
+// kSplit8Deep / kSplit16Deep: split K over 8 or 16 waves with 24 or 18
+// K-steps of loads in flight per wave, for lists whose items hold at most
+// 16 windows (others run kSplit8 under these ids).
+enum GemmSched {
+  kSplit16 = 0, kSplit8 = 1, kThrXcd = 2, kThrPlain = 3, kThrXcd64 = 4, kThrPlain64 = 5, kSplit8Deep = 6,
+  kSplit16Deep = 7, kNumSched = 8
+};
 
 // Default schedule when none was tuned (per-instance lists): by launch size.
 int gemm_default(int count, int rt16) {
@@ -716,9 +789,19 @@ int gemm_default(int count, int rt16) {
 
 template <typename TS, typename TO, typename TX, typename TY>
 void gemm_launch(smpm_handle *H, int sched, const GWork *w, int count, const int2 *units, int nunits, const TX *x,
-                 int vslot, const double *scale, TY *y, double *hsum, const GState *gs, hipStream_t st) {
+                 int vslot, const double *scale, TY *y, double *hsum, const GState *gs, hipStream_t st,
+                 bool narrow) {
   const int rt16 = (H->Nmax + 15) / 16;
+  if ((sched == kSplit8Deep || sched == kSplit16Deep) && !narrow) sched = kSplit8;
   switch (sched) {
+    case kSplit8Deep:
+      hipLaunchKernelGGL((k_half_gemm<TS, TO, TX, TY, 8, 24, false>), dim3(count, rt16), dim3(512), 0, st, w, H->g_vec,
+                         x, vslot, scale, y, hsum, gs);
+      break;
+    case kSplit16Deep:
+      hipLaunchKernelGGL((k_half_gemm<TS, TO, TX, TY, 16, 18, false>), dim3(count, rt16), dim3(1024), 0, st, w,
+                         H->g_vec, x, vslot, scale, y, hsum, gs);
+      break;
     case kSplit16:
       hipLaunchKernelGGL((k_half_gemm<TS, TO, TX, TY, 16>), dim3(count, rt16), dim3(1024), 0, st, w, H->g_vec, x, vslot,
                          scale, y, hsum, gs);
@@ -767,7 +850,7 @@ void gemv_ts(smpm_handle *H, int op, const TX *x, int vslot, const double *scale
       const int prec = sizeof(TS) == 8 ? 0 : (sizeof(TS) == 4 ? 1 : 2);
       const int sched = inst < 0 ? H->sched[op][prec] : gemm_default(count, (H->Nmax + 15) / 16);
       gemm_launch<TS, TO, TX, TY>(H, sched, w, count, inst < 0 ? H->u_all[op] : nullptr, H->n_u_all[op], x, vslot,
-                                  scale, y, hsum, gs, st);
+                                  scale, y, hsum, gs, st, H->g_maxv[op] <= 16);
     }
   }
   // halves with their own block: streaming kernel (S or M^-1 only)
@@ -894,6 +977,7 @@ void tune_schedules(smpm_handle *H, hipStream_t st) {
   for (int k = 0; k < 3; ++k)
     for (int w = 0; w < 2; ++w) H->cg_sched[k][w] = -1;
   for (int pr = 0; pr < 3; ++pr) H->use_fused[pr] = H->fused && (int64_t)H->n_g_all[2] * rt16 < 2048;
+  H->ba_sched = gemm_default(H->n_ba, rt16);
   if (H->no_tune) return;
   const int rmax = std::max(H->n2_max, H->nq_max);
   for (int k = 0; k < 3; ++k)
@@ -923,15 +1007,23 @@ void tune_schedules(smpm_handle *H, hipStream_t st) {
         H->sched[op][pr] = fastest(st, e0, e1, kNumSched, [&](int sc) {
           if (pr == 0)
             gemm_launch<double, double, double, double>(H, sc, w, count, u, nu, H->t64, 0, nullptr, H->y64,
-                                                        op == 0 ? H->hs : nullptr, nullptr, st);
+                                                        op == 0 ? H->hs : nullptr, nullptr, st,
+                H->g_maxv[op] <= 16);
           else if (pr == 1)
             gemm_launch<float, float, float, float>(H, sc, w, count, u, nu, H->t32, 0, nullptr, H->y32,
-                                                    op == 0 ? H->hs : nullptr, nullptr, st);
+                                                    op == 0 ? H->hs : nullptr, nullptr, st,
+                H->g_maxv[op] <= 16);
           else
             gemm_launch<_Float16, float, float, float>(H, sc, w, count, u, nu, H->t32, 0, nullptr, H->y32,
-                                                       op == 0 ? H->hs : nullptr, nullptr, st);
+                                                       op == 0 ? H->hs : nullptr, nullptr, st,
+                H->g_maxv[op] <= 16);
         });
     }
+    if (H->use_ba)   // the Schur right-hand side GEMM (FP64 only)
+      H->ba_sched = fastest(st, e0, e1, kNumSched, [&](int sc) {
+        gemm_launch<double, double, double, double>(H, sc, H->g_ba, H->n_ba, nullptr, 0, (const double *)H->F, 0,
+                                                    nullptr, H->bS, nullptr, nullptr, st, H->ba_maxv <= 16);
+      });
     // one fused S M^-1 GEMM per iteration, or M^-1 then S: whichever is faster
     if (H->fused)
       for (int pr = 0; pr < (H->op16 ? 3 : 2); ++pr) {
@@ -980,7 +1072,7 @@ void tune_schedules(smpm_handle *H, hipStream_t st) {
 }
 
 // Schedules of the handle's GEMM lists, timed at setup (or by size).  The
-// environment variables SMPM_GEMM_SCHED = 0..5 and SMPM_ELEM_SCHED = 1..5 then
+// environment variables SMPM_GEMM_SCHED = 0..7 and SMPM_ELEM_SCHED = 1..5 then
 // pin every shared-block matvec list (split K over 16 or 8 waves, LDS-staged
 // XCD-ordered or plain, with 32- or 64-value chunks) or every element-interior
 // list (split K, LDS-staged XCD-ordered, plain, 32-row or 16-row K-split
@@ -1132,7 +1224,19 @@ struct Inner {
       hipLaunchKernelGGL(k_seg_reduce, dim3(norm ? 1 : maxit + 1, H->ninst), dim3(kBlock), 0, st, H->d_ins, part, out,
                          (const GState *)H->gs, norm);
     };
-    if (seg) seg_reduce(H->part1, H->sr1, 0);
+    if (!seg) {
+      // CGS2 in two passes; the second takes the Givens step in its last
+      // workgroup (the first pass leaves |w|^2 for the Pythagorean norm)
+      hipLaunchKernelGGL((k_axpy_dot<T>), dim3(H->n_x), dim3(kBlock), shm_dot, st, H->d_sys, H->d_ins, H->w_x, Vb,
+                         (const double *)H->part1, H->part2, H->partn, (const double *)H->scale,
+                         (const GState *)H->gs, (const double *)nullptr);
+      hipLaunchKernelGGL((k_axpy_givens<T>), dim3(H->n_x), dim3(kBlock), sizeof(double) * (5 * maxit + 4), st,
+                         H->d_sys, H->d_ins, H->w_x, Vb, (const double *)H->part1, (const double *)H->part2,
+                         (const double *)H->partn, H->scale, H->Rm, H->cs, H->sn, H->g, H->gs, H->arrive, maxit,
+                         tol(H));
+      return;
+    }
+    seg_reduce(H->part1, H->sr1, 0);
     hipLaunchKernelGGL((k_axpy_dot<T>), dim3(H->n_x), dim3(kBlock), shm_dot, st, H->d_sys, H->d_ins, H->w_x, Vb,
                        (const double *)H->part1, H->part2, (double *)nullptr, (const double *)H->scale, (const GState *)H->gs,
                        seg ? (const double *)H->sr1 : nullptr);
@@ -1178,6 +1282,23 @@ struct Inner {
     }
     hipLaunchKernelGGL(k_xupdate<T>, dim3(H->n_x), dim3(kBlock), 0, st, H->d_sys, H->d_ins, H->w_x, P == 0 ? 0 : 1,
                        xfin, cfin, H->xS, (double *)nullptr, (const double *)nullptr);
+  }
+
+  // The iteration graphs: kIterChunk iterations, and 1 .. kIterChunk - 1.
+  static void capture_loops(smpm_handle *H, hipStream_t st) {
+    if (!H->g_loop[P])
+      H->g_loop[P] = capture(st, [&] {
+        for (int c = 0; c < kIterChunk; ++c) iteration(H, st);
+      });
+    for (int n = 1; n < kIterChunk; ++n)
+      if (!H->g_rem[P][n])
+        H->g_rem[P][n] = capture(st, [&] {
+          for (int c = 0; c < n; ++c) iteration(H, st);
+        });
+    if (P == 1) {   // the refinement's inner solves (FP64 folds these into its head and tail)
+      if (!H->g_pre[P]) H->g_pre[P] = capture(st, [&] { pre(H, st); });
+      if (!H->g_post[P]) H->g_post[P] = capture(st, [&] { post(H, st); });
+    }
   }
 
   // Enqueue n GMRES iterations: whole chunks, then one graph of the rest.
@@ -1245,8 +1366,19 @@ struct Inner {
 };
 
 // r = b~ - S x_S (FP64); pairs[2 i] = ||r||^2, pairs[2 i + 1] = u_S . r; then
-// r <- r - u_S (u_S . r) (the refinement residual, k = 0).
-void residual64(smpm_handle *H, hipStream_t st) {
+// r <- r - u_S (u_S . r) (the refinement residual, k = 0).  after_dbj: the
+// final check of an FP64 DBJ solve, right after its assembly left S z in
+// y64 and the coarse correction c in cv with x_S = z + Z c: then
+// S x_S = S z + (S Z) c needs no further Schur product, and r is only
+// measured, not projected.
+void residual64(smpm_handle *H, hipStream_t st, bool after_dbj = false) {
+  if (after_dbj) {
+    hipLaunchKernelGGL(k_xupdate<double>, dim3(H->n_x), dim3(kBlock), 0, st, H->d_sys, H->d_ins, H->w_x, 2,
+                       (const double *)H->y64, (const double *)H->cv, H->rb, H->partn, (const double *)H->bS);
+    hipLaunchKernelGGL(k_reduce_pairs, dim3(H->ninst), dim3(kBlock), 0, st, H->d_ins, (const double *)H->partn,
+                       H->pairs, (double *)nullptr);
+    return;
+  }
   gemv<double, double, double>(H, 0, H->xS, 0, nullptr, H->y64, nullptr, nullptr, st);
   hipLaunchKernelGGL(k_xupdate<double>, dim3(H->n_x), dim3(kBlock), 0, st, H->d_sys, H->d_ins, H->w_x, 2,
                      (const double *)H->y64, (const double *)nullptr, H->rb, H->partn, (const double *)H->bS);
@@ -1256,14 +1388,29 @@ void residual64(smpm_handle *H, hipStream_t st) {
                      (const double *)H->pairs);
 }
 
-// The Schur right-hand side of Algorithm 2: F = f + tau g, F~ = F - u_L u_L^T F, v = A^-1 F~,
-// b~ = B v - u_S u_S^T B v; then pairs = (||b~||^2, u_S . b~), and for the
-// refined form r = b~, x_S = 0.
-void stage_rhs(smpm_handle *H, const double *f, const double *g, hipStream_t st) {
+// F = f + tau g into the handle's F: the one step of the solve that reads the
+// caller's f and g.  It is launched on its own, ahead of the captured graphs,
+// so that the graphs never hold a caller pointer and are captured once per
+// handle whatever buffers the caller passes.
+void read_rhs(smpm_handle *H, const double *f, const double *g, hipStream_t st) {
   hipLaunchKernelGGL(k_rhs, dim3(H->n_r), dim3(kBlock), 0, st, H->d_sys, H->d_ins, H->w_r, f, g, H->F, H->pr);
+}
+
+// The rest of the Schur right-hand side of Algorithm 2, from F = f + tau g:
+// F~ = F - u_L u_L^T F, v = A^-1 F~, b~ = B v - u_S u_S^T B v; then pairs =
+// (||b~||^2, u_S . b~), and for the refined form r = b~, x_S = 0.
+void stage_rhs(smpm_handle *H, hipStream_t st) {
   hipLaunchKernelGGL(k_proj_r, dim3(H->n_r), dim3(kBlock), 0, st, H->d_sys, H->d_ins, H->w_r, H->F, H->pr, H->defect);
-  ainv(H, H->F, H->v, st);
-  hipLaunchKernelGGL(k_bS, dim3(H->n_h), dim3(kBlock), 0, st, H->d_sys, H->d_ins, H->w_h, (const double *)H->v, H->bS, H->hs);
+  if (H->use_ba) {   // b_S = (B A^-1) F~ in one GEMM over the strips, then u_S . b_S per half
+    gemm_launch<double, double, double, double>(H, H->ba_sched, H->g_ba, H->n_ba, nullptr, 0, (const double *)H->F,
+                                                0, nullptr, H->bS, nullptr, nullptr, st, H->ba_maxv <= 16);
+    hipLaunchKernelGGL(k_bS, dim3(H->n_h), dim3(kBlock), 0, st, H->d_sys, H->d_ins, H->w_h, (const double *)nullptr,
+                       H->bS, H->hs);
+  } else {
+    ainv(H, H->F, H->v, st);
+    hipLaunchKernelGGL(k_bS, dim3(H->n_h), dim3(kBlock), 0, st, H->d_sys, H->d_ins, H->w_h, (const double *)H->v, H->bS,
+                       H->hs);
+  }
   hipLaunchKernelGGL(k_proj_x, dim3(H->n_x), dim3(kBlock), 0, st, H->d_sys, H->d_ins, H->w_x, H->bS, (const double *)H->hs);
   hipLaunchKernelGGL(k_xupdate<double>, dim3(H->n_x), dim3(kBlock), 0, st, H->d_sys, H->d_ins, H->w_x, 2,
                      (const double *)nullptr, (const double *)nullptr, H->bS, H->partn, (const double *)nullptr);
@@ -1278,13 +1425,73 @@ void stage_rhs(smpm_handle *H, const double *f, const double *g, hipStream_t st)
   }
 }
 
-// Interior recovery of Algorithm 2 and the gauge: u = A^-1 (F~ - E x_S), minus its mean for k = 0.
-void finish_u(smpm_handle *H, double *u, hipStream_t st) {
+// Interior recovery of Algorithm 2: v = A^-1 (F~ - E x_S) into the handle's v
+// (free once b~ is formed) and the partial sums of its mean.
+void finish_u(smpm_handle *H, hipStream_t st) {
   hipLaunchKernelGGL(k_recover_rhs, dim3(H->n_r), dim3(kBlock), 0, st, H->d_sys, H->d_ins, H->w_r, (const double *)H->F,
                      (const double *)H->xS, H->Rr);
-  ainv(H, H->Rr, u, st);
-  hipLaunchKernelGGL(k_sum_r, dim3(H->n_r), dim3(kBlock), 0, st, H->d_sys, H->d_ins, H->w_r, (const double *)u, H->pr);
-  hipLaunchKernelGGL(k_sub_mean, dim3(H->n_r), dim3(kBlock), 0, st, H->d_sys, H->d_ins, H->w_r, u, (const double *)H->pr);
+  ainv(H, H->Rr, H->v, st);
+  hipLaunchKernelGGL(k_sum_r, dim3(H->n_r), dim3(kBlock), 0, st, H->d_sys, H->d_ins, H->w_r, (const double *)H->v, H->pr);
+}
+
+// The gauge and the output: u = v minus its nodal mean for k = 0, u = v for
+// k > 0.  Like read_rhs, launched outside the captured graphs, as the one
+// step that writes the caller's u.
+void write_u(smpm_handle *H, double *u, hipStream_t st) {
+  hipLaunchKernelGGL(k_sub_mean, dim3(H->n_r), dim3(kBlock), 0, st, H->d_sys, H->d_ins, H->w_r, (const double *)H->v, u,
+                     (const double *)H->pr);
+}
+
+// Every graph a solve of this handle launches, captured once at setup (the
+// graphs read and write the handle's own buffers only): a solve then launches
+// them without capturing or instantiating anything.
+void capture_graphs(smpm_handle *H) {
+  hipStream_t st = H->ws;
+  if (H->precision == SMPM_FP64) {
+    if (!H->g_head)
+      H->g_head = capture(st, [&] {
+        stage_rhs(H, st);
+        Inner<double>::pre(H, st);
+      });
+    if (!H->g_tail)
+      H->g_tail = capture(st, [&] {
+        Inner<double>::post(H, st);
+        residual64(H, st, H->method == SMPM_METHOD_DBJ);
+        finish_u(H, st);
+      });
+    Inner<double>::capture_loops(H, st);
+  } else {
+    if (!H->g_stage) H->g_stage = capture(st, [&] { stage_rhs(H, st); });
+    if (!H->g_resid) H->g_resid = capture(st, [&] { residual64(H, st); });
+    if (!H->g_finish) H->g_finish = capture(st, [&] { finish_u(H, st); });
+    Inner<float>::capture_loops(H, st);
+  }
+  HIPCHECK(hipStreamSynchronize(st));
+}
+
+// The FFT path of the y transform: m_y a power of two with at least one
+// column per workgroup's staging (else the dense DFT GEMM).
+bool fft_ok(int my) { return my >= 2 && (my & (my - 1)) == 0 && my <= kFftSlots; }
+
+// y transform of ncol columns: forward (planes -> Re/Im of m_y/2 + 1 modes,
+// scaled by 1/m_y) or inverse, by FFT where m_y allows, else by the DFT GEMM.
+void transform_y(smpm_handle *H, bool inverse, const double *in, double *out, int64_t ncol, hipStream_t st) {
+  const int my = H->my, nk2 = 2 * (my / 2 + 1);
+  if (H->fft_tw) {
+    int logmy = 0;
+    while ((1 << logmy) < my) ++logmy;
+    const int CT = kFftSlots / my;
+    const dim3 grid((unsigned)((ncol + CT - 1) / CT));
+    const size_t shm = sizeof(double2) * kFftSlots;
+    if (inverse)
+      hipLaunchKernelGGL(k_fft_y<true>, grid, dim3(256), shm, st, in, out, my, logmy, ncol, (const double2 *)H->fft_tw);
+    else
+      hipLaunchKernelGGL(k_fft_y<false>, grid, dim3(256), shm, st, in, out, my, logmy, ncol, (const double2 *)H->fft_tw);
+    return;
+  }
+  const int M = inverse ? my : nk2, K = inverse ? nk2 : my;
+  const dim3 grid((unsigned)((ncol + 63) / 64), (unsigned)(((M + 15) / 16 + kDftTiles - 1) / kDftTiles));
+  hipLaunchKernelGGL(k_dft_gemm, grid, dim3(256), 0, st, inverse ? H->dft_i : H->dft_f, M, K, in, out, ncol);
 }
 
 // Real DFT matrices and coefficient buffers of a Fourier handle:
@@ -1306,6 +1513,15 @@ void fourier_tables(smpm_handle *H, hipStream_t s0) {
   }
   H->dft_f = dupload(H->owned, F, s0);
   H->dft_i = dupload(H->owned, I, s0);
+  if (fft_ok(my)) {
+    std::vector<double> tw((size_t)my);   // (cos, -sin) pairs, angle reduced like the DFT tables
+    for (int k = 0; k < my / 2; ++k) {
+      const double th = 2.0 * M_PI * (double)k / my;
+      tw[2 * k] = std::cos(th);
+      tw[2 * k + 1] = -std::sin(th);
+    }
+    H->fft_tw = reinterpret_cast<double2 *>(dupload(H->owned, tw, s0));
+  }
   H->fhat = dalloc<double>(H->owned, H->tot_r);
   H->uhat = dalloc<double>(H->owned, H->tot_r);
   H->ghat = dalloc<double>(H->owned, H->tot_g);
@@ -1390,9 +1606,22 @@ smpm_status setup_common(const smpm_grid *grids, const double *k, int nsys, bool
   for (int i = 0; i < nsys; ++i)
     if (codes[i] != SMPM_OK) return fail((smpm_status)codes[i], "system " + std::to_string(i) + ": " + errs[i]);
   if (!H->host_only) {
+    const bool times = std::getenv("SMPM_SETUP_TIMES") != nullptr;
+    auto t0 = std::chrono::steady_clock::now();
+    auto lap = [&](const char *what) {
+      if (!times) return;
+      HIPCHECK(hipDeviceSynchronize());
+      const auto now = std::chrono::steady_clock::now();
+      std::fprintf(stderr, "setup %-28s %8.1f ms\n", what, std::chrono::duration<double, std::milli>(now - t0).count());
+      t0 = now;
+    };
     try {
       upload(H.get(), (hipStream_t)stream);
+      lap("upload");
       tune(H.get(), (hipStream_t)stream);
+      lap("schedule tuning");
+      capture_graphs(H.get());
+      lap("graph capture");
     } catch (const std::bad_alloc &) {
       return fail(SMPM_ENOMEM, "device allocation failed in setup");
     } catch (const std::exception &e) {
@@ -1490,6 +1719,7 @@ smpm_status smpm_load(const char *path, const smpm_opts *opts, void *hip_stream,
     try {
       upload(H.get(), (hipStream_t)hip_stream);
       tune(H.get(), (hipStream_t)hip_stream);
+      capture_graphs(H.get());
       if (H->my > 0) fourier_tables(H.get(), (hipStream_t)hip_stream);
     } catch (const std::bad_alloc &) {
       return fail(SMPM_ENOMEM, "device allocation failed while loading tables");
@@ -1511,19 +1741,39 @@ smpm_status smpm_solve_fourier(smpm_handle *H, const double *f, const double *g,
   const int nk2 = 2 * (H->my / 2 + 1);
   const System &s0 = H->sys[0];
   const int64_t r = s0.r, gsz = 2LL * s0.n * (s0.mx + s0.mz);
-  auto dft = [&](const double *A, int M, int K, const double *B, double *C, int64_t ncol) {
-    const dim3 grid((unsigned)((ncol + 63) / 64), (unsigned)(((M + 15) / 16 + kDftTiles - 1) / kDftTiles));
-    hipLaunchKernelGGL(k_dft_gemm, grid, dim3(256), 0, st, A, M, K, B, C, ncol);
-  };
-  dft(H->dft_f, nk2, H->my, f, H->fhat, r);
-  if (g) dft(H->dft_f, nk2, H->my, g, H->ghat, gsz);
+  (void)nk2;
+  transform_y(H, false, f, H->fhat, r, st);
+  if (g) transform_y(H, false, g, H->ghat, gsz, st);
   if (hipGetLastError() != hipSuccess) return fail(SMPM_EHIP, "transform launch failed");
   const smpm_status status = smpm_solve(H, H->fhat, g ? H->ghat : nullptr, H->uhat, hip_stream, stats);
   if (status == SMPM_OK || status == SMPM_ENOTCONV || status == SMPM_ENONFINITE) {
-    dft(H->dft_i, H->my, nk2, H->uhat, u, r);
+    transform_y(H, true, H->uhat, u, r, st);
     if (hipGetLastError() != hipSuccess) return fail(SMPM_EHIP, "transform launch failed");
   }
   return status;
+}
+
+smpm_status smpm_transform_y(smpm_handle *H, int32_t inverse, const double *in, double *out, void *hip_stream) {
+  if (!H) return fail(SMPM_EINVAL, "handle is NULL");
+  if (H->my == 0) return fail(SMPM_EINVAL, "not a Fourier handle (smpm_setup_fourier)");
+  if (H->host_only) return fail(SMPM_EUNSUPPORTED, "host-only handle");
+  if (!in || !out || in == out) return fail(SMPM_EINVAL, "in or out is NULL, or they are the same array");
+  transform_y(H, inverse != 0, in, out, H->sys[0].r, (hipStream_t)hip_stream);
+  if (hipGetLastError() != hipSuccess) return fail(SMPM_EHIP, "transform launch failed");
+  return SMPM_OK;
+}
+
+// Relative Schur residual of instance i from the reduced pairs (|r|^2,
+// u_S . r) and (|b~|^2, .): at k = 0 the part of r in range(S) = u_S-perp,
+// |r|^2 - (u_S . r)^2 (u_S has unit norm), since the regularized system's
+// residual lies there in exact arithmetic and its u_S component is the
+// rounding of u_S and of S x_S, which no iterate reduces (reported apart).
+static double range_residual(const smpm_handle *H, int i) {
+  const double nb = std::sqrt(H->h_nb[2 * i]);
+  if (!(nb > 0)) return 0.0;
+  double rr = H->h_pairs[2 * i];
+  if (H->sys[H->h_ins[i].sys].singular) rr = std::max(rr - H->h_pairs[2 * i + 1] * H->h_pairs[2 * i + 1], 0.0);
+  return std::sqrt(rr) / nb;
 }
 
 smpm_status smpm_solve(smpm_handle *H, const double *f, const double *g, double *u, void *hip_stream,
@@ -1549,29 +1799,13 @@ smpm_status smpm_solve(smpm_handle *H, const double *f, const double *g, double 
       // only overwrites its outputs and leaves the Krylov state alone, so
       // if an instance is still iterating the loop resumes and the tail is
       // enqueued again.
-      if (!H->g_head || H->head_f != f || H->head_g != g) {
-        if (H->g_head) HIPCHECK(hipGraphExecDestroy(H->g_head));
-        H->g_head = nullptr;
-        H->g_head = capture(st, [&] {
-          stage_rhs(H, f, g, st);
-          Inner<double>::pre(H, st);
-        });
-        H->head_f = f; H->head_g = g;
-      }
-      if (!H->g_tail || H->tail_u != u) {
-        if (H->g_tail) HIPCHECK(hipGraphExecDestroy(H->g_tail));
-        H->g_tail = nullptr;
-        H->g_tail = capture(st, [&] {
-          Inner<double>::post(H, st);
-          residual64(H, st);
-          finish_u(H, u, st);
-        });
-        H->tail_u = u;
-      }
+      capture_graphs(H);   // done at setup: nothing to capture here
+      read_rhs(H, f, g, st);
       HIPCHECK(hipGraphLaunch(H->g_head, st));
       int launched = Inner<double>::predicted(H, 0, st);
       for (;;) {
         HIPCHECK(hipGraphLaunch(H->g_tail, st));
+        write_u(H, u, st);   // again after a later tail if the loop resumes
         HIPCHECK(hipMemcpyAsync(H->h_rep, H->gs, H->rep_bytes, hipMemcpyDeviceToHost, st));
         HIPCHECK(hipStreamSynchronize(st));
         const GState *hg = reinterpret_cast<const GState *>(H->h_rep);
@@ -1591,13 +1825,8 @@ smpm_status smpm_solve(smpm_handle *H, const double *f, const double *g, double 
       sweeps = 1;
       S.schur_matvecs += H->ninst * ((useP ? 1 : 0) + 1);
     } else {
-      if (!H->g_stage || H->stage_f != f || H->stage_g != g) {
-        if (H->g_stage) HIPCHECK(hipGraphExecDestroy(H->g_stage));
-        H->g_stage = nullptr;
-        H->g_stage = capture(st, [&] { stage_rhs(H, f, g, st); });
-        H->stage_f = f; H->stage_g = g;
-      }
-      if (!H->g_resid) H->g_resid = capture(st, [&] { residual64(H, st); });
+      capture_graphs(H);   // done at setup: nothing to capture here
+      read_rhs(H, f, g, st);
       HIPCHECK(hipGraphLaunch(H->g_stage, st));
       HIPCHECK(hipMemcpyAsync(H->h_nb, H->pairs, sizeof(double) * 2 * H->ninst, hipMemcpyDeviceToHost, st));
       // As many sweeps as the previous solve took, each with its predicted
@@ -1623,8 +1852,7 @@ smpm_status smpm_solve(smpm_handle *H, const double *f, const double *g, double 
           bool done = true;
           double worst = 0.0;
           for (int i = 0; i < H->ninst; ++i) {
-            const double nb = std::sqrt(H->h_nb[2 * i]);
-            const double rel = nb > 0 ? std::sqrt(H->h_pairs[2 * i]) / nb : 0.0;
+            const double rel = range_residual(H, i);
             if (!std::isfinite(rel)) nonfinite = true;
             if (rel > H->tol) done = false;
             worst = std::max(worst, rel);
@@ -1647,13 +1875,8 @@ smpm_status smpm_solve(smpm_handle *H, const double *f, const double *g, double 
         S.schur_matvecs += useP ? H->ninst : 0;
       }
       HIPCHECK(hipMemcpyAsync(H->h_defect, H->defect, sizeof(double) * H->ninst, hipMemcpyDeviceToHost, st));
-      if (!H->g_finish || H->fin_u != u) {
-        if (H->g_finish) HIPCHECK(hipGraphExecDestroy(H->g_finish));
-        H->g_finish = nullptr;
-        H->g_finish = capture(st, [&] { finish_u(H, u, st); });
-        H->fin_u = u;
-      }
       HIPCHECK(hipGraphLaunch(H->g_finish, st));
+      write_u(H, u, st);
     }
     HIPCHECK(hipGetLastError());
     HIPCHECK(hipEventRecord(H->ev_out, st));
@@ -1678,17 +1901,21 @@ smpm_status smpm_solve(smpm_handle *H, const double *f, const double *g, double 
       }
     H->pred_iters[P] = itmax_all;
     S.sweeps_max = H->precision == SMPM_FP64 ? 1 : sweeps;
-    double relmax = 0.0, defmax = 0.0;
+    double relmax = 0.0, defmax = 0.0, nullmax = 0.0;
     int conv = 0;
     for (int i = 0; i < H->ninst; ++i) {
       const double nb = std::sqrt(H->h_nb[2 * i]);
-      const double rel = nb > 0 ? std::sqrt(H->h_pairs[2 * i]) / nb : 0.0;
+      const double rel = range_residual(H, i);
       if (!std::isfinite(rel)) nonfinite = true;
       relmax = std::max(relmax, rel);
-      if (H->sys[H->h_ins[i].sys].singular) defmax = std::max(defmax, H->h_defect[i]);
+      if (H->sys[H->h_ins[i].sys].singular) {
+        defmax = std::max(defmax, H->h_defect[i]);
+        if (nb > 0) nullmax = std::max(nullmax, std::fabs(H->h_pairs[2 * i + 1]) / nb);
+      }
       if (rel <= H->tol * 1.001) ++conv;
     }
     S.rel_residual_max = relmax;
+    S.null_residual_max = nullmax;
     S.compat_defect_max = defmax;
     S.converged = conv;
     S.solve_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
@@ -1804,6 +2031,57 @@ smpm_status smpm_schur_apply_all(smpm_handle *H, const void *x, void *y, int32_t
   return SMPM_OK;
 }
 
+smpm_status smpm_apply_all(smpm_handle *H, smpm_op op, const void *x, void *y, int32_t precision,
+                           void *hip_stream) {
+  if (!H) return fail(SMPM_EINVAL, "handle is NULL");
+  if (H->host_only) return fail(SMPM_EUNSUPPORTED, "host-only handle");
+  if (!x || !y || x == y) return fail(SMPM_EINVAL, "x or y is NULL, or x and y are the same array");
+  const bool p16 = precision == SMPM_FP16S_IR;
+  if (precision != SMPM_FP64 && precision != SMPM_FP32_IR && !p16) return fail(SMPM_EINVAL, "unknown precision");
+  if (p16 && !H->op16) return fail(SMPM_EINVAL, "FP16 tables exist on SMPM_FP16S_IR handles only");
+  if (op == SMPM_OP_AINV && precision != SMPM_FP64) return fail(SMPM_EINVAL, "AINV is FP64 only");
+  hipStream_t st = (hipStream_t)hip_stream;
+  try {
+    switch (op) {
+      case SMPM_OP_SCHUR:
+      case SMPM_OP_BJINV: {
+        const int kop = op == SMPM_OP_SCHUR ? 0 : 1;
+        if (precision == SMPM_FP64)
+          gemv<double, double, double>(H, kop, (const double *)x, 0, nullptr, (double *)y, nullptr, nullptr, st);
+        else
+          gemv<float, float, float>(H, kop, (const float *)x, 0, nullptr, (float *)y, nullptr, nullptr, st, -1, p16);
+        break;
+      }
+      case SMPM_OP_SCHUR_BJINV: {   // the GMRES iteration's operator, as the solve applies it
+        const int pr = precision == SMPM_FP64 ? 0 : (p16 ? 2 : 1);
+        if (precision == SMPM_FP64) {
+          if (H->use_fused[pr]) {
+            gemv<double, double, double>(H, 2, (const double *)x, 0, nullptr, (double *)y, nullptr, nullptr, st);
+          } else {
+            gemv<double, double, double>(H, 1, (const double *)x, 0, nullptr, H->z64, nullptr, nullptr, st);
+            gemv<double, double, double>(H, 0, (const double *)H->z64, 0, nullptr, (double *)y, nullptr, nullptr, st);
+          }
+        } else if (H->use_fused[pr]) {
+          gemv<float, float, float>(H, 2, (const float *)x, 0, nullptr, (float *)y, nullptr, nullptr, st, -1, p16);
+        } else {
+          gemv<float, float, float>(H, 1, (const float *)x, 0, nullptr, H->z32, nullptr, nullptr, st, -1, p16);
+          gemv<float, float, float>(H, 0, (const float *)H->z32, 0, nullptr, (float *)y, nullptr, nullptr, st, -1, p16);
+        }
+        break;
+      }
+      case SMPM_OP_AINV:
+        ainv(H, (const double *)x, (double *)y, st);
+        break;
+      default:
+        return fail(SMPM_EINVAL, "smpm_apply_all takes SCHUR, BJINV, SCHUR_BJINV or AINV");
+    }
+    HIPCHECK(hipGetLastError());
+  } catch (const std::exception &e) {
+    return fail(SMPM_EHIP, e.what());
+  }
+  return SMPM_OK;
+}
+
 int32_t smpm_num_systems(const smpm_handle *H) { return H ? (int32_t)H->sys.size() : 0; }
 
 smpm_status smpm_query(const smpm_handle *H, int32_t sysi, smpm_info *info) {
@@ -1827,8 +2105,47 @@ smpm_status smpm_query(const smpm_handle *H, int32_t sysi, smpm_info *info) {
       o.gemm_sched[2 * op + pr] = H->n_g_all[op] > 0 ? H->sched[op][pr == 1 && H->op16 ? 2 : pr] : -1;
   for (int k = 0; k < 3; ++k)
     for (int w = 0; w < 2; ++w) o.elem_sched[2 * k + w] = H->n_cg_all[k][w] > 0 ? H->cg_sched[k][w] : -1;
-  for (int pr = 0; pr < 3; ++pr) o.fused_op[pr] = H->use_fused[pr] ? 1 : 0;
+  for (int pr = 0; pr < 3; ++pr) {
+    o.fused_op[pr] = H->use_fused[pr] ? 1 : 0;
+    o.fused_sched[pr] = H->n_g_all[2] > 0 ? H->sched[2][pr] : -1;
+  }
   o.setup_device = s.dev_steps;
+  // Algorithmic operator sizes: nonzero entries only (a Schur block's
+  // column half for a window half outside the interface range is stored as
+  // zeros and not counted), distinct blocks once.
+  const int N = s.N, nh = s.nh;
+  const size_t wsz = (size_t)N * 2 * N;
+  for (int b = 0; b < s.nW; ++b)
+    for (int c = 0; c < 2; ++c) {
+      bool nz = false;
+      for (int i = 0; i < N && !nz; ++i)
+        for (int q = 0; q < N && !nz; ++q) nz = s.Wblk[b * wsz + (size_t)i * 2 * N + c * N + q] != 0.0;
+      if (nz) o.nnz_W_unique += (int64_t)N * N;
+    }
+  std::vector<int> mK(s.nM / 4, 0), fK(s.nF, 0);
+  for (int h = 0; h < nh; ++h) {
+    for (int p = 0; p < 2; ++p) {
+      const int wh = s.w_win[h] + p;
+      if (wh >= 0 && wh < nh) o.nnz_W_total += (int64_t)N * N;
+    }
+    o.nnz_M_total += (int64_t)N * s.m_K[h];
+    mK[s.m_id[h] / 4] = s.m_K[h];
+    if (s.nF > 0) {
+      o.nnz_F_total += (int64_t)N * s.f_K[h];
+      fK[s.f_id[h]] = s.f_K[h];
+    }
+  }
+  for (int K : mK) o.nnz_M_unique += (int64_t)K * K;
+  for (int K : fK) o.nnz_F_unique += (int64_t)N * K;
+  o.strip_classes = (int32_t)s.classes.size();
+  const size_t bsz = (size_t)s.n2 * s.n2;
+  for (const StripClass &c : s.classes)   // element inverses equal bit for bit are stored once
+    for (int e = 0; e < s.mz; ++e) {
+      bool seen = false;
+      for (int f = 0; f < e && !seen; ++f)
+        seen = !std::memcmp(c.Dinv.data() + f * bsz, c.Dinv.data() + e * bsz, sizeof(double) * bsz);
+      if (!seen) ++o.elem_unique;
+    }
   *info = o;
   return SMPM_OK;
 }

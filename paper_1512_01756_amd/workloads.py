@@ -119,10 +119,12 @@ def stretched_grid(mx, mz, seed=0, ratio_total=16.0):
     return xb, zb
 
 
-def c3(seed=0, mx=256, mz=16, n=13):
+def c3(seed=0, mx=256, mz=16, n=13, rhs_seed=None):
+    """The stretched grid of `seed`; f ~ U[0, 1] from `rhs_seed` (default: the
+    grid's seed), so several right-hand sides can share one grid."""
     xb, zb = stretched_grid(mx, mz, seed)
     r = n * n * mx * mz
-    f = np.random.default_rng(seed + 1).uniform(0.0, 1.0, r)
+    f = np.random.default_rng((seed if rhs_seed is None else rhs_seed) + 1).uniform(0.0, 1.0, r)
     return Problem("c3", xb, zb, n, np.zeros(1), f[None, None, :])
 
 
@@ -166,10 +168,11 @@ def c5_specs(seed=0, nprob=32):
     return specs
 
 
-def c5(seed=0, nprob=32, scale=1.0):
-    """The uneven batch; `scale` < 1 shrinks m_x and m_z for tests."""
+def c5(seed=0, nprob=32, scale=1.0, rhs_seed=None):
+    """The uneven batch; `scale` < 1 shrinks m_x and m_z for tests.  The
+    sizes come from `seed`, the forcing from `rhs_seed` (default: `seed`)."""
     probs = []
-    rng = np.random.default_rng(seed + 1000)
+    rng = np.random.default_rng((seed if rhs_seed is None else rhs_seed) + 1000)
     for i, (mx, mz, n, k) in enumerate(c5_specs(seed, nprob)):
         mx = max(4, int(round(mx * scale)))
         mz = max(1, int(round(mz * scale)))
@@ -179,6 +182,19 @@ def c5(seed=0, nprob=32, scale=1.0):
         f = rng.uniform(0.0, 1.0, r)
         probs.append(Problem(f"c5_{i}", xb, zb, n, np.array([k]), f[None, None, :]))
     return probs
+
+
+def smooth_field(xb, zb, n, seed):
+    """A smooth seeded node field: low Fourier modes in x and z,
+    sum_{kx < 4, kz < 3} a_{kx,kz} cos(pi kx x / L_x) cos(pi kz z), a ~ N(0, 1)."""
+    X, Z = node_coords(xb, zb, n)
+    lx = xb[-1] - xb[0]
+    rng = np.random.default_rng(seed)
+    v = np.zeros_like(X)
+    for kx in range(4):
+        for kz in range(3):
+            v += rng.standard_normal() * np.cos(np.pi * kx * X / lx) * np.cos(np.pi * kz * Z)
+    return v
 
 
 def random_problem(mx, mz, n, kwaves=(0.0,), nrhs=1, seed=0, lx=None, stretch=False,

@@ -105,3 +105,31 @@ def test_one_krylov_needs_dbj():
     with pytest.raises(P.SmpmError):
         P.Solver(np.linspace(0, 3, 5), np.linspace(0, 1, 2), 4, fourier=(4, 1.0), one_krylov=True,
                  method=P.METHOD_BJ)
+
+
+@pytest.mark.parametrize("my", [2, 8, 128, 256, 6, 12])
+def test_transform_y_matches_numpy_fft(my):
+    # The y transform alone (radix-2 FFT for powers of two, the dense real DFT
+    # otherwise) against the oracle's numpy real FFT, both directions, on a
+    # seeded field with a ragged last column tile (r = 25 * 2 * 36 = 1800
+    # columns is not a multiple of the FFT's 4096 / m_y columns per
+    # workgroup for m_y >= 128).
+    xb, zb, n = np.linspace(0.0, 12.5, 26), np.array([0.0, 0.5, 1.0]), 6
+    s = P.Solver(xb, zb, n - 1, fourier=(my, 3.0), tune=False)
+    r = s.info[0]["r"]
+    assert r == 1800
+    f = np.random.default_rng(my).uniform(-1.0, 1.0, (my, r))
+    fh = torch.empty((my // 2 + 1, 2, r), dtype=torch.float64, device="cuda")
+    s.transform_y(_dev(f), fh)
+    back = torch.empty((my, r), dtype=torch.float64, device="cuda")
+    s.transform_y(fh, back, inverse=True)
+    torch.cuda.synchronize()
+    ref = fourier.forward(f)
+    assert _rel(fh.cpu().numpy(), ref) <= 1e-14
+    assert _rel(back.cpu().numpy(), f) <= 1e-14
+    # inverse of arbitrary coefficients: Im of modes 0 and m_y/2 are ignored
+    c = np.random.default_rng(my + 1).standard_normal((my // 2 + 1, 2, r))
+    s.transform_y(_dev(c), back, inverse=True)
+    torch.cuda.synchronize()
+    assert _rel(back.cpu().numpy(), fourier.inverse(c, my)) <= 1e-13
+    s.close()

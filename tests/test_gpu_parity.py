@@ -20,22 +20,53 @@ def need_gpu():
     P.load()
 
 
-# The stopping test is |g| <= 1e-10 |b~|; the recursive and the true residual
-# agree to rounding, so the true residual is accepted up to 0.1% above 1e-10.
+# The stopping test is |g| <= tol |b~|; the recursive and the true residual
+# agree to rounding, so the true residual is accepted up to 0.1% above tol.
 ACCEPT = 1.001e-10
+# Solution parity: both sides solve to a 1e-12 relative Schur residual, so the
+# comparison sees the arithmetic (GEMM order, CGS2 against Householder, the two
+# routes to the null vectors), not where each side happened to stop; a
+# 1e-10-residual solution differs from the exact discrete one by about 1e-10
+# itself.  Every case, k = 0 included, is then held to 1e-10 relative: at
+# k = 0 the two sides' left null vectors (inverse iteration against a bordered
+# sparse LU) differ by about 1e-13 on these grids and 6e-11 on the 64:1 c2
+# grid, and the solution moves by less than that angle (the oracle's own
+# perturbation measurement), so the null vectors leave the bound untouched.
+TIGHT = 1e-12
+ACCEPT_TIGHT = 1.001e-12
+PARITY = 1e-10
+# At k = 0 with incompatible data (u_L^T F != 0) the solution of the
+# projected system moves with the left null vectors, which both sides
+# compute only to the rounding of S over the gap to its next singular value.
+# The oracle measures that spread on the same input (null_vector_floor:
+# null vectors from S perturbed at 2e-13, three samples); the bound is the
+# larger of PARITY and ten times it.
+FLOOR_FACTOR = 10
 
 
 def _dev(a):
     return torch.as_tensor(np.ascontiguousarray(a, dtype=np.float64)).cuda()
 
 
+def _bound(o, F):
+    """PARITY, or at k = 0 the larger of PARITY and FLOOR_FACTOR times the
+    oracle's null-vector floor for this input."""
+    if not o.singular:
+        return PARITY
+    return max(PARITY, FLOOR_FACTOR * solve.null_vector_floor(o, F, samples=3, tol=TIGHT))
+
+
 def _oracle(prob, s_idx, q, tol=1e-10, method="dbj", zlabel=0):
+    """The oracle's solve of one right-hand side; at the tight tolerance the
+    result also carries the parity bound for this input (ref.bound)."""
     grid = smpm.Grid(prob.xb, prob.zb, prob.n)
     k = float(prob.kwaves[s_idx])
     o = schur.build(grid, kwave=k, zlabel=zlabel)
     g = {side: arr[s_idx, q] for side, arr in prob.g.items()} if prob.g else None
     F = smpm.rhs(grid, o.tau, prob.f[s_idx, q], g)
-    return o, solve.dbj_solve(o, F, method=method, tol=tol)
+    ref = solve.dbj_solve(o, F, method=method, tol=tol)
+    ref.bound = _bound(o, F) if tol == TIGHT else None
+    return o, ref
 
 
 def _gpu_solve(prob, precision=P.FP64, method=P.METHOD_DBJ, **kw):
@@ -60,9 +91,13 @@ def test_c1_fp64_matches_oracle():
     print("c1 stats", st, "oracle iters", ref.iters)
     assert st["rel_residual_max"] <= ACCEPT
     assert abs(st["iters_max"] - ref.iters) <= 1
-    assert _rel(u, ref.u) <= 1e-10
     ue = p.exact - p.exact.mean()
     assert np.abs(u - ue).max() < 1e-9
+    s, u, st = _gpu_solve(p, tol=TIGHT)
+    o, ref = _oracle(p, 0, 0, tol=TIGHT)
+    assert st["rel_residual_max"] <= ACCEPT_TIGHT
+    assert abs(st["iters_max"] - ref.iters) <= 1
+    assert _rel(u, ref.u) <= ref.bound
 
 
 @pytest.mark.parametrize("mx,mz,n,stretch,with_g", [(6, 2, 5, False, True), (9, 3, 7, True, False),
@@ -71,10 +106,15 @@ def test_random_poisson_matches_oracle(mx, mz, n, stretch, with_g):
     p = workloads.random_problem(mx, mz, n, seed=mx + n, stretch=stretch, with_g=with_g)
     s, u, st = _gpu_solve(p)
     o, ref = _oracle(p, 0, 0)
-    print("stats", st, "oracle iters", ref.iters, "rel", _rel(u, ref.u))
+    print("stats", st, "oracle iters", ref.iters)
     assert st["rel_residual_max"] <= ACCEPT
     assert abs(st["iters_max"] - ref.iters) <= 1
-    assert _rel(u, ref.u) <= 1e-9
+    s, u, st = _gpu_solve(p, tol=TIGHT)
+    o, ref = _oracle(p, 0, 0, tol=TIGHT)
+    print("tight", st, "oracle iters", ref.iters, "rel", _rel(u, ref.u))
+    assert st["rel_residual_max"] <= ACCEPT_TIGHT
+    assert abs(st["iters_max"] - ref.iters) <= 1
+    assert _rel(u, ref.u) <= ref.bound
 
 
 @pytest.mark.parametrize("mx,mz,n,k", [(4, 1, 2, 0.0), (4, 1, 3, 0.0), (5, 1, 4, 2.0), (4, 2, 2, 0.0),
@@ -85,25 +125,26 @@ def test_degenerate_grids_match_oracle(mx, mz, n, k, precision):
     # blocks, the second one short), one element per strip (no z-interface:
     # an empty capacitance system), order 1 (n = 2 nodes per direction).
     p = workloads.random_problem(mx, mz, n, kwaves=(k,), seed=3 + mx + n, stretch=True, with_g=True)
-    s, u, st = _gpu_solve(p, precision=precision)
-    o, ref = _oracle(p, 0, 0, tol=1e-12)
+    s, u, st = _gpu_solve(p, precision=precision, tol=TIGHT)
+    o, ref = _oracle(p, 0, 0, tol=TIGHT)
     print(mx, mz, n, k, "stats", st, "oracle iters", ref.iters, "rel", _rel(u, ref.u))
-    assert st["rel_residual_max"] <= ACCEPT
-    assert _rel(u, ref.u) <= 1e-9
+    assert st["rel_residual_max"] <= ACCEPT_TIGHT
+    assert _rel(u, ref.u) <= ref.bound
 
 
 def test_fourier_modes_batched_match_oracle():
     p = workloads.fourier_problem("f", 4.0, 8, 2, 5, my=8, ly=2.0, seed=3)
-    s, u, st = _gpu_solve(p)
+    s, u, st = _gpu_solve(p, tol=TIGHT)
     u = u.reshape(p.nk, 2, p.r)
     assert st["instances"] == p.nk * 2
+    assert st["rel_residual_max"] <= ACCEPT_TIGHT
     for m in range(p.nk):
         for q in range(2):
-            o, ref = _oracle(p, m, q)
+            o, ref = _oracle(p, m, q, tol=TIGHT)
             if np.abs(p.f[m, q]).max() == 0:
                 assert np.abs(u[m, q]).max() == 0
                 continue
-            assert _rel(u[m, q], ref.u) <= 1e-9, (m, q)
+            assert _rel(u[m, q], ref.u) <= ref.bound, (m, q)
 
 
 @pytest.mark.parametrize("method,name", [(P.METHOD_DBJ, "dbj"), (P.METHOD_BJ, "bj"), (P.METHOD_SCHUR, "schur"),
@@ -115,10 +156,15 @@ def test_methods_match_oracle(method, name, k):
     p = workloads.random_problem(10, 2, 6, kwaves=(k,), seed=21, stretch=True, with_g=True)
     s, u, st = _gpu_solve(p, method=method)
     o, ref = _oracle(p, 0, 0, method=name)
-    print(name, k, "stats", st, "oracle iters", ref.iters, "rel", _rel(u, ref.u))
+    print(name, k, "stats", st, "oracle iters", ref.iters)
     assert st["rel_residual_max"] <= ACCEPT
     assert abs(st["iters_max"] - ref.iters) <= 1
-    assert _rel(u, ref.u) <= 1e-9
+    s, u, st = _gpu_solve(p, method=method, tol=TIGHT)
+    o, ref = _oracle(p, 0, 0, method=name, tol=TIGHT)
+    print(name, k, "tight", st, "oracle iters", ref.iters, "rel", _rel(u, ref.u))
+    assert st["rel_residual_max"] <= ACCEPT_TIGHT
+    assert abs(st["iters_max"] - ref.iters) <= 1
+    assert _rel(u, ref.u) <= ref.bound
 
 
 @pytest.mark.parametrize("method,name", [(P.METHOD_DBJ, "dbj"), (P.METHOD_2LAS, "2las")])
@@ -129,18 +175,22 @@ def test_per_element_deflation_matches_oracle(method, name, k):
     s, u, st = _gpu_solve(p, method=method, zlabel=1)
     assert s.info[0]["d"] == 9 * 3
     o, ref = _oracle(p, 0, 0, method=name, zlabel=1)
-    print("zlabel 1", name, k, st, "oracle iters", ref.iters, "rel", _rel(u, ref.u))
+    print("zlabel 1", name, k, st, "oracle iters", ref.iters)
     assert st["rel_residual_max"] <= ACCEPT
     assert abs(st["iters_max"] - ref.iters) <= 1
-    assert _rel(u, ref.u) <= 1e-9
+    s, u, st = _gpu_solve(p, method=method, zlabel=1, tol=TIGHT)
+    o, ref = _oracle(p, 0, 0, method=name, zlabel=1, tol=TIGHT)
+    print("zlabel 1 tight", name, k, st, "oracle iters", ref.iters, "rel", _rel(u, ref.u))
+    assert st["rel_residual_max"] <= ACCEPT_TIGHT
+    assert _rel(u, ref.u) <= ref.bound
 
 
 def test_per_element_deflation_fp32_refinement_and_operators():
     p = workloads.random_problem(12, 3, 7, seed=5, stretch=True)
-    s, u, st = _gpu_solve(p, precision=P.FP32_IR, zlabel=1)
-    o, ref = _oracle(p, 0, 0, tol=1e-12, zlabel=1)
-    assert st["rel_residual_max"] <= ACCEPT
-    assert _rel(u, ref.u) <= 1e-8
+    s, u, st = _gpu_solve(p, precision=P.FP32_IR, zlabel=1, tol=TIGHT)
+    o, ref = _oracle(p, 0, 0, tol=TIGHT, zlabel=1)
+    assert st["rel_residual_max"] <= ACCEPT_TIGHT
+    assert _rel(u, ref.u) <= ref.bound
     s64 = P.Solver(p.xb, p.zb, p.n - 1, zlabel=1)
     x = np.random.default_rng(8).standard_normal(o.grid.k)
     xd = _dev(x)
@@ -155,10 +205,10 @@ def test_per_element_deflation_fp32_refinement_and_operators():
 
 def test_2las_fp32_refinement():
     p = workloads.random_problem(12, 3, 7, seed=5, stretch=True)
-    s, u, st = _gpu_solve(p, precision=P.FP32_IR, method=P.METHOD_2LAS)
-    o, ref = _oracle(p, 0, 0, tol=1e-12)
-    assert st["rel_residual_max"] <= ACCEPT
-    assert _rel(u, ref.u) <= 1e-8
+    s, u, st = _gpu_solve(p, precision=P.FP32_IR, method=P.METHOD_2LAS, tol=TIGHT)
+    o, ref = _oracle(p, 0, 0, tol=TIGHT)
+    assert st["rel_residual_max"] <= ACCEPT_TIGHT
+    assert _rel(u, ref.u) <= ref.bound
 
 
 @pytest.mark.parametrize("stretch", [False, True])
@@ -167,12 +217,12 @@ def test_fp16_scaled_refinement_reaches_fp64_solution(stretch):
     # through the MFMA GEMM without stretch, distinct strips through the
     # streaming kernel with it), FP32 inner GMRES, FP64 refinement.
     p = workloads.random_problem(12, 3, 7, seed=6, stretch=stretch)
-    s, u, st = _gpu_solve(p, precision=P.FP16S_IR)
-    o, ref = _oracle(p, 0, 0, tol=1e-12)
-    print("fp16s stats", st)
-    assert st["rel_residual_max"] <= ACCEPT
+    s, u, st = _gpu_solve(p, precision=P.FP16S_IR, tol=TIGHT)
+    o, ref = _oracle(p, 0, 0, tol=TIGHT)
+    print("fp16s stats", st, "rel", _rel(u, ref.u))
+    assert st["rel_residual_max"] <= ACCEPT_TIGHT
     assert st["sweeps_max"] >= 2
-    assert _rel(u, ref.u) <= 1e-8
+    assert _rel(u, ref.u) <= ref.bound
     # the FP16 matvec itself: within FP16 rounding of the FP64 product
     x = np.random.default_rng(4).standard_normal(o.grid.k)
     x32 = _dev(x).float()
@@ -218,7 +268,7 @@ def _sched_problem():
 @pytest.fixture(scope="module")
 def sched_refs():
     p = _sched_problem()
-    return {(m, q): _oracle(p, m, q, tol=1e-12)[1].u for m in range(2) for q in range(2)}
+    return {(m, q): _oracle(p, m, q, tol=TIGHT)[1] for m in range(2) for q in range(2)}
 
 
 @pytest.mark.parametrize("sched", [1, 2, 3, 4, 5])
@@ -230,42 +280,65 @@ def test_element_gemm_schedules_match_oracle(sched, monkeypatch, sched_refs):
     # right-hand sides give items of 1 to 3 column tiles (the last one partial)
     # and one-column items in the same launch.  Both sides solve to 1e-12, so
     # at k > 0 the comparison sees the GEMMs' rounding, not the stopping
-    # test's error; at k = 0 the Neumann problem's conditioning leaves more.
+    # test's error.
     monkeypatch.setenv("SMPM_ELEM_SCHED", str(sched))
     p = _sched_problem()
-    s, u, st = _gpu_solve(p, tol=1e-12)
+    s, u, st = _gpu_solve(p, tol=TIGHT)
     assert all(v == sched for i in s.info for v in i["elem_sched"] if v >= 0)
-    assert st["rel_residual_max"] <= ACCEPT
+    assert st["rel_residual_max"] <= ACCEPT_TIGHT
     u = u.reshape(2, 2, p.r)
     for (m, q), ref in sched_refs.items():
-        assert _rel(u[m, q], ref) <= (1e-9 if m == 0 else 1e-11), (sched, m, q)
+        assert _rel(u[m, q], ref.u) <= (ref.bound if m == 0 else 1e-11), (sched, m, q)
 
 
-@pytest.mark.parametrize("sched", [0, 1, 2, 3, 4, 5])
+@pytest.mark.parametrize("sched", [0, 1, 2, 3, 4, 5, 6, 7])
 @pytest.mark.parametrize("precision", [P.FP64, P.FP32_IR])
 def test_shared_block_gemm_schedules_match_oracle(sched, precision, monkeypatch, sched_refs):
     # Every schedule of the shared-block S and M^-1 GEMMs, pinned for all lists
-    # (the fused S M^-1 block included): split K over 16 or 8 waves, and the
+    # (the fused S M^-1 block included): split K over 16 or 8 waves, the
     # LDS-staged 64-row tile, XCD-ordered or plain, staging 32 or 64 K-values
-    # per chunk.  FP32 refinement reaches the same FP64 solution.
+    # per chunk, and split K with a wave's whole K range in flight (lists of
+    # at most 16 windows per item; wider lists run split K 8 under that id).
+    # FP32 refinement reaches the same FP64 solution.
     monkeypatch.setenv("SMPM_GEMM_SCHED", str(sched))
     p = _sched_problem()
-    s, u, st = _gpu_solve(p, precision=precision, tol=1e-12)
+    s, u, st = _gpu_solve(p, precision=precision, tol=TIGHT)
     assert all(v == sched for i in s.info for v in i["gemm_sched"] if v >= 0)
-    assert st["rel_residual_max"] <= 1e-12 * 1.001
+    assert st["rel_residual_max"] <= ACCEPT_TIGHT
     u = u.reshape(2, 2, p.r)
     for (m, q), ref in sched_refs.items():
-        assert _rel(u[m, q], ref) <= (1e-9 if m == 0 else 1e-11), (sched, m, q)
+        assert _rel(u[m, q], ref.u) <= (ref.bound if m == 0 else 1e-11), (sched, m, q)
 
 
-def test_fp32_refinement_reaches_fp64_solution():
-    p = workloads.random_problem(12, 3, 7, seed=5, stretch=True)
-    s, u, st = _gpu_solve(p, precision=P.FP32_IR)
-    o, ref = _oracle(p, 0, 0, tol=1e-12)
-    print("ir stats", st)
-    assert st["rel_residual_max"] <= ACCEPT
+@pytest.mark.parametrize("k", [0.0, 2.1])
+def test_fp32_refinement_reaches_fp64_solution(k):
+    p = workloads.random_problem(12, 3, 7, kwaves=(k,), seed=5, stretch=True)
+    s, u, st = _gpu_solve(p, precision=P.FP32_IR, tol=TIGHT)
+    o, ref = _oracle(p, 0, 0, tol=TIGHT)
+    print("ir stats", st, "rel", _rel(u, ref.u))
+    assert st["rel_residual_max"] <= ACCEPT_TIGHT
     assert st["sweeps_max"] >= 2
-    assert _rel(u, ref.u) <= 1e-8
+    assert _rel(u, ref.u) <= ref.bound
+
+
+@pytest.mark.parametrize("k,inner_tol", [(0.0, 1e-4), (2.1, 1e-4), (0.0, 1e-6)])
+def test_fp32_refinement_counts_match_oracle(k, inner_tol):
+    # Sweeps and inner GMRES iterations of the refined form against the
+    # oracle's emulation (operators and inner vectors rounded to FP32, the
+    # same inner stopping rule max(inner_tol |r|, tol |b~| / 2)): sweeps
+    # within one, the inner iterations summed over the sweeps within one per
+    # sweep (the FP32 rounding of the two Arnoldi processes can move an
+    # iteration from one sweep to the next).
+    p = workloads.random_problem(12, 3, 7, kwaves=(k,), seed=5, stretch=True)
+    s, u, st = _gpu_solve(p, precision=P.FP32_IR, inner_tol=inner_tol)
+    grid = smpm.Grid(p.xb, p.zb, p.n)
+    o = schur.build(grid, kwave=k)
+    ref, sweeps, total = solve.refine_solve(o, smpm.rhs(grid, o.tau, p.f[0, 0]), inner_tol=inner_tol,
+                                           floor=0.5)
+    print("ir counts", st, "oracle sweeps", sweeps, "inner", ref.inner)
+    assert ref.converged and st["rel_residual_max"] <= ACCEPT
+    assert abs(st["sweeps_max"] - sweeps) <= 1
+    assert abs(st["iters_total"] - total) <= sweeps
 
 
 @pytest.mark.parametrize("batched", [False, True])
@@ -296,7 +369,7 @@ def test_repeated_fp64_solves_resume_after_a_short_prediction(batched):
     # the same right-hand side gives the same counts whatever came before,
     # and the two differ (so one of them resumes after its tail)
     assert its[0] == its[2] and its[1] == its[3] and its[0] != its[1]
-    if not batched:
+    if not batched:   # the last (resumed) solve, at 1e-10 on both sides
         grid = smpm.Grid(p.xb, p.zb, p.n)
         o = schur.build(grid)
         ref = solve.dbj_solve(o, smpm.rhs(grid, o.tau, f_hard)).u
@@ -310,7 +383,7 @@ def test_repeated_refinement_solves(precision):
     # on if needed: same right-hand side (exact prediction), then a harder one
     # (a 40x larger random part, prediction too short), then the first again.
     p = workloads.random_problem(12, 3, 7, seed=5, stretch=True)
-    s = P.Solver(p.xb, p.zb, p.n - 1, precision=precision, tune=False)
+    s = P.Solver(p.xb, p.zb, p.n - 1, precision=precision, tune=False, tol=TIGHT)
     f1 = p.f.reshape(-1)
     f2 = f1 + 40.0 * np.random.default_rng(9).standard_normal(f1.size)
     grid = smpm.Grid(p.xb, p.zb, p.n)
@@ -320,11 +393,12 @@ def test_repeated_refinement_solves(precision):
         u, st, status = s.solve(_dev(f))
         torch.cuda.synchronize()
         if name not in refs:
-            refs[name] = solve.dbj_solve(o, smpm.rhs(grid, o.tau, f), tol=1e-12).u
-        print(name, st)
+            F = smpm.rhs(grid, o.tau, f)
+            refs[name] = (solve.dbj_solve(o, F, tol=TIGHT).u, _bound(o, F))
+        print(name, st, "rel", _rel(u.cpu().numpy(), refs[name][0]))
         assert status == P.OK
-        assert st["rel_residual_max"] <= ACCEPT
-        assert _rel(u.cpu().numpy(), refs[name]) <= 1e-8
+        assert st["rel_residual_max"] <= ACCEPT_TIGHT
+        assert _rel(u.cpu().numpy(), refs[name][0]) <= refs[name][1]
 
 
 @pytest.mark.parametrize("k", [0.0, 2.3])
@@ -375,16 +449,17 @@ def test_solve_is_bitwise_deterministic():
 def test_batch_of_uneven_problems():
     probs = workloads.c5(seed=0, nprob=4, scale=0.1)
     grids = [(p.xb, p.zb, p.n - 1, float(p.kwaves[0])) for p in probs]
-    s = P.Solver(grids=grids)
+    s = P.Solver(grids=grids, tol=TIGHT)
     f = _dev(np.concatenate([p.f.reshape(-1) for p in probs]))
     u, st, status = s.solve(f)
+    assert st["rel_residual_max"] <= ACCEPT_TIGHT
     u = u.cpu().numpy()
     off = 0
     for i, p in enumerate(probs):
-        o, ref = _oracle(p, 0, 0)
+        o, ref = _oracle(p, 0, 0, tol=TIGHT)
         ui = u[off:off + p.r]
         off += p.r
-        assert _rel(ui, ref.u) <= 1e-9, i
+        assert _rel(ui, ref.u) <= ref.bound, i
 
 
 def test_notconv_and_nonfinite_statuses():

@@ -188,3 +188,22 @@ def test_paper_coarse_null_vector_gap_is_reported():
     gap = np.linalg.norm(v @ s.C) / np.linalg.norm(s.C)
     assert np.linalg.norm(s.uC @ s.C) / np.linalg.norm(s.C) < 1e-12
     assert gap < 1e-6
+
+
+def test_banded_left_null_route_on_a_long_grid(monkeypatch):
+    # The route taken above BORDERED_MAX_K unknowns (a banded LU of S^T with
+    # one diagonal entry raised), forced on the same 12:1 grid: the same
+    # left singular vector of the dense S, and a residual at the rounding of
+    # S.  Also with the first pivot entry placed where u_S is smallest.
+    from oracle import schur as sch
+    s = _sys(24, 4, 7)
+    Sd = s.S.toarray()
+    U, sv, Vt = np.linalg.svd(Sd)
+    u_svd = U[:, -1] * np.sign(U[:, -1].sum())
+    v = sch._left_null_banded(s.S, s.grid.nhalf)
+    v = v / np.linalg.norm(v) * np.sign(v.sum())
+    assert 1 - abs(u_svd @ v) < 1e-12
+    assert np.linalg.norm(v @ Sd) < 1e-13 * np.abs(Sd).sum(axis=0).max()
+    monkeypatch.setattr(sch, "BORDERED_MAX_K", 0)
+    uS, _, _ = sch.null_vectors(s)
+    assert np.abs(uS - s.uS).max() < 1e-12
