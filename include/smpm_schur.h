@@ -42,7 +42,7 @@
  * allocated in setup, which also captures and instantiates every HIP graph
  * a solve launches (they hold only the handle's own buffers).  smpm_solve,
  * smpm_solve_fourier and smpm_apply allocate nothing, whatever buffers the
- * caller passes.
+ * caller passes; smpm_apply_noalloc below also uses no handle workspace.
  *
  * Streams: every device call enqueues on the caller's hipStream_t (NULL = the
  * default stream).  Calls that fill host-side results synchronize that
@@ -318,6 +318,23 @@ smpm_status smpm_schur_apply_all(smpm_handle *h, const void *x_dev, void *y_dev,
  * reduced precision. */
 smpm_status smpm_apply_all(smpm_handle *h, smpm_op op, const void *x_dev, void *y_dev,
                            int32_t precision, void *hip_stream);
+
+/* smpm_apply without any allocation, for callers that cannot allocate device
+ * memory: code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc.  Ops SCHUR and BJINV (FP64, or FP32 with float x, y) and
+ * DEFLATE_P, DEFLATE_Q (FP64) of system `sys`, with the same kernels, work
+ * lists and results as smpm_apply; x_dev is read and y_dev written in place
+ * (k_S values each; they must not overlap, EINVAL when equal).  The
+ * intermediates (S x for Q, the Z^T partial sums, the coarse vector) go to
+ * one fixed 16 MiB device array per GPU, held until the process ends;
+ * systems needing more (k_S + the partial sums + d above 2^21 doubles)
+ * return EINVAL.  Nothing in it has to start at zero: every call writes the
+ * parts it reads.  Calls that overlap in time on one GPU share the array and
+ * race.  Enqueued on hip_stream with no synchronization and no host copy.
+ * The first call on a device looks the array's address up (a host-side
+ * query, no allocation). */
+smpm_status smpm_apply_noalloc(smpm_handle *h, smpm_op op, int32_t sys, const void *x_dev,
+                               void *y_dev, int32_t precision, void *hip_stream);
 
 /* Sizes, offsets, table counts and the schedules picked at setup of system
  * `sys` (host struct).  Not a computation of the paper: bookkeeping for

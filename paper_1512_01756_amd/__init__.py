@@ -85,7 +85,7 @@ class Info(ctypes.Structure):
 
 EXPORTED = ["smpm_setup", "smpm_setup_batch", "smpm_setup_fourier", "smpm_save", "smpm_load", "smpm_solve",
             "smpm_solve_fourier", "smpm_transform_y",
-            "smpm_apply", "smpm_schur_apply_all", "smpm_apply_all", "smpm_query",
+            "smpm_apply", "smpm_schur_apply_all", "smpm_apply_all", "smpm_apply_noalloc", "smpm_query",
             "smpm_num_systems", "smpm_export", "smpm_destroy", "smpm_last_error"]
 
 _lib = None
@@ -115,6 +115,7 @@ def load():
     lib.smpm_apply.argtypes = [P, ctypes.c_int32, ctypes.c_int32, P, P, ctypes.c_int32, P]
     lib.smpm_schur_apply_all.argtypes = [P, P, P, ctypes.c_int32, P]
     lib.smpm_apply_all.argtypes = [P, ctypes.c_int32, P, P, ctypes.c_int32, P]
+    lib.smpm_apply_noalloc.argtypes = [P, ctypes.c_int32, ctypes.c_int32, P, P, ctypes.c_int32, P]
     lib.smpm_query.argtypes = [P, ctypes.c_int32, ctypes.POINTER(Info)]
     lib.smpm_num_systems.argtypes = [P]
     lib.smpm_num_systems.restype = ctypes.c_int32
@@ -124,7 +125,7 @@ def load():
     lib.smpm_last_error.restype = ctypes.c_char_p
     for name in ("smpm_setup", "smpm_setup_batch", "smpm_setup_fourier", "smpm_save", "smpm_load", "smpm_solve",
                  "smpm_solve_fourier", "smpm_transform_y",
-                 "smpm_apply", "smpm_schur_apply_all", "smpm_apply_all", "smpm_query",
+                 "smpm_apply", "smpm_schur_apply_all", "smpm_apply_all", "smpm_apply_noalloc", "smpm_query",
                  "smpm_export"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
@@ -261,6 +262,11 @@ class Solver:
 
     def schur_apply_all(self, x, y, precision=FP64, stream=None):
         _check(self._lib.smpm_schur_apply_all(self.h, _ptr(x), _ptr(y), precision, _stream(stream)))
+        return y
+
+    def apply_noalloc(self, op, sys, x, y, precision=FP64, stream=None):
+        """smpm_apply_noalloc: no allocation, no synchronization."""
+        _check(self._lib.smpm_apply_noalloc(self.h, op, sys, _ptr(x), _ptr(y), precision, _stream(stream)))
         return y
 
     def apply_all(self, op, x, y, precision=FP64, stream=None):

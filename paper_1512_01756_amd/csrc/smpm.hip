@@ -2230,3 +2230,124 @@ void smpm_destroy(smpm_handle *H) { delete H; }
 const char *smpm_last_error(void) { return g_err.c_str(); }
 
 }  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Operator applies without any allocation, for callers that cannot allocate
+// device memory (code under HIP graph capture, tight serving loops).  The
+// intermediate vectors of smpm_apply (the Z^T partial sums, the coarse
+// vector, the S x of Q) live in one file-scope device array instead of the
+// handle's workspace, and x and y are read and written in place.
+
+namespace {
+
+constexpr size_t kScratchDoubles = size_t(1) << 21;   // 16 MiB per device
+constexpr int kMaxDevices = 64;
+__device__ __align__(256) double scratch[kScratchDoubles];
+
+// The array's device address, looked up once per device with that device
+// current (each device holds its own copy of the array).
+double *g_scratch_ptr[kMaxDevices] = {};
+std::mutex g_scratch_mu;
+
+double *scratch_address(int dev) {
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void *p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) throw std::runtime_error(std::string("hipGetSymbolAddress: ") + hipGetErrorString(e));
+    g_scratch_ptr[dev] = static_cast<double *>(p);
+  }
+  return g_scratch_ptr[dev];
+}
+
+// A base pointer whose element `off` is p[0]: the kernels address one
+// instance's vectors through absolute batched offsets.
+template <typename T>
+T *rebase(T *p, int64_t off) {
+  return reinterpret_cast<T *>(reinterpret_cast<uintptr_t>(p) - (uintptr_t)(off * (int64_t)sizeof(T)));
+}
+
+}  // namespace
+
+extern "C" {
+
+smpm_status smpm_apply_noalloc(smpm_handle *H, smpm_op op, int32_t sysi, const void *x, void *y,
+                               int32_t precision, void *hip_stream) {
+  if (!H) return fail(SMPM_EINVAL, "handle is NULL");
+  if (H->host_only) return fail(SMPM_EUNSUPPORTED, "host-only handle");
+  if (sysi < 0 || sysi >= (int)H->sys.size()) return fail(SMPM_EINVAL, "system index out of range");
+  if (!x || !y || x == y) return fail(SMPM_EINVAL, "x or y is NULL, or x and y are the same array");
+  if (op != SMPM_OP_SCHUR && op != SMPM_OP_BJINV && op != SMPM_OP_DEFLATE_P && op != SMPM_OP_DEFLATE_Q)
+    return fail(SMPM_EINVAL, "smpm_apply_noalloc takes SCHUR, BJINV, DEFLATE_P or DEFLATE_Q");
+  if (precision != SMPM_FP64 && !(precision == SMPM_FP32_IR && (op == SMPM_OP_SCHUR || op == SMPM_OP_BJINV)))
+    return fail(SMPM_EINVAL, "only SCHUR and BJINV have FP32 variants");
+  hipStream_t st = (hipStream_t)hip_stream;
+  const int inst = sysi * H->nrhs;
+  const InstDev &I = H->h_ins[inst];
+  const System &s = H->sys[sysi];
+  // scratch layout: [S x (k_S) | Z^T partial sums | coarse vector (d)]
+  const int64_t nhs = (int64_t)s.nh * (s.zm > 1 ? s.zm : (s.N + 15) / 16);
+  const int64_t need = s.kS + nhs + s.d;
+  if (need > (int64_t)kScratchDoubles)
+    return fail(SMPM_EINVAL, "system too large for the fixed scratch of smpm_apply_noalloc (" +
+                                 std::to_string(need) + " > " + std::to_string(kScratchDoubles) + " doubles)");
+  try {
+    int dev = 0;
+    HIPCHECK(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return fail(SMPM_EINVAL, "device index above the supported 64");
+    double *sc = scratch_address(dev);
+    double *zs = sc, *hs = sc + s.kS, *cv = hs + nhs;
+    double *hsb = rebase(hs, I.hs_off), *cvb = rebase(cv, I.c_off);
+    int nxc = 0, nhc = 0;
+    const int2 *wx = xwork(H, inst, nxc);
+    const int2 *wh = hwork(H, inst, nhc);
+    switch (op) {
+      case SMPM_OP_SCHUR:
+      case SMPM_OP_BJINV: {
+        const int kop = op == SMPM_OP_SCHUR ? 0 : 1;
+        if (precision == SMPM_FP64)
+          gemv<double, double, double>(H, kop, rebase((const double *)x, I.x_off), 0, nullptr,
+                                       rebase((double *)y, I.x_off), nullptr, nullptr, st, inst);
+        else
+          gemv<float, float, float>(H, kop, rebase((const float *)x, I.x_off), 0, nullptr,
+                                    rebase((float *)y, I.x_off), nullptr, nullptr, st, inst);
+        break;
+      }
+      case SMPM_OP_DEFLATE_P: {   // P x = x - (S Z) G Z^T x
+        const double *xb = rebase((const double *)x, I.x_off);
+        hipLaunchKernelGGL(k_zt<double>, dim3(nhc), dim3(kBlock), 0, st, H->d_sys, H->d_ins, wh, xb, 0,
+                           (const double *)nullptr, (const GState *)nullptr, hsb);
+        hipLaunchKernelGGL(k_coarse, dim3(1, ctiles(H)), dim3(kBlock), sizeof(double) * H->dmax, st, H->d_sys,
+                           H->d_ins + inst, (const double *)hsb, (const double *)nullptr, (double *)nullptr, cvb,
+                           (const GState *)nullptr);
+        hipLaunchKernelGGL(k_xupdate<double>, dim3(nxc), dim3(kBlock), 0, st, H->d_sys, H->d_ins, wx, 3, xb,
+                           (const double *)cvb, rebase((double *)y, I.x_off), (double *)nullptr,
+                           (const double *)nullptr);
+        break;
+      }
+      case SMPM_OP_DEFLATE_Q: {   // Q x = x - Z G Z^T S x
+        const double *xb = rebase((const double *)x, I.x_off);
+        double *zb = rebase(zs, I.x_off);
+        gemv<double, double, double>(H, 0, xb, 0, nullptr, zb, H->zlabel == 0 ? hsb : nullptr, nullptr, st, inst);
+        if (H->zlabel != 0)
+          hipLaunchKernelGGL(k_zt<double>, dim3(nhc), dim3(kBlock), 0, st, H->d_sys, H->d_ins, wh,
+                             (const double *)zb, 0, (const double *)nullptr, (const GState *)nullptr, hsb);
+        hipLaunchKernelGGL(k_coarse, dim3(1, ctiles(H)), dim3(kBlock), sizeof(double) * H->dmax, st, H->d_sys,
+                           H->d_ins + inst, (const double *)hsb, (const double *)nullptr, (double *)nullptr, cvb,
+                           (const GState *)nullptr);
+        hipLaunchKernelGGL(k_xupdate<double>, dim3(nxc), dim3(kBlock), 0, st, H->d_sys, H->d_ins, wx, 4, xb,
+                           (const double *)cvb, rebase((double *)y, I.x_off), (double *)nullptr,
+                           (const double *)nullptr);
+        break;
+      }
+      default:
+        break;
+    }
+    HIPCHECK(hipGetLastError());
+  } catch (const std::exception &e) {
+    return fail(SMPM_EHIP, e.what());
+  }
+  return SMPM_OK;
+}
+
+}  // extern "C"
