@@ -2005,6 +2005,109 @@ __global__ __launch_bounds__(256) void k_fft_y(const double *__restrict__ in, do
   }
 }
 
+// The same transforms for m_y = 2^LOGMY <= 2048 with every size fixed at
+// compile time, two real columns per complex FFT: a workgroup takes 2 CT
+// consecutive columns (CT = 2048 / m_y) and stages z = x_c + i x_{c+CT}
+// (32 KiB of LDS, so several workgroups share a CU).  All of a thread's
+// loads are issued before it writes the staging buffer.  Forward: with Z the
+// FFT of z, X_c(m) = (Z_m + conj Z_{m_y-m}) / 2 and X_{c+CT}(m) = (Z_m -
+// conj Z_{m_y-m}) / (2 i).  Inverse: Z_m = X_c(m) + i X_{c+CT}(m) over all
+// m by the Hermitian symmetry of both spectra; the inverse FFT of Z is then
+// x_c + i x_{c+CT}.
+constexpr int kFftPackSlots = 2048;
+template <int LOGMY, bool INV>
+__global__ __launch_bounds__(256) void k_fft_y_pack(const double *__restrict__ in, double *__restrict__ out,
+                                                    int64_t ncol, const double2 *__restrict__ tw) {
+  constexpr int MY = 1 << LOGMY, CT = kFftPackSlots / MY, CW = 2 * CT, NK = MY / 2 + 1;
+  static_assert(CT >= 1, "m_y too large for the packed FFT");
+  __shared__ double2 fb[MY * CT];
+  const int64_t c0 = (int64_t)blockIdx.x * CW;
+  const int nc = (int)min<int64_t>(CW, ncol - c0);
+  auto brev = [](int j) { return (int)(__brev((unsigned)j) >> (32 - LOGMY)); };
+  if (!INV) {
+    constexpr int PER = MY * CW / 256;   // values per thread
+    double v[PER];
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      const int idx = threadIdx.x + 256 * q, j = idx / CW, cc = idx % CW;
+      v[q] = cc < nc ? in[(int64_t)j * ncol + c0 + cc] : 0.0;
+    }
+    double *fd = reinterpret_cast<double *>(fb);
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      const int idx = threadIdx.x + 256 * q, j = idx / CW, cc = idx % CW;
+      fd[2 * (brev(j) * CT + cc % CT) + cc / CT] = v[q];
+    }
+  } else {
+    constexpr int ITEMS = NK * CT, PER = (ITEMS + 255) / 256;
+    double4 v[PER];
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      const int idx = threadIdx.x + 256 * q, m = idx / CT, c = idx % CT;
+      v[q] = make_double4(0.0, 0.0, 0.0, 0.0);
+      if (idx < ITEMS) {
+        const double *r0 = in + (int64_t)(2 * m) * ncol + c0, *r1 = r0 + ncol;
+        if (c < nc) { v[q].x = r0[c]; v[q].y = r1[c]; }
+        if (c + CT < nc) { v[q].z = r0[c + CT]; v[q].w = r1[c + CT]; }
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      const int idx = threadIdx.x + 256 * q, m = idx / CT, c = idx % CT;
+      if (idx >= ITEMS) continue;
+      double a = v[q].x, b = v[q].y, e = v[q].z, d = v[q].w;   // X_c = a + i b, X_{c+CT} = e + i d
+      if (m == 0 || m == MY / 2) b = d = 0.0;                  // real modes
+      fb[brev(m) * CT + c] = make_double2(a - d, b + e);
+      if (m > 0 && m < MY / 2) fb[brev(MY - m) * CT + c] = make_double2(a + d, e - b);
+    }
+  }
+  __syncthreads();
+  constexpr int NB = (MY / 2) * CT, BPER = (NB + 255) / 256;
+#pragma unroll
+  for (int s = 0; s < LOGMY; ++s) {
+    const int half = 1 << s, stride = (MY / 2) >> s;
+#pragma unroll
+    for (int q = 0; q < BPER; ++q) {
+      const int idx = threadIdx.x + 256 * q;
+      if (NB % 256 != 0 && idx >= NB) continue;
+      const int p = idx / CT, c = idx % CT;
+      const int k = p & (half - 1);
+      const int i0 = ((p >> s) << (s + 1)) + k, i1 = i0 + half;
+      double2 w = tw[k * stride];
+      if (INV) w.y = -w.y;
+      const double2 a = fb[i0 * CT + c], b = fb[i1 * CT + c];
+      const double2 t = make_double2(w.x * b.x - w.y * b.y, w.x * b.y + w.y * b.x);
+      fb[i0 * CT + c] = make_double2(a.x + t.x, a.y + t.y);
+      fb[i1 * CT + c] = make_double2(a.x - t.x, a.y - t.y);
+    }
+    __syncthreads();
+  }
+  if (!INV) {
+    constexpr double sc = 0.5 / MY;
+    constexpr int ITEMS = 2 * NK * CW;
+    for (int idx = threadIdx.x; idx < ITEMS; idx += 256) {
+      const int row = idx / CW, cc = idx % CW;
+      if (cc >= nc) continue;
+      const int m = row >> 1, c = cc % CT;
+      const double2 A = fb[m * CT + c], B = fb[((MY - m) & (MY - 1)) * CT + c];
+      double val;
+      if (cc < CT)   // (A + conj B) / 2
+        val = (row & 1) ? (A.y - B.y) : (A.x + B.x);
+      else           // (A - conj B) / (2 i)
+        val = (row & 1) ? -(A.x - B.x) : (A.y + B.y);
+      out[(int64_t)row * ncol + c0 + cc] = val * sc;
+    }
+  } else {
+    constexpr int ITEMS = MY * CW;
+    for (int idx = threadIdx.x; idx < ITEMS; idx += 256) {
+      const int j = idx / CW, cc = idx % CW;
+      if (cc >= nc) continue;
+      const double2 z = fb[j * CT + cc % CT];
+      out[(int64_t)j * ncol + c0 + cc] = cc < CT ? z.x : z.y;
+    }
+  }
+}
+
 __global__ __launch_bounds__(kBlock) void k_fill(double *__restrict__ p, int64_t n, double v) {
   const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (i < n) p[i] = v;

@@ -1480,6 +1480,24 @@ void transform_y(smpm_handle *H, bool inverse, const double *in, double *out, in
   if (H->fft_tw) {
     int logmy = 0;
     while ((1 << logmy) < my) ++logmy;
+    if (my >= 8 && my <= kFftPackSlots) {   // two real columns per complex FFT, sizes fixed at compile time
+      const dim3 grid((unsigned)((ncol + 2 * (kFftPackSlots / my) - 1) / (2 * (kFftPackSlots / my))));
+      const double2 *tw = (const double2 *)H->fft_tw;
+      switch (logmy * 2 + (inverse ? 1 : 0)) {
+#define SMPM_FFT_CASE(L)                                                                                   \
+  case 2 * L:                                                                                              \
+    hipLaunchKernelGGL((k_fft_y_pack<L, false>), grid, dim3(256), 0, st, in, out, ncol, tw);              \
+    return;                                                                                                \
+  case 2 * L + 1:                                                                                          \
+    hipLaunchKernelGGL((k_fft_y_pack<L, true>), grid, dim3(256), 0, st, in, out, ncol, tw);               \
+    return;
+        SMPM_FFT_CASE(3) SMPM_FFT_CASE(4) SMPM_FFT_CASE(5) SMPM_FFT_CASE(6) SMPM_FFT_CASE(7) SMPM_FFT_CASE(8)
+        SMPM_FFT_CASE(9) SMPM_FFT_CASE(10) SMPM_FFT_CASE(11)
+#undef SMPM_FFT_CASE
+        default:
+          break;
+      }
+    }
     const int CT = kFftSlots / my;
     const dim3 grid((unsigned)((ncol + CT - 1) / CT));
     const size_t shm = sizeof(double2) * kFftSlots;
