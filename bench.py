@@ -204,7 +204,10 @@ def gemm_kernel_name(s, op, dtype):
              4: "k_half_gemm_t<{t}> (LDS-staged, XCD-ordered, 64-value chunks)",
              5: "k_half_gemm_t<{t}> (LDS-staged, 64-value chunks)",
              6: "k_half_gemm<{t}, 8, 24> (split-K, 8 waves, 24 K-steps in flight)",
-             7: "k_half_gemm<{t}, 16, 18> (split-K, 16 waves, 18 K-steps in flight)"}
+             7: "k_half_gemm<{t}, 16, 18> (split-K, 16 waves, 18 K-steps in flight)",
+             8: "k_half_gemm_t<{t}> (LDS-staged, 128-row tile)",
+             9: "k_half_gemm_t<{t}> (LDS-staged, 64-row tile, K split 4 ways)",
+             10: "k_half_gemm_t<{t}> (LDS-staged, 128-row tile, K split 2 ways)"}
     t = "double" if dtype == "fp64" else "float"
     out = set()
     for i in s.info:
@@ -223,8 +226,10 @@ def gemm_kernel_name(s, op, dtype):
 # Keyed by (workload, operation, kernel): a run whose setup picked another
 # kernel reports no traffic, and an entry is dropped when its kernel changes.
 KERNEL_TRAFFIC = {
-    ("c2", "schur", "k_half_gemm<double, 16> (split-K, 16 waves)"): 6.482e6,
+    ("c2", "schur", "k_half_gemm<double, 8> (split-K, 8 waves)"): 6.495e6,
+    ("c2", "schur_bjinv", "k_half_gemm<double, 16> (split-K, 16 waves) over the stored S M^-1 blocks"): 2.170e7,
     ("c3", "schur", "k_half_gemv_stream<double> (distinct blocks)"): 3.568e8,
+    ("c4", "schur", "k_half_gemm_t<double> (LDS-staged, XCD-ordered)"): 9.522e7,
 }
 
 
@@ -255,7 +260,7 @@ def rooflines(cfg, s64, stream, reps):
     ms = kernel_ms(lambda: s64.apply_all(P.OP_AINV, r, ro, P.FP64), max(reps // 4, 20), stream)
     fl, by = alg_ainv(s64)
     out["element_interior_fp64"] = roofline("k_colgemm(_t) D^-1, k_lambda, K^-1, correction", ms, fl, by, "fp64")
-    for key, op in (("schur_matvec_fp64", "schur"),):
+    for key, op in (("schur_matvec_fp64", "schur"), ("schur_bjinv_fp64", "schur_bjinv")):
         t = KERNEL_TRAFFIC.get((cfg, op, out[key]["kernel"]))
         out[key]["traffic"] = t
     return out

@@ -175,8 +175,10 @@ typedef struct {
                               XCD-ordered, 3 LDS-staged plain, 4 / 5 the same two
                               staging 64 K-values per chunk, 6 / 7 split-K 8 / 16
                               waves with a wave's K range in flight at once, for
-                              lists of at most 16 windows per item; -1 no shared
-                              blocks).  SMPM_GEMM_SCHED = 0..7 in the environment,
+                              lists of at most 16 windows per item, 8 LDS-staged
+                              128-row tiles, 9 / 10 64- / 128-row tiles whose 16
+                              waves also split K; -1 no shared blocks).
+                              SMPM_GEMM_SCHED = 0..10 in the environment,
                               read at setup and load, pins them all (tests,
                               experiments) */
   int32_t elem_sched[6];   /* same for the element-interior GEMM lists

@@ -441,30 +441,39 @@ __global__ __launch_bounds__(64 * KP) void k_half_gemm(
   }
 }
 
-// Throughput schedule (many items): one workgroup per (item, 64-row tile),
-// items of up to 16 CT windows (CT = 4, or 1 for blocks that serve at most
-// 16 halves), 4 waves of 16 rows over all of K; the windows are staged through
-// double-buffered LDS in chunks of 32 K-steps with coalesced loads while the
-// next chunk's operands are in flight.  The (item, tile) pairs come in an
-// XCD-aware order (`units`): workgroup L runs on XCD L mod 8, and every tile
-// that reads one stored block is placed on the same XCD, so the block and the
-// windows are fetched into one L2 instead of eight.
-template <typename TS, typename TO, typename TX, typename TY, int CT, int KC>
-__global__ __launch_bounds__(256) void k_half_gemm_t(
+// Throughput schedule (many items): one workgroup per (item, row tile of
+// 16 RW rows), items of up to 16 CT windows (CT = 2, or 1 for items of at
+// most 16 windows), RW x KW waves: wave (r, p) takes rows 16 r .. 16 r + 15
+// of the tile and every KW-th chunk of K starting at chunk p.  The windows
+// are staged through double-buffered LDS, KW chunks of KC K-values at a
+// time, with coalesced loads while the next chunks' operands are in flight;
+// every wave of the tile reads them from there.  With KW > 1 the K parts
+// are summed through LDS in a fixed order before the epilogue.  RW = 4,
+// KW = 1 is the 64-row tile whose (item, tile) pairs may come in an
+// XCD-aware order (`units`): workgroup L runs on XCD L mod 8, and every
+// tile that reads one stored block is placed on the same XCD, so the block
+// and the windows are fetched into one L2 instead of eight.
+template <typename TS, typename TO, typename TX, typename TY, int CT, int KC, int RW = 4, int KW = 1>
+__global__ __launch_bounds__(64 * RW * KW) void k_half_gemm_t(
     const GWork *__restrict__ work, const int2 *__restrict__ units, const GVec *__restrict__ gvec,
     const TX *__restrict__ xbase, int x_vslot, const double *__restrict__ scale, TY *__restrict__ ybase,
     double *__restrict__ hsum, const GState *__restrict__ gs) {
-  // Staging as in k_colgemm_t: the TPC threads of a window read its chunk
-  // interleaved (thread j takes k = j + TPC p), and the row pitch puts the
-  // lanes that the LDS serves together (16 for 8-byte, 32 for 4-byte values)
-  // in distinct bank slots for the stores and the MFMA operand reads.
-  constexpr int VT = 16 * CT, PITCH = VT + (sizeof(TO) == 8 ? CT : 2 * CT);
-  constexpr int PV = KC * VT / 256;      // staged values per thread per chunk
-  constexpr int TPC = KC / PV;           // threads per window
-  __shared__ TO Bs[2][KC * PITCH];
+  // Staging as in k_colgemm_t: the TPC threads of a window read its KW KC
+  // values interleaved (thread j takes k = j + TPC p), and the row pitch puts
+  // the lanes that the LDS serves together (16 for 8-byte, 32 for 4-byte
+  // values) in distinct bank slots for the stores and the MFMA operand reads.
+  constexpr int NT = 64 * RW * KW, VT = 16 * CT, PITCH = VT + (sizeof(TO) == 8 ? CT : 2 * CT);
+  constexpr int KS = KW * KC;             // K-values staged per step
+  constexpr int PV = KS * VT / NT;        // staged values per thread per step
+  constexpr int TPC = KS / PV;            // threads per window
+  static_assert(PV >= 1 && TPC * PV == KS && NT % VT == 0, "staging shape");
+  constexpr int BS = KS * PITCH;          // one staging buffer
+  constexpr int RED = (KW > 1 ? (KW - 1) * RW * 64 * CT * 4 : 1);
+  static_assert(KW == 1 || RED * sizeof(TO) <= 2 * BS * sizeof(TO), "reduction fits the staging buffers");
+  __shared__ TO Bs[2 * BS];
   __shared__ WinInfo wi[VT];
   int item = blockIdx.x, rg = blockIdx.y;
-  if (units) {   // XCD-ordered (item, 64-row tile) list; x < 0 pads a bucket
+  if (units) {   // XCD-ordered (item, row tile) list; x < 0 pads a bucket
     const int2 u = units[blockIdx.x];
     if (u.x < 0) return;
     item = u.x; rg = u.y;
@@ -472,7 +481,8 @@ __global__ __launch_bounds__(256) void k_half_gemm_t(
   const GWork wk = work[item];
   const int N = wk.N, Np = wk.Np, K = wk.K;
   const int64_t kS = wk.kS;
-  if (rg * 64 >= Np) return;
+  constexpr int TR = 16 * RW;             // rows per tile
+  if (rg * TR >= Np) return;
   load_windows<VT>(wk, gvec, x_vslot, scale, gs, wi);
   __syncthreads();
   int anylive = 0;
@@ -480,50 +490,51 @@ __global__ __launch_bounds__(256) void k_half_gemm_t(
   if (!anylive) return;
   const TS *__restrict__ blk = Tab<TS>::blk(wk);
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int arow = rg * 64 + wave * 16 + (lane & 15);
-  const bool alive = arow < Np, wlive = rg * 64 + wave * 16 < N;
+  const int wr = wave % RW, kp = wave / RW;
+  const int arow = rg * TR + wr * 16 + (lane & 15);
+  const bool alive = arow < Np, wlive = rg * TR + wr * 16 < N;
   const int kq = lane >> 4, cl = lane & 15;
   const int scol = threadIdx.x / TPC, sj = threadIdx.x % TPC;
   const bool slive = scol < wk.vcount && wi[scol].live;
   const int64_t sx = wi[scol].xoff, sw = wi[scol].win;
   TO pre[PV];
   TO a[KC / 4], an[KC / 4];
-  auto load_b = [&](int kc) {
+  auto load_b = [&](int st) {   // staging step st: K-values st KS .. st KS + KS
 #pragma unroll
     for (int p = 0; p < PV; ++p) {
-      const int k = kc * KC + sj + TPC * p;
+      const int k = st * KS + sj + TPC * p;
       const int64_t g = sw + k;
       pre[p] = (slive && k < K && g >= 0 && g < kS) ? (TO)xbase[sx + g] : (TO)0;
     }
   };
-  auto load_a = [&](int kc, TO *dst) {
+  auto load_a = [&](int st, TO *dst) {   // this wave's chunk of step st
 #pragma unroll
     for (int s = 0; s < KC / 4; ++s) {
-      const int k = kc * KC + 4 * s + kq;
+      const int k = st * KS + kp * KC + 4 * s + kq;
       dst[s] = (alive && k < K) ? (TO)blk[(size_t)k * Np + arow] : (TO)0;
     }
   };
   auto store_b = [&](int buf) {
 #pragma unroll
-    for (int p = 0; p < PV; ++p) Bs[buf][(sj + TPC * p) * PITCH + scol] = pre[p];
+    for (int p = 0; p < PV; ++p) Bs[buf * BS + (sj + TPC * p) * PITCH + scol] = pre[p];
   };
   using Acc = typename Mfma<TO>::Acc;
   Acc acc[CT];
 #pragma unroll
   for (int t = 0; t < CT; ++t) acc[t] = Acc{0, 0, 0, 0};
-  const int nchunks = (K + KC - 1) / KC;
+  const int nsteps = (K + KS - 1) / KS;
   load_b(0);
   load_a(0, a);
   store_b(0);
   __syncthreads();
-  for (int kc = 0; kc < nchunks; ++kc) {
-    const int buf = kc & 1;
-    const bool more = kc + 1 < nchunks;
+  for (int st = 0; st < nsteps; ++st) {
+    const int buf = st & 1;
+    const bool more = st + 1 < nsteps;
     if (more) {
-      load_b(kc + 1);
-      load_a(kc + 1, an);
+      load_b(st + 1);
+      load_a(st + 1, an);
     }
-    const TO *__restrict__ B = Bs[buf];
+    const TO *__restrict__ B = Bs + buf * BS + kp * KC * PITCH;
     if (wlive) {   // a wave whose 16 rows all lie past the block stages only
 #pragma unroll
       for (int s = 0; s < KC / 4; ++s)
@@ -537,8 +548,25 @@ __global__ __launch_bounds__(256) void k_half_gemm_t(
     }
     __syncthreads();
   }
+  if constexpr (KW > 1) {   // sum the K parts: part p > 0 through LDS, in order p = 1 .. KW - 1
+    TO *R = Bs;
+    if (kp > 0) {
+#pragma unroll
+      for (int t = 0; t < CT; ++t)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) R[((((kp - 1) * RW + wr) * CT + t) * 4 + j) * 64 + lane] = acc[t][j];
+    }
+    __syncthreads();
+    if (kp > 0) return;
+#pragma unroll
+    for (int q = 1; q < KW; ++q)
+#pragma unroll
+      for (int t = 0; t < CT; ++t)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[t][j] += R[((((q - 1) * RW + wr) * CT + t) * 4 + j) * 64 + lane];
+  }
   // epilogue: lane holds rows Mfma::row(lane, j) of windows t * 16 + cl
-  const int slot = rg * 4 + wave;
+  const int slot = rg * RW + wr;
 #pragma unroll
   for (int t = 0; t < CT; ++t) {
     const int v = t * 16 + cl;
@@ -546,7 +574,7 @@ __global__ __launch_bounds__(256) void k_half_gemm_t(
     double part = 0.0;
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
-      const int row = rg * 64 + wave * 16 + Mfma<TO>::row(lane, j);
+      const int row = rg * TR + wr * 16 + Mfma<TO>::row(lane, j);
       if (ok && row < N) {
         TO val = acc[t][j] * (TO)Tab<TS>::rs(wk, row);
         if (wk.ident) val += (TO)xbase[wi[v].xoff + wi[v].xh + row];

@@ -774,10 +774,14 @@ void upload(smpm_handle *H, hipStream_t st) {
 // kThrPlain64, twice the work between the chunk barriers).
 // kSplit8Deep / kSplit16Deep: split K over 8 or 16 waves with 24 or 18
 // K-steps of loads in flight per wave, for lists whose items hold at most
-// 16 windows (others run kSplit8 under these ids).
+// 16 windows (others run kSplit8 under these ids).  kTile128: the staged
+// tile with 128 rows (8 waves), so a window is staged once for up to 128
+// rows; kTile64K4 / kTile128K2: 64- or 128-row tiles whose 16 waves also
+// split K four or two ways (shorter MFMA chains per wave).  The staged
+// schedules hold 16 windows per item column group where the items do.
 enum GemmSched {
   kSplit16 = 0, kSplit8 = 1, kThrXcd = 2, kThrPlain = 3, kThrXcd64 = 4, kThrPlain64 = 5, kSplit8Deep = 6,
-  kSplit16Deep = 7, kNumSched = 8
+  kSplit16Deep = 7, kTile128 = 8, kTile64K4 = 9, kTile128K2 = 10, kNumSched = 11
 };
 
 // Default schedule when none was tuned (per-instance lists): by launch size.
@@ -793,7 +797,32 @@ void gemm_launch(smpm_handle *H, int sched, const GWork *w, int count, const int
                  bool narrow) {
   const int rt16 = (H->Nmax + 15) / 16;
   if ((sched == kSplit8Deep || sched == kSplit16Deep) && !narrow) sched = kSplit8;
+  auto tiles = [&](int rows) { return (unsigned)((H->Nmax + rows - 1) / rows); };
   switch (sched) {
+    case kTile128:
+      if (narrow)
+        hipLaunchKernelGGL((k_half_gemm_t<TS, TO, TX, TY, 1, 32, 8, 1>), dim3(count, tiles(128)), dim3(512), 0, st, w,
+                           (const int2 *)nullptr, H->g_vec, x, vslot, scale, y, hsum, gs);
+      else
+        hipLaunchKernelGGL((k_half_gemm_t<TS, TO, TX, TY, 2, 32, 8, 1>), dim3(count, tiles(128)), dim3(512), 0, st, w,
+                           (const int2 *)nullptr, H->g_vec, x, vslot, scale, y, hsum, gs);
+      break;
+    case kTile64K4:
+      if (narrow)
+        hipLaunchKernelGGL((k_half_gemm_t<TS, TO, TX, TY, 1, 32, 4, 4>), dim3(count, tiles(64)), dim3(1024), 0, st, w,
+                           (const int2 *)nullptr, H->g_vec, x, vslot, scale, y, hsum, gs);
+      else
+        hipLaunchKernelGGL((k_half_gemm_t<TS, TO, TX, TY, 2, 32, 4, 4>), dim3(count, tiles(64)), dim3(1024), 0, st, w,
+                           (const int2 *)nullptr, H->g_vec, x, vslot, scale, y, hsum, gs);
+      break;
+    case kTile128K2:
+      if (narrow)
+        hipLaunchKernelGGL((k_half_gemm_t<TS, TO, TX, TY, 1, 32, 8, 2>), dim3(count, tiles(128)), dim3(1024), 0, st, w,
+                           (const int2 *)nullptr, H->g_vec, x, vslot, scale, y, hsum, gs);
+      else
+        hipLaunchKernelGGL((k_half_gemm_t<TS, TO, TX, TY, 2, 32, 8, 2>), dim3(count, tiles(128)), dim3(1024), 0, st, w,
+                           (const int2 *)nullptr, H->g_vec, x, vslot, scale, y, hsum, gs);
+      break;
     case kSplit8Deep:
       hipLaunchKernelGGL((k_half_gemm<TS, TO, TX, TY, 8, 24, false>), dim3(count, rt16), dim3(512), 0, st, w, H->g_vec,
                          x, vslot, scale, y, hsum, gs);
@@ -1061,6 +1090,22 @@ void tune_schedules(smpm_handle *H, hipStream_t st) {
           else colgemm_w<kColVecs / 16>(H, H->cg_all[k][w], cnt, H->cg_units[k][w], H->n_cg_units[k][w], k == 2 ? 1 : 0, x, y, st, sc);
         })];
       }
+    // the Schur right-hand side: the B A^-1 GEMM, or the element solves of
+    // A^-1 and the B row functionals, whichever is faster (the GEMM's K is
+    // m_z n^2, which on tall high-order strips costs more than the solves)
+    if (H->use_ba)
+      H->use_ba = fastest(st, e0, e1, 2, [&](int c) {
+        if (c == 0) {
+          gemm_launch<double, double, double, double>(H, H->ba_sched, H->g_ba, H->n_ba, nullptr, 0, (const double *)H->F,
+                                                      0, nullptr, H->bS, nullptr, nullptr, st, H->ba_maxv <= 16);
+          hipLaunchKernelGGL(k_bS, dim3(H->n_h), dim3(kBlock), 0, st, H->d_sys, H->d_ins, H->w_h,
+                             (const double *)nullptr, H->bS, H->hs);
+        } else {
+          ainv(H, H->F, H->v, st);
+          hipLaunchKernelGGL(k_bS, dim3(H->n_h), dim3(kBlock), 0, st, H->d_sys, H->d_ins, H->w_h, (const double *)H->v,
+                             H->bS, H->hs);
+        }
+      }) == 0;
     HIPCHECK(hipGetLastError());
   } catch (...) {
     (void)hipEventDestroy(e0);
@@ -1072,7 +1117,7 @@ void tune_schedules(smpm_handle *H, hipStream_t st) {
 }
 
 // Schedules of the handle's GEMM lists, timed at setup (or by size).  The
-// environment variables SMPM_GEMM_SCHED = 0..7 and SMPM_ELEM_SCHED = 1..5 then
+// environment variables SMPM_GEMM_SCHED = 0..10 and SMPM_ELEM_SCHED = 1..5 then
 // pin every shared-block matvec list (split K over 16 or 8 waves, LDS-staged
 // XCD-ordered or plain, with 32- or 64-value chunks) or every element-interior
 // list (split K, LDS-staged XCD-ordered, plain, 32-row or 16-row K-split

@@ -61,10 +61,13 @@ def test_roofline_takes_the_binding_roof():
 
 
 def test_traffic_only_for_the_measured_kernel():
-    shared = {"gemm_sched": [0, 0, 0, 0]}
+    shared = {"gemm_sched": [1, 1, 1, 1]}
     name = bench.gemm_kernel_name(_Info([shared]), 0, "fp64")
     assert ("c2", "schur", name) in bench.KERNEL_TRAFFIC
-    other = dict(shared, gemm_sched=[1, 0, 0, 0])
+    other = dict(shared, gemm_sched=[0, 0, 0, 0])
     assert ("c2", "schur", bench.gemm_kernel_name(_Info([other]), 0, "fp64")) not in bench.KERNEL_TRAFFIC
+    fused = {"fused_sched": [0, 7]}
+    name = bench.gemm_kernel_name(_Info([fused]), 2, "fp64") + " over the stored S M^-1 blocks"
+    assert ("c2", "schur_bjinv", name) in bench.KERNEL_TRAFFIC
     distinct = {"gemm_sched": [-1, -1, -1, -1]}
     assert ("c3", "schur", bench.gemm_kernel_name(_Info([distinct]), 0, "fp64")) in bench.KERNEL_TRAFFIC

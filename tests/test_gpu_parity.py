@@ -291,14 +291,15 @@ def test_element_gemm_schedules_match_oracle(sched, monkeypatch, sched_refs):
         assert _rel(u[m, q], ref.u) <= (ref.bound if m == 0 else 1e-11), (sched, m, q)
 
 
-@pytest.mark.parametrize("sched", [0, 1, 2, 3, 4, 5, 6, 7])
+@pytest.mark.parametrize("sched", [0, 1, 2, 3, 4, 5, 6, 7, 8, 9, 10])
 @pytest.mark.parametrize("precision", [P.FP64, P.FP32_IR])
 def test_shared_block_gemm_schedules_match_oracle(sched, precision, monkeypatch, sched_refs):
     # Every schedule of the shared-block S and M^-1 GEMMs, pinned for all lists
     # (the fused S M^-1 block included): split K over 16 or 8 waves, the
     # LDS-staged 64-row tile, XCD-ordered or plain, staging 32 or 64 K-values
-    # per chunk, and split K with a wave's whole K range in flight (lists of
-    # at most 16 windows per item; wider lists run split K 8 under that id).
+    # per chunk, split K with a wave's whole K range in flight (lists of at
+    # most 16 windows per item; wider lists run split K 8 under that id), and
+    # the staged 128-row tile and the 64- / 128-row tiles whose waves split K.
     # FP32 refinement reaches the same FP64 solution.
     monkeypatch.setenv("SMPM_GEMM_SCHED", str(sched))
     p = _sched_problem()
@@ -308,6 +309,30 @@ def test_shared_block_gemm_schedules_match_oracle(sched, precision, monkeypatch,
     u = u.reshape(2, 2, p.r)
     for (m, q), ref in sched_refs.items():
         assert _rel(u[m, q], ref.u) <= (ref.bound if m == 0 else 1e-11), (sched, m, q)
+
+
+def _tall_problem():
+    # N = 14 * 10 = 140 rows per half: two 128-row tiles (the second ragged),
+    # three 64-row tiles, and K = 2N .. 8N spans several staged chunks and
+    # K parts of every schedule.  k > 0: the solution does not move with the
+    # null vectors, which at k = 0 on this order-13 grid are determined only
+    # to about 4e-10 in u.
+    return workloads.random_problem(8, 10, 14, kwaves=(1.3,), seed=41)
+
+
+@pytest.fixture(scope="module")
+def tall_ref():
+    return _oracle(_tall_problem(), 0, 0, tol=TIGHT)[1]
+
+
+@pytest.mark.parametrize("sched", [0, 2, 6, 8, 9, 10])
+def test_shared_block_gemm_schedules_on_tall_blocks(sched, monkeypatch, tall_ref):
+    monkeypatch.setenv("SMPM_GEMM_SCHED", str(sched))
+    p = _tall_problem()
+    s, u, st = _gpu_solve(p, tol=TIGHT)
+    assert all(v == sched for i in s.info for v in i["gemm_sched"] if v >= 0)
+    assert st["rel_residual_max"] <= ACCEPT_TIGHT
+    assert _rel(u, tall_ref.u) <= tall_ref.bound, sched
 
 
 @pytest.mark.parametrize("k", [0.0, 2.1])
