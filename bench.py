@@ -16,8 +16,9 @@ time.
 The same line carries the other workloads, each in FP64 and with the FP32
 inner solve inside FP64 refinement, over three right-hand-side seeds: the
 stretched 256 x 16 grid with distinct strips (c3), the 65 Fourier modes x
-(Re, Im) of the 64 x 8 grid (c4) and the uneven 32-problem batch (c5); with
---table2, the four methods of the paper's Table 2 over m_x = 64 .. 1024.
+(Re, Im) of the 64 x 8 grid (c4) and the uneven 32-problem batch (c5); and
+the four methods of the paper's Table 2 over m_x = 64 .. 1024 (iterations and
+solve times of Schur, BJ, DBJ and 2LAS GMRES on m_x x 10 grids of order 9).
 
 Rooflines: each kernel the FP64 solve runs per iteration (the S M^-1 GEMM or
 its two parts), the standalone Schur matvec and the element-interior
@@ -464,12 +465,14 @@ def main():
     ap.add_argument("--config", default="c2", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-secondary", action="store_true", help="skip the c3 / c4 / c5 keys")
-    ap.add_argument("--table2", action="store_true", help="add the Table 2 method comparison")
+    ap.add_argument("--no-table2", action="store_true", help="skip the Table 2 method comparison")
     ap.add_argument("--table2-mx", default="64,128,256,512,1024")
     ap.add_argument("--matvec-reps", type=int, default=200)
     ap.add_argument("--kernel-only", choices=("schur", "schur_bjinv", "ainv"),
                     help="run one FP64 kernel alone (plus a 256 MiB copy that calibrates the byte counters)")
-    ap.add_argument("--solve-only", action="store_true", help="FP64 setup and timed solves only")
+    ap.add_argument("--solve-only", action="store_true", help="one precision's setup and timed solves only")
+    ap.add_argument("--solve-precision", default="fp64", choices=("fp64", "fp32_ir", "fp16s_ir"),
+                    help="the precision --solve-only times")
     ap.add_argument("--zlabel", type=int, default=0, choices=(0, 1),
                     help="deflation space: 0 one column per interface (the paper's), 1 per element segment")
     ap.add_argument("--setup", default="auto", choices=("auto", "host", "device"),
@@ -508,10 +511,12 @@ def main():
 
     seeds = list(range(10)) if args.config == "c2" else [0, 1, 2]
     if args.solve_only:
-        forms, _ = bench_forms(args.config, (("fp64", P.FP64),), seeds, args.steps, args.warmup, stream,
+        name = args.solve_precision
+        prec = {"fp64": P.FP64, "fp32_ir": P.FP32_IR, "fp16s_ir": P.FP16S_IR}[name]
+        forms, _ = bench_forms(args.config, ((name, prec),), seeds, args.steps, args.warmup, stream,
                                args.inner_tol, args.zlabel, args.setup)
-        d = forms["fp64"][1]
-        print(json.dumps({"config": args.config, "fp64": {k: v for k, v in d.items() if k != "u0"}}), flush=True)
+        d = forms[name][1]
+        print(json.dumps({"config": args.config, name: {k: v for k, v in d.items() if k != "u0"}}), flush=True)
         return
 
     forms, fs_np = bench_forms(args.config, (("fp64", P.FP64), ("fp32_ir", P.FP32_IR), ("fp16s_ir", P.FP16S_IR)),
@@ -586,11 +591,11 @@ def main():
                                                            forms["fp32_ir"][0].info[0]["fused_op"][1]],
                            "fused_S_Minv_sched_fp64_fp32": [i0["fused_sched"][0],
                                                             forms["fp32_ir"][0].info[0]["fused_sched"][1]],
-                           "legend": "0 split-K 16 waves, 1 split-K 8 waves, 2 LDS-staged XCD-ordered, "
-                                     "3 LDS-staged plain; matvec lists: 4 / 5 = 2 / 3 with 64-value chunks, "
-                                     "6 / 7 split-K 8 / 16 waves with a wave's K range in flight; "
-                                     "element lists: 4 / 5 LDS-staged 32- / 16-row tiles with K split over "
-                                     "the waves; -1 unused; picked by timing at setup"},
+                           "legend": "0 split-K 16 waves, 1 split-K 8 waves, 2 LDS-staged XCD-ordered, 3 LDS-staged plain; matvec lists: "
+                                     "4 / 5 = 2 / 3 with 64-value chunks, 6 / 7 split-K 8 / 16 waves with a wave's K range in "
+                                     "flight, 8 LDS-staged 128-row tiles, 9 / 10 64- / 128-row tiles whose waves also split K; "
+                                     "element lists: 4 / 5 LDS-staged 32- / 16-row tiles with K split over the waves; -1 unused; "
+                                     "picked by timing at setup"},
         "roofline": main_rl,
         "rooflines": rl,
     }
@@ -627,7 +632,7 @@ def main():
     if not args.no_secondary and args.config == "c2":
         line["workloads"] = {c: secondary(c, 6, 2, stream, max(args.matvec_reps // 4, 20), args.inner_tol)
                              for c in ("c3", "c4", "c5")}
-    if args.table2:
+    if not args.no_table2 and not args.no_secondary:
         line["table2"] = table2(stream, [int(v) for v in args.table2_mx.split(",")], 1200)
     print(json.dumps(line), flush=True)
 

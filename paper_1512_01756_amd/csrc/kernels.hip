@@ -2049,6 +2049,12 @@ __global__ __launch_bounds__(256) void k_fft_y_pack(const double *__restrict__ i
   constexpr int MY = 1 << LOGMY, CT = kFftPackSlots / MY, CW = 2 * CT, NK = MY / 2 + 1;
   static_assert(CT >= 1, "m_y too large for the packed FFT");
   __shared__ double2 fb[MY * CT];
+  __shared__ double2 tws[MY / 2];   // the twiddles, staged once: the stages read them from LDS
+  for (int k = threadIdx.x; k < MY / 2; k += 256) {
+    double2 w = tw[k];
+    if (INV) w.y = -w.y;
+    tws[k] = w;
+  }
   const int64_t c0 = (int64_t)blockIdx.x * CW;
   const int nc = (int)min<int64_t>(CW, ncol - c0);
   auto brev = [](int j) { return (int)(__brev((unsigned)j) >> (32 - LOGMY)); };
@@ -2101,8 +2107,7 @@ __global__ __launch_bounds__(256) void k_fft_y_pack(const double *__restrict__ i
       const int p = idx / CT, c = idx % CT;
       const int k = p & (half - 1);
       const int i0 = ((p >> s) << (s + 1)) + k, i1 = i0 + half;
-      double2 w = tw[k * stride];
-      if (INV) w.y = -w.y;
+      const double2 w = tws[k * stride];
       const double2 a = fb[i0 * CT + c], b = fb[i1 * CT + c];
       const double2 t = make_double2(w.x * b.x - w.y * b.y, w.x * b.y + w.y * b.x);
       fb[i0 * CT + c] = make_double2(a.x + t.x, a.y + t.y);

@@ -77,13 +77,16 @@ __global__ void k_inject(double *__restrict__ R, int64_t total, int n, int N, in
 
 struct DeviceDense {
   std::mutex mu;
+  int dev = 0;   // the caller's device at creation: the worker threads of the setup start on device 0
   hipStream_t st = nullptr;
   rocblas_handle h = nullptr;
   DenseBackend be;
 
   // The stream and the rocBLAS handle are made on first use, so setups that
-  // never reach the device back end do not pay for them.
+  // never reach the device back end do not pay for them.  Every entry makes
+  // the creating thread's device current on the thread that calls it.
   void ensure() {
+    hcheck(hipSetDevice(dev), "hipSetDevice");
     if (h) return;
     hcheck(hipStreamCreate(&st), "hipStreamCreate");
     rcheck(rocblas_create_handle(&h), "rocblas_create_handle");
@@ -184,6 +187,7 @@ struct DeviceDense {
   // backward x_i = T~_i^-1 y_i - X_i x_{i+1}[N..2N].
   void tri_solve(void *fp, double *v) {
     std::lock_guard<std::mutex> lk(mu);
+    hcheck(hipSetDevice(dev), "hipSetDevice");
     TriFact *f = static_cast<TriFact *>(fp);
     const int d = f->d, N = f->N, M = f->M;
     const double one = 1.0, minus = -1.0;
@@ -292,7 +296,16 @@ struct DeviceDense {
 };
 
 DeviceDense *device_dense_create(bool always) {
+  // The runtime starts on the calling thread, with its current device, before
+  // any worker thread of the setup reaches the back end; without a device
+  // the setup runs every step on the host.
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) {
+    (void)hipGetLastError();
+    return nullptr;
+  }
   DeviceDense *dd = new DeviceDense();
+  dd->dev = dev;
   dd->be.always = always;
   dd->be.invert = [dd](int n, int count, double *const *mats) { dd->invert(n, count, mats); };
   dd->be.tri_factor = [dd](int d, int N, const double *Td, const double *Lo, const double *Up) {
@@ -301,6 +314,7 @@ DeviceDense *device_dense_create(bool always) {
   dd->be.tri_solve = [dd](void *f, double *v) { dd->tri_solve(f, v); };
   dd->be.tri_free = [dd](void *f) {
     std::lock_guard<std::mutex> lk(dd->mu);
+    (void)hipSetDevice(dd->dev);
     delete static_cast<TriFact *>(f);
   };
   dd->be.strip_schur = [dd](int ncl, int n, int mz, const double *const *G, const double *lo, const double *up,

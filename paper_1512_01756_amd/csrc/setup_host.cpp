@@ -933,15 +933,50 @@ void build_system(System &s, int mx, int mz, int order, const double *xb, const 
     for (auto &a : uC) { a /= nu; sum += a; }
     if (sum < 0) for (auto &a : uC) a = -a;
     s.uC = uC;
-    // G = [[C_m^-1, 0], [0, 0]] (I - u_C u_C^T): the last coarse unknown is
-    // pinned to zero (any solution of the consistent system works, P is
-    // unchanged by a shift along 1_d).  A rank-one update of C_m^-1:
-    // G[i][j] = C_m^-1[i][j] - w_i u_C[j] with w = C_m^-1 u_C[0..m).
-    for (int i = 0; i < m; ++i) {
-      const double *ci = &Cinv[(size_t)i * m];
-      double w = 0.0;
-      for (int l = 0; l < m; ++l) w += ci[l] * uC[l];
-      for (int j = 0; j < d; ++j) s.Gc[(size_t)i * d + j] = (j < m ? ci[j] : 0.0) - w * uC[j];
+    // G = M^-1 (I - u_C u_C^T) with M = P_u C P_v + alpha u_C v^T, where
+    // P_u = I - u_C u_C^T, P_v = I - v v^T and v = 1_d / sqrt(d) is C's right
+    // null vector (Z 1_d = 1_Gamma, S 1_Gamma = 0).  M maps v-perp as the
+    // projected C does and v to alpha u_C, so it is nonsingular, and
+    // G C x = x - v (v . x) for the projected C: the coarse correction takes
+    // out every direction of S Z except the constant, to the rounding of C.
+    // (Pinning one coarse unknown and inverting the leading block instead
+    // leaves C's smallest singular value times |C_m^-1| in a whole column of
+    // G C; on a 64 x 10, order-9 grid that doubled the DBJ iterations.)
+    // Any solution of the consistent coarse system serves: P does not
+    // change under a shift along v.
+    {
+      const double sv = 1.0 / std::sqrt((double)d);
+      std::vector<double> ut(d, 0.0), cv(d, 0.0);   // u_C^T C and C v
+      double alpha = 0.0;
+      for (int i = 0; i < d; ++i) {
+        const double *ci = &s.C[(size_t)i * d];
+        double a = 0.0;
+        for (int j = 0; j < d; ++j) {
+          ut[j] += uC[i] * ci[j];
+          a += ci[j];
+        }
+        cv[i] = a * sv;
+        alpha = std::max(alpha, std::fabs(ci[i]));
+      }
+      double ucv = 0.0;
+      for (int i = 0; i < d; ++i) ucv += uC[i] * cv[i];
+      if (!(alpha > 0.0)) throw std::domain_error("zero coarse matrix C");
+      std::vector<double> Mi((size_t)d * d);
+      for (int i = 0; i < d; ++i)
+        for (int j = 0; j < d; ++j)
+          Mi[(size_t)i * d + j] = s.C[(size_t)i * d + j] - uC[i] * ut[j] - cv[i] * sv + uC[i] * ucv * sv +
+                                  alpha * uC[i] * sv;
+      try {
+        if (invert_many(opt, d, {Mi.data()})) s.dev_steps |= 4;
+      } catch (const std::domain_error &) {
+        throw std::domain_error("singular completed coarse matrix");
+      }
+      for (int i = 0; i < d; ++i) {   // G = M^-1 - (M^-1 u_C) u_C^T
+        const double *mi = &Mi[(size_t)i * d];
+        double w = 0.0;
+        for (int l = 0; l < d; ++l) w += mi[l] * uC[l];
+        for (int j = 0; j < d; ++j) s.Gc[(size_t)i * d + j] = mi[j] - w * uC[j];
+      }
     }
     timer.lap("deflation, coarse");
     // Null vectors of S and L.

@@ -234,6 +234,11 @@ struct smpm_handle {
   // the previous solve's number of sweeps (0: none yet).
   std::vector<int> pred_sweep;
   int pred_nsweeps = 0;
+  // Iterations added to each prediction once a solve of this handle had to
+  // go past one (a resumed FP64 loop, a cut-short inner solve or a checked
+  // sweep after the unchecked ones): 0 until then, so a handle whose counts
+  // never change runs exactly its previous count.
+  int pred_margin[2] = {0, 0};
   // The FP64 solve's report, read back with one copy: GMRES states, then
   // (||r||^2, u_S . r), the compatibility defects and (||b~||^2, u_S . b~)
   // per instance (gs, pairs, defect and nb2 point into it).
@@ -1368,7 +1373,7 @@ struct Inner {
   static int predicted(smpm_handle *H, int slot, hipStream_t st) {
     int pred = H->pred_iters[P];
     if (P == 1 && slot < (int)H->pred_sweep.size() && H->pred_sweep[slot] >= 0) pred = H->pred_sweep[slot];
-    if (pred < 0) pred = kIterChunk;
+    pred = pred < 0 ? kIterChunk : pred + H->pred_margin[P];
     const int n = std::min(pred, H->maxit);
     iterations(H, n, st);
     return n;
@@ -1854,7 +1859,7 @@ smpm_status smpm_solve(smpm_handle *H, const double *f, const double *g, double 
     HIPCHECK(hipStreamWaitEvent(st, H->ev_in, 0));
     const bool useP = H->method == SMPM_METHOD_DBJ;
     bool nonfinite = false, notconv = false;
-    int sweeps = 0;
+    int sweeps = 0, batch_run = 0;
     if (H->precision == SMPM_FP64) {
       // Head graph, the predicted iterations, then the tail graph (the
       // loop's end, the final FP64 check of the Schur residual, the
@@ -1866,7 +1871,9 @@ smpm_status smpm_solve(smpm_handle *H, const double *f, const double *g, double 
       read_rhs(H, f, g, st);
       HIPCHECK(hipGraphLaunch(H->g_head, st));
       int launched = Inner<double>::predicted(H, 0, st);
-      for (;;) {
+      const bool had_pred = H->pred_iters[0] >= 0;
+      for (int pass = 0;; ++pass) {
+        if (pass == 1 && had_pred) H->pred_margin[0] = 1;   // the prediction fell short
         HIPCHECK(hipGraphLaunch(H->g_tail, st));
         write_u(H, u, st);   // again after a later tail if the loop resumes
         HIPCHECK(hipMemcpyAsync(H->h_rep, H->gs, H->rep_bytes, hipMemcpyDeviceToHost, st));
@@ -1897,6 +1904,7 @@ smpm_status smpm_solve(smpm_handle *H, const double *f, const double *g, double 
       // residual is checked after them and the checked sweeps below go on
       // if it is not small enough.
       const int batch = std::min(H->pred_nsweeps, H->max_sweeps);
+      batch_run = batch;
       for (; sweeps < batch; ++sweeps) {
         if (sweeps > 0) {
           HIPCHECK(hipGraphLaunch(H->g_resid, st));
@@ -1985,7 +1993,14 @@ smpm_status smpm_solve(smpm_handle *H, const double *f, const double *g, double 
     if (stats) *stats = S;
     // the next refinement solve runs this many sweeps unchecked: only after
     // a converged one
-    if (P == 1) H->pred_nsweeps = (nonfinite || notconv) ? 0 : nslots;
+    // After checked sweeps beyond the unchecked ones (some inner solve was cut
+    // short by its prediction), keep the unchecked count: the grown per-sweep
+    // predictions and the margin make those sweeps suffice next time.
+    if (P == 1) {
+      const bool extra = batch_run > 0 && sweeps > batch_run;
+      if (extra) H->pred_margin[1] = 1;
+      H->pred_nsweeps = (nonfinite || notconv) ? 0 : (extra ? batch_run : nslots);
+    }
     if (nonfinite) return fail(SMPM_ENONFINITE, "non-finite value in the inputs or iterates");
     if (notconv) return fail(SMPM_ENOTCONV, "iteration limit reached before the tolerance");
   } catch (const std::exception &e) {

@@ -335,6 +335,40 @@ def test_shared_block_gemm_schedules_on_tall_blocks(sched, monkeypatch, tall_ref
     assert _rel(u, tall_ref.u) <= tall_ref.bound, sched
 
 
+@pytest.fixture(scope="module")
+def table2_grid():
+    # The m_x = 64 grid of the Table 2 comparison: 64 x 10 elements, order 9,
+    # U[0, 1] forcing.  Its coarse matrix C is singular only to 1e-9 of |C|
+    # (the rounding of S 1_Gamma), which a coarse inverse must not amplify.
+    mx, mz, n = 64, 10, 10
+    xb, zb = np.linspace(0.0, float(mx), mx + 1), np.linspace(0.0, 1.0, mz + 1)
+    grid = smpm.Grid(xb, zb, n)
+    o = schur.build(grid)
+    f = np.random.default_rng(0).uniform(0.0, 1.0, n * n * mx * mz)
+    F = smpm.rhs(grid, o.tau, f)
+    its = {m: solve.dbj_solve(o, F, method=m, tol=1e-10, maxit=400).iters for m in ("dbj", "2las")}
+    return xb, zb, n, f, o, its
+
+
+@pytest.mark.parametrize("method", ["dbj", "2las"])
+def test_deflation_iterations_on_table2_grid(method, table2_grid):
+    xb, zb, n, f, o, its = table2_grid
+    m = {"dbj": P.METHOD_DBJ, "2las": P.METHOD_2LAS}[method]
+    s = P.Solver(xb, zb, n - 1, method=m, max_iter=400)
+    _, st, status = s.solve(_dev(f))
+    print(method, "GPU", st["iters_max"], "oracle", its[method])
+    assert status == P.OK and abs(st["iters_max"] - its[method]) <= 1
+    # P itself: C is singular only to its rounding, so u_C, and with it the
+    # coarse projection, is determined to sigma_min(C) / sigma_{d-1}(C)
+    # (6e-9 here); the two sides' P agree to that.
+    sv = o.extra["C_svd"][1]
+    x = np.random.default_rng(3).standard_normal(o.SZ.shape[0])
+    y = torch.empty(x.size, dtype=torch.float64, device="cuda")
+    s.apply(P.OP_DEFLATE_P, 0, _dev(x), y)
+    assert _rel(y.cpu().numpy(), o.P_apply(x)) <= max(1e-11, sv[-1] / sv[-2])
+    s.close()
+
+
 @pytest.mark.parametrize("k", [0.0, 2.1])
 def test_fp32_refinement_reaches_fp64_solution(k):
     p = workloads.random_problem(12, 3, 7, kwaves=(k,), seed=5, stretch=True)
