@@ -406,7 +406,7 @@ def secondary(cfg, steps, warmup, stream, reps, inner_tol):
         ms_i = kernel_ms(lambda: sf.transform_y(fhat, back, inverse=True), reps, stream)
         res["transform_y"] = {"forward_us": ms_f * 1e3, "inverse_us": ms_i * 1e3, "bytes": nb,
                               "forward_GBps": nb / (ms_f * 1e-3) / 1e9, "inverse_GBps": nb / (ms_i * 1e-3) / 1e9,
-                              "kernel": "k_fft_y_pack (radix-2, two real columns per complex FFT, LDS-staged, m_y = 128)"}
+                              "kernel": "k_fft_y_4s (length-8 then length-16 register DFTs, one LDS pass between, two real columns per complex FFT, m_y = 128)"}
         # from the physical field: transform, the batched mode solves, inverse
         for name, prec in (("fp64", P.FP64), ("fp32_ir", P.FP32_IR)):
             sp = P.Solver(p4.xb, p4.zb, p4.n - 1, fourier=(my, ly), precision=prec)

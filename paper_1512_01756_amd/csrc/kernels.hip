@@ -2141,6 +2141,168 @@ __global__ __launch_bounds__(256) void k_fft_y_pack(const double *__restrict__ i
   }
 }
 
+// A length-R DFT in registers (R a power of two, all indices fixed at
+// compile time): `a` holds the inputs in bit-reversed order and ends with the
+// outputs in natural order.  Radix-2 decimation in time; the twiddle of span
+// 2h is W_R^k = W_MY^{k R' } with R' = MY / (2 h), read from the staged
+// table tws[k] = W_MY^k, k < MY / 2 (conjugated there for the inverse).
+template <int R, int MY>
+__device__ inline void dft_reg(double2 (&a)[R], const double2 *tws) {
+#pragma unroll
+  for (int h = 1; h < R; h *= 2) {
+#pragma unroll
+    for (int g = 0; g < R; g += 2 * h) {
+#pragma unroll
+      for (int k = 0; k < h; ++k) {
+        const double2 w = tws[k * (MY / (2 * h))];
+        const double2 b = a[g + k + h];
+        const double2 t = make_double2(w.x * b.x - w.y * b.y, w.x * b.y + w.y * b.x);
+        a[g + k + h] = make_double2(a[g + k].x - t.x, a[g + k].y - t.y);
+        a[g + k] = make_double2(a[g + k].x + t.x, a[g + k].y + t.y);
+      }
+    }
+  }
+}
+
+template <int L>
+__device__ constexpr int brev_c(int j) {
+  int r = 0;
+  for (int b = 0; b < L; ++b) r |= ((j >> b) & 1) << (L - 1 - b);
+  return r;
+}
+
+// The y transform for m_y = 16 .. 128 as a two-step (four-step) FFT,
+// m_y = 8 N2, two real columns per complex FFT as in k_fft_y_pack: with
+// j = N2 j1 + j2 and m = k1 + 8 k2, a thread first takes the length-8 DFT over
+// j1 of one (column, j2) in registers, multiplies by W^{j2 k1}, and stages
+// the result; after one barrier a thread takes the length-N2 DFT over j2 of
+// one (column, k1).  Two passes through LDS instead of log2(m_y).
+template <int LOGMY, bool INV>
+__global__ __launch_bounds__(256) void k_fft_y_4s(const double *__restrict__ in, double *__restrict__ out,
+                                                  int64_t ncol, const double2 *__restrict__ tw) {
+  constexpr int MY = 1 << LOGMY, N1 = 8, N2 = MY / N1, L2 = LOGMY - 3;
+  constexpr int CT = kFftPackSlots / MY, CW = 2 * CT, NK = MY / 2 + 1;
+  constexpr int I1 = CT * N2, I3 = CT * N1;                 // items of the two steps
+  constexpr int P1 = (I1 + 255) / 256, P3 = (I3 + 255) / 256;
+  static_assert(N2 >= 2 && N2 <= 16, "m_y from 16 to 128");
+  __shared__ double2 fb[MY * CT];
+  __shared__ double2 tws[MY / 2];
+  for (int k = threadIdx.x; k < MY / 2; k += 256) {
+    double2 w = tw[k];
+    if (INV) w.y = -w.y;
+    tws[k] = w;
+  }
+  const int64_t c0 = (int64_t)blockIdx.x * CW;
+  const int nc = (int)min<int64_t>(CW, ncol - c0);
+  auto twid = [&](int idx) {   // W_MY^idx, idx < MY
+    const double2 w = tws[idx & (MY / 2 - 1)];
+    return idx < MY / 2 ? w : make_double2(-w.x, -w.y);
+  };
+  double2 a[P1][N1];
+  if (!INV) {   // step 1 straight from the planes: z = x_c + i x_{c+CT}
+#pragma unroll
+    for (int q = 0; q < P1; ++q) {
+      const int it = threadIdx.x + 256 * q, c = it % CT, j2 = it / CT;
+#pragma unroll
+      for (int j1 = 0; j1 < N1; ++j1) {
+        const int64_t row = (int64_t)(N2 * j1 + j2) * ncol + c0;
+        const bool ok = it < I1;
+        a[q][brev_c<3>(j1)] = make_double2(ok && c < nc ? in[row + c] : 0.0, ok && c + CT < nc ? in[row + c + CT] : 0.0);
+      }
+    }
+    __syncthreads();   // the twiddle table
+  } else {   // the full spectrum Z_m = X_c(m) + i X_{c+CT}(m), natural order
+    constexpr int PS = (NK * CT + 255) / 256;
+    double4 v[PS];   // every load issued before the first store
+#pragma unroll
+    for (int q = 0; q < PS; ++q) {
+      const int it = threadIdx.x + 256 * q, m = it / CT, c = it % CT;
+      v[q] = make_double4(0.0, 0.0, 0.0, 0.0);
+      if (it < NK * CT) {
+        const double *r0 = in + (int64_t)(2 * m) * ncol + c0, *r1 = r0 + ncol;
+        if (c < nc) { v[q].x = r0[c]; v[q].y = r1[c]; }
+        if (c + CT < nc) { v[q].z = r0[c + CT]; v[q].w = r1[c + CT]; }
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < PS; ++q) {
+      const int it = threadIdx.x + 256 * q, m = it / CT, c = it % CT;
+      if (it >= NK * CT) continue;
+      double ar = v[q].x, br = v[q].y, er = v[q].z, dr = v[q].w;   // X_c = a + i b, X_{c+CT} = e + i d
+      if (m == 0 || m == MY / 2) br = dr = 0.0;
+      fb[m * CT + c] = make_double2(ar - dr, br + er);
+      if (m > 0 && m < MY / 2) fb[(MY - m) * CT + c] = make_double2(ar + dr, er - br);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < P1; ++q) {
+      const int it = threadIdx.x + 256 * q, c = it % CT, j2 = it / CT;
+#pragma unroll
+      for (int j1 = 0; j1 < N1; ++j1)
+        a[q][brev_c<3>(j1)] = it < I1 ? fb[(N2 * j1 + j2) * CT + c] : make_double2(0.0, 0.0);
+    }
+    __syncthreads();   // every read of the spectrum before step 1 overwrites it
+  }
+#pragma unroll
+  for (int q = 0; q < P1; ++q) {
+    const int it = threadIdx.x + 256 * q, c = it % CT, j2 = it / CT;
+    dft_reg<N1, MY>(a[q], tws);
+    if (it < I1) {
+#pragma unroll
+      for (int k1 = 0; k1 < N1; ++k1) {
+        const double2 w = twid(j2 * k1), v = a[q][k1];
+        fb[(k1 * N2 + j2) * CT + c] = make_double2(w.x * v.x - w.y * v.y, w.x * v.y + w.y * v.x);
+      }
+    }
+  }
+  __syncthreads();
+  double2 b[P3][N2];
+#pragma unroll
+  for (int q = 0; q < P3; ++q) {
+    const int it = threadIdx.x + 256 * q, c = it % CT, k1 = it / CT;
+#pragma unroll
+    for (int j2 = 0; j2 < N2; ++j2)
+      b[q][brev_c<L2>(j2)] = it < I3 ? fb[(k1 * N2 + j2) * CT + c] : make_double2(0.0, 0.0);
+    dft_reg<N2, MY>(b[q], tws);
+  }
+  if (INV) {   // z_j at j = k1 + 8 k2: column c in Re, column c + CT in Im
+#pragma unroll
+    for (int q = 0; q < P3; ++q) {
+      const int it = threadIdx.x + 256 * q, c = it % CT, k1 = it / CT;
+      if (it >= I3) continue;
+#pragma unroll
+      for (int k2 = 0; k2 < N2; ++k2) {
+        double *o = out + (int64_t)(k1 + N1 * k2) * ncol + c0;
+        if (c < nc) o[c] = b[q][k2].x;
+        if (c + CT < nc) o[c + CT] = b[q][k2].y;
+      }
+    }
+    return;
+  }
+  __syncthreads();   // every read of step 1's output before it is overwritten
+#pragma unroll
+  for (int q = 0; q < P3; ++q) {
+    const int it = threadIdx.x + 256 * q, c = it % CT, k1 = it / CT;
+    if (it >= I3) continue;
+#pragma unroll
+    for (int k2 = 0; k2 < N2; ++k2) fb[(k1 + N1 * k2) * CT + c] = b[q][k2];
+  }
+  __syncthreads();
+  constexpr double sc = 0.5 / MY;
+  for (int idx = threadIdx.x; idx < 2 * NK * CW; idx += 256) {
+    const int row = idx / CW, cc = idx % CW;
+    if (cc >= nc) continue;
+    const int m = row >> 1, c = cc % CT;
+    const double2 A = fb[m * CT + c], B = fb[((MY - m) & (MY - 1)) * CT + c];
+    double val;
+    if (cc < CT)   // (A + conj B) / 2
+      val = (row & 1) ? (A.y - B.y) : (A.x + B.x);
+    else           // (A - conj B) / (2 i)
+      val = (row & 1) ? -(A.x - B.x) : (A.y + B.y);
+    out[(int64_t)row * ncol + c0 + cc] = val * sc;
+  }
+}
+
 __global__ __launch_bounds__(kBlock) void k_fill(double *__restrict__ p, int64_t n, double v) {
   const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (i < n) p[i] = v;

@@ -1530,6 +1530,23 @@ void transform_y(smpm_handle *H, bool inverse, const double *in, double *out, in
   if (H->fft_tw) {
     int logmy = 0;
     while ((1 << logmy) < my) ++logmy;
+    if (my >= 16 && my <= 128) {   // two steps through LDS
+      const dim3 grid((unsigned)((ncol + 2 * (kFftPackSlots / my) - 1) / (2 * (kFftPackSlots / my))));
+      const double2 *tw = (const double2 *)H->fft_tw;
+      switch (logmy * 2 + (inverse ? 1 : 0)) {
+#define SMPM_FFT4_CASE(L)                                                                                  \
+  case 2 * L:                                                                                              \
+    hipLaunchKernelGGL((k_fft_y_4s<L, false>), grid, dim3(256), 0, st, in, out, ncol, tw);                \
+    return;                                                                                                \
+  case 2 * L + 1:                                                                                          \
+    hipLaunchKernelGGL((k_fft_y_4s<L, true>), grid, dim3(256), 0, st, in, out, ncol, tw);                 \
+    return;
+        SMPM_FFT4_CASE(4) SMPM_FFT4_CASE(5) SMPM_FFT4_CASE(6) SMPM_FFT4_CASE(7)
+#undef SMPM_FFT4_CASE
+        default:
+          break;
+      }
+    }
     if (my >= 8 && my <= kFftPackSlots) {   // two real columns per complex FFT, sizes fixed at compile time
       const dim3 grid((unsigned)((ncol + 2 * (kFftPackSlots / my) - 1) / (2 * (kFftPackSlots / my))));
       const double2 *tw = (const double2 *)H->fft_tw;

@@ -107,14 +107,15 @@ def test_one_krylov_needs_dbj():
                  method=P.METHOD_BJ)
 
 
-@pytest.mark.parametrize("my", [2, 4, 8, 128, 256, 2048, 6, 12])
+@pytest.mark.parametrize("my", [2, 4, 8, 16, 32, 64, 128, 256, 2048, 6, 12])
 def test_transform_y_matches_numpy_fft(my):
-    # The y transform alone (radix-2 FFT for powers of two: two real columns
-    # per complex FFT from m_y = 8 to 2048, one below; the dense real DFT
-    # otherwise) against the oracle's numpy real FFT, both directions, on a
-    # seeded field with a ragged last column tile (r = 25 * 2 * 36 = 1800
+    # The y transform alone (for powers of two an FFT with two real columns
+    # per complex FFT: two register steps from m_y = 16 to 128, radix-2
+    # stages in LDS for 8 and 256 .. 2048, unpacked below 8; the dense real
+    # DFT otherwise) against the oracle's numpy real FFT, both directions, on
+    # a seeded field with a ragged last column tile (r = 25 * 2 * 36 = 1800
     # columns is not a multiple of the 4096 / m_y columns a workgroup takes
-    # for m_y = 8, 128 and 256).
+    # for m_y = 8, 16, 32, 64, 128 and 256).
     xb, zb, n = np.linspace(0.0, 12.5, 26), np.array([0.0, 0.5, 1.0]), 6
     s = P.Solver(xb, zb, n - 1, fourier=(my, 3.0), tune=False)
     r = s.info[0]["r"]
