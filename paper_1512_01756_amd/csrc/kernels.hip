@@ -650,6 +650,44 @@ __global__ __launch_bounds__(kBlock) void k_coarse(const SysDev *__restrict__ sy
   }
 }
 
+// Short Krylov bases (j < kBasisRegs) are read into registers before
+// anything else a pass waits on: the two elements of a thread (e0 + tid and
+// e0 + tid + kBlock) of every basis vector t <= j, in one burst of loads that
+// overlaps the reduction of the previous pass's partials.  The dots of the
+// pass then come from the registers (one block reduction per vector) instead
+// of a second sweep over the basis.  Kernels take it with RB = true, for
+// handles whose vector launches are few workgroups (latency bound): the 32
+// extra registers halve the occupancy, which costs more than it saves where
+// thousands of workgroups stream the basis.
+constexpr int kBasisRegs = 16;
+template <typename TV>
+__device__ inline void prefetch_basis(const TV *__restrict__ Vi, int64_t kS, int64_t ea, bool ina, bool inb, int j,
+                                      double (&va)[kBasisRegs], double (&vb)[kBasisRegs]) {
+#pragma unroll
+  for (int t = 0; t < kBasisRegs; ++t) {
+    va[t] = (t <= j && ina) ? (double)Vi[(int64_t)t * kS + ea] : 0.0;
+    vb[t] = (t <= j && inb) ? (double)Vi[(int64_t)t * kS + ea + kBlock] : 0.0;
+  }
+}
+
+// part[t nchunk + ch] = sum over the workgroup of va[t] a0 + vb[t] a1, t <= j
+// (wave sums, then the four waves in a fixed order).
+__device__ inline void block_dots(const double (&va)[kBasisRegs], const double (&vb)[kBasisRegs], double a0,
+                                  double a1, int j, double *red, double *__restrict__ part, int nchunk, int ch) {
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+#pragma unroll
+  for (int t = 0; t < kBasisRegs; ++t) {
+    if (t <= j) {   // uniform over the workgroup
+      const double d = wave_sum(va[t] * a0 + vb[t] * a1);
+      if (lane == 0) red[wave * kBasisRegs + t] = d;
+    }
+  }
+  __syncthreads();
+  const int t = threadIdx.x;
+  if (t <= j)
+    part[(int64_t)t * nchunk + ch] = (red[t] + red[kBasisRegs + t]) + (red[2 * kBasisRegs + t] + red[3 * kBasisRegs + t]);
+}
+
 // Partial dots V_t . w over one chunk, t = 0 .. j, written to
 // part[t * nchunk + ch].  The chunk of w is in LDS (ws, zero past k_S); wave
 // q takes t = q, q + 4, ... two at a time over all kChunk elements (8
@@ -700,7 +738,7 @@ __device__ inline void chunk_dots(const TV *__restrict__ V, int64_t kS, int64_t 
 // dots instead of three times.  With cpre (large d, where the workgroups' G
 // rows would add up to several reads of G) it takes the coarse values from
 // c = G Z^T y formed beforehand by k_coarse.
-template <typename TV, typename TY>
+template <typename TV, typename TY, bool RB = false>
 __global__ __launch_bounds__(kBlock) void k_pcorr_dot(
     const SysDev *__restrict__ sys, const InstDev *__restrict__ ins, const int2 *__restrict__ work,
     const TY *__restrict__ ybase, const double *__restrict__ hsum, int useP, TV *__restrict__ V,
@@ -718,6 +756,10 @@ __global__ __launch_bounds__(kBlock) void k_pcorr_dot(
   const int64_t kS = S.kS;
   const int j = gs[i].iter;
   const int64_t e0 = (int64_t)ch * kChunk;
+  static_assert(Q == 2, "two elements per thread, as the register basis holds them");
+  const bool regs = RB && j < kBasisRegs;
+  double va[kBasisRegs], vb[kBasisRegs];   // the basis of a short space, loaded with everything else
+  if (regs) prefetch_basis(V + I.v_off, kS, e0 + threadIdx.x, e0 + threadIdx.x < kS, e0 + threadIdx.x + kBlock < kS, j, va, vb);
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const bool pre = useP && S.zm == 1 && !cpre;
   int c0 = 0, ncol = 0;
@@ -807,6 +849,7 @@ __global__ __launch_bounds__(kBlock) void k_pcorr_dot(
     }
     __syncthreads();
   }
+  double wq[Q];
 #pragma unroll
   for (int q = 0; q < Q; ++q) {
     const int64_t e = e0 + threadIdx.x + q * kBlock;
@@ -827,7 +870,12 @@ __global__ __launch_bounds__(kBlock) void k_pcorr_dot(
       V[I.v_off + (int64_t)(j + 1) * kS + e] = wt;
       w = (double)wt;
     }
-    ws[threadIdx.x + q * kBlock] = w;
+    wq[q] = w;
+    if (!regs) ws[threadIdx.x + q * kBlock] = w;
+  }
+  if (regs) {   // ws is free: the scratch of the block sums
+    block_dots(va, vb, wq[0], wq[1], j, ws, part + I.part_off, I.nchunk_x, ch);
+    return;
   }
   __syncthreads();
   chunk_dots(V + I.v_off, kS, e0, j, ws, part + I.part_off, I.nchunk_x, ch);
@@ -977,7 +1025,7 @@ __device__ inline void givens_step(const InstDev &I, int i, int j, const double 
 // Classical Gram-Schmidt pass: w -= sum_t coef_t V_t (coef from the partials
 // of the previous pass); then either the next pass's partial dots
 // (part_out) or the partial squared norm (partn).
-template <typename TV>
+template <typename TV, bool RB = false>
 __global__ __launch_bounds__(kBlock) void k_axpy_dot(
     const SysDev *__restrict__ sys, const InstDev *__restrict__ ins, const int2 *__restrict__ work,
     TV *__restrict__ V, const double *__restrict__ part_in, double *__restrict__ part_out,
@@ -994,6 +1042,15 @@ __global__ __launch_bounds__(kBlock) void k_axpy_dot(
   const SysDev &S = sys[I.sys];
   const int64_t kS = S.kS;
   const int j = G.iter;
+  static_assert(kChunk == 2 * kBlock, "two elements per thread");
+  const int64_t e0 = (int64_t)ch * kChunk;
+  const int64_t ea = e0 + threadIdx.x, eb = ea + kBlock;
+  const bool ina = ea < kS, inb = eb < kS;
+  TV *w = V + I.v_off + (int64_t)(j + 1) * kS;
+  double a0 = ina ? (double)w[ea] : 0.0, a1 = inb ? (double)w[eb] : 0.0;
+  const bool regs = RB && j < kBasisRegs && part_out && !coefr;
+  double va[kBasisRegs], vb[kBasisRegs];
+  if (regs) prefetch_basis(V + I.v_off, kS, ea, ina, inb, j, va, vb);
   if (coefr) {   // segment sums reduced by k_seg_reduce
     for (int t = threadIdx.x; t <= j; t += kBlock) {
       const double s = scale[I.st_off + t];
@@ -1003,12 +1060,34 @@ __global__ __launch_bounds__(kBlock) void k_axpy_dot(
   } else {
     reduce_coef(I, part_in, scale, j, coef);
   }
-  static_assert(kChunk == 2 * kBlock, "two elements per thread");
-  const int64_t e0 = (int64_t)ch * kChunk;
-  const int64_t ea = e0 + threadIdx.x, eb = ea + kBlock;
-  const bool ina = ea < kS, inb = eb < kS;
-  TV *w = V + I.v_off + (int64_t)(j + 1) * kS;
-  double a0 = ina ? (double)w[ea] : 0.0, a1 = inb ? (double)w[eb] : 0.0;
+  if (regs) {
+#pragma unroll
+    for (int t = 0; t < kBasisRegs; ++t) {
+      if (t <= j) {
+        const double c = coef[t];
+        a0 -= c * va[t];
+        a1 -= c * vb[t];
+      }
+    }
+    if (ina) {
+      const TV at = (TV)a0;
+      w[ea] = at;
+      a0 = (double)at;
+    }
+    if (inb) {
+      const TV at = (TV)a1;
+      w[eb] = at;
+      a1 = (double)at;
+    }
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    if (partn) {   // |w|^2 after this pass, for the Pythagorean norm of the next
+      const double a = wave_sum(a0 * a0 + a1 * a1);
+      if (lane == 0) red[wave] = a;
+    }
+    block_dots(va, vb, a0, a1, j, ws, part_out + I.part_off, I.nchunk_x, ch);   // syncs before the sums
+    if (partn && threadIdx.x == 0) partn[I.part_off + ch] = (red[0] + red[1]) + (red[2] + red[3]);
+    return;
+  }
   const TV *Vt = V + I.v_off + ea;
 #pragma unroll 4
   for (int t = 0; t <= j; ++t, Vt += kS) {
@@ -1062,7 +1141,7 @@ __global__ __launch_bounds__(kBlock) void k_axpy_dot(
 // the last one may advance it.  Saves the separate Givens launch per
 // iteration.  Instances of one Krylov space over several instances (segments)
 // keep the separate launch.
-template <typename TV>
+template <typename TV, bool RB = false>
 __global__ __launch_bounds__(kBlock) void k_axpy_givens(
     const SysDev *__restrict__ sys, const InstDev *__restrict__ ins, const int2 *__restrict__ work,
     TV *__restrict__ V, const double *__restrict__ part1, const double *__restrict__ part2,
@@ -1080,18 +1159,32 @@ __global__ __launch_bounds__(kBlock) void k_axpy_givens(
   const SysDev &S = sys[I.sys];
   const int64_t kS = S.kS;
   const int j = G.iter;
-  reduce_coef(I, part2, scale, j, coef);
   const int64_t e0 = (int64_t)ch * kChunk;
   const int64_t ea = e0 + threadIdx.x, eb = ea + kBlock;
   const bool ina = ea < kS, inb = eb < kS;
   TV *w = V + I.v_off + (int64_t)(j + 1) * kS;
   double a0 = ina ? (double)w[ea] : 0.0, a1 = inb ? (double)w[eb] : 0.0;
-  const TV *Vt = V + I.v_off + ea;
+  if (RB && j < kBasisRegs) {   // the basis loads overlap the reduction of the partials
+    double va[kBasisRegs], vb[kBasisRegs];
+    prefetch_basis(V + I.v_off, kS, ea, ina, inb, j, va, vb);
+    reduce_coef(I, part2, scale, j, coef);
+#pragma unroll
+    for (int t = 0; t < kBasisRegs; ++t) {
+      if (t <= j) {
+        const double c = coef[t];
+        a0 -= c * va[t];
+        a1 -= c * vb[t];
+      }
+    }
+  } else {
+    reduce_coef(I, part2, scale, j, coef);
+    const TV *Vt = V + I.v_off + ea;
 #pragma unroll 4
-  for (int t = 0; t <= j; ++t, Vt += kS) {
-    const double c = coef[t];
-    if (ina) a0 -= c * (double)Vt[0];
-    if (inb) a1 -= c * (double)Vt[kBlock];
+    for (int t = 0; t <= j; ++t, Vt += kS) {
+      const double c = coef[t];
+      if (ina) a0 -= c * (double)Vt[0];
+      if (inb) a1 -= c * (double)Vt[kBlock];
+    }
   }
   if (ina) w[ea] = (TV)a0;
   if (inb) w[eb] = (TV)a1;

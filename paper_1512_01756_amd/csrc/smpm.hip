@@ -127,6 +127,11 @@ std::vector<_Float16> to_half_scaled(const std::vector<double> &a, int nb, int r
 }
 
 constexpr int kIterChunk = 4;
+// Handles with at most this many vector workgroups (kChunk elements each)
+// run the GMRES vector kernels with the short basis in registers: c2 (68)
+// and c3 (208) gain 1-3%, the 3380 of c4's 130 instances lose 6% to the
+// halved occupancy.
+constexpr int kRegBasisChunks = 1024;
 // A refinement sweep's inner solve stops once its residual is below
 // kSweepSafety * tol * ||b~|| (or inner_tol times its own right-hand side).
 constexpr double kSweepSafety = 0.5;
@@ -239,6 +244,9 @@ struct smpm_handle {
   // sweep after the unchecked ones): 0 until then, so a handle whose counts
   // never change runs exactly its previous count.
   int pred_margin[2] = {0, 0};
+  // Vector kernels with the short Krylov basis in registers: for handles
+  // whose vector launches are at most kRegBasisChunks workgroups.
+  bool reg_basis = false;
   // The FP64 solve's report, read back with one copy: GMRES states, then
   // (||r||^2, u_S . r), the compatibility defects and (||b~||^2, u_S . b~)
   // per instance (gs, pairs, defect and nb2 point into it).
@@ -728,6 +736,7 @@ void upload(smpm_handle *H, hipStream_t st) {
   H->w_M1 = dupload(own, wM1, st); H->n_M1 = (int)wM1.size();
   H->w_h = dupload(own, wh, st); H->n_h = (int)wh.size();
   H->w_x = dupload(own, wx, st); H->n_x = (int)wx.size();
+  H->reg_basis = H->n_x <= kRegBasisChunks;
   H->w_r = dupload(own, wr, st); H->n_r = (int)wr.size();
   H->w_s = dupload(own, ws, st); H->n_s = (int)ws.size();
   H->F = dalloc<double>(own, f_off); H->v = dalloc<double>(own, f_off); H->Rr = dalloc<double>(own, f_off);
@@ -1264,9 +1273,14 @@ struct Inner {
                          H->d_ins, (const double *)H->hs, (const double *)nullptr, (double *)nullptr, H->cv,
                          (const GState *)H->gs);
     }
-    hipLaunchKernelGGL((k_pcorr_dot<T, T>), dim3(H->n_x), dim3(kBlock), cpre ? 0 : sizeof(double) * H->dmax, st,
-                       H->d_sys, H->d_ins, H->w_x, (const T *)yb, (const double *)H->hs, useP ? 1 : 0, Vb, H->part1,
-                       (const GState *)H->gs, cpre ? (const double *)H->cv : (const double *)nullptr);
+    if (H->reg_basis)
+      hipLaunchKernelGGL((k_pcorr_dot<T, T, true>), dim3(H->n_x), dim3(kBlock), cpre ? 0 : sizeof(double) * H->dmax, st,
+                         H->d_sys, H->d_ins, H->w_x, (const T *)yb, (const double *)H->hs, useP ? 1 : 0, Vb, H->part1,
+                         (const GState *)H->gs, cpre ? (const double *)H->cv : (const double *)nullptr);
+    else
+      hipLaunchKernelGGL((k_pcorr_dot<T, T>), dim3(H->n_x), dim3(kBlock), cpre ? 0 : sizeof(double) * H->dmax, st,
+                         H->d_sys, H->d_ins, H->w_x, (const T *)yb, (const double *)H->hs, useP ? 1 : 0, Vb, H->part1,
+                         (const GState *)H->gs, cpre ? (const double *)H->cv : (const double *)nullptr);
     // One Krylov space over all instances (Sec. 5.2): every reduction spans
     // the segment, so the partials go through k_seg_reduce first.
     const bool seg = H->one_krylov;
@@ -1277,6 +1291,16 @@ struct Inner {
     if (!seg) {
       // CGS2 in two passes; the second takes the Givens step in its last
       // workgroup (the first pass leaves |w|^2 for the Pythagorean norm)
+      if (H->reg_basis) {
+        hipLaunchKernelGGL((k_axpy_dot<T, true>), dim3(H->n_x), dim3(kBlock), shm_dot, st, H->d_sys, H->d_ins, H->w_x,
+                           Vb, (const double *)H->part1, H->part2, H->partn, (const double *)H->scale,
+                           (const GState *)H->gs, (const double *)nullptr);
+        hipLaunchKernelGGL((k_axpy_givens<T, true>), dim3(H->n_x), dim3(kBlock), sizeof(double) * (5 * maxit + 4), st,
+                           H->d_sys, H->d_ins, H->w_x, Vb, (const double *)H->part1, (const double *)H->part2,
+                           (const double *)H->partn, H->scale, H->Rm, H->cs, H->sn, H->g, H->gs, H->arrive, maxit,
+                           tol(H));
+        return;
+      }
       hipLaunchKernelGGL((k_axpy_dot<T>), dim3(H->n_x), dim3(kBlock), shm_dot, st, H->d_sys, H->d_ins, H->w_x, Vb,
                          (const double *)H->part1, H->part2, H->partn, (const double *)H->scale,
                          (const GState *)H->gs, (const double *)nullptr);
