@@ -132,6 +132,9 @@ struct SetupOptions {
   int threads = 0;
   int zlabel = 0;   // deflation space: 0 one column per interface, 1 per element segment
   const DenseBackend *dense = nullptr;
+  // A second back end for the u_S elimination, which runs beside the other
+  // setup steps (its own stream and library handle); nullptr: `dense`.
+  const DenseBackend *dense_null = nullptr;
 };
 
 // Build every host table of one system.  Throws std::runtime_error with a

@@ -20,6 +20,7 @@
 #include <cstdlib>
 #include <cstdio>
 #include <cstring>
+#include <future>
 #include <map>
 #include <stdexcept>
 #include <tuple>
@@ -467,7 +468,10 @@ static bool invert_many(const SetupOptions &opt, int n, const std::vector<double
 // (Sec. 2.4).  S is block tridiagonal over interfaces (2N x 2N blocks); the
 // shifted transpose T is factored by block elimination, the diagonal blocks
 // with partial pivoting, on the host or through opt.dense.
-static void left_null_schur(System &s, const SetupOptions &opt) {
+// Returns 1 when the elimination ran on the device back end, else 0.
+static int left_null_schur(const System &s, const SetupOptions &opt, std::vector<double> &uS) {
+  const DenseBackend *be = opt.dense_null ? opt.dense_null : opt.dense;
+  int dev = 0;
   const int N = s.N, M = 2 * N, d = s.mx - 1;   // d: interfaces
   // Interface blocks of S: Sd[i] (M x M), Su[i] = S[i][i+1] (upper-left N x N
   // of rows of half 2i, cols of half 2i+2), Sl[i] = S[i][i-1] (rows of half
@@ -513,10 +517,10 @@ static void left_null_schur(System &s, const SetupOptions &opt) {
   std::vector<double> X;
   // the elimination is sequential over the interfaces: one host thread
   const double elim = (double)d * (2.0 / 3.0 * M * M * M + 2.0 * M * M * N + 2.0 * N * N * N);
-  if (opt.dense && opt.dense->tri_factor && (elim >= kDeviceWork || opt.dense->always)) {
-    dev_fact = opt.dense->tri_factor(d, N, Td.data(), Lo.data(), Up.data());
-    s.dev_steps |= 1;
-    solve = [&](std::vector<double> &v) { opt.dense->tri_solve(dev_fact, v.data()); };
+  if (be && be->tri_factor && (elim >= kDeviceWork || be->always)) {
+    dev_fact = be->tri_factor(d, N, Td.data(), Lo.data(), Up.data());
+    dev = 1;
+    solve = [&](std::vector<double> &v) { be->tri_solve(dev_fact, v.data()); };
   } else {
     // Block elimination: T~_i = Td[i] - T[i][i-1] X_{i-1}, X_i = T~_i^-1 T[i][i+1]
     // (X_i: the M x N nonzero columns N..2N).
@@ -587,14 +591,15 @@ static void left_null_schur(System &s, const SetupOptions &opt) {
       if (norm2(Stu) <= 1e-13 * snorm && it >= 1) break;
     }
   } catch (...) {
-    if (dev_fact) opt.dense->tri_free(dev_fact);
+    if (dev_fact) be->tri_free(dev_fact);
     throw;
   }
-  if (dev_fact) opt.dense->tri_free(dev_fact);
+  if (dev_fact) be->tri_free(dev_fact);
   double sum = 0.0;
   for (double a : u) sum += a;
   if (sum < 0) for (auto &a : u) a = -a;
-  s.uS = u;
+  uS = std::move(u);
+  return dev;
 }
 
 // S M^-1 per half (shared-block grids): F_h = E_h M^-1 + W_h [M^-1 rows of the
@@ -795,6 +800,16 @@ void build_system(System &s, int mx, int mz, int order, const double *xb, const 
         std::memcpy(&s.Wblk[(size_t)b * N * 2 * N + (size_t)i * 2 * N + c * N], &Wq[(size_t)i * N], sizeof(double) * N);
     }
   }
+  // The left null vector of S (k = 0) needs only the Schur blocks, and its
+  // elimination is one sequential chain over the interfaces: it runs on a
+  // thread of its own (with its own device back end) beside the
+  // block-Jacobi, S M^-1 and coarse steps, which read none of its output.
+  std::vector<double> uS_out;
+  std::future<int> us_task;
+  if (s.singular) {
+    const System &cs = s;
+    us_task = std::async(std::launch::async, [&cs, &opt, &uS_out] { return left_null_schur(cs, opt, uS_out); });
+  }
   // Block-Jacobi: blocks over interfaces (2b, 2b+1), deduplicated.
   s.m_id.assign(s.nh, -1); s.m_win.assign(s.nh, 0); s.m_K.assign(s.nh, 0);
   const int nblocks = s.mx / 2;   // pairs of the m_x - 1 interfaces
@@ -980,8 +995,9 @@ void build_system(System &s, int mx, int mz, int order, const double *xb, const 
     }
     timer.lap("deflation, coarse");
     // Null vectors of S and L.
-    left_null_schur(s, opt);
-    timer.lap("u_S");
+    if (us_task.get()) s.dev_steps |= 1;
+    s.uS = std::move(uS_out);
+    timer.lap("u_S (the wait for it)");
     // u_L = A^-T B^T u_S (Claim 1, part 2)
     std::vector<double> uL(s.r, 0.0);
     const int n2 = s.n2;

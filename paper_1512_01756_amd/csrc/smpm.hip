@@ -1698,6 +1698,10 @@ smpm_status setup_common(const smpm_grid *grids, const double *k, int nsys, bool
           : device_dense_create((H->opts.flags & SMPM_FLAG_DEVICE_SETUP) != 0),
       device_dense_destroy);
   so.dense = device_dense_backend(dense.get());
+  // the u_S elimination runs beside the other steps: a back end of its own
+  std::unique_ptr<DeviceDense, void (*)(DeviceDense *)> dense_null(
+      dense ? device_dense_create((H->opts.flags & SMPM_FLAG_DEVICE_SETUP) != 0) : nullptr, device_dense_destroy);
+  so.dense_null = device_dense_backend(dense_null.get());
   parallel_for(nsys, nsys > 1 ? 0 : 1, [&](int i) {
     const smpm_grid &g = one_grid ? grids[0] : grids[i];
     try {
