@@ -2403,6 +2403,29 @@ __global__ __launch_bounds__(kBlock) void k_fill(double *__restrict__ p, int64_t
 
 // out[0, n) = (float)in[0, n): the FP32 operator tables from the uploaded
 // FP64 ones (same padded layout), at setup.
+// Column-major copy, rows padded to ld with zeros, of nb row-major rows x cols
+// blocks (the setup's tables as the host builds them): 32 x 32 tiles through
+// LDS, grid (column tiles, row tiles of ld, blocks), 32 x 8 threads.
+__global__ __launch_bounds__(256) void k_colmajor_pad(const double *__restrict__ src, double *__restrict__ dst,
+                                                      int nb, int rows, int cols, int ld) {
+  __shared__ double tile[32][33];
+  const int c0 = blockIdx.x * 32, r0 = blockIdx.y * 32;
+  for (int b = blockIdx.z; b < nb; b += gridDim.z) {
+    const double *sb = src + (size_t)b * rows * cols;
+    double *db = dst + (size_t)b * ld * cols;
+    for (int k = threadIdx.y; k < 32; k += 8) {
+      const int r = r0 + k, c = c0 + threadIdx.x;
+      tile[k][threadIdx.x] = (r < rows && c < cols) ? sb[(size_t)r * cols + c] : 0.0;
+    }
+    __syncthreads();
+    for (int k = threadIdx.y; k < 32; k += 8) {
+      const int c = c0 + k, r = r0 + threadIdx.x;
+      if (c < cols && r < ld) db[(size_t)c * ld + r] = tile[threadIdx.x][k];
+    }
+    __syncthreads();
+  }
+}
+
 __global__ __launch_bounds__(kBlock) void k_to_f32(const double *__restrict__ in, float *__restrict__ out, int64_t n) {
   const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (i < n) out[i] = (float)in[i];

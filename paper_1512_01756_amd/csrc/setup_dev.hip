@@ -10,7 +10,11 @@
 #include <rocsolver/rocsolver.h>
 
 #include <algorithm>
+#include <chrono>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
+#include <memory>
 #include <mutex>
 #include <stdexcept>
 #include <string>
@@ -43,16 +47,27 @@ struct DBuf {
   DBuf &operator=(const DBuf &) = delete;
 };
 
-// Factors of the block-tridiagonal T, all column-major on the device:
-// T~_i (M x M, LU with pivots), Lo_i (N x N), X_i = T~_i^-1 T[i][i+1]
-// (the M x N nonzero columns).
+// Cyclic reduction of the block-tridiagonal T (d blocks of M = 2N), all
+// column-major on the device.  Level 0 holds T: diagonal blocks A_i, the
+// coupling to block i - 1 (B_i) and to block i + 1 (C_i).  One level
+// eliminates the odd positions k of the current list: A_k is factored (LU with
+// pivots), B_k <- Y_k = A_k^-1 B_k and C_k <- Z_k = A_k^-1 C_k; the even
+// positions e become the next level, with A_e - B_e Z_{e-1} - C_e Y_{e+1},
+// -B_e Y_{e-1} and -C_e Z_{e+1}.  Every step of a level is one
+// strided-batched call over its odd or even blocks, so the d sequential steps
+// of a block elimination become log2(d) levels.  The last level is one block,
+// factored.
+struct CrLevel {
+  int m;                             // blocks on this level
+  DBuf<double> A, B, C, b;           // m blocks of M x M each; b: m blocks of M (solves)
+  DBuf<rocblas_int> ipiv, info;
+  CrLevel(int m_, int M)
+      : m(m_), A((size_t)m_ * M * M), B((size_t)m_ * M * M), C((size_t)m_ * M * M), b((size_t)m_ * M),
+        ipiv((size_t)m_ * M), info(m_) {}
+};
 struct TriFact {
   int d, N, M;
-  DBuf<double> T, Lo, X, v, tmp;
-  DBuf<rocblas_int> ipiv, info;
-  TriFact(int d_, int N_)
-      : d(d_), N(N_), M(2 * N_), T((size_t)d_ * 4 * N_ * N_), Lo((size_t)d_ * N_ * N_),
-        X((size_t)d_ * 2 * N_ * N_), v((size_t)d_ * 2 * N_), tmp(2 * N_), ipiv((size_t)d_ * 2 * N_), info(d_) {}
+  std::vector<std::unique_ptr<CrLevel>> lv;
 };
 
 // Right-hand sides of element e's boundary injections for cn classes, laid
@@ -134,85 +149,150 @@ struct DeviceDense {
     std::lock_guard<std::mutex> lk(mu);
     ensure();
     const int M = 2 * N;
-    TriFact *f = new TriFact(d, N);
-    try {
-      std::vector<double> buf((size_t)M * M), bl((size_t)N * N), bx((size_t)M * N);
-      for (int i = 0; i < d; ++i) {
-        const double *t = Td + (size_t)i * M * M;
-        for (int r = 0; r < M; ++r)
-          for (int c = 0; c < M; ++c) buf[(size_t)c * M + r] = t[(size_t)r * M + c];
-        hcheck(hipMemcpy(f->T.p + (size_t)i * M * M, buf.data(), sizeof(double) * M * M, hipMemcpyHostToDevice),
-               "upload T");
-        const double *l = Lo + (size_t)i * N * N;
-        for (int r = 0; r < N; ++r)
-          for (int c = 0; c < N; ++c) bl[(size_t)c * N + r] = l[(size_t)r * N + c];
-        hcheck(hipMemcpy(f->Lo.p + (size_t)i * N * N, bl.data(), sizeof(double) * N * N, hipMemcpyHostToDevice),
-               "upload Lo");
-        std::fill(bx.begin(), bx.end(), 0.0);
-        if (i + 1 < d) {
-          const double *u = Up + (size_t)i * N * N;
-          for (int r = 0; r < N; ++r)
-            for (int c = 0; c < N; ++c) bx[(size_t)c * M + N + r] = u[(size_t)r * N + c];
-        }
-        hcheck(hipMemcpy(f->X.p + (size_t)i * M * N, bx.data(), sizeof(double) * M * N, hipMemcpyHostToDevice),
-               "upload X");
-      }
-      const double one = 1.0, minus = -1.0;
-      for (int i = 0; i < d; ++i) {
-        double *T = f->T.p + (size_t)i * M * M;
-        if (i > 0)
-          rcheck(rocblas_dgemm(h, rocblas_operation_none, rocblas_operation_none, N, N, N, &minus,
-                               f->Lo.p + (size_t)i * N * N, N, f->X.p + (size_t)(i - 1) * M * N, M, &one, T + (size_t)N * M,
-                               M),
-                 "gemm");
-        rcheck(rocsolver_dgetrf(h, M, M, T, M, f->ipiv.p + (size_t)i * M, f->info.p + i), "getrf");
-        if (i + 1 < d)
-          rcheck(rocsolver_dgetrs(h, rocblas_operation_none, M, N, T, M, f->ipiv.p + (size_t)i * M,
-                                  f->X.p + (size_t)i * M * N, M),
-                 "getrs");
-      }
-      std::vector<rocblas_int> hinfo(d);
-      hcheck(hipMemcpyAsync(hinfo.data(), f->info.p, sizeof(rocblas_int) * d, hipMemcpyDeviceToHost, st), "info");
-      hcheck(hipStreamSynchronize(st), "elimination");
-      for (int i = 0; i < d; ++i)
-        if (hinfo[i] != 0) throw std::runtime_error("singular block in the inverse iteration for u_S");
-    } catch (...) {
-      delete f;
-      throw;
+    const size_t MM = (size_t)M * M;
+    std::unique_ptr<TriFact> f(new TriFact{d, N, M, {}});
+    const double one = 1.0, minus = -1.0, zero = 0.0;
+    const rocblas_operation nn = rocblas_operation_none;
+    // SMPM_SETUP_TIMES: the upload and each level, synchronized, to stderr
+    const bool times = std::getenv("SMPM_SETUP_TIMES") != nullptr;
+    auto t0 = std::chrono::steady_clock::now();
+    auto lap = [&](const char *what, int m) {
+      if (!times) return;
+      hcheck(hipStreamSynchronize(st), "lap");
+      const auto t1 = std::chrono::steady_clock::now();
+      std::fprintf(stderr, "  u_S reduction: %-24s m = %4d  %8.1f ms\n", what, m,
+                   std::chrono::duration<double, std::milli>(t1 - t0).count());
+      t0 = t1;
+    };
+    // level 0: T's blocks.  The host's row-major blocks go up as they are and
+    // are transposed on the device (a row-major block is the column-major
+    // transpose); B_i and C_i are zero but for one N x N quadrant (rows and
+    // columns 0..N of B_i, N..2N of C_i).
+    f->lv.emplace_back(new CrLevel(d, M));
+    {
+      CrLevel &L0 = *f->lv[0];
+      const size_t NN = (size_t)N * N;
+      DBuf<double> raw((size_t)d * MM), lo((size_t)d * NN), up((size_t)d * NN);
+      hcheck(hipMemcpyAsync(raw.p, Td, sizeof(double) * d * MM, hipMemcpyHostToDevice, st), "upload T");
+      hcheck(hipMemcpyAsync(lo.p, Lo, sizeof(double) * d * NN, hipMemcpyHostToDevice, st), "upload Lo");
+      hcheck(hipMemcpyAsync(up.p, Up, sizeof(double) * d * NN, hipMemcpyHostToDevice, st), "upload Up");
+      hcheck(hipMemsetAsync(L0.B.p, 0, sizeof(double) * d * MM, st), "zero B");
+      hcheck(hipMemsetAsync(L0.C.p, 0, sizeof(double) * d * MM, st), "zero C");
+      const rocblas_operation tt = rocblas_operation_transpose;
+      rcheck(rocblas_dgeam_strided_batched(h, tt, nn, M, M, &one, raw.p, M, MM, &zero, raw.p, M, MM, L0.A.p, M, MM, d),
+             "transpose A");
+      rcheck(rocblas_dgeam_strided_batched(h, tt, nn, N, N, &one, lo.p + NN, N, NN, &zero, lo.p + NN, N, NN,
+                                           L0.B.p + MM, M, MM, d - 1),
+             "transpose B");
+      rcheck(rocblas_dgeam_strided_batched(h, tt, nn, N, N, &one, up.p, N, NN, &zero, up.p, N, NN,
+                                           L0.C.p + (size_t)N * M + N, M, MM, d - 1),
+             "transpose C");
+      hcheck(hipStreamSynchronize(st), "level 0");   // before the staging buffers go
     }
-    return f;
+    lap("upload", d);
+    while (f->lv.back()->m > 1) {
+      CrLevel &L = *f->lv.back();
+      const int m = L.m, mo = m / 2, me = (m + 1) / 2;
+      // odd blocks: A_k = LU, Y_k = A_k^-1 B_k, Z_k = A_k^-1 C_k
+      rcheck(rocsolver_dgetrf_strided_batched(h, M, M, L.A.p + MM, M, 2 * MM, L.ipiv.p + M, 2 * M, L.info.p, mo),
+             "getrf (odd blocks)");
+      lap("getrf", m);
+      rcheck(rocsolver_dgetrs_strided_batched(h, nn, M, M, L.A.p + MM, M, 2 * MM, L.ipiv.p + M, 2 * M, L.B.p + MM, M,
+                                              2 * MM, mo),
+             "getrs Y");
+      rcheck(rocsolver_dgetrs_strided_batched(h, nn, M, M, L.A.p + MM, M, 2 * MM, L.ipiv.p + M, 2 * M, L.C.p + MM, M,
+                                              2 * MM, mo),
+             "getrs Z");
+      lap("getrs", m);
+      f->lv.emplace_back(new CrLevel(me, M));
+      CrLevel &Nx = *f->lv.back();
+      hcheck(hipMemsetAsync(Nx.B.p, 0, sizeof(double) * me * MM, st), "zero B'");
+      hcheck(hipMemsetAsync(Nx.C.p, 0, sizeof(double) * me * MM, st), "zero C'");
+      // even blocks e = 2q: A_e -= B_e Z_{e-1} (q >= 1), A_e -= C_e Y_{e+1} (q < mo)
+      if (me > 1)
+        rcheck(rocblas_dgemm_strided_batched(h, nn, nn, M, M, M, &minus, L.B.p + 2 * MM, M, 2 * MM, L.C.p + MM, M,
+                                             2 * MM, &one, L.A.p + 2 * MM, M, 2 * MM, me - 1),
+               "gemm A -= B Z");
+      rcheck(rocblas_dgemm_strided_batched(h, nn, nn, M, M, M, &minus, L.C.p, M, 2 * MM, L.B.p + MM, M, 2 * MM, &one,
+                                           L.A.p, M, 2 * MM, mo),
+             "gemm A -= C Y");
+      // B'_q = -B_e Y_{e-1} (q >= 1), C'_q = -C_e Z_{e+1} (q < mo)
+      if (me > 1)
+        rcheck(rocblas_dgemm_strided_batched(h, nn, nn, M, M, M, &minus, L.B.p + 2 * MM, M, 2 * MM, L.B.p + MM, M,
+                                             2 * MM, &zero, Nx.B.p + MM, M, MM, me - 1),
+               "gemm B'");
+      rcheck(rocblas_dgemm_strided_batched(h, nn, nn, M, M, M, &minus, L.C.p, M, 2 * MM, L.C.p + MM, M, 2 * MM, &zero,
+                                           Nx.C.p, M, MM, mo),
+             "gemm C'");
+      hcheck(hipMemcpy2DAsync(Nx.A.p, sizeof(double) * MM, L.A.p, sizeof(double) * 2 * MM, sizeof(double) * MM, me,
+                              hipMemcpyDeviceToDevice, st),
+             "next level A");
+      lap("gemms, next level", m);
+    }
+    CrLevel &Lc = *f->lv.back();
+    rcheck(rocsolver_dgetrf_strided_batched(h, M, M, Lc.A.p, M, MM, Lc.ipiv.p, M, Lc.info.p, 1), "getrf (last)");
+    for (size_t l = 0; l < f->lv.size(); ++l) {
+      CrLevel &L = *f->lv[l];
+      const int cnt = l + 1 == f->lv.size() ? 1 : L.m / 2;
+      std::vector<rocblas_int> hinfo(cnt);
+      hcheck(hipMemcpyAsync(hinfo.data(), L.info.p, sizeof(rocblas_int) * cnt, hipMemcpyDeviceToHost, st), "info");
+      hcheck(hipStreamSynchronize(st), "reduction");
+      for (int k = 0; k < cnt; ++k)
+        if (hinfo[k] != 0) throw std::runtime_error("singular block in the inverse iteration for u_S");
+    }
+    return f.release();
   }
 
-  // v <- T^-1 v: forward y_i = v_i - Lo_i T~_{i-1}^-1 y_{i-1} (first N rows),
-  // backward x_i = T~_i^-1 y_i - X_i x_{i+1}[N..2N].
+  // v <- T^-1 v through the levels: forward, w_k = A_k^-1 b_k on the odd
+  // blocks and b_e -= B_e w_{e-1} + C_e w_{e+1} on the even ones, which become
+  // the next level's right-hand side; the last block solved; backward, the
+  // even blocks take the next level's solution and the odd ones
+  // x_k = w_k - Y_k x_{k-1} - Z_k x_{k+1}.
   void tri_solve(void *fp, double *v) {
     std::lock_guard<std::mutex> lk(mu);
     hcheck(hipSetDevice(dev), "hipSetDevice");
     TriFact *f = static_cast<TriFact *>(fp);
-    const int d = f->d, N = f->N, M = f->M;
+    const int M = f->M;
+    const size_t MM = (size_t)M * M;
     const double one = 1.0, minus = -1.0;
-    double *dv = f->v.p;
-    hcheck(hipMemcpy(dv, v, sizeof(double) * d * M, hipMemcpyHostToDevice), "upload v");
-    for (int i = 1; i < d; ++i) {
-      hcheck(hipMemcpyAsync(f->tmp.p, dv + (size_t)(i - 1) * M, sizeof(double) * M, hipMemcpyDeviceToDevice, st),
-             "copy");
-      rcheck(rocsolver_dgetrs(h, rocblas_operation_none, M, 1, f->T.p + (size_t)(i - 1) * M * M, M,
-                              f->ipiv.p + (size_t)(i - 1) * M, f->tmp.p, M),
-             "getrs");
-      rcheck(rocblas_dgemv(h, rocblas_operation_none, N, N, &minus, f->Lo.p + (size_t)i * N * N, N, f->tmp.p, 1, &one,
-                           dv + (size_t)i * M, 1),
-             "gemv");
+    const rocblas_operation nn = rocblas_operation_none;
+    const int nl = (int)f->lv.size();
+    hcheck(hipMemcpyAsync(f->lv[0]->b.p, v, sizeof(double) * f->d * M, hipMemcpyHostToDevice, st), "upload v");
+    for (int l = 0; l + 1 < nl; ++l) {
+      CrLevel &L = *f->lv[l], &Nx = *f->lv[l + 1];
+      const int m = L.m, mo = m / 2, me = (m + 1) / 2;
+      rcheck(rocsolver_dgetrs_strided_batched(h, nn, M, 1, L.A.p + MM, M, 2 * MM, L.ipiv.p + M, 2 * M, L.b.p + M, M,
+                                              2 * M, mo),
+             "getrs w");
+      if (me > 1)
+        rcheck(rocblas_dgemv_strided_batched(h, nn, M, M, &minus, L.B.p + 2 * MM, M, 2 * MM, L.b.p + M, 1, 2 * M, &one,
+                                             L.b.p + 2 * M, 1, 2 * M, me - 1),
+               "gemv b -= B w");
+      rcheck(rocblas_dgemv_strided_batched(h, nn, M, M, &minus, L.C.p, M, 2 * MM, L.b.p + M, 1, 2 * M, &one, L.b.p, 1,
+                                           2 * M, mo),
+             "gemv b -= C w");
+      hcheck(hipMemcpy2DAsync(Nx.b.p, sizeof(double) * M, L.b.p, sizeof(double) * 2 * M, sizeof(double) * M, me,
+                              hipMemcpyDeviceToDevice, st),
+             "next level b");
     }
-    for (int i = d - 1; i >= 0; --i) {
-      rcheck(rocsolver_dgetrs(h, rocblas_operation_none, M, 1, f->T.p + (size_t)i * M * M, M, f->ipiv.p + (size_t)i * M,
-                              dv + (size_t)i * M, M),
-             "getrs");
-      if (i + 1 < d)
-        rcheck(rocblas_dgemv(h, rocblas_operation_none, M, N, &minus, f->X.p + (size_t)i * M * N, M,
-                             dv + (size_t)(i + 1) * M + N, 1, &one, dv + (size_t)i * M, 1),
-               "gemv");
+    CrLevel &Lc = *f->lv.back();
+    rcheck(rocsolver_dgetrs_strided_batched(h, nn, M, 1, Lc.A.p, M, MM, Lc.ipiv.p, M, Lc.b.p, M, M, 1), "getrs (last)");
+    for (int l = nl - 2; l >= 0; --l) {
+      CrLevel &L = *f->lv[l], &Nx = *f->lv[l + 1];
+      const int m = L.m, mo = m / 2, me = (m + 1) / 2;
+      hcheck(hipMemcpy2DAsync(L.b.p, sizeof(double) * 2 * M, Nx.b.p, sizeof(double) * M, sizeof(double) * M, me,
+                              hipMemcpyDeviceToDevice, st),
+             "even solution");
+      rcheck(rocblas_dgemv_strided_batched(h, nn, M, M, &minus, L.B.p + MM, M, 2 * MM, L.b.p, 1, 2 * M, &one,
+                                           L.b.p + M, 1, 2 * M, mo),
+             "gemv x -= Y x");
+      const int nz = (m % 2 == 1) ? mo : mo - 1;   // odd blocks with a right neighbour
+      if (nz > 0)
+        rcheck(rocblas_dgemv_strided_batched(h, nn, M, M, &minus, L.C.p + MM, M, 2 * MM, L.b.p + 2 * M, 1, 2 * M,
+                                             &one, L.b.p + M, 1, 2 * M, nz),
+               "gemv x -= Z x");
     }
-    hcheck(hipMemcpyAsync(v, dv, sizeof(double) * d * M, hipMemcpyDeviceToHost, st), "download v");
+    hcheck(hipMemcpyAsync(v, f->lv[0]->b.p, sizeof(double) * f->d * M, hipMemcpyDeviceToHost, st), "download v");
     hcheck(hipStreamSynchronize(st), "solve");
   }
 

@@ -445,6 +445,9 @@ static double norm2(const std::vector<double> &v) {
 // transfers and the library start-up cost more than the host threads take
 // (measured on the c2 and c3 grids).
 constexpr double kDeviceWork = 2e10;
+// Interfaces from which the u_S elimination goes to the device back end (its
+// cyclic reduction is log2(d) levels of batched calls).
+constexpr int kDeviceInterfaces = 16;
 
 // In-place inverses of row-major n x n matrices: through the device back end
 // when one is given and the work per host thread is large (2 n^3 per matrix;
@@ -515,9 +518,10 @@ static int left_null_schur(const System &s, const SetupOptions &opt, std::vector
   void *dev_fact = nullptr;
   std::vector<int> piv;
   std::vector<double> X;
-  // the elimination is sequential over the interfaces: one host thread
-  const double elim = (double)d * (2.0 / 3.0 * M * M * M + 2.0 * M * M * N + 2.0 * N * N * N);
-  if (be && be->tri_factor && (elim >= kDeviceWork || be->always)) {
+  // On the host the elimination is sequential over the interfaces (one
+  // thread); the device back end reduces the interfaces cyclically, log2(d)
+  // levels of batched calls, and takes every system of 16 interfaces or more.
+  if (be && be->tri_factor && (d >= kDeviceInterfaces || be->always)) {
     dev_fact = be->tri_factor(d, N, Td.data(), Lo.data(), Up.data());
     dev = 1;
     solve = [&](std::vector<double> &v) { be->tri_solve(dev_fact, v.data()); };

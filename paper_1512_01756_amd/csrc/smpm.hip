@@ -54,6 +54,41 @@ T *dalloc(std::vector<void *> &owned, size_t count) {
   return static_cast<T *>(p);
 }
 
+// Device copy, column-major with the rows padded to ld, of nb row-major
+// rows x cols blocks given as `parts` (consecutive runs of whole blocks, e.g.
+// one per strip class): the host memory goes up as it is and the device
+// transposes it, so the host neither copies nor transposes the tables.
+double *dupload_cm(std::vector<void *> &owned, const std::vector<std::pair<const double *, size_t>> &parts, int nb,
+                   int rows, int cols, int ld, hipStream_t st) {
+  double *out = dalloc<double>(owned, (size_t)nb * ld * cols);
+  if (nb == 0) return out;
+  double *raw = nullptr;
+  if (hipMalloc((void **)&raw, sizeof(double) * (size_t)nb * rows * cols) != hipSuccess) throw std::bad_alloc();
+  try {
+    size_t off = 0;
+    for (const auto &pr : parts) {
+      if (pr.second)
+        HIPCHECK(hipMemcpyAsync(raw + off, pr.first, sizeof(double) * pr.second, hipMemcpyHostToDevice, st));
+      off += pr.second;
+    }
+    if (off != (size_t)nb * rows * cols) throw std::runtime_error("table upload: sizes do not add up");
+    const dim3 grid((unsigned)((cols + 31) / 32), (unsigned)((ld + 31) / 32), (unsigned)std::min(nb, 65535));
+    hipLaunchKernelGGL(k_colmajor_pad, grid, dim3(32, 8), 0, st, (const double *)raw, out, nb, rows, cols, ld);
+    HIPCHECK(hipGetLastError());
+    HIPCHECK(hipStreamSynchronize(st));
+  } catch (...) {
+    (void)hipFree(raw);
+    throw;
+  }
+  HIPCHECK(hipFree(raw));
+  return out;
+}
+
+double *dupload_cm(std::vector<void *> &owned, const std::vector<double> &a, int nb, int rows, int cols, int ld,
+                   hipStream_t st) {
+  return dupload_cm(owned, {{a.data(), a.size()}}, nb, rows, cols, ld, st);
+}
+
 template <typename T>
 T *dupload(std::vector<void *> &owned, const std::vector<T> &v, hipStream_t st) {
   T *p = dalloc<T>(owned, v.size());
@@ -355,10 +390,10 @@ void upload(smpm_handle *H, hipStream_t st) {
     d.singular = s.singular ? 1 : 0; d.kS = s.kS; d.r = s.r; d.tau = s.tau;
     d.nq = 2 * s.n * (s.mz - 1);
     d.Np = (s.N + 7) / 8 * 8;   // 16-byte columns in FP64, FP32 and FP16
-    d.W64 = dupload(own, to_colmajor_padded<double>(s.Wblk, s.nW, s.N, 2 * s.N, d.Np), st);
+    d.W64 = dupload_cm(own, s.Wblk, s.nW, s.N, 2 * s.N, d.Np, st);
     d.W32 = dconvert32(own, d.W64, (size_t)s.nW * 2 * s.N * d.Np, st);
     if (s.nF > 0) {
-      d.F64 = dupload(own, to_colmajor_padded<double>(s.Fblk, s.nF, s.N, 8 * s.N, d.Np), st);
+      d.F64 = dupload_cm(own, s.Fblk, s.nF, s.N, 8 * s.N, d.Np, st);
       d.F32 = dconvert32(own, d.F64, (size_t)s.nF * 8 * s.N * d.Np, st);
     }
     if (H->op16) {
@@ -374,7 +409,7 @@ void upload(smpm_handle *H, hipStream_t st) {
     }
     d.w_id = dupload(own, s.w_id, st);
     d.w_win = dupload(own, s.w_win, st);
-    d.M64 = dupload(own, to_colmajor_padded<double>(s.Mblk, s.nM, s.N, 4 * s.N, d.Np), st);
+    d.M64 = dupload_cm(own, s.Mblk, s.nM, s.N, 4 * s.N, d.Np, st);
     d.M32 = dconvert32(own, d.M64, (size_t)s.nM * 4 * s.N * d.Np, st);
     d.m_id = dupload(own, s.m_id, st);
     d.m_win = dupload(own, s.m_win, st);
@@ -386,27 +421,19 @@ void upload(smpm_handle *H, hipStream_t st) {
     d.uS = s.singular ? dupload(own, s.uS, st) : nullptr;
     d.uL = s.singular ? dupload(own, s.uL, st) : nullptr;
     // element inverses (class, element) and capacitance inverses (class),
-    // column-major, on the host threads over 32-column slices
+    // column-major: each class's row-major tables go up as they are and the
+    // device transposes them
     const int ncl = (int)s.classes.size(), n2 = s.n2, nq = 2 * s.n * (s.mz - 1);
-    std::vector<double> Dinv((size_t)ncl * s.mz * n2 * n2), Kinv((size_t)ncl * nq * nq), beta;
-    const int ct2 = (n2 + 31) / 32, ctq = (nq + 31) / 32;
-    parallel_for(ncl * s.mz * ct2, 0, [&](int q) {
-      const int be = q / ct2, c0 = (q % ct2) * 32, ci = be / s.mz, e = be % s.mz;
-      colmajor_cols(s.classes[ci].Dinv.data() + (size_t)e * n2 * n2, n2, n2, n2, c0, std::min(n2, c0 + 32),
-                    Dinv.data() + (size_t)be * n2 * n2);
-    });
-    if (nq > 0)
-      parallel_for(ncl * ctq, 0, [&](int q) {
-        const int ci = q / ctq, c0 = (q % ctq) * 32;
-        colmajor_cols(s.classes[ci].Kinv.data(), nq, nq, nq, c0, std::min(nq, c0 + 32),
-                      Kinv.data() + (size_t)ci * nq * nq);
-      });
+    std::vector<std::pair<const double *, size_t>> dparts, kparts;
+    std::vector<double> beta;
     for (const StripClass &c : s.classes) {
+      dparts.emplace_back(c.Dinv.data(), (size_t)s.mz * n2 * n2);
+      if (nq > 0) kparts.emplace_back(c.Kinv.data(), (size_t)nq * nq);
       beta.insert(beta.end(), c.betaW.begin(), c.betaW.end());
       beta.insert(beta.end(), c.betaE.begin(), c.betaE.end());
     }
-    d.Dinv = dupload(own, Dinv, st);
-    d.Kinv = dupload(own, Kinv, st);
+    d.Dinv = dupload_cm(own, dparts, ncl * s.mz, n2, n2, n2, st);
+    d.Kinv = nq > 0 ? dupload_cm(own, kparts, ncl, nq, nq, nq, st) : dalloc<double>(own, 1);
     d.beta = dupload(own, beta, st);
     d.lo = dupload(own, s.lo, st);
     d.up = dupload(own, s.up, st);
@@ -686,10 +713,9 @@ void upload(smpm_handle *H, hipStream_t st) {
         const int N = s.N, K = s.mz * s.n2, ncl = (int)s.classes.size();
         std::vector<std::vector<double>> blocks(ncl);
         parallel_for(ncl, 0, [&](int c) { class_rhs_blocks(s, s.classes[c], blocks[c]); });
-        std::vector<double> all;
-        all.reserve((size_t)ncl * 2 * N * K);
-        for (auto &b : blocks) all.insert(all.end(), b.begin(), b.end());
-        const double *dba = dupload(own, to_colmajor_padded<double>(all, 2 * ncl, N, K, d.Np), st);
+        std::vector<std::pair<const double *, size_t>> parts;
+        for (auto &b : blocks) parts.emplace_back(b.data(), b.size());
+        const double *dba = dupload_cm(own, parts, 2 * ncl, N, K, d.Np, st);
         std::map<int, std::vector<int2>> byblk;   // block id -> (instance, strip * 2 + side)
         for (int q = 0; q < H->nrhs; ++q)
           for (int j = 0; j < s.mx; ++j) {
