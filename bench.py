@@ -208,7 +208,8 @@ def gemm_kernel_name(s, op, dtype):
              7: "k_half_gemm<{t}, 16, 18> (split-K, 16 waves, 18 K-steps in flight)",
              8: "k_half_gemm_t<{t}> (LDS-staged, 128-row tile)",
              9: "k_half_gemm_t<{t}> (LDS-staged, 64-row tile, K split 4 ways)",
-             10: "k_half_gemm_t<{t}> (LDS-staged, 128-row tile, K split 2 ways)"}
+             10: "k_half_gemm_t<{t}> (LDS-staged, 128-row tile, K split 2 ways)",
+             11: "k_half_gemm_t<{t}> (LDS-staged, 128-row tile, cost-ordered XCD-aware)"}
     t = "double" if dtype == "fp64" else "float"
     out = set()
     for i in s.info:

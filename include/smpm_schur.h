@@ -177,8 +177,10 @@ typedef struct {
                               waves with a wave's K range in flight at once, for
                               lists of at most 16 windows per item, 8 LDS-staged
                               128-row tiles, 9 / 10 64- / 128-row tiles whose 16
-                              waves also split K; -1 no shared blocks).
-                              SMPM_GEMM_SCHED = 0..10 in the environment,
+                              waves also split K, 11 LDS-staged 128-row tiles in
+                              a cost-ordered XCD-aware order; -1 no shared
+                              blocks).
+                              SMPM_GEMM_SCHED = 0..11 in the environment,
                               read at setup and load, pins them all (tests,
                               experiments) */
   int32_t elem_sched[6];   /* same for the element-interior GEMM lists

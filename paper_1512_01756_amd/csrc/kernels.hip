@@ -278,7 +278,7 @@ template <> struct Mfma<float> {
 // product in the epilogue, so the operand loads never wait for it).
 struct WinInfo {
   int64_t xoff, win, y, xh;
-  double scale;
+  int64_t sidx;   // entry of the scale vector applied to the output (-1: none)
   int live, hs, hn;
 };
 
@@ -289,6 +289,7 @@ __device__ inline void load_windows(const GWork &wk, const GVec *__restrict__ gv
   if (threadIdx.x < VT) {
     const int v = threadIdx.x;
     WinInfo w{};
+    w.sidx = -1;   // no scale for the unused slots past vcount
     if (v < wk.vcount) {
       const GVec e = gvec[wk.vstart + v];
       int it = 0;
@@ -304,7 +305,7 @@ __device__ inline void load_windows(const GWork &wk, const GVec *__restrict__ gv
       w.xh = e.xh;
       w.hs = e.hs;
       w.hn = e.hn;
-      w.scale = scale ? scale[e.st_off + it] : 1.0;
+      w.sidx = scale ? (int64_t)e.st_off + it : -1;
     }
     wi[v] = w;
   }
@@ -377,6 +378,17 @@ __global__ __launch_bounds__(64 * KP) void k_half_gemm(
   for (int v = 0; v < wk.vcount; ++v) anylive |= wi[v].live;
   if (!anylive) return;
   const bool two = TWO && wk.vcount > 16;   // second 16-window operand in use
+  // the scale and identity values of this thread's first output slot are
+  // in flight during the K loop instead of after it
+  double e_sc = 1.0;
+  TO e_id = (TO)0;
+  if (threadIdx.x < 16 * VT) {
+    const int lr = threadIdx.x / VT, v = threadIdx.x - lr * VT, row = rt * 16 + lr;
+    if (v < wk.vcount && wi[v].live && row < N) {
+      if (wi[v].sidx >= 0) e_sc = scale[wi[v].sidx];
+      if (wk.ident) e_id = (TO)xbase[wi[v].xoff + wi[v].xh + row];
+    }
+  }
   const int va = lane & 15, vb = 16 + (lane & 15);
   const bool la = va < wk.vcount && wi[va].live, lb = vb < wk.vcount && wi[vb].live;
   const int64_t xa = wi[va].xoff, wa = wi[va].win, xb = wi[vb].xoff, wb = wi[vb].win;
@@ -421,8 +433,10 @@ __global__ __launch_bounds__(64 * KP) void k_half_gemm(
 #pragma unroll
       for (int q = 1; q < KP; ++q) t += (TO)red[q * 16 * VT + idx];
       t *= (TO)Tab<TS>::rs(wk, row);
-      if (wk.ident) t += (TO)xbase[wi[v].xoff + wi[v].xh + row];
-      const TY out = (TY)((double)t * wi[v].scale);
+      const bool first = idx == (int)threadIdx.x;
+      if (wk.ident) t += first ? e_id : (TO)xbase[wi[v].xoff + wi[v].xh + row];
+      const double sc = first ? e_sc : (wi[v].sidx >= 0 ? scale[wi[v].sidx] : 1.0);
+      const TY out = (TY)((double)t * sc);
       ybase[wi[v].y + row] = out;
       outv = (double)out;
     }
@@ -453,6 +467,7 @@ __global__ __launch_bounds__(64 * KP) void k_half_gemm(
 // XCD-aware order (`units`): workgroup L runs on XCD L mod 8, and every
 // tile that reads one stored block is placed on the same XCD, so the block
 // and the windows are fetched into one L2 instead of eight.
+template <typename TO> constexpr bool kNarrowMfma = std::is_same<TO, double>::value;
 template <typename TS, typename TO, typename TX, typename TY, int CT, int KC, int RW = 4, int KW = 1>
 __global__ __launch_bounds__(64 * RW * KW) void k_half_gemm_t(
     const GWork *__restrict__ work, const int2 *__restrict__ units, const GVec *__restrict__ gvec,
@@ -483,35 +498,44 @@ __global__ __launch_bounds__(64 * RW * KW) void k_half_gemm_t(
   const int64_t kS = wk.kS;
   constexpr int TR = 16 * RW;             // rows per tile
   if (rg * TR >= Np) return;
-  load_windows<VT>(wk, gvec, x_vslot, scale, gs, wi);
-  __syncthreads();
-  int anylive = 0;
-  for (int v = 0; v < wk.vcount; ++v) anylive |= wi[v].live;
-  if (!anylive) return;
   const TS *__restrict__ blk = Tab<TS>::blk(wk);
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int wr = wave % RW, kp = wave / RW;
   const int arow = rg * TR + wr * 16 + (lane & 15);
   const bool alive = arow < Np, wlive = rg * TR + wr * 16 < N;
   const int kq = lane >> 4, cl = lane & 15;
+  TO a[KC / 4], an[KC / 4];
+  auto load_a = [&](int st, TO *dst) {   // this wave's chunk of step st
+#pragma unroll
+    for (int s = 0; s < KC / 4; ++s) {
+      const int k = st * KS + kp * KC + 4 * s + kq;
+      dst[s] = (alive && k < K) ? (TO)blk[(size_t)k * Np + arow] : (TO)0;
+    }
+  };
+  load_a(0, a);   // the first block chunk does not depend on the windows
+  load_windows<VT>(wk, gvec, x_vslot, scale, gs, wi);
+  __syncthreads();
+  // 16-window column tiles with a live window; the others take no MFMA
+  unsigned tmask = 0;
+  for (int v = 0; v < wk.vcount; ++v)
+    if (wi[v].live) tmask |= 1u << (v >> 4);
+  tmask = __builtin_amdgcn_readfirstlane(tmask);
+  if (!tmask) return;
+  // FP64 items of at most 4 windows: one 4-block 4 x 4 x 4 MFMA per K-step
+  // (blocks = the four 4-row groups of the wave's 16 rows, columns = the
+  // windows) instead of a 16-window 16 x 16 x 4 tile of which 12 columns
+  // would be zero
+  const bool narrow = wk.vcount <= 4;
   const int scol = threadIdx.x / TPC, sj = threadIdx.x % TPC;
   const bool slive = scol < wk.vcount && wi[scol].live;
   const int64_t sx = wi[scol].xoff, sw = wi[scol].win;
   TO pre[PV];
-  TO a[KC / 4], an[KC / 4];
   auto load_b = [&](int st) {   // staging step st: K-values st KS .. st KS + KS
 #pragma unroll
     for (int p = 0; p < PV; ++p) {
       const int k = st * KS + sj + TPC * p;
       const int64_t g = sw + k;
       pre[p] = (slive && k < K && g >= 0 && g < kS) ? (TO)xbase[sx + g] : (TO)0;
-    }
-  };
-  auto load_a = [&](int st, TO *dst) {   // this wave's chunk of step st
-#pragma unroll
-    for (int s = 0; s < KC / 4; ++s) {
-      const int k = st * KS + kp * KC + 4 * s + kq;
-      dst[s] = (alive && k < K) ? (TO)blk[(size_t)k * Np + arow] : (TO)0;
     }
   };
   auto store_b = [&](int buf) {
@@ -524,7 +548,6 @@ __global__ __launch_bounds__(64 * RW * KW) void k_half_gemm_t(
   for (int t = 0; t < CT; ++t) acc[t] = Acc{0, 0, 0, 0};
   const int nsteps = (K + KS - 1) / KS;
   load_b(0);
-  load_a(0, a);
   store_b(0);
   __syncthreads();
   for (int st = 0; st < nsteps; ++st) {
@@ -535,11 +558,21 @@ __global__ __launch_bounds__(64 * RW * KW) void k_half_gemm_t(
       load_a(st + 1, an);
     }
     const TO *__restrict__ B = Bs + buf * BS + kp * KC * PITCH;
-    if (wlive) {   // a wave whose 16 rows all lie past the block stages only
+    if constexpr (kNarrowMfma<TO>) {
+      if (wlive && narrow) {
 #pragma unroll
-      for (int s = 0; s < KC / 4; ++s)
+        for (int s = 0; s < KC / 4; ++s)
+          acc[0][0] = __builtin_amdgcn_mfma_f64_4x4x4f64(a[s], B[(4 * s + kq) * PITCH + (lane & 3)], acc[0][0], 0, 0, 0);
+      }
+    }
+    if (wlive && !(kNarrowMfma<TO> && narrow)) {   // a wave whose 16 rows all lie past the block stages only
 #pragma unroll
-        for (int t = 0; t < CT; ++t) acc[t] = Mfma<TO>::mac(a[s], B[(4 * s + kq) * PITCH + t * 16 + cl], acc[t]);
+      for (int t = 0; t < CT; ++t)
+        if ((tmask >> t) & 1u) {
+#pragma unroll
+          for (int s = 0; s < KC / 4; ++s)
+            acc[t] = Mfma<TO>::mac(a[s], B[(4 * s + kq) * PITCH + t * 16 + cl], acc[t]);
+        }
     }
     if (more) {
       store_b(buf ^ 1);
@@ -565,8 +598,33 @@ __global__ __launch_bounds__(64 * RW * KW) void k_half_gemm_t(
 #pragma unroll
         for (int j = 0; j < 4; ++j) acc[t][j] += R[((((q - 1) * RW + wr) * CT + t) * 4 + j) * 64 + lane];
   }
-  // epilogue: lane holds rows Mfma::row(lane, j) of windows t * 16 + cl
   const int slot = rg * RW + wr;
+  if constexpr (kNarrowMfma<TO>) {
+    if (narrow) {
+      // lane m holds row 4 ((m >> 2) & 3) + (m >> 4) of the wave's 16 for
+      // window m & 3; window c's scale is scv[0] of lane c
+      const int c = lane & 3;
+      const int row = rg * TR + wr * 16 + 4 * ((lane >> 2) & 3) + (lane >> 4);
+      const bool ok = c < wk.vcount && wi[c].live;
+      const double sc = (ok && wi[c].sidx >= 0) ? scale[wi[c].sidx] : 1.0;
+      double part = 0.0;
+      if (ok && row < N) {
+        TO val = acc[0][0] * (TO)Tab<TS>::rs(wk, row);
+        if (wk.ident) val += (TO)xbase[wi[c].xoff + wi[c].xh + row];
+        const TY out = (TY)((double)val * sc);
+        ybase[wi[c].y + row] = out;
+        part = (double)out;
+      }
+      // sum the 16 rows of this wave's slot: the lanes with the same c
+      part += __shfl_xor(part, 4, 64);
+      part += __shfl_xor(part, 8, 64);
+      part += __shfl_xor(part, 16, 64);
+      part += __shfl_xor(part, 32, 64);
+      if (hsum && ok && lane < 4 && slot * 16 < N) hsum[wi[c].hs + (int64_t)slot * wi[c].hn] = part;
+      return;
+    }
+  }
+  // epilogue: lane holds rows Mfma::row(lane, j) of windows t * 16 + cl
 #pragma unroll
   for (int t = 0; t < CT; ++t) {
     const int v = t * 16 + cl;
@@ -578,7 +636,7 @@ __global__ __launch_bounds__(64 * RW * KW) void k_half_gemm_t(
       if (ok && row < N) {
         TO val = acc[t][j] * (TO)Tab<TS>::rs(wk, row);
         if (wk.ident) val += (TO)xbase[wi[v].xoff + wi[v].xh + row];
-        const TY out = (TY)((double)val * wi[v].scale);
+        const TY out = (TY)((double)val * (wi[v].sidx >= 0 ? scale[wi[v].sidx] : 1.0));
         ybase[wi[v].y + row] = out;
         part += (double)out;
       }

@@ -200,6 +200,8 @@ struct smpm_handle {
   GVec *g_vec = nullptr;
   int2 *u_all[3] = {};   // XCD-ordered (item, 64-row tile) lists of g_all
   int n_u_all[3] = {};
+  int2 *u128_all[3] = {};   // the same for 128-row tiles, costliest tiles first
+  int n_u128_all[3] = {};
   bool fused = false;    // every system has S M^-1 blocks
   bool use_fused[3] = {}; // per precision: one S M^-1 GEMM per iteration beat M^-1 then S at setup
   // GEMM schedule of each batched list, picked at setup by timing every
@@ -325,28 +327,38 @@ namespace {
 // and bucket b fills grid positions b, b + kXcds, ...; short buckets are
 // padded with (-1, 0) entries, which exit at once.
 constexpr int kXcds = 8;
-std::vector<int2> xcd_units(const std::vector<uintptr_t> &key, const std::vector<int> &tiles) {
+std::vector<int2> xcd_units(const std::vector<uintptr_t> &key, const std::vector<int> &tiles,
+                            const std::vector<std::vector<int64_t>> *cost = nullptr) {
+  // cost of (item, tile): given, or one per tile
+  auto c = [&](int i, int r) -> int64_t { return cost ? (*cost)[i][r] : 1; };
   std::map<uintptr_t, std::vector<int>> by;
   for (int i = 0; i < (int)key.size(); ++i) by[key[i]].push_back(i);
-  std::vector<std::pair<int, uintptr_t>> order;
+  std::vector<std::pair<int64_t, uintptr_t>> order;
   for (auto &kv : by) {
-    int t = 0;
-    for (int i : kv.second) t += tiles[i];
+    int64_t t = 0;
+    for (int i : kv.second)
+      for (int r = 0; r < tiles[i]; ++r) t += c(i, r);
     order.push_back({t, kv.first});
   }
-  std::sort(order.begin(), order.end(), [](auto &a, auto &b) { return a.first > b.first; });
+  std::stable_sort(order.begin(), order.end(), [](auto &a, auto &b) { return a.first > b.first; });
   std::vector<std::vector<int2>> bucket(kXcds);
-  std::vector<int> load(kXcds, 0);
+  std::vector<int64_t> load(kXcds, 0);
   for (auto &o : order) {
     const int b = (int)(std::min_element(load.begin(), load.end()) - load.begin());
     for (int i : by[o.second])
       for (int r = 0; r < tiles[i]; ++r) bucket[b].push_back(make_int2(i, r));
     load[b] += o.first;
   }
-  const int depth = *std::max_element(load.begin(), load.end());
-  std::vector<int2> u((size_t)depth * kXcds, make_int2(-1, 0));
+  // with costs, each XCD takes its tiles costliest first (the dispatcher
+  // hands them out in order as slots free up: longest-first list scheduling)
+  if (cost)
+    for (auto &bk : bucket)
+      std::stable_sort(bk.begin(), bk.end(), [&](const int2 &a, const int2 &b) { return c(a.x, a.y) > c(b.x, b.y); });
+  size_t depth = 0;
+  for (auto &bk : bucket) depth = std::max(depth, bk.size());
+  std::vector<int2> u(depth * kXcds, make_int2(-1, 0));
   for (int b = 0; b < kXcds; ++b)
-    for (int k = 0; k < (int)bucket[b].size(); ++k) u[(size_t)k * kXcds + b] = bucket[b][k];
+    for (size_t k = 0; k < bucket[b].size(); ++k) u[k * kXcds + b] = bucket[b][k];
   return u;
 }
 
@@ -699,6 +711,23 @@ void upload(smpm_handle *H, hipStream_t st) {
       std::vector<int2> u = xcd_units(key, tiles);
       H->u_all[op] = dupload(own, u, st);
       H->n_u_all[op] = (int)u.size();
+      // 128-row tiles, each costed by its MFMA work (K x live 16-row groups
+      // x 16-window column tiles) plus one unit per K for the block's reads
+      std::vector<int> t128;
+      std::vector<std::vector<int64_t>> cost;
+      for (const GWork &w : ga[op]) {
+        const int nt = (w.Np + 127) / 128;
+        t128.push_back(nt);
+        std::vector<int64_t> cr(nt);
+        for (int r = 0; r < nt; ++r) {
+          const int lw = (std::min(w.N, 128 * (r + 1)) - 128 * r + 15) / 16;
+          cr[r] = (int64_t)w.K * ((int64_t)std::max(lw, 0) * ((w.vcount + 15) / 16) + 1);
+        }
+        cost.push_back(cr);
+      }
+      std::vector<int2> u2 = xcd_units(key, t128, &cost);
+      H->u128_all[op] = dupload(own, u2, st);
+      H->n_u128_all[op] = (int)u2.size();
     }
     // B A^-1 per strip class, for the Schur right-hand side of every
     // system in one GEMM over the strips (grids whose strips share classes:
@@ -819,9 +848,11 @@ void upload(smpm_handle *H, hipStream_t st) {
 // rows; kTile64K4 / kTile128K2: 64- or 128-row tiles whose 16 waves also
 // split K four or two ways (shorter MFMA chains per wave).  The staged
 // schedules hold 16 windows per item column group where the items do.
+// kTile128Xcd: the 128-row tile over a cost-ordered XCD-aware unit list
+// (each XCD's tiles costliest first).
 enum GemmSched {
   kSplit16 = 0, kSplit8 = 1, kThrXcd = 2, kThrPlain = 3, kThrXcd64 = 4, kThrPlain64 = 5, kSplit8Deep = 6,
-  kSplit16Deep = 7, kTile128 = 8, kTile64K4 = 9, kTile128K2 = 10, kNumSched = 11
+  kSplit16Deep = 7, kTile128 = 8, kTile64K4 = 9, kTile128K2 = 10, kTile128Xcd = 11, kNumSched = 12
 };
 
 // Default schedule when none was tuned (per-instance lists): by launch size.
@@ -834,11 +865,20 @@ int gemm_default(int count, int rt16) {
 template <typename TS, typename TO, typename TX, typename TY>
 void gemm_launch(smpm_handle *H, int sched, const GWork *w, int count, const int2 *units, int nunits, const TX *x,
                  int vslot, const double *scale, TY *y, double *hsum, const GState *gs, hipStream_t st,
-                 bool narrow) {
+                 bool narrow, const int2 *units128 = nullptr, int nunits128 = 0) {
   const int rt16 = (H->Nmax + 15) / 16;
   if ((sched == kSplit8Deep || sched == kSplit16Deep) && !narrow) sched = kSplit8;
   auto tiles = [&](int rows) { return (unsigned)((H->Nmax + rows - 1) / rows); };
+  if (sched == kTile128Xcd && !units128) sched = kTile128;
   switch (sched) {
+    case kTile128Xcd:
+      if (narrow)
+        hipLaunchKernelGGL((k_half_gemm_t<TS, TO, TX, TY, 1, 32, 8, 1>), dim3(nunits128), dim3(512), 0, st, w, units128,
+                           H->g_vec, x, vslot, scale, y, hsum, gs);
+      else
+        hipLaunchKernelGGL((k_half_gemm_t<TS, TO, TX, TY, 2, 32, 8, 1>), dim3(nunits128), dim3(512), 0, st, w, units128,
+                           H->g_vec, x, vslot, scale, y, hsum, gs);
+      break;
     case kTile128:
       if (narrow)
         hipLaunchKernelGGL((k_half_gemm_t<TS, TO, TX, TY, 1, 32, 8, 1>), dim3(count, tiles(128)), dim3(512), 0, st, w,
@@ -919,7 +959,8 @@ void gemv_ts(smpm_handle *H, int op, const TX *x, int vslot, const double *scale
       const int prec = sizeof(TS) == 8 ? 0 : (sizeof(TS) == 4 ? 1 : 2);
       const int sched = inst < 0 ? H->sched[op][prec] : gemm_default(count, (H->Nmax + 15) / 16);
       gemm_launch<TS, TO, TX, TY>(H, sched, w, count, inst < 0 ? H->u_all[op] : nullptr, H->n_u_all[op], x, vslot,
-                                  scale, y, hsum, gs, st, H->g_maxv[op] <= 16);
+                                  scale, y, hsum, gs, st, H->g_maxv[op] <= 16,
+                                  inst < 0 ? H->u128_all[op] : nullptr, H->n_u128_all[op]);
     }
   }
   // halves with their own block: streaming kernel (S or M^-1 only)
@@ -1077,15 +1118,15 @@ void tune_schedules(smpm_handle *H, hipStream_t st) {
           if (pr == 0)
             gemm_launch<double, double, double, double>(H, sc, w, count, u, nu, H->t64, 0, nullptr, H->y64,
                                                         op == 0 ? H->hs : nullptr, nullptr, st,
-                H->g_maxv[op] <= 16);
+                H->g_maxv[op] <= 16, H->u128_all[op], H->n_u128_all[op]);
           else if (pr == 1)
             gemm_launch<float, float, float, float>(H, sc, w, count, u, nu, H->t32, 0, nullptr, H->y32,
                                                     op == 0 ? H->hs : nullptr, nullptr, st,
-                H->g_maxv[op] <= 16);
+                H->g_maxv[op] <= 16, H->u128_all[op], H->n_u128_all[op]);
           else
             gemm_launch<_Float16, float, float, float>(H, sc, w, count, u, nu, H->t32, 0, nullptr, H->y32,
                                                        op == 0 ? H->hs : nullptr, nullptr, st,
-                H->g_maxv[op] <= 16);
+                H->g_maxv[op] <= 16, H->u128_all[op], H->n_u128_all[op]);
         });
     }
     if (H->use_ba)   // the Schur right-hand side GEMM (FP64 only)
@@ -1157,7 +1198,7 @@ void tune_schedules(smpm_handle *H, hipStream_t st) {
 }
 
 // Schedules of the handle's GEMM lists, timed at setup (or by size).  The
-// environment variables SMPM_GEMM_SCHED = 0..10 and SMPM_ELEM_SCHED = 1..5 then
+// environment variables SMPM_GEMM_SCHED = 0..11 and SMPM_ELEM_SCHED = 1..5 then
 // pin every shared-block matvec list (split K over 16 or 8 waves, LDS-staged
 // XCD-ordered or plain, with 32- or 64-value chunks) or every element-interior
 // list (split K, LDS-staged XCD-ordered, plain, 32-row or 16-row K-split
