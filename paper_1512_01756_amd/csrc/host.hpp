@@ -125,6 +125,10 @@ struct DenseBackend {
   std::function<void(int ncl, int n, int mz, const double *const *G, const double *lo, const double *up,
                      const double *const *betaW, const double *const *betaE, double *const *Wq)>
       strip_schur;
+  // Starts the back end's stream and library handles and loads the library
+  // kernels the steps above use, so that the first step does not pay for
+  // them; meant for a worker thread while the host steps run.  Never throws.
+  std::function<void()> warm;
 };
 
 struct SetupOptions {

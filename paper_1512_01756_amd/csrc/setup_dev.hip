@@ -113,6 +113,27 @@ struct DeviceDense {
     if (st) (void)hipStreamDestroy(st);
   }
 
+  // The stream, the rocBLAS handle and the solver kernels, ready before the
+  // first step: a 2 x 2 factorization, inverse and product on the device.
+  void warm() {
+    try {
+      std::lock_guard<std::mutex> lk(mu);
+      ensure();
+      DBuf<double> A(8), C(4);
+      DBuf<rocblas_int> ipiv(4), info(2);
+      const double h[8] = {2, 1, 1, 3, 2, 1, 1, 3};
+      hcheck(hipMemcpyAsync(A.p, h, sizeof(h), hipMemcpyHostToDevice, st), "upload");
+      rcheck(rocsolver_dgetrf_strided_batched(h_(), 2, 2, A.p, 2, 4, ipiv.p, 2, info.p, 2), "getrf");
+      rcheck(rocsolver_dgetri_strided_batched(h_(), 2, A.p, 2, 4, ipiv.p, 2, info.p, 2), "getri");
+      const double one = 1.0, zero = 0.0;
+      rcheck(rocblas_dgemm(h_(), rocblas_operation_none, rocblas_operation_none, 2, 2, 2, &one, A.p, 2, A.p + 4, 2,
+                           &zero, C.p, 2), "gemm");
+      hcheck(hipStreamSynchronize(st), "warm");
+    } catch (...) {
+    }
+  }
+  rocblas_handle h_() const { return h; }
+
   // Row-major A is column-major A^T, and inv(A^T) = inv(A)^T: inverting the
   // column-major view in place leaves inv(A) in the row-major layout.
   void invert(int n, int count, double *const *mats) {
@@ -392,6 +413,7 @@ DeviceDense *device_dense_create(bool always) {
     return dd->tri_factor(d, N, Td, Lo, Up);
   };
   dd->be.tri_solve = [dd](void *f, double *v) { dd->tri_solve(f, v); };
+  dd->be.warm = [dd] { dd->warm(); };
   dd->be.tri_free = [dd](void *f) {
     std::lock_guard<std::mutex> lk(dd->mu);
     (void)hipSetDevice(dd->dev);

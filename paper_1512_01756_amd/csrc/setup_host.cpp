@@ -445,6 +445,9 @@ static double norm2(const std::vector<double> &v) {
 // transfers and the library start-up cost more than the host threads take
 // (measured on the c2 and c3 grids).
 constexpr double kDeviceWork = 2e10;
+// Batches of inverses: from 5e9 flops per host thread on (the c3 block-Jacobi
+// blocks, 128 of 832 x 832, take 0.30 s there against 0.60 s on 16 threads).
+constexpr double kDeviceInvertWork = 5e9;
 // Interfaces from which the u_S elimination goes to the device back end (its
 // cyclic reduction is log2(d) levels of batched calls).
 constexpr int kDeviceInterfaces = 16;
@@ -457,7 +460,7 @@ static bool invert_many(const SetupOptions &opt, int n, const std::vector<double
   if (mats.empty()) return false;
   const int threads = std::max(1, std::min<int>((int)mats.size(), opt.threads > 0 ? opt.threads : default_threads()));
   const double per_thread = 2.0 * (double)n * n * n * (double)mats.size() / threads;
-  if (opt.dense && opt.dense->invert && (per_thread >= kDeviceWork || opt.dense->always)) {
+  if (opt.dense && opt.dense->invert && (per_thread >= kDeviceInvertWork || opt.dense->always)) {
     opt.dense->invert(n, (int)mats.size(), mats.data());
     return true;
   }

@@ -9,6 +9,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <future>
 #include <map>
 #include <memory>
 #include <mutex>
@@ -1769,6 +1770,20 @@ smpm_status setup_common(const smpm_grid *grids, const double *k, int nsys, bool
   std::unique_ptr<DeviceDense, void (*)(DeviceDense *)> dense_null(
       dense ? device_dense_create((H->opts.flags & SMPM_FLAG_DEVICE_SETUP) != 0) : nullptr, device_dense_destroy);
   so.dense_null = device_dense_backend(dense_null.get());
+  // Grids with 16 interfaces or more reach the back ends (the u_S
+  // elimination, then the large batches): their start-up runs on worker
+  // threads beside the host steps.  Declared after the back ends, so the
+  // futures are joined before those are destroyed.
+  bool wide = false, any_singular = false;
+  for (int i = 0; i < nsys; ++i) {
+    const smpm_grid &g = one_grid ? grids[0] : grids[i];
+    wide = wide || g.mx - 1 >= 16;
+    any_singular = any_singular || k[i] == 0.0;
+  }
+  std::future<void> warm_dense, warm_null;
+  if (wide && so.dense && so.dense->warm) warm_dense = std::async(std::launch::async, so.dense->warm);
+  if (wide && any_singular && so.dense_null && so.dense_null->warm)
+    warm_null = std::async(std::launch::async, so.dense_null->warm);
   parallel_for(nsys, nsys > 1 ? 0 : 1, [&](int i) {
     const smpm_grid &g = one_grid ? grids[0] : grids[i];
     try {
