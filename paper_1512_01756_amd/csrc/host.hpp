@@ -126,9 +126,12 @@ struct DenseBackend {
                      const double *const *betaW, const double *const *betaE, double *const *Wq)>
       strip_schur;
   // Starts the back end's stream and library handles and loads the library
-  // kernels the steps above use, so that the first step does not pay for
-  // them; meant for a worker thread while the host steps run.  Never throws.
-  std::function<void()> warm;
+  // kernels the steps above use (the strip solves of strips of m_z elements
+  // of order n - 1, if n > 0; inverses of inv_n x inv_n matrices, if
+  // inv_n > 0; the block-tridiagonal elimination with N-row halves, if
+  // tri_N > 0), so that the first step does not pay for them; meant for a
+  // worker thread while the host steps run.  Never throws.
+  std::function<void(int n, int mz, int inv_n, int tri_N)> warm;
 };
 
 struct SetupOptions {

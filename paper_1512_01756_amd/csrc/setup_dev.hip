@@ -113,26 +113,50 @@ struct DeviceDense {
     if (st) (void)hipStreamDestroy(st);
   }
 
-  // The stream, the rocBLAS handle and the solver kernels, ready before the
-  // first step: a 2 x 2 factorization, inverse and product on the device.
-  void warm() {
+  // The stream, the rocBLAS handle and the library kernels, ready before
+  // the first step: the first call of a rocSOLVER or rocBLAS routine at a
+  // new size class loads its kernels (0.15 s and more each), so the steps
+  // run once on small stand-ins of their real sizes (the strip solves of one
+  // class of zeros; two inverses of 2 x 2 and of inv_n x inv_n; the
+  // elimination over four interfaces of N-row halves and one solve).
+  void warm(int n, int mz, int inv_n, int tri_N) {
     try {
-      std::lock_guard<std::mutex> lk(mu);
-      ensure();
-      DBuf<double> A(8), C(4);
-      DBuf<rocblas_int> ipiv(4), info(2);
-      const double h[8] = {2, 1, 1, 3, 2, 1, 1, 3};
-      hcheck(hipMemcpyAsync(A.p, h, sizeof(h), hipMemcpyHostToDevice, st), "upload");
-      rcheck(rocsolver_dgetrf_strided_batched(h_(), 2, 2, A.p, 2, 4, ipiv.p, 2, info.p, 2), "getrf");
-      rcheck(rocsolver_dgetri_strided_batched(h_(), 2, A.p, 2, 4, ipiv.p, 2, info.p, 2), "getri");
-      const double one = 1.0, zero = 0.0;
-      rcheck(rocblas_dgemm(h_(), rocblas_operation_none, rocblas_operation_none, 2, 2, 2, &one, A.p, 2, A.p + 4, 2,
-                           &zero, C.p, 2), "gemm");
-      hcheck(hipStreamSynchronize(st), "warm");
+      {
+        std::lock_guard<std::mutex> lk(mu);
+        ensure();
+      }
+      if (n > 0 && mz > 0) {   // one strip class of zeros
+        const int n2 = n * n, N = n * mz;
+        std::vector<double> G((size_t)mz * n2 * n2, 0.0), lo((size_t)mz * n, 0.0), up((size_t)mz * n, 0.0),
+            bw(n, 0.0), bev(n, 0.0), Wq(4 * (size_t)N * N);
+        const double *Gp[1] = {G.data()}, *bwp[1] = {bw.data()}, *bep[1] = {bev.data()};
+        double *Wp[4] = {Wq.data(), Wq.data() + (size_t)N * N, Wq.data() + 2 * (size_t)N * N,
+                         Wq.data() + 3 * (size_t)N * N};
+        strip_schur(1, n, mz, Gp, lo.data(), up.data(), bwp, bep, Wp);
+      }
+      for (const int n : {2, inv_n}) {
+        if (n <= 0) continue;
+        std::vector<double> a(2 * (size_t)n * n, 0.0);
+        for (int q = 0; q < 2; ++q)
+          for (int i = 0; i < n; ++i) a[(size_t)q * n * n + (size_t)i * n + i] = 2.0 + q;
+        double *mats[2] = {a.data(), a.data() + (size_t)n * n};
+        invert(n, 2, mats);
+      }
+      if (tri_N > 0) {
+        const int d = 4, M = 2 * tri_N;
+        std::vector<double> Td((size_t)d * M * M, 0.0), Lo((size_t)d * tri_N * tri_N, 0.0),
+            Up((size_t)d * tri_N * tri_N, 0.0), v((size_t)d * M, 1.0);
+        for (int q = 0; q < d; ++q)
+          for (int i = 0; i < M; ++i) Td[(size_t)q * M * M + (size_t)i * M + i] = 2.0;
+        void *f = tri_factor(d, tri_N, Td.data(), Lo.data(), Up.data());
+        tri_solve(f, v.data());
+        std::lock_guard<std::mutex> lk(mu);
+        (void)hipSetDevice(dev);
+        delete static_cast<TriFact *>(f);
+      }
     } catch (...) {
     }
   }
-  rocblas_handle h_() const { return h; }
 
   // Row-major A is column-major A^T, and inv(A^T) = inv(A)^T: inverting the
   // column-major view in place leaves inv(A) in the row-major layout.
@@ -413,7 +437,7 @@ DeviceDense *device_dense_create(bool always) {
     return dd->tri_factor(d, N, Td, Lo, Up);
   };
   dd->be.tri_solve = [dd](void *f, double *v) { dd->tri_solve(f, v); };
-  dd->be.warm = [dd] { dd->warm(); };
+  dd->be.warm = [dd](int n, int mz, int inv_n, int tri_N) { dd->warm(n, mz, inv_n, tri_N); };
   dd->be.tri_free = [dd](void *f) {
     std::lock_guard<std::mutex> lk(dd->mu);
     (void)hipSetDevice(dd->dev);

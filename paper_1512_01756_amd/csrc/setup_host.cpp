@@ -165,7 +165,10 @@ static void factor_class(const System &s, const GLL &g, StripClass &cl) {
 // goes to the device back end when it is large (invert_many).
 static bool invert_many(const SetupOptions &opt, int n, const std::vector<double *> &mats);
 
-static void element_woodbury_all(System &s, const GLL &g, const SetupOptions &opt) {
+// Returns the setup_device bit of the inverses that ran on the device back end
+// (16) or 0; writes only the classes' Dinv and Kinv.
+static int element_woodbury_all(System &s, const GLL &g, const SetupOptions &opt) {
+  int dev = 0;
   const int n = s.n, n2 = s.n2, mz = s.mz;
   const int nq = 2 * n * (mz - 1);
   const int ncl = (int)s.classes.size();
@@ -181,9 +184,9 @@ static void element_woodbury_all(System &s, const GLL &g, const SetupOptions &op
     element_diag_block(s, g, cl.hx, s.zb[e + 1] - s.zb[e], cl.west_if, cl.east_if, e > 0, e < mz - 1, Dg);
     std::memcpy(mats[q], Dg.data(), sizeof(double) * n2 * n2);
   });
-  if (invert_many(opt, n2, mats)) s.dev_steps |= 16;
+  if (invert_many(opt, n2, mats)) dev = 16;
   for (StripClass &cl : s.classes) cl.Kinv.assign((size_t)nq * nq, 0.0);
-  if (nq == 0) return;
+  if (nq == 0) return dev;
   // column (interface i, part p, t): P puts a unit at element e_c, local l_c
   parallel_for(ncl, opt.threads, [&](int c) {
     StripClass &cl = s.classes[c];
@@ -218,7 +221,8 @@ static void element_woodbury_all(System &s, const GLL &g, const SetupOptions &op
   });
   std::vector<double *> kmats(ncl);
   for (int c = 0; c < ncl; ++c) kmats[c] = s.classes[c].Kinv.data();
-  if (invert_many(opt, nq, kmats)) s.dev_steps |= 16;
+  if (invert_many(opt, nq, kmats)) dev = 16;
+  return dev;
 }
 
 void strip_solve_woodbury(const System &s, const StripClass &cl, double *x) {
@@ -758,8 +762,20 @@ void build_system(System &s, int mx, int mz, int order, const double *xb, const 
     if (!dev_w) class_schur_blocks(s, s.classes[c]);
   });
   timer.lap(dev_w ? "strip factorizations" : "strip factorizations, W");
-  element_woodbury_all(s, g, opt);
-  timer.lap("element inverses");
+  // The element and capacitance inverses (Dinv, Kinv) serve the interior
+  // elimination of the solve only: with the host threads to itself, the
+  // setup runs them on a task of their own beside the W blocks' device
+  // solves and the block-Jacobi step, and joins it at the end.  The task
+  // writes only the classes' Dinv and Kinv, which nothing below reads.
+  std::future<int> elem_task;
+  SetupOptions eopt = opt;   // half the host threads: the rest drive the device steps and their copies
+  eopt.threads = std::max(1, (opt.threads > 0 ? opt.threads : default_threads()) / 2);
+  if (opt.threads != 1) {
+    elem_task = std::async(std::launch::async, [&s, &g, &eopt] { return element_woodbury_all(s, g, eopt); });
+  } else {
+    s.dev_steps |= element_woodbury_all(s, g, opt);
+    timer.lap("element inverses");
+  }
   if (dev_w) {
     std::vector<const double *> Gp(ncl), bw(ncl), be(ncl);
     std::vector<double *> Wp(4 * ncl);
@@ -834,13 +850,23 @@ void build_system(System &s, int mx, int mz, int order, const double *xb, const 
     mblock_uid[b] = it->second;
   }
   const int nMu = (int)mfirst.size();
-  std::vector<std::vector<double>> Minv(nMu);
+  // A full block (4 halves, K = 4N) is assembled and inverted in place in
+  // Mblk, whose four N x 4N chunks of unique block u are that block's K x K
+  // row-major matrix; a narrower last block goes through a buffer.
+  s.nM = nMu * 4;
+  s.Mblk.assign((size_t)s.nM * N * 4 * N, 0.0);
+  std::vector<std::vector<double>> narrow(nMu);
+  std::vector<double *> Mptr(nMu);
   parallel_for(nMu, opt.threads, [&](int u) {   // assemble; inverted below
     const int b = mfirst[u];
     const int h0 = 4 * b;
     const int nhb = std::min(4, s.nh - h0);
     const int K = nhb * N;
-    std::vector<double> Mb((size_t)K * K, 0.0);
+    double *Mb = &s.Mblk[(size_t)u * 16 * N * N];
+    if (nhb < 4) {
+      narrow[u].assign((size_t)K * K, 0.0);
+      Mb = narrow[u].data();
+    }
     for (int a = 0; a < K; ++a) Mb[(size_t)a * K + a] = 1.0;
     for (int q = 0; q < nhb; ++q) {
       const int h = h0 + q;
@@ -853,13 +879,13 @@ void build_system(System &s, int mx, int mz, int order, const double *xb, const 
           for (int c = 0; c < N; ++c) Mb[(size_t)(q * N + i) * K + lc * N + c] += W[(size_t)i * 2 * N + p * N + c];
       }
     }
-    Minv[u] = std::move(Mb);
+    Mptr[u] = Mb;
   });
   {
     std::map<int, std::vector<double *>> byK;   // the last block may be narrower
     for (int u = 0; u < nMu; ++u) {
       const int K = std::min(4, s.nh - 4 * mfirst[u]) * N;
-      byK[K].push_back(Minv[u].data());
+      byK[K].push_back(Mptr[u]);
     }
     try {
       for (auto &kv : byK)
@@ -868,15 +894,14 @@ void build_system(System &s, int mx, int mz, int order, const double *xb, const 
       throw std::domain_error("singular block-Jacobi block");
     }
   }
-  s.nM = nMu * 4;
-  s.Mblk.assign((size_t)s.nM * N * 4 * N, 0.0);
   for (int u = 0; u < nMu; ++u) {
-    const int b = mfirst[u];
-    const int nhb = std::min(4, s.nh - 4 * b);
+    if (narrow[u].empty()) continue;
+    const int nhb = std::min(4, s.nh - 4 * mfirst[u]);
     const int K = nhb * N;
     for (int q = 0; q < nhb; ++q)
       for (int i = 0; i < N; ++i)
-        std::memcpy(&s.Mblk[((size_t)(u * 4 + q) * N + i) * 4 * N], &Minv[u][(size_t)(q * N + i) * K], sizeof(double) * K);
+        std::memcpy(&s.Mblk[((size_t)(u * 4 + q) * N + i) * 4 * N], &narrow[u][(size_t)(q * N + i) * K],
+                    sizeof(double) * K);
   }
   for (int b = 0; b < nblocks; ++b) {
     const int h0 = 4 * b;
@@ -1033,6 +1058,10 @@ void build_system(System &s, int mx, int mz, int order, const double *xb, const 
     if (sl < 0) for (auto &a : uL) a = -a;
     s.uL = uL;
     timer.lap("u_L");
+  }
+  if (elem_task.valid()) {
+    s.dev_steps |= elem_task.get();
+    timer.lap("element inverses (the wait)");
   }
 }
 

@@ -1060,18 +1060,18 @@ void ainv(smpm_handle *H, const double *src, double *dst, hipStream_t st, int in
 // Setup-time autotuning of the GEMM schedules: every candidate schedule of
 // every batched list is timed with HIP events on zeroed operands and the
 // fastest is kept for the handle's lifetime.  The candidates are timed in
-// three interleaved rounds of 1 warm-up and 10 timed launches each, and each
+// two interleaved rounds of 1 warm-up and 6 timed launches each, and each
 // keeps its best round: clock ramps and cold caches then hit every candidate
 // alike, not the first one timed.  Without tuning, schedules follow the
 // launch size.
 template <typename F>
 int fastest(hipStream_t st, hipEvent_t e0, hipEvent_t e1, int ncand, F &&fn) {
   std::vector<float> best(ncand, 1e30f);
-  for (int round = 0; round < 3; ++round)
+  for (int round = 0; round < 2; ++round)
     for (int c = 0; c < ncand; ++c) {
       fn(c);
       HIPCHECK(hipEventRecord(e0, st));
-      for (int r = 0; r < 10; ++r) fn(c);
+      for (int r = 0; r < 6; ++r) fn(c);
       HIPCHECK(hipEventRecord(e1, st));
       HIPCHECK(hipEventSynchronize(e1));
       float ms = 0.f;
@@ -1771,19 +1771,24 @@ smpm_status setup_common(const smpm_grid *grids, const double *k, int nsys, bool
       dense ? device_dense_create((H->opts.flags & SMPM_FLAG_DEVICE_SETUP) != 0) : nullptr, device_dense_destroy);
   so.dense_null = device_dense_backend(dense_null.get());
   // Grids with 16 interfaces or more reach the back ends (the u_S
-  // elimination, then the large batches): their start-up runs on worker
-  // threads beside the host steps.  Declared after the back ends, so the
-  // futures are joined before those are destroyed.
+  // elimination, then the large batches of one system): their start-up
+  // runs on worker threads beside the host steps.  Batches of systems build
+  // on one host thread each, whose blocks stay small, so there only the u_S
+  // back end starts early.  Declared after the back ends, so the futures are
+  // joined before those are destroyed.
   bool wide = false, any_singular = false;
+  int nmax = 0;   // largest N = (order + 1) m_z
   for (int i = 0; i < nsys; ++i) {
     const smpm_grid &g = one_grid ? grids[0] : grids[i];
     wide = wide || g.mx - 1 >= 16;
     any_singular = any_singular || k[i] == 0.0;
+    nmax = std::max(nmax, (g.order + 1) * g.mz);
   }
   std::future<void> warm_dense, warm_null;
-  if (wide && so.dense && so.dense->warm) warm_dense = std::async(std::launch::async, so.dense->warm);
+  if (wide && nsys == 1 && so.dense && so.dense->warm)   // the block-Jacobi blocks are 4 N square
+    warm_dense = std::async(std::launch::async, so.dense->warm, grids[0].order + 1, grids[0].mz, 4 * nmax, 0);
   if (wide && any_singular && so.dense_null && so.dense_null->warm)
-    warm_null = std::async(std::launch::async, so.dense_null->warm);
+    warm_null = std::async(std::launch::async, so.dense_null->warm, 0, 0, 0, nmax);
   parallel_for(nsys, nsys > 1 ? 0 : 1, [&](int i) {
     const smpm_grid &g = one_grid ? grids[0] : grids[i];
     try {
