@@ -2292,22 +2292,42 @@ __global__ __launch_bounds__(256) void k_fft_y_pack(const double *__restrict__ i
   }
 }
 
-// A length-R DFT in registers (R a power of two, all indices fixed at
+// W_16^m = exp(-2 pi i m / 16), m < 8, correctly rounded (W_{2h}^k = W_16^{8k/h}):
+// the butterflies of a length-R DFT, R <= 16, take their twiddles as
+// constants, exact for m = 0 (1) and m = 4 (-i).
+__device__ constexpr double w16re(int m) {
+  return m == 0 ? 1.0 : m == 1 ? 0.9238795325112867 : m == 2 ? 0.7071067811865476 : m == 3 ? 0.3826834323650898
+       : m == 4 ? 0.0 : m == 5 ? -0.3826834323650898 : m == 6 ? -0.7071067811865476 : -0.9238795325112867;
+}
+__device__ constexpr double w16im(int m) {
+  return m == 0 ? 0.0 : m == 1 ? -0.3826834323650898 : m == 2 ? -0.7071067811865476 : m == 3 ? -0.9238795325112867
+       : m == 4 ? -1.0 : m == 5 ? -0.9238795325112867 : m == 6 ? -0.7071067811865476 : -0.3826834323650898;
+}
+
+// A length-R DFT in registers (R <= 16 a power of two, all indices fixed at
 // compile time): `a` holds the inputs in bit-reversed order and ends with the
 // outputs in natural order.  Radix-2 decimation in time; the twiddle of span
-// 2h is W_R^k = W_MY^{k R' } with R' = MY / (2 h), read from the staged
-// table tws[k] = W_MY^k, k < MY / 2 (conjugated there for the inverse).
-template <int R, int MY>
-__device__ inline void dft_reg(double2 (&a)[R], const double2 *tws) {
+// 2h is W_{2h}^k = W_16^{8k/h} (conjugated for the inverse).
+template <int R, bool INV>
+__device__ inline void dft_reg(double2 (&a)[R]) {
+  static_assert(R >= 2 && R <= 16 && (R & (R - 1)) == 0, "length 2 .. 16, a power of two");
 #pragma unroll
   for (int h = 1; h < R; h *= 2) {
 #pragma unroll
     for (int g = 0; g < R; g += 2 * h) {
 #pragma unroll
       for (int k = 0; k < h; ++k) {
-        const double2 w = tws[k * (MY / (2 * h))];
+        const int m = k * (8 / h);
         const double2 b = a[g + k + h];
-        const double2 t = make_double2(w.x * b.x - w.y * b.y, w.x * b.y + w.y * b.x);
+        double2 t;
+        if (m == 0) {
+          t = b;
+        } else if (m == 4) {   // -i, or i for the inverse
+          t = INV ? make_double2(-b.y, b.x) : make_double2(b.y, -b.x);
+        } else {
+          const double wr = w16re(m), wi = INV ? -w16im(m) : w16im(m);
+          t = make_double2(wr * b.x - wi * b.y, wr * b.y + wi * b.x);
+        }
         a[g + k + h] = make_double2(a[g + k].x - t.x, a[g + k].y - t.y);
         a[g + k] = make_double2(a[g + k].x + t.x, a[g + k].y + t.y);
       }
@@ -2329,7 +2349,8 @@ __device__ constexpr int brev_c(int j) {
 // the result; after one barrier a thread takes the length-N2 DFT over j2 of
 // one (column, k1).  Two passes through LDS instead of log2(m_y).
 template <int LOGMY, bool INV>
-__global__ __launch_bounds__(256) void k_fft_y_4s(const double *__restrict__ in, double *__restrict__ out,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(INV ? 3 : 4))) void k_fft_y_4s(
+    const double *__restrict__ in, double *__restrict__ out,
                                                   int64_t ncol, const double2 *__restrict__ tw) {
   constexpr int MY = 1 << LOGMY, N1 = 8, N2 = MY / N1, L2 = LOGMY - 3;
   constexpr int CT = kFftPackSlots / MY, CW = 2 * CT, NK = MY / 2 + 1;
@@ -2397,7 +2418,7 @@ __global__ __launch_bounds__(256) void k_fft_y_4s(const double *__restrict__ in,
 #pragma unroll
   for (int q = 0; q < P1; ++q) {
     const int it = threadIdx.x + 256 * q, c = it % CT, j2 = it / CT;
-    dft_reg<N1, MY>(a[q], tws);
+    dft_reg<N1, INV>(a[q]);
     if (it < I1) {
 #pragma unroll
       for (int k1 = 0; k1 < N1; ++k1) {
@@ -2414,7 +2435,7 @@ __global__ __launch_bounds__(256) void k_fft_y_4s(const double *__restrict__ in,
 #pragma unroll
     for (int j2 = 0; j2 < N2; ++j2)
       b[q][brev_c<L2>(j2)] = it < I3 ? fb[(k1 * N2 + j2) * CT + c] : make_double2(0.0, 0.0);
-    dft_reg<N2, MY>(b[q], tws);
+    dft_reg<N2, INV>(b[q]);
   }
   if (INV) {   // z_j at j = k1 + 8 k2: column c in Re, column c + CT in Im
 #pragma unroll
