@@ -228,10 +228,13 @@ def gemm_kernel_name(s, op, dtype):
 # Keyed by (workload, operation, kernel): a run whose setup picked another
 # kernel reports no traffic, and an entry is dropped when its kernel changes.
 KERNEL_TRAFFIC = {
-    ("c2", "schur", "k_half_gemm<double, 8> (split-K, 8 waves)"): 6.495e6,
+    ("c2", "schur", "k_half_gemm<double, 8> (split-K, 8 waves)"): 6.500e6,
+    ("c2", "schur", "k_half_gemm<double, 16> (split-K, 16 waves)"): 6.460e6,
+    ("c2", "schur_bjinv", "k_half_gemm<double, 8> (split-K, 8 waves) over the stored S M^-1 blocks"): 2.173e7,
     ("c2", "schur_bjinv", "k_half_gemm<double, 16> (split-K, 16 waves) over the stored S M^-1 blocks"): 2.170e7,
     ("c3", "schur", "k_half_gemv_stream<double> (distinct blocks)"): 3.568e8,
-    ("c4", "schur", "k_half_gemm_t<double> (LDS-staged, XCD-ordered)"): 9.522e7,
+    ("c4", "schur", "k_half_gemm_t<double> (LDS-staged, XCD-ordered)"): 9.906e7,
+    ("c4", "schur", "k_half_gemm_t<double> (LDS-staged, 128-row tile, cost-ordered XCD-aware)"): 9.800e7,
 }
 
 

@@ -64,7 +64,7 @@ def test_traffic_only_for_the_measured_kernel():
     shared = {"gemm_sched": [1, 1, 1, 1]}
     name = bench.gemm_kernel_name(_Info([shared]), 0, "fp64")
     assert ("c2", "schur", name) in bench.KERNEL_TRAFFIC
-    other = dict(shared, gemm_sched=[0, 0, 0, 0])
+    other = dict(shared, gemm_sched=[3, 3, 3, 3])
     assert ("c2", "schur", bench.gemm_kernel_name(_Info([other]), 0, "fp64")) not in bench.KERNEL_TRAFFIC
     fused = {"fused_sched": [0, 7]}
     name = bench.gemm_kernel_name(_Info([fused]), 2, "fp64") + " over the stored S M^-1 blocks"
