@@ -209,7 +209,8 @@ def gemm_kernel_name(s, op, dtype):
              8: "k_half_gemm_t<{t}> (LDS-staged, 128-row tile)",
              9: "k_half_gemm_t<{t}> (LDS-staged, 64-row tile, K split 4 ways)",
              10: "k_half_gemm_t<{t}> (LDS-staged, 128-row tile, K split 2 ways)",
-             11: "k_half_gemm_t<{t}> (LDS-staged, 128-row tile, cost-ordered XCD-aware)"}
+             11: "k_half_gemm_t<{t}> (LDS-staged, 128-row tile, cost-ordered XCD-aware)",
+             12: "k_half_gemm_t<{t}> (LDS-staged, 128-row tile, cost-ordered XCD-aware, 64-value chunks)"}
     t = "double" if dtype == "fp64" else "float"
     out = set()
     for i in s.info:

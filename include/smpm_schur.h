@@ -178,9 +178,9 @@ typedef struct {
                               lists of at most 16 windows per item, 8 LDS-staged
                               128-row tiles, 9 / 10 64- / 128-row tiles whose 16
                               waves also split K, 11 LDS-staged 128-row tiles in
-                              a cost-ordered XCD-aware order; -1 no shared
-                              blocks).
-                              SMPM_GEMM_SCHED = 0..11 in the environment,
+                              a cost-ordered XCD-aware order, 12 the same with
+                              64 K-values per chunk; -1 no shared blocks).
+                              SMPM_GEMM_SCHED = 0..12 in the environment,
                               read at setup and load, pins them all (tests,
                               experiments) */
   int32_t elem_sched[6];   /* same for the element-interior GEMM lists

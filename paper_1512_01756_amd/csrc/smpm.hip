@@ -850,10 +850,12 @@ void upload(smpm_handle *H, hipStream_t st) {
 // split K four or two ways (shorter MFMA chains per wave).  The staged
 // schedules hold 16 windows per item column group where the items do.
 // kTile128Xcd: the 128-row tile over a cost-ordered XCD-aware unit list
-// (each XCD's tiles costliest first).
+// (each XCD's tiles costliest first); kTile128Xcd64 the same staging 64
+// K-values per chunk.
 enum GemmSched {
   kSplit16 = 0, kSplit8 = 1, kThrXcd = 2, kThrPlain = 3, kThrXcd64 = 4, kThrPlain64 = 5, kSplit8Deep = 6,
-  kSplit16Deep = 7, kTile128 = 8, kTile64K4 = 9, kTile128K2 = 10, kTile128Xcd = 11, kNumSched = 12
+  kSplit16Deep = 7, kTile128 = 8, kTile64K4 = 9, kTile128K2 = 10, kTile128Xcd = 11, kTile128Xcd64 = 12,
+  kNumSched = 13
 };
 
 // Default schedule when none was tuned (per-instance lists): by launch size.
@@ -870,8 +872,16 @@ void gemm_launch(smpm_handle *H, int sched, const GWork *w, int count, const int
   const int rt16 = (H->Nmax + 15) / 16;
   if ((sched == kSplit8Deep || sched == kSplit16Deep) && !narrow) sched = kSplit8;
   auto tiles = [&](int rows) { return (unsigned)((H->Nmax + rows - 1) / rows); };
-  if (sched == kTile128Xcd && !units128) sched = kTile128;
+  if ((sched == kTile128Xcd || sched == kTile128Xcd64) && !units128) sched = kTile128;
   switch (sched) {
+    case kTile128Xcd64:
+      if (narrow)
+        hipLaunchKernelGGL((k_half_gemm_t<TS, TO, TX, TY, 1, 64, 8, 1>), dim3(nunits128), dim3(512), 0, st, w, units128,
+                           H->g_vec, x, vslot, scale, y, hsum, gs);
+      else
+        hipLaunchKernelGGL((k_half_gemm_t<TS, TO, TX, TY, 2, 64, 8, 1>), dim3(nunits128), dim3(512), 0, st, w, units128,
+                           H->g_vec, x, vslot, scale, y, hsum, gs);
+      break;
     case kTile128Xcd:
       if (narrow)
         hipLaunchKernelGGL((k_half_gemm_t<TS, TO, TX, TY, 1, 32, 8, 1>), dim3(nunits128), dim3(512), 0, st, w, units128,
@@ -1199,7 +1209,7 @@ void tune_schedules(smpm_handle *H, hipStream_t st) {
 }
 
 // Schedules of the handle's GEMM lists, timed at setup (or by size).  The
-// environment variables SMPM_GEMM_SCHED = 0..11 and SMPM_ELEM_SCHED = 1..5 then
+// environment variables SMPM_GEMM_SCHED = 0..12 and SMPM_ELEM_SCHED = 1..5 then
 // pin every shared-block matvec list (split K over 16 or 8 waves, LDS-staged
 // XCD-ordered or plain, with 32- or 64-value chunks) or every element-interior
 // list (split K, LDS-staged XCD-ordered, plain, 32-row or 16-row K-split

@@ -291,7 +291,7 @@ def test_element_gemm_schedules_match_oracle(sched, monkeypatch, sched_refs):
         assert _rel(u[m, q], ref.u) <= (ref.bound if m == 0 else 1e-11), (sched, m, q)
 
 
-@pytest.mark.parametrize("sched", [0, 1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 11])
+@pytest.mark.parametrize("sched", [0, 1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 11, 12])
 @pytest.mark.parametrize("precision", [P.FP64, P.FP32_IR])
 def test_shared_block_gemm_schedules_match_oracle(sched, precision, monkeypatch, sched_refs):
     # Every schedule of the shared-block S and M^-1 GEMMs, pinned for all lists
@@ -325,7 +325,7 @@ def tall_ref():
     return _oracle(_tall_problem(), 0, 0, tol=TIGHT)[1]
 
 
-@pytest.mark.parametrize("sched", [0, 2, 6, 8, 9, 10, 11])
+@pytest.mark.parametrize("sched", [0, 2, 6, 8, 9, 10, 11, 12])
 def test_shared_block_gemm_schedules_on_tall_blocks(sched, monkeypatch, tall_ref):
     monkeypatch.setenv("SMPM_GEMM_SCHED", str(sched))
     p = _tall_problem()
