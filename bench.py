@@ -598,7 +598,8 @@ def main():
                                                             forms["fp32_ir"][0].info[0]["fused_sched"][1]],
                            "legend": "0 split-K 16 waves, 1 split-K 8 waves, 2 LDS-staged XCD-ordered, 3 LDS-staged plain; matvec lists: "
                                      "4 / 5 = 2 / 3 with 64-value chunks, 6 / 7 split-K 8 / 16 waves with a wave's K range in "
-                                     "flight, 8 LDS-staged 128-row tiles, 9 / 10 64- / 128-row tiles whose waves also split K; "
+                                     "flight, 8 LDS-staged 128-row tiles, 9 / 10 64- / 128-row tiles whose waves also split K, "
+                                     "11 / 12 128-row tiles in a cost-ordered XCD-aware order with 32- / 64-value chunks; "
                                      "element lists: 4 / 5 LDS-staged 32- / 16-row tiles with K split over the waves; -1 unused; "
                                      "picked by timing at setup"},
         "roofline": main_rl,
