@@ -1987,6 +1987,7 @@ __global__ __launch_bounds__(kBlock) void k_sum_r(const SysDev *__restrict__ sys
   const int i = wk.x, ch = wk.y;
   const InstDev I = ins[i];
   const SysDev &S = sys[I.sys];
+  if (!S.singular) return;   // only the k = 0 gauge needs the sum (k_sub_mean reads it only then)
   double a = 0.0;
   for (int q = 0; q < kChunk / kBlock; ++q) {
     const int64_t e = (int64_t)ch * kChunk + threadIdx.x + q * kBlock;
