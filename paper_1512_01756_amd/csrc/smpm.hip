@@ -1118,6 +1118,22 @@ void tune_schedules(smpm_handle *H, hipStream_t st) {
       HIPCHECK(hipMemsetAsync(H->lam, 0, sizeof(double) * nl, st));
       HIPCHECK(hipMemsetAsync(H->qb, 0, sizeof(double) * nl, st));
     }
+    // A batch's instances converge at different iterations, and most of a
+    // solve's iterations run with a few instances left: there the workgroups
+    // of converged instances exit at once and the cost is the live items'
+    // latency, which ranks the schedules differently.  So on batches of 8
+    // instances or more each candidate is timed twice per launch, with every
+    // instance live and with the first tenth live (a GMRES state written
+    // for the purpose and cleared again below).
+    const bool mixed = H->ninst >= 8;
+    if (mixed) {
+      const int nlive = std::max(1, H->ninst / 10);
+      for (int i = 0; i < H->ninst; ++i) {
+        H->h_gs[i] = GState{};
+        H->h_gs[i].active = i < nlive ? 1 : 0;
+      }
+      HIPCHECK(hipMemcpyAsync(H->gs, H->h_gs, sizeof(GState) * H->ninst, hipMemcpyHostToDevice, st));
+    }
     for (int op = 0; op < 3; ++op) {
       const int count = H->n_g_all[op];
       if (count == 0) continue;
@@ -1126,18 +1142,21 @@ void tune_schedules(smpm_handle *H, hipStream_t st) {
       const int nu = H->n_u_all[op];
       for (int pr = 0; pr < (H->op16 ? 3 : 2); ++pr)
         H->sched[op][pr] = fastest(st, e0, e1, kNumSched, [&](int sc) {
-          if (pr == 0)
-            gemm_launch<double, double, double, double>(H, sc, w, count, u, nu, H->t64, 0, nullptr, H->y64,
-                                                        op == 0 ? H->hs : nullptr, nullptr, st,
-                H->g_maxv[op] <= 16, H->u128_all[op], H->n_u128_all[op]);
-          else if (pr == 1)
-            gemm_launch<float, float, float, float>(H, sc, w, count, u, nu, H->t32, 0, nullptr, H->y32,
-                                                    op == 0 ? H->hs : nullptr, nullptr, st,
-                H->g_maxv[op] <= 16, H->u128_all[op], H->n_u128_all[op]);
-          else
-            gemm_launch<_Float16, float, float, float>(H, sc, w, count, u, nu, H->t32, 0, nullptr, H->y32,
-                                                       op == 0 ? H->hs : nullptr, nullptr, st,
-                H->g_maxv[op] <= 16, H->u128_all[op], H->n_u128_all[op]);
+          for (int pass = 0; pass < (mixed ? 2 : 1); ++pass) {
+            const GState *g = pass == 0 ? nullptr : H->gs;
+            if (pr == 0)
+              gemm_launch<double, double, double, double>(H, sc, w, count, u, nu, H->t64, 0, nullptr, H->y64,
+                                                          op == 0 ? H->hs : nullptr, g, st, H->g_maxv[op] <= 16,
+                                                          H->u128_all[op], H->n_u128_all[op]);
+            else if (pr == 1)
+              gemm_launch<float, float, float, float>(H, sc, w, count, u, nu, H->t32, 0, nullptr, H->y32,
+                                                      op == 0 ? H->hs : nullptr, g, st, H->g_maxv[op] <= 16,
+                                                      H->u128_all[op], H->n_u128_all[op]);
+            else
+              gemm_launch<_Float16, float, float, float>(H, sc, w, count, u, nu, H->t32, 0, nullptr, H->y32,
+                                                         op == 0 ? H->hs : nullptr, g, st, H->g_maxv[op] <= 16,
+                                                         H->u128_all[op], H->n_u128_all[op]);
+          }
         });
     }
     if (H->use_ba)   // the Schur right-hand side GEMM (FP64 only)
@@ -1149,26 +1168,30 @@ void tune_schedules(smpm_handle *H, hipStream_t st) {
     if (H->fused)
       for (int pr = 0; pr < (H->op16 ? 3 : 2); ++pr) {
         // full operator applications (shared-block GEMMs and streamed blocks)
-        auto two = [&](int op, const void *x, void *y) {
+        auto two = [&](int op, const void *x, void *y, const GState *g) {
           if (pr == 0)
             gemv<double, double, double>(H, op, (const double *)x, 0, nullptr, (double *)y, op != 1 ? H->hs : nullptr,
-                                         nullptr, st);
+                                         g, st);
           else
             gemv<float, float, float>(H, op, (const float *)x, 0, nullptr, (float *)y, op != 1 ? H->hs : nullptr,
-                                      nullptr, st, -1, pr == 2);
+                                      g, st, -1, pr == 2);
         };
         const void *x = pr == 0 ? (const void *)H->t64 : (const void *)H->t32;
         void *z = pr == 0 ? (void *)H->z64 : (void *)H->z32;
         void *y = pr == 0 ? (void *)H->y64 : (void *)H->y32;
         H->use_fused[pr] = fastest(st, e0, e1, 2, [&](int c) {
-          if (c == 0) {
-            two(2, x, y);
-          } else {
-            two(1, x, z);
-            two(0, z, y);
+          for (int pass = 0; pass < (mixed ? 2 : 1); ++pass) {   // all live, then the first tenth (above)
+            const GState *g = pass == 0 ? nullptr : H->gs;
+            if (c == 0) {
+              two(2, x, y, g);
+            } else {
+              two(1, x, z, g);
+              two(0, z, y, g);
+            }
           }
         }) == 0;
       }
+    if (mixed) HIPCHECK(hipMemsetAsync(H->gs, 0, sizeof(GState) * H->ninst, st));
     const int cand[5] = {kSplit8, kThrXcd, kThrPlain, kCol32, kCol16};
     for (int k = 0; k < 3; ++k)
       for (int w = 0; w < 2; ++w) {
