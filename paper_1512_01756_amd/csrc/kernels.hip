@@ -1495,6 +1495,7 @@ __global__ __launch_bounds__(256) void k_colgemm_t(const CGItem *__restrict__ it
   const bool alive = arow < it.R, wlive = rg * TR + rw * 16 < it.R;
   const int kq = lane >> 4, cl = lane & 15;
   const int ctl = (it.ccount + 15) >> 4;   // column tiles holding columns
+  const bool narrow = it.ccount <= 4;
   const int K = it.K, ks = it.ksplit, lda = it.lda, agap = it.agap;
   const double *__restrict__ A = it.A;
   const int scol = threadIdx.x / TPC, sj = threadIdx.x % TPC;
@@ -1535,8 +1536,14 @@ __global__ __launch_bounds__(256) void k_colgemm_t(const CGItem *__restrict__ it
     }
     const double *__restrict__ B = Bs[buf];
     // A wave whose 16 rows all lie past the block stages only; an item of at
-    // most 16 columns multiplies one column tile.
-    if (wlive && ctl > 1) {
+    // most 16 columns multiplies one column tile, and one of at most 4 the
+    // 4-block 4 x 4 x 4 MFMA (blocks = the wave's four 4-row groups).
+    if (wlive && narrow) {
+#pragma unroll
+      for (int s = 0; s < SW; ++s)
+        acc[0][0] = __builtin_amdgcn_mfma_f64_4x4x4f64(a[s], B[(4 * (s * KW + kw) + kq) * PITCH + (lane & 3)], acc[0][0],
+                                                       0, 0, 0);
+    } else if (wlive && ctl > 1) {
 #pragma unroll
       for (int s = 0; s < SW; ++s)
 #pragma unroll
@@ -1568,6 +1575,16 @@ __global__ __launch_bounds__(256) void k_colgemm_t(const CGItem *__restrict__ it
       for (int t = 0; t < CT; ++t)
 #pragma unroll
         for (int j = 0; j < 4; ++j) acc[t][j] += red[((((q - 1) * RW + rw) * CT + t) * 4 + j) * 64 + lane];
+  }
+  if (narrow) {   // lane m: row 4 ((m >> 2) & 3) + (m >> 4) of the wave's 16, column m & 3
+    const int ci = lane & 3;
+    const int row = rg * TR + rw * 16 + 4 * ((lane >> 2) & 3) + (lane >> 4);
+    if (ci < it.ccount && row < it.R) {
+      const int64_t y0 = cols[it.cstart + ci].y;
+      if (MODE == 0) yb[y0 + row] = acc[0][0];
+      else yb[y0 + row] -= acc[0][0];
+    }
+    return;
   }
 #pragma unroll
   for (int t = 0; t < CT; ++t) {
