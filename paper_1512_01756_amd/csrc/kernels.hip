@@ -968,6 +968,111 @@ __device__ inline void reduce_coef(const InstDev &I, const double *__restrict__ 
   __syncthreads();
 }
 
+// The second pass's coefficients as reduce_coef forms them from part2, and
+// with them, from the same loads, what the Givens step of the column needs:
+// h[t] = s_t (sum part1_t + sum part2_t), h2sq[t] = (s_t sum part2_t)^2 and
+// the first pass's squared norm sum(partn) (returned in thread 0), summed in
+// the order givens_step sums them.  Every workgroup of the pass forms them
+// while its basis loads are in flight, so the one that arrives last starts
+// its Givens step without another round of loads.
+__device__ inline double reduce_coef_givens(const InstDev &I, const double *__restrict__ part1,
+                                            const double *__restrict__ part2, const double *__restrict__ partn,
+                                            const double *__restrict__ scale, int j, double *coef, double *h,
+                                            double *h2sq, double *lds4) {
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  double nn = 0.0;
+  for (int k = threadIdx.x; k < I.nchunk_x; k += kBlock) nn += partn[I.part_off + k];
+  for (int t = wave; t <= j; t += 8) {   // two columns per reduction pass
+    const int t2 = t + 4;
+    const bool two = t2 <= j;
+    const double *p1 = part1 + I.part_off + (int64_t)t * I.nchunk_x;
+    const double *p2 = part2 + I.part_off + (int64_t)t * I.nchunk_x;
+    const double *q1 = part1 + I.part_off + (int64_t)(two ? t2 : t) * I.nchunk_x;
+    const double *q2 = part2 + I.part_off + (int64_t)(two ? t2 : t) * I.nchunk_x;
+    double a = 0.0, b = 0.0, c = 0.0, d = 0.0;
+    for (int k = lane; k < I.nchunk_x; k += 64) {
+      a += p1[k];
+      b += p2[k];
+      c += q1[k];
+      d += q2[k];
+    }
+    a = wave_sum(a);
+    b = wave_sum(b);
+    c = wave_sum(c);
+    d = wave_sum(d);
+    if (lane == 0) {
+      const double st = scale[I.st_off + t];
+      coef[t] = st * st * b;
+      h[t] = st * (a + b);
+      h2sq[t] = (st * b) * (st * b);
+      if (two) {
+        const double st2 = scale[I.st_off + t2];
+        coef[t2] = st2 * st2 * d;
+        h[t2] = st2 * (c + d);
+        h2sq[t2] = (st2 * d) * (st2 * d);
+      }
+    }
+  }
+  return block_sum(nn, lds4);   // its barriers publish coef, h and h2sq
+}
+
+// The serial part of the Givens step, in thread 0, once h[0 .. j] (and h2sq
+// when pyth), the earlier rotations and nn (thread 0's value) are in place:
+// layout of sh as in givens_step.  r0 and ref: the instance's GMRES state,
+// carried over unchanged.
+__device__ inline void givens_rotate(const InstDev &I, int i, int j, double nn, double *scale, double *__restrict__ R,
+                                     double *__restrict__ cs, double *__restrict__ sn, double *__restrict__ g,
+                                     GState *gs, int maxit, double tol, double *sh, bool pyth, double r0,
+                                     double ref) {
+  if (threadIdx.x == 0) {
+    double *h = sh;
+    const double *cl = sh + maxit + 2, *sl = cl + maxit, *h2sq = sl + maxit;
+    if (pyth) {
+      for (int t = 0; t <= j; ++t) nn -= h2sq[t];
+      nn = nn > 0.0 ? nn : 0.0;
+    }
+    const double beta = sqrt(nn);
+    h[j + 1] = beta;
+    double *gI = g + I.st_off;
+    for (int t = 0; t < j; ++t) {
+      const double a = cl[t] * h[t] + sl[t] * h[t + 1];
+      h[t + 1] = -sl[t] * h[t] + cl[t] * h[t + 1];
+      h[t] = a;
+    }
+    const double den = hypot(h[j], h[j + 1]);
+    const double c = den != 0.0 ? h[j] / den : 1.0;
+    const double s = den != 0.0 ? h[j + 1] / den : 0.0;
+    cs[I.st_off + j] = c;
+    sn[I.st_off + j] = s;
+    h[j] = den;
+    gI[j + 1] = -s * gI[j];
+    gI[j] = c * gI[j];
+    double *Rc = R + I.rr_off + (int64_t)j * maxit;
+    for (int t = 0; t <= j; ++t) Rc[t] = h[t];
+    const double res = fabs(gI[j + 1]);
+    int active = 0, status = 0;
+    if (!isfinite(res) || !isfinite(den)) {
+      status = 3;
+    } else if (res <= tol * ref || beta == 0.0) {
+      status = 1;
+    } else if (j + 1 >= maxit) {
+      status = 2;
+    } else {
+      active = 1;
+      scale[I.st_off + j + 1] = 1.0 / beta;
+    }
+    // field by field: a whole-struct copy is kept in scratch by the compiler
+    for (int m = i; m < i + I.seg_count; ++m) {
+      gs[m].iter = j + 1;
+      gs[m].active = active;
+      gs[m].status = status;
+      gs[m].r0 = r0;
+      gs[m].res = res;
+      gs[m].ref = ref;
+    }
+  }
+}
+
 // One Givens step of instance (segment leader) i at Arnoldi column j: the
 // Hessenberg column h_t = s_t (sum part1 + sum part2), h_{j+1} = ||w|| from
 // the per-chunk partials (or from the segment sums r1, r2, rn), the earlier
@@ -1032,53 +1137,9 @@ __device__ inline void givens_step(const InstDev &I, int i, int j, const double 
     nn = block_sum(nn, lds4);
   }
   __syncthreads();
-  if (threadIdx.x == 0) {
-    if (pyth) {
-      for (int t = 0; t <= j; ++t) nn -= h2sq[t];
-      nn = nn > 0.0 ? nn : 0.0;
-    }
-    const double beta = sqrt(nn);
-    h[j + 1] = beta;
-    double *gI = g + I.st_off;
-    for (int t = 0; t < j; ++t) {
-      const double a = cl[t] * h[t] + sl[t] * h[t + 1];
-      h[t + 1] = -sl[t] * h[t] + cl[t] * h[t + 1];
-      h[t] = a;
-    }
-    const double den = hypot(h[j], h[j + 1]);
-    const double c = den != 0.0 ? h[j] / den : 1.0;
-    const double s = den != 0.0 ? h[j + 1] / den : 0.0;
-    cs[I.st_off + j] = c;
-    sn[I.st_off + j] = s;
-    h[j] = den;
-    gI[j + 1] = -s * gI[j];
-    gI[j] = c * gI[j];
-    double *Rc = R + I.rr_off + (int64_t)j * maxit;
-    for (int t = 0; t <= j; ++t) Rc[t] = h[t];
-    const double res = fabs(gI[j + 1]);
-    const double r0 = gs[i].r0, ref = gs[i].ref;
-    int active = 0, status = 0;
-    if (!isfinite(res) || !isfinite(den)) {
-      status = 3;
-    } else if (res <= tol * ref || beta == 0.0) {
-      status = 1;
-    } else if (j + 1 >= maxit) {
-      status = 2;
-    } else {
-      active = 1;
-      scale[I.st_off + j + 1] = 1.0 / beta;
-    }
-    // field by field: a whole-struct copy is kept in scratch by the compiler
-    for (int m = i; m < i + I.seg_count; ++m) {
-      gs[m].iter = j + 1;
-      gs[m].active = active;
-      gs[m].status = status;
-      gs[m].r0 = r0;
-      gs[m].res = res;
-      gs[m].ref = ref;
-    }
-  }
+  givens_rotate(I, i, j, nn, scale, R, cs, sn, g, gs, maxit, tol, sh, pyth, gs[i].r0, gs[i].ref);
 }
+
 
 // Classical Gram-Schmidt pass: w -= sum_t coef_t V_t (coef from the partials
 // of the previous pass); then either the next pass's partial dots
@@ -1209,6 +1270,7 @@ __global__ __launch_bounds__(kBlock) void k_axpy_givens(
   __shared__ double lds4[4];
   __shared__ int last_s;
   double *coef = dyn, *sh = dyn + maxit + 1;
+  double *hcol = sh, *cl = sh + maxit + 2, *sl = cl + maxit, *h2sq = sl + maxit;
   const int2 wk = work[blockIdx.x];
   const int i = wk.x, ch = wk.y;
   const InstDev I = ins[i];
@@ -1222,10 +1284,15 @@ __global__ __launch_bounds__(kBlock) void k_axpy_givens(
   const bool ina = ea < kS, inb = eb < kS;
   TV *w = V + I.v_off + (int64_t)(j + 1) * kS;
   double a0 = ina ? (double)w[ea] : 0.0, a1 = inb ? (double)w[eb] : 0.0;
+  for (int t = threadIdx.x; t < j; t += kBlock) {   // the earlier rotations, for the Givens step
+    cl[t] = cs[I.st_off + t];
+    sl[t] = sn[I.st_off + t];
+  }
+  double nn;
   if (RB && j < kBasisRegs) {   // the basis loads overlap the reduction of the partials
     double va[kBasisRegs], vb[kBasisRegs];
     prefetch_basis(V + I.v_off, kS, ea, ina, inb, j, va, vb);
-    reduce_coef(I, part2, scale, j, coef);
+    nn = reduce_coef_givens(I, part1, part2, partn, scale, j, coef, hcol, h2sq, lds4);
 #pragma unroll
     for (int t = 0; t < kBasisRegs; ++t) {
       if (t <= j) {
@@ -1235,7 +1302,7 @@ __global__ __launch_bounds__(kBlock) void k_axpy_givens(
       }
     }
   } else {
-    reduce_coef(I, part2, scale, j, coef);
+    nn = reduce_coef_givens(I, part1, part2, partn, scale, j, coef, hcol, h2sq, lds4);
     const TV *Vt = V + I.v_off + ea;
 #pragma unroll 4
     for (int t = 0; t <= j; ++t, Vt += kS) {
@@ -1254,8 +1321,7 @@ __global__ __launch_bounds__(kBlock) void k_axpy_givens(
   }
   __syncthreads();
   if (!last_s) return;
-  givens_step(I, i, j, part1, part2, partn, nullptr, nullptr, nullptr, scale, R, cs, sn, g, gs, maxit, tol, sh, lds4,
-              true);
+  givens_rotate(I, i, j, nn, scale, R, cs, sn, g, gs, maxit, tol, sh, true, G.r0, G.ref);
 }
 
 // Segment-wide sums of per-chunk partials, for instances that share one
