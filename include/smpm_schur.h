@@ -211,6 +211,16 @@ typedef struct {
   int32_t strip_classes, elem_unique;
   int32_t fused_sched[3];  /* schedule of the S M^-1 GEMM list (FP64, FP32, FP16
                               storage; -1 none), numbered as gemm_sched */
+  int32_t rhs_gemm[2];     /* the Schur right-hand side b_S = (B A^-1) F~ as one
+                              GEMM over the strips (grids whose strips share
+                              classes): its schedule, numbered as gemm_sched, and
+                              the windows per item of the list it runs on (32, or
+                              16 for the narrow schedules); -1 -1 when b_S comes
+                              from element solves.  SMPM_RHS_GEMM = "s,l" in the
+                              environment (s = 0..12; l = 0 for the 32-window
+                              list, 1 for the 16-window one, which exists only
+                              when some item has more than 16 windows), read at
+                              setup and load, pins both (tests, experiments) */
 } smpm_info;
 
 typedef struct smpm_handle smpm_handle;

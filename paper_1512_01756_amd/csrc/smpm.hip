@@ -215,8 +215,13 @@ struct smpm_handle {
   // B A^-1 per strip class (the Schur right-hand side as one GEMM), for
   // handles whose systems all share strip classes
   bool use_ba = false;
-  const GWork *g_ba = nullptr;
-  int n_ba = 0, ba_maxv = 0, ba_sched = 0;
+  // the Schur right-hand side GEMM over the strips, in items of up to
+  // kGemmVecs windows (list 0) and of up to 16 (list 1, for the narrow
+  // schedules; empty when list 0 has no wider item); the tuner picks the
+  // list and the schedule
+  const GWork *g_bal[2] = {nullptr, nullptr};
+  int n_bal[2] = {0, 0}, bal_maxv[2] = {0, 0};
+  int ba_list = 0, ba_sched = 0;
   std::vector<int> g_start[3], g_cnt[3];
   HWork *w_S1 = nullptr, *w_M1 = nullptr;   // single items (streamed blocks)
   int n_S1 = 0, n_M1 = 0;
@@ -736,7 +741,7 @@ void upload(smpm_handle *H, hipStream_t st) {
     // solves of A^-1 and the B row functionals).
     H->use_ba = H->fused;
     if (H->use_ba) {
-      std::vector<GWork> ba;
+      std::vector<GWork> ba, ba16;
       for (int si = 0; si < (int)H->sys.size(); ++si) {
         const System &s = H->sys[si];
         const SysDev &d = H->h_sys[si];
@@ -753,6 +758,9 @@ void upload(smpm_handle *H, hipStream_t st) {
             if (j >= 1) byblk[2 * cls].push_back(make_int2(inst, 2 * j));           // west rows -> half 2 (j - 1)
             if (j + 1 < s.mx) byblk[2 * cls + 1].push_back(make_int2(inst, 2 * j + 1));   // east rows -> half 2 j + 1
           }
+        // items of up to kGemmVecs windows, and of up to 16 (the narrow
+        // schedules: one column tile, or the whole K range in flight)
+        for (int cap : {kGemmVecs, 16})
         for (auto &kv : byblk) {
           const std::vector<int2> &vecs = kv.second;
           for (size_t a = 0; a < vecs.size();) {
@@ -761,7 +769,7 @@ void upload(smpm_handle *H, hipStream_t st) {
             w.n = s.n;
             w.N = N; w.Np = d.Np; w.K = K; w.kS = s.r; w.ident = 0;
             w.vstart = (int)gv.size();
-            w.vcount = (int)std::min<size_t>(kGemmVecs, vecs.size() - a);
+            w.vcount = (int)std::min<size_t>(cap, vecs.size() - a);
             for (int qq = 0; qq < w.vcount; ++qq) {
               const int inst = vecs[a + qq].x, j = vecs[a + qq].y / 2, side = vecs[a + qq].y % 2;
               const int h = side == 0 ? 2 * (j - 1) : 2 * j + 1;
@@ -776,14 +784,19 @@ void upload(smpm_handle *H, hipStream_t st) {
               e.st_off = (int)I.st_off;
               gv.push_back(e);
             }
-            ba.push_back(w);
+            (cap == 16 ? ba16 : ba).push_back(w);
             a += w.vcount;
           }
         }
       }
-      H->g_ba = dupload(own, ba, st);
-      H->n_ba = (int)ba.size();
-      for (const GWork &w : ba) H->ba_maxv = std::max(H->ba_maxv, w.vcount);
+      H->g_bal[0] = dupload(own, ba, st);
+      H->n_bal[0] = (int)ba.size();
+      for (const GWork &w : ba) H->bal_maxv[0] = std::max(H->bal_maxv[0], w.vcount);
+      if (H->bal_maxv[0] > 16) {   // else the two lists are the same
+        H->g_bal[1] = dupload(own, ba16, st);
+        H->n_bal[1] = (int)ba16.size();
+        H->bal_maxv[1] = 16;
+      }
     }
     H->g_vec = dupload(own, gv, st);
   }
@@ -1074,6 +1087,13 @@ void ainv(smpm_handle *H, const double *src, double *dst, hipStream_t st, int in
 // keeps its best round: clock ramps and cold caches then hit every candidate
 // alike, not the first one timed.  Without tuning, schedules follow the
 // launch size.
+// b_S = (B A^-1) F~ over the strips: item list `list` under schedule `sched`
+void ba_launch(smpm_handle *H, int list, int sched, hipStream_t st) {
+  gemm_launch<double, double, double, double>(H, sched, H->g_bal[list], H->n_bal[list], nullptr, 0,
+                                              (const double *)H->F, 0, nullptr, H->bS, nullptr, nullptr, st,
+                                              H->bal_maxv[list] <= 16);
+}
+
 template <typename F>
 int fastest(hipStream_t st, hipEvent_t e0, hipEvent_t e1, int ncand, F &&fn) {
   std::vector<float> best(ncand, 1e30f);
@@ -1098,7 +1118,8 @@ void tune_schedules(smpm_handle *H, hipStream_t st) {
   for (int k = 0; k < 3; ++k)
     for (int w = 0; w < 2; ++w) H->cg_sched[k][w] = -1;
   for (int pr = 0; pr < 3; ++pr) H->use_fused[pr] = H->fused && (int64_t)H->n_g_all[2] * rt16 < 2048;
-  H->ba_sched = gemm_default(H->n_ba, rt16);
+  H->ba_list = 0;
+  H->ba_sched = gemm_default(H->n_bal[0], rt16);
   if (H->no_tune) return;
   const int rmax = std::max(H->n2_max, H->nq_max);
   for (int k = 0; k < 3; ++k)
@@ -1159,11 +1180,12 @@ void tune_schedules(smpm_handle *H, hipStream_t st) {
           }
         });
     }
-    if (H->use_ba)   // the Schur right-hand side GEMM (FP64 only)
-      H->ba_sched = fastest(st, e0, e1, kNumSched, [&](int sc) {
-        gemm_launch<double, double, double, double>(H, sc, H->g_ba, H->n_ba, nullptr, 0, (const double *)H->F, 0,
-                                                    nullptr, H->bS, nullptr, nullptr, st, H->ba_maxv <= 16);
-      });
+    if (H->use_ba) {   // the Schur right-hand side GEMM (FP64 only), over either item list
+      const int c = fastest(st, e0, e1, H->n_bal[1] ? 2 * kNumSched : kNumSched,
+                            [&](int c) { ba_launch(H, c / kNumSched, c % kNumSched, st); });
+      H->ba_list = c / kNumSched;
+      H->ba_sched = c % kNumSched;
+    }
     // one fused S M^-1 GEMM per iteration, or M^-1 then S: whichever is faster
     if (H->fused)
       for (int pr = 0; pr < (H->op16 ? 3 : 2); ++pr) {
@@ -1211,8 +1233,7 @@ void tune_schedules(smpm_handle *H, hipStream_t st) {
     if (H->use_ba)
       H->use_ba = fastest(st, e0, e1, 2, [&](int c) {
         if (c == 0) {
-          gemm_launch<double, double, double, double>(H, H->ba_sched, H->g_ba, H->n_ba, nullptr, 0, (const double *)H->F,
-                                                      0, nullptr, H->bS, nullptr, nullptr, st, H->ba_maxv <= 16);
+          ba_launch(H, H->ba_list, H->ba_sched, st);
           hipLaunchKernelGGL(k_bS, dim3(H->n_h), dim3(kBlock), 0, st, H->d_sys, H->d_ins, H->w_h,
                              (const double *)nullptr, H->bS, H->hs);
         } else {
@@ -1244,6 +1265,13 @@ void tune(smpm_handle *H, hipStream_t st) {
     if (v >= 0 && v < kNumSched)
       for (int op = 0; op < 3; ++op)
         for (int pr = 0; pr < 3; ++pr) H->sched[op][pr] = v;
+  }
+  if (const char *e = std::getenv("SMPM_RHS_GEMM")) {   // "schedule,list"
+    int v = -1, l = 0;
+    if (std::sscanf(e, "%d,%d", &v, &l) >= 1 && v >= 0 && v < kNumSched && (l == 0 || (l == 1 && H->n_bal[1]))) {
+      H->ba_sched = v;
+      H->ba_list = l;
+    }
   }
   if (const char *e = std::getenv("SMPM_ELEM_SCHED")) {
     const int v = std::atoi(e);
@@ -1577,8 +1605,7 @@ void read_rhs(smpm_handle *H, const double *f, const double *g, hipStream_t st) 
 void stage_rhs(smpm_handle *H, hipStream_t st) {
   hipLaunchKernelGGL(k_proj_r, dim3(H->n_r), dim3(kBlock), 0, st, H->d_sys, H->d_ins, H->w_r, H->F, H->pr, H->defect);
   if (H->use_ba) {   // b_S = (B A^-1) F~ in one GEMM over the strips, then u_S . b_S per half
-    gemm_launch<double, double, double, double>(H, H->ba_sched, H->g_ba, H->n_ba, nullptr, 0, (const double *)H->F,
-                                                0, nullptr, H->bS, nullptr, nullptr, st, H->ba_maxv <= 16);
+    ba_launch(H, H->ba_list, H->ba_sched, st);
     hipLaunchKernelGGL(k_bS, dim3(H->n_h), dim3(kBlock), 0, st, H->d_sys, H->d_ins, H->w_h, (const double *)nullptr,
                        H->bS, H->hs);
   } else {
@@ -2353,6 +2380,8 @@ smpm_status smpm_query(const smpm_handle *H, int32_t sysi, smpm_info *info) {
     o.fused_sched[pr] = H->n_g_all[2] > 0 ? H->sched[2][pr] : -1;
   }
   o.setup_device = s.dev_steps;
+  o.rhs_gemm[0] = H->use_ba ? H->ba_sched : -1;
+  o.rhs_gemm[1] = H->use_ba ? (H->ba_list ? 16 : kGemmVecs) : -1;
   // Algorithmic operator sizes: nonzero entries only (a Schur block's
   // column half for a window half outside the interface range is stored as
   // zeros and not counted), distinct blocks once.

@@ -291,6 +291,23 @@ def test_element_gemm_schedules_match_oracle(sched, monkeypatch, sched_refs):
         assert _rel(u[m, q], ref.u) <= (ref.bound if m == 0 else 1e-11), (sched, m, q)
 
 
+@pytest.mark.parametrize("sched,lst", [(1, 0), (2, 0), (0, 1), (6, 1), (7, 1), (8, 1)])
+def test_rhs_gemm_item_lists_match_oracle(sched, lst, monkeypatch, sched_refs):
+    # The Schur right-hand side b_S = (B A^-1) F~ as one GEMM over the strips,
+    # pinned to a schedule on either item list: up to 32 windows per item, or
+    # up to 16 (the narrow schedules 6 and 7 need it).  Two right-hand sides of
+    # 10 interior strips give 20 windows per block side: one full 16-window
+    # item and a partial one on the second list.
+    monkeypatch.setenv("SMPM_RHS_GEMM", f"{sched},{lst}")
+    p = _sched_problem()
+    s, u, st = _gpu_solve(p, tol=TIGHT)
+    assert all(i["rhs_gemm"] == [sched, 16 if lst else 32] for i in s.info)
+    assert st["rel_residual_max"] <= ACCEPT_TIGHT
+    u = u.reshape(2, 2, p.r)
+    for (m, q), ref in sched_refs.items():
+        assert _rel(u[m, q], ref.u) <= (ref.bound if m == 0 else 1e-11), (sched, lst, m, q)
+
+
 @pytest.mark.parametrize("sched", [0, 1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 11, 12])
 @pytest.mark.parametrize("precision", [P.FP64, P.FP32_IR])
 def test_shared_block_gemm_schedules_match_oracle(sched, precision, monkeypatch, sched_refs):
