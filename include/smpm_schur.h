@@ -221,6 +221,16 @@ typedef struct {
                               list, 1 for the 16-window one, which exists only
                               when some item has more than 16 windows), read at
                               setup and load, pins both (tests, experiments) */
+  int32_t gemm_list[4];    /* windows per item (32, or 16 for the narrow
+                              schedules) of the list each gemm_sched entry runs
+                              on: every S and M^-1 list with an item of more
+                              than 16 windows is also built in items of at most
+                              16, and the tuner times every schedule on both (-1
+                              no shared blocks).  SMPM_GEMM_LIST = 1 in the
+                              environment, read at setup and load, pins the
+                              16-window lists where they exist (tests,
+                              experiments); SMPM_GEMM_SCHED pins the 32-window
+                              ones unless SMPM_GEMM_LIST = 1 is set too */
 } smpm_info;
 
 typedef struct smpm_handle smpm_handle;

@@ -178,6 +178,16 @@ constexpr int kWaves = 16;   // waves per workgroup of the GEMV-shaped kernels
 
 }  // namespace
 
+// One batched shared-block GEMM item list: the items, the most windows in
+// one item, and two XCD-ordered unit lists over it ((item, 64-row tile), and
+// 128-row tiles costliest first).
+struct GList {
+  const GWork *w = nullptr;
+  int n = 0, maxv = 0;
+  const int2 *u = nullptr, *u128 = nullptr;
+  int nu = 0, nu128 = 0;
+};
+
 struct smpm_handle {
   smpm_opts opts{};
   int nrhs = 1, maxit = 300, precision = SMPM_FP64, method = SMPM_METHOD_DBJ, max_sweeps = 12;
@@ -197,12 +207,14 @@ struct smpm_handle {
   // grouped by block id across all instances of a system (batched launches),
   // and within one instance (single-system applies).
   // Per operator: 0 S, 1 M^-1, 2 S M^-1 (fused, grids whose strips share blocks).
-  GWork *g_all[3] = {}, *g_one[3] = {};
+  // gl[op][0]: items of up to kGemmVecs windows (16 for S M^-1); gl[op][1]:
+  // the S and M^-1 lists again in items of up to 16 windows, for the narrow
+  // schedules (empty when list 0 has no wider item).  g_list: the list the
+  // tuner picked per [op][precision].
+  GList gl[3][2] = {};
+  int g_list[3][3] = {};
+  GWork *g_one[3] = {};
   GVec *g_vec = nullptr;
-  int2 *u_all[3] = {};   // XCD-ordered (item, 64-row tile) lists of g_all
-  int n_u_all[3] = {};
-  int2 *u128_all[3] = {};   // the same for 128-row tiles, costliest tiles first
-  int n_u128_all[3] = {};
   bool fused = false;    // every system has S M^-1 blocks
   bool use_fused[3] = {}; // per precision: one S M^-1 GEMM per iteration beat M^-1 then S at setup
   // GEMM schedule of each batched list, picked at setup by timing every
@@ -210,8 +222,6 @@ struct smpm_handle {
   // element-interior lists.
   int sched[3][3] = {};   // [op][FP64, FP32, FP16 storage]
   int cg_sched[3][2] = {};
-  int n_g_all[3] = {};
-  int g_maxv[3] = {};      // most windows in one item of each list
   // B A^-1 per strip class (the Schur right-hand side as one GEMM), for
   // handles whose systems all share strip classes
   bool use_ba = false;
@@ -631,11 +641,11 @@ void upload(smpm_handle *H, hipStream_t st) {
   }
   // MFMA GEMM items for systems with shared blocks.
   {
-    std::vector<GWork> ga[3], go[3];
+    std::vector<GWork> ga[3], go[3], ga16[2];
     std::vector<GVec> gv;
     // items of one stored block over its windows, kGemmVecs windows each
     // (half as many for the fused S M^-1 blocks)
-    auto emit = [&](int si, int op, int id, const std::vector<int2> &vecs, std::vector<GWork> &out) {
+    auto emit = [&](int si, int op, int id, const std::vector<int2> &vecs, std::vector<GWork> &out, int cap = 0) {
       const System &s = H->sys[si];
       const SysDev &d = H->h_sys[si];
       const int N = s.N, slots = (N + 15) / 16;
@@ -656,7 +666,7 @@ void upload(smpm_handle *H, hipStream_t st) {
         w.vstart = (int)gv.size();
         // S M^-1 blocks are up to 4x wider than S blocks: items of 16
         // windows give twice the workgroups at half the columns each.
-        const size_t width = op == 2 ? kGemmVecs / 2 : kGemmVecs;
+        const size_t width = cap ? cap : op == 2 ? kGemmVecs / 2 : kGemmVecs;
         w.vcount = (int)std::min<size_t>(width, vecs.size() - a);
         for (int q = 0; q < w.vcount; ++q) {
           const int inst = vecs[a + q].x, h = vecs[a + q].y;
@@ -691,7 +701,10 @@ void upload(smpm_handle *H, hipStream_t st) {
             all[ids[h]].push_back(e);
             per[q][ids[h]].push_back(e);
           }
-        for (auto &kv : all) emit(si, op, kv.first, kv.second, ga[op]);
+        for (auto &kv : all) {
+          emit(si, op, kv.first, kv.second, ga[op]);
+          if (op < 2) emit(si, op, kv.first, kv.second, ga16[op], 16);
+        }
         for (int q = 0; q < H->nrhs; ++q) {
           const int inst = si * H->nrhs + q;
           std::vector<int> &st_v = H->g_start[op], &ct_v = H->g_cnt[op];
@@ -702,26 +715,25 @@ void upload(smpm_handle *H, hipStream_t st) {
         }
       }
     }
-    for (int op = 0; op < 3; ++op) {
-      H->g_maxv[op] = 0;
-      for (const GWork &w : ga[op]) H->g_maxv[op] = std::max(H->g_maxv[op], w.vcount);
-      H->g_start[op].resize(H->ninst, 0); H->g_cnt[op].resize(H->ninst, 0);
-      H->g_all[op] = dupload(own, ga[op], st); H->n_g_all[op] = (int)ga[op].size();
-      H->g_one[op] = dupload(own, go[op], st);
+    auto make_list = [&](const std::vector<GWork> &items) {
+      GList L;
+      for (const GWork &w : items) L.maxv = std::max(L.maxv, w.vcount);
+      L.w = dupload(own, items, st);
+      L.n = (int)items.size();
       std::vector<uintptr_t> key;
       std::vector<int> tiles;
-      for (const GWork &w : ga[op]) {
+      for (const GWork &w : items) {
         key.push_back((uintptr_t)w.blk64);
         tiles.push_back((w.Np + 63) / 64);
       }
       std::vector<int2> u = xcd_units(key, tiles);
-      H->u_all[op] = dupload(own, u, st);
-      H->n_u_all[op] = (int)u.size();
+      L.u = dupload(own, u, st);
+      L.nu = (int)u.size();
       // 128-row tiles, each costed by its MFMA work (K x live 16-row groups
       // x 16-window column tiles) plus one unit per K for the block's reads
       std::vector<int> t128;
       std::vector<std::vector<int64_t>> cost;
-      for (const GWork &w : ga[op]) {
+      for (const GWork &w : items) {
         const int nt = (w.Np + 127) / 128;
         t128.push_back(nt);
         std::vector<int64_t> cr(nt);
@@ -732,8 +744,15 @@ void upload(smpm_handle *H, hipStream_t st) {
         cost.push_back(cr);
       }
       std::vector<int2> u2 = xcd_units(key, t128, &cost);
-      H->u128_all[op] = dupload(own, u2, st);
-      H->n_u128_all[op] = (int)u2.size();
+      L.u128 = dupload(own, u2, st);
+      L.nu128 = (int)u2.size();
+      return L;
+    };
+    for (int op = 0; op < 3; ++op) {
+      H->g_start[op].resize(H->ninst, 0); H->g_cnt[op].resize(H->ninst, 0);
+      H->g_one[op] = dupload(own, go[op], st);
+      H->gl[op][0] = make_list(ga[op]);
+      if (op < 2 && H->gl[op][0].maxv > 16) H->gl[op][1] = make_list(ga16[op]);
     }
     // B A^-1 per strip class, for the Schur right-hand side of every
     // system in one GEMM over the strips (grids whose strips share classes:
@@ -967,24 +986,29 @@ void gemm_launch(smpm_handle *H, int sched, const GWork *w, int count, const int
   }
 }
 
+// A batched list under schedule `sched`.
+template <typename TS, typename TO, typename TX, typename TY>
+void gemm_list(smpm_handle *H, int sched, const GList &L, const TX *x, int vslot, const double *scale, TY *y,
+               double *hsum, const GState *gs, hipStream_t st) {
+  gemm_launch<TS, TO, TX, TY>(H, sched, L.w, L.n, L.u, L.nu, x, vslot, scale, y, hsum, gs, st, L.maxv <= 16, L.u128,
+                              L.nu128);
+}
+
 template <typename TS, typename TO, typename TX, typename TY>
 void gemv_ts(smpm_handle *H, int op, const TX *x, int vslot, const double *scale, TY *y, double *hsum,
              const GState *gs, hipStream_t st, int inst) {
   const int Kmax = (op == 0 ? 2 : 4) * H->Nmax;
   // halves with a shared block: MFMA GEMM over the windows that share it
   {
-    const GWork *w = H->g_all[op];
-    int count = H->n_g_all[op];
-    if (inst >= 0) {
-      w = H->g_one[op] + H->g_start[op][inst];
-      count = H->g_cnt[op][inst];
-    }
-    if (count > 0) {
-      const int prec = sizeof(TS) == 8 ? 0 : (sizeof(TS) == 4 ? 1 : 2);
-      const int sched = inst < 0 ? H->sched[op][prec] : gemm_default(count, (H->Nmax + 15) / 16);
-      gemm_launch<TS, TO, TX, TY>(H, sched, w, count, inst < 0 ? H->u_all[op] : nullptr, H->n_u_all[op], x, vslot,
-                                  scale, y, hsum, gs, st, H->g_maxv[op] <= 16,
-                                  inst < 0 ? H->u128_all[op] : nullptr, H->n_u128_all[op]);
+    const int prec = sizeof(TS) == 8 ? 0 : (sizeof(TS) == 4 ? 1 : 2);
+    if (inst < 0) {
+      if (H->gl[op][0].n > 0)
+        gemm_list<TS, TO, TX, TY>(H, H->sched[op][prec], H->gl[op][H->g_list[op][prec]], x, vslot, scale, y, hsum, gs,
+                                  st);
+    } else if (H->g_cnt[op][inst] > 0) {
+      const int count = H->g_cnt[op][inst];
+      gemm_launch<TS, TO, TX, TY>(H, gemm_default(count, (H->Nmax + 15) / 16), H->g_one[op] + H->g_start[op][inst],
+                                  count, nullptr, 0, x, vslot, scale, y, hsum, gs, st, H->gl[op][0].maxv <= 16);
     }
   }
   // halves with their own block: streaming kernel (S or M^-1 only)
@@ -1114,10 +1138,13 @@ int fastest(hipStream_t st, hipEvent_t e0, hipEvent_t e1, int ncand, F &&fn) {
 void tune_schedules(smpm_handle *H, hipStream_t st) {
   const int rt16 = (H->Nmax + 15) / 16;
   for (int op = 0; op < 3; ++op)
-    for (int pr = 0; pr < 3; ++pr) H->sched[op][pr] = gemm_default(H->n_g_all[op], rt16);
+    for (int pr = 0; pr < 3; ++pr) {
+      H->sched[op][pr] = gemm_default(H->gl[op][0].n, rt16);
+      H->g_list[op][pr] = 0;
+    }
   for (int k = 0; k < 3; ++k)
     for (int w = 0; w < 2; ++w) H->cg_sched[k][w] = -1;
-  for (int pr = 0; pr < 3; ++pr) H->use_fused[pr] = H->fused && (int64_t)H->n_g_all[2] * rt16 < 2048;
+  for (int pr = 0; pr < 3; ++pr) H->use_fused[pr] = H->fused && (int64_t)H->gl[2][0].n * rt16 < 2048;
   H->ba_list = 0;
   H->ba_sched = gemm_default(H->n_bal[0], rt16);
   if (H->no_tune) return;
@@ -1155,30 +1182,31 @@ void tune_schedules(smpm_handle *H, hipStream_t st) {
       }
       HIPCHECK(hipMemcpyAsync(H->gs, H->h_gs, sizeof(GState) * H->ninst, hipMemcpyHostToDevice, st));
     }
+    // every schedule on each item list of the operator (the 16-window list
+    // where there is one)
     for (int op = 0; op < 3; ++op) {
-      const int count = H->n_g_all[op];
-      if (count == 0) continue;
-      const GWork *w = H->g_all[op];
-      const int2 *u = H->u_all[op];
-      const int nu = H->n_u_all[op];
-      for (int pr = 0; pr < (H->op16 ? 3 : 2); ++pr)
-        H->sched[op][pr] = fastest(st, e0, e1, kNumSched, [&](int sc) {
+      if (H->gl[op][0].n == 0) continue;
+      const int nl = H->gl[op][1].n ? 2 : 1;
+      for (int pr = 0; pr < (H->op16 ? 3 : 2); ++pr) {
+        const int c = fastest(st, e0, e1, nl * kNumSched, [&](int c) {
+          const GList &L = H->gl[op][c / kNumSched];
+          const int sc = c % kNumSched;
           for (int pass = 0; pass < (mixed ? 2 : 1); ++pass) {
             const GState *g = pass == 0 ? nullptr : H->gs;
             if (pr == 0)
-              gemm_launch<double, double, double, double>(H, sc, w, count, u, nu, H->t64, 0, nullptr, H->y64,
-                                                          op == 0 ? H->hs : nullptr, g, st, H->g_maxv[op] <= 16,
-                                                          H->u128_all[op], H->n_u128_all[op]);
+              gemm_list<double, double, double, double>(H, sc, L, H->t64, 0, nullptr, H->y64,
+                                                        op == 0 ? H->hs : nullptr, g, st);
             else if (pr == 1)
-              gemm_launch<float, float, float, float>(H, sc, w, count, u, nu, H->t32, 0, nullptr, H->y32,
-                                                      op == 0 ? H->hs : nullptr, g, st, H->g_maxv[op] <= 16,
-                                                      H->u128_all[op], H->n_u128_all[op]);
+              gemm_list<float, float, float, float>(H, sc, L, H->t32, 0, nullptr, H->y32, op == 0 ? H->hs : nullptr,
+                                                    g, st);
             else
-              gemm_launch<_Float16, float, float, float>(H, sc, w, count, u, nu, H->t32, 0, nullptr, H->y32,
-                                                         op == 0 ? H->hs : nullptr, g, st, H->g_maxv[op] <= 16,
-                                                         H->u128_all[op], H->n_u128_all[op]);
+              gemm_list<_Float16, float, float, float>(H, sc, L, H->t32, 0, nullptr, H->y32,
+                                                       op == 0 ? H->hs : nullptr, g, st);
           }
         });
+        H->g_list[op][pr] = c / kNumSched;
+        H->sched[op][pr] = c % kNumSched;
+      }
     }
     if (H->use_ba) {   // the Schur right-hand side GEMM (FP64 only), over either item list
       const int c = fastest(st, e0, e1, H->n_bal[1] ? 2 * kNumSched : kNumSched,
@@ -1264,7 +1292,16 @@ void tune(smpm_handle *H, hipStream_t st) {
     const int v = std::atoi(e);
     if (v >= 0 && v < kNumSched)
       for (int op = 0; op < 3; ++op)
-        for (int pr = 0; pr < 3; ++pr) H->sched[op][pr] = v;
+        for (int pr = 0; pr < 3; ++pr) {
+          H->sched[op][pr] = v;
+          H->g_list[op][pr] = 0;
+        }
+  }
+  if (const char *e = std::getenv("SMPM_GEMM_LIST")) {   // 1: the 16-window lists where there are any
+    const int l = std::atoi(e);
+    if (l == 0 || l == 1)
+      for (int op = 0; op < 2; ++op)
+        for (int pr = 0; pr < 3; ++pr) H->g_list[op][pr] = H->gl[op][1].n ? l : 0;
   }
   if (const char *e = std::getenv("SMPM_RHS_GEMM")) {   // "schedule,list"
     int v = -1, l = 0;
@@ -2372,16 +2409,21 @@ smpm_status smpm_query(const smpm_handle *H, int32_t sysi, smpm_info *info) {
   o.bytes_M64 = (int64_t)s.nM * s.N * 4 * s.N * 8;   // distinct block-Jacobi row chunks, FP64
   for (int op = 0; op < 2; ++op)
     for (int pr = 0; pr < 2; ++pr)
-      o.gemm_sched[2 * op + pr] = H->n_g_all[op] > 0 ? H->sched[op][pr == 1 && H->op16 ? 2 : pr] : -1;
+      o.gemm_sched[2 * op + pr] = H->gl[op][0].n > 0 ? H->sched[op][pr == 1 && H->op16 ? 2 : pr] : -1;
   for (int k = 0; k < 3; ++k)
     for (int w = 0; w < 2; ++w) o.elem_sched[2 * k + w] = H->n_cg_all[k][w] > 0 ? H->cg_sched[k][w] : -1;
   for (int pr = 0; pr < 3; ++pr) {
     o.fused_op[pr] = H->use_fused[pr] ? 1 : 0;
-    o.fused_sched[pr] = H->n_g_all[2] > 0 ? H->sched[2][pr] : -1;
+    o.fused_sched[pr] = H->gl[2][0].n > 0 ? H->sched[2][pr] : -1;
   }
   o.setup_device = s.dev_steps;
   o.rhs_gemm[0] = H->use_ba ? H->ba_sched : -1;
   o.rhs_gemm[1] = H->use_ba ? (H->ba_list ? 16 : kGemmVecs) : -1;
+  for (int op = 0; op < 2; ++op)
+    for (int pr = 0; pr < 2; ++pr) {
+      const int p = pr == 1 && H->op16 ? 2 : pr;
+      o.gemm_list[2 * op + pr] = H->gl[op][0].n > 0 ? (H->g_list[op][p] ? 16 : kGemmVecs) : -1;
+    }
   // Algorithmic operator sizes: nonzero entries only (a Schur block's
   // column half for a window half outside the interface range is stored as
   // zeros and not counted), distinct blocks once.

@@ -328,6 +328,24 @@ def test_shared_block_gemm_schedules_match_oracle(sched, precision, monkeypatch,
         assert _rel(u[m, q], ref.u) <= (ref.bound if m == 0 else 1e-11), (sched, m, q)
 
 
+@pytest.mark.parametrize("sched", [0, 1, 2, 6, 7, 8, 11, 12])
+@pytest.mark.parametrize("precision", [P.FP64, P.FP32_IR])
+def test_shared_block_gemm_16_window_lists_match_oracle(sched, precision, monkeypatch, sched_refs):
+    # The S and M^-1 lists built again in items of at most 16 windows (the
+    # narrow schedules' lists), pinned: the interior S blocks' 20 windows per
+    # system become a full and a partial item.
+    monkeypatch.setenv("SMPM_GEMM_SCHED", str(sched))
+    monkeypatch.setenv("SMPM_GEMM_LIST", "1")
+    p = _sched_problem()
+    s, u, st = _gpu_solve(p, precision=precision, tol=TIGHT)
+    assert all(v == sched for i in s.info for v in i["gemm_sched"] if v >= 0)
+    assert any(v == 16 for i in s.info for v in i["gemm_list"])
+    assert st["rel_residual_max"] <= ACCEPT_TIGHT
+    u = u.reshape(2, 2, p.r)
+    for (m, q), ref in sched_refs.items():
+        assert _rel(u[m, q], ref.u) <= (ref.bound if m == 0 else 1e-11), (sched, m, q)
+
+
 def _tall_problem():
     # N = 14 * 10 = 140 rows per half: two 128-row tiles (the second ragged),
     # three 64-row tiles, and K = 2N .. 8N spans several staged chunks and
