@@ -231,6 +231,14 @@ typedef struct {
                               16-window lists where they exist (tests,
                               experiments); SMPM_GEMM_SCHED pins the 32-window
                               ones unless SMPM_GEMM_LIST = 1 is set too */
+  int32_t elem_alt[3];     /* per element-interior product (D^-1, K^-1,
+                              correction): the schedule, numbered as elem_sched,
+                              of the whole product as one launch over items of
+                              at most 16 columns, where the tuner found that
+                              faster than the two width lists (products with an
+                              item wider than 16 only); -1 the width lists run.
+                              SMPM_ELEM_ALT = 1 with SMPM_ELEM_SCHED pins it
+                              (tests, experiments) */
 } smpm_info;
 
 typedef struct smpm_handle smpm_handle;

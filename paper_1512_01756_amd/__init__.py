@@ -74,7 +74,7 @@ class Info(ctypes.Structure):
                 ("nnz_F_unique", ctypes.c_int64), ("nnz_F_total", ctypes.c_int64),
                 ("strip_classes", ctypes.c_int32), ("elem_unique", ctypes.c_int32),
                 ("fused_sched", ctypes.c_int32 * 3), ("rhs_gemm", ctypes.c_int32 * 2),
-                ("gemm_list", ctypes.c_int32 * 4)]
+                ("gemm_list", ctypes.c_int32 * 4), ("elem_alt", ctypes.c_int32 * 3)]
 
     def as_dict(self):
         out = {}

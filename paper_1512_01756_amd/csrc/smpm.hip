@@ -245,6 +245,14 @@ struct smpm_handle {
   int n_cg_all[3][2] = {};
   int2 *cg_units[3][2] = {};   // XCD-ordered (item, 64-row tile) lists of cg_all
   int n_cg_units[3][2] = {};
+  // Each product again in items of at most 16 columns, as one launch of the
+  // 16-column kernel (products with a wide item only); used instead of the
+  // two width lists where the tuner found it faster.
+  CGItem *cg_alt[3] = {};
+  int n_cg_alt[3] = {};
+  int2 *cg_alt_units[3] = {};
+  int n_cg_alt_units[3] = {};
+  int cg_alt_sched[3] = {-1, -1, -1};   // -1: the two width lists
   std::vector<int> cg_start[3][2], cg_cnt[3][2];
   int n_h = 0, n_x = 0, n_r = 0, n_s = 0;
   std::vector<int> h_start, x_start, r_start, s_start;
@@ -534,10 +542,10 @@ void upload(smpm_handle *H, hipStream_t st) {
     // chunks of 64 columns; a class (or remainder) of at most 16 columns
     // goes to the narrow list
     auto emit = [&](const double *A, int R, int K, int lda, int ksplit, int agap, const std::vector<CGCol> &cv,
-                    std::vector<CGItem> *out) {
+                    std::vector<CGItem> *out, bool narrow) {
       for (size_t a = 0; a < cv.size();) {
         const size_t left = cv.size() - a;
-        const int w = left <= 16 ? 0 : 1;
+        const int w = left <= 16 || narrow ? 0 : 1;
         CGItem it{};
         it.A = A; it.R = R; it.K = K; it.lda = lda; it.ksplit = ksplit; it.agap = agap;
         it.cstart = (int)cols.size();
@@ -548,7 +556,8 @@ void upload(smpm_handle *H, hipStream_t st) {
       }
     };
     // items of system si over the instances [i0, i1)
-    auto items = [&](int si, int i0, int i1, std::vector<CGItem> (*out)[2]) {
+    // (narrow: every item of at most 16 columns, into out[kind][0])
+    auto items = [&](int si, int i0, int i1, std::vector<CGItem> (*out)[2], bool narrow = false) {
       const System &s = H->sys[si];
       const SysDev &d = H->h_sys[si];
       const int n = s.n, n2 = s.n2, mz = s.mz, nq = 2 * s.n * (s.mz - 1);
@@ -587,8 +596,8 @@ void upload(smpm_handle *H, hipStream_t st) {
               }
             }
           }
-          emit(A, n2, n2, n2, n2, 0, cs, out[0]);
-          if (nq > 0) emit(A, n2, 2 * n, n2, n, n2 - 2 * n, cc, out[2]);
+          emit(A, n2, n2, n2, n2, 0, cs, out[0], narrow);
+          if (nq > 0) emit(A, n2, 2 * n, n2, n, n2 - 2 * n, cc, out[2], narrow);
         }
         if (nq > 0) {
           std::vector<CGCol> cq;
@@ -597,11 +606,13 @@ void upload(smpm_handle *H, hipStream_t st) {
               const int64_t q0 = H->h_ins[i].lam_off + (int64_t)j * nq;
               cq.push_back(CGCol{q0, -1, q0});
             }
-          emit(d.Kinv + (size_t)c * nq * nq, nq, nq, nq, nq, 0, cq, out[1]);
+          emit(d.Kinv + (size_t)c * nq * nq, nq, nq, nq, nq, 0, cq, out[1], narrow);
         }
       }
     };
     for (int si = 0; si < (int)H->sys.size(); ++si) items(si, si * H->nrhs, (si + 1) * H->nrhs, all);
+    std::vector<CGItem> alt[3][2];
+    for (int si = 0; si < (int)H->sys.size(); ++si) items(si, si * H->nrhs, (si + 1) * H->nrhs, alt, true);
     // Where a product has wide items and only a few narrow ones (a launch of
     // fewer than 1024 row tiles, bound by latency), the 64-column kernel takes
     // the narrow ones too: one launch instead of two.  Many narrow items stay
@@ -637,6 +648,20 @@ void upload(smpm_handle *H, hipStream_t st) {
         H->cg_units[k][w] = dupload(own, u, st);
         H->n_cg_units[k][w] = (int)u.size();
       }
+    for (int k = 0; k < 3; ++k) {
+      if (all[k][1].empty()) continue;   // no wide item: the 16-column list is list 0
+      H->cg_alt[k] = dupload(own, alt[k][0], st);
+      H->n_cg_alt[k] = (int)alt[k][0].size();
+      std::vector<uintptr_t> key;
+      std::vector<int> tiles;
+      for (const CGItem &it : alt[k][0]) {
+        key.push_back((uintptr_t)it.A);
+        tiles.push_back((it.R + 63) / 64);
+      }
+      std::vector<int2> u = xcd_units(key, tiles);
+      H->cg_alt_units[k] = dupload(own, u, st);
+      H->n_cg_alt_units[k] = (int)u.size();
+    }
     H->cg_cols = dupload(own, cols, st);
   }
   // MFMA GEMM items for systems with shared blocks.
@@ -1080,6 +1105,11 @@ void colgemm_w(smpm_handle *H, const CGItem *items, int count, const int2 *units
 
 // One element-interior product (kind 0, 1, 2) over all instances or one.
 void colgemm(smpm_handle *H, int kind, int inst, int mode, const double *x, double *y, hipStream_t st) {
+  if (inst < 0 && H->cg_alt_sched[kind] >= 0) {
+    colgemm_w<1>(H, H->cg_alt[kind], H->n_cg_alt[kind], H->cg_alt_units[kind], H->n_cg_alt_units[kind], mode, x, y,
+                 st, H->cg_alt_sched[kind]);
+    return;
+  }
   for (int w = 0; w < 2; ++w) {
     const CGItem *it = inst >= 0 ? H->cg_one[kind][w] + H->cg_start[kind][w][inst] : H->cg_all[kind][w];
     const int cnt = inst >= 0 ? H->cg_cnt[kind][w][inst] : H->n_cg_all[kind][w];
@@ -1255,6 +1285,23 @@ void tune_schedules(smpm_handle *H, hipStream_t st) {
           else colgemm_w<kColVecs / 16>(H, H->cg_all[k][w], cnt, H->cg_units[k][w], H->n_cg_units[k][w], k == 2 ? 1 : 0, x, y, st, sc);
         })];
       }
+    // the whole product in 16-column items, one launch, against the two
+    // width lists under their schedules
+    for (int k = 0; k < 3; ++k) {
+      H->cg_alt_sched[k] = -1;
+      if (!H->n_cg_alt[k]) continue;
+      const double *x = k == 0 ? H->F : (k == 1 ? H->lam : H->qb);
+      double *y = k == 0 ? H->v : (k == 1 ? H->qb : H->v);
+      const int c = fastest(st, e0, e1, 6, [&](int c) {
+        if (c == 0) {
+          colgemm(H, k, -1, k == 2 ? 1 : 0, x, y, st);
+        } else {
+          colgemm_w<1>(H, H->cg_alt[k], H->n_cg_alt[k], H->cg_alt_units[k], H->n_cg_alt_units[k], k == 2 ? 1 : 0, x,
+                       y, st, cand[c - 1]);
+        }
+      });
+      H->cg_alt_sched[k] = c > 0 ? cand[c - 1] : -1;
+    }
     // the Schur right-hand side: the B A^-1 GEMM, or the element solves of
     // A^-1 and the B row functionals, whichever is faster (the GEMM's K is
     // m_z n^2, which on tall high-order strips costs more than the solves)
@@ -1312,9 +1359,14 @@ void tune(smpm_handle *H, hipStream_t st) {
   }
   if (const char *e = std::getenv("SMPM_ELEM_SCHED")) {
     const int v = std::atoi(e);
-    if (v >= kSplit8 && v <= kCol16)
-      for (int k = 0; k < 3; ++k)
+    if (v >= kSplit8 && v <= kCol16) {
+      const char *a = std::getenv("SMPM_ELEM_ALT");   // 1: the 16-column lists where there are any
+      const bool alt = a && std::atoi(a) == 1;
+      for (int k = 0; k < 3; ++k) {
         for (int w = 0; w < 2; ++w) H->cg_sched[k][w] = v;
+        H->cg_alt_sched[k] = alt && H->n_cg_alt[k] ? v : -1;
+      }
+    }
   }
 }
 
@@ -2412,6 +2464,7 @@ smpm_status smpm_query(const smpm_handle *H, int32_t sysi, smpm_info *info) {
       o.gemm_sched[2 * op + pr] = H->gl[op][0].n > 0 ? H->sched[op][pr == 1 && H->op16 ? 2 : pr] : -1;
   for (int k = 0; k < 3; ++k)
     for (int w = 0; w < 2; ++w) o.elem_sched[2 * k + w] = H->n_cg_all[k][w] > 0 ? H->cg_sched[k][w] : -1;
+  for (int k = 0; k < 3; ++k) o.elem_alt[k] = H->cg_alt_sched[k];
   for (int pr = 0; pr < 3; ++pr) {
     o.fused_op[pr] = H->use_fused[pr] ? 1 : 0;
     o.fused_sched[pr] = H->gl[2][0].n > 0 ? H->sched[2][pr] : -1;

@@ -308,6 +308,22 @@ def test_rhs_gemm_item_lists_match_oracle(sched, lst, monkeypatch, sched_refs):
         assert _rel(u[m, q], ref.u) <= (ref.bound if m == 0 else 1e-11), (sched, lst, m, q)
 
 
+@pytest.mark.parametrize("sched", [1, 2, 3, 4, 5])
+def test_element_gemm_16_column_lists_match_oracle(sched, monkeypatch, sched_refs):
+    # Each element-interior product as one launch over items of at most 16
+    # columns (the products that have wider items), pinned to every schedule.
+    monkeypatch.setenv("SMPM_ELEM_SCHED", str(sched))
+    monkeypatch.setenv("SMPM_ELEM_ALT", "1")
+    p = _sched_problem()
+    s, u, st = _gpu_solve(p, tol=TIGHT)
+    assert any(v == sched for i in s.info for v in i["elem_alt"])
+    assert all(v in (sched, -1) for i in s.info for v in i["elem_alt"])
+    assert st["rel_residual_max"] <= ACCEPT_TIGHT
+    u = u.reshape(2, 2, p.r)
+    for (m, q), ref in sched_refs.items():
+        assert _rel(u[m, q], ref.u) <= (ref.bound if m == 0 else 1e-11), (sched, m, q)
+
+
 @pytest.mark.parametrize("sched", [0, 1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 11, 12])
 @pytest.mark.parametrize("precision", [P.FP64, P.FP32_IR])
 def test_shared_block_gemm_schedules_match_oracle(sched, precision, monkeypatch, sched_refs):
