@@ -214,11 +214,14 @@ def gemm_kernel_name(s, op, dtype):
     t = "double" if dtype == "fp64" else "float"
     out = set()
     for i in s.info:
+        narrow = False
         if op == 2:
             sched = i["fused_sched"][0 if dtype == "fp64" else 1]
         else:
             sched = i["gemm_sched"][2 * op + (0 if dtype == "fp64" else 1)]
-        out.add(names.get(sched, "k_half_gemv_stream<{t}> (distinct blocks)").format(t=t))
+            narrow = i.get("gemm_list", [32] * 4)[2 * op + (0 if dtype == "fp64" else 1)] == 16
+        name = names.get(sched, "k_half_gemv_stream<{t}> (distinct blocks)").format(t=t)
+        out.add(name + (" on 16-window items" if narrow and sched >= 0 else ""))
     return " + ".join(sorted(out))
 
 

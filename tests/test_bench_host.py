@@ -69,5 +69,7 @@ def test_traffic_only_for_the_measured_kernel():
     fused = {"fused_sched": [0, 7]}
     name = bench.gemm_kernel_name(_Info([fused]), 2, "fp64") + " over the stored S M^-1 blocks"
     assert ("c2", "schur_bjinv", name) in bench.KERNEL_TRAFFIC
+    narrow = dict(shared, gemm_list=[16, 16, 16, 16])   # the same schedule on the 16-window list
+    assert ("c2", "schur", bench.gemm_kernel_name(_Info([narrow]), 0, "fp64")) not in bench.KERNEL_TRAFFIC
     distinct = {"gemm_sched": [-1, -1, -1, -1]}
     assert ("c3", "schur", bench.gemm_kernel_name(_Info([distinct]), 0, "fp64")) in bench.KERNEL_TRAFFIC
