@@ -234,6 +234,7 @@ def gemm_kernel_name(s, op, dtype):
 KERNEL_TRAFFIC = {
     ("c2", "schur", "k_half_gemm<double, 8> (split-K, 8 waves)"): 6.500e6,
     ("c2", "schur", "k_half_gemm<double, 16> (split-K, 16 waves)"): 6.460e6,
+    ("c2", "schur", "k_half_gemm<double, 16> (split-K, 16 waves) on 16-window items"): 8.277e6,
     ("c2", "schur_bjinv", "k_half_gemm<double, 8> (split-K, 8 waves) over the stored S M^-1 blocks"): 2.173e7,
     ("c2", "schur_bjinv", "k_half_gemm<double, 16> (split-K, 16 waves) over the stored S M^-1 blocks"): 2.170e7,
     ("c3", "schur", "k_half_gemv_stream<double> (distinct blocks)"): 3.568e8,
