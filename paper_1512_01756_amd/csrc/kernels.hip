@@ -2544,18 +2544,22 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(INV ? 3 : 4
     for (int k2 = 0; k2 < N2; ++k2) fb[(k1 + N1 * k2) * CT + c] = b[q][k2];
   }
   __syncthreads();
+  // Each (mode m, packed column c) gives both columns' Re and Im of mode m
+  // from the same two spectrum values; the planes are not read again, so the
+  // stores bypass the caches.
   constexpr double sc = 0.5 / MY;
-  for (int idx = threadIdx.x; idx < 2 * NK * CW; idx += 256) {
-    const int row = idx / CW, cc = idx % CW;
-    if (cc >= nc) continue;
-    const int m = row >> 1, c = cc % CT;
+  for (int idx = threadIdx.x; idx < NK * CT; idx += 256) {
+    const int m = idx / CT, c = idx % CT;
     const double2 A = fb[m * CT + c], B = fb[((MY - m) & (MY - 1)) * CT + c];
-    double val;
-    if (cc < CT)   // (A + conj B) / 2
-      val = (row & 1) ? (A.y - B.y) : (A.x + B.x);
-    else           // (A - conj B) / (2 i)
-      val = (row & 1) ? -(A.x - B.x) : (A.y + B.y);
-    out[(int64_t)row * ncol + c0 + cc] = val * sc;
+    double *o0 = out + (int64_t)(2 * m) * ncol + c0, *o1 = o0 + ncol;
+    if (c < nc) {   // column c: (A + conj B) / 2
+      __builtin_nontemporal_store((A.x + B.x) * sc, o0 + c);
+      __builtin_nontemporal_store((A.y - B.y) * sc, o1 + c);
+    }
+    if (c + CT < nc) {   // column c + CT: (A - conj B) / (2 i)
+      __builtin_nontemporal_store((A.y + B.y) * sc, o0 + c + CT);
+      __builtin_nontemporal_store(-(A.x - B.x) * sc, o1 + c + CT);
+    }
   }
 }
 
