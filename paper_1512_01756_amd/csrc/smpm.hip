@@ -804,32 +804,33 @@ void upload(smpm_handle *H, hipStream_t st) {
           }
         // items of up to kGemmVecs windows, and of up to 16 (the narrow
         // schedules: one column tile, or the whole K range in flight)
-        for (int cap : {kGemmVecs, 16})
-        for (auto &kv : byblk) {
-          const std::vector<int2> &vecs = kv.second;
-          for (size_t a = 0; a < vecs.size();) {
-            GWork w{};
-            w.blk64 = dba + (size_t)kv.first * K * d.Np;
-            w.n = s.n;
-            w.N = N; w.Np = d.Np; w.K = K; w.kS = s.r; w.ident = 0;
-            w.vstart = (int)gv.size();
-            w.vcount = (int)std::min<size_t>(cap, vecs.size() - a);
-            for (int qq = 0; qq < w.vcount; ++qq) {
-              const int inst = vecs[a + qq].x, j = vecs[a + qq].y / 2, side = vecs[a + qq].y % 2;
-              const int h = side == 0 ? 2 * (j - 1) : 2 * j + 1;
-              const InstDev &I = H->h_ins[inst];
-              GVec e{};
-              e.x0 = I.f_off;
-              e.win = (int64_t)j * K;
-              e.y = I.x_off + (int64_t)h * N;
-              e.inst = inst;
-              e.hs = (int)(I.hs_off + h);
-              e.hn = s.nh;
-              e.st_off = (int)I.st_off;
-              gv.push_back(e);
+        for (int cap : {kGemmVecs, 16}) {
+          for (auto &kv : byblk) {
+            const std::vector<int2> &vecs = kv.second;
+            for (size_t a = 0; a < vecs.size();) {
+              GWork w{};
+              w.blk64 = dba + (size_t)kv.first * K * d.Np;
+              w.n = s.n;
+              w.N = N; w.Np = d.Np; w.K = K; w.kS = s.r; w.ident = 0;
+              w.vstart = (int)gv.size();
+              w.vcount = (int)std::min<size_t>(cap, vecs.size() - a);
+              for (int qq = 0; qq < w.vcount; ++qq) {
+                const int inst = vecs[a + qq].x, j = vecs[a + qq].y / 2, side = vecs[a + qq].y % 2;
+                const int h = side == 0 ? 2 * (j - 1) : 2 * j + 1;
+                const InstDev &I = H->h_ins[inst];
+                GVec e{};
+                e.x0 = I.f_off;
+                e.win = (int64_t)j * K;
+                e.y = I.x_off + (int64_t)h * N;
+                e.inst = inst;
+                e.hs = (int)(I.hs_off + h);
+                e.hn = s.nh;
+                e.st_off = (int)I.st_off;
+                gv.push_back(e);
+              }
+              (cap == 16 ? ba16 : ba).push_back(w);
+              a += w.vcount;
             }
-            (cap == 16 ? ba16 : ba).push_back(w);
-            a += w.vcount;
           }
         }
       }
