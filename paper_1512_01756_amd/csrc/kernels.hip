@@ -1699,7 +1699,8 @@ __global__ __launch_bounds__(kBlock) void k_lambda(const SysDev *__restrict__ sy
 }
 
 // RHS of Eq. (smpm_poisson): F = f + tau g on the physical edges (corners get
-// both sides); partials of u_L . F and ||F||^2 for the Sec. 2.4 projection.
+// both sides); for singular (k = 0) systems, partials of u_L . F and ||F||^2
+// for the Sec. 2.4 projection.
 __global__ __launch_bounds__(kBlock) void k_rhs(const SysDev *__restrict__ sys,
                                                 const InstDev *__restrict__ ins,
                                                 const int2 *__restrict__ work,
@@ -1736,6 +1737,7 @@ __global__ __launch_bounds__(kBlock) void k_rhs(const SysDev *__restrict__ sys,
     if (S.singular) pd += S.uL[e] * v;
     pn += v * v;
   }
+  if (!S.singular) return;   // the sums feed only the k = 0 projection and its defect
   pd = block_sum(pd, lds4);
   __syncthreads();
   pn = block_sum(pn, lds4);
