@@ -1815,28 +1815,48 @@ __global__ __launch_bounds__(kBlock) void k_bS(const SysDev *__restrict__ sys,
   if (threadIdx.x == 0) hs[I.hs_off + h] = pd;
 }
 
-// b~ = b_S - u_S (u_S^T b_S) (Eq. regularize_schur), partials per half in hs.
+// b~ = b_S - u_S (u_S^T b_S) (Eq. regularize_schur), partials per half in hs;
+// then the chunk's partials of ||b~||^2 and u_S . b~ into partn (pairs per
+// chunk, as k_xupdate's residual mode leaves them), for every system.
 __global__ __launch_bounds__(kBlock) void k_proj_x(const SysDev *__restrict__ sys,
                                                    const InstDev *__restrict__ ins,
                                                    const int2 *__restrict__ work,
                                                    double *__restrict__ x,
-                                                   const double *__restrict__ hs) {
+                                                   const double *__restrict__ hs,
+                                                   double *__restrict__ partn) {
   __shared__ double lds4[4];
   __shared__ double alpha_s;
   const int2 wk = work[blockIdx.x];
   const int i = wk.x, ch = wk.y;
   const InstDev I = ins[i];
   const SysDev &S = sys[I.sys];
-  if (!S.singular) return;
-  double a = 0.0;
-  for (int c = threadIdx.x; c < S.nh; c += kBlock) a += hs[I.hs_off + c];
-  a = block_sum(a, lds4);
-  if (threadIdx.x == 0) alpha_s = a;
-  __syncthreads();
-  const double alpha = alpha_s;
+  double alpha = 0.0;
+  if (S.singular) {
+    double a = 0.0;
+    for (int c = threadIdx.x; c < S.nh; c += kBlock) a += hs[I.hs_off + c];
+    a = block_sum(a, lds4);
+    if (threadIdx.x == 0) alpha_s = a;
+    __syncthreads();
+    alpha = alpha_s;
+  }
+  double nn = 0.0, ud = 0.0;
   for (int q = 0; q < kChunk / kBlock; ++q) {
     const int64_t e = (int64_t)ch * kChunk + threadIdx.x + q * kBlock;
-    if (e < S.kS) x[I.x_off + e] -= alpha * S.uS[e];
+    if (e >= S.kS) continue;
+    double v = x[I.x_off + e];
+    if (S.singular) {
+      v -= alpha * S.uS[e];
+      x[I.x_off + e] = v;
+      ud += S.uS[e] * v;
+    }
+    nn += v * v;
+  }
+  nn = block_sum(nn, lds4);
+  __syncthreads();
+  ud = block_sum(ud, lds4);
+  if (threadIdx.x == 0) {
+    partn[I.part_off + 2 * ch] = nn;
+    partn[I.part_off + 2 * ch + 1] = ud;
   }
 }
 

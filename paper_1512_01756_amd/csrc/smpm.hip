@@ -1708,9 +1708,8 @@ void stage_rhs(smpm_handle *H, hipStream_t st) {
     hipLaunchKernelGGL(k_bS, dim3(H->n_h), dim3(kBlock), 0, st, H->d_sys, H->d_ins, H->w_h, (const double *)H->v, H->bS,
                        H->hs);
   }
-  hipLaunchKernelGGL(k_proj_x, dim3(H->n_x), dim3(kBlock), 0, st, H->d_sys, H->d_ins, H->w_x, H->bS, (const double *)H->hs);
-  hipLaunchKernelGGL(k_xupdate<double>, dim3(H->n_x), dim3(kBlock), 0, st, H->d_sys, H->d_ins, H->w_x, 2,
-                     (const double *)nullptr, (const double *)nullptr, H->bS, H->partn, (const double *)nullptr);
+  hipLaunchKernelGGL(k_proj_x, dim3(H->n_x), dim3(kBlock), 0, st, H->d_sys, H->d_ins, H->w_x, H->bS, (const double *)H->hs,
+                     H->partn);
   hipLaunchKernelGGL(k_reduce_pairs, dim3(H->ninst), dim3(kBlock), 0, st, H->d_ins, (const double *)H->partn, H->pairs,
                      H->nb2);
   if (H->precision != SMPM_FP64) {   // r = b~ (a copy through mode 0), x_S = 0
