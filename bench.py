@@ -595,7 +595,9 @@ def main():
         "rel_residual_max": {"fp64": fp64["rel_residual_max"], "fp32_ir": ir["rel_residual_max"],
                              "fp16s_ir": ir16["rel_residual_max"]},
         "setup_s": {"fp64": fp64["setup_s"], "fp32_ir": ir["setup_s"], "fp16s_ir": ir16["setup_s"]},
-        "gemm_schedules": {"matvec_S64_S32_M64_M32": i0["gemm_sched"], "element": i0["elem_sched"],
+        "gemm_schedules": {"matvec_S64_S32_M64_M32": i0["gemm_sched"],
+                           "matvec_windows_per_item": i0["gemm_list"], "element": i0["elem_sched"],
+                           "element_16_column_list": i0["elem_alt"], "rhs_gemm_sched_windows": i0["rhs_gemm"],
                            "fused_S_Minv_used_fp64_fp32": [i0["fused_op"][0],
                                                            forms["fp32_ir"][0].info[0]["fused_op"][1]],
                            "fused_S_Minv_sched_fp64_fp32": [i0["fused_sched"][0],
@@ -605,7 +607,8 @@ def main():
                                      "flight, 8 LDS-staged 128-row tiles, 9 / 10 64- / 128-row tiles whose waves also split K, "
                                      "11 / 12 128-row tiles in a cost-ordered XCD-aware order with 32- / 64-value chunks; "
                                      "element lists: 4 / 5 LDS-staged 32- / 16-row tiles with K split over the waves; -1 unused; "
-                                     "picked by timing at setup"},
+                                     "element_16_column_list: the schedule of a product run as one launch over items of at "
+                                     "most 16 columns, -1 where its two width lists run; picked by timing at setup"},
         "roofline": main_rl,
         "rooflines": rl,
     }
